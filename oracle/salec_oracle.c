@@ -1,0 +1,1252 @@
+/*
+ * salec_oracle.c -- plain FP64 CPU oracle of one explicit cycle of a
+ * SALE-type axisymmetric (r-z) impact hydrocode with perfectly matched layers.
+ *
+ * TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT. This is the slow, obviously
+ * correct reference against which the HIP library is checked. It is written
+ * for reading: whole-grid loops, one phase after another, in the order of the
+ * SALE operator split (Lagrangian step, then Eulerian step), with full-size
+ * temporary arrays and no blocking, fusion or reordering. It shares no code
+ * with the HIP library. Only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg may load it.
+ *
+ * Built with -O2 -ffp-contract=off (no fused multiply-add, no fast-math).
+ * OpenMP only splits independent per-cell / per-node loops over rows; the
+ * arithmetic of every cell is independent of the thread count and the time
+ * step minimum is exact, so results do not depend on the thread count.
+ *
+ * Paper: Li, Yue, Zhang, Zhang, Miao, "Parallel numerical simulation of
+ * impact crater with perfect matched layers" (SALEc-2D).
+ *   Sec. 2, eqs. (1)-(2): Lagrangian momentum and internal energy.
+ *   Sec. 2, eqs. (3)-(5): Eulerian advection of mass, momentum, energy.
+ *   Sec. 3: PML -- complex stretching, auxiliary variables phi1..3, psi1..2,
+ *           damped control equations and the damping profile d(y).
+ *   Sec. 4: boundary conditions (free-slip sides, outflow top, no-slip bottom).
+ *   Table 1: pressure-dependent strength (cohesion, friction, limit).
+ *   Sec. 7: Courant condition dt <= C0 min(dx, dy) / (|v| + c).
+ * The paper defers the discretisation, equation of state, artificial
+ * viscosity, strength update and remap to SALE; the discrete choices made
+ * here are the documented readings of those silent points (staggered grid,
+ * Tillotson EoS, compression-only linear+quadratic viscosity, Jaumann rate
+ * with radial return, first-order donor-cell remap, volume-fraction
+ * multi-material cells).
+ */
+#include "salec_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* regularisation constants (dimensionless; scaled by reference values) */
+#define PHI_EPS 1e-12       /* volume fraction below which a cell is void     */
+#define RHO_EOS_FLOOR 1e-6  /* EoS density floor, fraction of rho0            */
+#define RHO_DEN_FLOOR 1e-6  /* energy-update density floor, fraction of rho_ref */
+#define PML_RHO_FLOOR 1e-3  /* PML density floor, fraction of rho_ref        */
+#define M_ACC_EPS 1e-3      /* node mass floor for accelerations             */
+#define M_REMAP_FLOOR 1e-9  /* mass floor of remap denominators              */
+#define W_LO 1e-3           /* volume fraction where the CFL weight starts   */
+#define W_HI 1e-2           /* volume fraction where the CFL weight is 1     */
+#define NEG_MASS_TOL 1e-9   /* density below -tol*rho_ref is an error        */
+#define PCAV_FRAC 1e-4      /* pressure ramp of the cavitation rule, fraction of A */
+
+struct orc_ctx {
+    orc_grid g;
+    orc_mat m[ORC_MAX_MAT];
+    orc_pml pml;
+    int NR, NZ, NC, NN, nmat, any_strength;
+    double rho_ref, Gm[ORC_MAX_MAT]; /* shear / bulk modulus ratio per material */
+
+    /* state at the start of the cycle */
+    double *rho, *I, *f[ORC_MAX_MAT], *srr, *szz, *srz, *vr, *vz;
+    double t, dt, dt_prev;
+    int64_t cycle;
+    int err, err_cycle;
+
+    /* PML: damping profiles and auxiliary fields (zero outside the strips) */
+    double *dcz, *dnz, *dcr, *dnr;
+    double *phi1b, *phi3b, *psi2b, *phi1r, *phi3r, *psi2r, *rref, *msink;
+    double *phi2b_r, *phi2b_z, *psi1b_r, *psi1b_z;
+    double *phi2r_r, *phi2r_z, *psi1r_r, *psi1r_z;
+    double *mout_col, *eout_col;
+
+    /* per-cycle work arrays */
+    double *p, *c2, *G, *Y, *rmat, *phi, *sx, *Q, *sgrr, *sgzz, *sgtt, *sgrz;
+    double *vLr, *vLz, *heat;
+    double *J, *IL, *sLrr, *sLzz, *sLrz, *fL[ORC_MAX_MAT];
+    double *dVr, *Fr, *dVz, *Fz, *dVre, *dVze, *lam, *outv;
+    double *rho_n, *I_n, *f_n[ORC_MAX_MAT], *srr_n, *szz_n, *srz_n, *vr_n, *vz_n;
+};
+
+#define CI(i, j) ((j) * NR + (i))
+#define NI(i, j) ((j) * (NR + 1) + (i))
+#define RF(i, j) ((j) * (NR + 1) + (i)) /* radial face at r_i, row j, i in [0,NR] */
+#define AF(i, j) ((j) * NR + (i))       /* axial face at z_j, column i, j in [0,NZ] */
+
+static double dmax(double a, double b) { return a > b ? a : b; }
+static double dmin(double a, double b) { return a < b ? a : b; }
+
+/* ---- geometry (per radian): node radius, cell-centre radius, areas, volume ---- */
+static double r_node(const orc_ctx *x, int i) { return (double)i * x->g.dr; }
+static double r_cell(const orc_ctx *x, int i) { return ((double)i + 0.5) * x->g.dr; }
+static double area_r(const orc_ctx *x, int i) { return r_node(x, i) * x->g.dz; }
+static double area_z(const orc_ctx *x, int i) { return r_cell(x, i) * x->g.dr; }
+static double vol_c(const orc_ctx *x, int i) { return area_z(x, i) * x->g.dz; }
+
+/* ========================================================================
+ * Equation of state (the paper's EoS module is inherited from SALEc, Sec. 2;
+ * the form used is the four-region Tillotson equation of state).
+ * ======================================================================== */
+void orc_tillotson(const orc_mat *m, double rho, double e, double *p_out, double *c2_out)
+{
+    double rf = m->rho0 * RHO_EOS_FLOOR;
+    double r = rho > rf ? rho : rf;
+    double E = e > 0.0 ? e : 0.0;
+    double eta = r / m->rho0;
+    double mu = eta - 1.0;
+    double w = E / (m->E0 * eta * eta) + 1.0;
+
+    /* compressed / cold branch */
+    double pc = (m->a + m->b / w) * r * E + m->A * mu + m->B * mu * mu;
+    double pc_E = r * (m->a + m->b / w - m->b * (w - 1.0) / (w * w));
+    double pc_r = (m->a + m->b / w) * E + 2.0 * m->b * E * (w - 1.0) / (w * w)
+                + (m->A + 2.0 * m->B * mu) / m->rho0;
+    double p, dpdE, dpdr;
+    if (r >= m->rho0 || E <= m->Eiv) {
+        p = pc;
+        dpdE = pc_E;
+        dpdr = pc_r;
+    } else {
+        /* expanded branch */
+        double z = 1.0 / eta - 1.0;
+        double ea = exp(-m->alpha * z * z);
+        double eb = exp(-m->beta * z);
+        double pe = m->a * r * E + (m->b * r * E / w + m->A * mu * eb) * ea;
+        double pe_E = m->a * r + ea * m->b * r * (1.0 / w - (w - 1.0) / (w * w));
+        double pe_r = m->a * E
+                    + ea * (m->b * E / w + 2.0 * m->b * E * (w - 1.0) / (w * w)
+                            + (m->A / m->rho0) * eb + m->A * mu * m->beta * eb * m->rho0 / (r * r))
+                    + (m->b * r * E / w + m->A * mu * eb) * ea * 2.0 * m->alpha * z * m->rho0 / (r * r);
+        if (E >= m->Ecv) {
+            p = pe;
+            dpdE = pe_E;
+            dpdr = pe_r;
+        } else {
+            /* partial vaporisation: energy-weighted blend */
+            double x = (E - m->Eiv) / (m->Ecv - m->Eiv);
+            p = x * pe + (1.0 - x) * pc;
+            dpdE = x * pe_E + (1.0 - x) * pc_E + (pe - pc) / (m->Ecv - m->Eiv);
+            dpdr = x * pe_r + (1.0 - x) * pc_r;
+        }
+    }
+    *p_out = p;
+    *c2_out = dpdr + p / (r * r) * dpdE;
+}
+
+/* intact-rock yield strength (Table 1 parameters Y_i0, mu_i, Y_im) */
+double orc_yield(const orc_mat *m, double p)
+{
+    if (!m->strength) return 0.0;
+    if (p >= 0.0) {
+        double mp = m->mu_f * p;
+        return m->Y0 + mp / (1.0 + mp / (m->Ylim - m->Y0));
+    }
+    return dmax(0.0, m->Y0 + m->mu_f * p);
+}
+
+double orc_shear_modulus(const orc_mat *m)
+{
+    if (!m->strength) return 0.0;
+    return 3.0 * m->A * (1.0 - 2.0 * m->poisson) / (2.0 * (1.0 + m->poisson));
+}
+
+/* thermal softening of strength: full below the incipient-vaporisation
+ * energy, none above complete vaporisation, linear in between */
+double orc_softening(const orc_mat *m, double e)
+{
+    double E = e > 0.0 ? e : 0.0;
+    return dmin(dmax((m->Ecv - E) / (m->Ecv - m->Eiv), 0.0), 1.0);
+}
+
+/* mixture state of cell c: shared material density and energy, weights f_m/phi */
+static void mixture(const orc_ctx *x, int c, const double *rho, const double *I,
+                    double *const *f, double *p_o, double *c2_o, double *G_o,
+                    double *Y_o, double *rmat_o, double *phi_o, double *sx_o)
+{
+    double phi = 0.0;
+    for (int m = 0; m < x->nmat; m++) phi += f[m][c];
+    double den = phi > PHI_EPS ? phi : PHI_EPS;
+    double rm = rho[c] / den;
+    double p = 0.0, c2 = 0.0, G = 0.0;
+    double wm[ORC_MAX_MAT];
+    for (int m = 0; m < x->nmat; m++) {
+        double pm, c2m;
+        wm[m] = f[m][c] / den;
+        orc_tillotson(&x->m[m], rm, I[c], &pm, &c2m);
+        pm = dmax(pm, x->m[m].p_min);
+        c2m = dmax(c2m, x->m[m].c_floor_frac * x->m[m].A / x->m[m].rho0);
+        p += wm[m] * pm;
+        c2 += wm[m] * c2m;
+        /* shear modulus from the local bulk modulus K = rho c^2 at a fixed
+         * Poisson ratio (equals the reference value at rho0, E = 0) */
+        G += wm[m] * (orc_softening(&x->m[m], I[c]) * (x->Gm[m] * (rm * c2m)));
+    }
+    double Y = 0.0, pmin = 0.0, ps = 0.0;
+    for (int m = 0; m < x->nmat; m++) {
+        Y += wm[m] * (orc_softening(&x->m[m], I[c]) * orc_yield(&x->m[m], p));
+        pmin += wm[m] * x->m[m].p_min;
+        ps += wm[m] * (PCAV_FRAC * x->m[m].A);
+    }
+    /* expansion weight of the material: 1 above its tension floor + ps */
+    double d = p - pmin;
+    *sx_o = d >= ps ? 1.0 : (ps > 0.0 ? dmax(d, 0.0) / ps : 0.0);
+    *p_o = p;
+    *c2_o = c2;
+    *G_o = G;
+    *Y_o = Y;
+    *rmat_o = rm;
+    *phi_o = phi;
+}
+
+/* ========================================================================
+ * Cell kinematics: face-mean velocities, flux-form divergence and the
+ * strain-rate / spin components of cell (i, j) in r-z.
+ * ======================================================================== */
+typedef struct {
+    double ur_w, ur_e, uz_s, uz_n; /* face-mean normal velocities */
+    double Ur_w, Ur_e, Uz_s, Uz_n; /* face volume rates (area x velocity) */
+    double D, Dr, Dz;              /* flux-form divergence and its r / z parts */
+    double err, ezz, ett, erz, om, dvr_dz, dvz_dr;
+} kin_t;
+
+/* Axial faces weight their two nodes by the r-weighted areas of the node
+ * dual cells they cut, a_E(i) = (r_{i+1/2}^2 - r_i^2)/2 and
+ * a_W(i+1) = (r_{i+1}^2 - r_{i+1/2}^2)/2 (which sum to the face area); this
+ * makes the control-volume node force the exact gradient of the discrete
+ * cell volumes, so stress work and kinetic energy balance, also on the axis. */
+static void kinematics(const orc_grid *g, int i, const double *vr, const double *vz, kin_t *k)
+{
+    /* vr, vz ordered SW, SE, NW, NE (nodes (i,j), (i+1,j), (i,j+1), (i+1,j+1)) */
+    double rw = (double)i * g->dr, re = (double)(i + 1) * g->dr;
+    double rc = ((double)i + 0.5) * g->dr;
+    double Arw = rw * g->dz, Are = re * g->dz, Az = rc * g->dr, V = Az * g->dz;
+    double aw = 0.5 * (rc * rc - rw * rw), ae = 0.5 * (re * re - rc * rc);
+    k->ur_w = 0.5 * (vr[0] + vr[2]);
+    k->ur_e = 0.5 * (vr[1] + vr[3]);
+    k->Ur_w = Arw * k->ur_w;
+    k->Ur_e = Are * k->ur_e;
+    k->Uz_s = aw * vz[0] + ae * vz[1];
+    k->Uz_n = aw * vz[2] + ae * vz[3];
+    k->uz_s = k->Uz_s / Az;
+    k->uz_n = k->Uz_n / Az;
+    k->Dr = (k->Ur_e - k->Ur_w) / V;
+    k->Dz = (k->Uz_n - k->Uz_s) / V;
+    k->D = ((k->Ur_e - k->Ur_w) + (k->Uz_n - k->Uz_s)) / V;
+    k->err = (k->ur_e - k->ur_w) / g->dr;
+    k->ezz = (k->Uz_n - k->Uz_s) / V;
+    k->ett = (0.5 * (k->ur_w + k->ur_e)) / rc;
+    k->dvr_dz = ((aw * vr[2] + ae * vr[3]) - (aw * vr[0] + ae * vr[1])) / V;
+    k->dvz_dr = (0.5 * (vz[1] + vz[3]) - 0.5 * (vz[0] + vz[2])) / g->dr;
+    k->erz = 0.5 * (k->dvr_dz + k->dvz_dr);
+    k->om = 0.5 * (k->dvr_dz - k->dvz_dr);
+}
+
+void orc_cell_kinematics(const orc_grid *g, int32_t i, const double *vr, const double *vz, double *out)
+{
+    kin_t k;
+    kinematics(g, i, vr, vz, &k);
+    out[0] = k.err;
+    out[1] = k.ezz;
+    out[2] = k.ett;
+    out[3] = k.erz;
+    out[4] = k.om;
+    out[5] = k.D;
+}
+
+/* Jaumann-rate elastic trial stress and radial return onto Y (strength model,
+ * Table 1). rates = (e_rr, e_zz, e_tt, e_rz, omega); s = (s_rr, s_zz, s_rz). */
+void orc_stress_update(double G, double Y, double dt, const double *rt, double *s)
+{
+    double srr = s[0], szz = s[1], srz = s[2];
+    double tr3 = ((rt[0] + rt[1]) + rt[2]) / 3.0;
+    double om = rt[4];
+    double dsrr = 2.0 * G * (rt[0] - tr3) + 2.0 * om * srz;
+    double dszz = 2.0 * G * (rt[1] - tr3) - 2.0 * om * srz;
+    double dsrz = 2.0 * G * rt[3] + om * (szz - srr);
+    srr = srr + dt * dsrr;
+    szz = szz + dt * dszz;
+    srz = srz + dt * dsrz;
+    double J2 = srr * srr + szz * szz + srr * szz + srz * srz;
+    double seq = sqrt(3.0 * J2);
+    if (seq > Y) {
+        double fac = Y / seq;
+        srr = srr * fac;
+        szz = szz * fac;
+        srz = srz * fac;
+    }
+    s[0] = srr;
+    s[1] = szz;
+    s[2] = srz;
+}
+
+/* Material volume ratio over a Lagrangian step whose cell volume ratio is J,
+ * for a cell whose material fills the fraction phi. Compression closes the
+ * void first and only then compresses the material. Expansion stretches the
+ * material only while its pressure is above its tension floor (weight s in
+ * [0, 1], a ramp over a small pressure scale); at the floor the void opens
+ * instead (cavitation / spall). Full cells with s = 1 give exactly J. */
+static double material_ratio(double J, double phi, double s)
+{
+    if (J < 1.0) return dmin(1.0, J / dmax(phi, PHI_EPS));
+    return 1.0 + (J - 1.0) * s;
+}
+
+/* ========================================================================
+ * Construction
+ * ======================================================================== */
+static double *zalloc(size_t n) { return (double *)calloc(n ? n : 1, sizeof(double)); }
+
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
+/* PML damping d(y) = (3c / 2 delta) (y / delta)^2 log(1/R)  (Sec. 3) */
+static double pml_d(double c, double delta, double y, double R)
+{
+    return 1.5 * c / delta * (y / delta) * (y / delta) * log(1.0 / R);
+}
+
+orc_ctx *orc_create(const orc_grid *g, const orc_mat *mats, const orc_pml *pml)
+{
+    if (!g || !mats || !pml) return NULL;
+    if (g->n_r < 1 || g->n_z < 1 || g->pml_r < 0 || g->pml_b < 0) return NULL;
+    if (g->nmat < 1 || g->nmat > ORC_MAX_MAT) return NULL;
+    if (!(g->dr > 0) || !(g->dz > 0) || !(g->cfl > 0) || g->cfl > 1.0) return NULL;
+    orc_ctx *x = (orc_ctx *)calloc(1, sizeof(orc_ctx));
+    x->g = *g;
+    x->pml = *pml;
+    x->nmat = g->nmat;
+    for (int m = 0; m < g->nmat; m++) {
+        x->m[m] = mats[m];
+        x->Gm[m] = mats[m].strength ? 3.0 * (1.0 - 2.0 * mats[m].poisson) / (2.0 * (1.0 + mats[m].poisson)) : 0.0;
+        if (mats[m].strength) x->any_strength = 1;
+        if (mats[m].rho0 > x->rho_ref) x->rho_ref = mats[m].rho0;
+    }
+    int NR = g->n_r + g->pml_r, NZ = g->n_z + g->pml_b;
+    x->NR = NR;
+    x->NZ = NZ;
+    x->NC = NR * NZ;
+    x->NN = (NR + 1) * (NZ + 1);
+    size_t NC = x->NC, NN = x->NN, NRF = (size_t)(NR + 1) * NZ, NAF = (size_t)NR * (NZ + 1);
+
+    x->rho = zalloc(NC);
+    x->I = zalloc(NC);
+    x->srr = zalloc(NC);
+    x->szz = zalloc(NC);
+    x->srz = zalloc(NC);
+    x->vr = zalloc(NN);
+    x->vz = zalloc(NN);
+    x->rho_n = zalloc(NC);
+    x->I_n = zalloc(NC);
+    x->srr_n = zalloc(NC);
+    x->szz_n = zalloc(NC);
+    x->srz_n = zalloc(NC);
+    x->vr_n = zalloc(NN);
+    x->vz_n = zalloc(NN);
+    for (int m = 0; m < ORC_MAX_MAT; m++) {
+        x->f[m] = zalloc(NC);
+        x->f_n[m] = zalloc(NC);
+        x->fL[m] = zalloc(NC);
+    }
+    x->dcz = zalloc(NZ);
+    x->dnz = zalloc(NZ + 1);
+    x->dcr = zalloc(NR);
+    x->dnr = zalloc(NR + 1);
+    double **cellaux[] = {&x->phi1b, &x->phi3b, &x->psi2b, &x->phi1r, &x->phi3r, &x->psi2r,
+                          &x->rref, &x->msink, &x->p, &x->c2, &x->G, &x->Y, &x->rmat, &x->phi, &x->sx,
+                          &x->Q, &x->sgrr, &x->sgzz, &x->sgtt, &x->sgrz, &x->J, &x->IL,
+                          &x->sLrr, &x->sLzz, &x->sLrz};
+    for (size_t k = 0; k < sizeof(cellaux) / sizeof(cellaux[0]); k++) *cellaux[k] = zalloc(NC);
+    double **nodeaux[] = {&x->phi2b_r, &x->phi2b_z, &x->psi1b_r, &x->psi1b_z, &x->phi2r_r,
+                          &x->phi2r_z, &x->psi1r_r, &x->psi1r_z, &x->vLr, &x->vLz, &x->heat};
+    for (size_t k = 0; k < sizeof(nodeaux) / sizeof(nodeaux[0]); k++) *nodeaux[k] = zalloc(NN);
+    x->dVr = zalloc(NRF);
+    x->Fr = zalloc(NRF);
+    x->dVre = zalloc(NRF);
+    x->dVz = zalloc(NAF);
+    x->Fz = zalloc(NAF);
+    x->dVze = zalloc(NAF);
+    x->lam = zalloc(NC);
+    x->outv = zalloc(NC);
+    x->mout_col = zalloc(NR);
+    x->eout_col = zalloc(NR);
+
+    /* damping profiles; y is measured from the inner face of each layer,
+     * at cell centres for cell quantities and at nodes for node quantities */
+    if (pml->enabled) {
+        double c = pml->c_ref;
+        if (!(c > 0)) {
+            const orc_mat *m0 = &mats[0];
+            c = sqrt((m0->A + (4.0 / 3.0) * orc_shear_modulus(m0)) / m0->rho0);
+        }
+        if (g->pml_b > 0) {
+            double delta = g->pml_b * g->dz;
+            for (int j = 0; j < g->pml_b; j++)
+                x->dcz[j] = pml_d(c, delta, ((double)(g->pml_b - j) - 0.5) * g->dz, pml->R);
+            for (int j = 0; j < g->pml_b; j++)
+                x->dnz[j] = pml_d(c, delta, (double)(g->pml_b - j) * g->dz, pml->R);
+        }
+        if (g->pml_r > 0) {
+            double delta = g->pml_r * g->dr;
+            for (int i = g->n_r; i < NR; i++)
+                x->dcr[i] = pml_d(c, delta, ((double)(i - g->n_r) + 0.5) * g->dr, pml->R);
+            for (int i = g->n_r + 1; i <= NR; i++)
+                x->dnr[i] = pml_d(c, delta, (double)(i - g->n_r) * g->dr, pml->R);
+        }
+    }
+    return x;
+}
+
+void orc_destroy(orc_ctx *x)
+{
+    if (!x) return;
+    double *all[] = {x->rho, x->I, x->srr, x->szz, x->srz, x->vr, x->vz, x->rho_n, x->I_n,
+                     x->srr_n, x->szz_n, x->srz_n, x->vr_n, x->vz_n, x->dcz, x->dnz, x->dcr,
+                     x->dnr, x->phi1b, x->phi3b, x->psi2b, x->phi1r, x->phi3r, x->psi2r,
+                     x->rref, x->msink, x->p, x->c2, x->G, x->Y, x->rmat, x->phi, x->sx, x->Q,
+                     x->sgrr, x->sgzz, x->sgtt, x->sgrz, x->J, x->IL, x->sLrr, x->sLzz,
+                     x->sLrz, x->phi2b_r, x->phi2b_z, x->psi1b_r, x->psi1b_z, x->phi2r_r,
+                     x->phi2r_z, x->psi1r_r, x->psi1r_z, x->vLr, x->vLz, x->heat, x->dVr, x->Fr,
+                     x->dVz, x->Fz, x->dVre, x->dVze, x->lam, x->outv, x->mout_col, x->eout_col};
+    for (size_t k = 0; k < sizeof(all) / sizeof(all[0]); k++) free(all[k]);
+    for (int m = 0; m < ORC_MAX_MAT; m++) {
+        free(x->f[m]);
+        free(x->f_n[m]);
+        free(x->fL[m]);
+    }
+    free(x);
+}
+
+/* ========================================================================
+ * Time step (Sec. 7): dt <= C0 min(dr, dz) / (|v| + c), evaluated per cell
+ * with the longitudinal speed and the largest corner speed; cells whose
+ * volume fraction is below W_LO are ignored, with a continuous ramp to W_HI.
+ * ======================================================================== */
+static double dt_candidate_min(orc_ctx *x)
+{
+    int NR = x->NR, NZ = x->NZ;
+    double L = dmin(x->g.dr, x->g.dz);
+    double best = INFINITY;
+#pragma omp parallel for schedule(static) reduction(min : best)
+    for (int j = 0; j < NZ; j++) {
+        for (int i = 0; i < NR; i++) {
+            int c = CI(i, j);
+            double p, c2, G, Y, rm, phi, sx;
+            mixture(x, c, x->rho, x->I, x->f, &p, &c2, &G, &Y, &rm, &phi, &sx);
+            double cl2 = c2 + (4.0 / 3.0) * G / dmax(rm, x->rho_ref * RHO_DEN_FLOOR);
+            double cl = sqrt(cl2);
+            int nd[4] = {NI(i, j), NI(i + 1, j), NI(i, j + 1), NI(i + 1, j + 1)};
+            double u = 0.0;
+            for (int k = 0; k < 4; k++) {
+                double s = sqrt(x->vr[nd[k]] * x->vr[nd[k]] + x->vz[nd[k]] * x->vz[nd[k]]);
+                u = dmax(u, s);
+            }
+            double w = dmin(dmax((phi - W_LO) / (W_HI - W_LO), 0.0), 1.0);
+            if (w > 0.0) {
+                double cand = x->g.cfl * L / ((cl + u) * w);
+                if (cand < best) best = cand;
+            }
+        }
+    }
+    return best;
+}
+
+static void start_run(orc_ctx *x)
+{
+    int NR = x->NR;
+    memcpy(x->rref, x->rho, sizeof(double) * x->NC);
+    double **cz[] = {&x->phi1b, &x->phi3b, &x->psi2b, &x->phi1r, &x->phi3r, &x->psi2r, &x->msink};
+    for (size_t k = 0; k < sizeof(cz) / sizeof(cz[0]); k++) memset(*cz[k], 0, sizeof(double) * x->NC);
+    double **nz[] = {&x->phi2b_r, &x->phi2b_z, &x->psi1b_r, &x->psi1b_z,
+                     &x->phi2r_r, &x->phi2r_z, &x->psi1r_r, &x->psi1r_z};
+    for (size_t k = 0; k < sizeof(nz) / sizeof(nz[0]); k++) memset(*nz[k], 0, sizeof(double) * x->NN);
+    memset(x->mout_col, 0, sizeof(double) * NR);
+    memset(x->eout_col, 0, sizeof(double) * NR);
+    x->t = 0.0;
+    x->cycle = 0;
+    x->err = 0;
+    x->err_cycle = -1;
+    double dt = dmin(dt_candidate_min(x), x->g.dt_max);
+    if (x->g.t_stop > 0) dt = dmin(dt, x->g.t_stop);
+    x->dt = dt;
+    x->dt_prev = 0.0;
+}
+
+/* boundary conditions (Sec. 4): symmetry axis and outer side free-slip
+ * (v_r = 0), bottom no-slip (v = 0), top open unless closed */
+static void apply_bc(orc_ctx *x, double *vr, double *vz)
+{
+    int NR = x->NR, NZ = x->NZ;
+    for (int j = 0; j <= NZ; j++) {
+        vr[NI(0, j)] = 0.0;
+        vr[NI(NR, j)] = 0.0;
+    }
+    for (int i = 0; i <= NR; i++) {
+        vr[NI(i, 0)] = 0.0;
+        vz[NI(i, 0)] = 0.0;
+        if (x->g.top_closed) vz[NI(i, NZ)] = 0.0;
+    }
+}
+
+/* scene: target half-space (material 0) below surface_j, spherical
+ * projectile (material 1, or 0 when nmat = 1) resting on the surface at the
+ * axis and moving downward; momentum-exact nodal velocities */
+int orc_init_scene(orc_ctx *x, const orc_scene *s)
+{
+    if (!x || !s || s->subsample < 1 || !(s->radius > 0)) return ORC_E_INVALID;
+    int NR = x->NR, NZ = x->NZ, S = s->subsample;
+    int mp = x->nmat > 1 ? 1 : 0;
+    double R = s->radius, zc = (double)s->surface_j * x->g.dz + R;
+    double *fp = zalloc(x->NC);
+    for (int j = 0; j < NZ; j++) {
+        for (int i = 0; i < NR; i++) {
+            double num = 0.0, den = 0.0;
+            for (int l = 0; l < S; l++) {
+                double zl = ((double)j + ((double)l + 0.5) / (double)S) * x->g.dz;
+                for (int k = 0; k < S; k++) {
+                    double rk = ((double)i + ((double)k + 0.5) / (double)S) * x->g.dr;
+                    double dzl = zl - zc;
+                    if (rk * rk + dzl * dzl <= R * R) num += rk;
+                    den += rk;
+                }
+            }
+            fp[CI(i, j)] = num / den;
+        }
+    }
+    for (int j = 0; j < NZ; j++) {
+        for (int i = 0; i < NR; i++) {
+            int c = CI(i, j);
+            for (int m = 0; m < x->nmat; m++) x->f[m][c] = 0.0;
+            double ft = j < s->surface_j ? 1.0 : 0.0;
+            x->f[0][c] = ft;
+            x->f[mp][c] = x->f[mp][c] + fp[c];
+            double rho = 0.0;
+            for (int m = 0; m < x->nmat; m++) rho += x->f[m][c] * x->m[m].rho0;
+            x->rho[c] = rho;
+            x->I[c] = 0.0;
+            x->srr[c] = x->szz[c] = x->srz[c] = 0.0;
+        }
+    }
+    /* node velocity = -v_imp * (projectile mass) / (total mass) over the four
+     * cells around the node (quadrants SW, SE, NW, NE) */
+    for (int j = 0; j <= NZ; j++) {
+        for (int i = 0; i <= NR; i++) {
+            double Mt = 0.0, Mp = 0.0;
+            int qi[4] = {i - 1, i, i - 1, i}, qj[4] = {j - 1, j - 1, j, j};
+            for (int q = 0; q < 4; q++) {
+                if (qi[q] < 0 || qi[q] >= NR || qj[q] < 0 || qj[q] >= NZ) continue;
+                int c = CI(qi[q], qj[q]);
+                double V = vol_c(x, qi[q]);
+                Mt += x->rho[c] * V;
+                Mp += fp[c] * x->m[mp].rho0 * V;
+            }
+            x->vr[NI(i, j)] = 0.0;
+            x->vz[NI(i, j)] = Mt > 0.0 ? -s->v_imp * (Mp / Mt) : 0.0;
+        }
+    }
+    free(fp);
+    apply_bc(x, x->vr, x->vz);
+    start_run(x);
+    return ORC_OK;
+}
+
+int orc_set_fields(orc_ctx *x, const double *rho, const double *I, const double *f,
+                   const double *s, const double *v)
+{
+    if (!x || !rho || !I || !f || !v) return ORC_E_INVALID;
+    size_t NC = x->NC, NN = x->NN;
+    memcpy(x->rho, rho, sizeof(double) * NC);
+    memcpy(x->I, I, sizeof(double) * NC);
+    for (int m = 0; m < x->nmat; m++) memcpy(x->f[m], f + m * NC, sizeof(double) * NC);
+    if (s) {
+        memcpy(x->srr, s, sizeof(double) * NC);
+        memcpy(x->szz, s + NC, sizeof(double) * NC);
+        memcpy(x->srz, s + 2 * NC, sizeof(double) * NC);
+    } else {
+        memset(x->srr, 0, sizeof(double) * NC);
+        memset(x->szz, 0, sizeof(double) * NC);
+        memset(x->srz, 0, sizeof(double) * NC);
+    }
+    memcpy(x->vr, v, sizeof(double) * NN);
+    memcpy(x->vz, v + NN, sizeof(double) * NN);
+    start_run(x);
+    return ORC_OK;
+}
+
+/* ========================================================================
+ * One cycle
+ * ======================================================================== */
+
+/* (a) per cell: EoS, artificial viscosity from the start-of-cycle velocity
+ * divergence, total stress sigma = phi (s - (p + Q) I) */
+static void phase_cell_stress(orc_ctx *x)
+{
+    int NR = x->NR, NZ = x->NZ;
+    double L = dmin(x->g.dr, x->g.dz);
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < NZ; j++) {
+        for (int i = 0; i < NR; i++) {
+            int c = CI(i, j);
+            double p, c2, G, Y, rm, phi, sx;
+            mixture(x, c, x->rho, x->I, x->f, &p, &c2, &G, &Y, &rm, &phi, &sx);
+            double vr4[4] = {x->vr[NI(i, j)], x->vr[NI(i + 1, j)], x->vr[NI(i, j + 1)], x->vr[NI(i + 1, j + 1)]};
+            double vz4[4] = {x->vz[NI(i, j)], x->vz[NI(i + 1, j)], x->vz[NI(i, j + 1)], x->vz[NI(i + 1, j + 1)]};
+            kin_t k;
+            kinematics(&x->g, i, vr4, vz4, &k);
+            /* compression felt by the material (void closes first) */
+            double Jn = 1.0 + x->dt * k.D;
+            double Dm = Jn < 1.0 ? (1.0 - material_ratio(Jn, phi, sx)) / x->dt : 0.0;
+            double Ld = L * Dm;
+            double Q = rm * (x->g.q_quad * Ld * Ld + x->g.q_lin * sqrt(c2) * Ld);
+            double P = p + Q;
+            double stt = -(x->srr[c] + x->szz[c]);
+            x->p[c] = p;
+            x->c2[c] = c2;
+            x->G[c] = G;
+            x->Y[c] = Y;
+            x->rmat[c] = rm;
+            x->phi[c] = phi;
+            x->sx[c] = sx;
+            x->Q[c] = Q;
+            x->sgrr[c] = phi * (x->srr[c] - P);
+            x->sgzz[c] = phi * (x->szz[c] - P);
+            x->sgtt[c] = phi * (stt - P);
+            x->sgrz[c] = phi * x->srz[c];
+        }
+    }
+}
+
+/* (b) per node: control-volume force of eq. (1) over the dual cell, with the
+ * hoop stress, acceleration, PML psi1 (Sec. 3), boundary conditions -> v^L */
+static void phase_node_force(orc_ctx *x)
+{
+    int NR = x->NR, NZ = x->NZ;
+    double dt = x->dt, hdz = 0.5 * x->g.dz;
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j <= NZ; j++) {
+        for (int i = 0; i <= NR; i++) {
+            /* quadrant cells: NE = (i,j), NW = (i-1,j), SE = (i,j-1), SW = (i-1,j-1) */
+            double srr[4] = {0, 0, 0, 0}, szz[4] = {0, 0, 0, 0}, stt[4] = {0, 0, 0, 0},
+                   srz[4] = {0, 0, 0, 0}, rh[4] = {0, 0, 0, 0};
+            int qi[4] = {i, i - 1, i, i - 1}, qj[4] = {j, j, j - 1, j - 1}; /* NE NW SE SW */
+            for (int q = 0; q < 4; q++) {
+                if (qi[q] < 0 || qi[q] >= NR || qj[q] < 0 || qj[q] >= NZ) continue;
+                int c = CI(qi[q], qj[q]);
+                srr[q] = x->sgrr[c];
+                szz[q] = x->sgzz[c];
+                stt[q] = x->sgtt[c];
+                srz[q] = x->sgrz[c];
+                rh[q] = x->rho[c];
+            }
+            double rN = (double)i * x->g.dr;
+            double rE = ((double)i + 0.5) * x->g.dr;
+            double rW = ((double)i - 0.5) * x->g.dr;
+            double aE = i < NR ? 0.5 * (rE * rE - rN * rN) : 0.0;
+            double aW = i > 0 ? 0.5 * (rN * rN - rW * rW) : 0.0;
+            /* r-direction (radial faces + hoop) and z-direction (axial faces) parts */
+            double Frr = hdz * ((rE * (srr[0] - stt[0]) + rN * stt[0]) + (rE * (srr[2] - stt[2]) + rN * stt[2]))
+                       - hdz * ((rW * (srr[1] - stt[1]) + rN * stt[1]) + (rW * (srr[3] - stt[3]) + rN * stt[3]));
+            double Frz = (aW * srz[1] + aE * srz[0]) - (aW * srz[3] + aE * srz[2]);
+            double Fzr = hdz * (rE * (srz[0] + srz[2]) - rW * (srz[1] + srz[3]));
+            double Fzz = (aW * szz[1] + aE * szz[0]) - (aW * szz[3] + aE * szz[2]);
+            double Fr = Frr + Frz, Fz = Fzr + Fzz;
+            double VcE = aE * hdz, VcW = aW * hdz;
+            double macc = VcE * (rh[0] + rh[2]) + VcW * (rh[1] + rh[3]);
+            double nzh = (double)((j < NZ) + (j > 0));
+            double Vd = (VcE + VcW) * nzh;
+            double mt = dmax(macc, M_ACC_EPS * x->rho_ref * Vd);
+            int n = NI(i, j);
+            double db = x->dnz[j], drr = x->dnr[i];
+            double psr = x->psi1b_r[n] + x->psi1r_r[n];
+            double psz = x->psi1b_z[n] + x->psi1r_z[n];
+            double Fer = Fr - Vd * psr, Fez = Fz - Vd * psz;
+            x->vLr[n] = x->vr[n] + dt * (Fer / mt);
+            x->vLz[n] = x->vz[n] + dt * (Fez / mt);
+            if (db > 0.0) {
+                x->psi1b_r[n] = x->psi1b_r[n] - dt * db * (Frr / Vd);
+                x->psi1b_z[n] = x->psi1b_z[n] - dt * db * (Fzr / Vd);
+            }
+            if (drr > 0.0) {
+                x->psi1r_r[n] = x->psi1r_r[n] - dt * drr * (Frz / Vd);
+                x->psi1r_z[n] = x->psi1r_z[n] - dt * drr * (Fzz / Vd);
+            }
+        }
+    }
+    apply_bc(x, x->vLr, x->vLz);
+}
+
+/* (c) per cell: Lagrangian update -- strain rates from v^L, deviatoric stress
+ * (Jaumann rate + radial return), internal energy of eq. (2) with PML psi2,
+ * Lagrangian volume ratio J = V^L / V */
+static void phase_cell_lagrange(orc_ctx *x)
+{
+    int NR = x->NR, NZ = x->NZ;
+    double dt = x->dt;
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < NZ; j++) {
+        for (int i = 0; i < NR; i++) {
+            int c = CI(i, j);
+            double vr4[4] = {x->vLr[NI(i, j)], x->vLr[NI(i + 1, j)], x->vLr[NI(i, j + 1)], x->vLr[NI(i + 1, j + 1)]};
+            double vz4[4] = {x->vLz[NI(i, j)], x->vLz[NI(i + 1, j)], x->vLz[NI(i, j + 1)], x->vLz[NI(i + 1, j + 1)]};
+            kin_t k;
+            kinematics(&x->g, i, vr4, vz4, &k);
+            double s[3] = {x->srr[c], x->szz[c], x->srz[c]};
+            if (x->any_strength) {
+                double rt[5] = {k.err, k.ezz, k.ett, k.erz, k.om};
+                orc_stress_update(x->G[c], x->Y[c], dt, rt, s);
+            }
+            /* the deviatoric power uses s^n, the stress that produced the node
+             * forces, so the step's work equals the forces' work exactly */
+            double s0rr = x->srr[c], s0zz = x->szz[c], s0rz = x->srz[c];
+            double stt = -(s0rr + s0zz);
+            double P = x->p[c] + x->Q[c];
+            double sde = ((s0rr * k.err + s0zz * k.ezz) + stt * k.ett) + 2.0 * s0rz * k.erz;
+            double J = 1.0 + dt * k.D;
+            double Jm = material_ratio(J, x->phi[c], x->sx[c]);
+            /* specific work over the step: deviatoric power minus P dV, with the
+             * cell's volume change (the work of the phi-scaled stress) */
+            double Wdt = dt * sde - P * (J - 1.0);
+            double rden = dmax(x->rmat[c], x->rho_ref * RHO_DEN_FLOOR);
+            double rt_ = dmax(x->rho[c], x->rho_ref * PML_RHO_FLOOR);
+            double psi2 = x->psi2b[c] + x->psi2r[c];
+            /* Symplectic Euler (the grid moves with v^L) makes the p dV work
+             * fall short of the kinetic-energy change by m |v^L - v^n|^2 / 2
+             * per node; each corner mass of the node keeps its share, so the
+             * cell gains sum over corners |dv|^2 / 2 * (corner volume / V). */
+            double kd[4];
+            int nd[4] = {NI(i, j), NI(i + 1, j), NI(i, j + 1), NI(i + 1, j + 1)}; /* SW SE NW NE */
+            for (int q = 0; q < 4; q++) {
+                double dvr = x->vLr[nd[q]] - x->vr[nd[q]], dvz = x->vLz[nd[q]] - x->vz[nd[q]];
+                kd[q] = 0.5 * (dvr * dvr + dvz * dvz);
+            }
+            double rN0 = (double)i * x->g.dr, rC = ((double)i + 0.5) * x->g.dr, rN1 = (double)(i + 1) * x->g.dr;
+            double V = vol_c(x, i), hdz = 0.5 * x->g.dz;
+            double wW = (0.5 * (rC * rC - rN0 * rN0) * hdz) / V;
+            double wE = (0.5 * (rN1 * rN1 - rC * rC) * hdz) / V;
+            double hL = wW * (kd[0] + kd[2]) + wE * (kd[1] + kd[3]);
+            x->IL[c] = ((x->I[c] + Wdt / rden) + hL) - dt * (psi2 / rt_);
+            for (int m = 0; m < x->nmat; m++) x->fL[m][c] = x->f[m][c] * (Jm / J);
+            double db = x->dcz[j], drr = x->dcr[i];
+            if (db > 0.0) {
+                double Wr = ((s0rr * k.err + stt * k.ett) + s0rz * k.dvz_dr) - P * k.Dr;
+                x->psi2b[c] = x->psi2b[c] - dt * db * (x->phi[c] * Wr);
+            }
+            if (drr > 0.0) {
+                double Wz = (s0zz * k.ezz + s0rz * k.dvr_dz) - P * k.Dz;
+                x->psi2r[c] = x->psi2r[c] - dt * drr * (x->phi[c] * Wz);
+            }
+            x->sLrr[c] = s[0];
+            x->sLzz[c] = s[1];
+            x->sLrz[c] = s[2];
+            x->J[c] = J;
+        }
+    }
+}
+
+/* Lagrangian density and outflow limiter of cell (i, j); outside the grid: void */
+static double rhoL(const orc_ctx *x, int i, int j)
+{
+    int NR = x->NR;
+    if (i < 0 || i >= NR || j < 0 || j >= x->NZ) return 0.0;
+    return x->rho[CI(i, j)] / x->J[CI(i, j)];
+}
+static double lam_at(const orc_ctx *x, int i, int j)
+{
+    int NR = x->NR;
+    if (i < 0 || i >= NR || j < 0 || j >= x->NZ) return 1.0;
+    return x->lam[CI(i, j)];
+}
+
+/* (d) per face: volume swept by the face-mean Lagrangian velocity and the
+ * donor-cell (upwind) mass flux -- eqs. (3)-(5). A donor never gives away
+ * more than its Lagrangian volume: when the volume leaving a cell through its
+ * four faces exceeds V^L, all its outflows are scaled by V^L / outflow. */
+static void phase_faces(orc_ctx *x)
+{
+    int NR = x->NR, NZ = x->NZ;
+    double dt = x->dt;
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < NZ; j++) {
+        for (int i = 0; i <= NR; i++) {
+            double u = 0.5 * (x->vLr[NI(i, j)] + x->vLr[NI(i, j + 1)]);
+            x->dVr[RF(i, j)] = dt * (area_r(x, i) * u);
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j <= NZ; j++) {
+        for (int i = 0; i < NR; i++) {
+            double rw = (double)i * x->g.dr, rc = ((double)i + 0.5) * x->g.dr;
+            double re = (double)(i + 1) * x->g.dr;
+            double aw = 0.5 * (rc * rc - rw * rw), ae = 0.5 * (re * re - rc * rc);
+            x->dVz[AF(i, j)] = dt * (aw * x->vLz[NI(i, j)] + ae * x->vLz[NI(i + 1, j)]);
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < NZ; j++) {
+        for (int i = 0; i < NR; i++) {
+            int c = CI(i, j);
+            double O = ((dmax(-x->dVr[RF(i, j)], 0.0) + dmax(x->dVr[RF(i + 1, j)], 0.0))
+                        + dmax(-x->dVz[AF(i, j)], 0.0)) + dmax(x->dVz[AF(i, j + 1)], 0.0);
+            double VL = vol_c(x, i) * x->J[c];
+            x->outv[c] = O;
+            x->lam[c] = O > VL ? dmax(VL, 0.0) / O : 1.0;
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < NZ; j++) {
+        for (int i = 0; i <= NR; i++) {
+            double dV = x->dVr[RF(i, j)], e = 0.0, F = 0.0;
+            if (dV > 0.0) {
+                e = dV * lam_at(x, i - 1, j);
+                F = e * rhoL(x, i - 1, j);
+            } else if (dV < 0.0) {
+                e = dV * lam_at(x, i, j);
+                F = e * rhoL(x, i, j);
+            }
+            x->dVre[RF(i, j)] = e;
+            x->Fr[RF(i, j)] = F;
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j <= NZ; j++) {
+        for (int i = 0; i < NR; i++) {
+            double dV = x->dVz[AF(i, j)], e = 0.0, F = 0.0;
+            if (dV > 0.0) {
+                e = dV * lam_at(x, i, j - 1);
+                F = e * rhoL(x, i, j - 1);
+            } else if (dV < 0.0) {
+                e = dV * lam_at(x, i, j);
+                F = e * rhoL(x, i, j);
+            }
+            x->dVze[AF(i, j)] = e;
+            x->Fz[AF(i, j)] = F;
+        }
+    }
+}
+
+/* (e) per cell: conservative donor-cell remap back to the Eulerian cell of
+ * mass, specific internal energy, deviatoric stress and volume fractions,
+ * then the PML mass / energy damping with phi1, phi3 (Sec. 3) */
+static void phase_cell_remap(orc_ctx *x)
+{
+    int NR = x->NR, NZ = x->NZ, nm = x->nmat;
+    double dt = x->dt;
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < NZ; j++) {
+        for (int i = 0; i < NR; i++) {
+            int c = CI(i, j);
+            double V = vol_c(x, i);
+            /* faces W, E, S, N: flux (positive along +r / +z), donor cell, inflow flag */
+            double F[4] = {x->Fr[RF(i, j)], x->Fr[RF(i + 1, j)], x->Fz[AF(i, j)], x->Fz[AF(i, j + 1)]};
+            double dV[4] = {x->dVr[RF(i, j)], x->dVr[RF(i + 1, j)], x->dVz[AF(i, j)], x->dVz[AF(i, j + 1)]};
+            double dVe[4] = {x->dVre[RF(i, j)], x->dVre[RF(i + 1, j)], x->dVze[AF(i, j)], x->dVze[AF(i, j + 1)]};
+            int di[4] = {i - 1, i + 1, i, i}, dj[4] = {j, j, j - 1, j + 1};
+            int in[4] = {dV[0] > 0.0, dV[1] < 0.0, dV[2] > 0.0, dV[3] < 0.0};
+            double netin = ((F[0] - F[1]) + F[2]) - F[3];
+            double rho1 = x->rho[c] + netin / V;
+            double M1 = rho1 * V;
+            double min_ = 0.0, nI = 0.0, nsrr = 0.0, nszz = 0.0, nsrz = 0.0, vcut = 0.0;
+            double nf[ORC_MAX_MAT] = {0.0, 0.0};
+            double IL = x->IL[c];
+            double ed[4] = {0.0, 0.0, 0.0, 0.0}; /* energy flux through each face */
+            for (int q = 0; q < 4; q++) {
+                int dc_ok = di[q] >= 0 && di[q] < NR && dj[q] >= 0 && dj[q] < NZ;
+                int dc = dc_ok ? CI(di[q], dj[q]) : -1;
+                if (in[q]) {
+                    double aF = fabs(F[q]), adV = fabs(dVe[q]);
+                    vcut += fabs(dV[q]) - adV;
+                    double Id = dc_ok ? x->IL[dc] : 0.0;
+                    min_ += aF;
+                    nI += aF * (Id - IL);
+                    nsrr += aF * ((dc_ok ? x->sLrr[dc] : 0.0) - x->sLrr[c]);
+                    nszz += aF * ((dc_ok ? x->sLzz[dc] : 0.0) - x->sLzz[c]);
+                    nsrz += aF * ((dc_ok ? x->sLrz[dc] : 0.0) - x->sLrz[c]);
+                    for (int m = 0; m < nm; m++)
+                        nf[m] += adV * ((dc_ok ? x->fL[m][dc] : 0.0) - x->fL[m][c]);
+                    ed[q] = F[q] * Id;
+                } else {
+                    ed[q] = F[q] * IL;
+                }
+            }
+            double den = dmax(dmax(M1, min_), M_REMAP_FLOOR * x->rho_ref * V);
+            double I1 = IL + nI / den;
+            x->srr_n[c] = x->sLrr[c] + nsrr / den;
+            x->szz_n[c] = x->sLzz[c] + nszz / den;
+            x->srz_n[c] = x->sLrz[c] + nsrz / den;
+            double fs = 0.0;
+            double f1[ORC_MAX_MAT];
+            /* volume the limiter kept from leaving this cell, minus void that
+             * arrived in place of limited inflow (both zero without limiting) */
+            double ex = (1.0 - x->lam[c]) * x->outv[c] - vcut;
+            for (int m = 0; m < nm; m++) {
+                f1[m] = dmax(x->fL[m][c] + (nf[m] + x->fL[m][c] * ex) / V, 0.0);
+                fs += f1[m];
+            }
+            for (int m = 0; m < nm; m++) x->f_n[m][c] = f1[m] / dmax(fs, 1.0);
+
+            /* PML: damping of the fluctuation about the initial state plus the
+             * unstretched-direction auxiliary terms; r-faces feed the bottom
+             * layer's phi, z-faces feed the right layer's phi */
+            double db = x->dcz[j], drr = x->dcr[i];
+            if (db > 0.0 || drr > 0.0) {
+                double dsum = db + drr;
+                /* the layer is a sink that never leaves negative mass (ejecta
+                 * crossing the void part of a layer violate the small-fluctuation
+                 * assumption of the derivation) */
+                double rho2 = dmax(rho1 - dt * (dsum * (rho1 - x->rref[c]) + (x->phi1b[c] + x->phi1r[c])), 0.0);
+                double rt_ = dmax(rho1, x->rho_ref * PML_RHO_FLOOR);
+                double I2 = I1 - dt * (dsum * I1 + (x->phi3b[c] + x->phi3r[c]) / rt_);
+                x->msink[c] = x->msink[c] + V * (rho1 - rho2);
+                if (db > 0.0) {
+                    x->phi1b[c] = x->phi1b[c] + db * ((F[1] - F[0]) / V);
+                    x->phi3b[c] = x->phi3b[c] + db * ((ed[1] - ed[0]) / V);
+                }
+                if (drr > 0.0) {
+                    x->phi1r[c] = x->phi1r[c] + drr * ((F[3] - F[2]) / V);
+                    x->phi3r[c] = x->phi3r[c] + drr * ((ed[3] - ed[2]) / V);
+                }
+                rho1 = rho2;
+                I1 = I2;
+            }
+            x->rho_n[c] = rho1;
+            x->I_n[c] = I1;
+            if (j == NZ - 1) {
+                x->mout_col[i] += F[3];
+                x->eout_col[i] += ed[3];
+            }
+        }
+    }
+}
+
+/* (f) per node: momentum remap over the dual cell with dual mass fluxes built
+ * as quarter-sums of the four neighbouring primal fluxes (eq. (4)), donor
+ * velocity, PML phi2 and velocity damping (Sec. 3), boundary conditions */
+static double Fr_at(const orc_ctx *x, int i, int j)
+{
+    int NR = x->NR;
+    if (i < 0 || i > NR || j < 0 || j >= x->NZ) return 0.0;
+    return x->Fr[RF(i, j)];
+}
+static double Fz_at(const orc_ctx *x, int i, int j)
+{
+    int NR = x->NR;
+    if (i < 0 || i >= NR || j < 0 || j > x->NZ) return 0.0;
+    return x->Fz[AF(i, j)];
+}
+
+static void phase_node_remap(orc_ctx *x)
+{
+    int NR = x->NR, NZ = x->NZ;
+    double dt = x->dt, hdz = 0.5 * x->g.dz;
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j <= NZ; j++) {
+        for (int i = 0; i <= NR; i++) {
+            int n = NI(i, j);
+            /* node mass: quarter of the four cell masses (SW, SE, NW, NE) */
+            double M[4] = {0, 0, 0, 0};
+            int qi[4] = {i - 1, i, i - 1, i}, qj[4] = {j - 1, j - 1, j, j};
+            for (int q = 0; q < 4; q++) {
+                if (qi[q] < 0 || qi[q] >= NR || qj[q] < 0 || qj[q] >= NZ) continue;
+                M[q] = x->rho[CI(qi[q], qj[q])] * vol_c(x, qi[q]);
+            }
+            double mL = 0.25 * ((M[0] + M[1]) + (M[2] + M[3]));
+            /* dual faces W, E, S, N */
+            double FD[4];
+            FD[0] = 0.25 * ((Fr_at(x, i - 1, j - 1) + Fr_at(x, i, j - 1)) + (Fr_at(x, i - 1, j) + Fr_at(x, i, j)));
+            FD[1] = 0.25 * ((Fr_at(x, i, j - 1) + Fr_at(x, i + 1, j - 1)) + (Fr_at(x, i, j) + Fr_at(x, i + 1, j)));
+            FD[2] = 0.25 * ((Fz_at(x, i - 1, j - 1) + Fz_at(x, i, j - 1)) + (Fz_at(x, i - 1, j) + Fz_at(x, i, j)));
+            FD[3] = 0.25 * ((Fz_at(x, i - 1, j) + Fz_at(x, i, j)) + (Fz_at(x, i - 1, j + 1) + Fz_at(x, i, j + 1)));
+            if (i == 0) FD[0] = 0.0;
+            if (i == NR) FD[1] = 0.0;
+            if (j == 0) FD[2] = 0.0;
+            int ni[4] = {i - 1, i + 1, i, i}, nj[4] = {j, j, j - 1, j + 1};
+            int in[4] = {FD[0] > 0.0, FD[1] < 0.0, FD[2] > 0.0, FD[3] < 0.0};
+            double m1 = mL + (((FD[0] - FD[1]) + FD[2]) - FD[3]);
+            double vLr = x->vLr[n], vLz = x->vLz[n];
+            double min_ = 0.0, nr = 0.0, nz = 0.0;
+            double upr[4], upz[4];
+            for (int q = 0; q < 4; q++) {
+                int ok = ni[q] >= 0 && ni[q] <= NR && nj[q] >= 0 && nj[q] <= NZ;
+                if (in[q] && ok) {
+                    int d = NI(ni[q], nj[q]);
+                    double aF = fabs(FD[q]);
+                    min_ += aF;
+                    nr += aF * (x->vLr[d] - vLr);
+                    nz += aF * (x->vLz[d] - vLz);
+                    upr[q] = x->vLr[d];
+                    upz[q] = x->vLz[d];
+                } else {
+                    upr[q] = vLr;
+                    upz[q] = vLz;
+                }
+            }
+            double rN = (double)i * x->g.dr;
+            double rE = ((double)i + 0.5) * x->g.dr;
+            double rW = ((double)i - 0.5) * x->g.dr;
+            double aE = i < NR ? 0.5 * (rE * rE - rN * rN) : 0.0;
+            double aW = i > 0 ? 0.5 * (rN * rN - rW * rW) : 0.0;
+            double nzh = (double)((j < NZ) + (j > 0));
+            double Vd = (aE * hdz + aW * hdz) * nzh;
+            double den = dmax(dmax(m1, min_), M_REMAP_FLOOR * x->rho_ref * Vd);
+            double v1r = vLr + nr / den;
+            double v1z = vLz + nz / den;
+            /* kinetic energy the donor-cell mixing destroyed, in shift-invariant
+             * form (exactly zero for a uniform field, >= 0 by Cauchy-Schwarz),
+             * returned as specific heat to the surrounding cells by mass */
+            double kin = 0.0;
+            for (int q = 0; q < 4; q++) {
+                int ok = ni[q] >= 0 && ni[q] <= NR && nj[q] >= 0 && nj[q] <= NZ;
+                if (in[q] && ok) {
+                    double ar = upr[q] - vLr, az = upz[q] - vLz;
+                    kin += fabs(FD[q]) * (ar * ar + az * az);
+                }
+            }
+            double dKE = 0.5 * (kin - (nr * nr + nz * nz) / den);
+            double Mn = 0.0;
+            for (int q = 0; q < 4; q++) {
+                if (qi[q] < 0 || qi[q] >= NR || qj[q] < 0 || qj[q] >= NZ) continue;
+                Mn += x->rho_n[CI(qi[q], qj[q])] * vol_c(x, qi[q]);
+            }
+            x->heat[n] = Mn > M_REMAP_FLOOR * x->rho_ref * Vd ? dmax(dKE, 0.0) / Mn : 0.0;
+            double db = x->dnz[j], drr = x->dnr[i];
+            if (db > 0.0 || drr > 0.0) {
+                double dsum = db + drr;
+                double mt = dmax(m1, M_ACC_EPS * x->rho_ref * Vd);
+                double pr = x->phi2b_r[n] + x->phi2r_r[n];
+                double pz = x->phi2b_z[n] + x->phi2r_z[n];
+                double v2r = v1r - dt * (dsum * v1r + (pr * Vd) / mt);
+                double v2z = v1z - dt * (dsum * v1z + (pz * Vd) / mt);
+                if (db > 0.0) {
+                    x->phi2b_r[n] = x->phi2b_r[n] + db * ((FD[1] * upr[1] - FD[0] * upr[0]) / Vd);
+                    x->phi2b_z[n] = x->phi2b_z[n] + db * ((FD[1] * upz[1] - FD[0] * upz[0]) / Vd);
+                }
+                if (drr > 0.0) {
+                    x->phi2r_r[n] = x->phi2r_r[n] + drr * ((FD[3] * upr[3] - FD[2] * upr[2]) / Vd);
+                    x->phi2r_z[n] = x->phi2r_z[n] + drr * ((FD[3] * upz[3] - FD[2] * upz[2]) / Vd);
+                }
+                v1r = v2r;
+                v1z = v2z;
+            }
+            x->vr_n[n] = v1r;
+            x->vz_n[n] = v1z;
+        }
+    }
+    apply_bc(x, x->vr_n, x->vz_n);
+}
+
+/* (g) per cell: add the specific heat of the remap's kinetic-energy loss
+ * from the four corner nodes */
+static void phase_cell_heat(orc_ctx *x)
+{
+    int NR = x->NR, NZ = x->NZ;
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < NZ; j++) {
+        for (int i = 0; i < NR; i++) {
+            int c = CI(i, j);
+            double h = (x->heat[NI(i, j)] + x->heat[NI(i + 1, j)]) + (x->heat[NI(i, j + 1)] + x->heat[NI(i + 1, j + 1)]);
+            x->I_n[c] = x->I_n[c] + h;
+        }
+    }
+}
+
+static void swap(double **a, double **b)
+{
+    double *t = *a;
+    *a = *b;
+    *b = t;
+}
+
+static int check_state(orc_ctx *x)
+{
+    int bad = 0, neg = 0;
+    size_t NC = x->NC, NN = x->NN;
+    double tol = -NEG_MASS_TOL * x->rho_ref;
+    for (size_t c = 0; c < NC; c++) {
+        double s = x->rho[c] + x->I[c] + x->srr[c] + x->szz[c] + x->srz[c];
+        for (int m = 0; m < x->nmat; m++) s += x->f[m][c];
+        if (!isfinite(s)) bad = 1;
+        if (x->rho[c] < tol) neg = 1;
+    }
+    for (size_t n = 0; n < NN; n++)
+        if (!isfinite(x->vr[n] + x->vz[n])) bad = 1;
+    if (bad) return ORC_E_NONFINITE;
+    if (neg) return ORC_E_NEG_MASS;
+    return ORC_OK;
+}
+
+static int one_cycle(orc_ctx *x)
+{
+    phase_cell_stress(x);
+    phase_node_force(x);
+    phase_cell_lagrange(x);
+    phase_faces(x);
+    phase_cell_remap(x);
+    phase_node_remap(x);
+    phase_cell_heat(x);
+    swap(&x->rho, &x->rho_n);
+    swap(&x->I, &x->I_n);
+    for (int m = 0; m < x->nmat; m++) swap(&x->f[m], &x->f_n[m]);
+    swap(&x->srr, &x->srr_n);
+    swap(&x->szz, &x->szz_n);
+    swap(&x->srz, &x->srz_n);
+    swap(&x->vr, &x->vr_n);
+    swap(&x->vz, &x->vz_n);
+    x->t = x->t + x->dt;
+    x->cycle += 1;
+    int e = check_state(x);
+    /* next time step: Courant limit, growth cap, maximum, stop time */
+    double dt = dmin(dmin(dt_candidate_min(x), x->g.dt_grow * x->dt), x->g.dt_max);
+    if (x->g.t_stop > 0) dt = dmin(dt, dmax(x->g.t_stop - x->t, 0.0));
+    x->dt_prev = x->dt;
+    x->dt = dt;
+    int stopped = x->g.t_stop > 0 && x->t >= x->g.t_stop;
+    if (e == ORC_OK && !stopped && dt < x->g.dt_floor) e = ORC_E_DT_FLOOR;
+    return e;
+}
+
+int orc_step(orc_ctx *x, int32_t n)
+{
+    if (!x || n < 0) return ORC_E_INVALID;
+    if (x->err) return x->err;
+    for (int32_t k = 0; k < n; k++) {
+        int e = one_cycle(x);
+        if (e) {
+            x->err = e;
+            x->err_cycle = (int)x->cycle;
+            return e;
+        }
+    }
+    return ORC_OK;
+}
+
+int orc_get_fields(orc_ctx *x, double *rho, double *I, double *f, double *s, double *v,
+                   double *p, double *c2)
+{
+    if (!x) return ORC_E_INVALID;
+    size_t NC = x->NC, NN = x->NN;
+    if (rho) memcpy(rho, x->rho, sizeof(double) * NC);
+    if (I) memcpy(I, x->I, sizeof(double) * NC);
+    if (f)
+        for (int m = 0; m < x->nmat; m++) memcpy(f + m * NC, x->f[m], sizeof(double) * NC);
+    if (s) {
+        memcpy(s, x->srr, sizeof(double) * NC);
+        memcpy(s + NC, x->szz, sizeof(double) * NC);
+        memcpy(s + 2 * NC, x->srz, sizeof(double) * NC);
+    }
+    if (v) {
+        memcpy(v, x->vr, sizeof(double) * NN);
+        memcpy(v + NN, x->vz, sizeof(double) * NN);
+    }
+    if (p || c2) {
+        for (size_t c = 0; c < NC; c++) {
+            double pp, cc, G, Y, rm, phi, sx;
+            mixture(x, (int)c, x->rho, x->I, x->f, &pp, &cc, &G, &Y, &rm, &phi, &sx);
+            if (p) p[c] = pp;
+            if (c2) c2[c] = cc;
+        }
+    }
+    return ORC_OK;
+}
+
+int orc_get_pml(orc_ctx *x, double *ca, double *na)
+{
+    if (!x) return ORC_E_INVALID;
+    size_t NC = x->NC, NN = x->NN;
+    if (ca) {
+        const double *src[8] = {x->phi1b, x->phi3b, x->psi2b, x->phi1r, x->phi3r, x->psi2r, x->rref, x->msink};
+        for (int k = 0; k < 8; k++) memcpy(ca + k * NC, src[k], sizeof(double) * NC);
+    }
+    if (na) {
+        const double *src[8] = {x->phi2b_r, x->phi2b_z, x->psi1b_r, x->psi1b_z,
+                                x->phi2r_r, x->phi2r_z, x->psi1r_r, x->psi1r_z};
+        for (int k = 0; k < 8; k++) memcpy(na + k * NN, src[k], sizeof(double) * NN);
+    }
+    return ORC_OK;
+}
+
+int orc_get_profiles(orc_ctx *x, double *dcz, double *dnz, double *dcr, double *dnr)
+{
+    if (!x) return ORC_E_INVALID;
+    if (dcz) memcpy(dcz, x->dcz, sizeof(double) * x->NZ);
+    if (dnz) memcpy(dnz, x->dnz, sizeof(double) * (x->NZ + 1));
+    if (dcr) memcpy(dcr, x->dcr, sizeof(double) * x->NR);
+    if (dnr) memcpy(dnr, x->dnr, sizeof(double) * (x->NR + 1));
+    return ORC_OK;
+}
+
+/* compensated (Neumaier) summation in a fixed order */
+typedef struct {
+    double s, c;
+} ksum;
+static void kadd(ksum *k, double v)
+{
+    double t = k->s + v;
+    if (fabs(k->s) >= fabs(v)) k->c += (k->s - t) + v;
+    else k->c += (v - t) + k->s;
+    k->s = t;
+}
+static double kval(const ksum *k) { return k->s + k->c; }
+
+int orc_diag(orc_ctx *x, double *out)
+{
+    if (!x || !out) return ORC_E_INVALID;
+    int NR = x->NR, NZ = x->NZ;
+    ksum mass = {0, 0}, ie = {0, 0}, ke = {0, 0}, mo = {0, 0}, mp = {0, 0}, eo = {0, 0};
+    for (int j = 0; j < NZ; j++)
+        for (int i = 0; i < NR; i++) {
+            int c = CI(i, j);
+            double M = x->rho[c] * vol_c(x, i);
+            kadd(&mass, M);
+            kadd(&ie, M * x->I[c]);
+            kadd(&mp, x->msink[c]);
+        }
+    for (int j = 0; j <= NZ; j++)
+        for (int i = 0; i <= NR; i++) {
+            double M = 0.0;
+            int qi[4] = {i - 1, i, i - 1, i}, qj[4] = {j - 1, j - 1, j, j};
+            double Mq[4] = {0, 0, 0, 0};
+            for (int q = 0; q < 4; q++) {
+                if (qi[q] < 0 || qi[q] >= NR || qj[q] < 0 || qj[q] >= NZ) continue;
+                Mq[q] = x->rho[CI(qi[q], qj[q])] * vol_c(x, qi[q]);
+            }
+            M = 0.25 * ((Mq[0] + Mq[1]) + (Mq[2] + Mq[3]));
+            int n = NI(i, j);
+            kadd(&ke, 0.5 * M * (x->vr[n] * x->vr[n] + x->vz[n] * x->vz[n]));
+        }
+    for (int i = 0; i < NR; i++) {
+        kadd(&mo, x->mout_col[i]);
+        kadd(&eo, x->eout_col[i]);
+    }
+    out[0] = x->t;
+    out[1] = x->dt;
+    out[2] = (double)x->cycle;
+    out[3] = kval(&mass);
+    out[4] = kval(&ie);
+    out[5] = kval(&ke);
+    out[6] = kval(&mo);
+    out[7] = kval(&mp);
+    out[8] = kval(&eo);
+    out[9] = (double)x->err;
+    out[10] = (double)x->err_cycle;
+    out[11] = x->dt_prev;
+    return ORC_OK;
+}

@@ -1,0 +1,113 @@
+/*
+ * salec_oracle.h -- C interface of the plain FP64 CPU oracle.
+ *
+ * TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT. The oracle is the slow,
+ * obviously-correct reference the HIP library is checked against. Only the
+ * test-suite, the smoke check and the benchmark's CPU-baseline leg may load
+ * it. It shares no code, header, table or helper with the HIP library.
+ *
+ * Method: Li et al., "Parallel numerical simulation of impact crater with
+ * perfect matched layers" (SALEc-2D), Sec. 2 eqs. (1)-(5) (SALE operator
+ * split), Sec. 3 (PML), Sec. 4 (boundary conditions), Table 1 (strength
+ * parameters), Sec. 7 (Courant condition). Every point where the paper is
+ * silent is resolved by the readings listed in the repository's design notes;
+ * the oracle and the HIP path follow the same readings.
+ *
+ * Layout: cell (i, j) with i = 0..NR-1 outward from the symmetry axis and
+ * j = 0..NZ-1 upward from the bottom is element j*NR + i. Node (i, j),
+ * i = 0..NR, j = 0..NZ, is element j*(NR+1) + i. NR = n_r + pml_r,
+ * NZ = n_z + pml_b. All quantities are SI; volumes and areas are per radian.
+ */
+#ifndef SALEC_ORACLE_H
+#define SALEC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAX_MAT 2
+
+/* error codes (negative), shared meaning with the product library */
+#define ORC_OK 0
+#define ORC_E_INVALID (-1)
+#define ORC_E_NONFINITE (-4)
+#define ORC_E_NEG_MASS (-5)
+#define ORC_E_DT_FLOOR (-6)
+
+typedef struct {
+    int32_t n_r, n_z;   /* physical cells in r and z                        */
+    int32_t pml_r;      /* PML cells to the right of the physical region    */
+    int32_t pml_b;      /* PML cells below the physical region              */
+    int32_t nmat;       /* 1 or 2 materials                                 */
+    int32_t top_closed; /* 0: open (outflow) top, 1: rigid top wall         */
+    double dr, dz;      /* cell size, m                                     */
+    double cfl;         /* Courant constant C0                               */
+    double dt_grow;     /* max growth factor of dt per cycle                */
+    double dt_max, dt_floor;
+    double t_stop;      /* >0: clip the step so that t never passes t_stop  */
+    double q_lin, q_quad; /* artificial viscosity coefficients C1, C2       */
+} orc_grid;
+
+typedef struct {
+    double rho0, A, B, E0, a, b, alpha, beta, Eiv, Ecv; /* Tillotson       */
+    double p_min;        /* pressure floor, Pa                              */
+    double c_floor_frac; /* c^2 floor = c_floor_frac * A / rho0             */
+    int32_t strength;    /* 0: hydrodynamic, 1: elasto-plastic              */
+    double Y0, mu_f, Ylim, poisson;
+} orc_mat;
+
+typedef struct {
+    int32_t enabled;
+    double R;     /* theoretical reflection coefficient                    */
+    double c_ref; /* <=0: longitudinal speed of material 0 at rest         */
+} orc_pml;
+
+typedef struct {
+    int32_t surface_j;  /* first void row above the target                  */
+    int32_t subsample;  /* S x S sub-samples per cell for the disc fraction */
+    double radius;      /* projectile radius, m                             */
+    double v_imp;       /* impact speed, m/s (downwards)                    */
+} orc_scene;
+
+typedef struct orc_ctx orc_ctx;
+
+orc_ctx *orc_create(const orc_grid *g, const orc_mat *mats, const orc_pml *pml);
+void orc_destroy(orc_ctx *x);
+int orc_set_threads(int n); /* OpenMP thread count; returns threads in use */
+
+int orc_init_scene(orc_ctx *x, const orc_scene *s);
+/* f: nmat*NC values (material-major); s: 3*NC (rr, zz, rz) or NULL;
+ * v: 2*NN (r then z). Starts a new run at t = 0. */
+int orc_set_fields(orc_ctx *x, const double *rho, const double *I,
+                   const double *f, const double *s, const double *v);
+int orc_step(orc_ctx *x, int32_t n);
+/* any pointer may be NULL; p and c2 are evaluated from the current state */
+int orc_get_fields(orc_ctx *x, double *rho, double *I, double *f, double *s,
+                   double *v, double *p, double *c2);
+/* cell_aux: 8*NC = phi1_b, phi3_b, psi2_b, phi1_r, phi3_r, psi2_r, rho_ref, msink
+ * node_aux: 8*NN = phi2_b(r,z), psi1_b(r,z), phi2_r(r,z), psi1_r(r,z) */
+int orc_get_pml(orc_ctx *x, double *cell_aux, double *node_aux);
+/* out[0..11]: t, dt, cycle, mass, internal energy, kinetic energy,
+ * mass_out, mass_pml, ie_out, err, err_cycle, dt_prev */
+int orc_diag(orc_ctx *x, double *out);
+/* damping profiles: dcz[NZ], dnz[NZ+1], dcr[NR], dnr[NR+1] */
+int orc_get_profiles(orc_ctx *x, double *dcz, double *dnz, double *dcr, double *dnr);
+
+/* point functions, exposed for the pins */
+void orc_tillotson(const orc_mat *m, double rho, double e, double *p, double *c2);
+double orc_yield(const orc_mat *m, double p);
+double orc_shear_modulus(const orc_mat *m);
+/* strength factor in [0, 1] from the specific internal energy */
+double orc_softening(const orc_mat *m, double e);
+/* one constitutive update: s[3] in/out, rates = (e_rr, e_zz, e_tt, e_rz, omega) */
+void orc_stress_update(double G, double Y, double dt, const double *rates, double *s);
+/* strain rates of cell (i, j) from its four node velocities
+ * vr[4], vz[4] ordered SW, SE, NW, NE -> out = (e_rr, e_zz, e_tt, e_rz, omega, D) */
+void orc_cell_kinematics(const orc_grid *g, int32_t i, const double *vr,
+                         const double *vz, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,201 @@
+"""Problem definitions and seeded synthetic inputs.
+
+This module only *describes* problems: grid sizes, material constants, the
+impact scene and seeded parameter draws for ensembles. It holds none of the
+method's arithmetic, so both the HIP library binding and the CPU oracle can
+be driven from the same description without sharing any computation.
+
+Workloads stand in for the paper's vertical-impact simulations (Sec. 4): a
+spherical projectile hitting a half-space in axisymmetric r-z geometry, with
+PML layers on the right and bottom edges (Table 2 lists the same layer
+placement). The paper's Chicxulub set-up needs material laws it does not give,
+so a basalt-like Tillotson half-space is used instead.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+
+@dataclass
+class Material:
+    """Tillotson constants plus optional pressure-dependent strength (Table 1 form)."""
+    rho0: float
+    A: float
+    B: float
+    E0: float
+    a: float
+    b: float
+    alpha: float
+    beta: float
+    Eiv: float
+    Ecv: float
+    p_min: float = 0.0
+    c_floor_frac: float = 0.25
+    strength: int = 0
+    Y0: float = 0.0
+    mu_f: float = 0.0
+    Ylim: float = 0.0
+    poisson: float = 0.25
+
+
+@dataclass
+class Grid:
+    n_r: int
+    n_z: int
+    pml_r: int = 0
+    pml_b: int = 0
+    nmat: int = 1
+    top_closed: int = 0
+    dr: float = 1.0
+    dz: float = 1.0
+    cfl: float = 0.5
+    dt_grow: float = 1.1
+    dt_max: float = 1e30
+    dt_floor: float = 0.0
+    t_stop: float = 0.0
+    q_lin: float = 0.25
+    q_quad: float = 1.0
+
+    @property
+    def NR(self) -> int:
+        return self.n_r + self.pml_r
+
+    @property
+    def NZ(self) -> int:
+        return self.n_z + self.pml_b
+
+    @property
+    def ncells(self) -> int:
+        return self.NR * self.NZ
+
+    @property
+    def nnodes(self) -> int:
+        return (self.NR + 1) * (self.NZ + 1)
+
+
+@dataclass
+class Pml:
+    enabled: int = 1
+    R: float = 0.01
+    c_ref: float = 0.0  # <= 0: longitudinal speed of material 0 at rest
+
+
+@dataclass
+class Scene:
+    surface_j: int
+    radius: float
+    v_imp: float
+    subsample: int = 8
+
+
+@dataclass
+class Problem:
+    grid: Grid
+    mats: List[Material]
+    pml: Pml = field(default_factory=Pml)
+    scene: Optional[Scene] = None
+    cycles: int = 0
+    precision: str = "fp64"  # "fp64" or "mixed"
+    name: str = ""
+
+    def replace(self, **kw) -> "Problem":
+        return dataclasses.replace(self, **kw)
+
+
+# --------------------------------------------------------------------------
+# materials
+# --------------------------------------------------------------------------
+def basalt(strength: bool = False, Y0: float = 10e6, mu_f: float = 0.8,
+           Ylim: float = 2.5e9) -> Material:
+    """Basalt-like Tillotson half-space: rho0 = 2860 kg/m^3, A = B = 18 GPa,
+    E0 = 487 MJ/kg; a, b, alpha, beta, Eiv, Ecv from the standard basalt set.
+    With strength the tension floor is where the yield curve reaches zero."""
+    m = Material(rho0=2860.0, A=18e9, B=18e9, E0=487e6, a=0.5, b=1.5, alpha=5.0,
+                 beta=5.0, Eiv=4.72e6, Ecv=18.2e6, p_min=0.0, c_floor_frac=0.25)
+    if strength:
+        m.strength = 1
+        m.Y0, m.mu_f, m.Ylim = Y0, mu_f, Ylim
+        m.p_min = -Y0 / mu_f
+    return m
+
+
+def ideal_gas(gamma: float = 1.4) -> Material:
+    """Tillotson with a = gamma - 1 and b = A = B = 0 is exactly an ideal gas."""
+    return Material(rho0=1.0, A=0.0, B=0.0, E0=1.0, a=gamma - 1.0, b=0.0, alpha=5.0,
+                    beta=5.0, Eiv=1.0, Ecv=2.0, p_min=-1e300, c_floor_frac=0.0)
+
+
+# --------------------------------------------------------------------------
+# impact scenes
+# --------------------------------------------------------------------------
+def surface_row(n: int, pml_b: int, radius_cells: int) -> int:
+    """Target surface row: leave 2R + max(4, ceil(R/2)) void rows above it."""
+    h_void = 2 * radius_cells + max(4, math.ceil(radius_cells / 2))
+    return pml_b + n - h_void
+
+
+def impact(n: int, pml: int, radius_cells: int, v_imp: float, nmat: int, strength: bool,
+           cycles: int, precision: str = "fp64", Y0: float = 10e6, name: str = "",
+           dx: float = 1.0, cfl: float = 0.5) -> Problem:
+    g = Grid(n_r=n, n_z=n, pml_r=pml, pml_b=pml, nmat=nmat, dr=dx, dz=dx, cfl=cfl)
+    mat = basalt(strength=strength, Y0=Y0)
+    mats = [mat] * nmat
+    sc = Scene(surface_j=surface_row(n, pml, radius_cells), radius=radius_cells * dx, v_imp=v_imp)
+    return Problem(grid=g, mats=mats, pml=Pml(), scene=sc, cycles=cycles, precision=precision,
+                   name=name)
+
+
+def config_small() -> Problem:
+    """100x100 cells + 20-cell PML, one material, hydrodynamic, R = 10 cells,
+    10 km/s, 500 cycles, plain FP64."""
+    return impact(100, 20, 10, 10e3, nmat=1, strength=False, cycles=500, name="impact-100-hydro-fp64")
+
+
+def config_scale() -> Problem:
+    """1000x1000 cells + 50-cell PML, two materials with strength
+    (Y0 = 10 MPa, friction 0.8, Ylim = 2.5 GPa), R = 50 cells, 15 km/s,
+    5000 cycles, plain FP64."""
+    return impact(1000, 50, 50, 15e3, nmat=2, strength=True, cycles=5000, name="impact-1000-strength-fp64")
+
+
+def config_large(precision: str = "mixed") -> Problem:
+    """4000x4000 cells + 100-cell PML, two materials with strength, R = 200
+    cells, 12 km/s, 2000 cycles."""
+    return impact(4000, 100, 200, 12e3, nmat=2, strength=True, cycles=2000, precision=precision,
+                  name=f"impact-4000-strength-{precision}")
+
+
+def ensemble(seed: int, n: int, side_lo: int, side_hi: int, cycles: int = 1000,
+             precision: str = "fp64") -> List[Problem]:
+    """Seeded ensemble of uneven impacts: side ~ U{side_lo..side_hi},
+    R ~ U{5..40} cells, v ~ U(5, 20) km/s, Y0 ~ U(1, 50) MPa, PML = 10 % of
+    the side (rounded), two materials with strength."""
+    rng = np.random.default_rng(seed)
+    side = rng.integers(side_lo, side_hi + 1, size=n)
+    rad = rng.integers(5, 41, size=n)
+    vel = rng.uniform(5e3, 20e3, size=n)
+    y0 = rng.uniform(1e6, 50e6, size=n)
+    out = []
+    for k in range(n):
+        s = int(side[k])
+        p = (s + 5) // 10
+        out.append(impact(s, p, int(rad[k]), float(vel[k]), nmat=2, strength=True,
+                          cycles=cycles, precision=precision, Y0=float(y0[k]),
+                          name=f"ens{seed}-{k}"))
+    return out
+
+
+def random_state(grid: Grid, seed: int, rho0: float = 2860.0):
+    """Seeded smooth random state (for parity tests away from the impact path):
+    full cells with density within +-2 %, small energies and velocities."""
+    rng = np.random.default_rng(seed)
+    NR, NZ = grid.NR, grid.NZ
+    rho = rho0 * (1.0 + 0.02 * rng.uniform(-1, 1, size=(NZ, NR)))
+    I = 1e4 * rng.uniform(0, 1, size=(NZ, NR))
+    v = 10.0 * rng.uniform(-1, 1, size=(2, NZ + 1, NR + 1))
+    return rho, I, v
