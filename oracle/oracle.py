@@ -65,6 +65,8 @@ def _load():
     lib.orc_diag.argtypes = [P, D]
     lib.orc_get_profiles.argtypes = [P, D, D, D, D]
     lib.orc_tillotson.argtypes = [C.POINTER(_Mat), C.c_double, C.c_double, D, D]
+    lib.orc_exp.argtypes = [C.c_double]
+    lib.orc_exp.restype = C.c_double
     lib.orc_yield.argtypes = [C.POINTER(_Mat), C.c_double]
     lib.orc_yield.restype = C.c_double
     lib.orc_shear_modulus.argtypes = [C.POINTER(_Mat)]
@@ -197,6 +199,10 @@ class Oracle:
 
 
 # ---- point functions ----------------------------------------------------
+def exp(x: float) -> float:
+    return _load().orc_exp(float(x))
+
+
 def tillotson(mat, rho: float, e: float):
     p, c2 = C.c_double(), C.c_double()
     _load().orc_tillotson(C.byref(_mat(mat)), float(rho), float(e), C.byref(p), C.byref(c2))

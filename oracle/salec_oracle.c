@@ -95,6 +95,45 @@ static double area_r(const orc_ctx *x, int i) { return r_node(x, i) * x->g.dz; }
 static double area_z(const orc_ctx *x, int i) { return r_cell(x, i) * x->g.dr; }
 static double vol_c(const orc_ctx *x, int i) { return area_z(x, i) * x->g.dz; }
 
+/* exp(x) by a fixed published method so that every implementation of this
+ * algorithm rounds identically: Cody & Waite range reduction
+ * x = k ln2 + r, |r| <= ln2/2, with ln2 split into a 32-bit head and a tail,
+ * then the Taylor polynomial of e^r to degree 13 in Horner form (truncation
+ * below 1e-17 relative), then scaling by 2^k. Results below e^-700 are
+ * flushed to 0 and above e^709 overflow to +inf. */
+static double exp_cw(double x)
+{
+    if (x != x) return x;
+    if (x < -700.0) return 0.0;
+    if (x > 709.0) return INFINITY;
+    const double inv_ln2 = 0x1.71547652b82fep+0;
+    const double ln2_hi = 0x1.62e42fee00000p-1;
+    const double ln2_lo = 0x1.a39ef35793c76p-33;
+    double kd = floor(x * inv_ln2 + 0.5);
+    double r = (x - kd * ln2_hi) - kd * ln2_lo;
+    double q = 1.0 / 6227020800.0;
+    q = q * r + 1.0 / 479001600.0;
+    q = q * r + 1.0 / 39916800.0;
+    q = q * r + 1.0 / 3628800.0;
+    q = q * r + 1.0 / 362880.0;
+    q = q * r + 1.0 / 40320.0;
+    q = q * r + 1.0 / 5040.0;
+    q = q * r + 1.0 / 720.0;
+    q = q * r + 1.0 / 120.0;
+    q = q * r + 1.0 / 24.0;
+    q = q * r + 1.0 / 6.0;
+    q = q * r + 0.5;
+    q = q * r + 1.0;
+    q = q * r + 1.0;
+    int k = (int)kd;
+    uint64_t bits = (uint64_t)(k + 1023) << 52;
+    double scale;
+    memcpy(&scale, &bits, sizeof scale);
+    return q * scale;
+}
+
+double orc_exp(double x) { return exp_cw(x); }
+
 /* ========================================================================
  * Equation of state (the paper's EoS module is inherited from SALEc, Sec. 2;
  * the form used is the four-region Tillotson equation of state).
@@ -121,8 +160,8 @@ void orc_tillotson(const orc_mat *m, double rho, double e, double *p_out, double
     } else {
         /* expanded branch */
         double z = 1.0 / eta - 1.0;
-        double ea = exp(-m->alpha * z * z);
-        double eb = exp(-m->beta * z);
+        double ea = exp_cw(-m->alpha * z * z);
+        double eb = exp_cw(-m->beta * z);
         double pe = m->a * r * E + (m->b * r * E / w + m->A * mu * eb) * ea;
         double pe_E = m->a * r + ea * m->b * r * (1.0 / w - (w - 1.0) / (w * w));
         double pe_r = m->a * E

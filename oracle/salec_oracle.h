@@ -95,6 +95,7 @@ int orc_diag(orc_ctx *x, double *out);
 int orc_get_profiles(orc_ctx *x, double *dcz, double *dnz, double *dcr, double *dnr);
 
 /* point functions, exposed for the pins */
+double orc_exp(double x);
 void orc_tillotson(const orc_mat *m, double rho, double e, double *p, double *c2);
 double orc_yield(const orc_mat *m, double p);
 double orc_shear_modulus(const orc_mat *m);

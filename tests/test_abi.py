@@ -1,0 +1,64 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/salec.h declares, and validates problem descriptions
+in salec_plan (pure host code)."""
+import ctypes as C
+import os
+
+import pytest
+
+from paper_2403_04267_amd import inputs, salec
+
+
+def test_library_exports_every_declared_function():
+    lib = salec.load()
+    names = salec.header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_plan_accepts_workloads_and_scales():
+    small = salec.plan_bytes(inputs.config_small())
+    scale = salec.plan_bytes(inputs.config_scale())
+    assert small > 0 and scale > 0
+    # state + scratch grow with the cell count (1050^2 / 120^2 = 76.6)
+    assert 50 < scale / small < 110
+
+
+@pytest.mark.parametrize("field,value", [
+    ("n_r", 0), ("pml_b", -1), ("nmat", 3), ("dr", 0.0), ("cfl", 1.5), ("cfl", 0.0),
+    ("dt_grow", 0.5), ("q_lin", -1.0),
+])
+def test_plan_rejects_invalid_grids(field, value):
+    pb = inputs.config_small()
+    setattr(pb.grid, field, value)
+    assert salec.plan_bytes(pb) == 0
+
+
+def test_plan_rejects_invalid_materials_and_pml():
+    pb = inputs.config_small()
+    pb.mats = [inputs.basalt()]
+    pb.mats[0].Ecv = pb.mats[0].Eiv
+    assert salec.plan_bytes(pb) == 0
+    pb = inputs.impact(50, 10, 5, 1e4, nmat=2, strength=True, cycles=0)
+    bad = inputs.basalt(strength=True)
+    bad.Ylim = bad.Y0
+    pb.mats = [pb.mats[0], bad]
+    assert salec.plan_bytes(pb) == 0
+    pb = inputs.config_small()
+    pb.pml.R = 1.5
+    assert salec.plan_bytes(pb) == 0
+
+
+def test_mixed_precision_not_accepted_by_fp64_build():
+    pb = inputs.config_small().replace(precision="mixed")
+    # documented in the header: only SALEC_FP64 is implemented in this build
+    assert salec.plan_bytes(pb) == 0
+
+
+def test_binding_refuses_to_run_without_a_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is visible")
+    with pytest.raises(RuntimeError):
+        salec.Salec(inputs.config_small())

@@ -196,3 +196,21 @@ def test_spin_sign_from_rigid_rotation_velocity_field():
     k = O.cell_kinematics(g, i, om * zs, -om * rs)
     assert k["om"] == pytest.approx(om, rel=1e-14)
     assert abs(k["erz"]) < 1e-15 and abs(k["err"]) < 1e-15 and abs(k["ezz"]) < 1e-15
+
+
+# ---------------------------------------------------------------- exp
+def test_exp_method_accuracy():
+    """The EoS exponentials use Cody-Waite reduction + degree-13 Taylor
+    polynomial: within 2 ulp of the correctly rounded value over the range the
+    EoS uses, exact at 0, flushed to 0 below e^-700, monotone."""
+    import numpy as np
+    xs = np.concatenate([np.linspace(-700, 709, 20001), np.linspace(-1, 1, 20001), -np.logspace(-12, 2.8, 5000)])
+    for x in xs:
+        y = O.exp(float(x))
+        ref = math.exp(float(x))
+        assert abs(y - ref) <= 2.5 * np.spacing(ref), (x, y, ref)
+    assert O.exp(0.0) == 1.0
+    assert O.exp(-701.0) == 0.0 and O.exp(-1e12) == 0.0
+    assert math.isinf(O.exp(710.0))
+    ys = [O.exp(float(x)) for x in np.linspace(-5, 5, 10001)]
+    assert all(b >= a for a, b in zip(ys, ys[1:]))
