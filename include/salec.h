@@ -1,0 +1,172 @@
+/*
+ * salec.h -- C ABI of libsalec: the per-cycle grid update of a SALE-type
+ * axisymmetric (r-z) impact hydrocode with perfectly matched layers, on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method (Li et al., "Parallel numerical simulation of impact crater with
+ * perfect matched layers"): each cycle is the SALE operator split of Sec. 2 --
+ * a Lagrangian step for momentum and internal energy (eqs. (1)-(2)) followed by
+ * an Eulerian advection step for mass, momentum and energy (eqs. (3)-(5)) --
+ * with the PML auxiliary variables and damping of Sec. 3 in the right and
+ * bottom layers, the boundary conditions of Sec. 4 (free-slip symmetry axis
+ * and outer side, no-slip bottom, open top) and the Courant time step of
+ * Sec. 7. Material laws: Tillotson equation of state and the pressure-
+ * dependent intact-rock strength whose parameters Table 1 lists.
+ *
+ * Conventions
+ *   Cell (i, j): i = 0..NR-1 outward from the axis, j = 0..NZ-1 upward, with
+ *   NR = n_r + pml_r and NZ = n_z + pml_b. Node (i, j): i = 0..NR, j = 0..NZ.
+ *   Host arrays exchanged through this ABI are FP64, row-major with r
+ *   fastest: cells NZ x NR, nodes (NZ+1) x (NR+1). SI units; volumes and
+ *   areas per radian.
+ *
+ * Ownership
+ *   Device memory is owned by the caller: salec_plan() gives the byte count,
+ *   the caller allocates it (e.g. a torch uint8 tensor on the GPU) and passes
+ *   its address to salec_init(); the library never allocates device memory
+ *   and the caller keeps the buffer alive until salec_destroy(). The stream
+ *   (a hipStream_t, or NULL for the default stream) is also the caller's.
+ *   Host arrays are owned by the caller and only read/written during a call.
+ *   A context may be used by one host thread at a time.
+ *
+ * Errors
+ *   Every int-returning call returns SALEC_OK (0) or a negative code. Device-
+ *   detected errors (non-finite field, negative mass, collapsed time step)
+ *   are sticky: salec_step() returns them until a new state is set with
+ *   salec_set_fields(), salec_init() or salec_set_state(); the state after
+ *   such an error is undefined. salec_last_error() returns a message for the
+ *   most recent failure of the context.
+ */
+#ifndef SALEC_H
+#define SALEC_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SALEC_OK 0
+#define SALEC_E_INVALID (-1)   /* bad sizes or parameters                       */
+#define SALEC_E_BUFFER (-2)    /* device buffer or host blob too small          */
+#define SALEC_E_HIP (-3)       /* HIP runtime error (message in last_error)      */
+#define SALEC_E_NONFINITE (-4) /* a field became NaN or infinite                 */
+#define SALEC_E_NEG_MASS (-5)  /* a density fell below -1e-9 rho_ref             */
+#define SALEC_E_DT_FLOOR (-6)  /* the time step fell below dt_floor              */
+
+#define SALEC_FP64 0  /* every field and all arithmetic in FP64                  */
+#define SALEC_MIXED 1 /* FP32 stencil/EoS/stress arithmetic; FP64 energy, mass,
+                         volume fractions, flux sums and the time step           */
+
+#define SALEC_MAX_MAT 2
+
+typedef struct salec_grid {
+    int32_t n_r, n_z;    /* physical cells in r and z (>= 1)                      */
+    int32_t pml_r;       /* PML cells right of the physical region (>= 0)        */
+    int32_t pml_b;       /* PML cells below the physical region (>= 0)           */
+    int32_t nmat;        /* 1 or 2 materials                                     */
+    int32_t top_closed;  /* 0: open top (void ghost), 1: rigid top wall          */
+    int32_t precision;   /* SALEC_FP64 or SALEC_MIXED                            */
+    int32_t reserved;    /* must be 0                                            */
+    double dr, dz;       /* cell size, m (> 0)                                   */
+    double cfl;          /* Courant constant C0 in (0, 1] (Sec. 7)               */
+    double dt_grow;      /* largest dt growth factor per cycle (>= 1)            */
+    double dt_max;       /* largest time step, s                                 */
+    double dt_floor;     /* dt below this is an error (0 disables)               */
+    double t_stop;       /* > 0: the step is clipped so t never passes t_stop    */
+    double q_lin, q_quad;/* artificial viscosity coefficients C1, C2 (>= 0)       */
+} salec_grid;
+
+typedef struct salec_material {
+    double rho0, A, B, E0, a, b, alpha, beta, Eiv, Ecv; /* Tillotson constants  */
+    double p_min;        /* pressure floor, Pa                                   */
+    double c_floor_frac; /* c^2 >= c_floor_frac * A / rho0                       */
+    int32_t strength;    /* 0: hydrodynamic, 1: elasto-plastic (Table 1 form)     */
+    int32_t reserved;    /* must be 0                                            */
+    double Y0, mu_f, Ylim, poisson; /* cohesion, friction, limit strength, nu   */
+} salec_material;
+
+typedef struct salec_pml {
+    int32_t enabled;     /* 0: plain walls, 1: damping layers (Sec. 3)           */
+    int32_t reserved;    /* must be 0                                            */
+    double R;            /* theoretical reflection coefficient (0, 1)            */
+    double c_ref;        /* damping speed; <= 0: longitudinal speed of material 0 */
+} salec_pml;
+
+typedef struct salec_scene {
+    int32_t surface_j;   /* first void row above the target half-space           */
+    int32_t subsample;   /* S x S sub-samples per cell for the sphere's fraction  */
+    double radius;       /* projectile radius, m                                 */
+    double v_imp;        /* vertical impact speed, m/s (downwards)               */
+} salec_scene;
+
+/* Host FP64 arrays; any pointer may be NULL to skip that field.
+ *   rho, I, p, c2 : NZ*NR        f : nmat*NZ*NR (material-major)
+ *   s             : 3*NZ*NR (s_rr, s_zz, s_rz)       v : 2*(NZ+1)*(NR+1) (v_r, v_z)
+ * p and c2 are outputs only (evaluated from the state). */
+typedef struct salec_fields {
+    double *rho, *I, *f, *s, *v, *p, *c2;
+} salec_fields;
+
+typedef struct salec_diag {
+    double t, dt, dt_prev;
+    int64_t cycle;
+    double mass, ie, ke;   /* compensated totals: sum rho V, sum rho V I, node KE */
+    double mass_out, mass_pml, ie_out; /* outflow through the top, PML sink      */
+    int32_t err, err_cycle;
+} salec_diag_t;
+
+typedef struct salec_ctx salec_ctx;
+
+/* Bytes of device memory salec_init() needs for this problem; 0 if invalid. */
+size_t salec_plan(const salec_grid *grid, const salec_material *mats, const salec_pml *pml);
+
+/* Lays out the state in dev_buf (dev_bytes >= salec_plan()), uploads the
+ * constants and, if scene is not NULL, builds the impact scene (target
+ * half-space of material 0, spherical projectile of material nmat-1) on the
+ * device; otherwise the state is zero until salec_set_fields(). Computes the
+ * first time step. stream: hipStream_t or NULL. */
+int salec_init(const salec_grid *grid, const salec_material *mats, const salec_pml *pml,
+               const salec_scene *scene, void *dev_buf, size_t dev_bytes, void *stream,
+               salec_ctx **out);
+
+/* Advances n >= 0 cycles (replaying captured HIP graphs), then synchronises
+ * the stream once and returns the sticky device error, if any. */
+int salec_step(salec_ctx *ctx, int32_t n);
+
+/* Enqueues n cycles without synchronising or checking errors (for timing
+ * loops); errors surface at the next salec_step() or salec_diag(). */
+int salec_enqueue(salec_ctx *ctx, int32_t n);
+
+/* Copies the current state (and p, c2 if requested) to host FP64 arrays. */
+int salec_get_fields(salec_ctx *ctx, const salec_fields *out);
+
+/* Replaces the state with host arrays (rho, I, f, v required; s optional,
+ * zero if NULL) and starts a new run at t = 0: PML auxiliaries and budgets
+ * are cleared, the PML reference density is taken from rho, dt recomputed. */
+int salec_set_fields(salec_ctx *ctx, const salec_fields *in);
+
+/* PML auxiliaries expanded to full grids (zero outside the layers):
+ *   cell_aux 8*NZ*NR: phi1_b, phi3_b, psi2_b, phi1_r, phi3_r, psi2_r, rho_ref, msink
+ *   node_aux 8*(NZ+1)*(NR+1): phi2_b (r, z), psi1_b (r, z), phi2_r (r, z), psi1_r (r, z) */
+int salec_get_pml(salec_ctx *ctx, double *cell_aux, double *node_aux);
+
+/* Checkpoint: the whole device state (fields, PML, budgets, t, dt, cycle). */
+size_t salec_state_bytes(const salec_ctx *ctx);
+int salec_get_state(salec_ctx *ctx, void *host_blob, size_t bytes);
+int salec_set_state(salec_ctx *ctx, const void *host_blob, size_t bytes);
+
+/* Time, step, cycle, compensated totals and budgets, sticky error. */
+int salec_diag(salec_ctx *ctx, salec_diag_t *out);
+
+/* Device time of the grid-update kernels over the last salec_step() call,
+ * measured with HIP events on the context's stream, in milliseconds. */
+int salec_last_step_ms(salec_ctx *ctx, double *ms);
+
+const char *salec_last_error(const salec_ctx *ctx);
+void salec_destroy(salec_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,253 @@
+"""Thin ctypes binding of libsalec (include/salec.h).
+
+Argument marshalling only: every step of the grid update runs in the HIP
+library. PyTorch supplies the device buffer (a uint8 tensor sized by
+``salec_plan``) and the stream. There is no CPU fallback: constructing a
+``Salec`` without the built library or without a HIP device raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsalec.so")
+HEADER = os.path.join(HERE, "..", "include", "salec.h")
+
+SALEC_FP64, SALEC_MIXED = 0, 1
+ERRORS = {-1: "SALEC_E_INVALID", -2: "SALEC_E_BUFFER", -3: "SALEC_E_HIP", -4: "SALEC_E_NONFINITE",
+          -5: "SALEC_E_NEG_MASS", -6: "SALEC_E_DT_FLOOR"}
+
+
+class Grid(C.Structure):
+    _fields_ = [("n_r", C.c_int32), ("n_z", C.c_int32), ("pml_r", C.c_int32), ("pml_b", C.c_int32),
+                ("nmat", C.c_int32), ("top_closed", C.c_int32), ("precision", C.c_int32),
+                ("reserved", C.c_int32)] + \
+               [(n, C.c_double) for n in ("dr", "dz", "cfl", "dt_grow", "dt_max", "dt_floor", "t_stop",
+                                          "q_lin", "q_quad")]
+
+
+class Material(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("rho0", "A", "B", "E0", "a", "b", "alpha", "beta", "Eiv", "Ecv",
+                                          "p_min", "c_floor_frac")] + \
+               [("strength", C.c_int32), ("reserved", C.c_int32)] + \
+               [(n, C.c_double) for n in ("Y0", "mu_f", "Ylim", "poisson")]
+
+
+class PmlC(C.Structure):
+    _fields_ = [("enabled", C.c_int32), ("reserved", C.c_int32), ("R", C.c_double), ("c_ref", C.c_double)]
+
+
+class SceneC(C.Structure):
+    _fields_ = [("surface_j", C.c_int32), ("subsample", C.c_int32), ("radius", C.c_double),
+                ("v_imp", C.c_double)]
+
+
+_DP = C.POINTER(C.c_double)
+
+
+class Fields(C.Structure):
+    _fields_ = [(n, _DP) for n in ("rho", "I", "f", "s", "v", "p", "c2")]
+
+
+class Diag(C.Structure):
+    _fields_ = [("t", C.c_double), ("dt", C.c_double), ("dt_prev", C.c_double), ("cycle", C.c_int64),
+                ("mass", C.c_double), ("ie", C.c_double), ("ke", C.c_double), ("mass_out", C.c_double),
+                ("mass_pml", C.c_double), ("ie_out", C.c_double), ("err", C.c_int32),
+                ("err_cycle", C.c_int32)]
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libsalec.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libsalec.so not built ({LIB_PATH}); run __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    lib.salec_plan.restype = C.c_size_t
+    lib.salec_plan.argtypes = [C.POINTER(Grid), C.POINTER(Material), C.POINTER(PmlC)]
+    lib.salec_init.argtypes = [C.POINTER(Grid), C.POINTER(Material), C.POINTER(PmlC), C.POINTER(SceneC),
+                               P, C.c_size_t, P, C.POINTER(P)]
+    lib.salec_step.argtypes = [P, C.c_int32]
+    lib.salec_enqueue.argtypes = [P, C.c_int32]
+    lib.salec_get_fields.argtypes = [P, C.POINTER(Fields)]
+    lib.salec_set_fields.argtypes = [P, C.POINTER(Fields)]
+    lib.salec_get_pml.argtypes = [P, _DP, _DP]
+    lib.salec_state_bytes.restype = C.c_size_t
+    lib.salec_state_bytes.argtypes = [P]
+    lib.salec_get_state.argtypes = [P, P, C.c_size_t]
+    lib.salec_set_state.argtypes = [P, P, C.c_size_t]
+    lib.salec_diag.argtypes = [P, C.POINTER(Diag)]
+    lib.salec_last_step_ms.argtypes = [P, _DP]
+    lib.salec_last_error.restype = C.c_char_p
+    lib.salec_last_error.argtypes = [P]
+    lib.salec_destroy.argtypes = [P]
+    _lib = lib
+    return lib
+
+
+def header_functions() -> list:
+    """Names of the functions include/salec.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(salec_[a-z_0-9]+)\s*\(", txt)))
+
+
+def _grid(g, precision) -> Grid:
+    return Grid(g.n_r, g.n_z, g.pml_r, g.pml_b, g.nmat, g.top_closed,
+                SALEC_MIXED if precision == "mixed" else SALEC_FP64, 0,
+                g.dr, g.dz, g.cfl, g.dt_grow, g.dt_max, g.dt_floor, g.t_stop, g.q_lin, g.q_quad)
+
+
+def _mat(m) -> Material:
+    return Material(m.rho0, m.A, m.B, m.E0, m.a, m.b, m.alpha, m.beta, m.Eiv, m.Ecv, m.p_min,
+                    m.c_floor_frac, int(m.strength), 0, m.Y0, m.mu_f, m.Ylim, m.poisson)
+
+
+def _mats(problem):
+    arr = (Material * 2)()
+    for k, m in enumerate(problem.mats[:problem.grid.nmat]):
+        arr[k] = _mat(m)
+    return arr
+
+
+def plan_bytes(problem) -> int:
+    lib = load()
+    p = problem.pml
+    return lib.salec_plan(C.byref(_grid(problem.grid, problem.precision)), _mats(problem),
+                          C.byref(PmlC(int(p.enabled), 0, p.R, p.c_ref)))
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_DP)
+
+
+class SalecError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Salec:
+    """One simulation context on a HIP device."""
+
+    def __init__(self, problem, device: str = "cuda:0"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libsalec needs a HIP device; none is visible")
+        lib = load()
+        self.lib = lib
+        self.problem = problem
+        g = problem.grid
+        self.NR, self.NZ = g.n_r + g.pml_r, g.n_z + g.pml_b
+        self.NC, self.NN = self.NR * self.NZ, (self.NR + 1) * (self.NZ + 1)
+        self.nmat = g.nmat
+        self.device = torch.device(device)
+        grid = _grid(g, problem.precision)
+        mats = _mats(problem)
+        p = problem.pml
+        pml = PmlC(int(p.enabled), 0, p.R, p.c_ref)
+        nbytes = lib.salec_plan(C.byref(grid), mats, C.byref(pml))
+        if nbytes == 0:
+            raise ValueError("salec_plan rejected the problem description")
+        with torch.cuda.device(self.device):
+            self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.buf.data_ptr()
+            off = (-base) % 256
+            # a stream of our own (default priority): the legacy null stream
+            # cannot be captured into HIP graphs
+            self.stream = torch.cuda.Stream(device=self.device)
+        sc = None
+        if problem.scene is not None:
+            s = problem.scene
+            sc = SceneC(s.surface_j, s.subsample, s.radius, s.v_imp)
+        h = C.c_void_p()
+        rc = lib.salec_init(C.byref(grid), mats, C.byref(pml), C.byref(sc) if sc is not None else None,
+                            C.c_void_p(base + off), C.c_size_t(nbytes), C.c_void_p(self.stream.cuda_stream),
+                            C.byref(h))
+        self._h = h
+        if rc:
+            msg = lib.salec_last_error(h).decode() if h else ""
+            raise SalecError(rc, msg)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self.lib.salec_destroy(h)
+            self._h = None
+
+    def _check(self, rc):
+        if rc:
+            raise SalecError(rc, self.lib.salec_last_error(self._h).decode())
+
+    def step(self, n: int, check: bool = True) -> int:
+        rc = self.lib.salec_step(self._h, int(n))
+        if rc and check:
+            self._check(rc)
+        return rc
+
+    def enqueue(self, n: int):
+        self._check(self.lib.salec_enqueue(self._h, int(n)))
+
+    def last_step_ms(self) -> float:
+        v = C.c_double()
+        self._check(self.lib.salec_last_step_ms(self._h, C.byref(v)))
+        return v.value
+
+    def fields(self, eos: bool = True) -> dict:
+        NR, NZ, NC, NN = self.NR, self.NZ, self.NC, self.NN
+        rho, I = np.empty(NC), np.empty(NC)
+        f, s, v = np.empty(self.nmat * NC), np.empty(3 * NC), np.empty(2 * NN)
+        p = np.empty(NC) if eos else None
+        c2 = np.empty(NC) if eos else None
+        fl = Fields(_ptr(rho), _ptr(I), _ptr(f), _ptr(s), _ptr(v), _ptr(p), _ptr(c2))
+        self._check(self.lib.salec_get_fields(self._h, C.byref(fl)))
+        out = {"rho": rho.reshape(NZ, NR), "I": I.reshape(NZ, NR), "f": f.reshape(self.nmat, NZ, NR),
+               "s": s.reshape(3, NZ, NR), "v": v.reshape(2, NZ + 1, NR + 1)}
+        if eos:
+            out["p"] = p.reshape(NZ, NR)
+            out["c2"] = c2.reshape(NZ, NR)
+        return out
+
+    def set_fields(self, rho, I, f, v, s=None):
+        NC, NN = self.NC, self.NN
+        arr = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in (rho, I, f, v)]
+        assert arr[0].size == NC and arr[1].size == NC and arr[2].size == self.nmat * NC and arr[3].size == 2 * NN
+        sp = None if s is None else np.ascontiguousarray(s, dtype=np.float64).reshape(3 * NC)
+        fl = Fields(_ptr(arr[0]), _ptr(arr[1]), _ptr(arr[2]), _ptr(sp), _ptr(arr[3]), None, None)
+        self._check(self.lib.salec_set_fields(self._h, C.byref(fl)))
+
+    def pml_aux(self) -> dict:
+        NR, NZ, NC, NN = self.NR, self.NZ, self.NC, self.NN
+        ca, na = np.empty(8 * NC), np.empty(8 * NN)
+        self._check(self.lib.salec_get_pml(self._h, _ptr(ca), _ptr(na)))
+        ca, na = ca.reshape(8, NZ, NR), na.reshape(8, NZ + 1, NR + 1)
+        names_c = ["phi1_b", "phi3_b", "psi2_b", "phi1_r", "phi3_r", "psi2_r", "rho_ref", "msink"]
+        names_n = ["phi2_b_r", "phi2_b_z", "psi1_b_r", "psi1_b_z", "phi2_r_r", "phi2_r_z", "psi1_r_r",
+                   "psi1_r_z"]
+        out = {k: ca[i] for i, k in enumerate(names_c)}
+        out.update({k: na[i] for i, k in enumerate(names_n)})
+        return out
+
+    def diag(self) -> dict:
+        d = Diag()
+        self._check(self.lib.salec_diag(self._h, C.byref(d)))
+        return {k: getattr(d, k) for k, _ in Diag._fields_}
+
+    def get_state(self) -> bytes:
+        n = self.lib.salec_state_bytes(self._h)
+        buf = C.create_string_buffer(n)
+        self._check(self.lib.salec_get_state(self._h, buf, n))
+        return buf.raw
+
+    def set_state(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        self._check(self.lib.salec_set_state(self._h, buf, len(blob)))

@@ -47,8 +47,9 @@ def compare(gpu, orc, label, tol=TOL, pml=True):
         # the library keeps the reference density only inside the layers
         g = orc.g
         lay = np.zeros_like(Ao["rho_ref"], dtype=bool)
-        lay[:g.pml_b, :] = True
-        lay[:, g.n_r:] = True
+        if orc.problem.pml.enabled:
+            lay[:g.pml_b, :] = True
+            lay[:, g.n_r:] = True
         Ao = dict(Ao)
         Ao["rho_ref"] = np.where(lay, Ao["rho_ref"], 0.0)
         for k in Ao:
