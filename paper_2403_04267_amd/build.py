@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsalec.so")
-SOURCES = ["salec_kernels.hip", "salec_host.hip"]
+SOURCES = ["salec_kernels.hip", "salec_fused.hip", "salec_host.hip"]
 HEADERS = ["salec_device.hpp", "salec_internal.hpp"]
 ARCH = os.environ.get("SALEC_ARCH", "gfx950")
 

@@ -41,6 +41,8 @@ struct Geo {
   int NR, NZ, n_r, n_z, pml_r, pml_b, nmat, top_closed;
   int pc, pn;          // row pitch (elements) of cell and node arrays
   int any_strength, pml_on;
+  int nblocks_fused;   // workgroups of the fused cycle kernel
+  int same_mat;        // all materials share every constant: evaluate the laws once
   double dr, dz, cfl, dt_grow, dt_max, dt_floor, t_stop, q_lin, q_quad;
   double rho_ref;
   MatC m[kMaxMat];
@@ -57,16 +59,23 @@ struct Scal {
   long long cycle;
   unsigned long long dtmin;  // bit pattern of the running minimum (dt > 0)
   unsigned flags;
-  int err, err_cycle, pad;
+  unsigned done;             // blocks of the current cycle that have finished
+  int err, err_cycle;
+};
+
+// PML auxiliaries of one time level; two levels ping-pong by cycle parity so
+// that halo reads of neighbouring tiles always see the old values.
+struct PmlAux {
+  double *b_phi1, *b_phi3, *b_psi2;               // bottom strip cells  [pml_b][NR]
+  double *r_phi1, *r_phi3, *r_psi2;               // right strip cells   [NZ][pml_r]
+  double *b_phi2r, *b_phi2z, *b_psi1r, *b_psi1z;  // bottom strip nodes  [pml_b][NR+1]
+  double *r_phi2r, *r_phi2z, *r_psi1r, *r_psi1z;  // right strip nodes   [NZ+1][pml_r]
 };
 
 struct Pml {
-  const double *dcz, *dnz, *dcr, *dnr;          // damping profiles
-  double *b_phi1, *b_phi3, *b_psi2;             // bottom strip cells  [pml_b][NR]
-  double *r_phi1, *r_phi3, *r_psi2;             // right strip cells   [NZ][pml_r]
-  double *rref, *msink;                         // union of strip cells
-  double *b_phi2r, *b_phi2z, *b_psi1r, *b_psi1z;  // bottom strip nodes [pml_b][NR+1]
-  double *r_phi2r, *r_phi2z, *r_psi1r, *r_psi1z;  // right strip nodes  [NZ+1][pml_r]
+  const double *dcz, *dnz, *dcr, *dnr;  // damping profiles
+  double *rref, *msink;                 // union of strip cells (single level)
+  PmlAux a[2];
 };
 
 struct Work {
@@ -79,6 +88,7 @@ struct Work {
   double *heat;                           // node specific heat of the remap
   double *mout, *eout;                    // per-column outflow budgets
   double *red;                            // reduction partials
+  double *dtpart;                         // per-block Courant minima of the fused cycle
 };
 
 __device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : b; }
@@ -203,26 +213,42 @@ struct Mix {
 __device__ inline Mix mixture(const Geo& g, double rho, double I, const double* f) {
   Mix o;
   double phi = 0.0;
-  for (int m = 0; m < g.nmat; m++) phi += f[m];
+#pragma unroll
+  for (int m = 0; m < kMaxMat; m++)
+    if (m < g.nmat) phi += f[m];
   double den = phi > kPhiEps ? phi : kPhiEps;
   double rm = rho / den;
   double p = 0.0, c2 = 0.0, G = 0.0;
-  double wm[kMaxMat];
-  for (int m = 0; m < g.nmat; m++) {
+  double wm[kMaxMat], pmv[kMaxMat], c2v[kMaxMat], sov[kMaxMat];
+#pragma unroll
+  for (int m = 0; m < kMaxMat; m++) {
+    if (m >= g.nmat) break;
     const MatC& M = g.m[m];
-    double pm, c2m;
     wm[m] = f[m] / den;
-    tillotson(M, rm, I, pm, c2m);
-    pm = dmax(pm, M.p_min);
-    c2m = dmax(c2m, M.cf2);
-    p += wm[m] * pm;
-    c2 += wm[m] * c2m;
-    G += wm[m] * (softening(M, I) * (M.gfac * (rm * c2m)));
+    if (m > 0 && g.same_mat) {
+      // identical constants and inputs give identical results
+      pmv[m] = pmv[0];
+      c2v[m] = c2v[0];
+      sov[m] = sov[0];
+    } else {
+      double pm, c2m;
+      tillotson(M, rm, I, pm, c2m);
+      pmv[m] = dmax(pm, M.p_min);
+      c2v[m] = dmax(c2m, M.cf2);
+      sov[m] = softening(M, I);
+    }
+    p += wm[m] * pmv[m];
+    c2 += wm[m] * c2v[m];
+    G += wm[m] * (sov[m] * (M.gfac * (rm * c2v[m])));
   }
-  double Y = 0.0, pmin = 0.0, ps = 0.0;
-  for (int m = 0; m < g.nmat; m++) {
+  double Y = 0.0, pmin = 0.0, ps = 0.0, y0 = 0.0;
+#pragma unroll
+  for (int m = 0; m < kMaxMat; m++) {
+    if (m >= g.nmat) break;
     const MatC& M = g.m[m];
-    Y += wm[m] * (softening(M, I) * yield_strength(M, p));
+    double ym = (m > 0 && g.same_mat) ? y0 : yield_strength(M, p);
+    if (m == 0) y0 = ym;
+    Y += wm[m] * (sov[m] * ym);
     pmin += wm[m] * M.p_min;
     ps += wm[m] * M.pcav;
   }

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -73,22 +74,25 @@ void carve(const Geo& g, void* base, Layout& L) {
   L.n_pml = g.pml_on ? nu : 0;
   Pml& pm = L.pm;
   auto opt = [&](long long n) { return (g.pml_on && n > 0) ? cv.d((size_t)n) : nullptr; };
-  pm.b_phi1 = opt(nbc);
-  pm.b_phi3 = opt(nbc);
-  pm.b_psi2 = opt(nbc);
-  pm.r_phi1 = opt(nrc);
-  pm.r_phi3 = opt(nrc);
-  pm.r_psi2 = opt(nrc);
   pm.rref = opt(nu);
   pm.msink = opt(nu);
-  pm.b_phi2r = opt(nbn);
-  pm.b_phi2z = opt(nbn);
-  pm.b_psi1r = opt(nbn);
-  pm.b_psi1z = opt(nbn);
-  pm.r_phi2r = opt(nrn);
-  pm.r_phi2z = opt(nrn);
-  pm.r_psi1r = opt(nrn);
-  pm.r_psi1z = opt(nrn);
+  for (int lv = 0; lv < 2; lv++) {
+    PmlAux& a = pm.a[lv];
+    a.b_phi1 = opt(nbc);
+    a.b_phi3 = opt(nbc);
+    a.b_psi2 = opt(nbc);
+    a.r_phi1 = opt(nrc);
+    a.r_phi3 = opt(nrc);
+    a.r_psi2 = opt(nrc);
+    a.b_phi2r = opt(nbn);
+    a.b_phi2z = opt(nbn);
+    a.b_psi1r = opt(nbn);
+    a.b_psi1z = opt(nbn);
+    a.r_phi2r = opt(nrn);
+    a.r_phi2z = opt(nrn);
+    a.r_psi1r = opt(nrn);
+    a.r_psi1z = opt(nrn);
+  }
   L.w.mout = cv.d(g.pc);
   L.w.eout = cv.d(g.pc);
   L.persist_bytes = cv.off;
@@ -119,6 +123,7 @@ void carve(const Geo& g, void* base, Layout& L) {
   w.Fz = cv.d((size_t)(g.NZ + 1) * g.pc);
   w.heat = cv.d(nn);
   w.red = cv.d((size_t)kDiagBlocks * 12);
+  w.dtpart = cv.d((size_t)g.nblocks_fused + 1);
   L.diag_out = cv.d(8);
   L.total = cv.off;
 }
@@ -147,6 +152,7 @@ int validate(const salec_grid* g, const salec_material* mats, const salec_pml* p
 
 Geo make_geo(const salec_grid* gr, const salec_material* mats, const salec_pml* pml) {
   Geo g{};
+  std::memset(&g, 0, sizeof(g));
   g.n_r = gr->n_r;
   g.n_z = gr->n_z;
   g.pml_r = gr->pml_r;
@@ -158,6 +164,11 @@ Geo make_geo(const salec_grid* gr, const salec_material* mats, const salec_pml* 
   g.pc = (int)((g.NR + 31) / 32 * 32);
   g.pn = (int)((g.NR + 1 + 31) / 32 * 32);
   g.pml_on = pml->enabled ? 1 : 0;
+  {
+    int tr, tz;
+    fused_tiles(g.NR, g.NZ, &tr, &tz);
+    g.nblocks_fused = tr * tz;
+  }
   g.dr = gr->dr;
   g.dz = gr->dz;
   g.cfl = gr->cfl;
@@ -192,6 +203,9 @@ Geo make_geo(const salec_grid* gr, const salec_material* mats, const salec_pml* 
     if (M.strength) g.any_strength = 1;
     if (M.rho0 > g.rho_ref) g.rho_ref = M.rho0;
   }
+  g.same_mat = 1;
+  for (int m = 1; m < gr->nmat; m++)
+    if (std::memcmp(&g.m[m], &g.m[0], sizeof(MatC)) != 0) g.same_mat = 0;
   return g;
 }
 
@@ -234,6 +248,7 @@ struct salec_ctx {
   hipGraphExec_t gx1 = nullptr, gxN = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0.0;
+  bool phased = false;  // one kernel per phase instead of the fused cycle
   std::string err;
 };
 
@@ -266,7 +281,12 @@ int start_run(salec_ctx* x) {
 int capture(salec_ctx* x, int ncyc, hipGraphExec_t* out) {
   hipGraph_t gr = nullptr;
   HIPCHK(x, hipStreamBeginCapture(x->st, hipStreamCaptureModeThreadLocal));
-  for (int k = 0; k < ncyc; k++) launch_cycle(x->g, x->L.S[0], x->L.S[1], x->L.w, x->L.pm, x->L.sc, x->st);
+  for (int k = 0; k < ncyc; k++) {
+    if (x->phased)
+      launch_cycle(x->g, x->L.S[0], x->L.S[1], x->L.w, x->L.pm, x->L.sc, x->st);
+    else
+      launch_cycle_fused(x->g, x->L.S[0], x->L.S[1], x->L.w, x->L.pm, x->L.sc, x->st);
+  }
   hipError_t e = hipStreamEndCapture(x->st, &gr);
   if (e != hipSuccess) return hip_fail(x, e, "hipStreamEndCapture");
   e = hipGraphInstantiate(out, gr, nullptr, nullptr, 0);
@@ -346,6 +366,10 @@ int salec_init(const salec_grid* grid, const salec_material* mats, const salec_p
   }
   x->buf = dev_buf;
   carve(x->g, dev_buf, x->L);
+  {
+    const char* pe = std::getenv("SALEC_PIPELINE");
+    x->phased = pe && std::strcmp(pe, "phased") == 0;
+  }
   if (stream) {
     x->st = (hipStream_t)stream;
   } else {
@@ -479,6 +503,8 @@ int salec_get_pml(salec_ctx* x, double* ca, double* na) {
   const Geo& g = x->g;
   size_t NC = (size_t)g.NR * g.NZ, NN = (size_t)(g.NR + 1) * (g.NZ + 1);
   const Pml& pm = x->L.pm;
+  Scal sc_now = read_scal(x);
+  const PmlAux& au = pm.a[sc_now.cycle & 1];
   auto fetch = [&](const double* dev, size_t n, std::vector<double>& h) -> int {
     h.assign(n, 0.0);
     if (dev && n) HIPCHK(x, hipMemcpy(h.data(), dev, n * sizeof(double), hipMemcpyDeviceToHost));
@@ -490,8 +516,8 @@ int salec_get_pml(salec_ctx* x, double* ca, double* na) {
     std::memset(ca, 0, 8 * NC * sizeof(double));
     if (g.pml_on) {
       std::vector<double> h[8];
-      const double* b[3] = {pm.b_phi1, pm.b_phi3, pm.b_psi2};
-      const double* r[3] = {pm.r_phi1, pm.r_phi3, pm.r_psi2};
+      const double* b[3] = {au.b_phi1, au.b_phi3, au.b_psi2};
+      const double* r[3] = {au.r_phi1, au.r_phi3, au.r_psi2};
       for (int k = 0; k < 3; k++) {
         if (fetch(b[k], nbc, h[k]) || fetch(r[k], nrc, h[3 + k])) return SALEC_E_HIP;
       }
@@ -517,8 +543,8 @@ int salec_get_pml(salec_ctx* x, double* ca, double* na) {
     std::memset(na, 0, 8 * NN * sizeof(double));
     if (g.pml_on) {
       std::vector<double> h[8];
-      const double* b[4] = {pm.b_phi2r, pm.b_phi2z, pm.b_psi1r, pm.b_psi1z};
-      const double* r[4] = {pm.r_phi2r, pm.r_phi2z, pm.r_psi1r, pm.r_psi1z};
+      const double* b[4] = {au.b_phi2r, au.b_phi2z, au.b_psi1r, au.b_psi1z};
+      const double* r[4] = {au.r_phi2r, au.r_phi2z, au.r_psi1r, au.r_psi1z};
       for (int k = 0; k < 4; k++)
         if (fetch(b[k], nbn, h[k]) || fetch(r[k], nrn, h[4 + k])) return SALEC_E_HIP;
       for (int j = 0; j <= g.NZ; j++)

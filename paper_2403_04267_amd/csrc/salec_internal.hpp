@@ -11,6 +11,9 @@ constexpr unsigned kDiagBlocks = 240;
 
 void launch_cycle(const Geo& g, const State& S0, const State& S1, const Work& w, const Pml& pm, Scal* sc,
                   hipStream_t st);
+void launch_cycle_fused(const Geo& g, const State& S0, const State& S1, const Work& w, const Pml& pm, Scal* sc,
+                        hipStream_t st);
+void fused_tiles(int NR, int NZ, int* tr, int* tz);
 void launch_dt0(const Geo& g, const State& S0, const State& S1, Scal* sc, hipStream_t st);
 void launch_scene(const Geo& g, const State& S0, const Work& w, int surface_j, int S, double R, double zc,
                   double v_imp, hipStream_t st);

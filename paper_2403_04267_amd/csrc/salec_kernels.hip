@@ -46,7 +46,7 @@ __device__ __forceinline__ bool node_of(const Geo& g, int& i, int& j) {
 }
 
 __device__ __forceinline__ void load_f(const Geo& g, const State& S, long long c, double* f) {
-  for (int m = 0; m < g.nmat; m++) f[m] = S.f[m][c];
+  _Pragma("unroll") for (int m = 0; m < kMaxMat; m++) if (m < g.nmat) f[m] = S.f[m][c];
 }
 
 __device__ __forceinline__ void apply_bc(const Geo& g, int i, int j, double& vr, double& vz) {
@@ -110,6 +110,8 @@ __global__ void k_force(Geo g, State S0, State S1, Work w, Pml pm, const Scal* s
   if (!node_of(g, i, j)) return;
   State S, D;
   pick(sc, S0, S1, S, D);
+  const PmlAux& po = pm.a[sc->cycle & 1];
+  const PmlAux& pn = pm.a[(sc->cycle & 1) ^ 1];
   double dt = sc->dt, hdz = 0.5 * g.dz;
   // quadrants NE = (i, j), NW = (i-1, j), SE = (i, j-1), SW = (i-1, j-1)
   double srr[4] = {0, 0, 0, 0}, szz[4] = {0, 0, 0, 0}, stt[4] = {0, 0, 0, 0}, srz[4] = {0, 0, 0, 0},
@@ -148,8 +150,8 @@ __global__ void k_force(Geo g, State S0, State S1, Work w, Pml pm, const Scal* s
     drr = pm.dnr[i];
     if (j < g.pml_b) kb = pml_bn(g, i, j);
     if (i > g.n_r) kr = pml_rn(g, i, j);
-    double br = kb >= 0 ? pm.b_psi1r[kb] : 0.0, bz = kb >= 0 ? pm.b_psi1z[kb] : 0.0;
-    double rr = kr >= 0 ? pm.r_psi1r[kr] : 0.0, rz = kr >= 0 ? pm.r_psi1z[kr] : 0.0;
+    double br = kb >= 0 ? po.b_psi1r[kb] : 0.0, bz = kb >= 0 ? po.b_psi1z[kb] : 0.0;
+    double rr = kr >= 0 ? po.r_psi1r[kr] : 0.0, rz = kr >= 0 ? po.r_psi1z[kr] : 0.0;
     psr = br + rr;
     psz = bz + rz;
   }
@@ -157,12 +159,12 @@ __global__ void k_force(Geo g, State S0, State S1, Work w, Pml pm, const Scal* s
   double vLr = S.v[0][n] + dt * (Fer / mt);
   double vLz = S.v[1][n] + dt * (Fez / mt);
   if (db > 0.0) {
-    pm.b_psi1r[kb] = pm.b_psi1r[kb] - dt * db * (Frr / Vd);
-    pm.b_psi1z[kb] = pm.b_psi1z[kb] - dt * db * (Fzr / Vd);
+    pn.b_psi1r[kb] = po.b_psi1r[kb] - dt * db * (Frr / Vd);
+    pn.b_psi1z[kb] = po.b_psi1z[kb] - dt * db * (Fzr / Vd);
   }
   if (drr > 0.0) {
-    pm.r_psi1r[kr] = pm.r_psi1r[kr] - dt * drr * (Frz / Vd);
-    pm.r_psi1z[kr] = pm.r_psi1z[kr] - dt * drr * (Fzz / Vd);
+    pn.r_psi1r[kr] = po.r_psi1r[kr] - dt * drr * (Frz / Vd);
+    pn.r_psi1z[kr] = po.r_psi1z[kr] - dt * drr * (Fzz / Vd);
   }
   apply_bc(g, i, j, vLr, vLz);
   w.vL[0][n] = vLr;
@@ -178,6 +180,8 @@ __global__ void k_lagrange(Geo g, State S0, State S1, Work w, Pml pm, const Scal
   if (!cell_of(g, i, j)) return;
   State S, D;
   pick(sc, S0, S1, S, D);
+  const PmlAux& po = pm.a[sc->cycle & 1];
+  const PmlAux& pn = pm.a[(sc->cycle & 1) ^ 1];
   double dt = sc->dt;
   long long c = cidx(g, i, j);
   const long long nd[4] = {nidx(g, i, j), nidx(g, i + 1, j), nidx(g, i, j + 1), nidx(g, i + 1, j + 1)};
@@ -242,18 +246,18 @@ __global__ void k_lagrange(Geo g, State S0, State S1, Work w, Pml pm, const Scal
     drr = pm.dcr[i];
     if (j < g.pml_b) kb = pml_bc(g, i, j);
     if (i >= g.n_r) kr = pml_rc(g, i, j);
-    double b = kb >= 0 ? pm.b_psi2[kb] : 0.0, r = kr >= 0 ? pm.r_psi2[kr] : 0.0;
+    double b = kb >= 0 ? po.b_psi2[kb] : 0.0, r = kr >= 0 ? po.r_psi2[kr] : 0.0;
     psi2 = b + r;
   }
   double IL = ((S.I[c] + Wdt / rden) + hL) - dt * (psi2 / rt);
-  for (int m = 0; m < g.nmat; m++) w.fL[m][c] = S.f[m][c] * (Jm / J);
+  _Pragma("unroll") for (int m = 0; m < kMaxMat; m++) if (m < g.nmat) w.fL[m][c] = S.f[m][c] * (Jm / J);
   if (db > 0.0) {
     double Wr = ((s0rr * k.err + stt * k.ett) + s0rz * k.dvz_dr) - P * k.Dr;
-    pm.b_psi2[kb] = pm.b_psi2[kb] - dt * db * (phi * Wr);
+    pn.b_psi2[kb] = po.b_psi2[kb] - dt * db * (phi * Wr);
   }
   if (drr > 0.0) {
     double Wz = (s0zz * k.ezz + s0rz * k.dvr_dz) - P * k.Dz;
-    pm.r_psi2[kr] = pm.r_psi2[kr] - dt * drr * (phi * Wz);
+    pn.r_psi2[kr] = po.r_psi2[kr] - dt * drr * (phi * Wz);
   }
   w.IL[c] = IL;
   w.sL[0][c] = srr;
@@ -332,6 +336,8 @@ __global__ void k_remap(Geo g, State S0, State S1, Work w, Pml pm, const Scal* s
   if (!cell_of(g, i, j)) return;
   State S, D;
   pick(sc, S0, S1, S, D);
+  const PmlAux& po = pm.a[sc->cycle & 1];
+  const PmlAux& pn = pm.a[(sc->cycle & 1) ^ 1];
   double dt = sc->dt;
   long long c = cidx(g, i, j);
   double V = cell_volume(g, i);
@@ -352,7 +358,7 @@ __global__ void k_remap(Geo g, State S0, State S1, Work w, Pml pm, const Scal* s
   double IL = w.IL[c];
   double sLc[3] = {w.sL[0][c], w.sL[1][c], w.sL[2][c]};
   double fLc[kMaxMat];
-  for (int m = 0; m < g.nmat; m++) fLc[m] = w.fL[m][c];
+  _Pragma("unroll") for (int m = 0; m < kMaxMat; m++) if (m < g.nmat) fLc[m] = w.fL[m][c];
   double ed[4];
   for (int q = 0; q < 4; q++) {
     bool ok = di[q] >= 0 && di[q] < g.NR && dj[q] >= 0 && dj[q] < g.NZ;
@@ -366,7 +372,7 @@ __global__ void k_remap(Geo g, State S0, State S1, Work w, Pml pm, const Scal* s
       nsrr += aF * ((ok ? w.sL[0][dc] : 0.0) - sLc[0]);
       nszz += aF * ((ok ? w.sL[1][dc] : 0.0) - sLc[1]);
       nsrz += aF * ((ok ? w.sL[2][dc] : 0.0) - sLc[2]);
-      for (int m = 0; m < g.nmat; m++) nf[m] += adV * ((ok ? w.fL[m][dc] : 0.0) - fLc[m]);
+      _Pragma("unroll") for (int m = 0; m < kMaxMat; m++) if (m < g.nmat) nf[m] += adV * ((ok ? w.fL[m][dc] : 0.0) - fLc[m]);
       ed[q] = F[q] * Id;
     } else {
       ed[q] = F[q] * IL;
@@ -382,11 +388,11 @@ __global__ void k_remap(Geo g, State S0, State S1, Work w, Pml pm, const Scal* s
   double ex = (1.0 - w.lam[c]) * w.outv[c] - vcut;
   double fs = 0.0;
   double f1[kMaxMat];
-  for (int m = 0; m < g.nmat; m++) {
+  _Pragma("unroll") for (int m = 0; m < kMaxMat; m++) if (m < g.nmat) {
     f1[m] = dmax(fLc[m] + (nf[m] + fLc[m] * ex) / V, 0.0);
     fs += f1[m];
   }
-  for (int m = 0; m < g.nmat; m++) D.f[m][c] = f1[m] / dmax(fs, 1.0);
+  _Pragma("unroll") for (int m = 0; m < kMaxMat; m++) if (m < g.nmat) D.f[m][c] = f1[m] / dmax(fs, 1.0);
   if (g.pml_on) {
     double db = pm.dcz[j], drr = pm.dcr[i];
     if (db > 0.0 || drr > 0.0) {
@@ -394,19 +400,19 @@ __global__ void k_remap(Geo g, State S0, State S1, Work w, Pml pm, const Scal* s
       long long kr = i >= g.n_r ? pml_rc(g, i, j) : -1;
       long long ku = pml_cell_union(g, i, j);
       double dsum = db + drr;
-      double p1b = kb >= 0 ? pm.b_phi1[kb] : 0.0, p1r = kr >= 0 ? pm.r_phi1[kr] : 0.0;
-      double p3b = kb >= 0 ? pm.b_phi3[kb] : 0.0, p3r = kr >= 0 ? pm.r_phi3[kr] : 0.0;
+      double p1b = kb >= 0 ? po.b_phi1[kb] : 0.0, p1r = kr >= 0 ? po.r_phi1[kr] : 0.0;
+      double p3b = kb >= 0 ? po.b_phi3[kb] : 0.0, p3r = kr >= 0 ? po.r_phi3[kr] : 0.0;
       double rho2 = dmax(rho1 - dt * (dsum * (rho1 - pm.rref[ku]) + (p1b + p1r)), 0.0);
       double rt = dmax(rho1, g.rho_ref * kPmlRhoFloor);
       double I2 = I1 - dt * (dsum * I1 + (p3b + p3r) / rt);
       pm.msink[ku] = pm.msink[ku] + V * (rho1 - rho2);
       if (db > 0.0) {
-        pm.b_phi1[kb] = p1b + db * ((F[1] - F[0]) / V);
-        pm.b_phi3[kb] = p3b + db * ((ed[1] - ed[0]) / V);
+        pn.b_phi1[kb] = p1b + db * ((F[1] - F[0]) / V);
+        pn.b_phi3[kb] = p3b + db * ((ed[1] - ed[0]) / V);
       }
       if (drr > 0.0) {
-        pm.r_phi1[kr] = p1r + drr * ((F[3] - F[2]) / V);
-        pm.r_phi3[kr] = p3r + drr * ((ed[3] - ed[2]) / V);
+        pn.r_phi1[kr] = p1r + drr * ((F[3] - F[2]) / V);
+        pn.r_phi3[kr] = p3r + drr * ((ed[3] - ed[2]) / V);
       }
       rho1 = rho2;
       I1 = I2;
@@ -444,6 +450,8 @@ __global__ void k_mremap(Geo g, State S0, State S1, Work w, Pml pm, const Scal* 
   if (!node_of(g, i, j)) return;
   State S, D;
   pick(sc, S0, S1, S, D);
+  const PmlAux& po = pm.a[sc->cycle & 1];
+  const PmlAux& pn = pm.a[(sc->cycle & 1) ^ 1];
   double dt = sc->dt, hdz = 0.5 * g.dz;
   long long n = nidx(g, i, j);
   double M[4] = {0, 0, 0, 0};
@@ -513,18 +521,18 @@ __global__ void k_mremap(Geo g, State S0, State S1, Work w, Pml pm, const Scal* 
       long long kr = i > g.n_r ? pml_rn(g, i, j) : -1;
       double dsum = db + drr;
       double mt = dmax(m1, kMAccEps * g.rho_ref * Vd);
-      double bpr = kb >= 0 ? pm.b_phi2r[kb] : 0.0, bpz = kb >= 0 ? pm.b_phi2z[kb] : 0.0;
-      double rpr = kr >= 0 ? pm.r_phi2r[kr] : 0.0, rpz = kr >= 0 ? pm.r_phi2z[kr] : 0.0;
+      double bpr = kb >= 0 ? po.b_phi2r[kb] : 0.0, bpz = kb >= 0 ? po.b_phi2z[kb] : 0.0;
+      double rpr = kr >= 0 ? po.r_phi2r[kr] : 0.0, rpz = kr >= 0 ? po.r_phi2z[kr] : 0.0;
       double pr = bpr + rpr, pz = bpz + rpz;
       double v2r = v1r - dt * (dsum * v1r + (pr * Vd) / mt);
       double v2z = v1z - dt * (dsum * v1z + (pz * Vd) / mt);
       if (db > 0.0) {
-        pm.b_phi2r[kb] = bpr + db * ((FD[1] * upr[1] - FD[0] * upr[0]) / Vd);
-        pm.b_phi2z[kb] = bpz + db * ((FD[1] * upz[1] - FD[0] * upz[0]) / Vd);
+        pn.b_phi2r[kb] = bpr + db * ((FD[1] * upr[1] - FD[0] * upr[0]) / Vd);
+        pn.b_phi2z[kb] = bpz + db * ((FD[1] * upz[1] - FD[0] * upz[0]) / Vd);
       }
       if (drr > 0.0) {
-        pm.r_phi2r[kr] = rpr + drr * ((FD[3] * upr[3] - FD[2] * upr[2]) / Vd);
-        pm.r_phi2z[kr] = rpz + drr * ((FD[3] * upz[3] - FD[2] * upz[2]) / Vd);
+        pn.r_phi2r[kr] = rpr + drr * ((FD[3] * upr[3] - FD[2] * upr[2]) / Vd);
+        pn.r_phi2z[kr] = rpz + drr * ((FD[3] * upz[3] - FD[2] * upz[2]) / Vd);
       }
       v1r = v2r;
       v1z = v2z;
@@ -594,7 +602,7 @@ __global__ void k_final(Geo g, State S0, State S1, Work w, Scal* sc) {
     D.I[c] = I1;
     double s = D.rho[c] + I1;
     if (g.any_strength) s += D.s[0][c] + D.s[1][c] + D.s[2][c];
-    for (int m = 0; m < g.nmat; m++) s += D.f[m][c];
+    _Pragma("unroll") for (int m = 0; m < kMaxMat; m++) if (m < g.nmat) s += D.f[m][c];
     if (!finite_d(s)) flags |= kFlagNonFinite;
     if (D.rho[c] < -kNegMassTol * g.rho_ref) flags |= kFlagNegMass;
     if (!finite_d(D.v[0][nidx(g, i, j)] + D.v[1][nidx(g, i, j)])) flags |= kFlagNonFinite;
@@ -680,7 +688,7 @@ __global__ void k_scene_cells(Geo g, State S0, Work w, int surface_j, int S, dou
   f[0] = j < surface_j ? 1.0 : 0.0;
   f[mp] = f[mp] + fp;
   double rho = 0.0;
-  for (int m = 0; m < g.nmat; m++) {
+  _Pragma("unroll") for (int m = 0; m < kMaxMat; m++) if (m < g.nmat) {
     S0.f[m][c] = f[m];
     rho += f[m] * g.m[m].rho0;
   }
