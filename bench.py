@@ -65,16 +65,36 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tune", type=int, default=2, metavar="K",
+                    help="time every tile shape over K cycles during warm-up and keep the fastest (0: off)")
+    ap.add_argument("--variant", type=int, default=-1, help="force a tile shape (disables --tune)")
+    ap.add_argument("--grid", type=int, default=0, help="workgroups per launch with --variant (0: one per tile)")
+    ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB mebibytes (3 launches) and exit; "
+                         "profiling it gives the HBM counter scale factors")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
+    if args.copy_calibrate:
+        n = args.copy_calibrate * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}), flush=True)
+        return
     from paper_2403_04267_amd import inputs
     from paper_2403_04267_amd.salec import Salec
 
     pb = inputs.config_scale()
     ctx = Salec(pb, "cuda:0")
+    if args.variant >= 0:
+        ctx.set_schedule(args.variant, args.grid)
+    elif args.tune > 0:
+        ctx.tune(args.tune)  # advances the run; counted as warm-up
     if args.warmup:
         ctx.step(args.warmup)
     torch.cuda.synchronize()
@@ -101,6 +121,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_cell_update": bpc, "scope": "whole cycle"},
         "sim": {"t": d["t"], "dt": d["dt"], "cycle": d["cycle"]},
+        "schedule": ctx.schedule(),
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pb)

@@ -55,8 +55,10 @@ extern "C" {
 #define SALEC_E_DT_FLOOR (-6)  /* the time step fell below dt_floor              */
 
 #define SALEC_FP64 0  /* every field and all arithmetic in FP64                  */
-#define SALEC_MIXED 1 /* FP32 stencil/EoS/stress arithmetic; FP64 energy, mass,
-                         volume fractions, flux sums and the time step           */
+#define SALEC_MIXED 1 /* FP32 stencil, EoS, stress and velocity arithmetic and
+                         storage; FP64 density, volume fractions, internal
+                         energy, every mass / volume / energy flux and its sums,
+                         and the Courant reduction                               */
 
 #define SALEC_MAX_MAT 2
 
@@ -116,52 +118,103 @@ typedef struct salec_diag {
     int32_t err, err_cycle;
 } salec_diag_t;
 
+/* One member of an ensemble (salec_init_batch). Every member of a context
+ * uses the same precision. scene is used when has_scene != 0. */
+typedef struct salec_instance {
+    salec_grid grid;
+    salec_material mats[SALEC_MAX_MAT];
+    salec_pml pml;
+    salec_scene scene;
+    int32_t has_scene;
+    int32_t reserved;    /* must be 0                                            */
+} salec_instance;
+
+/* Launch schedule of the cycle kernel: tile shape (cells per workgroup tile,
+ * threads per workgroup), workgroups per launch and the time the tuner
+ * measured for it (0 if not timed). */
+typedef struct salec_schedule {
+    int32_t variant;     /* index of the tile shape, 0 .. salec_num_variants()-1 */
+    int32_t tile_r, tile_z, threads;
+    int32_t grid;        /* workgroups per launch (0: one per tile)              */
+    int32_t reserved;
+    double ms_per_cycle; /* measured by salec_tune(), else 0                     */
+} salec_schedule;
+
 typedef struct salec_ctx salec_ctx;
 
 /* Bytes of device memory salec_init() needs for this problem; 0 if invalid. */
 size_t salec_plan(const salec_grid *grid, const salec_material *mats, const salec_pml *pml);
 
-/* Lays out the state in dev_buf (dev_bytes >= salec_plan()), uploads the
- * constants and, if scene is not NULL, builds the impact scene (target
- * half-space of material 0, spherical projectile of material nmat-1) on the
- * device; otherwise the state is zero until salec_set_fields(). Computes the
- * first time step. stream: hipStream_t or NULL. */
+/* Lays out the state in dev_buf (dev_bytes >= salec_plan(), 256-byte
+ * aligned), uploads the constants and, if scene is not NULL, builds the
+ * impact scene (target half-space of material 0, spherical projectile of
+ * material nmat-1, Sec. 4) on the device; otherwise the state is zero until
+ * salec_set_fields(). Computes the first time step. stream: hipStream_t or
+ * NULL (a stream of the library's own is created). A context made here is
+ * an ensemble of one: instance index 0 below. */
 int salec_init(const salec_grid *grid, const salec_material *mats, const salec_pml *pml,
                const salec_scene *scene, void *dev_buf, size_t dev_bytes, void *stream,
                salec_ctx **out);
 
-/* Advances n >= 0 cycles (replaying captured HIP graphs), then synchronises
- * the stream once and returns the sticky device error, if any. */
+/* Ensembles: n >= 1 independent impacts of any sizes advanced together, one
+ * kernel launch per cycle for all of them (captured in HIP graphs); each
+ * member keeps its own time step, time and cycle count and its own sticky
+ * error. Same ownership rules as salec_plan/salec_init. */
+size_t salec_plan_batch(const salec_instance *inst, int32_t n);
+int salec_init_batch(const salec_instance *inst, int32_t n, void *dev_buf, size_t dev_bytes,
+                     void *stream, salec_ctx **out);
+int32_t salec_num_instances(const salec_ctx *ctx);
+
+/* Advances every member n >= 0 cycles (replaying captured HIP graphs), then
+ * synchronises the stream once and returns the first sticky device error
+ * among the members, if any (members without an error keep advancing). */
 int salec_step(salec_ctx *ctx, int32_t n);
 
 /* Enqueues n cycles without synchronising or checking errors (for timing
  * loops); errors surface at the next salec_step() or salec_diag(). */
 int salec_enqueue(salec_ctx *ctx, int32_t n);
 
-/* Copies the current state (and p, c2 if requested) to host FP64 arrays. */
-int salec_get_fields(salec_ctx *ctx, const salec_fields *out);
+/* Copies the current state of member `instance` (and p, c2 if requested)
+ * to host FP64 arrays. */
+int salec_get_fields(salec_ctx *ctx, int32_t instance, const salec_fields *out);
 
-/* Replaces the state with host arrays (rho, I, f, v required; s optional,
- * zero if NULL) and starts a new run at t = 0: PML auxiliaries and budgets
- * are cleared, the PML reference density is taken from rho, dt recomputed. */
-int salec_set_fields(salec_ctx *ctx, const salec_fields *in);
+/* Replaces the state of member `instance` with host arrays (rho, I, f, v
+ * required; s optional, zero if NULL) and starts a new run of that member at
+ * t = 0: PML auxiliaries and budgets are cleared, the PML reference density
+ * is taken from rho, dt recomputed, its error cleared. */
+int salec_set_fields(salec_ctx *ctx, int32_t instance, const salec_fields *in);
 
-/* PML auxiliaries expanded to full grids (zero outside the layers):
+/* PML auxiliaries of member `instance` expanded to full grids (zero outside
+ * the layers):
  *   cell_aux 8*NZ*NR: phi1_b, phi3_b, psi2_b, phi1_r, phi3_r, psi2_r, rho_ref, msink
  *   node_aux 8*(NZ+1)*(NR+1): phi2_b (r, z), psi1_b (r, z), phi2_r (r, z), psi1_r (r, z) */
-int salec_get_pml(salec_ctx *ctx, double *cell_aux, double *node_aux);
+int salec_get_pml(salec_ctx *ctx, int32_t instance, double *cell_aux, double *node_aux);
 
-/* Checkpoint: the whole device state (fields, PML, budgets, t, dt, cycle). */
+/* Checkpoint: the whole device state of every member (fields, EoS cache,
+ * PML, budgets, t, dt, cycle, errors). */
 size_t salec_state_bytes(const salec_ctx *ctx);
 int salec_get_state(salec_ctx *ctx, void *host_blob, size_t bytes);
 int salec_set_state(salec_ctx *ctx, const void *host_blob, size_t bytes);
 
-/* Time, step, cycle, compensated totals and budgets, sticky error. */
-int salec_diag(salec_ctx *ctx, salec_diag_t *out);
+/* Time, step, cycle, compensated totals and budgets, sticky error of one
+ * member. */
+int salec_diag(salec_ctx *ctx, int32_t instance, salec_diag_t *out);
 
-/* Device time of the grid-update kernels over the last salec_step() call,
- * measured with HIP events on the context's stream, in milliseconds. */
+/* Device time of the cycle kernels over the last salec_step() call, measured
+ * with HIP events on the context's stream, in milliseconds. */
 int salec_last_step_ms(salec_ctx *ctx, double *ms);
+
+/* Launch schedules. Every tile shape computes bit-identical results, so the
+ * schedule only changes speed. salec_set_schedule() selects a shape and a
+ * workgroup count (grid 0: one workgroup per tile; otherwise that many
+ * workgroups walk the tiles). salec_tune() times each shape over `cycles`
+ * real cycles of the run (after one warm-up cycle each: the members advance
+ * by (cycles + 1) * salec_num_variants() cycles), keeps the fastest and
+ * reports it in out (may be NULL). */
+int32_t salec_num_variants(void);
+int salec_get_schedule(const salec_ctx *ctx, salec_schedule *out);
+int salec_set_schedule(salec_ctx *ctx, int32_t variant, int32_t grid);
+int salec_tune(salec_ctx *ctx, int32_t cycles, salec_schedule *out);
 
 const char *salec_last_error(const salec_ctx *ctx);
 void salec_destroy(salec_ctx *ctx);

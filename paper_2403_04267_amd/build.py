@@ -1,30 +1,51 @@
 """Build libsalec.so (HIP, gfx950) in-tree with hipcc.
 
 FP64 parity build: no floating-point contraction (-ffp-contract=off), no
-fast-math; packed FP32 instructions disabled (-packed-fp32-ops).
+fast-math; packed FP32 instructions disabled (-packed-fp32-ops). Each
+translation unit compiles in its own process (the two cycle-kernel units are
+the slow ones), then one link step.
 """
+import concurrent.futures as cf
 import os
 import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsalec.so")
-SOURCES = ["salec_kernels.hip", "salec_fused.hip", "salec_host.hip"]
-HEADERS = ["salec_device.hpp", "salec_internal.hpp"]
+SOURCES = ["salec_cycle_f64.hip", "salec_cycle_f32.hip", "salec_cycle.hip", "salec_kernels.hip",
+           "salec_host.hip"]
+HEADERS = ["salec_device.hpp", "salec_internal.hpp", "salec_cycle.hpp"]
 ARCH = os.environ.get("SALEC_ARCH", "gfx950")
 
 
 def flags():
-    return ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
+    return ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
             "-ffp-contract=off", "-fno-fast-math",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
 
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+    cmd = ["hipcc"] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    out = "\n".join(ln for ln in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in ln)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{out}")
+    if out.strip() and verbose:
+        print(out, flush=True)
+    return obj
+
+
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    cmd = ["hipcc"] + flags() + srcs + ["-o", LIB + ".tmp"]
+    os.makedirs(OBJ, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC"] + objs + ["-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

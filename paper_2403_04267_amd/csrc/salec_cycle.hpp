@@ -1,0 +1,795 @@
+// salec_cycle.hpp -- the whole explicit cycle of the r-z SALE scheme with PML
+// (Li et al., SALEc-2D: Sec. 2 eqs. (1)-(5), Sec. 3, Sec. 4, Sec. 7) as ONE
+// gfx950 kernel launch per cycle, for one instance or a batch of instances.
+//
+// A launch walks a schedule of (instance, tile) entries. Each workgroup takes
+// entries in a grid-stride loop; for a TW x TH tile of cells (and the nodes
+// at their lower-left corners) it recomputes every phase over the halo it
+// needs, keeping intermediates in LDS:
+//   A  cells [i0-3, i0+TW+3)  viscosity, phi-scaled stress (EoS from cache) -> LDS
+//   B  nodes [i0-2, i0+TW+2]  control-volume force, PML psi1 -> v^L         -> LDS
+//   C  cells [i0-2, i0+TW+1]  Lagrangian update, PML psi2, limiter           -> LDS
+//   E1 faces of the cells below: volume and donor mass fluxes                -> LDS
+//   E2 cells [i0-1, i0+TW]    donor-cell remap, PML phi1/phi3                -> LDS
+//   F  nodes [i0, i0+TW]      momentum remap, KE-loss heat, PML phi2         -> LDS
+//   G  cells of the tile      heat, checks, EoS of the new state (cached), dt
+// (the same ranges in z). Halo values are recomputed with bit-identical
+// arithmetic; only the owner of a cell or node writes it. The state, its EoS
+// cache and the PML auxiliaries ping-pong by cycle parity, so every halo read
+// sees level n. The Courant minimum of a tile is reduced with wave shuffles
+// and LDS; the last tile of an instance to finish (done counter) finalises
+// that instance's t, dt and cycle count, so instances keep their own dt.
+//
+// T is the bulk arithmetic and storage type of stress, velocity and the EoS
+// cache (double, or float in the mixed mode). Density, volume fractions,
+// internal energy, every mass / volume / energy flux and its sums, and the
+// Courant reduction are FP64 in both modes.
+#pragma once
+#include "salec_device.hpp"
+#include "salec_internal.hpp"
+
+namespace salec {
+
+template <int TW, int TH>
+struct Regions {
+  static constexpr int AW = TW + 6, AH = TH + 6, NA = AW * AH;  // cells, origin (i0-3, j0-3)
+  static constexpr int BW = TW + 5, BH = TH + 5, NB = BW * BH;  // nodes, origin (i0-2, j0-2)
+  static constexpr int CW = TW + 4, CH = TH + 4, NC = CW * CH;  // cells, origin (i0-2, j0-2)
+  static constexpr int EW = TW + 2, EH = TH + 2, NE = EW * EH;  // cells, origin (i0-1, j0-1)
+  static constexpr int FW = TW + 1, FH = TH + 1, NF = FW * FH;  // nodes, origin (i0, j0)
+  static constexpr int RW = TW + 3, RH = TH + 2, NRF = RW * RH;  // radial faces, origin (i0-1, j0-1)
+  static constexpr int ZW = TW + 2, ZH = TH + 3, NZF = ZW * ZH;  // axial faces, origin (i0-1, j0-1)
+};
+
+template <int TW, int TH, class T>
+struct Smem {
+  using R = Regions<TW, TH>;
+  static constexpr int kBigA = 4 * R::NA * (int)sizeof(T);          // sigma[4][NA]
+  static constexpr int kBigC = R::NC * (4 * 8 + 4 * (int)sizeof(T));  // rhoL, IL, f0, f1 | lambda, sL x3
+  static constexpr int kBigF = R::NF * (8 + (int)sizeof(T));          // heat | speed
+  static constexpr int kBig = kBigA > kBigC ? (kBigA > kBigF ? kBigA : kBigF) : (kBigC > kBigF ? kBigC : kBigF);
+  static constexpr int kBigD = (kBig + 7) / 8;
+};
+
+__device__ __forceinline__ bool in_cells(const Geo& g, int i, int j) {
+  return i >= 0 && i < g.NR && j >= 0 && j < g.NZ;
+}
+
+// Courant candidate of one cell of a new state, and its EoS (cached for the
+// next cycle). u4 is the largest corner speed.
+template <class T>
+__device__ __forceinline__ double cell_dt(const Geo& g, const Mix<T>& mx, T u4) {
+  using N = Num<T>;
+  T cl2 = mx.c2 + N::div(T(4.0 / 3.0) * mx.G, tmax(mx.rmat, GeoT<T>::rho_ref(g) * T(kRhoDenFloor)));
+  T cl = N::sqr(cl2);
+  T wgt = tmin(tmax(N::div(mx.phi - T(kWLo), T(kWHi - kWLo)), T(0)), T(1));
+  if (wgt > T(0)) return g.cfl * dmin(g.dr, g.dz) / (((double)cl + (double)u4) * (double)wgt);
+  return __builtin_huge_val();
+}
+
+template <class T>
+__device__ __forceinline__ void store_eos(const State& D, long long c, const Mix<T>& mx) {
+  ((T*)D.eos[0])[c] = mx.p;
+  ((T*)D.eos[1])[c] = mx.c2;
+  ((T*)D.eos[2])[c] = mx.G;
+  ((T*)D.eos[3])[c] = mx.Y;
+  ((T*)D.eos[4])[c] = mx.sx;
+}
+
+// Reduces `cand` over the workgroup into s_min[0] (all threads call it).
+template <int NT>
+__device__ __forceinline__ double block_min(double cand, double* s_min) {
+  for (int off = 32; off > 0; off >>= 1) cand = dmin(cand, __shfl_down(cand, off, 64));
+  if ((threadIdx.x & 63) == 0) s_min[threadIdx.x >> 6] = cand;
+  __syncthreads();
+  double m = s_min[0];
+  for (int q = 1; q < NT / 64; q++) m = dmin(m, s_min[q]);
+  return m;
+}
+
+template <int TW, int TH, int NT, class T>
+__device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_rho, double* s_bigd, T* s_vL,
+                                           double* s_Fr, double* s_Fz, double* s_rho1, double* s_min,
+                                           int* s_last) {
+  using R = Regions<TW, TH>;
+  using N = Num<T>;
+  using GT = GeoT<T>;
+  constexpr int UA = (R::NA + NT - 1) / NT;
+
+  const Geo& g = in.g;
+  Scal* sc = in.sc;
+  if (sc->err) return;
+  const int tid = threadIdx.x;
+  const int ti = tile % in.tiles_r, tj = tile / in.tiles_r;
+  const int i0 = ti * TW, j0 = tj * TH;
+  const int i1 = min(i0 + TW, g.NR), j1 = min(j0 + TH, g.NZ);  // owned cells [i0, i1) x [j0, j1)
+  const int par = (int)(sc->cycle & 1);
+  const State& S = in.S[par];
+  const State& D = in.S[par ^ 1];
+  const Pml& pm = in.pm;
+  const PmlAux& po = pm.a[par];
+  const PmlAux& pn = pm.a[par ^ 1];
+  const T* Sv0 = (const T*)S.v[0];
+  const T* Sv1 = (const T*)S.v[1];
+  const T* Ss0 = (const T*)S.s[0];
+  const T* Ss1 = (const T*)S.s[1];
+  const T* Ss2 = (const T*)S.s[2];
+  const double dt = sc->dt;
+  const T dtT = (T)dt;
+  const T dr = GT::dr(g), dz = GT::dz(g);
+  const T hdz = T(0.5) * dz;
+  const double hdzd = 0.5 * g.dz;
+  auto owns_cell = [&](int i, int j) { return i >= i0 && i < i1 && j >= j0 && j < j1; };
+  auto owns_node = [&](int i, int j) {
+    bool oi = (i >= i0 && i < i1) || (i == g.NR && i1 == g.NR);
+    bool oj = (j >= j0 && j < j1) || (j == g.NZ && j1 == g.NZ);
+    return oi && oj;
+  };
+  auto kA = [&](int i, int j) { return (i - (i0 - 3)) + (j - (j0 - 3)) * R::AW; };
+  auto kB = [&](int i, int j) { return (i - (i0 - 2)) + (j - (j0 - 2)) * R::BW; };
+  auto kC = [&](int i, int j) { return (i - (i0 - 2)) + (j - (j0 - 2)) * R::CW; };
+  auto kE = [&](int i, int j) { return (i - (i0 - 1)) + (j - (j0 - 1)) * R::EW; };
+  auto kF = [&](int i, int j) { return (i - i0) + (j - j0) * R::FW; };
+  auto kR = [&](int i, int j) { return (i - (i0 - 1)) + (j - (j0 - 1)) * R::RW; };
+  auto kZ = [&](int i, int j) { return (i - (i0 - 1)) + (j - (j0 - 1)) * R::ZW; };
+  T* sig = (T*)s_bigd;                // [4][NA] during A..B
+  double* cd = s_bigd;                // [4][NC] rhoL, IL, f0, f1 during C..E2
+  T* ct = (T*)(s_bigd + 4 * R::NC);   // [4][NC] lambda, sL x3 during C..E2
+  double* heat = s_bigd;              // [NF] during F..G
+  T* speed = (T*)(s_bigd + R::NF);    // [NF] during F..G
+
+  // ------------------------------------------------------------------ A
+  T rP[UA];
+#pragma unroll
+  for (int u = 0; u < UA; u++) {
+    int k = tid + u * NT;
+    rP[u] = T(0);
+    if (k >= R::NA) continue;
+    int i = i0 - 3 + k % R::AW, j = j0 - 3 + k / R::AW;
+    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+    double rh = 0.0;
+    if (in_cells(g, i, j)) {
+      long long c = cidx(g, i, j);
+      T f[kMaxMat];
+#pragma unroll
+      for (int m = 0; m < kMaxMat; m++) f[m] = m < g.nmat ? (T)S.f[m][c] : T(0);
+      rh = S.rho[c];
+      T phi, den, rm;
+      matter(g, (T)rh, f, phi, den, rm);
+      T p = ((const T*)S.eos[0])[c], c2 = ((const T*)S.eos[1])[c], sx = ((const T*)S.eos[4])[c];
+      T vr4[4] = {Sv0[nidx(g, i, j)], Sv0[nidx(g, i + 1, j)], Sv0[nidx(g, i, j + 1)], Sv0[nidx(g, i + 1, j + 1)]};
+      T vz4[4] = {Sv1[nidx(g, i, j)], Sv1[nidx(g, i + 1, j)], Sv1[nidx(g, i, j + 1)], Sv1[nidx(g, i + 1, j + 1)]};
+      Kin<T> kn = kinematics(g, i, vr4, vz4);
+      T L = tmin(dr, dz);
+      T dDn = dtT * kn.D;
+      T Jn = T(1) + dDn;
+      T Dm = Jn < T(1) ? N::div(Vol<T>::closing(Jn, dDn, phi, sx), dtT) : T(0);
+      T Ld = L * Dm;
+      T Q = rm * (GT::q_quad(g) * Ld * Ld + GT::q_lin(g) * N::sqr(c2) * Ld);
+      T P = p + Q;
+      T srr = T(0), szz = T(0), srz = T(0);
+      if (g.any_strength) {
+        srr = Ss0[c];
+        szz = Ss1[c];
+        srz = Ss2[c];
+      }
+      T stt = -(srr + szz);
+      s0 = phi * (srr - P);
+      s1 = phi * (szz - P);
+      s2 = phi * (stt - P);
+      s3 = phi * srz;
+      rP[u] = P;
+    }
+    sig[0 * R::NA + k] = s0;
+    sig[1 * R::NA + k] = s1;
+    sig[2 * R::NA + k] = s2;
+    sig[3 * R::NA + k] = s3;
+    s_rho[k] = rh;
+  }
+  __syncthreads();
+
+  // ------------------------------------------------------------------ B
+  for (int k = tid; k < R::NB; k += NT) {
+    int i = i0 - 2 + k % R::BW, j = j0 - 2 + k / R::BW;
+    T vLr = T(0), vLz = T(0);
+    if (i >= 0 && i <= g.NR && j >= 0 && j <= g.NZ) {
+      // quadrants NE = (i, j), NW = (i-1, j), SE = (i, j-1), SW = (i-1, j-1)
+      const int qa[4] = {kA(i, j), kA(i - 1, j), kA(i, j - 1), kA(i - 1, j - 1)};
+      T srr[4], szz[4], stt[4], srz[4], rh[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        srr[q] = sig[0 * R::NA + qa[q]];
+        szz[q] = sig[1 * R::NA + qa[q]];
+        stt[q] = sig[2 * R::NA + qa[q]];
+        srz[q] = sig[3 * R::NA + qa[q]];
+        rh[q] = (T)s_rho[qa[q]];
+      }
+      T rN = (T)i * dr;
+      T rE = ((T)i + T(0.5)) * dr;
+      T rW = ((T)i - T(0.5)) * dr;
+      T aE = i < g.NR ? Ring<T>::w(g, i) : T(0);
+      T aW = i > 0 ? Ring<T>::e(g, i - 1) : T(0);
+      T Frr = hdz * ((rE * (srr[0] - stt[0]) + rN * stt[0]) + (rE * (srr[2] - stt[2]) + rN * stt[2])) -
+              hdz * ((rW * (srr[1] - stt[1]) + rN * stt[1]) + (rW * (srr[3] - stt[3]) + rN * stt[3]));
+      T Frz = (aW * srz[1] + aE * srz[0]) - (aW * srz[3] + aE * srz[2]);
+      T Fzr = hdz * (rE * (srz[0] + srz[2]) - rW * (srz[1] + srz[3]));
+      T Fzz = (aW * szz[1] + aE * szz[0]) - (aW * szz[3] + aE * szz[2]);
+      T Fr = Frr + Frz, Fz = Fzr + Fzz;
+      T VcE = aE * hdz, VcW = aW * hdz;
+      T macc = VcE * (rh[0] + rh[2]) + VcW * (rh[1] + rh[3]);
+      T nzh = (T)((j < g.NZ) + (j > 0));
+      T Vd = (VcE + VcW) * nzh;
+      T mt = tmax(macc, T(kMAccEps) * GT::rho_ref(g) * Vd);
+      long long n = nidx(g, i, j);
+      T psr = T(0), psz = T(0);
+      double db = 0.0, drr = 0.0;
+      long long kb = -1, kr = -1;
+      if (g.pml_on) {
+        db = pm.dnz[j];
+        drr = pm.dnr[i];
+        if (j < g.pml_b) kb = pml_bn(g, i, j);
+        if (i > g.n_r) kr = pml_rn(g, i, j);
+        double br = kb >= 0 ? po.b_psi1r[kb] : 0.0, bz = kb >= 0 ? po.b_psi1z[kb] : 0.0;
+        double rr = kr >= 0 ? po.r_psi1r[kr] : 0.0, rz = kr >= 0 ? po.r_psi1z[kr] : 0.0;
+        psr = (T)(br + rr);
+        psz = (T)(bz + rz);
+      }
+      T Fer = Fr - Vd * psr, Fez = Fz - Vd * psz;
+      vLr = Sv0[n] + dtT * N::div(Fer, mt);
+      vLz = Sv1[n] + dtT * N::div(Fez, mt);
+      if (owns_node(i, j)) {
+        if (db > 0.0) {
+          pn.b_psi1r[kb] = po.b_psi1r[kb] - dt * db * (double)N::div(Frr, Vd);
+          pn.b_psi1z[kb] = po.b_psi1z[kb] - dt * db * (double)N::div(Fzr, Vd);
+        }
+        if (drr > 0.0) {
+          pn.r_psi1r[kr] = po.r_psi1r[kr] - dt * drr * (double)N::div(Frz, Vd);
+          pn.r_psi1z[kr] = po.r_psi1z[kr] - dt * drr * (double)N::div(Fzz, Vd);
+        }
+      }
+      if (i == 0 || i == g.NR) vLr = T(0);
+      if (j == 0) {
+        vLr = T(0);
+        vLz = T(0);
+      }
+      if (g.top_closed && j == g.NZ) vLz = T(0);
+    }
+    s_vL[k] = vLr;
+    s_vL[R::NB + k] = vLz;
+  }
+  __syncthreads();
+
+  // face volumes from v^L (radial face at r_i of row j; axial face at z_j of
+  // column i with dual-area node weights)
+  auto dv_r = [&](int i, int j) {
+    T u = T(0.5) * (s_vL[kB(i, j)] + s_vL[kB(i, j + 1)]);
+    return dtT * ((((T)i * dr) * dz) * u);
+  };
+  auto dv_z = [&](int i, int j) {
+    T rw = (T)i * dr, rc = ((T)i + T(0.5)) * dr;
+    T re = (T)(i + 1) * dr;
+    T aw = Ring<T>::w(g, i), ae = Ring<T>::e(g, i);
+    return dtT * (aw * s_vL[R::NB + kB(i, j)] + ae * s_vL[R::NB + kB(i + 1, j)]);
+  };
+
+  // ------------------------------------------------------------------ C
+  // (same cell-to-thread map as A, so A's per-cell results stay in registers;
+  // the stress buffer is dead after B, so results go straight into it)
+#pragma unroll
+  for (int u = 0; u < UA; u++) {
+    int k = tid + u * NT;
+    int i = i0 - 3 + k % R::AW, j = j0 - 3 + k / R::AW;
+    bool inC = k < R::NA && i >= i0 - 2 && i < i0 + TW + 2 && j >= j0 - 2 && j < j0 + TH + 2;
+    if (!inC) continue;
+    // outside the grid: a void donor (rho^L = 0, lambda = 1, zero state)
+    double oRhoL = 0.0, oIL = 0.0, of0 = 0.0, of1 = 0.0;
+    T oLam = T(1), os0 = T(0), os1 = T(0), os2 = T(0);
+    if (in_cells(g, i, j)) {
+      long long c = cidx(g, i, j);
+      const long long nd[4] = {nidx(g, i, j), nidx(g, i + 1, j), nidx(g, i, j + 1), nidx(g, i + 1, j + 1)};
+      const int nb[4] = {kB(i, j), kB(i + 1, j), kB(i, j + 1), kB(i + 1, j + 1)};
+      T vr4[4], vz4[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        vr4[q] = s_vL[nb[q]];
+        vz4[q] = s_vL[R::NB + nb[q]];
+      }
+      Kin<T> kn = kinematics(g, i, vr4, vz4);
+      T s0rr = T(0), s0zz = T(0), s0rz = T(0);
+      if (g.any_strength) {
+        s0rr = Ss0[c];
+        s0zz = Ss1[c];
+        s0rz = Ss2[c];
+      }
+      T srr = s0rr, szz = s0zz, srz = s0rz;
+      if (g.any_strength) {
+        T G = ((const T*)S.eos[2])[c], Y = ((const T*)S.eos[3])[c];
+        T tr3 = N::div((kn.err + kn.ezz) + kn.ett, T(3));
+        T om = kn.om;
+        T dsrr = T(2) * G * (kn.err - tr3) + T(2) * om * srz;
+        T dszz = T(2) * G * (kn.ezz - tr3) - T(2) * om * srz;
+        T dsrz = T(2) * G * kn.erz + om * (szz - srr);
+        srr = srr + dtT * dsrr;
+        szz = szz + dtT * dszz;
+        srz = srz + dtT * dsrz;
+        T J2 = srr * srr + szz * szz + srr * szz + srz * srz;
+        T seq = N::sqr(T(3) * J2);
+        if (seq > Y) {
+          T fac = N::div(Y, seq);
+          srr = srr * fac;
+          szz = szz * fac;
+          srz = srz * fac;
+        }
+      }
+      T stt = -(s0rr + s0zz);
+      T P = rP[u];
+      T sde = ((s0rr * kn.err + s0zz * kn.ezz) + stt * kn.ett) + T(2) * s0rz * kn.erz;
+      T dD = dtT * kn.D;
+      T J = T(1) + dD;
+      double rho = S.rho[c];
+      double f0n = S.f[0][c], f1n = g.nmat > 1 ? S.f[1][c] : 0.0;
+      T fq[kMaxMat] = {(T)f0n, (T)f1n};
+      T phi, den, rm;
+      matter(g, (T)rho, fq, phi, den, rm);
+      T Jm = Vol<T>::ratio(J, dD, phi, ((const T*)S.eos[4])[c]);
+      T Wdt = dtT * sde - P * Vol<T>::jm1(J, dD);
+      T rden = tmax(rm, GT::rho_ref(g) * T(kRhoDenFloor));
+      double rt = dmax(rho, g.rho_ref * kPmlRhoFloor);
+      T kd[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        T dvr = vr4[q] - Sv0[nd[q]], dvz = vz4[q] - Sv1[nd[q]];
+        kd[q] = T(0.5) * (dvr * dvr + dvz * dvz);
+      }
+      T rN0 = (T)i * dr, rC = ((T)i + T(0.5)) * dr, rN1 = (T)(i + 1) * dr;
+      T V = cell_volume<T>(g, i);
+      T wW = N::div(Ring<T>::w(g, i) * hdz, V);
+      T wE = N::div(Ring<T>::e(g, i) * hdz, V);
+      T hL = wW * (kd[0] + kd[2]) + wE * (kd[1] + kd[3]);
+      double psi2 = 0.0, db = 0.0, drr = 0.0;
+      long long kb = -1, kr = -1;
+      if (g.pml_on) {
+        db = pm.dcz[j];
+        drr = pm.dcr[i];
+        if (j < g.pml_b) kb = pml_bc(g, i, j);
+        if (i >= g.n_r) kr = pml_rc(g, i, j);
+        double b = kb >= 0 ? po.b_psi2[kb] : 0.0, r = kr >= 0 ? po.r_psi2[kr] : 0.0;
+        psi2 = b + r;
+      }
+      double IL = ((S.I[c] + (double)N::div(Wdt, rden)) + (double)hL) - dt * (psi2 / rt);
+      double fr = (double)N::div(Jm, J);
+      double f0 = f0n * fr;
+      double f1 = g.nmat > 1 ? f1n * fr : 0.0;
+      if (owns_cell(i, j)) {
+        if (db > 0.0) {
+          T Wr = ((s0rr * kn.err + stt * kn.ett) + s0rz * kn.dvz_dr) - P * kn.Dr;
+          pn.b_psi2[kb] = po.b_psi2[kb] - dt * db * (double)(phi * Wr);
+        }
+        if (drr > 0.0) {
+          T Wz = (s0zz * kn.ezz + s0rz * kn.dvr_dz) - P * kn.Dz;
+          pn.r_psi2[kr] = po.r_psi2[kr] - dt * drr * (double)(phi * Wz);
+        }
+      }
+      // donor outflow limiter: volume leaving through the four faces vs V^L
+      T dW = dv_r(i, j), dE = dv_r(i + 1, j), dS = dv_z(i, j), dN = dv_z(i, j + 1);
+      T O = ((tmax(-dW, T(0)) + tmax(dE, T(0))) + tmax(-dS, T(0))) + tmax(dN, T(0));
+      T VL = V * J;
+      oRhoL = rho / (double)J;
+      oIL = IL;
+      os0 = srr;
+      os1 = szz;
+      os2 = srz;
+      of0 = f0;
+      of1 = f1;
+      oLam = O > VL ? N::div(tmax(VL, T(0)), O) : T(1);
+    }
+    int kc = kC(i, j);
+    cd[0 * R::NC + kc] = oRhoL;
+    cd[1 * R::NC + kc] = oIL;
+    cd[2 * R::NC + kc] = of0;
+    cd[3 * R::NC + kc] = of1;
+    ct[0 * R::NC + kc] = oLam;
+    ct[1 * R::NC + kc] = os0;
+    ct[2 * R::NC + kc] = os1;
+    ct[3 * R::NC + kc] = os2;
+  }
+  __syncthreads();
+
+  // ------------------------------------------------------------------ E1
+  // mass flux of every face the remap and the momentum remap touch; 0 where
+  // there is no face
+  for (int k = tid; k < R::NRF; k += NT) {
+    int i = i0 - 1 + k % R::RW, j = j0 - 1 + k / R::RW;
+    double F = 0.0;
+    if (i >= 0 && i <= g.NR && j >= 0 && j < g.NZ) {
+      T dV = dv_r(i, j);
+      int d = dV > T(0) ? kC(i - 1, j) : kC(i, j);
+      if (dV > T(0) || dV < T(0)) F = ((double)dV * (double)ct[0 * R::NC + d]) * cd[0 * R::NC + d];
+    }
+    s_Fr[k] = F;
+  }
+  for (int k = tid; k < R::NZF; k += NT) {
+    int i = i0 - 1 + k % R::ZW, j = j0 - 1 + k / R::ZW;
+    double F = 0.0;
+    if (i >= 0 && i < g.NR && j >= 0 && j <= g.NZ) {
+      T dV = dv_z(i, j);
+      int d = dV > T(0) ? kC(i, j - 1) : kC(i, j);
+      if (dV > T(0) || dV < T(0)) F = ((double)dV * (double)ct[0 * R::NC + d]) * cd[0 * R::NC + d];
+    }
+    s_Fz[k] = F;
+  }
+  __syncthreads();
+
+  // ------------------------------------------------------------------ E2
+  unsigned flags = 0;
+  for (int k = tid; k < R::NE; k += NT) {
+    int i = i0 - 1 + k % R::EW, j = j0 - 1 + k / R::EW;
+    double rho1 = 0.0;
+    if (in_cells(g, i, j)) {
+      bool own = owns_cell(i, j);
+      double V = cell_volume<double>(g, i);
+      T dV[4] = {dv_r(i, j), dv_r(i + 1, j), dv_z(i, j), dv_z(i, j + 1)};
+      double F[4] = {s_Fr[kR(i, j)], s_Fr[kR(i + 1, j)], s_Fz[kZ(i, j)], s_Fz[kZ(i, j + 1)]};
+      const int dk[4] = {kC(i - 1, j), kC(i + 1, j), kC(i, j - 1), kC(i, j + 1)};
+      const bool inq[4] = {dV[0] > T(0), dV[1] < T(0), dV[2] > T(0), dV[3] < T(0)};
+      int kc = kC(i, j);
+      double netin = ((F[0] - F[1]) + F[2]) - F[3];
+      rho1 = s_rho[kA(i, j)] + netin / V;
+      double M1 = rho1 * V;
+      double min_ = 0.0, nI = 0.0, nsrr = 0.0, nszz = 0.0, nsrz = 0.0, vcut = 0.0;
+      double nf0 = 0.0, nf1 = 0.0;
+      double IL = cd[1 * R::NC + kc];
+      double sL0 = (double)ct[1 * R::NC + kc], sL1 = (double)ct[2 * R::NC + kc], sL2 = (double)ct[3 * R::NC + kc];
+      double fL0 = cd[2 * R::NC + kc], fL1 = cd[3 * R::NC + kc];
+      double ed[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        // e = dV * lambda of the donor (the own cell on outflow faces)
+        int d = inq[q] ? dk[q] : kc;
+        if (inq[q]) {
+          double adV = fabs((double)dV[q] * (double)ct[0 * R::NC + d]);
+          double aF = fabs(F[q]);
+          vcut += fabs((double)dV[q]) - adV;
+          double Id = cd[1 * R::NC + d];
+          min_ += aF;
+          nI += aF * (Id - IL);
+          nsrr += aF * ((double)ct[1 * R::NC + d] - sL0);
+          nszz += aF * ((double)ct[2 * R::NC + d] - sL1);
+          nsrz += aF * ((double)ct[3 * R::NC + d] - sL2);
+          nf0 += adV * (cd[2 * R::NC + d] - fL0);
+          if (g.nmat > 1) nf1 += adV * (cd[3 * R::NC + d] - fL1);
+          ed[q] = F[q] * Id;
+        } else {
+          ed[q] = F[q] * IL;
+        }
+      }
+      double lam = (double)ct[0 * R::NC + kc];
+      double O = (double)(((tmax(-dV[0], T(0)) + tmax(dV[1], T(0))) + tmax(-dV[2], T(0))) + tmax(dV[3], T(0)));
+      double den = dmax(dmax(M1, min_), kMRemapFloor * g.rho_ref * V);
+      double I1 = IL + nI / den;
+      double ex = (1.0 - lam) * O - vcut;
+      double f1a = dmax(fL0 + (nf0 + fL0 * ex) / V, 0.0);
+      double f1b = g.nmat > 1 ? dmax(fL1 + (nf1 + fL1 * ex) / V, 0.0) : 0.0;
+      double fs = g.nmat > 1 ? f1a + f1b : f1a;
+      if (g.pml_on) {
+        double db = pm.dcz[j], drr = pm.dcr[i];
+        if (db > 0.0 || drr > 0.0) {
+          long long kb = j < g.pml_b ? pml_bc(g, i, j) : -1;
+          long long kr = i >= g.n_r ? pml_rc(g, i, j) : -1;
+          long long ku = pml_cell_union(g, i, j);
+          double dsum = db + drr;
+          double p1b = kb >= 0 ? po.b_phi1[kb] : 0.0, p1r = kr >= 0 ? po.r_phi1[kr] : 0.0;
+          double p3b = kb >= 0 ? po.b_phi3[kb] : 0.0, p3r = kr >= 0 ? po.r_phi3[kr] : 0.0;
+          double rho2 = dmax(rho1 - dt * (dsum * (rho1 - pm.rref[ku]) + (p1b + p1r)), 0.0);
+          double rt = dmax(rho1, g.rho_ref * kPmlRhoFloor);
+          double I2 = I1 - dt * (dsum * I1 + (p3b + p3r) / rt);
+          if (own) {
+            pm.msink[ku] = pm.msink[ku] + V * (rho1 - rho2);
+            if (db > 0.0) {
+              pn.b_phi1[kb] = p1b + db * ((F[1] - F[0]) / V);
+              pn.b_phi3[kb] = p3b + db * ((ed[1] - ed[0]) / V);
+            }
+            if (drr > 0.0) {
+              pn.r_phi1[kr] = p1r + drr * ((F[3] - F[2]) / V);
+              pn.r_phi3[kr] = p3r + drr * ((ed[3] - ed[2]) / V);
+            }
+          }
+          rho1 = rho2;
+          I1 = I2;
+        }
+      }
+      if (own) {
+        long long c = cidx(g, i, j);
+        D.rho[c] = rho1;
+        double fa = f1a / dmax(fs, 1.0);
+        double fb = f1b / dmax(fs, 1.0);
+        D.f[0][c] = fa;
+        if (g.nmat > 1) D.f[1][c] = fb;
+        T s0n = (T)(sL0 + nsrr / den), s1n = (T)(sL1 + nszz / den), s2n = (T)(sL2 + nsrz / den);
+        if (g.any_strength) {
+          ((T*)D.s[0])[c] = s0n;
+          ((T*)D.s[1])[c] = s1n;
+          ((T*)D.s[2])[c] = s2n;
+        }
+        if (j == g.NZ - 1) {
+          in.mout[i] += F[3];
+          in.eout[i] += ed[3];
+        }
+        // internal energy before the remap heat, which G adds
+        D.I[c] = I1;
+        double chk = rho1 + I1;
+        if (g.any_strength) chk += (double)s0n + (double)s1n + (double)s2n;
+        chk += fa;
+        if (g.nmat > 1) chk += fb;
+        if (!((chk - chk) == 0.0)) flags |= kFlagNonFinite;
+        if (rho1 < -kNegMassTol * g.rho_ref) flags |= kFlagNegMass;
+      }
+    }
+    s_rho1[k] = rho1;
+  }
+  __syncthreads();
+
+  // ------------------------------------------------------------------ F
+  for (int k = tid; k < R::NF; k += NT) {
+    int i = i0 + k % R::FW, j = j0 + k / R::FW;
+    if (i > g.NR || j > g.NZ) continue;
+    // node mass: a quarter of the four cell masses (SW, SE, NW, NE)
+    const int qi[4] = {i - 1, i, i - 1, i}, qj[4] = {j - 1, j - 1, j, j};
+    double M[4] = {0, 0, 0, 0};
+    bool qok[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      qok[q] = in_cells(g, qi[q], qj[q]);
+      if (qok[q]) M[q] = s_rho[kA(qi[q], qj[q])] * cell_volume<double>(g, qi[q]);
+    }
+    double mL = 0.25 * ((M[0] + M[1]) + (M[2] + M[3]));
+    double FD[4];
+    FD[0] = 0.25 * ((s_Fr[kR(i - 1, j - 1)] + s_Fr[kR(i, j - 1)]) + (s_Fr[kR(i - 1, j)] + s_Fr[kR(i, j)]));
+    FD[1] = 0.25 * ((s_Fr[kR(i, j - 1)] + s_Fr[kR(i + 1, j - 1)]) + (s_Fr[kR(i, j)] + s_Fr[kR(i + 1, j)]));
+    FD[2] = 0.25 * ((s_Fz[kZ(i - 1, j - 1)] + s_Fz[kZ(i, j - 1)]) + (s_Fz[kZ(i - 1, j)] + s_Fz[kZ(i, j)]));
+    FD[3] = 0.25 * ((s_Fz[kZ(i - 1, j)] + s_Fz[kZ(i, j)]) + (s_Fz[kZ(i - 1, j + 1)] + s_Fz[kZ(i, j + 1)]));
+    if (i == 0) FD[0] = 0.0;
+    if (i == g.NR) FD[1] = 0.0;
+    if (j == 0) FD[2] = 0.0;
+    const int ni[4] = {i - 1, i + 1, i, i}, nj[4] = {j, j, j - 1, j + 1};
+    const bool inq[4] = {FD[0] > 0.0, FD[1] < 0.0, FD[2] > 0.0, FD[3] < 0.0};
+    double m1 = mL + (((FD[0] - FD[1]) + FD[2]) - FD[3]);
+    int kb0 = kB(i, j);
+    T vLr = s_vL[kb0], vLz = s_vL[R::NB + kb0];
+    double min_ = 0.0, nr = 0.0, nz = 0.0, kin = 0.0;
+    T upr[4], upz[4];
+    bool ok[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      ok[q] = ni[q] >= 0 && ni[q] <= g.NR && nj[q] >= 0 && nj[q] <= g.NZ;
+      if (inq[q] && ok[q]) {
+        int d = kB(ni[q], nj[q]);
+        double aF = fabs(FD[q]);
+        T ur = s_vL[d], uz = s_vL[R::NB + d];
+        min_ += aF;
+        nr += aF * (double)(ur - vLr);
+        nz += aF * (double)(uz - vLz);
+        upr[q] = ur;
+        upz[q] = uz;
+      } else {
+        upr[q] = vLr;
+        upz[q] = vLz;
+      }
+    }
+    double rN = (double)i * g.dr;
+    double rE = ((double)i + 0.5) * g.dr;
+    double rW = ((double)i - 0.5) * g.dr;
+    double aE = i < g.NR ? 0.5 * (rE * rE - rN * rN) : 0.0;
+    double aW = i > 0 ? 0.5 * (rN * rN - rW * rW) : 0.0;
+    double nzh = (double)((j < g.NZ) + (j > 0));
+    double Vd = (aE * hdzd + aW * hdzd) * nzh;
+    double den = dmax(dmax(m1, min_), kMRemapFloor * g.rho_ref * Vd);
+    double v1r = (double)vLr + nr / den;
+    double v1z = (double)vLz + nz / den;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      if (inq[q] && ok[q]) {
+        T ar = upr[q] - vLr, az = upz[q] - vLz;
+        kin += fabs(FD[q]) * (double)(ar * ar + az * az);
+      }
+    }
+    double dKE = 0.5 * (kin - (nr * nr + nz * nz) / den);
+    double Mn = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+      if (qok[q]) Mn += s_rho1[kE(qi[q], qj[q])] * cell_volume<double>(g, qi[q]);
+    double h = Mn > kMRemapFloor * g.rho_ref * Vd ? dmax(dKE, 0.0) / Mn : 0.0;
+    bool own = owns_node(i, j);
+    if (g.pml_on) {
+      double db = pm.dnz[j], drr = pm.dnr[i];
+      if (db > 0.0 || drr > 0.0) {
+        long long kb = j < g.pml_b ? pml_bn(g, i, j) : -1;
+        long long kr = i > g.n_r ? pml_rn(g, i, j) : -1;
+        double dsum = db + drr;
+        double mt = dmax(m1, kMAccEps * g.rho_ref * Vd);
+        double bpr = kb >= 0 ? po.b_phi2r[kb] : 0.0, bpz = kb >= 0 ? po.b_phi2z[kb] : 0.0;
+        double rpr = kr >= 0 ? po.r_phi2r[kr] : 0.0, rpz = kr >= 0 ? po.r_phi2z[kr] : 0.0;
+        double pr = bpr + rpr, pz = bpz + rpz;
+        double v2r = v1r - dt * (dsum * v1r + (pr * Vd) / mt);
+        double v2z = v1z - dt * (dsum * v1z + (pz * Vd) / mt);
+        if (own) {
+          if (db > 0.0) {
+            pn.b_phi2r[kb] = bpr + db * ((FD[1] * (double)upr[1] - FD[0] * (double)upr[0]) / Vd);
+            pn.b_phi2z[kb] = bpz + db * ((FD[1] * (double)upz[1] - FD[0] * (double)upz[0]) / Vd);
+          }
+          if (drr > 0.0) {
+            pn.r_phi2r[kr] = rpr + drr * ((FD[3] * (double)upr[3] - FD[2] * (double)upr[2]) / Vd);
+            pn.r_phi2z[kr] = rpz + drr * ((FD[3] * (double)upz[3] - FD[2] * (double)upz[2]) / Vd);
+          }
+        }
+        v1r = v2r;
+        v1z = v2z;
+      }
+    }
+    T vr = (T)v1r, vz = (T)v1z;
+    if (i == 0 || i == g.NR) vr = T(0);
+    if (j == 0) {
+      vr = T(0);
+      vz = T(0);
+    }
+    if (g.top_closed && j == g.NZ) vz = T(0);
+    if (own) {
+      long long n = nidx(g, i, j);
+      ((T*)D.v[0])[n] = vr;
+      ((T*)D.v[1])[n] = vz;
+    }
+    heat[k] = h;
+    speed[k] = N::sqr(vr * vr + vz * vz);
+    // a non-finite velocity makes the speed non-finite and is caught in G
+  }
+  __syncthreads();
+
+  // ------------------------------------------------------------------ G
+  // (the new state of the tile's cells was written in E2 by the same
+  // threads: the cell-to-thread map of the E region)
+  double cand = __builtin_huge_val();
+  constexpr int UE = (R::NE + NT - 1) / NT;
+#pragma unroll
+  for (int u = 0; u < UE; u++) {
+    int k = tid + u * NT;
+    if (k >= R::NE) continue;
+    int i = i0 - 1 + k % R::EW, j = j0 - 1 + k / R::EW;
+    if (!owns_cell(i, j)) continue;
+    long long c = cidx(g, i, j);
+    const int nf[4] = {kF(i, j), kF(i + 1, j), kF(i, j + 1), kF(i + 1, j + 1)};
+    double h = (heat[nf[0]] + heat[nf[1]]) + (heat[nf[2]] + heat[nf[3]]);
+    double I1 = D.I[c] + h;
+    D.I[c] = I1;
+    if (!((I1 - I1) == 0.0)) flags |= kFlagNonFinite;
+    T u4 = T(0);
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      T sp = speed[nf[q]];
+      if (!((sp - sp) == T(0))) flags |= kFlagNonFinite;
+      u4 = tmax(u4, sp);
+    }
+    double f[kMaxMat] = {D.f[0][c], g.nmat > 1 ? D.f[1][c] : 0.0};
+    Mix<T> mx = mixture<T>(g, D.rho[c], I1, f);
+    store_eos(D, c, mx);
+    cand = dmin(cand, cell_dt(g, mx, u4));
+  }
+  if (flags) atomicOr(&sc->flags, flags);
+  double m = block_min<NT>(cand, s_min);
+  if (tid == 0) {
+    in.dtpart[tile] = m;
+    __threadfence();
+    unsigned prev = atomicAdd(&sc->done, 1u);
+    *s_last = (prev == (unsigned)(in.ntiles - 1));
+  }
+  __syncthreads();
+  if (!*s_last) return;
+  // ------------------------------------------------------------ finalize
+  __threadfence();
+  double mm = __builtin_huge_val();
+  for (int q = tid; q < in.ntiles; q += NT)
+    mm = dmin(mm, __hip_atomic_load(&in.dtpart[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  __syncthreads();  // s_min is reused
+  mm = block_min<NT>(mm, s_min);
+  if (tid == 0) {
+    double t = sc->t + sc->dt;
+    sc->t = t;
+    sc->cycle = sc->cycle + 1;
+    double dtn = dmin(dmin(mm, g.dt_grow * sc->dt), g.dt_max);
+    if (g.t_stop > 0) dtn = dmin(dtn, dmax(g.t_stop - t, 0.0));
+    sc->dt_prev = sc->dt;
+    sc->dt = dtn;
+    sc->done = 0u;
+    unsigned fl = __hip_atomic_load(&sc->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int e = 0;
+    if (fl & kFlagNonFinite) e = -4;
+    else if (fl & kFlagNegMass) e = -5;
+    bool stopped = g.t_stop > 0 && t >= g.t_stop;
+    if (e == 0 && !stopped && dtn < g.dt_floor) e = -6;
+    if (e) {
+      sc->err = e;
+      sc->err_cycle = (int)sc->cycle;
+    }
+  }
+}
+
+template <int TW, int TH, int NT, class T>
+__global__ __launch_bounds__(NT) void k_cycle(const Inst* __restrict__ insts, const TileRef* __restrict__ sched,
+                                              int nsched) {
+  using R = Regions<TW, TH>;
+  using SM = Smem<TW, TH, T>;
+  __shared__ double s_rho[R::NA];     // rho^n over A (0 outside the grid)
+  __shared__ double s_bigd[SM::kBigD];  // A..B stress; C..E2 Lagrangian state; F..G heat, speed
+  __shared__ T s_vL[2 * R::NB];       // v^L over B
+  __shared__ double s_Fr[R::NRF], s_Fz[R::NZF];  // face mass fluxes (0 where no face)
+  __shared__ double s_rho1[R::NE];    // rho^{n+1} over E (0 outside the grid)
+  __shared__ double s_min[NT / 64];
+  __shared__ int s_last;
+  // Descriptors and schedule are read-only for the whole launch: reading them
+  // through the constant address space lets the compiler keep or re-issue
+  // those scalar loads freely across the workgroup barriers below.
+  using CInst = const __attribute__((address_space(4))) Inst;
+  using CTile = const __attribute__((address_space(4))) TileRef;
+  CInst* cinst = (CInst*)insts;
+  CTile* csched = (CTile*)sched;
+  for (int e = blockIdx.x; e < nsched; e += gridDim.x) {
+    const TileRef tr{csched[e].inst, csched[e].tile};
+    if (tr.inst < 0) continue;
+    const Inst* in = (const Inst*)(cinst + tr.inst);
+    tile_cycle<TW, TH, NT, T>(*in, tr.tile, s_rho, s_bigd, s_vL, s_Fr, s_Fz, s_rho1, s_min, &s_last);
+    __syncthreads();  // LDS is reused by the next entry
+  }
+}
+
+// EoS cache and Courant candidates of the current state of one instance (the
+// first step of a run, after the state was set).
+template <class T>
+__global__ void k_prime(Inst in) {
+  const Geo& g = in.g;
+  Scal* sc = in.sc;
+  const int par = (int)(sc->cycle & 1);
+  const State& S = in.S[par];
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double cand = __builtin_huge_val();
+  if (t < (long long)g.NR * g.NZ) {
+    int j = (int)(t / g.NR), i = (int)(t - (long long)j * g.NR);
+    long long c = cidx(g, i, j);
+    double f[kMaxMat] = {S.f[0][c], g.nmat > 1 ? S.f[1][c] : 0.0};
+    Mix<T> mx = mixture<T>(g, S.rho[c], S.I[c], f);
+    store_eos(S, c, mx);
+    const long long nd[4] = {nidx(g, i, j), nidx(g, i + 1, j), nidx(g, i, j + 1), nidx(g, i + 1, j + 1)};
+    T u4 = T(0);
+    for (int q = 0; q < 4; q++) {
+      T a = ((const T*)S.v[0])[nd[q]], b = ((const T*)S.v[1])[nd[q]];
+      u4 = tmax(u4, Num<T>::sqr(a * a + b * b));
+    }
+    cand = cell_dt(g, mx, u4);
+  }
+  for (int off = 32; off > 0; off >>= 1) cand = dmin(cand, __shfl_down(cand, off, 64));
+  __shared__ double part[4];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cand;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = dmin(dmin(part[0], part[1]), dmin(part[2], part[3]));
+    atomicMin(&sc->dtmin, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// Instantiates the cycle kernel of every tile shape and the priming kernel
+// for one bulk type (one translation unit per type keeps builds parallel).
+#define SALEC_CYCLE_TABLE(T, suffix)                                                         \
+  CycleFn cycle_kernel_##suffix(int v) {                                                       \
+    switch (v) {                                                                               \
+      case 0: return k_cycle<64, 16, 512, T>;                                                  \
+      case 1: return k_cycle<64, 16, 1024, T>;                                                 \
+      case 2: return k_cycle<32, 32, 1024, T>;                                                 \
+      case 3: return k_cycle<32, 16, 256, T>;                                                  \
+      default: return nullptr;                                                                 \
+    }                                                                                          \
+  }                                                                                            \
+  hipError_t launch_prime_##suffix(const Inst& in, hipStream_t st) {                           \
+    long long nc = (long long)in.g.NR * in.g.NZ;                                               \
+    hipLaunchKernelGGL(k_prime<T>, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, in); \
+    return hipGetLastError();                                                                  \
+  }
+
+}  // namespace salec

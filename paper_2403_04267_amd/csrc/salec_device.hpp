@@ -28,29 +28,61 @@ constexpr double kPcavFrac = 1e-4;      // cavitation pressure ramp (x A)
 // error flags raised by kernels, turned into codes by the finalize kernel
 constexpr unsigned kFlagNonFinite = 1u, kFlagNegMass = 2u;
 
-struct MatC {
-  double rho0, A, B, E0, a, b, alpha, beta, Eiv, Ecv;
-  double p_min, cf2;   // pressure floor, c^2 floor
-  double gfac;         // shear / bulk modulus ratio (0: no strength)
-  double Y0, mu_f, Ylim;
-  double pcav;         // cavitation pressure ramp
+// Material constants in the bulk arithmetic type (double; float copies for
+// the mixed mode).
+template <class T>
+struct MatT {
+  T rho0, A, B, E0, a, b, alpha, beta, Eiv, Ecv;
+  T p_min, cf2;   // pressure floor, c^2 floor
+  T gfac;         // shear / bulk modulus ratio (0: no strength)
+  T Y0, mu_f, Ylim;
+  T pcav;         // cavitation pressure ramp
   int strength, pad;
 };
+using MatC = MatT<double>;
+using MatF = MatT<float>;
 
 struct Geo {
   int NR, NZ, n_r, n_z, pml_r, pml_b, nmat, top_closed;
   int pc, pn;          // row pitch (elements) of cell and node arrays
   int any_strength, pml_on;
-  int nblocks_fused;   // workgroups of the fused cycle kernel
   int same_mat;        // all materials share every constant: evaluate the laws once
+  int prec;            // 0: FP64 throughout; 1: FP32 bulk with FP64 energy, mass and volume sums
   double dr, dz, cfl, dt_grow, dt_max, dt_floor, t_stop, q_lin, q_quad;
   double rho_ref;
+  float drf, dzf, q_linf, q_quadf, rho_reff, pad_f;
   MatC m[kMaxMat];
+  MatF mf[kMaxMat];
 };
 
+template <class T> struct GeoT;
+template <> struct GeoT<double> {
+  static __device__ __forceinline__ const MatC& mat(const Geo& g, int m) { return g.m[m]; }
+  static __device__ __forceinline__ double dr(const Geo& g) { return g.dr; }
+  static __device__ __forceinline__ double dz(const Geo& g) { return g.dz; }
+  static __device__ __forceinline__ double q_lin(const Geo& g) { return g.q_lin; }
+  static __device__ __forceinline__ double q_quad(const Geo& g) { return g.q_quad; }
+  static __device__ __forceinline__ double rho_ref(const Geo& g) { return g.rho_ref; }
+};
+template <> struct GeoT<float> {
+  static __device__ __forceinline__ const MatF& mat(const Geo& g, int m) { return g.mf[m]; }
+  static __device__ __forceinline__ float dr(const Geo& g) { return g.drf; }
+  static __device__ __forceinline__ float dz(const Geo& g) { return g.dzf; }
+  static __device__ __forceinline__ float q_lin(const Geo& g) { return g.q_linf; }
+  static __device__ __forceinline__ float q_quad(const Geo& g) { return g.q_quadf; }
+  static __device__ __forceinline__ float rho_ref(const Geo& g) { return g.rho_reff; }
+};
+
+// EoS results of a state level, written with the state that produced them
+// and read by the next cycle (p, c^2, G, Y, cavitation weight).
+constexpr int kEos = 5;
+
 // One copy of the evolving state (two copies ping-pong by cycle parity).
+// rho, I and f are FP64 in every precision; stress, velocity and the EoS
+// cache hold the bulk type (double, or float in the mixed mode).
 struct State {
-  double *rho, *I, *f[kMaxMat], *s[3], *v[2];
+  double *rho, *I, *f[kMaxMat];
+  void *s[3], *v[2], *eos[kEos];
 };
 
 // Scalars living in device memory so that captured graphs can be replayed.
@@ -59,7 +91,7 @@ struct Scal {
   long long cycle;
   unsigned long long dtmin;  // bit pattern of the running minimum (dt > 0)
   unsigned flags;
-  unsigned done;             // blocks of the current cycle that have finished
+  unsigned done;             // tiles of the current cycle that have finished
   int err, err_cycle;
 };
 
@@ -78,17 +110,21 @@ struct Pml {
   PmlAux a[2];
 };
 
-struct Work {
-  double *sg[4];                          // phi-scaled total stress rr, zz, tt, rz
-  double *p, *Q, *G, *Y, *rmat, *phi, *sx;
-  double *vL[2];                          // Lagrangian node velocity
-  double *J, *IL, *sL[3], *fL[kMaxMat];  // Lagrangian cell state
-  double *lam, *outv;                     // donor outflow limiter
-  double *Fr, *Fz;                        // face mass fluxes (radial: NZ x (NR+1), axial: (NZ+1) x NR)
-  double *heat;                           // node specific heat of the remap
-  double *mout, *eout;                    // per-column outflow budgets
-  double *red;                            // reduction partials
-  double *dtpart;                         // per-block Courant minima of the fused cycle
+// One simulation instance as the cycle kernel sees it (device resident).
+struct Inst {
+  Geo g;
+  State S[2];
+  Pml pm;
+  Scal* sc;
+  double* dtpart;         // per-tile Courant minima
+  double *mout, *eout;    // per-column outflow budgets (mass, internal energy)
+  int tiles_r, tiles_z;   // tile grid of this instance
+  int ntiles, pad;
+};
+
+// One entry of the launch schedule: a tile of an instance.
+struct TileRef {
+  int inst, tile;
 };
 
 __device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : b; }
@@ -143,117 +179,190 @@ __device__ inline double exp_cw(double x) {
   return q * __longlong_as_double((k + 1023) << 52);
 }
 
+// Elementary operations of the bulk type. FP64 keeps IEEE division, square
+// root and the fixed exponential above (reproducible to the bit); the mixed
+// mode's FP32 uses the hardware reciprocal, square root and exponential.
+template <class T> struct Num;
+template <> struct Num<double> {
+  static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+  static __device__ __forceinline__ double sqr(double a) { return sqrt(a); }
+  static __device__ __forceinline__ double ex(double a) { return exp_cw(a); }
+  static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
+};
+template <> struct Num<float> {
+  static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+  static __device__ __forceinline__ float sqr(float a) { return __builtin_sqrtf(a); }
+  static __device__ __forceinline__ float ex(float a) { return __expf(a); }
+  static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
+};
+template <class T> __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+template <class T> __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
+
 // ------------------------------------------------------------------ EoS
-// Four-region Tillotson pressure and squared sound speed at material density
-// rho and specific internal energy e (the EoS sees max(e, 0) and a density
-// floor of 1e-6 rho0).
-__device__ inline void tillotson(const MatC& m, double rho, double e, double& p_out, double& c2_out) {
+// Density terms of the Tillotson law at material density rho (floored at
+// 1e-6 rho0): r, eta = r / rho0, mu = eta - 1, z = 1 / eta - 1. FP32 forms
+// them in FP64 from the FP64 density and rounds once, since mu and z cancel
+// most of their digits in weak waves.
+template <class T>
+struct Dens {
+  T r, eta, mu, z;
+};
+__device__ __forceinline__ Dens<double> dens_terms(const MatC& m, double rho, double*) {
+  Dens<double> d;
+  double rf = m.rho0 * kRhoEosFloor;
+  d.r = rho > rf ? rho : rf;
+  d.eta = d.r / m.rho0;
+  d.mu = d.eta - 1.0;
+  d.z = 1.0 / d.eta - 1.0;
+  return d;
+}
+__device__ __forceinline__ Dens<float> dens_terms(const MatC& m, double rho, float*) {
+  Dens<float> d;
   double rf = m.rho0 * kRhoEosFloor;
   double r = rho > rf ? rho : rf;
-  double E = e > 0.0 ? e : 0.0;
   double eta = r / m.rho0;
-  double mu = eta - 1.0;
-  double w = E / (m.E0 * eta * eta) + 1.0;
-  double pc = (m.a + m.b / w) * r * E + m.A * mu + m.B * mu * mu;
-  double pc_E = r * (m.a + m.b / w - m.b * (w - 1.0) / (w * w));
-  double pc_r = (m.a + m.b / w) * E + 2.0 * m.b * E * (w - 1.0) / (w * w) + (m.A + 2.0 * m.B * mu) / m.rho0;
-  double p, dpdE, dpdr;
+  d.r = (float)r;
+  d.eta = (float)eta;
+  d.mu = (float)((r - m.rho0) / m.rho0);
+  d.z = (float)((m.rho0 - r) / r);
+  return d;
+}
+
+// Four-region Tillotson pressure and squared sound speed at the density
+// terms d and specific internal energy e (the EoS sees max(e, 0)).
+template <class T>
+__device__ inline void tillotson(const MatT<T>& m, const Dens<T>& d, T e, T& p_out, T& c2_out) {
+  using N = Num<T>;
+  const T r = d.r, eta = d.eta, mu = d.mu;
+  T E = e > T(0) ? e : T(0);
+  T w = N::div(E, m.E0 * eta * eta) + T(1);
+  T bw = N::div(m.b, w);
+  T ww = N::div(w - T(1), w * w);
+  T pc = (m.a + bw) * r * E + m.A * mu + m.B * mu * mu;
+  T pc_E = r * (m.a + bw - N::div(m.b * (w - T(1)), w * w));
+  T pc_r = (m.a + bw) * E + N::div(T(2) * m.b * E * (w - T(1)), w * w) + N::div(m.A + T(2) * m.B * mu, m.rho0);
+  T p, dpdE, dpdr;
   if (r >= m.rho0 || E <= m.Eiv) {
     p = pc;
     dpdE = pc_E;
     dpdr = pc_r;
   } else {
-    double z = 1.0 / eta - 1.0;
-    double ea = exp_cw(-m.alpha * z * z);
-    double eb = exp_cw(-m.beta * z);
-    double pe = m.a * r * E + (m.b * r * E / w + m.A * mu * eb) * ea;
-    double pe_E = m.a * r + ea * m.b * r * (1.0 / w - (w - 1.0) / (w * w));
-    double pe_r = m.a * E +
-                  ea * (m.b * E / w + 2.0 * m.b * E * (w - 1.0) / (w * w) + (m.A / m.rho0) * eb +
-                        m.A * mu * m.beta * eb * m.rho0 / (r * r)) +
-                  (m.b * r * E / w + m.A * mu * eb) * ea * 2.0 * m.alpha * z * m.rho0 / (r * r);
+    T z = d.z;
+    T ea = N::ex(-m.alpha * z * z);
+    T eb = N::ex(-m.beta * z);
+    T rr = r * r;
+    T pe = m.a * r * E + (N::div(m.b * r * E, w) + m.A * mu * eb) * ea;
+    T pe_E = m.a * r + ea * m.b * r * (N::div(T(1), w) - ww);
+    T pe_r = m.a * E +
+             ea * (N::div(m.b * E, w) + N::div(T(2) * m.b * E * (w - T(1)), w * w) + N::div(m.A, m.rho0) * eb +
+                   N::div(m.A * mu * m.beta * eb * m.rho0, rr)) +
+             N::div((N::div(m.b * r * E, w) + m.A * mu * eb) * ea * T(2) * m.alpha * z * m.rho0, rr);
     if (E >= m.Ecv) {
       p = pe;
       dpdE = pe_E;
       dpdr = pe_r;
     } else {
-      double x = (E - m.Eiv) / (m.Ecv - m.Eiv);
-      p = x * pe + (1.0 - x) * pc;
-      dpdE = x * pe_E + (1.0 - x) * pc_E + (pe - pc) / (m.Ecv - m.Eiv);
-      dpdr = x * pe_r + (1.0 - x) * pc_r;
+      T x = N::div(E - m.Eiv, m.Ecv - m.Eiv);
+      p = x * pe + (T(1) - x) * pc;
+      dpdE = x * pe_E + (T(1) - x) * pc_E + N::div(pe - pc, m.Ecv - m.Eiv);
+      dpdr = x * pe_r + (T(1) - x) * pc_r;
     }
   }
   p_out = p;
-  c2_out = dpdr + p / (r * r) * dpdE;
+  c2_out = dpdr + N::div(p, r * r) * dpdE;
 }
 
 // intact-rock yield curve (Table 1 parameters)
-__device__ inline double yield_strength(const MatC& m, double p) {
-  if (!m.strength) return 0.0;
-  if (p >= 0.0) {
-    double mp = m.mu_f * p;
-    return m.Y0 + mp / (1.0 + mp / (m.Ylim - m.Y0));
+template <class T>
+__device__ inline T yield_strength(const MatT<T>& m, T p) {
+  if (!m.strength) return T(0);
+  if (p >= T(0)) {
+    T mp = m.mu_f * p;
+    return m.Y0 + Num<T>::div(mp, T(1) + Num<T>::div(mp, m.Ylim - m.Y0));
   }
-  return dmax(0.0, m.Y0 + m.mu_f * p);
+  return tmax(T(0), m.Y0 + m.mu_f * p);
 }
 
 // strength fades linearly between incipient and complete vaporisation
-__device__ inline double softening(const MatC& m, double e) {
-  double E = e > 0.0 ? e : 0.0;
-  return dmin(dmax((m.Ecv - E) / (m.Ecv - m.Eiv), 0.0), 1.0);
+template <class T>
+__device__ inline T softening(const MatT<T>& m, T e) {
+  T E = e > T(0) ? e : T(0);
+  return tmin(tmax(Num<T>::div(m.Ecv - E, m.Ecv - m.Eiv), T(0)), T(1));
 }
 
+template <class T>
 struct Mix {
-  double p, c2, G, Y, rmat, phi, sx;
+  T p, c2, G, Y, rmat, phi, sx;
 };
 
-// Mixed-cell state: all materials share rho_mat = rho / phi and I; p, c^2,
-// G, Y are volume-fraction weighted; sx is the expansion weight of the
-// cavitation rule (1 above the tension floor + ramp).
-__device__ inline Mix mixture(const Geo& g, double rho, double I, const double* f) {
-  Mix o;
-  double phi = 0.0;
+// volume fraction of matter and the shared material density of a mixed cell
+template <class T>
+__device__ __forceinline__ void matter(const Geo& g, T rho, const T* f, T& phi, T& den, T& rm) {
+  phi = T(0);
 #pragma unroll
   for (int m = 0; m < kMaxMat; m++)
     if (m < g.nmat) phi += f[m];
-  double den = phi > kPhiEps ? phi : kPhiEps;
-  double rm = rho / den;
-  double p = 0.0, c2 = 0.0, G = 0.0;
-  double wm[kMaxMat], pmv[kMaxMat], c2v[kMaxMat], sov[kMaxMat];
+  den = phi > T(kPhiEps) ? phi : T(kPhiEps);
+  rm = Num<T>::div(rho, den);
+}
+
+// Mixed-cell state from the FP64 cell state (rho, I, f): all materials
+// share rho_mat = rho / phi and I; p, c^2, G, Y are volume-fraction
+// weighted; sx is the expansion weight of the cavitation rule (1 above the
+// tension floor + ramp). Arithmetic in T (the density terms as above).
+template <class T>
+__device__ inline Mix<T> mixture(const Geo& g, double rho, double I, const double* fd) {
+  using N = Num<T>;
+  Mix<T> o;
+  T f[kMaxMat];
+#pragma unroll
+  for (int m = 0; m < kMaxMat; m++) f[m] = m < g.nmat ? (T)fd[m] : T(0);
+  T phi, den, rm;
+  matter(g, (T)rho, f, phi, den, rm);
+  // material density for the density terms, in FP64
+  double phid = 0.0;
+#pragma unroll
+  for (int m = 0; m < kMaxMat; m++)
+    if (m < g.nmat) phid += fd[m];
+  double rmd = rho / (phid > kPhiEps ? phid : kPhiEps);
+  T Ie = (T)I;
+  T p = T(0), c2 = T(0), G = T(0);
+  T wm[kMaxMat], pmv[kMaxMat], c2v[kMaxMat], sov[kMaxMat];
 #pragma unroll
   for (int m = 0; m < kMaxMat; m++) {
     if (m >= g.nmat) break;
-    const MatC& M = g.m[m];
-    wm[m] = f[m] / den;
+    const MatT<T>& M = GeoT<T>::mat(g, m);
+    wm[m] = N::div(f[m], den);
     if (m > 0 && g.same_mat) {
       // identical constants and inputs give identical results
       pmv[m] = pmv[0];
       c2v[m] = c2v[0];
       sov[m] = sov[0];
     } else {
-      double pm, c2m;
-      tillotson(M, rm, I, pm, c2m);
-      pmv[m] = dmax(pm, M.p_min);
-      c2v[m] = dmax(c2m, M.cf2);
-      sov[m] = softening(M, I);
+      T pm, c2m;
+      Dens<T> dn = dens_terms(g.m[m], rmd, (T*)nullptr);
+      tillotson(M, dn, Ie, pm, c2m);
+      pmv[m] = tmax(pm, M.p_min);
+      c2v[m] = tmax(c2m, M.cf2);
+      sov[m] = softening(M, Ie);
     }
     p += wm[m] * pmv[m];
     c2 += wm[m] * c2v[m];
     G += wm[m] * (sov[m] * (M.gfac * (rm * c2v[m])));
   }
-  double Y = 0.0, pmin = 0.0, ps = 0.0, y0 = 0.0;
+  T Y = T(0), pmin = T(0), ps = T(0), y0 = T(0);
 #pragma unroll
   for (int m = 0; m < kMaxMat; m++) {
     if (m >= g.nmat) break;
-    const MatC& M = g.m[m];
-    double ym = (m > 0 && g.same_mat) ? y0 : yield_strength(M, p);
+    const MatT<T>& M = GeoT<T>::mat(g, m);
+    T ym = (m > 0 && g.same_mat) ? y0 : yield_strength(M, p);
     if (m == 0) y0 = ym;
     Y += wm[m] * (sov[m] * ym);
     pmin += wm[m] * M.p_min;
     ps += wm[m] * M.pcav;
   }
-  double d = p - pmin;
-  o.sx = d >= ps ? 1.0 : (ps > 0.0 ? dmax(d, 0.0) / ps : 0.0);
+  T d = p - pmin;
+  o.sx = d >= ps ? T(1) : (ps > T(0) ? N::div(tmax(d, T(0)), ps) : T(0));
   o.p = p;
   o.c2 = c2;
   o.G = G;
@@ -264,47 +373,106 @@ __device__ inline Mix mixture(const Geo& g, double rho, double I, const double* 
 }
 
 // material volume ratio (void closes first; expansion gated by cavitation)
-__device__ __forceinline__ double material_ratio(double J, double phi, double sx) {
-  if (J < 1.0) return dmin(1.0, J / dmax(phi, kPhiEps));
-  return 1.0 + (J - 1.0) * sx;
+template <class T>
+__device__ __forceinline__ T material_ratio(T J, T phi, T sx) {
+  if (J < T(1)) return tmin(T(1), Num<T>::div(J, tmax(phi, T(kPhiEps))));
+  return T(1) + (J - T(1)) * sx;
 }
 
+// Volume-change terms of a cell whose volume ratio over the step is
+// J = 1 + dD (dD = dt * div v). FP64 forms them from J exactly as the
+// discrete algorithm is written; FP32 forms them from dD, because J - 1 and
+// 1 - ratio would cancel away most of the digits of dD in single precision.
+template <class T> struct Vol;
+template <> struct Vol<double> {
+  static __device__ __forceinline__ double jm1(double J, double) { return J - 1.0; }
+  static __device__ __forceinline__ double ratio(double J, double, double phi, double sx) {
+    return material_ratio(J, phi, sx);
+  }
+  // 1 - ratio, for J < 1
+  static __device__ __forceinline__ double closing(double J, double, double phi, double sx) {
+    return 1.0 - material_ratio(J, phi, sx);
+  }
+};
+template <> struct Vol<float> {
+  static __device__ __forceinline__ float jm1(float, float dD) { return dD; }
+  static __device__ __forceinline__ float ratio(float J, float dD, float phi, float sx) {
+    if (J < 1.0f) return tmin(1.0f, Num<float>::div(J, tmax(phi, (float)kPhiEps)));
+    return 1.0f + dD * sx;
+  }
+  static __device__ __forceinline__ float closing(float, float dD, float phi, float) {
+    float ph = tmax(phi, (float)kPhiEps);
+    return tmax(0.0f, Num<float>::div((ph - 1.0f) - dD, ph));
+  }
+};
+
+// r-weighted areas of the west and east halves of cell column i,
+// 0.5 (r_{i+1/2}^2 - r_i^2) and 0.5 (r_{i+1}^2 - r_{i+1/2}^2) (per radian,
+// per unit height). FP64 evaluates them as written; FP32 uses the exact
+// factored forms dr^2 (2i + 1/2) / 4 and dr^2 (2i + 3/2) / 4, since the
+// difference of squares cancels at large radius. The west and east halves
+// of node i are ring_w(i) and ring_e(i - 1).
+template <class T> struct Ring;
+template <> struct Ring<double> {
+  static __device__ __forceinline__ double w(const Geo& g, int i) {
+    double rw = (double)i * g.dr, rc = ((double)i + 0.5) * g.dr;
+    return 0.5 * (rc * rc - rw * rw);
+  }
+  static __device__ __forceinline__ double e(const Geo& g, int i) {
+    double rc = ((double)i + 0.5) * g.dr, re = (double)(i + 1) * g.dr;
+    return 0.5 * (re * re - rc * rc);
+  }
+};
+template <> struct Ring<float> {
+  static __device__ __forceinline__ float w(const Geo& g, int i) {
+    return (0.25f * g.drf * g.drf) * (2.0f * (float)i + 0.5f);
+  }
+  static __device__ __forceinline__ float e(const Geo& g, int i) {
+    return (0.25f * g.drf * g.drf) * (2.0f * (float)i + 1.5f);
+  }
+};
+
 // ------------------------------------------------------------------ kinematics
+template <class T>
 struct Kin {
-  double ur_w, ur_e, Ur_w, Ur_e, Uz_s, Uz_n;
-  double D, Dr, Dz, err, ezz, ett, erz, om, dvr_dz, dvz_dr;
+  T D, Dr, Dz, err, ezz, ett, erz, om, dvr_dz, dvz_dr;
 };
 
 // Face-mean velocities and rates of cell column i from the corner velocities
 // (SW, SE, NW, NE). Axial faces weight their nodes by the r-weighted areas of
 // the node dual cells, so the node force is the exact volume gradient.
-__device__ inline Kin kinematics(const Geo& g, int i, const double vr[4], const double vz[4]) {
-  Kin k;
-  double rw = (double)i * g.dr, re = (double)(i + 1) * g.dr;
-  double rc = ((double)i + 0.5) * g.dr;
-  double Arw = rw * g.dz, Are = re * g.dz, Az = rc * g.dr, V = Az * g.dz;
-  double aw = 0.5 * (rc * rc - rw * rw), ae = 0.5 * (re * re - rc * rc);
-  k.ur_w = 0.5 * (vr[0] + vr[2]);
-  k.ur_e = 0.5 * (vr[1] + vr[3]);
-  k.Ur_w = Arw * k.ur_w;
-  k.Ur_e = Are * k.ur_e;
-  k.Uz_s = aw * vz[0] + ae * vz[1];
-  k.Uz_n = aw * vz[2] + ae * vz[3];
-  k.Dr = (k.Ur_e - k.Ur_w) / V;
-  k.Dz = (k.Uz_n - k.Uz_s) / V;
-  k.D = ((k.Ur_e - k.Ur_w) + (k.Uz_n - k.Uz_s)) / V;
-  k.err = (k.ur_e - k.ur_w) / g.dr;
-  k.ezz = (k.Uz_n - k.Uz_s) / V;
-  k.ett = (0.5 * (k.ur_w + k.ur_e)) / rc;
-  k.dvr_dz = ((aw * vr[2] + ae * vr[3]) - (aw * vr[0] + ae * vr[1])) / V;
-  k.dvz_dr = (0.5 * (vz[1] + vz[3]) - 0.5 * (vz[0] + vz[2])) / g.dr;
-  k.erz = 0.5 * (k.dvr_dz + k.dvz_dr);
-  k.om = 0.5 * (k.dvr_dz - k.dvz_dr);
+template <class T>
+__device__ inline Kin<T> kinematics(const Geo& g, int i, const T vr[4], const T vz[4]) {
+  using N = Num<T>;
+  Kin<T> k;
+  const T dr = GeoT<T>::dr(g), dz = GeoT<T>::dz(g);
+  T rw = (T)i * dr, re = (T)(i + 1) * dr;
+  T rc = ((T)i + T(0.5)) * dr;
+  T Arw = rw * dz, Are = re * dz, Az = rc * dr, V = Az * dz;
+  T aw = Ring<T>::w(g, i), ae = Ring<T>::e(g, i);
+  T ur_w = T(0.5) * (vr[0] + vr[2]);
+  T ur_e = T(0.5) * (vr[1] + vr[3]);
+  T Ur_w = Arw * ur_w;
+  T Ur_e = Are * ur_e;
+  T Uz_s = aw * vz[0] + ae * vz[1];
+  T Uz_n = aw * vz[2] + ae * vz[3];
+  k.Dr = N::div(Ur_e - Ur_w, V);
+  k.Dz = N::div(Uz_n - Uz_s, V);
+  k.D = N::div((Ur_e - Ur_w) + (Uz_n - Uz_s), V);
+  k.err = N::div(ur_e - ur_w, dr);
+  k.ezz = k.Dz;
+  k.ett = N::div(T(0.5) * (ur_w + ur_e), rc);
+  k.dvr_dz = N::div((aw * vr[2] + ae * vr[3]) - (aw * vr[0] + ae * vr[1]), V);
+  k.dvz_dr = N::div(T(0.5) * (vz[1] + vz[3]) - T(0.5) * (vz[0] + vz[2]), dr);
+  k.erz = T(0.5) * (k.dvr_dz + k.dvz_dr);
+  k.om = T(0.5) * (k.dvr_dz - k.dvz_dr);
   return k;
 }
 
-__device__ __forceinline__ double cell_volume(const Geo& g, int i) {
-  return (((double)i + 0.5) * g.dr * g.dr) * g.dz;
+template <class T>
+__device__ __forceinline__ T cell_volume(const Geo& g, int i) {
+  const T dr = GeoT<T>::dr(g);
+  return (((T)i + T(0.5)) * dr * dr) * GeoT<T>::dz(g);
 }
 
 }  // namespace salec

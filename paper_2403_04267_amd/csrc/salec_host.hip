@@ -1,8 +1,10 @@
 // salec_host.hip -- host runtime of libsalec: validation, layout of the
-// caller's device buffer, scene set-up, HIP-graph capture and replay of the
-// cycle, field I/O, checkpoints and diagnostics. Implements include/salec.h.
+// caller's device buffer for one impact or an ensemble, scene set-up, launch
+// schedules and their tuner, HIP-graph capture and replay of the cycle, field
+// I/O, checkpoints and diagnostics. Implements include/salec.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -18,8 +20,9 @@ using namespace salec;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kGraphCycles = 16;  // cycles per captured graph
-constexpr uint64_t kStateMagic = 0x53414c4543535431ull;  // "SALECST1"
+constexpr int kGraphCycles = 16;                         // cycles per captured graph
+constexpr uint64_t kStateMagic = 0x53414c4543535432ull;  // "SALECST2"
+constexpr int kXcds = 8;                                 // L2 domains the schedule groups tiles by
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -28,51 +31,63 @@ struct Carver {
   uint8_t* base;
   size_t off = 0;
   explicit Carver(void* b) : base((uint8_t*)b) {}
-  double* d(size_t n) {
+  void* bytes(size_t n) {
     size_t o = off;
-    off = align_up(off + n * sizeof(double));
-    return base ? (double*)(base + o) : nullptr;
+    off = align_up(off + n);
+    return base ? (void*)(base + o) : nullptr;
   }
+  double* d(size_t n) { return (double*)bytes(n * sizeof(double)); }
   template <class T>
-  T* obj() {
-    size_t o = off;
-    off = align_up(off + sizeof(T));
-    return base ? (T*)(base + o) : nullptr;
+  T* obj(size_t n = 1) {
+    return (T*)bytes(n * sizeof(T));
   }
 };
 
-struct Layout {
-  Scal* sc = nullptr;
-  State S[2];
-  Pml pm{};
-  Work w{};
-  double* diag_out = nullptr;
-  size_t aux_off = 0;        // [aux_off, persist_bytes): PML auxiliaries and budgets
-  size_t persist_bytes = 0;  // [0, persist_bytes): checkpointed region
-  size_t total = 0;
+// Host view of one member: its constants, its device descriptor and the
+// byte range of its persistent (checkpointed) state.
+struct Member {
+  Geo g{};
+  Inst d{};
   long long n_pml = 0;
+  size_t aux_off = 0, aux_end = 0;  // PML auxiliaries and budgets (cleared at a run start)
+  std::vector<double> dcz, dnz, dcr, dnr;
+  salec_scene scene{};
+  bool has_scene = false;
 };
 
-void carve(const Geo& g, void* base, Layout& L) {
-  Carver cv(base);
+int tiles_of(const Geo& g, int v, int* tr, int* tz) {
+  int tw, th, nt;
+  variant_shape(v, &tw, &th, &nt);
+  *tr = (g.NR + tw - 1) / tw;
+  *tz = (g.NZ + th - 1) / th;
+  return *tr * *tz;
+}
+
+// Persistent state of one member: scalars, both state levels (with their
+// EoS caches), PML auxiliaries of both levels, reference density, sink and
+// outflow budgets.
+void carve_persistent(Member& mb, Carver& cv) {
+  const Geo& g = mb.g;
+  size_t es = g.prec ? sizeof(float) : sizeof(double);
   long long nc = (long long)g.NZ * g.pc, nn = (long long)(g.NZ + 1) * g.pn;
-  // persistent region: scalars, both state copies, PML auxiliaries, budgets
-  L.sc = cv.obj<Scal>();
+  Inst& d = mb.d;
+  d.sc = cv.obj<Scal>();
   for (int b = 0; b < 2; b++) {
-    State& S = L.S[b];
+    State& S = d.S[b];
     S.rho = cv.d(nc);
     S.I = cv.d(nc);
     for (int m = 0; m < kMaxMat; m++) S.f[m] = m < g.nmat ? cv.d(nc) : nullptr;
-    for (int k = 0; k < 3; k++) S.s[k] = g.any_strength ? cv.d(nc) : nullptr;
-    S.v[0] = cv.d(nn);
-    S.v[1] = cv.d(nn);
+    for (int k = 0; k < 3; k++) S.s[k] = g.any_strength ? cv.bytes(nc * es) : nullptr;
+    S.v[0] = cv.bytes(nn * es);
+    S.v[1] = cv.bytes(nn * es);
+    for (int k = 0; k < kEos; k++) S.eos[k] = cv.bytes(nc * es);
   }
-  L.aux_off = cv.off;
+  mb.aux_off = cv.off;
   long long nbc = (long long)g.pml_b * g.NR, nrc = (long long)g.NZ * g.pml_r;
   long long nbn = (long long)g.pml_b * (g.NR + 1), nrn = (long long)(g.NZ + 1) * g.pml_r;
   long long nu = nbc + (long long)g.n_z * g.pml_r;
-  L.n_pml = g.pml_on ? nu : 0;
-  Pml& pm = L.pm;
+  mb.n_pml = g.pml_on ? nu : 0;
+  Pml& pm = d.pm;
   auto opt = [&](long long n) { return (g.pml_on && n > 0) ? cv.d((size_t)n) : nullptr; };
   pm.rref = opt(nu);
   pm.msink = opt(nu);
@@ -93,37 +108,66 @@ void carve(const Geo& g, void* base, Layout& L) {
     a.r_psi1r = opt(nrn);
     a.r_psi1z = opt(nrn);
   }
-  L.w.mout = cv.d(g.pc);
-  L.w.eout = cv.d(g.pc);
-  L.persist_bytes = cv.off;
-  // constants
+  d.mout = cv.d(g.pc);
+  d.eout = cv.d(g.pc);
+  mb.aux_end = cv.off;
+}
+
+// Constants and per-cycle scratch of one member.
+void carve_constants(Member& mb, Carver& cv) {
+  const Geo& g = mb.g;
+  Pml& pm = mb.d.pm;
   pm.dcz = cv.d(g.NZ);
   pm.dnz = cv.d(g.NZ + 1);
   pm.dcr = cv.d(g.NR);
   pm.dnr = cv.d(g.NR + 1);
-  // per-cycle scratch
-  Work& w = L.w;
-  for (int k = 0; k < 4; k++) w.sg[k] = cv.d(nc);
-  w.p = cv.d(nc);
-  w.Q = cv.d(nc);
-  w.G = cv.d(nc);
-  w.Y = cv.d(nc);
-  w.rmat = cv.d(nc);
-  w.phi = cv.d(nc);
-  w.sx = cv.d(nc);
-  w.vL[0] = cv.d(nn);
-  w.vL[1] = cv.d(nn);
-  w.J = cv.d(nc);
-  w.IL = cv.d(nc);
-  for (int k = 0; k < 3; k++) w.sL[k] = cv.d(nc);
-  for (int m = 0; m < kMaxMat; m++) w.fL[m] = m < g.nmat ? cv.d(nc) : nullptr;
-  w.lam = cv.d(nc);
-  w.outv = cv.d(nc);
-  w.Fr = cv.d((size_t)g.NZ * g.pn);
-  w.Fz = cv.d((size_t)(g.NZ + 1) * g.pc);
-  w.heat = cv.d(nn);
-  w.red = cv.d((size_t)kDiagBlocks * 12);
-  w.dtpart = cv.d((size_t)g.nblocks_fused + 1);
+  int most = 0;
+  for (int v = 0; v < n_variants(); v++) {
+    int tr, tz;
+    most = std::max(most, tiles_of(g, v, &tr, &tz));
+  }
+  mb.d.dtpart = cv.d((size_t)most);
+}
+
+// Entries of the largest schedule over all tile shapes.
+size_t schedule_capacity(const std::vector<Member>& ms) {
+  size_t cap = 0;
+  for (int v = 0; v < n_variants(); v++) {
+    size_t t = 0;
+    for (const Member& mb : ms) {
+      int tr, tz;
+      t += (size_t)tiles_of(mb.g, v, &tr, &tz);
+    }
+    cap = std::max(cap, (t + kXcds - 1) / kXcds * kXcds);
+  }
+  return cap;
+}
+
+struct Layout {
+  size_t persist_bytes = 0, total = 0;
+  Inst* d_inst = nullptr;
+  TileRef* d_sched = nullptr;
+  size_t sched_cap = 0;
+  double *scratch = nullptr, *red = nullptr, *diag_out = nullptr;
+};
+
+// Buffer layout: every member's persistent state first (one contiguous,
+// checkpointable block), then descriptors, the schedule, constants and the
+// shared scratch.
+void carve_all(std::vector<Member>& ms, void* base, Layout& L) {
+  Carver cv(base);
+  for (Member& mb : ms) carve_persistent(mb, cv);
+  L.persist_bytes = cv.off;
+  L.d_inst = cv.obj<Inst>(ms.size());
+  L.sched_cap = schedule_capacity(ms);
+  L.d_sched = cv.obj<TileRef>(L.sched_cap);
+  size_t most = 0;
+  for (Member& mb : ms) {
+    carve_constants(mb, cv);
+    most = std::max(most, (size_t)mb.g.NZ * mb.g.pc);
+  }
+  L.scratch = cv.d(2 * most);
+  L.red = cv.d((size_t)kDiagBlocks * kDiagQ * 2);
   L.diag_out = cv.d(8);
   L.total = cv.off;
 }
@@ -132,9 +176,9 @@ int validate(const salec_grid* g, const salec_material* mats, const salec_pml* p
   if (!g || !mats || !pml) return why = "null argument", SALEC_E_INVALID;
   if (g->n_r < 1 || g->n_z < 1 || g->pml_r < 0 || g->pml_b < 0) return why = "grid sizes", SALEC_E_INVALID;
   if ((long long)(g->n_r + g->pml_r + 1) * (g->n_z + g->pml_b + 1) > (1ll << 31))
-    return why = "grid too large for one context", SALEC_E_INVALID;
+    return why = "grid too large for one instance", SALEC_E_INVALID;
   if (g->nmat < 1 || g->nmat > SALEC_MAX_MAT) return why = "nmat must be 1 or 2", SALEC_E_INVALID;
-  if (g->precision != SALEC_FP64) return why = "only SALEC_FP64 is implemented", SALEC_E_INVALID;
+  if (g->precision != SALEC_FP64 && g->precision != SALEC_MIXED) return why = "precision", SALEC_E_INVALID;
   if (!(g->dr > 0) || !(g->dz > 0)) return why = "cell size must be > 0", SALEC_E_INVALID;
   if (!(g->cfl > 0) || g->cfl > 1.0) return why = "cfl must be in (0, 1]", SALEC_E_INVALID;
   if (!(g->dt_grow >= 1.0) || !(g->dt_max > 0) || g->dt_floor < 0 || g->q_lin < 0 || g->q_quad < 0)
@@ -150,8 +194,30 @@ int validate(const salec_grid* g, const salec_material* mats, const salec_pml* p
   return SALEC_OK;
 }
 
+template <class T>
+void fill_mat(MatT<T>& c, const salec_material& M) {
+  c.rho0 = (T)M.rho0;
+  c.A = (T)M.A;
+  c.B = (T)M.B;
+  c.E0 = (T)M.E0;
+  c.a = (T)M.a;
+  c.b = (T)M.b;
+  c.alpha = (T)M.alpha;
+  c.beta = (T)M.beta;
+  c.Eiv = (T)M.Eiv;
+  c.Ecv = (T)M.Ecv;
+  c.p_min = (T)M.p_min;
+  c.cf2 = (T)(M.c_floor_frac * M.A / M.rho0);
+  c.strength = M.strength ? 1 : 0;
+  c.gfac = (T)(M.strength ? 3.0 * (1.0 - 2.0 * M.poisson) / (2.0 * (1.0 + M.poisson)) : 0.0);
+  c.Y0 = (T)M.Y0;
+  c.mu_f = (T)M.mu_f;
+  c.Ylim = (T)M.Ylim;
+  c.pcav = (T)(kPcavFrac * M.A);
+}
+
 Geo make_geo(const salec_grid* gr, const salec_material* mats, const salec_pml* pml) {
-  Geo g{};
+  Geo g;
   std::memset(&g, 0, sizeof(g));
   g.n_r = gr->n_r;
   g.n_z = gr->n_z;
@@ -161,14 +227,12 @@ Geo make_geo(const salec_grid* gr, const salec_material* mats, const salec_pml* 
   g.NZ = gr->n_z + gr->pml_b;
   g.nmat = gr->nmat;
   g.top_closed = gr->top_closed;
-  g.pc = (int)((g.NR + 31) / 32 * 32);
-  g.pn = (int)((g.NR + 1 + 31) / 32 * 32);
+  g.prec = gr->precision == SALEC_MIXED ? 1 : 0;
+  // row pitch: 64 elements for FP32 rows, 32 for FP64 (256 bytes either way)
+  int q = g.prec ? 64 : 32;
+  g.pc = (g.NR + q - 1) / q * q;
+  g.pn = (g.NR + 1 + q - 1) / q * q;
   g.pml_on = pml->enabled ? 1 : 0;
-  {
-    int tr, tz;
-    fused_tiles(g.NR, g.NZ, &tr, &tz);
-    g.nblocks_fused = tr * tz;
-  }
   g.dr = gr->dr;
   g.dz = gr->dz;
   g.cfl = gr->cfl;
@@ -180,29 +244,16 @@ Geo make_geo(const salec_grid* gr, const salec_material* mats, const salec_pml* 
   g.q_quad = gr->q_quad;
   g.rho_ref = 0.0;
   for (int m = 0; m < gr->nmat; m++) {
-    const salec_material& M = mats[m];
-    MatC& c = g.m[m];
-    c.rho0 = M.rho0;
-    c.A = M.A;
-    c.B = M.B;
-    c.E0 = M.E0;
-    c.a = M.a;
-    c.b = M.b;
-    c.alpha = M.alpha;
-    c.beta = M.beta;
-    c.Eiv = M.Eiv;
-    c.Ecv = M.Ecv;
-    c.p_min = M.p_min;
-    c.cf2 = M.c_floor_frac * M.A / M.rho0;
-    c.strength = M.strength ? 1 : 0;
-    c.gfac = M.strength ? 3.0 * (1.0 - 2.0 * M.poisson) / (2.0 * (1.0 + M.poisson)) : 0.0;
-    c.Y0 = M.Y0;
-    c.mu_f = M.mu_f;
-    c.Ylim = M.Ylim;
-    c.pcav = kPcavFrac * M.A;
-    if (M.strength) g.any_strength = 1;
-    if (M.rho0 > g.rho_ref) g.rho_ref = M.rho0;
+    fill_mat(g.m[m], mats[m]);
+    fill_mat(g.mf[m], mats[m]);
+    if (mats[m].strength) g.any_strength = 1;
+    if (mats[m].rho0 > g.rho_ref) g.rho_ref = mats[m].rho0;
   }
+  g.drf = (float)g.dr;
+  g.dzf = (float)g.dz;
+  g.q_linf = (float)g.q_lin;
+  g.q_quadf = (float)g.q_quad;
+  g.rho_reff = (float)g.rho_ref;
   g.same_mat = 1;
   for (int m = 1; m < gr->nmat; m++)
     if (std::memcmp(&g.m[m], &g.m[0], sizeof(MatC)) != 0) g.same_mat = 0;
@@ -212,12 +263,12 @@ Geo make_geo(const salec_grid* gr, const salec_material* mats, const salec_pml* 
 // damping profile d(y) = (3c / 2 delta) (y / delta)^2 log(1/R)  (Sec. 3)
 double pml_d(double c, double delta, double y, double R) { return 1.5 * c / delta * (y / delta) * (y / delta) * std::log(1.0 / R); }
 
-void pml_profiles(const Geo& g, const salec_material* mats, const salec_pml* pml, std::vector<double>& dcz,
-                  std::vector<double>& dnz, std::vector<double>& dcr, std::vector<double>& dnr) {
-  dcz.assign(g.NZ, 0.0);
-  dnz.assign(g.NZ + 1, 0.0);
-  dcr.assign(g.NR, 0.0);
-  dnr.assign(g.NR + 1, 0.0);
+void pml_profiles(Member& mb, const salec_material* mats, const salec_pml* pml) {
+  const Geo& g = mb.g;
+  mb.dcz.assign(g.NZ, 0.0);
+  mb.dnz.assign(g.NZ + 1, 0.0);
+  mb.dcr.assign(g.NR, 0.0);
+  mb.dnr.assign(g.NR + 1, 0.0);
   if (!pml->enabled) return;
   double c = pml->c_ref;
   if (!(c > 0)) {
@@ -227,28 +278,50 @@ void pml_profiles(const Geo& g, const salec_material* mats, const salec_pml* pml
   }
   if (g.pml_b > 0) {
     double delta = g.pml_b * g.dz;
-    for (int j = 0; j < g.pml_b; j++) dcz[j] = pml_d(c, delta, ((double)(g.pml_b - j) - 0.5) * g.dz, pml->R);
-    for (int j = 0; j < g.pml_b; j++) dnz[j] = pml_d(c, delta, (double)(g.pml_b - j) * g.dz, pml->R);
+    for (int j = 0; j < g.pml_b; j++) mb.dcz[j] = pml_d(c, delta, ((double)(g.pml_b - j) - 0.5) * g.dz, pml->R);
+    for (int j = 0; j < g.pml_b; j++) mb.dnz[j] = pml_d(c, delta, (double)(g.pml_b - j) * g.dz, pml->R);
   }
   if (g.pml_r > 0) {
     double delta = g.pml_r * g.dr;
-    for (int i = g.n_r; i < g.NR; i++) dcr[i] = pml_d(c, delta, ((double)(i - g.n_r) + 0.5) * g.dr, pml->R);
-    for (int i = g.n_r + 1; i <= g.NR; i++) dnr[i] = pml_d(c, delta, (double)(i - g.n_r) * g.dr, pml->R);
+    for (int i = g.n_r; i < g.NR; i++) mb.dcr[i] = pml_d(c, delta, ((double)(i - g.n_r) + 0.5) * g.dr, pml->R);
+    for (int i = g.n_r + 1; i <= g.NR; i++) mb.dnr[i] = pml_d(c, delta, (double)(i - g.n_r) * g.dr, pml->R);
   }
+}
+
+int check_members(const salec_instance* inst, int32_t n, std::vector<Member>& ms, std::string& why) {
+  if (!inst || n < 1) return why = "no instances", SALEC_E_INVALID;
+  ms.assign((size_t)n, Member{});
+  for (int32_t k = 0; k < n; k++) {
+    const salec_instance& I = inst[k];
+    int rc = validate(&I.grid, I.mats, &I.pml, why);
+    if (rc) return why = "instance " + std::to_string(k) + ": " + why, rc;
+    if (I.grid.precision != inst[0].grid.precision)
+      return why = "every instance of a context must use the same precision", SALEC_E_INVALID;
+    if (I.has_scene && (I.scene.subsample < 1 || !(I.scene.radius > 0)))
+      return why = "instance " + std::to_string(k) + ": scene parameters", SALEC_E_INVALID;
+    ms[k].g = make_geo(&I.grid, I.mats, &I.pml);
+    ms[k].d.g = ms[k].g;
+    ms[k].has_scene = I.has_scene != 0;
+    ms[k].scene = I.scene;
+  }
+  return SALEC_OK;
 }
 
 }  // namespace
 
 struct salec_ctx {
-  Geo g{};
+  std::vector<Member> ms;
   Layout L;
+  int prec = 0;
   void* buf = nullptr;
   hipStream_t st = nullptr;
   bool own_stream = false;
   hipGraphExec_t gx1 = nullptr, gxN = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_ms = 0.0;
-  bool phased = false;  // one kernel per phase instead of the fused cycle
+  int variant = 0, grid = 0, nsched = 0;
+  double tuned_ms = 0.0;
+  bool ready = false;
   std::string err;
 };
 
@@ -264,30 +337,65 @@ int hip_fail(salec_ctx* x, hipError_t e, const char* where) {
     if (e_ != hipSuccess) return hip_fail((x), e_, #call); \
   } while (0)
 
-// Clears PML auxiliaries and budgets, sets the PML reference density and the
-// clock, and computes the first time step; the state is in copy 0.
-int start_run(salec_ctx* x) {
-  Layout& L = x->L;
-  uint8_t* base = (uint8_t*)L.sc;
-  if (L.persist_bytes > L.aux_off)
-    HIPCHK(x, hipMemsetAsync(base + L.aux_off, 0, L.persist_bytes - L.aux_off, x->st));
-  launch_start_run(x->g, L.S[0], L.pm, L.sc, x->st);
-  launch_dt0(x->g, L.S[0], L.S[1], L.sc, x->st);
-  HIPCHK(x, hipGetLastError());
+// Clears member k's PML auxiliaries and budgets, sets its PML reference
+// density and clock, and computes the EoS cache and first time step of its
+// state (level 0).
+int start_run(salec_ctx* x, int k) {
+  Member& mb = x->ms[k];
+  uint8_t* base = (uint8_t*)x->buf;
+  if (mb.aux_end > mb.aux_off) HIPCHK(x, hipMemsetAsync(base + mb.aux_off, 0, mb.aux_end - mb.aux_off, x->st));
+  HIPCHK(x, launch_start_run(mb.d, x->st));
+  HIPCHK(x, launch_prime(mb.d, x->st));
+  HIPCHK(x, launch_finalize0(mb.d, x->st));
   HIPCHK(x, hipStreamSynchronize(x->st));
+  return SALEC_OK;
+}
+
+// Tile list of every member for tile shape v, grouped into kXcds contiguous
+// chunks: entry e goes to chunk e % kXcds, so the workgroups one L2 domain
+// runs work on neighbouring tiles.
+int build_schedule(salec_ctx* x, int v) {
+  std::vector<TileRef> list;
+  for (size_t k = 0; k < x->ms.size(); k++) {
+    Member& mb = x->ms[k];
+    int tr, tz;
+    int nt = tiles_of(mb.g, v, &tr, &tz);
+    mb.d.tiles_r = tr;
+    mb.d.tiles_z = tz;
+    mb.d.ntiles = nt;
+    for (int t = 0; t < nt; t++) list.push_back(TileRef{(int)k, t});
+  }
+  size_t T = list.size(), per = (T + kXcds - 1) / kXcds;
+  std::vector<TileRef> sched(per * kXcds);
+  for (size_t e = 0; e < sched.size(); e++) {
+    size_t idx = (e % kXcds) * per + e / kXcds;
+    sched[e] = idx < T ? list[idx] : TileRef{-1, 0};
+  }
+  if (sched.size() > x->L.sched_cap) {
+    x->err = "schedule larger than its reserved space";
+    return SALEC_E_INVALID;
+  }
+  std::vector<Inst> di(x->ms.size());
+  for (size_t k = 0; k < x->ms.size(); k++) di[k] = x->ms[k].d;
+  HIPCHK(x, hipMemcpyAsync(x->L.d_inst, di.data(), di.size() * sizeof(Inst), hipMemcpyHostToDevice, x->st));
+  HIPCHK(x, hipMemcpyAsync(x->L.d_sched, sched.data(), sched.size() * sizeof(TileRef), hipMemcpyHostToDevice, x->st));
+  HIPCHK(x, hipStreamSynchronize(x->st));
+  x->nsched = (int)sched.size();
   return SALEC_OK;
 }
 
 int capture(salec_ctx* x, int ncyc, hipGraphExec_t* out) {
   hipGraph_t gr = nullptr;
+  int grid = x->grid > 0 ? std::min(x->grid, x->nsched) : x->nsched;
   HIPCHK(x, hipStreamBeginCapture(x->st, hipStreamCaptureModeThreadLocal));
-  for (int k = 0; k < ncyc; k++) {
-    if (x->phased)
-      launch_cycle(x->g, x->L.S[0], x->L.S[1], x->L.w, x->L.pm, x->L.sc, x->st);
-    else
-      launch_cycle_fused(x->g, x->L.S[0], x->L.S[1], x->L.w, x->L.pm, x->L.sc, x->st);
-  }
+  hipError_t le = hipSuccess;
+  for (int k = 0; k < ncyc && le == hipSuccess; k++)
+    le = launch_cycle(x->variant, x->prec, x->L.d_inst, x->L.d_sched, x->nsched, grid, x->st);
   hipError_t e = hipStreamEndCapture(x->st, &gr);
+  if (le != hipSuccess) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return hip_fail(x, le, "launch_cycle");
+  }
   if (e != hipSuccess) return hip_fail(x, e, "hipStreamEndCapture");
   e = hipGraphInstantiate(out, gr, nullptr, nullptr, 0);
   (void)hipGraphDestroy(gr);
@@ -295,118 +403,162 @@ int capture(salec_ctx* x, int ncyc, hipGraphExec_t* out) {
   return SALEC_OK;
 }
 
-Scal read_scal(salec_ctx* x) {
+// Selects a schedule: uploads descriptors and tile list, recaptures graphs.
+int use_schedule(salec_ctx* x, int v, int grid) {
+  if (v < 0 || v >= n_variants() || grid < 0) {
+    x->err = "schedule out of range";
+    return SALEC_E_INVALID;
+  }
+  HIPCHK(x, hipStreamSynchronize(x->st));
+  if (x->gx1) (void)hipGraphExecDestroy(x->gx1);
+  if (x->gxN) (void)hipGraphExecDestroy(x->gxN);
+  x->gx1 = x->gxN = nullptr;
+  x->variant = v;
+  x->grid = grid > 0 ? (grid + kXcds - 1) / kXcds * kXcds : 0;
+  int rc = build_schedule(x, v);
+  if (rc) return rc;
+  rc = capture(x, 1, &x->gx1);
+  if (rc) return rc;
+  return capture(x, kGraphCycles, &x->gxN);
+}
+
+Scal read_scal(salec_ctx* x, int k) {
   Scal s{};
-  (void)hipMemcpyAsync(&s, x->L.sc, sizeof(Scal), hipMemcpyDeviceToHost, x->st);
+  (void)hipMemcpyAsync(&s, x->ms[k].d.sc, sizeof(Scal), hipMemcpyDeviceToHost, x->st);
   (void)hipStreamSynchronize(x->st);
   return s;
 }
 
-const State& current(salec_ctx* x, const Scal& s) { return (s.cycle & 1) ? x->L.S[1] : x->L.S[0]; }
+size_t elem_size(const salec_ctx* x) { return x->prec ? sizeof(float) : sizeof(double); }
 
-int copy_cells_out(salec_ctx* x, double* host, const double* dev) {
-  const Geo& g = x->g;
-  HIPCHK(x, hipMemcpy2DAsync(host, g.NR * sizeof(double), dev, g.pc * sizeof(double), g.NR * sizeof(double), g.NZ,
-                             hipMemcpyDeviceToHost, x->st));
+// 2D copies between packed host FP64 arrays and pitched device arrays of
+// element size es (FP32 device arrays are converted on the host).
+int copy_out(salec_ctx* x, double* host, const void* dev, int w, int h, int pitch, size_t es) {
+  if (es == sizeof(double)) {
+    HIPCHK(x, hipMemcpy2DAsync(host, w * sizeof(double), dev, pitch * es, w * es, h, hipMemcpyDeviceToHost, x->st));
+    return SALEC_OK;
+  }
+  std::vector<float> tmp((size_t)w * h);
+  HIPCHK(x, hipMemcpy2DAsync(tmp.data(), w * es, dev, pitch * es, w * es, h, hipMemcpyDeviceToHost, x->st));
+  HIPCHK(x, hipStreamSynchronize(x->st));
+  for (size_t t = 0; t < tmp.size(); t++) host[t] = (double)tmp[t];
   return SALEC_OK;
 }
-int copy_nodes_out(salec_ctx* x, double* host, const double* dev) {
-  const Geo& g = x->g;
-  HIPCHK(x, hipMemcpy2DAsync(host, (g.NR + 1) * sizeof(double), dev, g.pn * sizeof(double),
-                             (g.NR + 1) * sizeof(double), g.NZ + 1, hipMemcpyDeviceToHost, x->st));
+int copy_in(salec_ctx* x, void* dev, const double* host, int w, int h, int pitch, size_t es) {
+  if (es == sizeof(double)) {
+    HIPCHK(x, hipMemcpy2DAsync(dev, pitch * es, host, w * sizeof(double), w * es, h, hipMemcpyHostToDevice, x->st));
+    HIPCHK(x, hipStreamSynchronize(x->st));
+    return SALEC_OK;
+  }
+  std::vector<float> tmp((size_t)w * h);
+  for (size_t t = 0; t < tmp.size(); t++) tmp[t] = (float)host[t];
+  HIPCHK(x, hipMemcpy2DAsync(dev, pitch * es, tmp.data(), w * es, w * es, h, hipMemcpyHostToDevice, x->st));
+  HIPCHK(x, hipStreamSynchronize(x->st));
   return SALEC_OK;
 }
-int copy_cells_in(salec_ctx* x, double* dev, const double* host) {
-  const Geo& g = x->g;
-  HIPCHK(x, hipMemcpy2DAsync(dev, g.pc * sizeof(double), host, g.NR * sizeof(double), g.NR * sizeof(double), g.NZ,
-                             hipMemcpyHostToDevice, x->st));
+
+int init_common(salec_ctx* x, void* dev_buf, size_t dev_bytes, void* stream) {
+  Layout probe;
+  carve_all(x->ms, nullptr, probe);
+  if (!dev_buf || dev_bytes < probe.total || ((uintptr_t)dev_buf % kAlign) != 0) {
+    x->err = "device buffer smaller than the plan or not 256-byte aligned";
+    return SALEC_E_BUFFER;
+  }
+  x->buf = dev_buf;
+  x->prec = x->ms[0].g.prec;
+  carve_all(x->ms, dev_buf, x->L);
+  if (stream) {
+    x->st = (hipStream_t)stream;
+  } else {
+    HIPCHK(x, hipStreamCreate(&x->st));
+    x->own_stream = true;
+  }
+  HIPCHK(x, hipEventCreate(&x->ev0));
+  HIPCHK(x, hipEventCreate(&x->ev1));
+  HIPCHK(x, hipMemsetAsync(dev_buf, 0, x->L.total, x->st));
+  for (size_t k = 0; k < x->ms.size(); k++) {
+    Member& mb = x->ms[k];
+    mb.d.g = mb.g;
+    HIPCHK(x, hipMemcpyAsync((void*)mb.d.pm.dcz, mb.dcz.data(), mb.dcz.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
+    HIPCHK(x, hipMemcpyAsync((void*)mb.d.pm.dnz, mb.dnz.data(), mb.dnz.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
+    HIPCHK(x, hipMemcpyAsync((void*)mb.d.pm.dcr, mb.dcr.data(), mb.dcr.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
+    HIPCHK(x, hipMemcpyAsync((void*)mb.d.pm.dnr, mb.dnr.data(), mb.dnr.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
+    if (mb.has_scene) {
+      const salec_scene& sc = mb.scene;
+      double zc = (double)sc.surface_j * mb.g.dz + sc.radius;
+      HIPCHK(x, launch_scene(mb.d, sc.surface_j, sc.subsample, sc.radius, zc, sc.v_imp, x->L.scratch, x->st));
+    }
+    HIPCHK(x, hipStreamSynchronize(x->st));  // the profile vectors are reused below
+    int rc = start_run(x, (int)k);
+    if (rc) return rc;
+  }
+  int rc = use_schedule(x, 0, 0);
+  if (rc) return rc;
+  x->ready = true;
   return SALEC_OK;
 }
-int copy_nodes_in(salec_ctx* x, double* dev, const double* host) {
-  const Geo& g = x->g;
-  HIPCHK(x, hipMemcpy2DAsync(dev, g.pn * sizeof(double), host, (g.NR + 1) * sizeof(double),
-                             (g.NR + 1) * sizeof(double), g.NZ + 1, hipMemcpyHostToDevice, x->st));
-  return SALEC_OK;
-}
+
+bool member_ok(const salec_ctx* x, int32_t k) { return x && x->ready && k >= 0 && (size_t)k < x->ms.size(); }
 
 }  // namespace
 
 extern "C" {
 
-size_t salec_plan(const salec_grid* grid, const salec_material* mats, const salec_pml* pml) {
+size_t salec_plan_batch(const salec_instance* inst, int32_t n) {
+  std::vector<Member> ms;
   std::string why;
-  if (validate(grid, mats, pml, why) != SALEC_OK) return 0;
-  Geo g = make_geo(grid, mats, pml);
+  if (check_members(inst, n, ms, why) != SALEC_OK) return 0;
   Layout L;
-  carve(g, nullptr, L);
+  carve_all(ms, nullptr, L);
   return L.total;
+}
+
+size_t salec_plan(const salec_grid* grid, const salec_material* mats, const salec_pml* pml) {
+  if (!grid || !mats || !pml) return 0;
+  salec_instance I;
+  std::memset(&I, 0, sizeof(I));
+  I.grid = *grid;
+  for (int m = 0; m < grid->nmat && m < SALEC_MAX_MAT; m++) I.mats[m] = mats[m];
+  I.pml = *pml;
+  return salec_plan_batch(&I, 1);
+}
+
+int salec_init_batch(const salec_instance* inst, int32_t n, void* dev_buf, size_t dev_bytes, void* stream,
+                     salec_ctx** out) {
+  if (!out) return SALEC_E_INVALID;
+  salec_ctx* x = new salec_ctx();
+  *out = x;  // returned even on failure, so salec_last_error() can explain it
+  int rc = check_members(inst, n, x->ms, x->err);
+  if (rc) return rc;
+  for (int32_t k = 0; k < n; k++) pml_profiles(x->ms[k], inst[k].mats, &inst[k].pml);
+  return init_common(x, dev_buf, dev_bytes, stream);
 }
 
 int salec_init(const salec_grid* grid, const salec_material* mats, const salec_pml* pml, const salec_scene* scene,
                void* dev_buf, size_t dev_bytes, void* stream, salec_ctx** out) {
   if (!out) return SALEC_E_INVALID;
-  *out = nullptr;
-  salec_ctx* x = new salec_ctx();
-  int rc = validate(grid, mats, pml, x->err);
-  if (rc == SALEC_OK && scene && (scene->subsample < 1 || !(scene->radius > 0))) {
-    x->err = "scene parameters";
-    rc = SALEC_E_INVALID;
-  }
-  if (rc != SALEC_OK) {
-    *out = x;  // keep the message reachable through salec_last_error
-    return rc;
-  }
-  x->g = make_geo(grid, mats, pml);
-  Layout probe;
-  carve(x->g, nullptr, probe);
-  if (!dev_buf || dev_bytes < probe.total || ((uintptr_t)dev_buf % kAlign) != 0) {
-    x->err = "device buffer smaller than salec_plan() or not 256-byte aligned";
+  if (!grid || !mats || !pml) {
+    salec_ctx* x = new salec_ctx();
+    x->err = "null argument";
     *out = x;
-    return SALEC_E_BUFFER;
+    return SALEC_E_INVALID;
   }
-  x->buf = dev_buf;
-  carve(x->g, dev_buf, x->L);
-  {
-    const char* pe = std::getenv("SALEC_PIPELINE");
-    x->phased = pe && std::strcmp(pe, "phased") == 0;
-  }
-  if (stream) {
-    x->st = (hipStream_t)stream;
-  } else {
-    hipError_t e = hipStreamCreate(&x->st);
-    if (e != hipSuccess) {
-      *out = x;
-      return hip_fail(x, e, "hipStreamCreate");
-    }
-    x->own_stream = true;
-  }
-  *out = x;
-  HIPCHK(x, hipEventCreate(&x->ev0));
-  HIPCHK(x, hipEventCreate(&x->ev1));
-  HIPCHK(x, hipMemsetAsync(dev_buf, 0, x->L.total, x->st));
-  std::vector<double> dcz, dnz, dcr, dnr;
-  pml_profiles(x->g, mats, pml, dcz, dnz, dcr, dnr);
-  HIPCHK(x, hipMemcpyAsync((void*)x->L.pm.dcz, dcz.data(), dcz.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
-  HIPCHK(x, hipMemcpyAsync((void*)x->L.pm.dnz, dnz.data(), dnz.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
-  HIPCHK(x, hipMemcpyAsync((void*)x->L.pm.dcr, dcr.data(), dcr.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
-  HIPCHK(x, hipMemcpyAsync((void*)x->L.pm.dnr, dnr.data(), dnr.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
+  salec_instance I;
+  std::memset(&I, 0, sizeof(I));
+  I.grid = *grid;
+  for (int m = 0; m < grid->nmat && m < SALEC_MAX_MAT; m++) I.mats[m] = mats[m];
+  I.pml = *pml;
   if (scene) {
-    double zc = (double)scene->surface_j * x->g.dz + scene->radius;
-    launch_scene(x->g, x->L.S[0], x->L.w, scene->surface_j, scene->subsample, scene->radius, zc, scene->v_imp, x->st);
-    HIPCHK(x, hipGetLastError());
+    I.scene = *scene;
+    I.has_scene = 1;
   }
-  HIPCHK(x, hipStreamSynchronize(x->st));  // host vectors above go out of scope
-  rc = start_run(x);
-  if (rc) return rc;
-  rc = capture(x, 1, &x->gx1);
-  if (rc) return rc;
-  rc = capture(x, kGraphCycles, &x->gxN);
-  if (rc) return rc;
-  return SALEC_OK;
+  return salec_init_batch(&I, 1, dev_buf, dev_bytes, stream, out);
 }
 
+int32_t salec_num_instances(const salec_ctx* x) { return x ? (int32_t)x->ms.size() : 0; }
+
 int salec_enqueue(salec_ctx* x, int32_t n) {
-  if (!x || n < 0 || !x->gx1) return SALEC_E_INVALID;
+  if (!x || n < 0 || !x->ready) return SALEC_E_INVALID;
   int32_t big = n / kGraphCycles, rem = n % kGraphCycles;
   for (int32_t k = 0; k < big; k++) HIPCHK(x, hipGraphLaunch(x->gxN, x->st));
   for (int32_t k = 0; k < rem; k++) HIPCHK(x, hipGraphLaunch(x->gx1, x->st));
@@ -414,7 +566,7 @@ int salec_enqueue(salec_ctx* x, int32_t n) {
 }
 
 int salec_step(salec_ctx* x, int32_t n) {
-  if (!x || n < 0 || !x->gx1) return SALEC_E_INVALID;
+  if (!x || n < 0 || !x->ready) return SALEC_E_INVALID;
   HIPCHK(x, hipEventRecord(x->ev0, x->st));
   int rc = salec_enqueue(x, n);
   if (rc) return rc;
@@ -423,10 +575,13 @@ int salec_step(salec_ctx* x, int32_t n) {
   float ms = 0.0f;
   HIPCHK(x, hipEventElapsedTime(&ms, x->ev0, x->ev1));
   x->last_ms = ms;
-  Scal s = read_scal(x);
-  if (s.err) {
-    x->err = "device error " + std::to_string(s.err) + " at cycle " + std::to_string(s.err_cycle);
-    return s.err;
+  for (size_t k = 0; k < x->ms.size(); k++) {
+    Scal s = read_scal(x, (int)k);
+    if (s.err) {
+      x->err = "instance " + std::to_string(k) + ": device error " + std::to_string(s.err) + " at cycle " +
+               std::to_string(s.err_cycle);
+      return s.err;
+    }
   }
   return SALEC_OK;
 }
@@ -437,73 +592,77 @@ int salec_last_step_ms(salec_ctx* x, double* ms) {
   return SALEC_OK;
 }
 
-int salec_get_fields(salec_ctx* x, const salec_fields* o) {
-  if (!x || !o || !x->gx1) return SALEC_E_INVALID;
+int salec_get_fields(salec_ctx* x, int32_t k, const salec_fields* o) {
+  if (!member_ok(x, k) || !o) return SALEC_E_INVALID;
   HIPCHK(x, hipStreamSynchronize(x->st));
-  Scal s = read_scal(x);
-  const State& S = current(x, s);
-  const Geo& g = x->g;
-  size_t NC = (size_t)g.NR * g.NZ, NN = (size_t)(g.NR + 1) * (g.NZ + 1);
+  Member& mb = x->ms[k];
+  Scal s = read_scal(x, k);
+  const State& S = mb.d.S[s.cycle & 1];
+  const Geo& g = mb.g;
+  size_t NC = (size_t)g.NR * g.NZ, NN = (size_t)(g.NR + 1) * (g.NZ + 1), es = elem_size(x);
   int rc = SALEC_OK;
-  if (o->rho && (rc = copy_cells_out(x, o->rho, S.rho))) return rc;
-  if (o->I && (rc = copy_cells_out(x, o->I, S.I))) return rc;
+  if (o->rho && (rc = copy_out(x, o->rho, S.rho, g.NR, g.NZ, g.pc, sizeof(double)))) return rc;
+  if (o->I && (rc = copy_out(x, o->I, S.I, g.NR, g.NZ, g.pc, sizeof(double)))) return rc;
   if (o->f)
     for (int m = 0; m < g.nmat; m++)
-      if ((rc = copy_cells_out(x, o->f + m * NC, S.f[m]))) return rc;
+      if ((rc = copy_out(x, o->f + m * NC, S.f[m], g.NR, g.NZ, g.pc, sizeof(double)))) return rc;
   if (o->s) {
     if (g.any_strength) {
-      for (int k = 0; k < 3; k++)
-        if ((rc = copy_cells_out(x, o->s + k * NC, S.s[k]))) return rc;
+      for (int q = 0; q < 3; q++)
+        if ((rc = copy_out(x, o->s + q * NC, S.s[q], g.NR, g.NZ, g.pc, es))) return rc;
     } else {
       std::memset(o->s, 0, 3 * NC * sizeof(double));
     }
   }
   if (o->v) {
-    if ((rc = copy_nodes_out(x, o->v, S.v[0]))) return rc;
-    if ((rc = copy_nodes_out(x, o->v + NN, S.v[1]))) return rc;
+    if ((rc = copy_out(x, o->v, S.v[0], g.NR + 1, g.NZ + 1, g.pn, es))) return rc;
+    if ((rc = copy_out(x, o->v + NN, S.v[1], g.NR + 1, g.NZ + 1, g.pn, es))) return rc;
   }
   if (o->p || o->c2) {
-    launch_eos_out(g, x->L.S[0], x->L.S[1], x->L.sc, x->L.w.sg[0], x->L.w.sg[1], x->st);
-    HIPCHK(x, hipGetLastError());
-    if (o->p && (rc = copy_cells_out(x, o->p, x->L.w.sg[0]))) return rc;
-    if (o->c2 && (rc = copy_cells_out(x, o->c2, x->L.w.sg[1]))) return rc;
+    double* p = x->L.scratch;
+    double* c2 = x->L.scratch + (size_t)g.NZ * g.pc;
+    HIPCHK(x, launch_eos_out(mb.d, p, c2, x->st));
+    if (o->p && (rc = copy_out(x, o->p, p, g.NR, g.NZ, g.pc, sizeof(double)))) return rc;
+    if (o->c2 && (rc = copy_out(x, o->c2, c2, g.NR, g.NZ, g.pc, sizeof(double)))) return rc;
   }
   HIPCHK(x, hipStreamSynchronize(x->st));
   return SALEC_OK;
 }
 
-int salec_set_fields(salec_ctx* x, const salec_fields* in) {
-  if (!x || !in || !in->rho || !in->I || !in->f || !in->v || !x->gx1) return SALEC_E_INVALID;
+int salec_set_fields(salec_ctx* x, int32_t k, const salec_fields* in) {
+  if (!member_ok(x, k) || !in || !in->rho || !in->I || !in->f || !in->v) return SALEC_E_INVALID;
   HIPCHK(x, hipStreamSynchronize(x->st));
-  const Geo& g = x->g;
-  const State& S = x->L.S[0];
-  size_t NC = (size_t)g.NR * g.NZ, NN = (size_t)(g.NR + 1) * (g.NZ + 1);
+  Member& mb = x->ms[k];
+  const Geo& g = mb.g;
+  const State& S = mb.d.S[0];
+  size_t NC = (size_t)g.NR * g.NZ, NN = (size_t)(g.NR + 1) * (g.NZ + 1), es = elem_size(x);
   int rc;
-  if ((rc = copy_cells_in(x, S.rho, in->rho))) return rc;
-  if ((rc = copy_cells_in(x, S.I, in->I))) return rc;
+  if ((rc = copy_in(x, S.rho, in->rho, g.NR, g.NZ, g.pc, sizeof(double)))) return rc;
+  if ((rc = copy_in(x, S.I, in->I, g.NR, g.NZ, g.pc, sizeof(double)))) return rc;
   for (int m = 0; m < g.nmat; m++)
-    if ((rc = copy_cells_in(x, S.f[m], in->f + m * NC))) return rc;
+    if ((rc = copy_in(x, S.f[m], in->f + m * NC, g.NR, g.NZ, g.pc, sizeof(double)))) return rc;
   if (g.any_strength) {
-    for (int k = 0; k < 3; k++) {
+    for (int q = 0; q < 3; q++) {
       if (in->s) {
-        if ((rc = copy_cells_in(x, S.s[k], in->s + k * NC))) return rc;
+        if ((rc = copy_in(x, S.s[q], in->s + q * NC, g.NR, g.NZ, g.pc, es))) return rc;
       } else {
-        HIPCHK(x, hipMemsetAsync(S.s[k], 0, (size_t)g.NZ * g.pc * sizeof(double), x->st));
+        HIPCHK(x, hipMemsetAsync(S.s[q], 0, (size_t)g.NZ * g.pc * es, x->st));
       }
     }
   }
-  if ((rc = copy_nodes_in(x, S.v[0], in->v))) return rc;
-  if ((rc = copy_nodes_in(x, S.v[1], in->v + NN))) return rc;
-  return start_run(x);
+  if ((rc = copy_in(x, S.v[0], in->v, g.NR + 1, g.NZ + 1, g.pn, es))) return rc;
+  if ((rc = copy_in(x, S.v[1], in->v + NN, g.NR + 1, g.NZ + 1, g.pn, es))) return rc;
+  return start_run(x, k);
 }
 
-int salec_get_pml(salec_ctx* x, double* ca, double* na) {
-  if (!x || !x->gx1) return SALEC_E_INVALID;
+int salec_get_pml(salec_ctx* x, int32_t k, double* ca, double* na) {
+  if (!member_ok(x, k)) return SALEC_E_INVALID;
   HIPCHK(x, hipStreamSynchronize(x->st));
-  const Geo& g = x->g;
+  Member& mb = x->ms[k];
+  const Geo& g = mb.g;
   size_t NC = (size_t)g.NR * g.NZ, NN = (size_t)(g.NR + 1) * (g.NZ + 1);
-  const Pml& pm = x->L.pm;
-  Scal sc_now = read_scal(x);
+  const Pml& pm = mb.d.pm;
+  Scal sc_now = read_scal(x, k);
   const PmlAux& au = pm.a[sc_now.cycle & 1];
   auto fetch = [&](const double* dev, size_t n, std::vector<double>& h) -> int {
     h.assign(n, 0.0);
@@ -518,17 +677,16 @@ int salec_get_pml(salec_ctx* x, double* ca, double* na) {
       std::vector<double> h[8];
       const double* b[3] = {au.b_phi1, au.b_phi3, au.b_psi2};
       const double* r[3] = {au.r_phi1, au.r_phi3, au.r_psi2};
-      for (int k = 0; k < 3; k++) {
-        if (fetch(b[k], nbc, h[k]) || fetch(r[k], nrc, h[3 + k])) return SALEC_E_HIP;
-      }
+      for (int q = 0; q < 3; q++)
+        if (fetch(b[q], nbc, h[q]) || fetch(r[q], nrc, h[3 + q])) return SALEC_E_HIP;
       if (fetch(pm.rref, nu, h[6]) || fetch(pm.msink, nu, h[7])) return SALEC_E_HIP;
       for (int j = 0; j < g.NZ; j++)
         for (int i = 0; i < g.NR; i++) {
           size_t c = (size_t)j * g.NR + i;
           if (j < g.pml_b)
-            for (int k = 0; k < 3; k++) ca[k * NC + c] = h[k][(size_t)j * g.NR + i];
+            for (int q = 0; q < 3; q++) ca[q * NC + c] = h[q][(size_t)j * g.NR + i];
           if (i >= g.n_r)
-            for (int k = 0; k < 3; k++) ca[(3 + k) * NC + c] = h[3 + k][(size_t)j * g.pml_r + (i - g.n_r)];
+            for (int q = 0; q < 3; q++) ca[(3 + q) * NC + c] = h[3 + q][(size_t)j * g.pml_r + (i - g.n_r)];
           long long u = -1;
           if (j < g.pml_b) u = (long long)j * g.NR + i;
           else if (i >= g.n_r) u = (long long)nbc + (long long)(j - g.pml_b) * g.pml_r + (i - g.n_r);
@@ -545,15 +703,15 @@ int salec_get_pml(salec_ctx* x, double* ca, double* na) {
       std::vector<double> h[8];
       const double* b[4] = {au.b_phi2r, au.b_phi2z, au.b_psi1r, au.b_psi1z};
       const double* r[4] = {au.r_phi2r, au.r_phi2z, au.r_psi1r, au.r_psi1z};
-      for (int k = 0; k < 4; k++)
-        if (fetch(b[k], nbn, h[k]) || fetch(r[k], nrn, h[4 + k])) return SALEC_E_HIP;
+      for (int q = 0; q < 4; q++)
+        if (fetch(b[q], nbn, h[q]) || fetch(r[q], nrn, h[4 + q])) return SALEC_E_HIP;
       for (int j = 0; j <= g.NZ; j++)
         for (int i = 0; i <= g.NR; i++) {
           size_t n = (size_t)j * (g.NR + 1) + i;
           if (j < g.pml_b)
-            for (int k = 0; k < 4; k++) na[k * NN + n] = h[k][(size_t)j * (g.NR + 1) + i];
+            for (int q = 0; q < 4; q++) na[q * NN + n] = h[q][(size_t)j * (g.NR + 1) + i];
           if (i > g.n_r)
-            for (int k = 0; k < 4; k++) na[(4 + k) * NN + n] = h[4 + k][(size_t)j * g.pml_r + (i - g.n_r - 1)];
+            for (int q = 0; q < 4; q++) na[(4 + q) * NN + n] = h[4 + q][(size_t)j * g.pml_r + (i - g.n_r - 1)];
         }
     }
   }
@@ -561,42 +719,43 @@ int salec_get_pml(salec_ctx* x, double* ca, double* na) {
 }
 
 size_t salec_state_bytes(const salec_ctx* x) {
-  if (!x || !x->gx1) return 0;
-  return 16 + x->L.persist_bytes;
+  if (!x || !x->ready) return 0;
+  return 32 + x->L.persist_bytes;
 }
 
 int salec_get_state(salec_ctx* x, void* blob, size_t bytes) {
-  if (!x || !blob || !x->gx1) return SALEC_E_INVALID;
+  if (!x || !blob || !x->ready) return SALEC_E_INVALID;
   if (bytes < salec_state_bytes(x)) return SALEC_E_BUFFER;
   HIPCHK(x, hipStreamSynchronize(x->st));
-  uint64_t head[2] = {kStateMagic, (uint64_t)x->L.persist_bytes};
-  std::memcpy(blob, head, 16);
-  HIPCHK(x, hipMemcpy((uint8_t*)blob + 16, x->L.sc, x->L.persist_bytes, hipMemcpyDeviceToHost));
+  uint64_t head[4] = {kStateMagic, (uint64_t)x->L.persist_bytes, (uint64_t)x->ms.size(), (uint64_t)x->prec};
+  std::memcpy(blob, head, 32);
+  HIPCHK(x, hipMemcpy((uint8_t*)blob + 32, x->buf, x->L.persist_bytes, hipMemcpyDeviceToHost));
   return SALEC_OK;
 }
 
 int salec_set_state(salec_ctx* x, const void* blob, size_t bytes) {
-  if (!x || !blob || !x->gx1) return SALEC_E_INVALID;
+  if (!x || !blob || !x->ready) return SALEC_E_INVALID;
   if (bytes < salec_state_bytes(x)) return SALEC_E_BUFFER;
-  uint64_t head[2];
-  std::memcpy(head, blob, 16);
-  if (head[0] != kStateMagic || head[1] != x->L.persist_bytes) {
+  uint64_t head[4];
+  std::memcpy(head, blob, 32);
+  if (head[0] != kStateMagic || head[1] != x->L.persist_bytes || head[2] != x->ms.size() ||
+      head[3] != (uint64_t)x->prec) {
     x->err = "state blob does not match this context";
     return SALEC_E_INVALID;
   }
   HIPCHK(x, hipStreamSynchronize(x->st));
-  HIPCHK(x, hipMemcpy(x->L.sc, (const uint8_t*)blob + 16, x->L.persist_bytes, hipMemcpyHostToDevice));
+  HIPCHK(x, hipMemcpy(x->buf, (const uint8_t*)blob + 32, x->L.persist_bytes, hipMemcpyHostToDevice));
   return SALEC_OK;
 }
 
-int salec_diag(salec_ctx* x, salec_diag_t* out) {
-  if (!x || !out || !x->gx1) return SALEC_E_INVALID;
+int salec_diag(salec_ctx* x, int32_t k, salec_diag_t* out) {
+  if (!member_ok(x, k) || !out) return SALEC_E_INVALID;
   HIPCHK(x, hipStreamSynchronize(x->st));
-  launch_diag(x->g, x->L.S[0], x->L.S[1], x->L.w, x->L.pm, x->L.sc, x->L.n_pml, x->L.diag_out, x->st);
-  HIPCHK(x, hipGetLastError());
-  double q[6];
+  Member& mb = x->ms[k];
+  HIPCHK(x, launch_diag(mb.d, mb.n_pml, x->L.red, x->L.diag_out, x->st));
+  double q[kDiagQ];
   HIPCHK(x, hipMemcpyAsync(q, x->L.diag_out, sizeof(q), hipMemcpyDeviceToHost, x->st));
-  Scal s = read_scal(x);
+  Scal s = read_scal(x, k);
   out->t = s.t;
   out->dt = s.dt;
   out->dt_prev = s.dt_prev;
@@ -609,6 +768,55 @@ int salec_diag(salec_ctx* x, salec_diag_t* out) {
   out->ie_out = q[5];
   out->err = s.err;
   out->err_cycle = s.err_cycle;
+  return SALEC_OK;
+}
+
+int32_t salec_num_variants(void) { return n_variants(); }
+
+int salec_get_schedule(const salec_ctx* x, salec_schedule* out) {
+  if (!x || !out || !x->ready) return SALEC_E_INVALID;
+  std::memset(out, 0, sizeof(*out));
+  out->variant = x->variant;
+  variant_shape(x->variant, &out->tile_r, &out->tile_z, &out->threads);
+  out->grid = x->grid;
+  out->ms_per_cycle = x->tuned_ms;
+  return SALEC_OK;
+}
+
+int salec_set_schedule(salec_ctx* x, int32_t variant, int32_t grid) {
+  if (!x || !x->ready) return SALEC_E_INVALID;
+  x->tuned_ms = 0.0;
+  int rc = use_schedule(x, variant, grid);
+  if (rc) x->ready = false;
+  return rc;
+}
+
+int salec_tune(salec_ctx* x, int32_t cycles, salec_schedule* out) {
+  if (!x || !x->ready || cycles < 1) return SALEC_E_INVALID;
+  int best_v = x->variant, best_g = x->grid;
+  double best = 1e300;
+  for (int v = 0; v < n_variants(); v++) {
+    int rc = use_schedule(x, v, 0);
+    if (rc) {
+      x->ready = false;
+      return rc;
+    }
+    if ((rc = salec_step(x, 1))) return rc;
+    if ((rc = salec_step(x, cycles))) return rc;
+    double ms = x->last_ms / cycles;
+    if (ms < best) {
+      best = ms;
+      best_v = v;
+      best_g = 0;
+    }
+  }
+  int rc = use_schedule(x, best_v, best_g);
+  if (rc) {
+    x->ready = false;
+    return rc;
+  }
+  x->tuned_ms = best;
+  if (out) return salec_get_schedule(x, out);
   return SALEC_OK;
 }
 

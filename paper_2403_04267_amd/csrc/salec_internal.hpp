@@ -8,19 +8,29 @@
 namespace salec {
 
 constexpr unsigned kDiagBlocks = 240;
+constexpr int kDiagQ = 6;  // mass, ie, ke, mass_out, mass_pml, ie_out
 
-void launch_cycle(const Geo& g, const State& S0, const State& S1, const Work& w, const Pml& pm, Scal* sc,
-                  hipStream_t st);
-void launch_cycle_fused(const Geo& g, const State& S0, const State& S1, const Work& w, const Pml& pm, Scal* sc,
+using CycleFn = void (*)(const Inst*, const TileRef*, int);
+
+// cycle kernel: tile-shape variants, one instantiation per bulk type
+int n_variants();
+void variant_shape(int v, int* tw, int* th, int* nt);
+CycleFn cycle_kernel_f64(int v);
+CycleFn cycle_kernel_f32(int v);
+hipError_t launch_cycle(int v, int prec, const Inst* insts, const TileRef* sched, int nsched, int grid,
                         hipStream_t st);
-void fused_tiles(int NR, int NZ, int* tr, int* tz);
-void launch_dt0(const Geo& g, const State& S0, const State& S1, Scal* sc, hipStream_t st);
-void launch_scene(const Geo& g, const State& S0, const Work& w, int surface_j, int S, double R, double zc,
-                  double v_imp, hipStream_t st);
-void launch_eos_out(const Geo& g, const State& S0, const State& S1, const Scal* sc, double* p, double* c2,
-                    hipStream_t st);
-void launch_diag(const Geo& g, const State& S0, const State& S1, const Work& w, const Pml& pm, const Scal* sc,
-                 long long n_pml, double* out, hipStream_t st);
-void launch_start_run(const Geo& g, const State& S0, const Pml& pm, Scal* sc, hipStream_t st);
+
+// EoS cache and Courant candidates of the current state (start of a run)
+hipError_t launch_prime_f64(const Inst& in, hipStream_t st);
+hipError_t launch_prime_f32(const Inst& in, hipStream_t st);
+hipError_t launch_prime(const Inst& in, hipStream_t st);
+
+// set-up, outputs and diagnostics of one instance
+hipError_t launch_scene(const Inst& in, int surface_j, int S, double R, double zc, double v_imp, double* scratch,
+                        hipStream_t st);
+hipError_t launch_start_run(const Inst& in, hipStream_t st);
+hipError_t launch_finalize0(const Inst& in, hipStream_t st);
+hipError_t launch_eos_out(const Inst& in, double* p, double* c2, hipStream_t st);
+hipError_t launch_diag(const Inst& in, long long n_pml, double* red, double* out, hipStream_t st);
 
 }  // namespace salec

@@ -60,6 +60,16 @@ class Diag(C.Structure):
                 ("err_cycle", C.c_int32)]
 
 
+class Instance(C.Structure):
+    _fields_ = [("grid", Grid), ("mats", Material * 2), ("pml", PmlC), ("scene", SceneC),
+                ("has_scene", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Schedule(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("tile_r", C.c_int32), ("tile_z", C.c_int32), ("threads", C.c_int32),
+                ("grid", C.c_int32), ("reserved", C.c_int32), ("ms_per_cycle", C.c_double)]
+
+
 _lib = None
 
 
@@ -72,21 +82,32 @@ def load() -> C.CDLL:
         raise RuntimeError(f"libsalec.so not built ({LIB_PATH}); run __graft_entry__.build()")
     lib = C.CDLL(LIB_PATH)
     P = C.c_void_p
+    I32 = C.c_int32
     lib.salec_plan.restype = C.c_size_t
     lib.salec_plan.argtypes = [C.POINTER(Grid), C.POINTER(Material), C.POINTER(PmlC)]
+    lib.salec_plan_batch.restype = C.c_size_t
+    lib.salec_plan_batch.argtypes = [C.POINTER(Instance), I32]
     lib.salec_init.argtypes = [C.POINTER(Grid), C.POINTER(Material), C.POINTER(PmlC), C.POINTER(SceneC),
                                P, C.c_size_t, P, C.POINTER(P)]
-    lib.salec_step.argtypes = [P, C.c_int32]
-    lib.salec_enqueue.argtypes = [P, C.c_int32]
-    lib.salec_get_fields.argtypes = [P, C.POINTER(Fields)]
-    lib.salec_set_fields.argtypes = [P, C.POINTER(Fields)]
-    lib.salec_get_pml.argtypes = [P, _DP, _DP]
+    lib.salec_init_batch.argtypes = [C.POINTER(Instance), I32, P, C.c_size_t, P, C.POINTER(P)]
+    lib.salec_num_instances.restype = I32
+    lib.salec_num_instances.argtypes = [P]
+    lib.salec_step.argtypes = [P, I32]
+    lib.salec_enqueue.argtypes = [P, I32]
+    lib.salec_get_fields.argtypes = [P, I32, C.POINTER(Fields)]
+    lib.salec_set_fields.argtypes = [P, I32, C.POINTER(Fields)]
+    lib.salec_get_pml.argtypes = [P, I32, _DP, _DP]
     lib.salec_state_bytes.restype = C.c_size_t
     lib.salec_state_bytes.argtypes = [P]
     lib.salec_get_state.argtypes = [P, P, C.c_size_t]
     lib.salec_set_state.argtypes = [P, P, C.c_size_t]
-    lib.salec_diag.argtypes = [P, C.POINTER(Diag)]
+    lib.salec_diag.argtypes = [P, I32, C.POINTER(Diag)]
     lib.salec_last_step_ms.argtypes = [P, _DP]
+    lib.salec_num_variants.restype = I32
+    lib.salec_num_variants.argtypes = []
+    lib.salec_get_schedule.argtypes = [P, C.POINTER(Schedule)]
+    lib.salec_set_schedule.argtypes = [P, I32, I32]
+    lib.salec_tune.argtypes = [P, I32, C.POINTER(Schedule)]
     lib.salec_last_error.restype = C.c_char_p
     lib.salec_last_error.argtypes = [P]
     lib.salec_destroy.argtypes = [P]
@@ -119,11 +140,31 @@ def _mats(problem):
     return arr
 
 
-def plan_bytes(problem) -> int:
-    lib = load()
+def _instance(problem) -> Instance:
+    g = problem.grid
+    inst = Instance()
+    inst.grid = _grid(g, problem.precision)
+    for k, m in enumerate(problem.mats[:g.nmat]):
+        inst.mats[k] = _mat(m)
     p = problem.pml
-    return lib.salec_plan(C.byref(_grid(problem.grid, problem.precision)), _mats(problem),
-                          C.byref(PmlC(int(p.enabled), 0, p.R, p.c_ref)))
+    inst.pml = PmlC(int(p.enabled), 0, p.R, p.c_ref)
+    if problem.scene is not None:
+        sc = problem.scene
+        inst.scene = SceneC(sc.surface_j, sc.subsample, sc.radius, sc.v_imp)
+        inst.has_scene = 1
+    return inst
+
+
+def plan_bytes(problems) -> int:
+    """Device bytes for one problem or a list of problems (an ensemble)."""
+    lib = load()
+    probs = problems if isinstance(problems, (list, tuple)) else [problems]
+    arr = (Instance * len(probs))(*[_instance(pb) for pb in probs])
+    return lib.salec_plan_batch(arr, len(probs))
+
+
+def num_variants() -> int:
+    return load().salec_num_variants()
 
 
 def _ptr(a):
@@ -137,27 +178,29 @@ class SalecError(RuntimeError):
 
 
 class Salec:
-    """One simulation context on a HIP device."""
+    """A simulation context on a HIP device: one problem, or a list of
+    problems advanced together as an ensemble (member k is `problems[k]`)."""
 
-    def __init__(self, problem, device: str = "cuda:0"):
+    def __init__(self, problems, device: str = "cuda:0"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libsalec needs a HIP device; none is visible")
         lib = load()
         self.lib = lib
-        self.problem = problem
-        g = problem.grid
-        self.NR, self.NZ = g.n_r + g.pml_r, g.n_z + g.pml_b
+        self.problems = list(problems) if isinstance(problems, (list, tuple)) else [problems]
+        self.problem = self.problems[0]
+        self.dims = []
+        for pb in self.problems:
+            g = pb.grid
+            NR, NZ = g.n_r + g.pml_r, g.n_z + g.pml_b
+            self.dims.append((NR, NZ, g.nmat))
+        self.NR, self.NZ, self.nmat = self.dims[0]
         self.NC, self.NN = self.NR * self.NZ, (self.NR + 1) * (self.NZ + 1)
-        self.nmat = g.nmat
         self.device = torch.device(device)
-        grid = _grid(g, problem.precision)
-        mats = _mats(problem)
-        p = problem.pml
-        pml = PmlC(int(p.enabled), 0, p.R, p.c_ref)
-        nbytes = lib.salec_plan(C.byref(grid), mats, C.byref(pml))
+        arr = (Instance * len(self.problems))(*[_instance(pb) for pb in self.problems])
+        nbytes = lib.salec_plan_batch(arr, len(self.problems))
         if nbytes == 0:
-            raise ValueError("salec_plan rejected the problem description")
+            raise ValueError("salec_plan_batch rejected the problem description")
         with torch.cuda.device(self.device):
             self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
             base = self.buf.data_ptr()
@@ -165,14 +208,9 @@ class Salec:
             # a stream of our own (default priority): the legacy null stream
             # cannot be captured into HIP graphs
             self.stream = torch.cuda.Stream(device=self.device)
-        sc = None
-        if problem.scene is not None:
-            s = problem.scene
-            sc = SceneC(s.surface_j, s.subsample, s.radius, s.v_imp)
         h = C.c_void_p()
-        rc = lib.salec_init(C.byref(grid), mats, C.byref(pml), C.byref(sc) if sc is not None else None,
-                            C.c_void_p(base + off), C.c_size_t(nbytes), C.c_void_p(self.stream.cuda_stream),
-                            C.byref(h))
+        rc = lib.salec_init_batch(arr, len(self.problems), C.c_void_p(base + off), C.c_size_t(nbytes),
+                                  C.c_void_p(self.stream.cuda_stream), C.byref(h))
         self._h = h
         if rc:
             msg = lib.salec_last_error(h).decode() if h else ""
@@ -188,6 +226,10 @@ class Salec:
         if rc:
             raise SalecError(rc, self.lib.salec_last_error(self._h).decode())
 
+    @property
+    def num_instances(self) -> int:
+        return self.lib.salec_num_instances(self._h)
+
     def step(self, n: int, check: bool = True) -> int:
         rc = self.lib.salec_step(self._h, int(n))
         if rc and check:
@@ -202,45 +244,49 @@ class Salec:
         self._check(self.lib.salec_last_step_ms(self._h, C.byref(v)))
         return v.value
 
-    def fields(self, eos: bool = True) -> dict:
-        NR, NZ, NC, NN = self.NR, self.NZ, self.NC, self.NN
+    def fields(self, eos: bool = True, k: int = 0) -> dict:
+        NR, NZ, nmat = self.dims[k]
+        NC, NN = NR * NZ, (NR + 1) * (NZ + 1)
         rho, I = np.empty(NC), np.empty(NC)
-        f, s, v = np.empty(self.nmat * NC), np.empty(3 * NC), np.empty(2 * NN)
+        f, s, v = np.empty(nmat * NC), np.empty(3 * NC), np.empty(2 * NN)
         p = np.empty(NC) if eos else None
         c2 = np.empty(NC) if eos else None
         fl = Fields(_ptr(rho), _ptr(I), _ptr(f), _ptr(s), _ptr(v), _ptr(p), _ptr(c2))
-        self._check(self.lib.salec_get_fields(self._h, C.byref(fl)))
-        out = {"rho": rho.reshape(NZ, NR), "I": I.reshape(NZ, NR), "f": f.reshape(self.nmat, NZ, NR),
+        self._check(self.lib.salec_get_fields(self._h, int(k), C.byref(fl)))
+        out = {"rho": rho.reshape(NZ, NR), "I": I.reshape(NZ, NR), "f": f.reshape(nmat, NZ, NR),
                "s": s.reshape(3, NZ, NR), "v": v.reshape(2, NZ + 1, NR + 1)}
         if eos:
             out["p"] = p.reshape(NZ, NR)
             out["c2"] = c2.reshape(NZ, NR)
         return out
 
-    def set_fields(self, rho, I, f, v, s=None):
-        NC, NN = self.NC, self.NN
+    def set_fields(self, rho, I, f, v, s=None, k: int = 0):
+        NR, NZ, nmat = self.dims[k]
+        NC, NN = NR * NZ, (NR + 1) * (NZ + 1)
         arr = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in (rho, I, f, v)]
-        assert arr[0].size == NC and arr[1].size == NC and arr[2].size == self.nmat * NC and arr[3].size == 2 * NN
+        if not (arr[0].size == NC and arr[1].size == NC and arr[2].size == nmat * NC and arr[3].size == 2 * NN):
+            raise ValueError("field shapes do not match the instance")
         sp = None if s is None else np.ascontiguousarray(s, dtype=np.float64).reshape(3 * NC)
         fl = Fields(_ptr(arr[0]), _ptr(arr[1]), _ptr(arr[2]), _ptr(sp), _ptr(arr[3]), None, None)
-        self._check(self.lib.salec_set_fields(self._h, C.byref(fl)))
+        self._check(self.lib.salec_set_fields(self._h, int(k), C.byref(fl)))
 
-    def pml_aux(self) -> dict:
-        NR, NZ, NC, NN = self.NR, self.NZ, self.NC, self.NN
+    def pml_aux(self, k: int = 0) -> dict:
+        NR, NZ, _ = self.dims[k]
+        NC, NN = NR * NZ, (NR + 1) * (NZ + 1)
         ca, na = np.empty(8 * NC), np.empty(8 * NN)
-        self._check(self.lib.salec_get_pml(self._h, _ptr(ca), _ptr(na)))
+        self._check(self.lib.salec_get_pml(self._h, int(k), _ptr(ca), _ptr(na)))
         ca, na = ca.reshape(8, NZ, NR), na.reshape(8, NZ + 1, NR + 1)
         names_c = ["phi1_b", "phi3_b", "psi2_b", "phi1_r", "phi3_r", "psi2_r", "rho_ref", "msink"]
         names_n = ["phi2_b_r", "phi2_b_z", "psi1_b_r", "psi1_b_z", "phi2_r_r", "phi2_r_z", "psi1_r_r",
                    "psi1_r_z"]
-        out = {k: ca[i] for i, k in enumerate(names_c)}
-        out.update({k: na[i] for i, k in enumerate(names_n)})
+        out = {n: ca[i] for i, n in enumerate(names_c)}
+        out.update({n: na[i] for i, n in enumerate(names_n)})
         return out
 
-    def diag(self) -> dict:
+    def diag(self, k: int = 0) -> dict:
         d = Diag()
-        self._check(self.lib.salec_diag(self._h, C.byref(d)))
-        return {k: getattr(d, k) for k, _ in Diag._fields_}
+        self._check(self.lib.salec_diag(self._h, int(k), C.byref(d)))
+        return {n: getattr(d, n) for n, _ in Diag._fields_}
 
     def get_state(self) -> bytes:
         n = self.lib.salec_state_bytes(self._h)
@@ -251,3 +297,16 @@ class Salec:
     def set_state(self, blob: bytes):
         buf = C.create_string_buffer(blob, len(blob))
         self._check(self.lib.salec_set_state(self._h, buf, len(blob)))
+
+    def schedule(self) -> dict:
+        s = Schedule()
+        self._check(self.lib.salec_get_schedule(self._h, C.byref(s)))
+        return {n: getattr(s, n) for n, _ in Schedule._fields_}
+
+    def set_schedule(self, variant: int, grid: int = 0):
+        self._check(self.lib.salec_set_schedule(self._h, int(variant), int(grid)))
+
+    def tune(self, cycles: int) -> dict:
+        s = Schedule()
+        self._check(self.lib.salec_tune(self._h, int(cycles), C.byref(s)))
+        return {n: getattr(s, n) for n, _ in Schedule._fields_}

@@ -50,10 +50,29 @@ def test_plan_rejects_invalid_materials_and_pml():
     assert salec.plan_bytes(pb) == 0
 
 
-def test_mixed_precision_not_accepted_by_fp64_build():
-    pb = inputs.config_small().replace(precision="mixed")
-    # documented in the header: only SALEC_FP64 is implemented in this build
-    assert salec.plan_bytes(pb) == 0
+def test_mixed_precision_plan_is_smaller():
+    fp64 = salec.plan_bytes(inputs.config_scale())
+    mixed = salec.plan_bytes(inputs.config_scale().replace(precision="mixed"))
+    # stress, velocity and the EoS cache are FP32 in the mixed mode
+    assert 0 < mixed < 0.8 * fp64
+
+
+def test_batch_plan_is_the_sum_of_its_members():
+    members = inputs.ensemble(2403, 4, 200, 800)
+    whole = salec.plan_bytes(members)
+    parts = sum(salec.plan_bytes(m) for m in members)
+    # shared scratch is counted once in the batch
+    assert 0.8 * parts < whole <= parts
+
+
+def test_batch_plan_rejects_mixed_precisions():
+    a, b = inputs.ensemble(7, 2, 200, 300)
+    assert salec.plan_bytes([a, b]) > 0
+    assert salec.plan_bytes([a, b.replace(precision="mixed")]) == 0
+
+
+def test_schedule_variants_are_listed():
+    assert salec.num_variants() >= 2
 
 
 def test_binding_refuses_to_run_without_a_device():
