@@ -1,16 +1,30 @@
 """Benchmark: cell-updates/s of the per-cycle grid update on one MI355X.
 
-Workload: 1000 x 1000 cells + 50-cell PML (1050 x 1050 = 1,102,500 cells),
-two materials with pressure-dependent strength, R = 50 cells, 15 km/s,
-plain FP64 (the scale configuration). One step = one full cycle of the hot
-path over the whole grid. W warm-up cycles, then K timed cycles, bracketed by
-stream synchronisation; inputs are resident in HBM throughout.
+Headline workload: 1000 x 1000 cells + 50-cell PML (1050 x 1050 =
+1,102,500 cells), two materials with pressure-dependent strength, R = 50
+cells, 15 km/s, plain FP64. One step = one full cycle of the hot path over
+the whole grid (one launch of the cycle kernel). The tile shape is chosen by
+the library's tuner during warm-up; W warm-up cycles, then K timed cycles
+bracketed by stream synchronisation, inputs resident in HBM throughout. The
+device time comes from HIP events the library records on its own stream
+around the replayed graphs.
 
-Prints one JSON line. `roofline` reports the whole cycle's algorithmic bytes
-per cell-update (state read + written once, PML auxiliaries in layer cells)
-over the measured device time, against the 8 TB/s HBM peak.
+Also measured (the "extensions" object; skipped with --headline-only):
+  mixed_scale    the same workload in the mixed-precision mode
+  mixed_large    4000 x 4000 + 100 PML (4100^2 cells), mixed precision
+  batched_fp64   256 seeded uneven impacts (sides 200-800), plain FP64
+  batched_mixed  1024 seeded uneven impacts (sides 200-1200), mixed
+Each is init + tune + warm-up, then a short timed run.
+
+Prints one JSON line. `roofline` is the cycle kernel's algorithmic HBM
+bytes per launch (state read and written once, PML auxiliaries) over its
+measured average duration, against the 8 TB/s HBM peak; `traffic` is the
+kernel's measured HBM bytes per launch from the committed counter summary,
+or null when the kernel sources changed since it was taken.
 """
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -20,6 +34,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_cycle_fp64_1050x1050_hbm_traffic.json")
+
+
+def kernel_sources_sha() -> str:
+    """Hash of the sources that define the cycle kernel's memory traffic."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2403_04267_amd", "csrc")
+    for name in ("salec_cycle.hpp", "salec_device.hpp", "salec_cycle.hip", "salec_cycle_f64.hip"):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def algorithmic_bytes_per_cell(pb) -> float:
@@ -27,19 +52,35 @@ def algorithmic_bytes_per_cell(pb) -> float:
     three deviatoric stresses when strength is on, two node velocities per
     cell; plus the PML auxiliaries (3 cell + 4 node values per damped
     direction, read + written; corner cells count twice; the reference
-    density and the sink read / written once) averaged over all cells."""
+    density read and the sink read + written) averaged over all cells.
+    Mixed precision: stress and velocity are 4-byte values."""
     g = pb.grid
     nmat = g.nmat
     strength = any(m.strength for m in pb.mats[:nmat])
-    per_cell = 2 + nmat + (3 if strength else 0) + 2
-    state = 2 * 8 * per_cell
+    wide = 8 * (2 + nmat)
+    narrow = (8 if pb.precision == "fp64" else 4) * ((3 if strength else 0) + 2)
+    state = 2 * (wide + narrow)
     NR, NZ = g.NR, g.NZ
     ncell = NR * NZ
     bottom = g.pml_b * NR
     right = g.pml_r * NZ
     union = bottom + g.n_z * g.pml_r
-    aux = 2 * 8 * 7 * (bottom + right) + 8 * 3 * union  # rho_ref read, msink r+w
+    aux = 2 * 8 * 7 * (bottom + right) + 8 * 3 * union
     return state + aux / ncell if pb.pml.enabled else state
+
+
+def traffic_per_launch():
+    """Measured HBM bytes per cycle-kernel launch (FETCH_SIZE + WRITE_SIZE,
+    each scaled by the reading for a plain copy of known size), if the
+    summary matches the current kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sources_sha256") != kernel_sources_sha():
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(pb, budget_s=12.0):
@@ -56,7 +97,46 @@ def cpu_baseline(pb, budget_s=12.0):
         if el >= budget_s or n >= 2000:
             break
     return {"value": cells * n / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} cycles of the same 1050x1050 workload from its initial state"}
+            "sample": f"{n} cycles of the same 1050x1050 FP64 workload from its initial state "
+                      f"({el:.1f} s of CPU time)"}
+
+
+def run(problems, steps, warmup, tune, variant=-1, grid=0):
+    """Times `steps` cycles of a context; returns (cell-updates/s, ms per
+    cycle, schedule, context)."""
+    from paper_2403_04267_amd.salec import Salec
+    ctx = Salec(problems, "cuda:0")
+    if variant >= 0:
+        ctx.set_schedule(variant, grid)
+    elif tune > 0:
+        ctx.tune(tune)
+    if warmup:
+        ctx.step(warmup)
+    ctx.step(steps)
+    ms = ctx.last_step_ms()
+    probs = problems if isinstance(problems, list) else [problems]
+    cells = sum(p.grid.ncells for p in probs)
+    return cells * steps / (ms / 1e3), ms / steps, ctx.schedule(), ctx
+
+
+def extension(name, problems, steps, warmup, tune, fp64_rate=None):
+    import torch
+    t0 = time.perf_counter()
+    rate, ms, sch, ctx = run(problems, steps, warmup, tune)
+    probs = problems if isinstance(problems, list) else [problems]
+    out = {"value": rate, "unit": "cell-updates/s", "ms_per_cycle": ms, "cycles": steps,
+           "instances": len(probs), "cells": sum(p.grid.ncells for p in probs),
+           "precision": probs[0].precision, "schedule": {k: sch[k] for k in ("tile_r", "tile_z", "threads")},
+           "bytes_per_cell_update": sum(algorithmic_bytes_per_cell(p) * p.grid.ncells for p in probs) /
+           sum(p.grid.ncells for p in probs)}
+    out["hbm_frac"] = out["bytes_per_cell_update"] * rate / 1e9 / HBM_PEAK_GBS
+    if fp64_rate:
+        out["speedup_vs_fp64"] = rate / fp64_rate
+    del ctx
+    torch.cuda.empty_cache()
+    out["wall_s"] = time.perf_counter() - t0
+    print(f"[bench] {name}: {rate:.3e} cu/s, {ms * 1e3:.1f} us/cycle", file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -65,6 +145,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--headline-only", action="store_true", help="skip the mixed and batched measurements")
     ap.add_argument("--tune", type=int, default=2, metavar="K",
                     help="time every tile shape over K cycles during warm-up and keep the fastest (0: off)")
     ap.add_argument("--variant", type=int, default=-1, help="force a tile shape (disables --tune)")
@@ -87,42 +168,41 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}), flush=True)
         return
     from paper_2403_04267_amd import inputs
-    from paper_2403_04267_amd.salec import Salec
 
     pb = inputs.config_scale()
-    ctx = Salec(pb, "cuda:0")
-    if args.variant >= 0:
-        ctx.set_schedule(args.variant, args.grid)
-    elif args.tune > 0:
-        ctx.tune(args.tune)  # advances the run; counted as warm-up
-    if args.warmup:
-        ctx.step(args.warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.step(args.steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    dev_ms = ctx.last_step_ms()
-    cells = pb.grid.ncells
-    cu = cells * args.steps
-    value = cu / (dev_ms / 1e3)
+    t_wall = time.perf_counter()
+    value, ms_cycle, sch, ctx = run(pb, args.steps, args.warmup, args.tune, args.variant, args.grid)
+    wall = time.perf_counter() - t_wall
     bpc = algorithmic_bytes_per_cell(pb)
-    achieved = bpc * value / 1e9
+    achieved = bpc * pb.grid.ncells / (ms_cycle / 1e3) / 1e9
+    traffic = traffic_per_launch()
     d = ctx.diag()
+    del ctx
     out = {
         "metric": "cell-updates/s", "value": value, "unit": "cell-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dev_ms / args.steps,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_cycle,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "impact-1050x1050-2mat-strength-pml50-fp64", "cells": cells,
+        "config": {"workload": "impact-1050x1050-2mat-strength-pml50-fp64", "cells": pb.grid.ncells,
                    "cycles": args.steps, "precision": "fp64"},
-        "wall_ms_per_step": wall * 1e3 / args.steps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_cell_update": bpc, "scope": "whole cycle"},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_cycle (one launch = one cycle of the whole grid)",
+                     "bytes_per_cell_update": bpc},
+        "schedule": sch,
         "sim": {"t": d["t"], "dt": d["dt"], "cycle": d["cycle"]},
-        "schedule": ctx.schedule(),
+        "wall_s": wall,
     }
+    torch.cuda.empty_cache()
+    if not args.headline_only:
+        ext = {}
+        ext["mixed_scale"] = extension("mixed 1050^2", pb.replace(precision="mixed"), args.steps,
+                                       args.warmup, args.tune, value)
+        ext["mixed_large"] = extension("mixed 4100^2", inputs.config_large("mixed"), 200, 10, 1)
+        ext["batched_fp64"] = extension("batched 256 fp64", inputs.ensemble(2403, 256, 200, 800), 40, 2, 1)
+        ext["batched_mixed"] = extension("batched 1024 mixed",
+                                         inputs.ensemble(4267, 1024, 200, 1200, precision="mixed"), 10, 1, 1)
+        out["extensions"] = ext
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pb)
     print(json.dumps(out), flush=True)

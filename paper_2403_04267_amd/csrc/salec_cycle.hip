@@ -22,6 +22,43 @@ hipError_t launch_cycle(int v, int prec, const Inst* insts, const TileRef* sched
   return hipGetLastError();
 }
 
+// End of a cycle, one workgroup (one wave) per instance: the Courant minimum
+// over the instance's tiles, then time, cycle count, next step (growth cap,
+// maximum, stop time) and sticky errors (Sec. 7).
+__global__ __launch_bounds__(64) void k_finalize(const Inst* __restrict__ insts) {
+  using CInst = const __attribute__((address_space(4))) Inst;
+  const Inst& in = *(const Inst*)((CInst*)insts + blockIdx.x);
+  Scal* sc = in.sc;
+  if (sc->err) return;
+  double m = __builtin_huge_val();
+  for (int q = threadIdx.x; q < in.ntiles; q += 64) m = dmin(m, in.dtpart[q]);
+  for (int off = 32; off > 0; off >>= 1) m = dmin(m, __shfl_down(m, off, 64));
+  if (threadIdx.x != 0) return;
+  const Geo& g = in.g;
+  double t = sc->t + sc->dt;
+  sc->t = t;
+  sc->cycle = sc->cycle + 1;
+  double dtn = dmin(dmin(m, g.dt_grow * sc->dt), g.dt_max);
+  if (g.t_stop > 0) dtn = dmin(dtn, dmax(g.t_stop - t, 0.0));
+  sc->dt_prev = sc->dt;
+  sc->dt = dtn;
+  unsigned fl = sc->flags;
+  int e = 0;
+  if (fl & kFlagNonFinite) e = -4;
+  else if (fl & kFlagNegMass) e = -5;
+  bool stopped = g.t_stop > 0 && t >= g.t_stop;
+  if (e == 0 && !stopped && dtn < g.dt_floor) e = -6;
+  if (e) {
+    sc->err = e;
+    sc->err_cycle = (int)sc->cycle;
+  }
+}
+
+hipError_t launch_finalize(const Inst* insts, int n_inst, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(n_inst), dim3(64), 0, st, insts);
+  return hipGetLastError();
+}
+
 hipError_t launch_prime(const Inst& in, hipStream_t st) {
   return in.g.prec == 0 ? launch_prime_f64(in, st) : launch_prime_f32(in, st);
 }

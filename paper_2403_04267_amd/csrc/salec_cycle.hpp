@@ -17,8 +17,9 @@
 // arithmetic; only the owner of a cell or node writes it. The state, its EoS
 // cache and the PML auxiliaries ping-pong by cycle parity, so every halo read
 // sees level n. The Courant minimum of a tile is reduced with wave shuffles
-// and LDS; the last tile of an instance to finish (done counter) finalises
-// that instance's t, dt and cycle count, so instances keep their own dt.
+// and LDS and stored per tile; the finalize kernel that follows in the same
+// graph reduces each instance's tile minima and advances that instance's t,
+// dt and cycle count, so instances keep their own dt.
 //
 // T is the bulk arithmetic and storage type of stress, velocity and the EoS
 // cache (double, or float in the mixed mode). Density, volume fractions,
@@ -89,8 +90,7 @@ __device__ __forceinline__ double block_min(double cand, double* s_min) {
 
 template <int TW, int TH, int NT, class T>
 __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_rho, double* s_bigd, T* s_vL,
-                                           double* s_Fr, double* s_Fz, double* s_rho1, double* s_min,
-                                           int* s_last) {
+                                           double* s_Fr, double* s_Fz, double* s_rho1, double* s_min) {
   using R = Regions<TW, TH>;
   using N = Num<T>;
   using GT = GeoT<T>;
@@ -675,41 +675,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   }
   if (flags) atomicOr(&sc->flags, flags);
   double m = block_min<NT>(cand, s_min);
-  if (tid == 0) {
-    in.dtpart[tile] = m;
-    __threadfence();
-    unsigned prev = atomicAdd(&sc->done, 1u);
-    *s_last = (prev == (unsigned)(in.ntiles - 1));
-  }
-  __syncthreads();
-  if (!*s_last) return;
-  // ------------------------------------------------------------ finalize
-  __threadfence();
-  double mm = __builtin_huge_val();
-  for (int q = tid; q < in.ntiles; q += NT)
-    mm = dmin(mm, __hip_atomic_load(&in.dtpart[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-  __syncthreads();  // s_min is reused
-  mm = block_min<NT>(mm, s_min);
-  if (tid == 0) {
-    double t = sc->t + sc->dt;
-    sc->t = t;
-    sc->cycle = sc->cycle + 1;
-    double dtn = dmin(dmin(mm, g.dt_grow * sc->dt), g.dt_max);
-    if (g.t_stop > 0) dtn = dmin(dtn, dmax(g.t_stop - t, 0.0));
-    sc->dt_prev = sc->dt;
-    sc->dt = dtn;
-    sc->done = 0u;
-    unsigned fl = __hip_atomic_load(&sc->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int e = 0;
-    if (fl & kFlagNonFinite) e = -4;
-    else if (fl & kFlagNegMass) e = -5;
-    bool stopped = g.t_stop > 0 && t >= g.t_stop;
-    if (e == 0 && !stopped && dtn < g.dt_floor) e = -6;
-    if (e) {
-      sc->err = e;
-      sc->err_cycle = (int)sc->cycle;
-    }
-  }
+  if (tid == 0) in.dtpart[tile] = m;
 }
 
 template <int TW, int TH, int NT, class T>
@@ -723,7 +689,6 @@ __global__ __launch_bounds__(NT) void k_cycle(const Inst* __restrict__ insts, co
   __shared__ double s_Fr[R::NRF], s_Fz[R::NZF];  // face mass fluxes (0 where no face)
   __shared__ double s_rho1[R::NE];    // rho^{n+1} over E (0 outside the grid)
   __shared__ double s_min[NT / 64];
-  __shared__ int s_last;
   // Descriptors and schedule are read-only for the whole launch: reading them
   // through the constant address space lets the compiler keep or re-issue
   // those scalar loads freely across the workgroup barriers below.
@@ -735,7 +700,7 @@ __global__ __launch_bounds__(NT) void k_cycle(const Inst* __restrict__ insts, co
     const TileRef tr{csched[e].inst, csched[e].tile};
     if (tr.inst < 0) continue;
     const Inst* in = (const Inst*)(cinst + tr.inst);
-    tile_cycle<TW, TH, NT, T>(*in, tr.tile, s_rho, s_bigd, s_vL, s_Fr, s_Fz, s_rho1, s_min, &s_last);
+    tile_cycle<TW, TH, NT, T>(*in, tr.tile, s_rho, s_bigd, s_vL, s_Fr, s_Fz, s_rho1, s_min);
     __syncthreads();  // LDS is reused by the next entry
   }
 }

@@ -91,7 +91,7 @@ struct Scal {
   long long cycle;
   unsigned long long dtmin;  // bit pattern of the running minimum (dt > 0)
   unsigned flags;
-  unsigned done;             // tiles of the current cycle that have finished
+  unsigned pad;
   int err, err_cycle;
 };
 

@@ -389,8 +389,10 @@ int capture(salec_ctx* x, int ncyc, hipGraphExec_t* out) {
   int grid = x->grid > 0 ? std::min(x->grid, x->nsched) : x->nsched;
   HIPCHK(x, hipStreamBeginCapture(x->st, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
-  for (int k = 0; k < ncyc && le == hipSuccess; k++)
+  for (int k = 0; k < ncyc && le == hipSuccess; k++) {
     le = launch_cycle(x->variant, x->prec, x->L.d_inst, x->L.d_sched, x->nsched, grid, x->st);
+    if (le == hipSuccess) le = launch_finalize(x->L.d_inst, (int)x->ms.size(), x->st);
+  }
   hipError_t e = hipStreamEndCapture(x->st, &gr);
   if (le != hipSuccess) {
     if (gr) (void)hipGraphDestroy(gr);

@@ -19,6 +19,8 @@ CycleFn cycle_kernel_f64(int v);
 CycleFn cycle_kernel_f32(int v);
 hipError_t launch_cycle(int v, int prec, const Inst* insts, const TileRef* sched, int nsched, int grid,
                         hipStream_t st);
+// end of a cycle: per-instance Courant minimum, clock, errors
+hipError_t launch_finalize(const Inst* insts, int n_inst, hipStream_t st);
 
 // EoS cache and Courant candidates of the current state (start of a run)
 hipError_t launch_prime_f64(const Inst& in, hipStream_t st);

@@ -111,7 +111,7 @@ __global__ void k_start_run(Inst in) {
     sc->cycle = 0;
     sc->dtmin = 0x7FF0000000000000ull;
     sc->flags = 0;
-    sc->done = 0;
+    sc->pad = 0;
     sc->err = 0;
     sc->err_cycle = -1;
   }

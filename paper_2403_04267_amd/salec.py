@@ -80,6 +80,10 @@ def load() -> C.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"libsalec.so not built ({LIB_PATH}); run __graft_entry__.build()")
+    # torch first: the library must bind to the HIP runtime torch loads (a
+    # process whose first HIP runtime came with libsalec sees no device from
+    # it once torch has initialised its own)
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     P = C.c_void_p
     I32 = C.c_int32

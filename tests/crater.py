@@ -44,3 +44,35 @@ def rel_l2(a, b):
     den = float(np.sqrt(np.sum(np.asarray(b, dtype=np.float64) ** 2)))
     num = float(np.sqrt(np.sum((np.asarray(a, dtype=np.float64) - b) ** 2)))
     return num / den if den > 0 else num
+
+
+def node_mass(rho, grid):
+    """A quarter of the masses (rho V, per radian) of the cells around each node."""
+    NZ, NR = rho.shape
+    V = (np.arange(NR) + 0.5) * grid.dr * grid.dr * grid.dz
+    M = rho * V[None, :]
+    out = np.zeros((NZ + 1, NR + 1))
+    out[:-1, :-1] += M
+    out[:-1, 1:] += M
+    out[1:, :-1] += M
+    out[1:, 1:] += M
+    return 0.25 * out
+
+
+def conserved_errors(Fa, Fb, grid):
+    """Relative L2 errors of run a against reference run b on the volume
+    densities the scheme conserves or uses: rho, rho I, phi p (the pressure
+    that enters the stress), f, phi s, and the node momentum m v. Intensive
+    p, I and v are ill-conditioned in cells and nodes holding only traces of
+    matter, so they are compared through these densities."""
+    pa, pb = Fa["f"].sum(0), Fb["f"].sum(0)
+    e = {"rho": rel_l2(Fa["rho"], Fb["rho"]),
+         "rhoI": rel_l2(Fa["rho"] * Fa["I"], Fb["rho"] * Fb["I"]),
+         "phi_p": rel_l2(pa * Fa["p"], pb * Fb["p"]),
+         "f": rel_l2(Fa["f"], Fb["f"])}
+    if np.any(Fb["s"]):
+        e["phi_s"] = rel_l2(pa[None] * Fa["s"], pb[None] * Fb["s"])
+    ma, mb = node_mass(Fa["rho"], grid), node_mass(Fb["rho"], grid)
+    e["mv_r"] = rel_l2(ma * Fa["v"][0], mb * Fb["v"][0])
+    e["mv_z"] = rel_l2(ma * Fa["v"][1], mb * Fb["v"][1])
+    return e
