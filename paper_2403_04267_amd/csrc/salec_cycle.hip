@@ -4,7 +4,9 @@
 namespace salec {
 
 // must match the order of SALEC_CYCLE_TABLE
-static const int kShapes[][3] = {{64, 16, 512}, {64, 16, 1024}, {32, 32, 1024}, {32, 16, 256}};
+static const int kShapes[][3] = {{64, 16, 512}, {64, 16, 1024}, {32, 32, 1024},
+                                  {64, 15, 768},  {64, 16, 768},  {48, 20, 768},
+                                  {64, 14, 768},  {40, 24, 768}};
 
 int n_variants() { return (int)(sizeof(kShapes) / sizeof(kShapes[0])); }
 

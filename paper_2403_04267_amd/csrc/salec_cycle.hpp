@@ -88,6 +88,20 @@ __device__ __forceinline__ double block_min(double cand, double* s_min) {
   return m;
 }
 
+// register-array element by a run-time index without dynamic indexing
+template <int N, class T>
+__device__ __forceinline__ T reg_get(const T (&a)[N], int u) {
+  T r = a[0];
+#pragma unroll
+  for (int q = 1; q < N; q++) r = (u == q) ? a[q] : r;
+  return r;
+}
+template <int N, class T>
+__device__ __forceinline__ void reg_put(T (&a)[N], int u, T v) {
+#pragma unroll
+  for (int q = 0; q < N; q++) a[q] = (u == q) ? v : a[q];
+}
+
 template <int TW, int TH, int NT, class T>
 __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_rho, double* s_bigd, T* s_vL,
                                            double* s_Fr, double* s_Fz, double* s_rho1, double* s_min) {
@@ -137,13 +151,19 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   T* ct = (T*)(s_bigd + 4 * R::NC);   // [4][NC] lambda, sL x3 during C..E2
   double* heat = s_bigd;              // [NF] during F..G
   T* speed = (T*)(s_bigd + R::NF);    // [NF] during F..G
+  T* s_kd = (T*)s_Fr;                 // [NB] during B..C: 1/2 |v^L - v^n|^2 per node
+  static_assert(R::NB * (int)sizeof(T) <= (R::NRF + R::NZF) * 8, "node buffer must fit in the flux buffers");
 
   // ------------------------------------------------------------------ A
+  // 1024-thread workgroups keep the per-cell loops of A and C rolled: four
+  // waves per SIMD leave no registers for two cells in flight at once
+  constexpr int kUnroll = NT >= 1024 ? 1 : UA;
   T rP[UA];
 #pragma unroll
+  for (int u = 0; u < UA; u++) rP[u] = T(0);
+#pragma unroll kUnroll
   for (int u = 0; u < UA; u++) {
     int k = tid + u * NT;
-    rP[u] = T(0);
     if (k >= R::NA) continue;
     int i = i0 - 3 + k % R::AW, j = j0 - 3 + k / R::AW;
     T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
@@ -178,7 +198,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       s1 = phi * (szz - P);
       s2 = phi * (stt - P);
       s3 = phi * srz;
-      rP[u] = P;
+      reg_put(rP, u, P);
     }
     sig[0 * R::NA + k] = s0;
     sig[1 * R::NA + k] = s1;
@@ -191,7 +211,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   // ------------------------------------------------------------------ B
   for (int k = tid; k < R::NB; k += NT) {
     int i = i0 - 2 + k % R::BW, j = j0 - 2 + k / R::BW;
-    T vLr = T(0), vLz = T(0);
+    T vLr = T(0), vLz = T(0), kdn = T(0);
     if (i >= 0 && i <= g.NR && j >= 0 && j <= g.NZ) {
       // quadrants NE = (i, j), NW = (i-1, j), SE = (i, j-1), SW = (i-1, j-1)
       const int qa[4] = {kA(i, j), kA(i - 1, j), kA(i, j - 1), kA(i - 1, j - 1)};
@@ -253,9 +273,12 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         vLz = T(0);
       }
       if (g.top_closed && j == g.NZ) vLz = T(0);
+      T dvr = vLr - Sv0[n], dvz = vLz - Sv1[n];
+      kdn = T(0.5) * (dvr * dvr + dvz * dvz);
     }
     s_vL[k] = vLr;
     s_vL[R::NB + k] = vLz;
+    s_kd[k] = kdn;
   }
   __syncthreads();
 
@@ -275,7 +298,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   // ------------------------------------------------------------------ C
   // (same cell-to-thread map as A, so A's per-cell results stay in registers;
   // the stress buffer is dead after B, so results go straight into it)
-#pragma unroll
+#pragma unroll kUnroll
   for (int u = 0; u < UA; u++) {
     int k = tid + u * NT;
     int i = i0 - 3 + k % R::AW, j = j0 - 3 + k / R::AW;
@@ -286,7 +309,6 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     T oLam = T(1), os0 = T(0), os1 = T(0), os2 = T(0);
     if (in_cells(g, i, j)) {
       long long c = cidx(g, i, j);
-      const long long nd[4] = {nidx(g, i, j), nidx(g, i + 1, j), nidx(g, i, j + 1), nidx(g, i + 1, j + 1)};
       const int nb[4] = {kB(i, j), kB(i + 1, j), kB(i, j + 1), kB(i + 1, j + 1)};
       T vr4[4], vz4[4];
 #pragma unroll
@@ -322,7 +344,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         }
       }
       T stt = -(s0rr + s0zz);
-      T P = rP[u];
+      T P = reg_get(rP, u);
       T sde = ((s0rr * kn.err + s0zz * kn.ezz) + stt * kn.ett) + T(2) * s0rz * kn.erz;
       T dD = dtT * kn.D;
       T J = T(1) + dD;
@@ -337,10 +359,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       double rt = dmax(rho, g.rho_ref * kPmlRhoFloor);
       T kd[4];
 #pragma unroll
-      for (int q = 0; q < 4; q++) {
-        T dvr = vr4[q] - Sv0[nd[q]], dvz = vz4[q] - Sv1[nd[q]];
-        kd[q] = T(0.5) * (dvr * dvr + dvz * dvz);
-      }
+      for (int q = 0; q < 4; q++) kd[q] = s_kd[nb[q]];
       T rN0 = (T)i * dr, rC = ((T)i + T(0.5)) * dr, rN1 = (T)(i + 1) * dr;
       T V = cell_volume<T>(g, i);
       T wW = N::div(Ring<T>::w(g, i) * hdz, V);
@@ -686,7 +705,7 @@ __global__ __launch_bounds__(NT) void k_cycle(const Inst* __restrict__ insts, co
   __shared__ double s_rho[R::NA];     // rho^n over A (0 outside the grid)
   __shared__ double s_bigd[SM::kBigD];  // A..B stress; C..E2 Lagrangian state; F..G heat, speed
   __shared__ T s_vL[2 * R::NB];       // v^L over B
-  __shared__ double s_Fr[R::NRF], s_Fz[R::NZF];  // face mass fluxes (0 where no face)
+  __shared__ double s_F[R::NRF + R::NZF];  // B..C: node KE defect; E1..F: face mass fluxes
   __shared__ double s_rho1[R::NE];    // rho^{n+1} over E (0 outside the grid)
   __shared__ double s_min[NT / 64];
   // Descriptors and schedule are read-only for the whole launch: reading them
@@ -700,7 +719,7 @@ __global__ __launch_bounds__(NT) void k_cycle(const Inst* __restrict__ insts, co
     const TileRef tr{csched[e].inst, csched[e].tile};
     if (tr.inst < 0) continue;
     const Inst* in = (const Inst*)(cinst + tr.inst);
-    tile_cycle<TW, TH, NT, T>(*in, tr.tile, s_rho, s_bigd, s_vL, s_Fr, s_Fz, s_rho1, s_min);
+    tile_cycle<TW, TH, NT, T>(*in, tr.tile, s_rho, s_bigd, s_vL, s_F, s_F + R::NRF, s_rho1, s_min);
     __syncthreads();  // LDS is reused by the next entry
   }
 }
@@ -747,7 +766,11 @@ __global__ void k_prime(Inst in) {
       case 0: return k_cycle<64, 16, 512, T>;                                                  \
       case 1: return k_cycle<64, 16, 1024, T>;                                                 \
       case 2: return k_cycle<32, 32, 1024, T>;                                                 \
-      case 3: return k_cycle<32, 16, 256, T>;                                                  \
+      case 3: return k_cycle<64, 15, 768, T>;                                                  \
+      case 4: return k_cycle<64, 16, 768, T>;                                                  \
+      case 5: return k_cycle<48, 20, 768, T>;                                                  \
+      case 6: return k_cycle<64, 14, 768, T>;                                                  \
+      case 7: return k_cycle<40, 24, 768, T>;                                                  \
       default: return nullptr;                                                                 \
     }                                                                                          \
   }                                                                                            \
