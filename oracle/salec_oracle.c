@@ -143,15 +143,20 @@ void orc_tillotson(const orc_mat *m, double rho, double e, double *p_out, double
     double rf = m->rho0 * RHO_EOS_FLOOR;
     double r = rho > rf ? rho : rf;
     double E = e > 0.0 ? e : 0.0;
+    /* reciprocals shared by the terms below (material constants, then 1/r
+     * and 1/w); eta keeps a true division so that eta = 1 exactly at rho0 */
+    double irho0 = 1.0 / m->rho0, Ar = m->A / m->rho0, idE = 1.0 / (m->Ecv - m->Eiv);
+    double ir = 1.0 / r, irr = ir * ir;
     double eta = r / m->rho0;
     double mu = eta - 1.0;
     double w = E / (m->E0 * eta * eta) + 1.0;
+    double iw = 1.0 / w, iw2 = iw * iw;
 
     /* compressed / cold branch */
-    double pc = (m->a + m->b / w) * r * E + m->A * mu + m->B * mu * mu;
-    double pc_E = r * (m->a + m->b / w - m->b * (w - 1.0) / (w * w));
-    double pc_r = (m->a + m->b / w) * E + 2.0 * m->b * E * (w - 1.0) / (w * w)
-                + (m->A + 2.0 * m->B * mu) / m->rho0;
+    double pc = (m->a + m->b * iw) * r * E + m->A * mu + m->B * mu * mu;
+    double pc_E = r * (m->a + m->b * iw - m->b * (w - 1.0) * iw2);
+    double pc_r = (m->a + m->b * iw) * E + 2.0 * m->b * E * (w - 1.0) * iw2
+                + (m->A + 2.0 * m->B * mu) * irho0;
     double p, dpdE, dpdr;
     if (r >= m->rho0 || E <= m->Eiv) {
         p = pc;
@@ -159,29 +164,29 @@ void orc_tillotson(const orc_mat *m, double rho, double e, double *p_out, double
         dpdr = pc_r;
     } else {
         /* expanded branch */
-        double z = 1.0 / eta - 1.0;
+        double z = m->rho0 * ir - 1.0;
         double ea = exp_cw(-m->alpha * z * z);
         double eb = exp_cw(-m->beta * z);
-        double pe = m->a * r * E + (m->b * r * E / w + m->A * mu * eb) * ea;
-        double pe_E = m->a * r + ea * m->b * r * (1.0 / w - (w - 1.0) / (w * w));
+        double pe = m->a * r * E + (m->b * r * E * iw + m->A * mu * eb) * ea;
+        double pe_E = m->a * r + ea * m->b * r * (iw - (w - 1.0) * iw2);
         double pe_r = m->a * E
-                    + ea * (m->b * E / w + 2.0 * m->b * E * (w - 1.0) / (w * w)
-                            + (m->A / m->rho0) * eb + m->A * mu * m->beta * eb * m->rho0 / (r * r))
-                    + (m->b * r * E / w + m->A * mu * eb) * ea * 2.0 * m->alpha * z * m->rho0 / (r * r);
+                    + ea * (m->b * E * iw + 2.0 * m->b * E * (w - 1.0) * iw2
+                            + Ar * eb + m->A * mu * m->beta * eb * m->rho0 * irr)
+                    + (m->b * r * E * iw + m->A * mu * eb) * ea * 2.0 * m->alpha * z * m->rho0 * irr;
         if (E >= m->Ecv) {
             p = pe;
             dpdE = pe_E;
             dpdr = pe_r;
         } else {
             /* partial vaporisation: energy-weighted blend */
-            double x = (E - m->Eiv) / (m->Ecv - m->Eiv);
+            double x = (E - m->Eiv) * idE;
             p = x * pe + (1.0 - x) * pc;
-            dpdE = x * pe_E + (1.0 - x) * pc_E + (pe - pc) / (m->Ecv - m->Eiv);
+            dpdE = x * pe_E + (1.0 - x) * pc_E + (pe - pc) * idE;
             dpdr = x * pe_r + (1.0 - x) * pc_r;
         }
     }
     *p_out = p;
-    *c2_out = dpdr + p / (r * r) * dpdE;
+    *c2_out = dpdr + p * irr * dpdE;
 }
 
 /* intact-rock yield strength (Table 1 parameters Y_i0, mu_i, Y_im) */
@@ -190,7 +195,8 @@ double orc_yield(const orc_mat *m, double p)
     if (!m->strength) return 0.0;
     if (p >= 0.0) {
         double mp = m->mu_f * p;
-        return m->Y0 + mp / (1.0 + mp / (m->Ylim - m->Y0));
+        double iYd = 1.0 / (m->Ylim - m->Y0);
+        return m->Y0 + mp / (1.0 + mp * iYd);
     }
     return dmax(0.0, m->Y0 + m->mu_f * p);
 }
@@ -206,7 +212,8 @@ double orc_shear_modulus(const orc_mat *m)
 double orc_softening(const orc_mat *m, double e)
 {
     double E = e > 0.0 ? e : 0.0;
-    return dmin(dmax((m->Ecv - E) / (m->Ecv - m->Eiv), 0.0), 1.0);
+    double idE = 1.0 / (m->Ecv - m->Eiv);
+    return dmin(dmax((m->Ecv - E) * idE, 0.0), 1.0);
 }
 
 /* mixture state of cell c: shared material density and energy, weights f_m/phi */
@@ -217,12 +224,13 @@ static void mixture(const orc_ctx *x, int c, const double *rho, const double *I,
     double phi = 0.0;
     for (int m = 0; m < x->nmat; m++) phi += f[m][c];
     double den = phi > PHI_EPS ? phi : PHI_EPS;
-    double rm = rho[c] / den;
+    double iden = 1.0 / den;
+    double rm = rho[c] * iden;
     double p = 0.0, c2 = 0.0, G = 0.0;
     double wm[ORC_MAX_MAT];
     for (int m = 0; m < x->nmat; m++) {
         double pm, c2m;
-        wm[m] = f[m][c] / den;
+        wm[m] = f[m][c] * iden;
         orc_tillotson(&x->m[m], rm, I[c], &pm, &c2m);
         pm = dmax(pm, x->m[m].p_min);
         c2m = dmax(c2m, x->m[m].c_floor_frac * x->m[m].A / x->m[m].rho0);
@@ -280,14 +288,15 @@ static void kinematics(const orc_grid *g, int i, const double *vr, const double 
     k->Uz_n = aw * vz[2] + ae * vz[3];
     k->uz_s = k->Uz_s / Az;
     k->uz_n = k->Uz_n / Az;
-    k->Dr = (k->Ur_e - k->Ur_w) / V;
-    k->Dz = (k->Uz_n - k->Uz_s) / V;
-    k->D = ((k->Ur_e - k->Ur_w) + (k->Uz_n - k->Uz_s)) / V;
-    k->err = (k->ur_e - k->ur_w) / g->dr;
-    k->ezz = (k->Uz_n - k->Uz_s) / V;
-    k->ett = (0.5 * (k->ur_w + k->ur_e)) / rc;
-    k->dvr_dz = ((aw * vr[2] + ae * vr[3]) - (aw * vr[0] + ae * vr[1])) / V;
-    k->dvz_dr = (0.5 * (vz[1] + vz[3]) - 0.5 * (vz[0] + vz[2])) / g->dr;
+    double iV = 1.0 / V, irc = 1.0 / rc, idr = 1.0 / g->dr;
+    k->Dr = (k->Ur_e - k->Ur_w) * iV;
+    k->Dz = (k->Uz_n - k->Uz_s) * iV;
+    k->D = ((k->Ur_e - k->Ur_w) + (k->Uz_n - k->Uz_s)) * iV;
+    k->err = (k->ur_e - k->ur_w) * idr;
+    k->ezz = (k->Uz_n - k->Uz_s) * iV;
+    k->ett = (0.5 * (k->ur_w + k->ur_e)) * irc;
+    k->dvr_dz = ((aw * vr[2] + ae * vr[3]) - (aw * vr[0] + ae * vr[1])) * iV;
+    k->dvz_dr = (0.5 * (vz[1] + vz[3]) - 0.5 * (vz[0] + vz[2])) * idr;
     k->erz = 0.5 * (k->dvr_dz + k->dvz_dr);
     k->om = 0.5 * (k->dvr_dz - k->dvz_dr);
 }
@@ -309,7 +318,7 @@ void orc_cell_kinematics(const orc_grid *g, int32_t i, const double *vr, const d
 void orc_stress_update(double G, double Y, double dt, const double *rt, double *s)
 {
     double srr = s[0], szz = s[1], srz = s[2];
-    double tr3 = ((rt[0] + rt[1]) + rt[2]) / 3.0;
+    double tr3 = ((rt[0] + rt[1]) + rt[2]) * (1.0 / 3.0);
     double om = rt[4];
     double dsrr = 2.0 * G * (rt[0] - tr3) + 2.0 * om * srz;
     double dszz = 2.0 * G * (rt[1] - tr3) - 2.0 * om * srz;
@@ -653,7 +662,7 @@ static void phase_cell_stress(orc_ctx *x)
             kinematics(&x->g, i, vr4, vz4, &k);
             /* compression felt by the material (void closes first) */
             double Jn = 1.0 + x->dt * k.D;
-            double Dm = Jn < 1.0 ? (1.0 - material_ratio(Jn, phi, sx)) / x->dt : 0.0;
+            double Dm = Jn < 1.0 ? (1.0 - material_ratio(Jn, phi, sx)) * (1.0 / x->dt) : 0.0;
             double Ld = L * Dm;
             double Q = rm * (x->g.q_quad * Ld * Ld + x->g.q_lin * sqrt(c2) * Ld);
             double P = p + Q;
@@ -718,15 +727,19 @@ static void phase_node_force(orc_ctx *x)
             double psr = x->psi1b_r[n] + x->psi1r_r[n];
             double psz = x->psi1b_z[n] + x->psi1r_z[n];
             double Fer = Fr - Vd * psr, Fez = Fz - Vd * psz;
-            x->vLr[n] = x->vr[n] + dt * (Fer / mt);
-            x->vLz[n] = x->vz[n] + dt * (Fez / mt);
-            if (db > 0.0) {
-                x->psi1b_r[n] = x->psi1b_r[n] - dt * db * (Frr / Vd);
-                x->psi1b_z[n] = x->psi1b_z[n] - dt * db * (Fzr / Vd);
-            }
-            if (drr > 0.0) {
-                x->psi1r_r[n] = x->psi1r_r[n] - dt * drr * (Frz / Vd);
-                x->psi1r_z[n] = x->psi1r_z[n] - dt * drr * (Fzz / Vd);
+            double imt = 1.0 / mt;
+            x->vLr[n] = x->vr[n] + dt * (Fer * imt);
+            x->vLz[n] = x->vz[n] + dt * (Fez * imt);
+            if (db > 0.0 || drr > 0.0) {
+                double iVd = 1.0 / Vd;
+                if (db > 0.0) {
+                    x->psi1b_r[n] = x->psi1b_r[n] - dt * db * (Frr * iVd);
+                    x->psi1b_z[n] = x->psi1b_z[n] - dt * db * (Fzr * iVd);
+                }
+                if (drr > 0.0) {
+                    x->psi1r_r[n] = x->psi1r_r[n] - dt * drr * (Frz * iVd);
+                    x->psi1r_z[n] = x->psi1r_z[n] - dt * drr * (Fzz * iVd);
+                }
             }
         }
     }
@@ -779,8 +792,9 @@ static void phase_cell_lagrange(orc_ctx *x)
             }
             double rN0 = (double)i * x->g.dr, rC = ((double)i + 0.5) * x->g.dr, rN1 = (double)(i + 1) * x->g.dr;
             double V = vol_c(x, i), hdz = 0.5 * x->g.dz;
-            double wW = (0.5 * (rC * rC - rN0 * rN0) * hdz) / V;
-            double wE = (0.5 * (rN1 * rN1 - rC * rC) * hdz) / V;
+            double iV = 1.0 / V;
+            double wW = (0.5 * (rC * rC - rN0 * rN0) * hdz) * iV;
+            double wE = (0.5 * (rN1 * rN1 - rC * rC) * hdz) * iV;
             double hL = wW * (kd[0] + kd[2]) + wE * (kd[1] + kd[3]);
             x->IL[c] = ((x->I[c] + Wdt / rden) + hL) - dt * (psi2 / rt_);
             for (int m = 0; m < x->nmat; m++) x->fL[m][c] = x->f[m][c] * (Jm / J);
@@ -900,8 +914,9 @@ static void phase_cell_remap(orc_ctx *x)
             double dVe[4] = {x->dVre[RF(i, j)], x->dVre[RF(i + 1, j)], x->dVze[AF(i, j)], x->dVze[AF(i, j + 1)]};
             int di[4] = {i - 1, i + 1, i, i}, dj[4] = {j, j, j - 1, j + 1};
             int in[4] = {dV[0] > 0.0, dV[1] < 0.0, dV[2] > 0.0, dV[3] < 0.0};
+            double iV = 1.0 / V;
             double netin = ((F[0] - F[1]) + F[2]) - F[3];
-            double rho1 = x->rho[c] + netin / V;
+            double rho1 = x->rho[c] + netin * iV;
             double M1 = rho1 * V;
             double min_ = 0.0, nI = 0.0, nsrr = 0.0, nszz = 0.0, nsrz = 0.0, vcut = 0.0;
             double nf[ORC_MAX_MAT] = {0.0, 0.0};
@@ -927,20 +942,22 @@ static void phase_cell_remap(orc_ctx *x)
                 }
             }
             double den = dmax(dmax(M1, min_), M_REMAP_FLOOR * x->rho_ref * V);
-            double I1 = IL + nI / den;
-            x->srr_n[c] = x->sLrr[c] + nsrr / den;
-            x->szz_n[c] = x->sLzz[c] + nszz / den;
-            x->srz_n[c] = x->sLrz[c] + nsrz / den;
+            double iden = 1.0 / den;
+            double I1 = IL + nI * iden;
+            x->srr_n[c] = x->sLrr[c] + nsrr * iden;
+            x->szz_n[c] = x->sLzz[c] + nszz * iden;
+            x->srz_n[c] = x->sLrz[c] + nsrz * iden;
             double fs = 0.0;
             double f1[ORC_MAX_MAT];
             /* volume the limiter kept from leaving this cell, minus void that
              * arrived in place of limited inflow (both zero without limiting) */
             double ex = (1.0 - x->lam[c]) * x->outv[c] - vcut;
             for (int m = 0; m < nm; m++) {
-                f1[m] = dmax(x->fL[m][c] + (nf[m] + x->fL[m][c] * ex) / V, 0.0);
+                f1[m] = dmax(x->fL[m][c] + (nf[m] + x->fL[m][c] * ex) * iV, 0.0);
                 fs += f1[m];
             }
-            for (int m = 0; m < nm; m++) x->f_n[m][c] = f1[m] / dmax(fs, 1.0);
+            double ifs = 1.0 / dmax(fs, 1.0);
+            for (int m = 0; m < nm; m++) x->f_n[m][c] = f1[m] * ifs;
 
             /* PML: damping of the fluctuation about the initial state plus the
              * unstretched-direction auxiliary terms; r-faces feed the bottom
@@ -956,12 +973,12 @@ static void phase_cell_remap(orc_ctx *x)
                 double I2 = I1 - dt * (dsum * I1 + (x->phi3b[c] + x->phi3r[c]) / rt_);
                 x->msink[c] = x->msink[c] + V * (rho1 - rho2);
                 if (db > 0.0) {
-                    x->phi1b[c] = x->phi1b[c] + db * ((F[1] - F[0]) / V);
-                    x->phi3b[c] = x->phi3b[c] + db * ((ed[1] - ed[0]) / V);
+                    x->phi1b[c] = x->phi1b[c] + db * ((F[1] - F[0]) * iV);
+                    x->phi3b[c] = x->phi3b[c] + db * ((ed[1] - ed[0]) * iV);
                 }
                 if (drr > 0.0) {
-                    x->phi1r[c] = x->phi1r[c] + drr * ((F[3] - F[2]) / V);
-                    x->phi3r[c] = x->phi3r[c] + drr * ((ed[3] - ed[2]) / V);
+                    x->phi1r[c] = x->phi1r[c] + drr * ((F[3] - F[2]) * iV);
+                    x->phi3r[c] = x->phi3r[c] + drr * ((ed[3] - ed[2]) * iV);
                 }
                 rho1 = rho2;
                 I1 = I2;
@@ -1046,8 +1063,9 @@ static void phase_node_remap(orc_ctx *x)
             double nzh = (double)((j < NZ) + (j > 0));
             double Vd = (aE * hdz + aW * hdz) * nzh;
             double den = dmax(dmax(m1, min_), M_REMAP_FLOOR * x->rho_ref * Vd);
-            double v1r = vLr + nr / den;
-            double v1z = vLz + nz / den;
+            double iden = 1.0 / den;
+            double v1r = vLr + nr * iden;
+            double v1z = vLz + nz * iden;
             /* kinetic energy the donor-cell mixing destroyed, in shift-invariant
              * form (exactly zero for a uniform field, >= 0 by Cauchy-Schwarz),
              * returned as specific heat to the surrounding cells by mass */
@@ -1059,7 +1077,7 @@ static void phase_node_remap(orc_ctx *x)
                     kin += fabs(FD[q]) * (ar * ar + az * az);
                 }
             }
-            double dKE = 0.5 * (kin - (nr * nr + nz * nz) / den);
+            double dKE = 0.5 * (kin - (nr * nr + nz * nz) * iden);
             double Mn = 0.0;
             for (int q = 0; q < 4; q++) {
                 if (qi[q] < 0 || qi[q] >= NR || qj[q] < 0 || qj[q] >= NZ) continue;
@@ -1072,15 +1090,16 @@ static void phase_node_remap(orc_ctx *x)
                 double mt = dmax(m1, M_ACC_EPS * x->rho_ref * Vd);
                 double pr = x->phi2b_r[n] + x->phi2r_r[n];
                 double pz = x->phi2b_z[n] + x->phi2r_z[n];
-                double v2r = v1r - dt * (dsum * v1r + (pr * Vd) / mt);
-                double v2z = v1z - dt * (dsum * v1z + (pz * Vd) / mt);
+                double imt = 1.0 / mt, iVd = 1.0 / Vd;
+                double v2r = v1r - dt * (dsum * v1r + (pr * Vd) * imt);
+                double v2z = v1z - dt * (dsum * v1z + (pz * Vd) * imt);
                 if (db > 0.0) {
-                    x->phi2b_r[n] = x->phi2b_r[n] + db * ((FD[1] * upr[1] - FD[0] * upr[0]) / Vd);
-                    x->phi2b_z[n] = x->phi2b_z[n] + db * ((FD[1] * upz[1] - FD[0] * upz[0]) / Vd);
+                    x->phi2b_r[n] = x->phi2b_r[n] + db * ((FD[1] * upr[1] - FD[0] * upr[0]) * iVd);
+                    x->phi2b_z[n] = x->phi2b_z[n] + db * ((FD[1] * upz[1] - FD[0] * upz[0]) * iVd);
                 }
                 if (drr > 0.0) {
-                    x->phi2r_r[n] = x->phi2r_r[n] + drr * ((FD[3] * upr[3] - FD[2] * upr[2]) / Vd);
-                    x->phi2r_z[n] = x->phi2r_z[n] + drr * ((FD[3] * upz[3] - FD[2] * upz[2]) / Vd);
+                    x->phi2r_r[n] = x->phi2r_r[n] + drr * ((FD[3] * upr[3] - FD[2] * upr[2]) * iVd);
+                    x->phi2r_z[n] = x->phi2r_z[n] + drr * ((FD[3] * upz[3] - FD[2] * upz[2]) * iVd);
                 }
                 v1r = v2r;
                 v1z = v2z;

@@ -174,8 +174,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
 #pragma unroll
       for (int m = 0; m < kMaxMat; m++) f[m] = m < g.nmat ? (T)S.f[m][c] : T(0);
       rh = S.rho[c];
-      T phi, den, rm;
-      matter(g, (T)rh, f, phi, den, rm);
+      T phi, iden, rm;
+      matter(g, (T)rh, f, phi, iden, rm);
       T p = ((const T*)S.eos[0])[c], c2 = ((const T*)S.eos[1])[c], sx = ((const T*)S.eos[4])[c];
       T vr4[4] = {Sv0[nidx(g, i, j)], Sv0[nidx(g, i + 1, j)], Sv0[nidx(g, i, j + 1)], Sv0[nidx(g, i + 1, j + 1)]};
       T vz4[4] = {Sv1[nidx(g, i, j)], Sv1[nidx(g, i + 1, j)], Sv1[nidx(g, i, j + 1)], Sv1[nidx(g, i + 1, j + 1)]};
@@ -183,7 +183,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       T L = tmin(dr, dz);
       T dDn = dtT * kn.D;
       T Jn = T(1) + dDn;
-      T Dm = Jn < T(1) ? N::div(Vol<T>::closing(Jn, dDn, phi, sx), dtT) : T(0);
+      T Dm = Jn < T(1) ? Vol<T>::closing(Jn, dDn, phi, sx) * N::div(T(1), dtT) : T(0);
       T Ld = L * Dm;
       T Q = rm * (GT::q_quad(g) * Ld * Ld + GT::q_lin(g) * N::sqr(c2) * Ld);
       T P = p + Q;
@@ -255,16 +255,18 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         psz = (T)(bz + rz);
       }
       T Fer = Fr - Vd * psr, Fez = Fz - Vd * psz;
-      vLr = Sv0[n] + dtT * N::div(Fer, mt);
-      vLz = Sv1[n] + dtT * N::div(Fez, mt);
-      if (owns_node(i, j)) {
+      T imt = N::div(T(1), mt);
+      vLr = Sv0[n] + dtT * (Fer * imt);
+      vLz = Sv1[n] + dtT * (Fez * imt);
+      if (owns_node(i, j) && (db > 0.0 || drr > 0.0)) {
+        T iVd = N::div(T(1), Vd);
         if (db > 0.0) {
-          pn.b_psi1r[kb] = po.b_psi1r[kb] - dt * db * (double)N::div(Frr, Vd);
-          pn.b_psi1z[kb] = po.b_psi1z[kb] - dt * db * (double)N::div(Fzr, Vd);
+          pn.b_psi1r[kb] = po.b_psi1r[kb] - dt * db * (double)(Frr * iVd);
+          pn.b_psi1z[kb] = po.b_psi1z[kb] - dt * db * (double)(Fzr * iVd);
         }
         if (drr > 0.0) {
-          pn.r_psi1r[kr] = po.r_psi1r[kr] - dt * drr * (double)N::div(Frz, Vd);
-          pn.r_psi1z[kr] = po.r_psi1z[kr] - dt * drr * (double)N::div(Fzz, Vd);
+          pn.r_psi1r[kr] = po.r_psi1r[kr] - dt * drr * (double)(Frz * iVd);
+          pn.r_psi1z[kr] = po.r_psi1z[kr] - dt * drr * (double)(Fzz * iVd);
         }
       }
       if (i == 0 || i == g.NR) vLr = T(0);
@@ -326,7 +328,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       T srr = s0rr, szz = s0zz, srz = s0rz;
       if (g.any_strength) {
         T G = ((const T*)S.eos[2])[c], Y = ((const T*)S.eos[3])[c];
-        T tr3 = N::div((kn.err + kn.ezz) + kn.ett, T(3));
+        T tr3 = ((kn.err + kn.ezz) + kn.ett) * T(1.0 / 3.0);
         T om = kn.om;
         T dsrr = T(2) * G * (kn.err - tr3) + T(2) * om * srz;
         T dszz = T(2) * G * (kn.ezz - tr3) - T(2) * om * srz;
@@ -351,8 +353,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       double rho = S.rho[c];
       double f0n = S.f[0][c], f1n = g.nmat > 1 ? S.f[1][c] : 0.0;
       T fq[kMaxMat] = {(T)f0n, (T)f1n};
-      T phi, den, rm;
-      matter(g, (T)rho, fq, phi, den, rm);
+      T phi, iden, rm;
+      matter(g, (T)rho, fq, phi, iden, rm);
       T Jm = Vol<T>::ratio(J, dD, phi, ((const T*)S.eos[4])[c]);
       T Wdt = dtT * sde - P * Vol<T>::jm1(J, dD);
       T rden = tmax(rm, GT::rho_ref(g) * T(kRhoDenFloor));
@@ -362,8 +364,9 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       for (int q = 0; q < 4; q++) kd[q] = s_kd[nb[q]];
       T rN0 = (T)i * dr, rC = ((T)i + T(0.5)) * dr, rN1 = (T)(i + 1) * dr;
       T V = cell_volume<T>(g, i);
-      T wW = N::div(Ring<T>::w(g, i) * hdz, V);
-      T wE = N::div(Ring<T>::e(g, i) * hdz, V);
+      T iV = N::div(T(1), V);
+      T wW = (Ring<T>::w(g, i) * hdz) * iV;
+      T wE = (Ring<T>::e(g, i) * hdz) * iV;
       T hL = wW * (kd[0] + kd[2]) + wE * (kd[1] + kd[3]);
       double psi2 = 0.0, db = 0.0, drr = 0.0;
       long long kb = -1, kr = -1;
@@ -452,8 +455,9 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       const int dk[4] = {kC(i - 1, j), kC(i + 1, j), kC(i, j - 1), kC(i, j + 1)};
       const bool inq[4] = {dV[0] > T(0), dV[1] < T(0), dV[2] > T(0), dV[3] < T(0)};
       int kc = kC(i, j);
+      double iV = 1.0 / V;
       double netin = ((F[0] - F[1]) + F[2]) - F[3];
-      rho1 = s_rho[kA(i, j)] + netin / V;
+      rho1 = s_rho[kA(i, j)] + netin * iV;
       double M1 = rho1 * V;
       double min_ = 0.0, nI = 0.0, nsrr = 0.0, nszz = 0.0, nsrz = 0.0, vcut = 0.0;
       double nf0 = 0.0, nf1 = 0.0;
@@ -485,10 +489,11 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       double lam = (double)ct[0 * R::NC + kc];
       double O = (double)(((tmax(-dV[0], T(0)) + tmax(dV[1], T(0))) + tmax(-dV[2], T(0))) + tmax(dV[3], T(0)));
       double den = dmax(dmax(M1, min_), kMRemapFloor * g.rho_ref * V);
-      double I1 = IL + nI / den;
+      double iden = 1.0 / den;
+      double I1 = IL + nI * iden;
       double ex = (1.0 - lam) * O - vcut;
-      double f1a = dmax(fL0 + (nf0 + fL0 * ex) / V, 0.0);
-      double f1b = g.nmat > 1 ? dmax(fL1 + (nf1 + fL1 * ex) / V, 0.0) : 0.0;
+      double f1a = dmax(fL0 + (nf0 + fL0 * ex) * iV, 0.0);
+      double f1b = g.nmat > 1 ? dmax(fL1 + (nf1 + fL1 * ex) * iV, 0.0) : 0.0;
       double fs = g.nmat > 1 ? f1a + f1b : f1a;
       if (g.pml_on) {
         double db = pm.dcz[j], drr = pm.dcr[i];
@@ -505,12 +510,12 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
           if (own) {
             pm.msink[ku] = pm.msink[ku] + V * (rho1 - rho2);
             if (db > 0.0) {
-              pn.b_phi1[kb] = p1b + db * ((F[1] - F[0]) / V);
-              pn.b_phi3[kb] = p3b + db * ((ed[1] - ed[0]) / V);
+              pn.b_phi1[kb] = p1b + db * ((F[1] - F[0]) * iV);
+              pn.b_phi3[kb] = p3b + db * ((ed[1] - ed[0]) * iV);
             }
             if (drr > 0.0) {
-              pn.r_phi1[kr] = p1r + drr * ((F[3] - F[2]) / V);
-              pn.r_phi3[kr] = p3r + drr * ((ed[3] - ed[2]) / V);
+              pn.r_phi1[kr] = p1r + drr * ((F[3] - F[2]) * iV);
+              pn.r_phi3[kr] = p3r + drr * ((ed[3] - ed[2]) * iV);
             }
           }
           rho1 = rho2;
@@ -520,11 +525,12 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       if (own) {
         long long c = cidx(g, i, j);
         D.rho[c] = rho1;
-        double fa = f1a / dmax(fs, 1.0);
-        double fb = f1b / dmax(fs, 1.0);
+        double ifs = 1.0 / dmax(fs, 1.0);
+        double fa = f1a * ifs;
+        double fb = f1b * ifs;
         D.f[0][c] = fa;
         if (g.nmat > 1) D.f[1][c] = fb;
-        T s0n = (T)(sL0 + nsrr / den), s1n = (T)(sL1 + nszz / den), s2n = (T)(sL2 + nsrz / den);
+        T s0n = (T)(sL0 + nsrr * iden), s1n = (T)(sL1 + nszz * iden), s2n = (T)(sL2 + nsrz * iden);
         if (g.any_strength) {
           ((T*)D.s[0])[c] = s0n;
           ((T*)D.s[1])[c] = s1n;
@@ -603,8 +609,9 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     double nzh = (double)((j < g.NZ) + (j > 0));
     double Vd = (aE * hdzd + aW * hdzd) * nzh;
     double den = dmax(dmax(m1, min_), kMRemapFloor * g.rho_ref * Vd);
-    double v1r = (double)vLr + nr / den;
-    double v1z = (double)vLz + nz / den;
+    double iden = 1.0 / den;
+    double v1r = (double)vLr + nr * iden;
+    double v1z = (double)vLz + nz * iden;
 #pragma unroll
     for (int q = 0; q < 4; q++) {
       if (inq[q] && ok[q]) {
@@ -612,7 +619,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         kin += fabs(FD[q]) * (double)(ar * ar + az * az);
       }
     }
-    double dKE = 0.5 * (kin - (nr * nr + nz * nz) / den);
+    double dKE = 0.5 * (kin - (nr * nr + nz * nz) * iden);
     double Mn = 0.0;
 #pragma unroll
     for (int q = 0; q < 4; q++)
@@ -629,16 +636,17 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         double bpr = kb >= 0 ? po.b_phi2r[kb] : 0.0, bpz = kb >= 0 ? po.b_phi2z[kb] : 0.0;
         double rpr = kr >= 0 ? po.r_phi2r[kr] : 0.0, rpz = kr >= 0 ? po.r_phi2z[kr] : 0.0;
         double pr = bpr + rpr, pz = bpz + rpz;
-        double v2r = v1r - dt * (dsum * v1r + (pr * Vd) / mt);
-        double v2z = v1z - dt * (dsum * v1z + (pz * Vd) / mt);
+        double imt = 1.0 / mt, iVd = 1.0 / Vd;
+        double v2r = v1r - dt * (dsum * v1r + (pr * Vd) * imt);
+        double v2z = v1z - dt * (dsum * v1z + (pz * Vd) * imt);
         if (own) {
           if (db > 0.0) {
-            pn.b_phi2r[kb] = bpr + db * ((FD[1] * (double)upr[1] - FD[0] * (double)upr[0]) / Vd);
-            pn.b_phi2z[kb] = bpz + db * ((FD[1] * (double)upz[1] - FD[0] * (double)upz[0]) / Vd);
+            pn.b_phi2r[kb] = bpr + db * ((FD[1] * (double)upr[1] - FD[0] * (double)upr[0]) * iVd);
+            pn.b_phi2z[kb] = bpz + db * ((FD[1] * (double)upz[1] - FD[0] * (double)upz[0]) * iVd);
           }
           if (drr > 0.0) {
-            pn.r_phi2r[kr] = rpr + drr * ((FD[3] * (double)upr[3] - FD[2] * (double)upr[2]) / Vd);
-            pn.r_phi2z[kr] = rpz + drr * ((FD[3] * (double)upz[3] - FD[2] * (double)upz[2]) / Vd);
+            pn.r_phi2r[kr] = rpr + drr * ((FD[3] * (double)upr[3] - FD[2] * (double)upr[2]) * iVd);
+            pn.r_phi2z[kr] = rpz + drr * ((FD[3] * (double)upz[3] - FD[2] * (double)upz[2]) * iVd);
           }
         }
         v1r = v2r;

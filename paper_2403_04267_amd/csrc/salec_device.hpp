@@ -37,6 +37,7 @@ struct MatT {
   T gfac;         // shear / bulk modulus ratio (0: no strength)
   T Y0, mu_f, Ylim;
   T pcav;         // cavitation pressure ramp
+  T irho0, Ar, idE, iYd;  // 1/rho0, A/rho0, 1/(Ecv - Eiv), 1/(Ylim - Y0)
   int strength, pad;
 };
 using MatC = MatT<double>;
@@ -205,15 +206,16 @@ template <class T> __device__ __forceinline__ T tmin(T a, T b) { return a < b ? 
 // most of their digits in weak waves.
 template <class T>
 struct Dens {
-  T r, eta, mu, z;
+  T r, ir, eta, mu, z;
 };
 __device__ __forceinline__ Dens<double> dens_terms(const MatC& m, double rho, double*) {
   Dens<double> d;
   double rf = m.rho0 * kRhoEosFloor;
   d.r = rho > rf ? rho : rf;
-  d.eta = d.r / m.rho0;
+  d.ir = 1.0 / d.r;
+  d.eta = d.r / m.rho0;  // a true division: eta = 1 exactly at rho0
   d.mu = d.eta - 1.0;
-  d.z = 1.0 / d.eta - 1.0;
+  d.z = m.rho0 * d.ir - 1.0;
   return d;
 }
 __device__ __forceinline__ Dens<float> dens_terms(const MatC& m, double rho, float*) {
@@ -222,6 +224,7 @@ __device__ __forceinline__ Dens<float> dens_terms(const MatC& m, double rho, flo
   double r = rho > rf ? rho : rf;
   double eta = r / m.rho0;
   d.r = (float)r;
+  d.ir = Num<float>::div(1.0f, d.r);
   d.eta = (float)eta;
   d.mu = (float)((r - m.rho0) / m.rho0);
   d.z = (float)((m.rho0 - r) / r);
@@ -233,14 +236,14 @@ __device__ __forceinline__ Dens<float> dens_terms(const MatC& m, double rho, flo
 template <class T>
 __device__ inline void tillotson(const MatT<T>& m, const Dens<T>& d, T e, T& p_out, T& c2_out) {
   using N = Num<T>;
-  const T r = d.r, eta = d.eta, mu = d.mu;
+  const T r = d.r, eta = d.eta, mu = d.mu, ir = d.ir;
+  const T irr = ir * ir;
   T E = e > T(0) ? e : T(0);
   T w = N::div(E, m.E0 * eta * eta) + T(1);
-  T bw = N::div(m.b, w);
-  T ww = N::div(w - T(1), w * w);
-  T pc = (m.a + bw) * r * E + m.A * mu + m.B * mu * mu;
-  T pc_E = r * (m.a + bw - N::div(m.b * (w - T(1)), w * w));
-  T pc_r = (m.a + bw) * E + N::div(T(2) * m.b * E * (w - T(1)), w * w) + N::div(m.A + T(2) * m.B * mu, m.rho0);
+  T iw = N::div(T(1), w), iw2 = iw * iw;
+  T pc = (m.a + m.b * iw) * r * E + m.A * mu + m.B * mu * mu;
+  T pc_E = r * (m.a + m.b * iw - m.b * (w - T(1)) * iw2);
+  T pc_r = (m.a + m.b * iw) * E + T(2) * m.b * E * (w - T(1)) * iw2 + (m.A + T(2) * m.B * mu) * m.irho0;
   T p, dpdE, dpdr;
   if (r >= m.rho0 || E <= m.Eiv) {
     p = pc;
@@ -250,26 +253,24 @@ __device__ inline void tillotson(const MatT<T>& m, const Dens<T>& d, T e, T& p_o
     T z = d.z;
     T ea = N::ex(-m.alpha * z * z);
     T eb = N::ex(-m.beta * z);
-    T rr = r * r;
-    T pe = m.a * r * E + (N::div(m.b * r * E, w) + m.A * mu * eb) * ea;
-    T pe_E = m.a * r + ea * m.b * r * (N::div(T(1), w) - ww);
+    T pe = m.a * r * E + (m.b * r * E * iw + m.A * mu * eb) * ea;
+    T pe_E = m.a * r + ea * m.b * r * (iw - (w - T(1)) * iw2);
     T pe_r = m.a * E +
-             ea * (N::div(m.b * E, w) + N::div(T(2) * m.b * E * (w - T(1)), w * w) + N::div(m.A, m.rho0) * eb +
-                   N::div(m.A * mu * m.beta * eb * m.rho0, rr)) +
-             N::div((N::div(m.b * r * E, w) + m.A * mu * eb) * ea * T(2) * m.alpha * z * m.rho0, rr);
+             ea * (m.b * E * iw + T(2) * m.b * E * (w - T(1)) * iw2 + m.Ar * eb + m.A * mu * m.beta * eb * m.rho0 * irr) +
+             (m.b * r * E * iw + m.A * mu * eb) * ea * T(2) * m.alpha * z * m.rho0 * irr;
     if (E >= m.Ecv) {
       p = pe;
       dpdE = pe_E;
       dpdr = pe_r;
     } else {
-      T x = N::div(E - m.Eiv, m.Ecv - m.Eiv);
+      T x = (E - m.Eiv) * m.idE;
       p = x * pe + (T(1) - x) * pc;
-      dpdE = x * pe_E + (T(1) - x) * pc_E + N::div(pe - pc, m.Ecv - m.Eiv);
+      dpdE = x * pe_E + (T(1) - x) * pc_E + (pe - pc) * m.idE;
       dpdr = x * pe_r + (T(1) - x) * pc_r;
     }
   }
   p_out = p;
-  c2_out = dpdr + N::div(p, r * r) * dpdE;
+  c2_out = dpdr + p * irr * dpdE;
 }
 
 // intact-rock yield curve (Table 1 parameters)
@@ -278,7 +279,7 @@ __device__ inline T yield_strength(const MatT<T>& m, T p) {
   if (!m.strength) return T(0);
   if (p >= T(0)) {
     T mp = m.mu_f * p;
-    return m.Y0 + Num<T>::div(mp, T(1) + Num<T>::div(mp, m.Ylim - m.Y0));
+    return m.Y0 + Num<T>::div(mp, T(1) + mp * m.iYd);
   }
   return tmax(T(0), m.Y0 + m.mu_f * p);
 }
@@ -287,7 +288,7 @@ __device__ inline T yield_strength(const MatT<T>& m, T p) {
 template <class T>
 __device__ inline T softening(const MatT<T>& m, T e) {
   T E = e > T(0) ? e : T(0);
-  return tmin(tmax(Num<T>::div(m.Ecv - E, m.Ecv - m.Eiv), T(0)), T(1));
+  return tmin(tmax((m.Ecv - E) * m.idE, T(0)), T(1));
 }
 
 template <class T>
@@ -297,13 +298,14 @@ struct Mix {
 
 // volume fraction of matter and the shared material density of a mixed cell
 template <class T>
-__device__ __forceinline__ void matter(const Geo& g, T rho, const T* f, T& phi, T& den, T& rm) {
+__device__ __forceinline__ void matter(const Geo& g, T rho, const T* f, T& phi, T& iden, T& rm) {
   phi = T(0);
 #pragma unroll
   for (int m = 0; m < kMaxMat; m++)
     if (m < g.nmat) phi += f[m];
-  den = phi > T(kPhiEps) ? phi : T(kPhiEps);
-  rm = Num<T>::div(rho, den);
+  T den = phi > T(kPhiEps) ? phi : T(kPhiEps);
+  iden = Num<T>::div(T(1), den);
+  rm = rho * iden;
 }
 
 // Mixed-cell state from the FP64 cell state (rho, I, f): all materials
@@ -317,14 +319,14 @@ __device__ inline Mix<T> mixture(const Geo& g, double rho, double I, const doubl
   T f[kMaxMat];
 #pragma unroll
   for (int m = 0; m < kMaxMat; m++) f[m] = m < g.nmat ? (T)fd[m] : T(0);
-  T phi, den, rm;
-  matter(g, (T)rho, f, phi, den, rm);
+  T phi, iden, rm;
+  matter(g, (T)rho, f, phi, iden, rm);
   // material density for the density terms, in FP64
   double phid = 0.0;
 #pragma unroll
   for (int m = 0; m < kMaxMat; m++)
     if (m < g.nmat) phid += fd[m];
-  double rmd = rho / (phid > kPhiEps ? phid : kPhiEps);
+  double rmd = rho * (1.0 / (phid > kPhiEps ? phid : kPhiEps));
   T Ie = (T)I;
   T p = T(0), c2 = T(0), G = T(0);
   T wm[kMaxMat], pmv[kMaxMat], c2v[kMaxMat], sov[kMaxMat];
@@ -332,7 +334,7 @@ __device__ inline Mix<T> mixture(const Geo& g, double rho, double I, const doubl
   for (int m = 0; m < kMaxMat; m++) {
     if (m >= g.nmat) break;
     const MatT<T>& M = GeoT<T>::mat(g, m);
-    wm[m] = N::div(f[m], den);
+    wm[m] = f[m] * iden;
     if (m > 0 && g.same_mat) {
       // identical constants and inputs give identical results
       pmv[m] = pmv[0];
@@ -456,14 +458,15 @@ __device__ inline Kin<T> kinematics(const Geo& g, int i, const T vr[4], const T 
   T Ur_e = Are * ur_e;
   T Uz_s = aw * vz[0] + ae * vz[1];
   T Uz_n = aw * vz[2] + ae * vz[3];
-  k.Dr = N::div(Ur_e - Ur_w, V);
-  k.Dz = N::div(Uz_n - Uz_s, V);
-  k.D = N::div((Ur_e - Ur_w) + (Uz_n - Uz_s), V);
-  k.err = N::div(ur_e - ur_w, dr);
+  T iV = N::div(T(1), V), irc = N::div(T(1), rc), idr = N::div(T(1), dr);
+  k.Dr = (Ur_e - Ur_w) * iV;
+  k.Dz = (Uz_n - Uz_s) * iV;
+  k.D = ((Ur_e - Ur_w) + (Uz_n - Uz_s)) * iV;
+  k.err = (ur_e - ur_w) * idr;
   k.ezz = k.Dz;
-  k.ett = N::div(T(0.5) * (ur_w + ur_e), rc);
-  k.dvr_dz = N::div((aw * vr[2] + ae * vr[3]) - (aw * vr[0] + ae * vr[1]), V);
-  k.dvz_dr = N::div(T(0.5) * (vz[1] + vz[3]) - T(0.5) * (vz[0] + vz[2]), dr);
+  k.ett = (T(0.5) * (ur_w + ur_e)) * irc;
+  k.dvr_dz = ((aw * vr[2] + ae * vr[3]) - (aw * vr[0] + ae * vr[1])) * iV;
+  k.dvz_dr = (T(0.5) * (vz[1] + vz[3]) - T(0.5) * (vz[0] + vz[2])) * idr;
   k.erz = T(0.5) * (k.dvr_dz + k.dvz_dr);
   k.om = T(0.5) * (k.dvr_dz - k.dvz_dr);
   return k;

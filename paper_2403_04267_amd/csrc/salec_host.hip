@@ -214,6 +214,11 @@ void fill_mat(MatT<T>& c, const salec_material& M) {
   c.mu_f = (T)M.mu_f;
   c.Ylim = (T)M.Ylim;
   c.pcav = (T)(kPcavFrac * M.A);
+  // reciprocals, formed in FP64 exactly as the reference algorithm forms them
+  c.irho0 = (T)(1.0 / M.rho0);
+  c.Ar = (T)(M.A / M.rho0);
+  c.idE = (T)(1.0 / (M.Ecv - M.Eiv));
+  c.iYd = (T)(M.strength && M.Ylim != M.Y0 ? 1.0 / (M.Ylim - M.Y0) : 0.0);
 }
 
 Geo make_geo(const salec_grid* gr, const salec_material* mats, const salec_pml* pml) {
