@@ -207,10 +207,12 @@ int salec_last_step_ms(salec_ctx *ctx, double *ms);
 /* Launch schedules. Every tile shape computes bit-identical results, so the
  * schedule only changes speed. salec_set_schedule() selects a shape and a
  * workgroup count (grid 0: one workgroup per tile; otherwise that many
- * workgroups walk the tiles). salec_tune() times each shape over `cycles`
- * real cycles of the run (after one warm-up cycle each: the members advance
- * by (cycles + 1) * salec_num_variants() cycles), keeps the fastest and
- * reports it in out (may be NULL). */
+ * workgroups walk the tiles). salec_tune() times each shape, with one
+ * workgroup per tile and with as many workgroups as fit on the device at
+ * once, over `cycles` real cycles of the run after one warm-up cycle each
+ * (the members advance by (cycles + 1) cycles per candidate, at most
+ * 2 * salec_num_variants() candidates), keeps the fastest and reports it in
+ * out (may be NULL). */
 int32_t salec_num_variants(void);
 int salec_get_schedule(const salec_ctx *ctx, salec_schedule *out);
 int salec_set_schedule(salec_ctx *ctx, int32_t variant, int32_t grid);

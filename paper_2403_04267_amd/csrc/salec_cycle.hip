@@ -24,27 +24,43 @@ hipError_t launch_cycle(int v, int prec, const Inst* insts, const TileRef* sched
   return hipGetLastError();
 }
 
-// End of a cycle, one workgroup (one wave) per instance: the Courant minimum
-// over the instance's tiles, then time, cycle count, next step (growth cap,
-// maximum, stop time) and sticky errors (Sec. 7).
-__global__ __launch_bounds__(64) void k_finalize(const Inst* __restrict__ insts) {
+// End of a cycle, one workgroup per instance: the Courant minimum over the
+// instance's tiles, then time, cycle count, next step (growth cap, maximum,
+// stop time) and sticky errors (Sec. 7). The clock is read while the tile
+// minima load, so the kernel costs about two memory round trips.
+constexpr int kFinalizeThreads = 256;
+
+__global__ __launch_bounds__(kFinalizeThreads) void k_finalize(const Inst* __restrict__ insts) {
   using CInst = const __attribute__((address_space(4))) Inst;
   const Inst& in = *(const Inst*)((CInst*)insts + blockIdx.x);
   Scal* sc = in.sc;
-  if (sc->err) return;
+  const int tid = threadIdx.x;
+  double t0 = 0.0, dt0 = 0.0;
+  unsigned fl = 0;
+  int err = 0;
+  if (tid == 0) {
+    t0 = sc->t;
+    dt0 = sc->dt;
+    fl = sc->flags;
+    err = sc->err;
+  }
   double m = __builtin_huge_val();
-  for (int q = threadIdx.x; q < in.ntiles; q += 64) m = dmin(m, in.dtpart[q]);
+  for (int q = tid; q < in.ntiles; q += kFinalizeThreads) m = dmin(m, in.dtpart[q]);
   for (int off = 32; off > 0; off >>= 1) m = dmin(m, __shfl_down(m, off, 64));
-  if (threadIdx.x != 0) return;
+  __shared__ double part[kFinalizeThreads / 64];
+  if ((tid & 63) == 0) part[tid >> 6] = m;
+  __syncthreads();
+  if (tid != 0 || err) return;
+  for (int q = 1; q < kFinalizeThreads / 64; q++) m = dmin(m, part[q]);
+  m = dmin(m, part[0]);
   const Geo& g = in.g;
-  double t = sc->t + sc->dt;
+  double t = t0 + dt0;
   sc->t = t;
   sc->cycle = sc->cycle + 1;
-  double dtn = dmin(dmin(m, g.dt_grow * sc->dt), g.dt_max);
+  double dtn = dmin(dmin(m, g.dt_grow * dt0), g.dt_max);
   if (g.t_stop > 0) dtn = dmin(dtn, dmax(g.t_stop - t, 0.0));
-  sc->dt_prev = sc->dt;
+  sc->dt_prev = dt0;
   sc->dt = dtn;
-  unsigned fl = sc->flags;
   int e = 0;
   if (fl & kFlagNonFinite) e = -4;
   else if (fl & kFlagNegMass) e = -5;
@@ -57,8 +73,17 @@ __global__ __launch_bounds__(64) void k_finalize(const Inst* __restrict__ insts)
 }
 
 hipError_t launch_finalize(const Inst* insts, int n_inst, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(n_inst), dim3(64), 0, st, insts);
+  hipLaunchKernelGGL(k_finalize, dim3(n_inst), dim3(kFinalizeThreads), 0, st, insts);
   return hipGetLastError();
+}
+
+int resident_groups(int v, int prec) {
+  CycleFn f = prec == 0 ? cycle_kernel_f64(v) : cycle_kernel_f32(v);
+  int per_cu = 0, cus = 0, dev = 0;
+  if (!f || hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)f, kShapes[v][2], 0) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return per_cu * cus;
 }
 
 hipError_t launch_prime(const Inst& in, hipStream_t st) {

@@ -803,18 +803,24 @@ int salec_tune(salec_ctx* x, int32_t cycles, salec_schedule* out) {
   int best_v = x->variant, best_g = x->grid;
   double best = 1e300;
   for (int v = 0; v < n_variants(); v++) {
-    int rc = use_schedule(x, v, 0);
-    if (rc) {
-      x->ready = false;
-      return rc;
-    }
-    if ((rc = salec_step(x, 1))) return rc;
-    if ((rc = salec_step(x, cycles))) return rc;
-    double ms = x->last_ms / cycles;
-    if (ms < best) {
-      best = ms;
-      best_v = v;
-      best_g = 0;
+    // one workgroup per tile, and as many workgroups as fit at once walking
+    // the tiles (when that is fewer than the tiles)
+    int grids[2] = {0, resident_groups(v, x->prec)};
+    for (int gi = 0; gi < 2; gi++) {
+      if (gi == 1 && (grids[1] <= 0 || grids[1] >= x->nsched)) continue;
+      int rc = use_schedule(x, v, grids[gi]);
+      if (rc) {
+        x->ready = false;
+        return rc;
+      }
+      if ((rc = salec_step(x, 1))) return rc;
+      if ((rc = salec_step(x, cycles))) return rc;
+      double ms = x->last_ms / cycles;
+      if (ms < best) {
+        best = ms;
+        best_v = v;
+        best_g = grids[gi];
+      }
     }
   }
   int rc = use_schedule(x, best_v, best_g);

@@ -21,6 +21,8 @@ hipError_t launch_cycle(int v, int prec, const Inst* insts, const TileRef* sched
                         hipStream_t st);
 // end of a cycle: per-instance Courant minimum, clock, errors
 hipError_t launch_finalize(const Inst* insts, int n_inst, hipStream_t st);
+// workgroups of shape v that fit on the device at once (0 if unknown)
+int resident_groups(int v, int prec);
 
 // EoS cache and Courant candidates of the current state (start of a run)
 hipError_t launch_prime_f64(const Inst& in, hipStream_t st);

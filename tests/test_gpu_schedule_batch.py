@@ -109,8 +109,9 @@ def test_tuner_picks_a_schedule_without_changing_results():
     a, b = ctx(members), ctx(members)
     sch = a.tune(2)
     assert 0 <= sch["variant"] < num_variants() and sch["ms_per_cycle"] > 0
-    advanced = 3 * num_variants()
-    assert a.diag(k=0)["cycle"] == advanced
+    # (cycles + 1) per candidate: every shape, some also with a persistent grid
+    advanced = int(a.diag(k=0)["cycle"])
+    assert advanced % 3 == 0 and 3 * num_variants() <= advanced <= 6 * num_variants()
     b.step(advanced)
     a.step(20)
     b.step(20)
