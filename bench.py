@@ -17,10 +17,11 @@ Also measured (the "extensions" object; skipped with --headline-only):
 Each is init + tune + warm-up, then a short timed run.
 
 Prints one JSON line. `roofline` is the cycle kernel's algorithmic HBM
-bytes per launch (state read and written once, PML auxiliaries) over its
-measured average duration, against the 8 TB/s HBM peak; `traffic` is the
-kernel's measured HBM bytes per launch from the committed counter summary,
-or null when the kernel sources changed since it was taken.
+bytes per launch (state read and written once, PML auxiliaries) over the
+measured time per cycle, against the 8 TB/s HBM peak; `traffic` is the
+kernel's measured HBM bytes per launch (committed counter summary) over the
+same time, in GB/s, or null when the kernel sources or the schedule differ
+from those the counters were taken with.
 """
 import argparse
 import glob
@@ -69,16 +70,20 @@ def algorithmic_bytes_per_cell(pb) -> float:
     return state + aux / ncell if pb.pml.enabled else state
 
 
-def traffic_per_launch():
+def traffic_per_launch(schedule):
     """Measured HBM bytes per cycle-kernel launch (FETCH_SIZE + WRITE_SIZE,
     each scaled by the reading for a plain copy of known size), if the
-    summary matches the current kernel sources."""
+    recorded counters were taken from the current kernel sources and the
+    schedule being timed."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
     if rec.get("kernel_sources_sha256") != kernel_sources_sha():
+        return None
+    want = rec.get("schedule", {})
+    if any(schedule.get(k) != v for k, v in want.items()):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -146,7 +151,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--headline-only", action="store_true", help="skip the mixed and batched measurements")
-    ap.add_argument("--tune", type=int, default=2, metavar="K",
+    ap.add_argument("--mixed", action="store_true",
+                    help="time the headline workload in the mixed-precision mode (profiling; not the headline)")
+    ap.add_argument("--tune", type=int, default=5, metavar="K",
                     help="time every tile shape over K cycles during warm-up and keep the fastest (0: off)")
     ap.add_argument("--variant", type=int, default=-1, help="force a tile shape (disables --tune)")
     ap.add_argument("--grid", type=int, default=0, help="workgroups per launch with --variant (0: one per tile)")
@@ -170,23 +177,27 @@ def main():
     from paper_2403_04267_amd import inputs
 
     pb = inputs.config_scale()
+    if args.mixed:
+        pb = pb.replace(precision="mixed")
     t_wall = time.perf_counter()
     value, ms_cycle, sch, ctx = run(pb, args.steps, args.warmup, args.tune, args.variant, args.grid)
     wall = time.perf_counter() - t_wall
     bpc = algorithmic_bytes_per_cell(pb)
     achieved = bpc * pb.grid.ncells / (ms_cycle / 1e3) / 1e9
-    traffic = traffic_per_launch()
+    traffic_b = traffic_per_launch(sch)
+    traffic = traffic_b / (ms_cycle / 1e3) / 1e9 if traffic_b else None
     d = ctx.diag()
     del ctx
     out = {
         "metric": "cell-updates/s", "value": value, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_cycle,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "impact-1050x1050-2mat-strength-pml50-fp64", "cells": pb.grid.ncells,
-                   "cycles": args.steps, "precision": "fp64"},
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if args.mixed else "f64", "data": "synthetic",
+        "config": {"workload": f"impact-1050x1050-2mat-strength-pml50-{pb.precision}", "cells": pb.grid.ncells,
+                   "cycles": args.steps, "precision": pb.precision},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_bytes_per_launch": traffic_b,
                      "kernel": "k_cycle (one launch = one cycle of the whole grid)",
                      "bytes_per_cell_update": bpc},
         "schedule": sch,

@@ -219,15 +219,16 @@ __device__ __forceinline__ Dens<double> dens_terms(const MatC& m, double rho, do
   return d;
 }
 __device__ __forceinline__ Dens<float> dens_terms(const MatC& m, double rho, float*) {
+  // mu from the FP64 density (one FP64 multiply); eta = 1 + mu and
+  // z = 1/eta - 1 = -mu/eta then lose nothing in FP32
   Dens<float> d;
   double rf = m.rho0 * kRhoEosFloor;
   double r = rho > rf ? rho : rf;
-  double eta = r / m.rho0;
   d.r = (float)r;
   d.ir = Num<float>::div(1.0f, d.r);
-  d.eta = (float)eta;
-  d.mu = (float)((r - m.rho0) / m.rho0);
-  d.z = (float)((m.rho0 - r) / r);
+  d.mu = (float)((r - m.rho0) * m.irho0);
+  d.eta = 1.0f + d.mu;
+  d.z = -Num<float>::div(d.mu, d.eta);
   return d;
 }
 
