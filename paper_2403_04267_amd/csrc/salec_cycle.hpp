@@ -443,8 +443,19 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   __syncthreads();
 
   // ------------------------------------------------------------------ E2
+  // (the new density, energy and volume fractions of owned cells reach G,
+  // which uses the same cell-to-thread map, in registers; 1024-thread
+  // workgroups have no registers to spare and G reads them back instead)
   unsigned flags = 0;
-  for (int k = tid; k < R::NE; k += NT) {
+  constexpr int UE = (R::NE + NT - 1) / NT;
+  constexpr bool kCarry = NT < 1024;
+  double eRho[UE], eI[UE], eF0[UE], eF1[UE];
+#pragma unroll
+  for (int u = 0; u < UE; u++) eRho[u] = eI[u] = eF0[u] = eF1[u] = 0.0;
+#pragma unroll 1
+  for (int u = 0; u < UE; u++) {
+    int k = tid + u * NT;
+    if (k >= R::NE) continue;
     int i = i0 - 1 + k % R::EW, j = j0 - 1 + k / R::EW;
     double rho1 = 0.0;
     if (in_cells(g, i, j)) {
@@ -540,8 +551,14 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
           in.mout[i] += F[3];
           in.eout[i] += ed[3];
         }
-        // internal energy before the remap heat, which G adds
-        D.I[c] = I1;
+        if constexpr (kCarry) {
+          reg_put(eRho, u, rho1);
+          reg_put(eI, u, I1);  // before the remap heat, which G adds
+          reg_put(eF0, u, fa);
+          reg_put(eF1, u, fb);
+        } else {
+          D.I[c] = I1;  // before the remap heat, which G adds
+        }
         double chk = rho1 + I1;
         if (g.any_strength) chk += (double)s0n + (double)s1n + (double)s2n;
         chk += fa;
@@ -672,10 +689,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   __syncthreads();
 
   // ------------------------------------------------------------------ G
-  // (the new state of the tile's cells was written in E2 by the same
-  // threads: the cell-to-thread map of the E region)
   double cand = __builtin_huge_val();
-  constexpr int UE = (R::NE + NT - 1) / NT;
 #pragma unroll
   for (int u = 0; u < UE; u++) {
     int k = tid + u * NT;
@@ -685,7 +699,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     long long c = cidx(g, i, j);
     const int nf[4] = {kF(i, j), kF(i + 1, j), kF(i, j + 1), kF(i + 1, j + 1)};
     double h = (heat[nf[0]] + heat[nf[1]]) + (heat[nf[2]] + heat[nf[3]]);
-    double I1 = D.I[c] + h;
+    double I1 = (kCarry ? eI[u] : D.I[c]) + h;
     D.I[c] = I1;
     if (!((I1 - I1) == 0.0)) flags |= kFlagNonFinite;
     T u4 = T(0);
@@ -695,8 +709,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       if (!((sp - sp) == T(0))) flags |= kFlagNonFinite;
       u4 = tmax(u4, sp);
     }
-    double f[kMaxMat] = {D.f[0][c], g.nmat > 1 ? D.f[1][c] : 0.0};
-    Mix<T> mx = mixture<T>(g, D.rho[c], I1, f);
+    double f[kMaxMat] = {kCarry ? eF0[u] : D.f[0][c], kCarry ? eF1[u] : (g.nmat > 1 ? D.f[1][c] : 0.0)};
+    Mix<T> mx = mixture<T>(g, kCarry ? eRho[u] : D.rho[c], I1, f);
     store_eos(D, c, mx);
     cand = dmin(cand, cell_dt(g, mx, u4));
   }
