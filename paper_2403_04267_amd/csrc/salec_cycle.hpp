@@ -392,10 +392,6 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
           pn.r_psi2[kr] = po.r_psi2[kr] - dt * drr * (double)(phi * Wz);
         }
       }
-      // donor outflow limiter: volume leaving through the four faces vs V^L
-      T dW = dv_r(i, j), dE = dv_r(i + 1, j), dS = dv_z(i, j), dN = dv_z(i, j + 1);
-      T O = ((tmax(-dW, T(0)) + tmax(dE, T(0))) + tmax(-dS, T(0))) + tmax(dN, T(0));
-      T VL = V * J;
       oRhoL = rho / (double)J;
       oIL = IL;
       os0 = srr;
@@ -403,7 +399,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       os2 = srz;
       of0 = f0;
       of1 = f1;
-      oLam = O > VL ? N::div(tmax(VL, T(0)), O) : T(1);
+      oLam = J;  // the limiter pass below turns J into lambda
     }
     int kc = kC(i, j);
     cd[0 * R::NC + kc] = oRhoL;
@@ -414,6 +410,22 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     ct[1 * R::NC + kc] = os0;
     ct[2 * R::NC + kc] = os1;
     ct[3 * R::NC + kc] = os2;
+  }
+  // donor outflow limiter (same cells and threads as C, in a pass of its own
+  // to keep C's register peak down): volume leaving through the four faces
+  // vs V^L = V J
+#pragma unroll kUnroll
+  for (int u = 0; u < UA; u++) {
+    int k = tid + u * NT;
+    int i = i0 - 3 + k % R::AW, j = j0 - 3 + k / R::AW;
+    bool inC = k < R::NA && i >= i0 - 2 && i < i0 + TW + 2 && j >= j0 - 2 && j < j0 + TH + 2;
+    if (!inC || !in_cells(g, i, j)) continue;
+    int kc = kC(i, j);
+    T J = ct[0 * R::NC + kc];
+    T dW = dv_r(i, j), dE = dv_r(i + 1, j), dS = dv_z(i, j), dN = dv_z(i, j + 1);
+    T O = ((tmax(-dW, T(0)) + tmax(dE, T(0))) + tmax(-dS, T(0))) + tmax(dN, T(0));
+    T VL = cell_volume<T>(g, i) * J;
+    ct[0 * R::NC + kc] = O > VL ? N::div(tmax(VL, T(0)), O) : T(1);
   }
   __syncthreads();
 
