@@ -144,6 +144,20 @@ def extension(name, problems, steps, warmup, tune, fp64_rate=None):
     return out
 
 
+def pml_payoff():
+    """The PML payoff study: the 100x100 hydrodynamic impact (R = 10 cells,
+    10 km/s) with a 20-cell PML, with plain walls, and on a 1000x1000 domain,
+    each to t = 0.08 s; interior differences against the large domain,
+    crater geometry, cells and device time."""
+    from paper_2403_04267_amd.pml_study import Setup, run
+    t0 = time.perf_counter()
+    r = run(Setup())
+    r["wall_s"] = time.perf_counter() - t0
+    print(f"[bench] pml payoff: pml {r['pml']['err_vs_big']}, bare {r['bare']['err_vs_big']}",
+          file=sys.stderr, flush=True)
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,6 +227,7 @@ def main():
         ext["batched_fp64"] = extension("batched 256 fp64", inputs.ensemble(2403, 256, 200, 800), 40, 2, 1)
         ext["batched_mixed"] = extension("batched 1024 mixed",
                                          inputs.ensemble(4267, 1024, 200, 1200, precision="mixed"), 10, 1, 1)
+        ext["pml_payoff"] = pml_payoff()
         out["extensions"] = ext
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pb)

@@ -1,0 +1,151 @@
+"""What the perfectly matched layer buys (Sec. 4 compares a PML run with an
+unbounded reference): the same vertical impact on
+
+  pml   an n x n domain with a p-cell PML on the right and bottom,
+  bare  the same n x n domain with plain walls (no layer),
+  big   a (k n) x (k n) domain with plain walls, far enough that nothing
+        reflected from its walls reaches the window before the stop time,
+
+each run on the GPU to the same stop time. The n x n window at the top of the
+axis (the pml run's physical region) is compared with the big run: the
+energy of the difference field (kinetic plus linear-acoustic pressure energy
+about the target at rest) per unit impact energy, relative L2 differences of
+density and node momentum, and the crater depth and radius (matter-fraction
+0.5 crossings, as in Sec. 4's profile comparison), next to each run's cells
+and device time.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import inputs
+
+
+@dataclass
+class Setup:
+    n: int = 100            # physical cells per side
+    p: int = 20             # PML cells (right and bottom) of the pml run
+    radius: int = 10        # projectile radius, cells
+    v_imp: float = 10e3     # impact speed, m/s
+    t_end: float = 0.08     # stop time, s
+    big: int = 10           # size factor of the reference domain
+    strength: bool = False
+    precision: str = "fp64"
+
+
+def problems(s: Setup):
+    """The three problems (pml, bare, big) and each one's window rows."""
+    hv = 2 * s.radius + max(4, math.ceil(s.radius / 2))
+    mats = [inputs.basalt(strength=s.strength)]
+
+    def make(n, p, pml_on, name):
+        g = inputs.Grid(n_r=n, n_z=n, pml_r=p, pml_b=p, t_stop=s.t_end)
+        sc = inputs.Scene(surface_j=p + n - hv, radius=float(s.radius), v_imp=s.v_imp)
+        return inputs.Problem(grid=g, mats=mats, pml=inputs.Pml(enabled=pml_on), scene=sc,
+                              precision=s.precision, name=name)
+
+    out = {"pml": make(s.n, s.p, 1, "pml"), "bare": make(s.n, 0, 0, "bare"),
+           "big": make(s.big * s.n, 0, 0, "big")}
+    # rows of the n x n window under the top of each domain
+    rows = {"pml": s.p, "bare": 0, "big": s.big * s.n - s.n}
+    return out, rows
+
+
+def _window(F, r0, n):
+    return {"rho": F["rho"][r0:r0 + n, :n], "p": F["p"][r0:r0 + n, :n], "f": F["f"][:, r0:r0 + n, :n],
+            "v": F["v"][:, r0:r0 + n + 1, :n + 1]}
+
+
+def _rel_l2(a, b):
+    den = float(np.sqrt(np.sum(b * b)))
+    return float(np.sqrt(np.sum((a - b) ** 2))) / den if den > 0 else 0.0
+
+
+def _node_mass(rho, dr, dz):
+    nz, nr = rho.shape
+    M = rho * ((np.arange(nr) + 0.5) * dr * dr * dz)[None, :]
+    out = np.zeros((nz + 1, nr + 1))
+    out[:-1, :-1] += M
+    out[:-1, 1:] += M
+    out[1:, :-1] += M
+    out[1:, 1:] += M
+    return 0.25 * out
+
+
+def _crater(f, surface_row, dr, dz):
+    """Depth below the surface along the axis and radius along the top
+    target row where the matter fraction crosses 0.5."""
+    phi = f.sum(axis=0)
+    col, depth = phi[:, 0], 0.0
+    for j in range(1, col.size):
+        if col[j] < 0.5 <= col[j - 1]:
+            z = (j - 0.5) + (0.5 - col[j - 1]) / (col[j] - col[j - 1])  # centres at (j + 1/2) dz
+            depth = (surface_row - z) * dz
+            break
+    row, radius = phi[surface_row - 1, :], 0.0
+    if row[0] < 0.5:
+        radius = (row.size - 0.5) * dr
+        for i in range(1, row.size):
+            if row[i] >= 0.5 > row[i - 1]:
+                radius = ((i - 0.5) + (0.5 - row[i - 1]) / (row[i] - row[i - 1])) * dr
+                break
+    return depth, radius
+
+
+def run(s: Setup = Setup(), device: str = "cuda:0", chunk: int = 200, max_cycles: int = 20000) -> dict:
+    """Runs the three problems to s.t_end on the GPU and compares them.
+    (The step is clipped so that t lands on t_end; cycles after that have
+    dt = 0 and change nothing.)"""
+    from .salec import Salec
+    probs, rows = problems(s)
+    res, win = {}, {}
+    ke0 = 0.0
+    for key, pb in probs.items():
+        ctx = Salec(pb, device)
+        if key == "big":
+            ke0 = ctx.diag()["ke"]  # impact kinetic energy (per radian)
+        ms, cycles = 0.0, 0
+        while ctx.diag()["t"] < s.t_end * (1.0 - 1e-12) and cycles < max_cycles:
+            ctx.step(chunk)
+            ms += ctx.last_step_ms()
+            cycles += chunk
+        d = ctx.diag()
+        F = ctx.fields()
+        w = _window(F, rows[key], s.n)
+        win[key] = w
+        sj = pb.scene.surface_j - rows[key]
+        depth, radius = _crater(w["f"], sj, pb.grid.dr, pb.grid.dz)
+        res[key] = {"cells": pb.grid.ncells, "cycles": int(d["cycle"]), "t": d["t"], "device_ms": ms,
+                    "crater_depth": depth, "crater_radius": radius}
+        del ctx
+    ref = win["big"]
+    g = probs["pml"].grid
+    mat = probs["pml"].mats[0]
+    rho0, c2 = mat.rho0, mat.A / mat.rho0
+    vol = _node_mass(np.ones((s.n, s.n)), g.dr, g.dz)  # dual volumes of the window's nodes
+    vc = ((np.arange(s.n) + 0.5) * g.dr * g.dr * g.dz)[None, :]
+    mref = _node_mass(ref["rho"], g.dr, g.dz)
+    for key in ("pml", "bare"):
+        w = win[key]
+        m = _node_mass(w["rho"], g.dr, g.dz)
+        # energy of the difference field (linear acoustics about the target at
+        # rest), per unit impact energy: what the walls sent back
+        dv2 = np.sum((w["v"] - ref["v"]) ** 2, axis=0)
+        e_k = 0.5 * rho0 * np.sum(vol * dv2)
+        e_p = np.sum(vc * (w["p"] - ref["p"]) ** 2) / (2.0 * rho0 * c2)
+        res[key]["err_vs_big"] = {
+            "rho": _rel_l2(w["rho"], ref["rho"]),
+            "momentum": _rel_l2(m[None] * w["v"], mref[None] * ref["v"]),
+            "reflected_energy": (e_k + e_p) / ke0,
+        }
+    res["setup"] = {"n": s.n, "p": s.p, "radius": s.radius, "v_imp": s.v_imp, "t_end": s.t_end,
+                    "big": s.big, "strength": s.strength, "precision": s.precision}
+    return res
+
+
+if __name__ == "__main__":
+    import json
+    print(json.dumps(run(), indent=1))
