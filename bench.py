@@ -167,7 +167,7 @@ def main():
     ap.add_argument("--headline-only", action="store_true", help="skip the mixed and batched measurements")
     ap.add_argument("--mixed", action="store_true",
                     help="time the headline workload in the mixed-precision mode (profiling; not the headline)")
-    ap.add_argument("--tune", type=int, default=5, metavar="K",
+    ap.add_argument("--tune", type=int, default=32, metavar="K",
                     help="time every tile shape over K cycles during warm-up and keep the fastest (0: off)")
     ap.add_argument("--variant", type=int, default=-1, help="force a tile shape (disables --tune)")
     ap.add_argument("--grid", type=int, default=0, help="workgroups per launch with --variant (0: one per tile)")

@@ -205,7 +205,9 @@ int salec_diag(salec_ctx *ctx, int32_t instance, salec_diag_t *out);
 int salec_last_step_ms(salec_ctx *ctx, double *ms);
 
 /* Launch schedules. Every tile shape computes bit-identical results, so the
- * schedule only changes speed. salec_set_schedule() selects a shape and a
+ * schedule only changes speed. A new context starts on the shape measured
+ * fastest for its precision on a filled device, with as many workgroups as
+ * fit at once when that is fewer than the tiles. salec_set_schedule() selects a shape and a
  * workgroup count (grid 0: one workgroup per tile; otherwise that many
  * workgroups walk the tiles). salec_tune() times each shape, with one
  * workgroup per tile and with as many workgroups as fit on the device at

@@ -3,10 +3,25 @@
 
 namespace salec {
 
-// must match the order of SALEC_CYCLE_TABLE
-static const int kShapes[][3] = {{64, 16, 512}, {64, 16, 1024}, {32, 32, 1024},
-                                  {64, 15, 768},  {64, 16, 768},  {48, 20, 768},
-                                  {64, 14, 768},  {40, 24, 768}};
+// Tile shapes (cells r x z, threads), in the order of SALEC_CYCLE_TABLE.
+// 768-thread tiles run one workgroup per CU at three waves per SIMD (LDS
+// holds one tile); 512-thread tiles are capped at 128 registers so that two
+// workgroups (four waves per SIMD) share a CU where two tiles fit the LDS
+// (the FP32 instantiation); 256-thread tiles run three to a CU.
+static const int kShapes[][3] = {
+    {64, 14, 768},
+    {40, 16, 512},
+    {32, 20, 512},
+    {64, 15, 768},
+    {64, 16, 768},
+    {48, 20, 768},
+    {40, 24, 768},
+    {28, 18, 512},
+    {64, 16, 1024},
+    {32, 32, 1024},
+    {20, 13, 256}};
+
+int default_variant(int prec) { return prec == 0 ? 0 : 1; }
 
 int n_variants() { return (int)(sizeof(kShapes) / sizeof(kShapes[0])); }
 

@@ -102,7 +102,7 @@ __device__ __forceinline__ void reg_put(T (&a)[N], int u, T v) {
   for (int q = 0; q < N; q++) a[q] = (u == q) ? v : a[q];
 }
 
-template <int TW, int TH, int NT, class T>
+template <int TW, int TH, int NT, int WPE, class T>
 __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_rho, double* s_bigd, T* s_vL,
                                            double* s_Fr, double* s_Fz, double* s_rho1, double* s_min) {
   using R = Regions<TW, TH>;
@@ -157,7 +157,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   // ------------------------------------------------------------------ A
   // 1024-thread workgroups keep the per-cell loops of A and C rolled: four
   // waves per SIMD leave no registers for two cells in flight at once
-  constexpr int kUnroll = NT >= 1024 ? 1 : UA;
+  constexpr int kUnroll = WPE >= 4 ? 1 : UA;
   T rP[UA];
 #pragma unroll
   for (int u = 0; u < UA; u++) rP[u] = T(0);
@@ -460,7 +460,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   // workgroups have no registers to spare and G reads them back instead)
   unsigned flags = 0;
   constexpr int UE = (R::NE + NT - 1) / NT;
-  constexpr bool kCarry = NT < 1024;
+  constexpr bool kCarry = WPE < 4;
   double eRho[UE], eI[UE], eF0[UE], eF1[UE];
 #pragma unroll
   for (int u = 0; u < UE; u++) eRho[u] = eI[u] = eF0[u] = eF1[u] = 0.0;
@@ -731,8 +731,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   if (tid == 0) in.dtpart[tile] = m;
 }
 
-template <int TW, int TH, int NT, class T>
-__global__ __launch_bounds__(NT) void k_cycle(const Inst* __restrict__ insts, const TileRef* __restrict__ sched,
+template <int TW, int TH, int NT, int WPE, class T>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_cycle(const Inst* __restrict__ insts, const TileRef* __restrict__ sched,
                                               int nsched) {
   using R = Regions<TW, TH>;
   using SM = Smem<TW, TH, T>;
@@ -753,7 +753,7 @@ __global__ __launch_bounds__(NT) void k_cycle(const Inst* __restrict__ insts, co
     const TileRef tr{csched[e].inst, csched[e].tile};
     if (tr.inst < 0) continue;
     const Inst* in = (const Inst*)(cinst + tr.inst);
-    tile_cycle<TW, TH, NT, T>(*in, tr.tile, s_rho, s_bigd, s_vL, s_F, s_F + R::NRF, s_rho1, s_min);
+    tile_cycle<TW, TH, NT, WPE, T>(*in, tr.tile, s_rho, s_bigd, s_vL, s_F, s_F + R::NRF, s_rho1, s_min);
     __syncthreads();  // LDS is reused by the next entry
   }
 }
@@ -797,14 +797,17 @@ __global__ void k_prime(Inst in) {
 #define SALEC_CYCLE_TABLE(T, suffix)                                                         \
   CycleFn cycle_kernel_##suffix(int v) {                                                       \
     switch (v) {                                                                               \
-      case 0: return k_cycle<64, 16, 512, T>;                                                  \
-      case 1: return k_cycle<64, 16, 1024, T>;                                                 \
-      case 2: return k_cycle<32, 32, 1024, T>;                                                 \
-      case 3: return k_cycle<64, 15, 768, T>;                                                  \
-      case 4: return k_cycle<64, 16, 768, T>;                                                  \
-      case 5: return k_cycle<48, 20, 768, T>;                                                  \
-      case 6: return k_cycle<64, 14, 768, T>;                                                  \
-      case 7: return k_cycle<40, 24, 768, T>;                                                  \
+      case 0: return k_cycle<64, 14, 768, 3, T>;                                             \
+      case 1: return k_cycle<40, 16, 512, 4, T>;                                             \
+      case 2: return k_cycle<32, 20, 512, 4, T>;                                             \
+      case 3: return k_cycle<64, 15, 768, 3, T>;                                             \
+      case 4: return k_cycle<64, 16, 768, 3, T>;                                             \
+      case 5: return k_cycle<48, 20, 768, 3, T>;                                             \
+      case 6: return k_cycle<40, 24, 768, 3, T>;                                             \
+      case 7: return k_cycle<28, 18, 512, 4, T>;                                             \
+      case 8: return k_cycle<64, 16, 1024, 4, T>;                                            \
+      case 9: return k_cycle<32, 32, 1024, 4, T>;                                            \
+      case 10: return k_cycle<20, 13, 256, 3, T>;                                            \
       default: return nullptr;                                                                 \
     }                                                                                          \
   }                                                                                            \

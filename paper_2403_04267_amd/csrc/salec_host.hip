@@ -499,8 +499,12 @@ int init_common(salec_ctx* x, void* dev_buf, size_t dev_bytes, void* stream) {
     int rc = start_run(x, (int)k);
     if (rc) return rc;
   }
-  int rc = use_schedule(x, 0, 0);
+  // the default shape; a persistent grid when it has fewer workgroups than tiles
+  const int v0 = default_variant(x->prec);
+  int rc = use_schedule(x, v0, 0);
   if (rc) return rc;
+  const int g0 = resident_groups(v0, x->prec);
+  if (g0 > 0 && g0 < x->nsched && (rc = use_schedule(x, v0, g0))) return rc;
   x->ready = true;
   return SALEC_OK;
 }

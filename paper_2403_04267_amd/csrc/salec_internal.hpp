@@ -15,6 +15,8 @@ using CycleFn = void (*)(const Inst*, const TileRef*, int);
 // cycle kernel: tile-shape variants, one instantiation per bulk type
 int n_variants();
 void variant_shape(int v, int* tw, int* th, int* nt);
+// the shape measured fastest on a filled device, per bulk type (0 FP64, 1 FP32)
+int default_variant(int prec);
 CycleFn cycle_kernel_f64(int v);
 CycleFn cycle_kernel_f32(int v);
 hipError_t launch_cycle(int v, int prec, const Inst* insts, const TileRef* sched, int nsched, int grid,
