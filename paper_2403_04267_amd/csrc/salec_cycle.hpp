@@ -146,6 +146,22 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   auto kF = [&](int i, int j) { return (i - i0) + (j - j0) * R::FW; };
   auto kR = [&](int i, int j) { return (i - (i0 - 1)) + (j - (j0 - 1)) * R::RW; };
   auto kZ = [&](int i, int j) { return (i - (i0 - 1)) + (j - (j0 - 1)) * R::ZW; };
+  // Thread maps of the cell loops, row-major with the rows reordered. A and
+  // C share one (A's results stay in registers for C): C's rows first, then
+  // the row below and the row above them that only A covers, so C's loop
+  // over the first AW (AH - 2) entries leaves whole waves idle instead of
+  // masking lanes. E2 and G share another: the tile's rows first, then E2's
+  // rows below and above it.
+  auto a_cell = [&](int k, int& i, int& j) {
+    int q = k / R::AW;
+    i = i0 - 3 + (k - q * R::AW);
+    j = q < R::AH - 2 ? j0 - 2 + q : (q == R::AH - 2 ? j0 - 3 : j0 + TH + 2);
+  };
+  auto e_cell = [&](int k, int& i, int& j) {
+    int q = k / R::EW;
+    i = i0 - 1 + (k - q * R::EW);
+    j = q < TH ? j0 + q : (q == TH ? j0 - 1 : j0 + TH);
+  };
   T* sig = (T*)s_bigd;                // [4][NA] during A..B
   double* cd = s_bigd;                // [4][NC] rhoL, IL, f0, f1 during C..E2
   T* ct = (T*)(s_bigd + 4 * R::NC);   // [4][NC] lambda, sL x3 during C..E2
@@ -165,7 +181,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   for (int u = 0; u < UA; u++) {
     int k = tid + u * NT;
     if (k >= R::NA) continue;
-    int i = i0 - 3 + k % R::AW, j = j0 - 3 + k / R::AW;
+    int i, j;
+    a_cell(k, i, j);
     T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
     double rh = 0.0;
     if (in_cells(g, i, j)) {
@@ -200,11 +217,12 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       s3 = phi * srz;
       reg_put(rP, u, P);
     }
-    sig[0 * R::NA + k] = s0;
-    sig[1 * R::NA + k] = s1;
-    sig[2 * R::NA + k] = s2;
-    sig[3 * R::NA + k] = s3;
-    s_rho[k] = rh;
+    const int ka = kA(i, j);
+    sig[0 * R::NA + ka] = s0;
+    sig[1 * R::NA + ka] = s1;
+    sig[2 * R::NA + ka] = s2;
+    sig[3 * R::NA + ka] = s3;
+    s_rho[ka] = rh;
   }
   __syncthreads();
 
@@ -303,9 +321,10 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
 #pragma unroll kUnroll
   for (int u = 0; u < UA; u++) {
     int k = tid + u * NT;
-    int i = i0 - 3 + k % R::AW, j = j0 - 3 + k / R::AW;
-    bool inC = k < R::NA && i >= i0 - 2 && i < i0 + TW + 2 && j >= j0 - 2 && j < j0 + TH + 2;
-    if (!inC) continue;
+    if (k >= (R::AH - 2) * R::AW) continue;
+    int i, j;
+    a_cell(k, i, j);
+    if (i < i0 - 2 || i >= i0 + TW + 2) continue;
     // outside the grid: a void donor (rho^L = 0, lambda = 1, zero state)
     double oRhoL = 0.0, oIL = 0.0, of0 = 0.0, of1 = 0.0;
     T oLam = T(1), os0 = T(0), os1 = T(0), os2 = T(0);
@@ -417,9 +436,10 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
 #pragma unroll kUnroll
   for (int u = 0; u < UA; u++) {
     int k = tid + u * NT;
-    int i = i0 - 3 + k % R::AW, j = j0 - 3 + k / R::AW;
-    bool inC = k < R::NA && i >= i0 - 2 && i < i0 + TW + 2 && j >= j0 - 2 && j < j0 + TH + 2;
-    if (!inC || !in_cells(g, i, j)) continue;
+    if (k >= (R::AH - 2) * R::AW) continue;
+    int i, j;
+    a_cell(k, i, j);
+    if (i < i0 - 2 || i >= i0 + TW + 2 || !in_cells(g, i, j)) continue;
     int kc = kC(i, j);
     T J = ct[0 * R::NC + kc];
     T dW = dv_r(i, j), dE = dv_r(i + 1, j), dS = dv_z(i, j), dN = dv_z(i, j + 1);
@@ -468,7 +488,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   for (int u = 0; u < UE; u++) {
     int k = tid + u * NT;
     if (k >= R::NE) continue;
-    int i = i0 - 1 + k % R::EW, j = j0 - 1 + k / R::EW;
+    int i, j;
+    e_cell(k, i, j);
     double rho1 = 0.0;
     if (in_cells(g, i, j)) {
       bool own = owns_cell(i, j);
@@ -579,7 +600,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         if (rho1 < -kNegMassTol * g.rho_ref) flags |= kFlagNegMass;
       }
     }
-    s_rho1[k] = rho1;
+    s_rho1[kE(i, j)] = rho1;
   }
   __syncthreads();
 
@@ -705,8 +726,9 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
 #pragma unroll
   for (int u = 0; u < UE; u++) {
     int k = tid + u * NT;
-    if (k >= R::NE) continue;
-    int i = i0 - 1 + k % R::EW, j = j0 - 1 + k / R::EW;
+    if (k >= TH * R::EW) continue;
+    int i, j;
+    e_cell(k, i, j);
     if (!owns_cell(i, j)) continue;
     long long c = cidx(g, i, j);
     const int nf[4] = {kF(i, j), kF(i + 1, j), kF(i, j + 1), kF(i + 1, j + 1)};
