@@ -7,18 +7,25 @@ the whole grid (one launch of the cycle kernel). The tile shape is chosen by
 the library's tuner during warm-up; W warm-up cycles, then K timed cycles
 bracketed by stream synchronisation, inputs resident in HBM throughout. The
 device time comes from HIP events the library records on its own stream
-around the replayed graphs.
+around the replayed graphs (the timed cycles run as 5 consecutive calls; the
+median call is reported beside the total). Right after them, the cycle
+kernel's own mean duration is measured over further cycles launched between
+HIP events; the roofline uses it.
 
 Also measured (the "extensions" object; skipped with --headline-only):
   mixed_scale    the same workload in the mixed-precision mode
   mixed_large    4000 x 4000 + 100 PML (4100^2 cells), mixed precision
   batched_fp64   256 seeded uneven impacts (sides 200-800), plain FP64
   batched_mixed  1024 seeded uneven impacts (sides 200-1200), mixed
-Each is init + tune + warm-up, then a short timed run.
+  pml_payoff     the same small impact with a PML, with plain walls and on a
+                 10x larger domain, each to the same time (interior error,
+                 reflected energy, crater geometry, device time)
+Each of the first four is init + tune + warm-up, then a short timed run.
 
 Prints one JSON line. `roofline` is the cycle kernel's algorithmic HBM
 bytes per launch (state read and written once, PML auxiliaries) over the
-measured time per cycle, against the 8 TB/s HBM peak; `traffic` is the
+cycle kernel's mean duration, against the 8 TB/s HBM peak and against the
+device-to-device copy rate measured in the same run; `traffic` is the
 kernel's measured HBM bytes per launch (committed counter summary) over the
 same time, in GB/s, or null when the kernel sources or the schedule differ
 from those the counters were taken with.
@@ -77,15 +84,15 @@ def traffic_per_launch(schedule):
     schedule being timed."""
     try:
         with open(TRAFFIC_FILE) as fh:
-            rec = json.load(fh)
-    except (OSError, ValueError):
+            recs = json.load(fh).get("records", [])
+    except (OSError, ValueError, AttributeError):
         return None
-    if rec.get("kernel_sources_sha256") != kernel_sources_sha():
-        return None
-    want = rec.get("schedule", {})
-    if any(schedule.get(k) != v for k, v in want.items()):
-        return None
-    return rec.get("hbm_bytes_per_launch")
+    sha = kernel_sources_sha()
+    for rec in recs:
+        want = rec.get("schedule", {})
+        if rec.get("kernel_sources_sha256") == sha and all(schedule.get(k) == v for k, v in want.items()):
+            return rec.get("hbm_bytes_per_launch")
+    return None
 
 
 def cpu_baseline(pb, budget_s=12.0):
@@ -106,9 +113,31 @@ def cpu_baseline(pb, budget_s=12.0):
                       f"({el:.1f} s of CPU time)"}
 
 
-def run(problems, steps, warmup, tune, variant=-1, grid=0):
-    """Times `steps` cycles of a context; returns (cell-updates/s, ms per
-    cycle, schedule, context)."""
+def copy_bandwidth(mib=2048, reps=5):
+    """Device-to-device copy rate (bytes read + written per second, GB/s):
+    the attainable HBM bandwidth on this device, next to the 8 TB/s peak."""
+    import torch
+    n = mib * (1 << 20)
+    src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(reps):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * n / (best / 1e3) / 1e9
+
+
+def run(problems, steps, warmup, tune, variant=-1, grid=0, parts=1):
+    """Times `steps` cycles of a context in `parts` consecutive calls; returns
+    (cell-updates/s over all of them, ms per cycle, schedule, context, rate
+    of each call)."""
     from paper_2403_04267_amd.salec import Salec
     ctx = Salec(problems, "cuda:0")
     if variant >= 0:
@@ -117,17 +146,23 @@ def run(problems, steps, warmup, tune, variant=-1, grid=0):
         ctx.tune(tune)
     if warmup:
         ctx.step(warmup)
-    ctx.step(steps)
-    ms = ctx.last_step_ms()
     probs = problems if isinstance(problems, list) else [problems]
     cells = sum(p.grid.ncells for p in probs)
-    return cells * steps / (ms / 1e3), ms / steps, ctx.schedule(), ctx
+    ms, rates, done = 0.0, [], 0
+    for q in range(parts):
+        n = steps * (q + 1) // parts - done
+        ctx.step(n)
+        m = ctx.last_step_ms()
+        ms += m
+        rates.append(cells * n / (m / 1e3))
+        done += n
+    return cells * steps / (ms / 1e3), ms / steps, ctx.schedule(), ctx, rates
 
 
 def extension(name, problems, steps, warmup, tune, fp64_rate=None):
     import torch
     t0 = time.perf_counter()
-    rate, ms, sch, ctx = run(problems, steps, warmup, tune)
+    rate, ms, sch, ctx, _ = run(problems, steps, warmup, tune)
     probs = problems if isinstance(problems, list) else [problems]
     out = {"value": rate, "unit": "cell-updates/s", "ms_per_cycle": ms, "cycles": steps,
            "instances": len(probs), "cells": sum(p.grid.ncells for p in probs),
@@ -171,6 +206,8 @@ def main():
                     help="time every tile shape over K cycles during warm-up and keep the fastest (0: off)")
     ap.add_argument("--variant", type=int, default=-1, help="force a tile shape (disables --tune)")
     ap.add_argument("--grid", type=int, default=0, help="workgroups per launch with --variant (0: one per tile)")
+    ap.add_argument("--kernel-cycles", type=int, default=200,
+                    help="cycles after the timed ones over which the cycle kernel's own duration is measured")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes (3 launches) and exit; "
                          "profiling it gives the HBM counter scale factors")
@@ -194,14 +231,20 @@ def main():
     if args.mixed:
         pb = pb.replace(precision="mixed")
     t_wall = time.perf_counter()
-    value, ms_cycle, sch, ctx = run(pb, args.steps, args.warmup, args.tune, args.variant, args.grid)
+    value, ms_cycle, sch, ctx, rates = run(pb, args.steps, args.warmup, args.tune, args.variant, args.grid, parts=5)
     wall = time.perf_counter() - t_wall
+    rates.sort()
+    # the cycle kernel's own mean duration, right after the timed cycles, same
+    # context and schedule (launched between HIP events instead of in graphs)
+    k_ms, f_ms = ctx.time_kernels(args.kernel_cycles)
     bpc = algorithmic_bytes_per_cell(pb)
-    achieved = bpc * pb.grid.ncells / (ms_cycle / 1e3) / 1e9
+    achieved = bpc * pb.grid.ncells / (k_ms / 1e3) / 1e9
     traffic_b = traffic_per_launch(sch)
-    traffic = traffic_b / (ms_cycle / 1e3) / 1e9 if traffic_b else None
+    traffic = traffic_b / (k_ms / 1e3) / 1e9 if traffic_b else None
     d = ctx.diag()
     del ctx
+    torch.cuda.empty_cache()
+    copy_gbs = copy_bandwidth()
     out = {
         "metric": "cell-updates/s", "value": value, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_cycle,
@@ -212,9 +255,14 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_bytes_per_launch": traffic_b,
+                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+                     "traffic_frac_of_copy": traffic / copy_gbs if traffic else None,
                      "kernel": "k_cycle (one launch = one cycle of the whole grid)",
-                     "bytes_per_cell_update": bpc},
+                     "kernel_ms": k_ms, "kernel_timing_cycles": args.kernel_cycles,
+                     "finalize_ms": f_ms, "bytes_per_cell_update": bpc},
         "schedule": sch,
+        "median_of_5": {"value": rates[2], "min": rates[0], "max": rates[4],
+                        "note": "the timed cycles as 5 consecutive calls; value is over all of them"},
         "sim": {"t": d["t"], "dt": d["dt"], "cycle": d["cycle"]},
         "wall_s": wall,
     }

@@ -204,6 +204,15 @@ int salec_diag(salec_ctx *ctx, int32_t instance, salec_diag_t *out);
  * with HIP events on the context's stream, in milliseconds. */
 int salec_last_step_ms(salec_ctx *ctx, double *ms);
 
+/* Advances every member by n cycles (1 <= n <= 100000) like salec_step(),
+ * but launches each cycle's two kernels directly (no graph) with a HIP event
+ * after each on the context's stream, queues all n cycles before waiting,
+ * and returns the mean time between consecutive events: per cycle kernel and
+ * per finalize kernel, in milliseconds (each includes its launch gap). Same
+ * kernels, same results; meant for measurement. Returns the first member
+ * error like salec_step(). */
+int salec_time_kernels(salec_ctx *ctx, int32_t n, double *cycle_ms, double *finalize_ms);
+
 /* Launch schedules. Every tile shape computes bit-identical results, so the
  * schedule only changes speed. A new context starts on the shape measured
  * fastest for its precision on a filled device, with as many workgroups as

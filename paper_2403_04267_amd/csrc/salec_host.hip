@@ -597,6 +597,51 @@ int salec_step(salec_ctx* x, int32_t n) {
   return SALEC_OK;
 }
 
+int salec_time_kernels(salec_ctx* x, int32_t n, double* cycle_ms, double* finalize_ms) {
+  if (!x || n < 1 || n > 100000 || !x->ready || !cycle_ms || !finalize_ms) return SALEC_E_INVALID;
+  // one event before the first cycle, then one after each kernel; the host
+  // queues every cycle before waiting, so the kernels run back to back
+  std::vector<hipEvent_t> ev(2 * (size_t)n + 1, nullptr);
+  int rc = SALEC_OK;
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      rc = hip_fail(x, hipErrorOutOfMemory, "hipEventCreate");
+      break;
+    }
+  const int grid = x->grid > 0 ? std::min(x->grid, x->nsched) : x->nsched;
+  hipError_t e = rc ? hipErrorOutOfMemory : hipEventRecord(ev[0], x->st);
+  for (int c = 0; c < n && e == hipSuccess; c++) {
+    e = launch_cycle(x->variant, x->prec, x->L.d_inst, x->L.d_sched, x->nsched, grid, x->st);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * c + 1], x->st);
+    if (e == hipSuccess) e = launch_finalize(x->L.d_inst, (int)x->ms.size(), x->st);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * c + 2], x->st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(x->st);
+  double a = 0.0, b = 0.0;
+  for (int c = 0; c < n && e == hipSuccess; c++) {
+    float m1 = 0.0f, m2 = 0.0f;
+    e = hipEventElapsedTime(&m1, ev[2 * c], ev[2 * c + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&m2, ev[2 * c + 1], ev[2 * c + 2]);
+    a += m1;
+    b += m2;
+  }
+  for (auto& q : ev)
+    if (q) (void)hipEventDestroy(q);
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_fail(x, e, "salec_time_kernels");
+  *cycle_ms = a / n;
+  *finalize_ms = b / n;
+  for (size_t k = 0; k < x->ms.size(); k++) {
+    Scal s = read_scal(x, (int)k);
+    if (s.err) {
+      x->err = "instance " + std::to_string(k) + ": device error " + std::to_string(s.err) + " at cycle " +
+               std::to_string(s.err_cycle);
+      return s.err;
+    }
+  }
+  return SALEC_OK;
+}
+
 int salec_last_step_ms(salec_ctx* x, double* ms) {
   if (!x || !ms) return SALEC_E_INVALID;
   *ms = x->last_ms;

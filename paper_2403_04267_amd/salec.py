@@ -107,6 +107,7 @@ def load() -> C.CDLL:
     lib.salec_set_state.argtypes = [P, P, C.c_size_t]
     lib.salec_diag.argtypes = [P, I32, C.POINTER(Diag)]
     lib.salec_last_step_ms.argtypes = [P, _DP]
+    lib.salec_time_kernels.argtypes = [P, I32, _DP, _DP]
     lib.salec_num_variants.restype = I32
     lib.salec_num_variants.argtypes = []
     lib.salec_get_schedule.argtypes = [P, C.POINTER(Schedule)]
@@ -247,6 +248,14 @@ class Salec:
         v = C.c_double()
         self._check(self.lib.salec_last_step_ms(self._h, C.byref(v)))
         return v.value
+
+    def time_kernels(self, n: int) -> tuple:
+        """Advances n cycles with the two kernels of each cycle launched
+        between HIP events; returns their mean durations (cycle kernel,
+        finalize kernel) in milliseconds."""
+        a, b = C.c_double(), C.c_double()
+        self._check(self.lib.salec_time_kernels(self._h, int(n), C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def fields(self, eos: bool = True, k: int = 0) -> dict:
         NR, NZ, nmat = self.dims[k]

@@ -134,3 +134,17 @@ def test_ensemble_checkpoint_restart_is_bitwise():
         Fa, Fb = a.fields(k=k), b.fields(k=k)
         for name in Fa:
             assert np.array_equal(Fa[name], Fb[name]), (k, name)
+
+
+def test_kernel_timing_advances_like_step():
+    """salec_time_kernels runs the same kernels eagerly: same bits as graphs."""
+    members = small_members()[:2]
+    a, b = ctx(members), ctx(members)
+    a.step(25)
+    ms_cycle, ms_fin = b.time_kernels(25)
+    assert ms_cycle > 0 and ms_fin > 0
+    for k in range(len(members)):
+        assert b.diag(k=k)["cycle"] == 25
+        Fa, Fb = a.fields(k=k), b.fields(k=k)
+        for name in Fa:
+            assert np.array_equal(Fa[name], Fb[name]), (k, name)
