@@ -175,8 +175,16 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   // waves per SIMD leave no registers for two cells in flight at once
   constexpr int kUnroll = WPE >= 4 ? 1 : UA;
   T rP[UA];
+  // level-n values A loads that C needs again, kept in registers for C
+  // (FP64 tiles capped at 128 registers reload them instead)
+  constexpr bool kKeepA = !(WPE >= 4 && sizeof(T) == 8);
+  double rF0[UA], rF1[UA];
+  T rS0[UA], rS1[UA], rS2[UA], rSx[UA];
 #pragma unroll
-  for (int u = 0; u < UA; u++) rP[u] = T(0);
+  for (int u = 0; u < UA; u++) {
+    rP[u] = rS0[u] = rS1[u] = rS2[u] = rSx[u] = T(0);
+    rF0[u] = rF1[u] = 0.0;
+  }
 #pragma unroll kUnroll
   for (int u = 0; u < UA; u++) {
     int k = tid + u * NT;
@@ -185,17 +193,29 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     a_cell(k, i, j);
     T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
     double rh = 0.0;
+    // v^n of the node at the cell's lower-left corner; B's nodes are these
+    // corners of A's cells from (i0-2, j0-2) on, so A hands them to B in LDS
+    const bool node_ok = i >= 0 && i <= g.NR && j >= 0 && j <= g.NZ;
+    T v0r = T(0), v0z = T(0);
+    if (node_ok) {
+      const long long n = nidx(g, i, j);
+      v0r = Sv0[n];
+      v0z = Sv1[n];
+    }
+    if (node_ok && i >= i0 - 2 && j >= j0 - 2) {
+      s_vL[kB(i, j)] = v0r;
+      s_vL[R::NB + kB(i, j)] = v0z;
+    }
     if (in_cells(g, i, j)) {
       long long c = cidx(g, i, j);
-      T f[kMaxMat];
-#pragma unroll
-      for (int m = 0; m < kMaxMat; m++) f[m] = m < g.nmat ? (T)S.f[m][c] : T(0);
+      const double f0d = S.f[0][c], f1d = g.nmat > 1 ? S.f[1][c] : 0.0;
+      T f[kMaxMat] = {(T)f0d, (T)f1d};
       rh = S.rho[c];
       T phi, iden, rm;
       matter(g, (T)rh, f, phi, iden, rm);
       T p = ((const T*)S.eos[0])[c], c2 = ((const T*)S.eos[1])[c], sx = ((const T*)S.eos[4])[c];
-      T vr4[4] = {Sv0[nidx(g, i, j)], Sv0[nidx(g, i + 1, j)], Sv0[nidx(g, i, j + 1)], Sv0[nidx(g, i + 1, j + 1)]};
-      T vz4[4] = {Sv1[nidx(g, i, j)], Sv1[nidx(g, i + 1, j)], Sv1[nidx(g, i, j + 1)], Sv1[nidx(g, i + 1, j + 1)]};
+      T vr4[4] = {v0r, Sv0[nidx(g, i + 1, j)], Sv0[nidx(g, i, j + 1)], Sv0[nidx(g, i + 1, j + 1)]};
+      T vz4[4] = {v0z, Sv1[nidx(g, i + 1, j)], Sv1[nidx(g, i, j + 1)], Sv1[nidx(g, i + 1, j + 1)]};
       Kin<T> kn = kinematics(g, i, vr4, vz4);
       T L = tmin(dr, dz);
       T dDn = dtT * kn.D;
@@ -216,6 +236,12 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       s2 = phi * (stt - P);
       s3 = phi * srz;
       reg_put(rP, u, P);
+      reg_put(rF0, u, f0d);
+      reg_put(rF1, u, f1d);
+      reg_put(rS0, u, srr);
+      reg_put(rS1, u, szz);
+      reg_put(rS2, u, srz);
+      reg_put(rSx, u, sx);
     }
     const int ka = kA(i, j);
     sig[0 * R::NA + ka] = s0;
@@ -231,6 +257,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     int i = i0 - 2 + k % R::BW, j = j0 - 2 + k / R::BW;
     T vLr = T(0), vLz = T(0), kdn = T(0);
     if (i >= 0 && i <= g.NR && j >= 0 && j <= g.NZ) {
+      const T vnr = s_vL[k], vnz = s_vL[R::NB + k];  // v^n, from A
       // quadrants NE = (i, j), NW = (i-1, j), SE = (i, j-1), SW = (i-1, j-1)
       const int qa[4] = {kA(i, j), kA(i - 1, j), kA(i, j - 1), kA(i - 1, j - 1)};
       T srr[4], szz[4], stt[4], srz[4], rh[4];
@@ -258,7 +285,6 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       T nzh = (T)((j < g.NZ) + (j > 0));
       T Vd = (VcE + VcW) * nzh;
       T mt = tmax(macc, T(kMAccEps) * GT::rho_ref(g) * Vd);
-      long long n = nidx(g, i, j);
       T psr = T(0), psz = T(0);
       double db = 0.0, drr = 0.0;
       long long kb = -1, kr = -1;
@@ -274,8 +300,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       }
       T Fer = Fr - Vd * psr, Fez = Fz - Vd * psz;
       T imt = N::div(T(1), mt);
-      vLr = Sv0[n] + dtT * (Fer * imt);
-      vLz = Sv1[n] + dtT * (Fez * imt);
+      vLr = vnr + dtT * (Fer * imt);
+      vLz = vnz + dtT * (Fez * imt);
       if (owns_node(i, j) && (db > 0.0 || drr > 0.0)) {
         T iVd = N::div(T(1), Vd);
         if (db > 0.0) {
@@ -293,7 +319,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         vLz = T(0);
       }
       if (g.top_closed && j == g.NZ) vLz = T(0);
-      T dvr = vLr - Sv0[n], dvz = vLz - Sv1[n];
+      T dvr = vLr - vnr, dvz = vLz - vnz;
       kdn = T(0.5) * (dvr * dvr + dvz * dvz);
     }
     s_vL[k] = vLr;
@@ -339,7 +365,11 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       }
       Kin<T> kn = kinematics(g, i, vr4, vz4);
       T s0rr = T(0), s0zz = T(0), s0rz = T(0);
-      if (g.any_strength) {
+      if (kKeepA) {
+        s0rr = reg_get(rS0, u);
+        s0zz = reg_get(rS1, u);
+        s0rz = reg_get(rS2, u);
+      } else if (g.any_strength) {
         s0rr = Ss0[c];
         s0zz = Ss1[c];
         s0rz = Ss2[c];
@@ -369,12 +399,13 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       T sde = ((s0rr * kn.err + s0zz * kn.ezz) + stt * kn.ett) + T(2) * s0rz * kn.erz;
       T dD = dtT * kn.D;
       T J = T(1) + dD;
-      double rho = S.rho[c];
-      double f0n = S.f[0][c], f1n = g.nmat > 1 ? S.f[1][c] : 0.0;
+      double rho = s_rho[kA(i, j)];
+      double f0n = kKeepA ? reg_get(rF0, u) : S.f[0][c];
+      double f1n = kKeepA ? reg_get(rF1, u) : (g.nmat > 1 ? S.f[1][c] : 0.0);
       T fq[kMaxMat] = {(T)f0n, (T)f1n};
       T phi, iden, rm;
       matter(g, (T)rho, fq, phi, iden, rm);
-      T Jm = Vol<T>::ratio(J, dD, phi, ((const T*)S.eos[4])[c]);
+      T Jm = Vol<T>::ratio(J, dD, phi, kKeepA ? reg_get(rSx, u) : ((const T*)S.eos[4])[c]);
       T Wdt = dtT * sde - P * Vol<T>::jm1(J, dD);
       T rden = tmax(rm, GT::rho_ref(g) * T(kRhoDenFloor));
       double rt = dmax(rho, g.rho_ref * kPmlRhoFloor);
