@@ -98,8 +98,11 @@ typedef struct salec_pml {
 typedef struct salec_scene {
     int32_t surface_j;   /* first void row above the target half-space           */
     int32_t subsample;   /* S x S sub-samples per cell for the sphere's fraction  */
-    double radius;       /* projectile radius, m                                 */
+    double radius;       /* projectile radius, m (0: no projectile)              */
     double v_imp;        /* vertical impact speed, m/s (downwards)               */
+    double gravity;      /* g, m/s^2; > 0: lithostatic target (see below)        */
+    int32_t layer_j;     /* two materials: target rows below it are material 1   */
+                         /* (the projectile's), rows from it up material 0       */
 } salec_scene;
 
 /* Host FP64 arrays; any pointer may be NULL to skip that field.
@@ -203,6 +206,21 @@ int salec_diag(salec_ctx *ctx, int32_t instance, salec_diag_t *out);
 /* Device time of the cycle kernels over the last salec_step() call, measured
  * with HIP events on the context's stream, in milliseconds. */
 int salec_last_step_ms(salec_ctx *ctx, double *ms);
+
+/* Initial pressure p0 per cell row of member `instance` (NZ host values, Pa;
+ * row 0 at the bottom). Sec. 3 writes the momentum balance with
+ * div(tau - p + p0), p0 the pressure of the state before impact with
+ * -grad p0 + rho g = 0, and carries p - p0 into the PML auxiliary psi1: the
+ * node force and psi1 use p - p0; the energy equation and psi2 keep p. A
+ * scene with gravity > 0 sets it to a lithostatic column (trapezoid-rule
+ * integral of rho g from the surface, each row's density the cold compressed
+ * Tillotson state of its pressure, p0 re-evaluated by the equation of state
+ * so that a target at rest stays at rest exactly in FP64); otherwise it is 0.
+ * salec_set_p0 replaces it (values must be finite; the state is untouched;
+ * checkpoints do not include it). Both return SALEC_E_INVALID for a bad
+ * context, instance or pointer. */
+int salec_set_p0(salec_ctx *ctx, int32_t instance, const double *p0);
+int salec_get_p0(salec_ctx *ctx, int32_t instance, double *p0);
 
 /* Advances every member by n cycles (1 <= n <= 100000) like salec_step(),
  * but launches each cycle's two kernels directly (no graph) with a HIP event

@@ -39,7 +39,7 @@ class _Pml(C.Structure):
 
 class _Scene(C.Structure):
     _fields_ = [("surface_j", C.c_int32), ("subsample", C.c_int32), ("radius", C.c_double),
-                ("v_imp", C.c_double)]
+                ("v_imp", C.c_double), ("gravity", C.c_double), ("layer_j", C.c_int32)]
 
 
 def _load():
@@ -59,6 +59,8 @@ def _load():
     lib.orc_set_threads.restype = C.c_int
     lib.orc_init_scene.argtypes = [P, C.POINTER(_Scene)]
     lib.orc_set_fields.argtypes = [P, D, D, D, D, D]
+    lib.orc_set_p0.argtypes = [P, D]
+    lib.orc_get_p0.argtypes = [P, D]
     lib.orc_step.argtypes = [P, C.c_int32]
     lib.orc_get_fields.argtypes = [P, D, D, D, D, D, D, D]
     lib.orc_get_pml.argtypes = [P, D, D]
@@ -124,7 +126,8 @@ class Oracle:
         self._lib = lib
         if problem.scene is not None:
             sc = problem.scene
-            rc = lib.orc_init_scene(self._h, C.byref(_Scene(sc.surface_j, sc.subsample, sc.radius, sc.v_imp)))
+            rc = lib.orc_init_scene(self._h, C.byref(_Scene(sc.surface_j, sc.subsample, sc.radius, sc.v_imp,
+                                                            sc.gravity, sc.layer_j)))
             if rc:
                 raise ValueError(f"orc_init_scene failed: {rc}")
 
@@ -144,6 +147,17 @@ class Oracle:
         rc = self._lib.orc_set_fields(self._h, _ptr(rho), _ptr(I), _ptr(f), _ptr(sp), _ptr(v))
         if rc:
             raise ValueError(f"orc_set_fields failed: {rc}")
+
+    def set_p0(self, p0):
+        """Initial pressure per cell row (NZ values, Pa)."""
+        p0 = np.ascontiguousarray(p0, dtype=np.float64).reshape(self.NZ)
+        if self._lib.orc_set_p0(self._h, _ptr(p0)):
+            raise ValueError("orc_set_p0 failed")
+
+    def p0(self):
+        out = np.empty(self.NZ)
+        self._lib.orc_get_p0(self._h, _ptr(out))
+        return out
 
     def step(self, n: int, check: bool = True) -> int:
         rc = self._lib.orc_step(self._h, int(n))

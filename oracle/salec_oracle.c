@@ -65,6 +65,9 @@ struct orc_ctx {
     int64_t cycle;
     int err, err_cycle;
 
+    /* initial (lithostatic) pressure per cell row */
+    double *p0;
+
     /* PML: damping profiles and auxiliary fields (zero outside the strips) */
     double *dcz, *dnz, *dcr, *dnr;
     double *phi1b, *phi3b, *psi2b, *phi1r, *phi3r, *psi2r, *rref, *msink;
@@ -415,6 +418,7 @@ orc_ctx *orc_create(const orc_grid *g, const orc_mat *mats, const orc_pml *pml)
         x->f_n[m] = zalloc(NC);
         x->fL[m] = zalloc(NC);
     }
+    x->p0 = zalloc(NZ);
     x->dcz = zalloc(NZ);
     x->dnz = zalloc(NZ + 1);
     x->dcr = zalloc(NR);
@@ -467,7 +471,7 @@ orc_ctx *orc_create(const orc_grid *g, const orc_mat *mats, const orc_pml *pml)
 void orc_destroy(orc_ctx *x)
 {
     if (!x) return;
-    double *all[] = {x->rho, x->I, x->srr, x->szz, x->srz, x->vr, x->vz, x->rho_n, x->I_n,
+    double *all[] = {x->rho, x->I, x->srr, x->szz, x->srz, x->vr, x->vz, x->rho_n, x->I_n, x->p0,
                      x->srr_n, x->szz_n, x->srz_n, x->vr_n, x->vz_n, x->dcz, x->dnz, x->dcr,
                      x->dnr, x->phi1b, x->phi3b, x->psi2b, x->phi1r, x->phi3r, x->psi2r,
                      x->rref, x->msink, x->p, x->c2, x->G, x->Y, x->rmat, x->phi, x->sx, x->Q,
@@ -555,17 +559,53 @@ static void apply_bc(orc_ctx *x, double *vr, double *vz)
     }
 }
 
-/* scene: target half-space (material 0) below surface_j, spherical
+/* Lithostatic column of the target rows below surface_j (the initial
+ * pressure p0 of Sec. 3's momentum equation, with -grad p0 + rho g = 0).
+ * Cell-centre pressures are integrated down from p = 0 at the surface with
+ * the trapezoid rule: p(top row) = g dz rho / 2, p(j) = p(j+1) + g dz
+ * (rho(j) + rho(j+1)) / 2. Each row's density is the cold (E = 0) compressed
+ * state at its pressure: with p = A mu + B mu^2, mu = 2p / (A + sqrt(A^2 +
+ * 4Bp)); since p(j) depends on rho(j) too, the two are iterated to a fixed
+ * point (at most 50 times). p0(j) is then set to the equation of state's own
+ * pressure at that density and E = 0, so the column is in exact discrete
+ * equilibrium: p - p0 = 0 in every target cell. mat_row[j] is the row's
+ * material. */
+static void lithostatic(orc_ctx *x, int surface_j, const int *mat_row, double g, double *rho_row)
+{
+    double hg = 0.5 * g * x->g.dz;
+    for (int j = surface_j - 1; j >= 0; j--) {
+        const orc_mat *m = &x->m[mat_row[j]];
+        double p_up = j == surface_j - 1 ? 0.0 : x->p0[j + 1];
+        double r_up = j == surface_j - 1 ? 0.0 : rho_row[j + 1];
+        double r = m->rho0;
+        for (int it = 0; it < 50; it++) {
+            double p = p_up + hg * (r_up + r);
+            double mu = 2.0 * p / (m->A + sqrt(m->A * m->A + 4.0 * m->B * p));
+            double rn = m->rho0 * (1.0 + mu);
+            if (rn == r) break;
+            r = rn;
+        }
+        double p, c2;
+        orc_tillotson(m, r, 0.0, &p, &c2);
+        rho_row[j] = r;
+        x->p0[j] = p;
+    }
+}
+
+/* scene: target half-space below surface_j (material 0; with two materials
+ * and layer_j > 0 the rows below layer_j are material 1, the projectile's),
+ * with an optional lithostatic column (gravity > 0), and a spherical
  * projectile (material 1, or 0 when nmat = 1) resting on the surface at the
- * axis and moving downward; momentum-exact nodal velocities */
+ * axis and moving downward (radius 0: none); momentum-exact nodal velocities */
 int orc_init_scene(orc_ctx *x, const orc_scene *s)
 {
-    if (!x || !s || s->subsample < 1 || !(s->radius > 0)) return ORC_E_INVALID;
+    if (!x || !s || s->subsample < 1 || !(s->radius >= 0) || !(s->gravity >= 0)) return ORC_E_INVALID;
+    if (s->surface_j < 0 || s->surface_j > x->NZ || s->layer_j < 0 || s->layer_j > s->surface_j) return ORC_E_INVALID;
     int NR = x->NR, NZ = x->NZ, S = s->subsample;
     int mp = x->nmat > 1 ? 1 : 0;
     double R = s->radius, zc = (double)s->surface_j * x->g.dz + R;
     double *fp = zalloc(x->NC);
-    for (int j = 0; j < NZ; j++) {
+    for (int j = 0; j < NZ && R > 0; j++) {
         for (int i = 0; i < NR; i++) {
             double num = 0.0, den = 0.0;
             for (int l = 0; l < S; l++) {
@@ -580,15 +620,27 @@ int orc_init_scene(orc_ctx *x, const orc_scene *s)
             fp[CI(i, j)] = num / den;
         }
     }
+    /* material and density of each target row */
+    int *mat_row = (int *)calloc((size_t)NZ + 1, sizeof(int));
+    double *rho_row = zalloc((size_t)NZ + 1);
+    for (int j = 0; j < s->surface_j; j++) {
+        mat_row[j] = x->nmat > 1 && j < s->layer_j ? 1 : 0;
+        rho_row[j] = x->m[mat_row[j]].rho0;
+    }
+    memset(x->p0, 0, sizeof(double) * (size_t)NZ);
+    if (s->gravity > 0) lithostatic(x, s->surface_j, mat_row, s->gravity, rho_row);
     for (int j = 0; j < NZ; j++) {
         for (int i = 0; i < NR; i++) {
             int c = CI(i, j);
             for (int m = 0; m < x->nmat; m++) x->f[m][c] = 0.0;
-            double ft = j < s->surface_j ? 1.0 : 0.0;
-            x->f[0][c] = ft;
-            x->f[mp][c] = x->f[mp][c] + fp[c];
             double rho = 0.0;
-            for (int m = 0; m < x->nmat; m++) rho += x->f[m][c] * x->m[m].rho0;
+            if (j < s->surface_j) {
+                x->f[mat_row[j]][c] = 1.0;
+                rho = rho_row[j];
+            } else {
+                x->f[mp][c] = fp[c];
+                rho = fp[c] * x->m[mp].rho0;
+            }
             x->rho[c] = rho;
             x->I[c] = 0.0;
             x->srr[c] = x->szz[c] = x->srz[c] = 0.0;
@@ -612,8 +664,24 @@ int orc_init_scene(orc_ctx *x, const orc_scene *s)
         }
     }
     free(fp);
+    free(mat_row);
+    free(rho_row);
     apply_bc(x, x->vr, x->vz);
     start_run(x);
+    return ORC_OK;
+}
+
+int orc_set_p0(orc_ctx *x, const double *p0)
+{
+    if (!x || !p0) return ORC_E_INVALID;
+    memcpy(x->p0, p0, sizeof(double) * (size_t)x->NZ);
+    return ORC_OK;
+}
+
+int orc_get_p0(orc_ctx *x, double *p0)
+{
+    if (!x || !p0) return ORC_E_INVALID;
+    memcpy(p0, x->p0, sizeof(double) * (size_t)x->NZ);
     return ORC_OK;
 }
 
@@ -645,7 +713,9 @@ int orc_set_fields(orc_ctx *x, const double *rho, const double *I, const double 
  * ======================================================================== */
 
 /* (a) per cell: EoS, artificial viscosity from the start-of-cycle velocity
- * divergence, total stress sigma = phi (s - (p + Q) I) */
+ * divergence, total stress sigma = phi (s - (p + Q - p0) I), p0 the initial
+ * pressure of the cell's row (Sec. 3: the momentum balance and psi1 carry
+ * p - p0; the energy equation keeps p) */
 static void phase_cell_stress(orc_ctx *x)
 {
     int NR = x->NR, NZ = x->NZ;
@@ -666,6 +736,7 @@ static void phase_cell_stress(orc_ctx *x)
             double Ld = L * Dm;
             double Q = rm * (x->g.q_quad * Ld * Ld + x->g.q_lin * sqrt(c2) * Ld);
             double P = p + Q;
+            double Pf = P - x->p0[j];
             double stt = -(x->srr[c] + x->szz[c]);
             x->p[c] = p;
             x->c2[c] = c2;
@@ -675,9 +746,9 @@ static void phase_cell_stress(orc_ctx *x)
             x->phi[c] = phi;
             x->sx[c] = sx;
             x->Q[c] = Q;
-            x->sgrr[c] = phi * (x->srr[c] - P);
-            x->sgzz[c] = phi * (x->szz[c] - P);
-            x->sgtt[c] = phi * (stt - P);
+            x->sgrr[c] = phi * (x->srr[c] - Pf);
+            x->sgzz[c] = phi * (x->szz[c] - Pf);
+            x->sgtt[c] = phi * (stt - Pf);
             x->sgrz[c] = phi * x->srz[c];
         }
     }

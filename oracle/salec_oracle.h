@@ -66,8 +66,11 @@ typedef struct {
 typedef struct {
     int32_t surface_j;  /* first void row above the target                  */
     int32_t subsample;  /* S x S sub-samples per cell for the disc fraction */
-    double radius;      /* projectile radius, m                             */
+    double radius;      /* projectile radius, m (0: no projectile)          */
     double v_imp;       /* impact speed, m/s (downwards)                    */
+    double gravity;     /* g, m/s^2 (0: no lithostatic pressure)            */
+    int32_t layer_j;    /* rows below it are material 1 (nmat = 2), the     */
+                        /* rows from it up to the surface material 0        */
 } orc_scene;
 
 typedef struct orc_ctx orc_ctx;
@@ -81,6 +84,12 @@ int orc_init_scene(orc_ctx *x, const orc_scene *s);
  * v: 2*NN (r then z). Starts a new run at t = 0. */
 int orc_set_fields(orc_ctx *x, const double *rho, const double *I,
                    const double *f, const double *s, const double *v);
+/* initial pressure p0 per cell row (NZ values, Pa): the momentum balance
+ * and the PML's psi1 use p - p0 (Sec. 3 momentum equation with -grad p0 +
+ * rho g = 0). Zero unless a scene with gravity or this call sets it; kept
+ * across orc_set_fields. */
+int orc_set_p0(orc_ctx *x, const double *p0);
+int orc_get_p0(orc_ctx *x, double *p0);
 int orc_step(orc_ctx *x, int32_t n);
 /* any pointer may be NULL; p and c2 are evaluated from the current state */
 int orc_get_fields(orc_ctx *x, double *rho, double *I, double *f, double *s,

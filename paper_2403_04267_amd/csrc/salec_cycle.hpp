@@ -6,7 +6,7 @@
 // entries in a grid-stride loop; for a TW x TH tile of cells (and the nodes
 // at their lower-left corners) it recomputes every phase over the halo it
 // needs, keeping intermediates in LDS:
-//   A  cells [i0-3, i0+TW+3)  viscosity, phi-scaled stress (EoS from cache) -> LDS
+//   A  cells [i0-3, i0+TW+3)  viscosity, phi-scaled stress less p0 (EoS from cache) -> LDS
 //   B  nodes [i0-2, i0+TW+2]  control-volume force, PML psi1 -> v^L         -> LDS
 //   C  cells [i0-2, i0+TW+1]  Lagrangian update, PML psi2, limiter           -> LDS
 //   E1 faces of the cells below: volume and donor mass fluxes                -> LDS
@@ -224,6 +224,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       T Ld = L * Dm;
       T Q = rm * (GT::q_quad(g) * Ld * Ld + GT::q_lin(g) * N::sqr(c2) * Ld);
       T P = p + Q;
+      // the momentum balance (and so psi1) sees p - p0; C's energy terms keep P
+      const T Pf = g.has_p0 ? P - (T)in.p0[j] : P;
       T srr = T(0), szz = T(0), srz = T(0);
       if (g.any_strength) {
         srr = Ss0[c];
@@ -231,9 +233,9 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         srz = Ss2[c];
       }
       T stt = -(srr + szz);
-      s0 = phi * (srr - P);
-      s1 = phi * (szz - P);
-      s2 = phi * (stt - P);
+      s0 = phi * (srr - Pf);
+      s1 = phi * (szz - Pf);
+      s2 = phi * (stt - Pf);
       s3 = phi * srz;
       reg_put(rP, u, P);
       reg_put(rF0, u, f0d);

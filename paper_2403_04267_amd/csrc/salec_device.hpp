@@ -49,6 +49,7 @@ struct Geo {
   int any_strength, pml_on;
   int same_mat;        // all materials share every constant: evaluate the laws once
   int prec;            // 0: FP64 throughout; 1: FP32 bulk with FP64 energy, mass and volume sums
+  int has_p0, pad_i;   // nonzero initial (lithostatic) pressure profile
   double dr, dz, cfl, dt_grow, dt_max, dt_floor, t_stop, q_lin, q_quad;
   double rho_ref;
   float drf, dzf, q_linf, q_quadf, rho_reff, pad_f;
@@ -119,6 +120,7 @@ struct Inst {
   Scal* sc;
   double* dtpart;         // per-tile Courant minima
   double *mout, *eout;    // per-column outflow budgets (mass, internal energy)
+  const double* p0;       // initial pressure per cell row (read when g.has_p0)
   int tiles_r, tiles_z;   // tile grid of this instance
   int ntiles, pad;
 };

@@ -51,9 +51,40 @@ struct Member {
   long long n_pml = 0;
   size_t aux_off = 0, aux_end = 0;  // PML auxiliaries and budgets (cleared at a run start)
   std::vector<double> dcz, dnz, dcr, dnr;
+  std::vector<double> p0;  // initial pressure per cell row (host copy)
   salec_scene scene{};
   bool has_scene = false;
 };
+
+// Lithostatic target column (Sec. 3: the initial pressure p0 with
+// -grad p0 + rho g = 0), rows below surface_j: cell-centre pressures from
+// p = 0 at the surface by the trapezoid rule (top row g dz rho / 2, then
+// g dz (rho_j + rho_{j+1}) / 2 per row), each row's density the cold (E = 0)
+// compressed Tillotson state of its pressure, mu = 2p / (A + sqrt(A^2 + 4Bp)),
+// iterated with the pressure to a fixed point (at most 50 passes). p0 is then
+// the cold pressure A mu + B mu^2 of the final density, evaluated as the
+// cycle kernel evaluates the equation of state at E = 0, so that a target at
+// rest is in exact discrete equilibrium (p - p0 = 0 in every cell).
+void lithostatic_column(const Geo& g, int surface_j, int layer_j, double grav, std::vector<double>& rho_row,
+                        std::vector<double>& p0) {
+  const double hg = 0.5 * grav * g.dz;
+  for (int j = surface_j - 1; j >= 0; j--) {
+    const MatC& m = g.m[g.nmat > 1 && j < layer_j ? 1 : 0];
+    const bool top = j == surface_j - 1;
+    const double p_up = top ? 0.0 : p0[j + 1], r_up = top ? 0.0 : rho_row[j + 1];
+    double r = m.rho0;
+    for (int it = 0; it < 50; it++) {
+      double p = p_up + hg * (r_up + r);
+      double mu = 2.0 * p / (m.A + std::sqrt(m.A * m.A + 4.0 * m.B * p));
+      double rn = m.rho0 * (1.0 + mu);
+      if (rn == r) break;
+      r = rn;
+    }
+    const double mu = r / m.rho0 - 1.0;
+    rho_row[j] = r;
+    p0[j] = m.A * mu + m.B * mu * mu;
+  }
+}
 
 int tiles_of(const Geo& g, int v, int* tr, int* tz) {
   int tw, th, nt;
@@ -127,6 +158,7 @@ void carve_constants(Member& mb, Carver& cv) {
     most = std::max(most, tiles_of(g, v, &tr, &tz));
   }
   mb.d.dtpart = cv.d((size_t)most);
+  mb.d.p0 = cv.d((size_t)g.NZ);
 }
 
 // Entries of the largest schedule over all tile shapes.
@@ -302,7 +334,9 @@ int check_members(const salec_instance* inst, int32_t n, std::vector<Member>& ms
     if (rc) return why = "instance " + std::to_string(k) + ": " + why, rc;
     if (I.grid.precision != inst[0].grid.precision)
       return why = "every instance of a context must use the same precision", SALEC_E_INVALID;
-    if (I.has_scene && (I.scene.subsample < 1 || !(I.scene.radius > 0)))
+    const salec_scene& sc = I.scene;
+    if (I.has_scene && (sc.subsample < 1 || !(sc.radius >= 0) || !(sc.gravity >= 0) || sc.surface_j < 0 ||
+                        sc.surface_j > I.grid.n_z + I.grid.pml_b || sc.layer_j < 0 || sc.layer_j > sc.surface_j))
       return why = "instance " + std::to_string(k) + ": scene parameters", SALEC_E_INVALID;
     ms[k].g = make_geo(&I.grid, I.mats, &I.pml);
     ms[k].d.g = ms[k].g;
@@ -490,10 +524,28 @@ int init_common(salec_ctx* x, void* dev_buf, size_t dev_bytes, void* stream) {
     HIPCHK(x, hipMemcpyAsync((void*)mb.d.pm.dnz, mb.dnz.data(), mb.dnz.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
     HIPCHK(x, hipMemcpyAsync((void*)mb.d.pm.dcr, mb.dcr.data(), mb.dcr.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
     HIPCHK(x, hipMemcpyAsync((void*)mb.d.pm.dnr, mb.dnr.data(), mb.dnr.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
+    mb.p0.assign((size_t)mb.g.NZ, 0.0);
+    std::vector<double> rho_row;
+    if (mb.has_scene && mb.scene.gravity > 0) {
+      rho_row.assign((size_t)mb.g.NZ, 0.0);
+      lithostatic_column(mb.g, mb.scene.surface_j, mb.scene.layer_j, mb.scene.gravity, rho_row, mb.p0);
+    }
+    HIPCHK(x, hipMemcpyAsync((void*)mb.d.p0, mb.p0.data(), mb.p0.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
+    mb.g.has_p0 = 0;
+    for (double v : mb.p0)
+      if (v != 0.0) mb.g.has_p0 = 1;
+    mb.d.g = mb.g;
     if (mb.has_scene) {
       const salec_scene& sc = mb.scene;
       double zc = (double)sc.surface_j * mb.g.dz + sc.radius;
-      HIPCHK(x, launch_scene(mb.d, sc.surface_j, sc.subsample, sc.radius, zc, sc.v_imp, x->L.scratch, x->st));
+      // per-row densities of a lithostatic target go after the projectile fractions
+      double* rr = nullptr;
+      if (!rho_row.empty()) {
+        rr = x->L.scratch + (size_t)mb.g.NZ * mb.g.pc;
+        HIPCHK(x, hipMemcpyAsync(rr, rho_row.data(), rho_row.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
+      }
+      HIPCHK(x, launch_scene(mb.d, sc.surface_j, sc.layer_j, sc.subsample, sc.radius, zc, sc.v_imp, rr,
+                             x->L.scratch, x->st));
     }
     HIPCHK(x, hipStreamSynchronize(x->st));  // the profile vectors are reused below
     int rc = start_run(x, (int)k);
@@ -594,6 +646,33 @@ int salec_step(salec_ctx* x, int32_t n) {
       return s.err;
     }
   }
+  return SALEC_OK;
+}
+
+int salec_set_p0(salec_ctx* x, int32_t k, const double* p0) {
+  if (!member_ok(x, k) || !p0) return SALEC_E_INVALID;
+  Member& mb = x->ms[k];
+  for (int j = 0; j < mb.g.NZ; j++)
+    if (!std::isfinite(p0[j])) {
+      x->err = "initial pressure not finite";
+      return SALEC_E_INVALID;
+    }
+  HIPCHK(x, hipStreamSynchronize(x->st));
+  mb.p0.assign(p0, p0 + mb.g.NZ);
+  HIPCHK(x, hipMemcpyAsync((void*)mb.d.p0, mb.p0.data(), mb.p0.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
+  mb.g.has_p0 = 0;
+  for (double v : mb.p0)
+    if (v != 0.0) mb.g.has_p0 = 1;
+  mb.d.g.has_p0 = mb.g.has_p0;
+  // the descriptor carries the flag: upload it again (graphs read it at run time)
+  HIPCHK(x, hipMemcpyAsync(x->L.d_inst + k, &mb.d, sizeof(Inst), hipMemcpyHostToDevice, x->st));
+  HIPCHK(x, hipStreamSynchronize(x->st));
+  return SALEC_OK;
+}
+
+int salec_get_p0(salec_ctx* x, int32_t k, double* p0) {
+  if (!member_ok(x, k) || !p0) return SALEC_E_INVALID;
+  std::copy(x->ms[k].p0.begin(), x->ms[k].p0.end(), p0);
   return SALEC_OK;
 }
 

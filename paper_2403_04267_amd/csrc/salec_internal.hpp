@@ -32,8 +32,8 @@ hipError_t launch_prime_f32(const Inst& in, hipStream_t st);
 hipError_t launch_prime(const Inst& in, hipStream_t st);
 
 // set-up, outputs and diagnostics of one instance
-hipError_t launch_scene(const Inst& in, int surface_j, int S, double R, double zc, double v_imp, double* scratch,
-                        hipStream_t st);
+hipError_t launch_scene(const Inst& in, int surface_j, int layer_j, int S, double R, double zc, double v_imp,
+                        const double* rho_row, double* scratch, hipStream_t st);
 hipError_t launch_start_run(const Inst& in, hipStream_t st);
 hipError_t launch_finalize0(const Inst& in, hipStream_t st);
 hipError_t launch_eos_out(const Inst& in, double* p, double* c2, hipStream_t st);

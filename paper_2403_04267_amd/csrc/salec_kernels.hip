@@ -35,7 +35,8 @@ inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs)
 // node velocities (state level 0)
 // ======================================================================
 template <class T>
-__global__ void k_scene_cells(Inst in, int surface_j, int S, double R, double zc, double* fproj) {
+__global__ void k_scene_cells(Inst in, int surface_j, int layer_j, int S, double R, double zc,
+                              const double* rho_row, double* fproj) {
   const Geo& g = in.g;
   const State& S0 = in.S[0];
   int i, j;
@@ -51,16 +52,19 @@ __global__ void k_scene_cells(Inst in, int surface_j, int S, double R, double zc
       den += rk;
     }
   }
-  double fp = num / den;
+  double fp = R > 0.0 ? num / den : 0.0;
   int mp = g.nmat > 1 ? 1 : 0;
   double f[kMaxMat] = {0.0, 0.0};
-  f[0] = j < surface_j ? 1.0 : 0.0;
-  f[mp] = f[mp] + fp;
-  double rho = 0.0;
-  _Pragma("unroll") for (int m = 0; m < kMaxMat; m++) if (m < g.nmat) {
-    S0.f[m][c] = f[m];
-    rho += f[m] * g.m[m].rho0;
+  double rho;
+  if (j < surface_j) {  // target row: material 1 below layer_j (two materials), else 0
+    const int mt = g.nmat > 1 && j < layer_j ? 1 : 0;
+    f[mt] = 1.0;
+    rho = rho_row ? rho_row[j] : g.m[mt].rho0;
+  } else {
+    f[mp] = fp;
+    rho = fp * g.m[mp].rho0;
   }
+  _Pragma("unroll") for (int m = 0; m < kMaxMat; m++) if (m < g.nmat) S0.f[m][c] = f[m];
   S0.rho[c] = rho;
   S0.I[c] = 0.0;
   if (g.any_strength)
@@ -243,15 +247,17 @@ __global__ void k_diag_final(const double* red, int nblocks, double* out) {
 // ======================================================================
 // launchers
 // ======================================================================
-hipError_t launch_scene(const Inst& in, int surface_j, int S, double R, double zc, double v_imp, double* scratch,
-                        hipStream_t st) {
+hipError_t launch_scene(const Inst& in, int surface_j, int layer_j, int S, double R, double zc, double v_imp,
+                        const double* rho_row, double* scratch, hipStream_t st) {
   const int bs = 256;
   long long nc = (long long)in.g.NR * in.g.NZ, nn = (long long)(in.g.NR + 1) * (in.g.NZ + 1);
   if (in.g.prec == 0) {
-    hipLaunchKernelGGL(k_scene_cells<double>, dim3(nblk(nc, bs)), dim3(bs), 0, st, in, surface_j, S, R, zc, scratch);
+    hipLaunchKernelGGL(k_scene_cells<double>, dim3(nblk(nc, bs)), dim3(bs), 0, st, in, surface_j, layer_j, S, R, zc,
+                       rho_row, scratch);
     hipLaunchKernelGGL(k_scene_nodes<double>, dim3(nblk(nn, bs)), dim3(bs), 0, st, in, scratch, v_imp);
   } else {
-    hipLaunchKernelGGL(k_scene_cells<float>, dim3(nblk(nc, bs)), dim3(bs), 0, st, in, surface_j, S, R, zc, scratch);
+    hipLaunchKernelGGL(k_scene_cells<float>, dim3(nblk(nc, bs)), dim3(bs), 0, st, in, surface_j, layer_j, S, R, zc,
+                       rho_row, scratch);
     hipLaunchKernelGGL(k_scene_nodes<float>, dim3(nblk(nn, bs)), dim3(bs), 0, st, in, scratch, v_imp);
   }
   return hipGetLastError();

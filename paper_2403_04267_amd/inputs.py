@@ -88,9 +88,11 @@ class Pml:
 @dataclass
 class Scene:
     surface_j: int
-    radius: float
+    radius: float            # 0: no projectile
     v_imp: float
     subsample: int = 8
+    gravity: float = 0.0     # m/s^2; > 0: lithostatic target (initial pressure p0)
+    layer_j: int = 0         # two materials: rows below it are material 1
 
 
 @dataclass
@@ -124,6 +126,20 @@ def basalt(strength: bool = False, Y0: float = 10e6, mu_f: float = 0.8,
     return m
 
 
+def mantle_like(strength: bool = False, Y0: float = 10e6, mu_f: float = 0.8,
+                Ylim: float = 3.5e9) -> Material:
+    """Dense mantle-rock stand-in (the paper's Table 1 gives strength
+    parameters only): rho0 = 3320 kg/m^3 and A = B = 131 GPa (a bulk sound
+    speed of about 6.3 km/s), the other Tillotson constants as basalt."""
+    m = Material(rho0=3320.0, A=131e9, B=131e9, E0=487e6, a=0.5, b=1.5, alpha=5.0,
+                 beta=5.0, Eiv=4.72e6, Ecv=18.2e6, p_min=0.0, c_floor_frac=0.25)
+    if strength:
+        m.strength = 1
+        m.Y0, m.mu_f, m.Ylim = Y0, mu_f, Ylim
+        m.p_min = -Y0 / mu_f
+    return m
+
+
 def ideal_gas(gamma: float = 1.4) -> Material:
     """Tillotson with a = gamma - 1 and b = A = B = 0 is exactly an ideal gas."""
     return Material(rho0=1.0, A=0.0, B=0.0, E0=1.0, a=gamma - 1.0, b=0.0, alpha=5.0,
@@ -148,6 +164,22 @@ def impact(n: int, pml: int, radius_cells: int, v_imp: float, nmat: int, strengt
     sc = Scene(surface_j=surface_row(n, pml, radius_cells), radius=radius_cells * dx, v_imp=v_imp)
     return Problem(grid=g, mats=mats, pml=Pml(), scene=sc, cycles=cycles, precision=precision,
                    name=name)
+
+
+def layered_impact(n: int, pml: int, radius_cells: int, v_imp: float, crust_cells: int,
+                   dx: float = 400.0, gravity: float = 9.81, strength: bool = True, cycles: int = 0,
+                   precision: str = "fp64", name: str = "") -> Problem:
+    """Vertical impact of a mantle-rock sphere on a two-layer target under
+    gravity, the setting of Sec. 4 reduced to two materials: a basalt crust
+    of crust_cells rows over a mantle-rock half-space (material 1, the
+    projectile's), lithostatic initial pressure, PML right and below.
+    Cells of dx metres (the paper's runs use 400 m)."""
+    g = Grid(n_r=n, n_z=n, pml_r=pml, pml_b=pml, nmat=2, dr=dx, dz=dx)
+    sj = surface_row(n, pml, radius_cells)
+    sc = Scene(surface_j=sj, radius=radius_cells * dx, v_imp=v_imp, gravity=gravity,
+               layer_j=max(sj - crust_cells, 0))
+    return Problem(grid=g, mats=[basalt(strength=strength), mantle_like(strength=strength)], pml=Pml(),
+                   scene=sc, cycles=cycles, precision=precision, name=name)
 
 
 def config_small() -> Problem:

@@ -43,7 +43,7 @@ class PmlC(C.Structure):
 
 class SceneC(C.Structure):
     _fields_ = [("surface_j", C.c_int32), ("subsample", C.c_int32), ("radius", C.c_double),
-                ("v_imp", C.c_double)]
+                ("v_imp", C.c_double), ("gravity", C.c_double), ("layer_j", C.c_int32)]
 
 
 _DP = C.POINTER(C.c_double)
@@ -108,6 +108,8 @@ def load() -> C.CDLL:
     lib.salec_diag.argtypes = [P, I32, C.POINTER(Diag)]
     lib.salec_last_step_ms.argtypes = [P, _DP]
     lib.salec_time_kernels.argtypes = [P, I32, _DP, _DP]
+    lib.salec_set_p0.argtypes = [P, I32, _DP]
+    lib.salec_get_p0.argtypes = [P, I32, _DP]
     lib.salec_num_variants.restype = I32
     lib.salec_num_variants.argtypes = []
     lib.salec_get_schedule.argtypes = [P, C.POINTER(Schedule)]
@@ -155,7 +157,7 @@ def _instance(problem) -> Instance:
     inst.pml = PmlC(int(p.enabled), 0, p.R, p.c_ref)
     if problem.scene is not None:
         sc = problem.scene
-        inst.scene = SceneC(sc.surface_j, sc.subsample, sc.radius, sc.v_imp)
+        inst.scene = SceneC(sc.surface_j, sc.subsample, sc.radius, sc.v_imp, sc.gravity, sc.layer_j)
         inst.has_scene = 1
     return inst
 
@@ -282,6 +284,18 @@ class Salec:
         sp = None if s is None else np.ascontiguousarray(s, dtype=np.float64).reshape(3 * NC)
         fl = Fields(_ptr(arr[0]), _ptr(arr[1]), _ptr(arr[2]), _ptr(sp), _ptr(arr[3]), None, None)
         self._check(self.lib.salec_set_fields(self._h, int(k), C.byref(fl)))
+
+    def set_p0(self, p0, k: int = 0):
+        """Initial pressure per cell row (NZ values, Pa) of member k."""
+        NR, NZ, _ = self.dims[k]
+        p0 = np.ascontiguousarray(p0, dtype=np.float64).reshape(NZ)
+        self._check(self.lib.salec_set_p0(self._h, int(k), _ptr(p0)))
+
+    def p0(self, k: int = 0):
+        NR, NZ, _ = self.dims[k]
+        out = np.empty(NZ)
+        self._check(self.lib.salec_get_p0(self._h, int(k), _ptr(out)))
+        return out
 
     def pml_aux(self, k: int = 0) -> dict:
         NR, NZ, _ = self.dims[k]
