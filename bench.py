@@ -17,10 +17,12 @@ Also measured (the "extensions" object; skipped with --headline-only):
   mixed_large    4000 x 4000 + 100 PML (4100^2 cells), mixed precision
   batched_fp64   256 seeded uneven impacts (sides 200-800), plain FP64
   batched_mixed  1024 seeded uneven impacts (sides 200-1200), mixed
+  layered_fp64   the 1050^2 workload as a two-layer target under gravity
+                 (400 m cells, lithostatic initial pressure), plain FP64
   pml_payoff     the same small impact with a PML, with plain walls and on a
                  10x larger domain, each to the same time (interior error,
                  reflected energy, crater geometry, device time)
-Each of the first four is init + tune + warm-up, then a short timed run.
+Each of the first five is init + tune + warm-up, then a short timed run.
 
 Prints one JSON line. `roofline` is the cycle kernel's algorithmic HBM
 bytes per launch (state read and written once, PML auxiliaries) over the
@@ -275,6 +277,9 @@ def main():
         ext["batched_fp64"] = extension("batched 256 fp64", inputs.ensemble(2403, 256, 200, 800), 40, 2, 1)
         ext["batched_mixed"] = extension("batched 1024 mixed",
                                          inputs.ensemble(4267, 1024, 200, 1200, precision="mixed"), 10, 1, 1)
+        ext["layered_fp64"] = extension("layered 1050^2 fp64",
+                                        inputs.layered_impact(1000, 50, 50, 15e3, 70, name="layered"), 500, 20,
+                                        args.tune, value)
         ext["pml_payoff"] = pml_payoff()
         out["extensions"] = ext
     if not args.no_cpu:
