@@ -333,12 +333,18 @@ __device__ inline Mix<T> mixture(const Geo& g, double rho, double I, const doubl
   T Ie = (T)I;
   T p = T(0), c2 = T(0), G = T(0);
   T wm[kMaxMat], pmv[kMaxMat], c2v[kMaxMat], sov[kMaxMat];
+  // A material absent from the cell (f = 0) would add exactly +0 to every
+  // sum below (its laws give finite values times a zero weight), so it is
+  // not evaluated at all; sums that skip it are bit-identical.
+  bool have0 = false;
 #pragma unroll
   for (int m = 0; m < kMaxMat; m++) {
     if (m >= g.nmat) break;
     const MatT<T>& M = GeoT<T>::mat(g, m);
     wm[m] = f[m] * iden;
-    if (m > 0 && g.same_mat) {
+    pmv[m] = c2v[m] = sov[m] = T(0);
+    if (fd[m] == 0.0) continue;
+    if (m > 0 && g.same_mat && have0) {
       // identical constants and inputs give identical results
       pmv[m] = pmv[0];
       c2v[m] = c2v[0];
@@ -350,6 +356,7 @@ __device__ inline Mix<T> mixture(const Geo& g, double rho, double I, const doubl
       pmv[m] = tmax(pm, M.p_min);
       c2v[m] = tmax(c2m, M.cf2);
       sov[m] = softening(M, Ie);
+      if (m == 0) have0 = true;
     }
     p += wm[m] * pmv[m];
     c2 += wm[m] * c2v[m];
@@ -359,8 +366,9 @@ __device__ inline Mix<T> mixture(const Geo& g, double rho, double I, const doubl
 #pragma unroll
   for (int m = 0; m < kMaxMat; m++) {
     if (m >= g.nmat) break;
+    if (fd[m] == 0.0) continue;
     const MatT<T>& M = GeoT<T>::mat(g, m);
-    T ym = (m > 0 && g.same_mat) ? y0 : yield_strength(M, p);
+    T ym = (m > 0 && g.same_mat && have0) ? y0 : yield_strength(M, p);
     if (m == 0) y0 = ym;
     Y += wm[m] * (sov[m] * ym);
     pmin += wm[m] * M.p_min;
