@@ -77,6 +77,11 @@ typedef struct salec_grid {
     double dt_floor;     /* dt below this is an error (0 disables)               */
     double t_stop;       /* > 0: the step is clipped so t never passes t_stop    */
     double q_lin, q_quad;/* artificial viscosity coefficients C1, C2 (>= 0)       */
+    /* Stretched grid (Table 2's extension zones), or NULL for uniform dr / dz:
+     * dr_col[NR] column widths outward from the axis, dz_row[NZ] row heights
+     * upward from the bottom (m, > 0, host arrays read at init). Node radii
+     * and heights are their running sums, cell centres halfway between. */
+    const double *dr_col, *dz_row;
 } salec_grid;
 
 typedef struct salec_material {

@@ -23,7 +23,8 @@ class _Grid(C.Structure):
                 ("pml_b", C.c_int32), ("nmat", C.c_int32), ("top_closed", C.c_int32),
                 ("dr", C.c_double), ("dz", C.c_double), ("cfl", C.c_double),
                 ("dt_grow", C.c_double), ("dt_max", C.c_double), ("dt_floor", C.c_double),
-                ("t_stop", C.c_double), ("q_lin", C.c_double), ("q_quad", C.c_double)]
+                ("t_stop", C.c_double), ("q_lin", C.c_double), ("q_quad", C.c_double),
+                ("dr_col", C.POINTER(C.c_double)), ("dz_row", C.POINTER(C.c_double))]
 
 
 class _Mat(C.Structure):
@@ -74,7 +75,8 @@ def _load():
     lib.orc_shear_modulus.argtypes = [C.POINTER(_Mat)]
     lib.orc_shear_modulus.restype = C.c_double
     lib.orc_stress_update.argtypes = [C.c_double, C.c_double, C.c_double, D, D]
-    lib.orc_cell_kinematics.argtypes = [C.POINTER(_Grid), C.c_int32, D, D, D]
+    lib.orc_cell_kinematics.argtypes = [C.POINTER(_Grid), C.c_int32, C.c_int32, D, D, D]
+    lib.orc_get_geometry.argtypes = [P, D, D, D, D]
     _lib = lib
     return lib
 
@@ -86,8 +88,14 @@ def _ptr(a):
 
 
 def _grid(g) -> _Grid:
-    return _Grid(g.n_r, g.n_z, g.pml_r, g.pml_b, g.nmat, g.top_closed, g.dr, g.dz, g.cfl,
-                 g.dt_grow, g.dt_max, g.dt_floor, g.t_stop, g.q_lin, g.q_quad)
+    """The C grid description; a stretched grid's width / height arrays are
+    kept alive on the returned structure for as long as it is used."""
+    drc = None if g.dr_col is None else np.ascontiguousarray(g.dr_col, dtype=np.float64)
+    dzr = None if g.dz_row is None else np.ascontiguousarray(g.dz_row, dtype=np.float64)
+    out = _Grid(g.n_r, g.n_z, g.pml_r, g.pml_b, g.nmat, g.top_closed, g.dr, g.dz, g.cfl,
+                g.dt_grow, g.dt_max, g.dt_floor, g.t_stop, g.q_lin, g.q_quad, _ptr(drc), _ptr(dzr))
+    out._keep = (drc, dzr)
+    return out
 
 
 def _mat(m) -> _Mat:
@@ -198,6 +206,13 @@ class Oracle:
         out.update({k: na[i] for i, k in enumerate(names_n)})
         return out
 
+    def geometry(self):
+        """Node and centre radii and heights of the grid."""
+        rn, rc = np.empty(self.NR + 1), np.empty(self.NR)
+        zn, zc = np.empty(self.NZ + 1), np.empty(self.NZ)
+        self._lib.orc_get_geometry(self._h, _ptr(rn), _ptr(rc), _ptr(zn), _ptr(zc))
+        return rn, rc, zn, zc
+
     def profiles(self):
         dcz, dnz = np.empty(self.NZ), np.empty(self.NZ + 1)
         dcr, dnr = np.empty(self.NR), np.empty(self.NR + 1)
@@ -238,9 +253,10 @@ def stress_update(G: float, Y: float, dt: float, rates, s):
     return s
 
 
-def cell_kinematics(grid, i: int, vr4, vz4):
+def cell_kinematics(grid, i: int, vr4, vz4, j: int = 0):
     vr = np.ascontiguousarray(vr4, dtype=np.float64)
     vz = np.ascontiguousarray(vz4, dtype=np.float64)
     out = np.empty(6)
-    _load().orc_cell_kinematics(C.byref(_grid(grid)), int(i), _ptr(vr), _ptr(vz), _ptr(out))
+    cg = _grid(grid)
+    _load().orc_cell_kinematics(C.byref(cg), int(i), int(j), _ptr(vr), _ptr(vz), _ptr(out))
     return dict(zip(["err", "ezz", "ett", "erz", "om", "D"], out.tolist()))

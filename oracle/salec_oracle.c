@@ -68,6 +68,11 @@ struct orc_ctx {
     /* initial (lithostatic) pressure per cell row */
     double *p0;
 
+    /* geometry tables: node and centre radii, column widths and the
+     * r-weighted areas of each column's west and east halves; node and centre
+     * heights and row heights */
+    double *rn, *rcn, *drc, *awc, *aec, *azc, *zn, *zcn, *dzr;
+
     /* PML: damping profiles and auxiliary fields (zero outside the strips) */
     double *dcz, *dnz, *dcr, *dnr;
     double *phi1b, *phi3b, *psi2b, *phi1r, *phi3r, *psi2r, *rref, *msink;
@@ -91,12 +96,9 @@ struct orc_ctx {
 static double dmax(double a, double b) { return a > b ? a : b; }
 static double dmin(double a, double b) { return a < b ? a : b; }
 
-/* ---- geometry (per radian): node radius, cell-centre radius, areas, volume ---- */
-static double r_node(const orc_ctx *x, int i) { return (double)i * x->g.dr; }
-static double r_cell(const orc_ctx *x, int i) { return ((double)i + 0.5) * x->g.dr; }
-static double area_r(const orc_ctx *x, int i) { return r_node(x, i) * x->g.dz; }
-static double area_z(const orc_ctx *x, int i) { return r_cell(x, i) * x->g.dr; }
-static double vol_c(const orc_ctx *x, int i) { return area_z(x, i) * x->g.dz; }
+/* ---- geometry (per radian): radial face area, cell volume ---- */
+static double area_r(const orc_ctx *x, int i, int j) { return x->rn[i] * x->dzr[j]; }
+static double vol_c(const orc_ctx *x, int i, int j) { return x->azc[i] * x->dzr[j]; }
 
 /* exp(x) by a fixed published method so that every implementation of this
  * algorithm rounds identically: Cody & Waite range reduction
@@ -276,13 +278,45 @@ typedef struct {
  * a_W(i+1) = (r_{i+1}^2 - r_{i+1/2}^2)/2 (which sum to the face area); this
  * makes the control-volume node force the exact gradient of the discrete
  * cell volumes, so stress work and kinetic energy balance, also on the axis. */
-static void kinematics(const orc_grid *g, int i, const double *vr, const double *vz, kin_t *k)
+/* one column's geometry: node radii rw, re, centre radius rc, width dr, the
+ * r-weighted areas aw, ae of its halves and its area per unit height az */
+typedef struct {
+    double rw, re, rc, dr, aw, ae, az;
+} col_t;
+
+/* column i of a uniform grid; a stretched column takes rc = rw + dr / 2 and
+ * re = rw + dr from the running sum of widths instead */
+static col_t col_uniform(double dr, int i)
+{
+    col_t c;
+    c.rw = (double)i * dr;
+    c.re = (double)(i + 1) * dr;
+    c.rc = ((double)i + 0.5) * dr;
+    c.dr = dr;
+    c.aw = 0.5 * (c.rc * c.rc - c.rw * c.rw);
+    c.ae = 0.5 * (c.re * c.re - c.rc * c.rc);
+    c.az = c.rc * c.dr;
+    return c;
+}
+
+static col_t col_at(const orc_ctx *x, int i)
+{
+    col_t c;
+    c.rw = x->rn[i];
+    c.re = x->rn[i + 1];
+    c.rc = x->rcn[i];
+    c.dr = x->drc[i];
+    c.aw = x->awc[i];
+    c.ae = x->aec[i];
+    c.az = x->azc[i];
+    return c;
+}
+
+static void kinematics(const col_t *cg, double dz, const double *vr, const double *vz, kin_t *k)
 {
     /* vr, vz ordered SW, SE, NW, NE (nodes (i,j), (i+1,j), (i,j+1), (i+1,j+1)) */
-    double rw = (double)i * g->dr, re = (double)(i + 1) * g->dr;
-    double rc = ((double)i + 0.5) * g->dr;
-    double Arw = rw * g->dz, Are = re * g->dz, Az = rc * g->dr, V = Az * g->dz;
-    double aw = 0.5 * (rc * rc - rw * rw), ae = 0.5 * (re * re - rc * rc);
+    double Arw = cg->rw * dz, Are = cg->re * dz, Az = cg->az, V = Az * dz;
+    double aw = cg->aw, ae = cg->ae;
     k->ur_w = 0.5 * (vr[0] + vr[2]);
     k->ur_e = 0.5 * (vr[1] + vr[3]);
     k->Ur_w = Arw * k->ur_w;
@@ -291,7 +325,7 @@ static void kinematics(const orc_grid *g, int i, const double *vr, const double 
     k->Uz_n = aw * vz[2] + ae * vz[3];
     k->uz_s = k->Uz_s / Az;
     k->uz_n = k->Uz_n / Az;
-    double iV = 1.0 / V, irc = 1.0 / rc, idr = 1.0 / g->dr;
+    double iV = 1.0 / V, irc = 1.0 / cg->rc, idr = 1.0 / cg->dr;
     k->Dr = (k->Ur_e - k->Ur_w) * iV;
     k->Dz = (k->Uz_n - k->Uz_s) * iV;
     k->D = ((k->Ur_e - k->Ur_w) + (k->Uz_n - k->Uz_s)) * iV;
@@ -304,10 +338,26 @@ static void kinematics(const orc_grid *g, int i, const double *vr, const double 
     k->om = 0.5 * (k->dvr_dz - k->dvz_dr);
 }
 
-void orc_cell_kinematics(const orc_grid *g, int32_t i, const double *vr, const double *vz, double *out)
+void orc_cell_kinematics(const orc_grid *g, int32_t i, int32_t j, const double *vr, const double *vz, double *out)
 {
     kin_t k;
-    kinematics(g, i, vr, vz, &k);
+    col_t c;
+    double dz;
+    if (g->dr_col) {
+        double rw = 0.0;
+        for (int q = 0; q < i; q++) rw += g->dr_col[q];
+        c.rw = rw;
+        c.dr = g->dr_col[i];
+        c.re = rw + c.dr;
+        c.rc = rw + 0.5 * c.dr;
+        c.aw = 0.5 * (c.rc * c.rc - c.rw * c.rw);
+        c.ae = 0.5 * (c.re * c.re - c.rc * c.rc);
+        c.az = c.rc * c.dr;
+    } else {
+        c = col_uniform(g->dr, i);
+    }
+    dz = g->dz_row ? g->dz_row[j] : g->dz;
+    kinematics(&c, dz, vr, vz, &k);
     out[0] = k.err;
     out[1] = k.ezz;
     out[2] = k.ett;
@@ -382,6 +432,10 @@ orc_ctx *orc_create(const orc_grid *g, const orc_mat *mats, const orc_pml *pml)
     if (g->n_r < 1 || g->n_z < 1 || g->pml_r < 0 || g->pml_b < 0) return NULL;
     if (g->nmat < 1 || g->nmat > ORC_MAX_MAT) return NULL;
     if (!(g->dr > 0) || !(g->dz > 0) || !(g->cfl > 0) || g->cfl > 1.0) return NULL;
+    for (int i = 0; g->dr_col && i < g->n_r + g->pml_r; i++)
+        if (!(g->dr_col[i] > 0) || !isfinite(g->dr_col[i])) return NULL;
+    for (int j = 0; g->dz_row && j < g->n_z + g->pml_b; j++)
+        if (!(g->dz_row[j] > 0) || !isfinite(g->dz_row[j])) return NULL;
     orc_ctx *x = (orc_ctx *)calloc(1, sizeof(orc_ctx));
     x->g = *g;
     x->pml = *pml;
@@ -398,6 +452,52 @@ orc_ctx *orc_create(const orc_grid *g, const orc_mat *mats, const orc_pml *pml)
     x->NC = NR * NZ;
     x->NN = (NR + 1) * (NZ + 1);
     size_t NC = x->NC, NN = x->NN, NRF = (size_t)(NR + 1) * NZ, NAF = (size_t)NR * (NZ + 1);
+
+    /* geometry tables; a stretched grid sums its widths outward from the
+     * axis and its heights upward from the bottom, centres halfway */
+    x->rn = zalloc((size_t)NR + 1);
+    x->rcn = zalloc(NR);
+    x->drc = zalloc(NR);
+    x->awc = zalloc(NR);
+    x->aec = zalloc(NR);
+    x->azc = zalloc(NR);
+    x->zn = zalloc((size_t)NZ + 1);
+    x->zcn = zalloc(NZ);
+    x->dzr = zalloc(NZ);
+    for (int i = 0; i < NR; i++) {
+        col_t c;
+        if (g->dr_col) {
+            c.rw = x->rn[i];
+            c.dr = g->dr_col[i];
+            c.re = c.rw + c.dr;
+            c.rc = c.rw + 0.5 * c.dr;
+            c.aw = 0.5 * (c.rc * c.rc - c.rw * c.rw);
+            c.ae = 0.5 * (c.re * c.re - c.rc * c.rc);
+            c.az = c.rc * c.dr;
+        } else {
+            c = col_uniform(g->dr, i);
+        }
+        x->rn[i] = c.rw;
+        x->rn[i + 1] = c.re;
+        x->rcn[i] = c.rc;
+        x->drc[i] = c.dr;
+        x->awc[i] = c.aw;
+        x->aec[i] = c.ae;
+        x->azc[i] = c.az;
+    }
+    for (int j = 0; j < NZ; j++) {
+        if (g->dz_row) {
+            x->dzr[j] = g->dz_row[j];
+            x->zn[j + 1] = x->zn[j] + x->dzr[j];
+            x->zcn[j] = x->zn[j] + 0.5 * x->dzr[j];
+        } else {
+            x->dzr[j] = g->dz;
+            x->zn[j] = (double)j * g->dz;
+            x->zn[j + 1] = (double)(j + 1) * g->dz;
+            x->zcn[j] = ((double)j + 0.5) * g->dz;
+        }
+    }
+    x->g.dr_col = x->g.dz_row = NULL; /* the tables hold them now */
 
     x->rho = zalloc(NC);
     x->I = zalloc(NC);
@@ -451,18 +551,18 @@ orc_ctx *orc_create(const orc_grid *g, const orc_mat *mats, const orc_pml *pml)
             c = sqrt((m0->A + (4.0 / 3.0) * orc_shear_modulus(m0)) / m0->rho0);
         }
         if (g->pml_b > 0) {
-            double delta = g->pml_b * g->dz;
+            double zf = x->zn[g->pml_b], delta = zf - x->zn[0];
             for (int j = 0; j < g->pml_b; j++)
-                x->dcz[j] = pml_d(c, delta, ((double)(g->pml_b - j) - 0.5) * g->dz, pml->R);
+                x->dcz[j] = pml_d(c, delta, zf - x->zcn[j], pml->R);
             for (int j = 0; j < g->pml_b; j++)
-                x->dnz[j] = pml_d(c, delta, (double)(g->pml_b - j) * g->dz, pml->R);
+                x->dnz[j] = pml_d(c, delta, zf - x->zn[j], pml->R);
         }
         if (g->pml_r > 0) {
-            double delta = g->pml_r * g->dr;
+            double rf = x->rn[g->n_r], delta = x->rn[NR] - rf;
             for (int i = g->n_r; i < NR; i++)
-                x->dcr[i] = pml_d(c, delta, ((double)(i - g->n_r) + 0.5) * g->dr, pml->R);
+                x->dcr[i] = pml_d(c, delta, x->rcn[i] - rf, pml->R);
             for (int i = g->n_r + 1; i <= NR; i++)
-                x->dnr[i] = pml_d(c, delta, (double)(i - g->n_r) * g->dr, pml->R);
+                x->dnr[i] = pml_d(c, delta, x->rn[i] - rf, pml->R);
         }
     }
     return x;
@@ -472,6 +572,7 @@ void orc_destroy(orc_ctx *x)
 {
     if (!x) return;
     double *all[] = {x->rho, x->I, x->srr, x->szz, x->srz, x->vr, x->vz, x->rho_n, x->I_n, x->p0,
+                     x->rn, x->rcn, x->drc, x->awc, x->aec, x->azc, x->zn, x->zcn, x->dzr,
                      x->srr_n, x->szz_n, x->srz_n, x->vr_n, x->vz_n, x->dcz, x->dnz, x->dcr,
                      x->dnr, x->phi1b, x->phi3b, x->psi2b, x->phi1r, x->phi3r, x->psi2r,
                      x->rref, x->msink, x->p, x->c2, x->G, x->Y, x->rmat, x->phi, x->sx, x->Q,
@@ -496,7 +597,6 @@ void orc_destroy(orc_ctx *x)
 static double dt_candidate_min(orc_ctx *x)
 {
     int NR = x->NR, NZ = x->NZ;
-    double L = dmin(x->g.dr, x->g.dz);
     double best = INFINITY;
 #pragma omp parallel for schedule(static) reduction(min : best)
     for (int j = 0; j < NZ; j++) {
@@ -514,6 +614,7 @@ static double dt_candidate_min(orc_ctx *x)
             }
             double w = dmin(dmax((phi - W_LO) / (W_HI - W_LO), 0.0), 1.0);
             if (w > 0.0) {
+                double L = dmin(x->drc[i], x->dzr[j]);
                 double cand = x->g.cfl * L / ((cl + u) * w);
                 if (cand < best) best = cand;
             }
@@ -561,9 +662,9 @@ static void apply_bc(orc_ctx *x, double *vr, double *vz)
 
 /* Lithostatic column of the target rows below surface_j (the initial
  * pressure p0 of Sec. 3's momentum equation, with -grad p0 + rho g = 0).
- * Cell-centre pressures are integrated down from p = 0 at the surface with
- * the trapezoid rule: p(top row) = g dz rho / 2, p(j) = p(j+1) + g dz
- * (rho(j) + rho(j+1)) / 2. Each row's density is the cold (E = 0) compressed
+ * Cell-centre pressures are integrated down from p = 0 at the surface over
+ * the piecewise-constant density: p(top row) = g rho dz / 2, p(j) = p(j+1)
+ * + g (rho(j+1) dz(j+1) / 2 + rho(j) dz(j) / 2). Each row's density is the cold (E = 0) compressed
  * state at its pressure: with p = A mu + B mu^2, mu = 2p / (A + sqrt(A^2 +
  * 4Bp)); since p(j) depends on rho(j) too, the two are iterated to a fixed
  * point (at most 50 times). p0(j) is then set to the equation of state's own
@@ -572,14 +673,16 @@ static void apply_bc(orc_ctx *x, double *vr, double *vz)
  * material. */
 static void lithostatic(orc_ctx *x, int surface_j, const int *mat_row, double g, double *rho_row)
 {
-    double hg = 0.5 * g * x->g.dz;
     for (int j = surface_j - 1; j >= 0; j--) {
         const orc_mat *m = &x->m[mat_row[j]];
-        double p_up = j == surface_j - 1 ? 0.0 : x->p0[j + 1];
-        double r_up = j == surface_j - 1 ? 0.0 : rho_row[j + 1];
+        int top = j == surface_j - 1;
+        double p_up = top ? 0.0 : x->p0[j + 1];
+        /* weight per unit area between the two row centres */
+        double w_up = top ? 0.0 : g * (0.5 * x->dzr[j + 1]) * rho_row[j + 1];
+        double hj = g * (0.5 * x->dzr[j]);
         double r = m->rho0;
         for (int it = 0; it < 50; it++) {
-            double p = p_up + hg * (r_up + r);
+            double p = p_up + (w_up + hj * r);
             double mu = 2.0 * p / (m->A + sqrt(m->A * m->A + 4.0 * m->B * p));
             double rn = m->rho0 * (1.0 + mu);
             if (rn == r) break;
@@ -603,15 +706,15 @@ int orc_init_scene(orc_ctx *x, const orc_scene *s)
     if (s->surface_j < 0 || s->surface_j > x->NZ || s->layer_j < 0 || s->layer_j > s->surface_j) return ORC_E_INVALID;
     int NR = x->NR, NZ = x->NZ, S = s->subsample;
     int mp = x->nmat > 1 ? 1 : 0;
-    double R = s->radius, zc = (double)s->surface_j * x->g.dz + R;
+    double R = s->radius, zc = x->zn[s->surface_j] + R;
     double *fp = zalloc(x->NC);
     for (int j = 0; j < NZ && R > 0; j++) {
         for (int i = 0; i < NR; i++) {
             double num = 0.0, den = 0.0;
             for (int l = 0; l < S; l++) {
-                double zl = ((double)j + ((double)l + 0.5) / (double)S) * x->g.dz;
+                double zl = x->zn[j] + (((double)l + 0.5) / (double)S) * x->dzr[j];
                 for (int k = 0; k < S; k++) {
-                    double rk = ((double)i + ((double)k + 0.5) / (double)S) * x->g.dr;
+                    double rk = x->rn[i] + (((double)k + 0.5) / (double)S) * x->drc[i];
                     double dzl = zl - zc;
                     if (rk * rk + dzl * dzl <= R * R) num += rk;
                     den += rk;
@@ -655,7 +758,7 @@ int orc_init_scene(orc_ctx *x, const orc_scene *s)
             for (int q = 0; q < 4; q++) {
                 if (qi[q] < 0 || qi[q] >= NR || qj[q] < 0 || qj[q] >= NZ) continue;
                 int c = CI(qi[q], qj[q]);
-                double V = vol_c(x, qi[q]);
+                double V = vol_c(x, qi[q], qj[q]);
                 Mt += x->rho[c] * V;
                 Mp += fp[c] * x->m[mp].rho0 * V;
             }
@@ -668,6 +771,16 @@ int orc_init_scene(orc_ctx *x, const orc_scene *s)
     free(rho_row);
     apply_bc(x, x->vr, x->vz);
     start_run(x);
+    return ORC_OK;
+}
+
+int orc_get_geometry(orc_ctx *x, double *r_node, double *r_cell, double *z_node, double *z_cell)
+{
+    if (!x) return ORC_E_INVALID;
+    if (r_node) memcpy(r_node, x->rn, sizeof(double) * ((size_t)x->NR + 1));
+    if (r_cell) memcpy(r_cell, x->rcn, sizeof(double) * (size_t)x->NR);
+    if (z_node) memcpy(z_node, x->zn, sizeof(double) * ((size_t)x->NZ + 1));
+    if (z_cell) memcpy(z_cell, x->zcn, sizeof(double) * (size_t)x->NZ);
     return ORC_OK;
 }
 
@@ -719,17 +832,18 @@ int orc_set_fields(orc_ctx *x, const double *rho, const double *I, const double 
 static void phase_cell_stress(orc_ctx *x)
 {
     int NR = x->NR, NZ = x->NZ;
-    double L = dmin(x->g.dr, x->g.dz);
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < NZ; j++) {
         for (int i = 0; i < NR; i++) {
             int c = CI(i, j);
+            double L = dmin(x->drc[i], x->dzr[j]);
             double p, c2, G, Y, rm, phi, sx;
             mixture(x, c, x->rho, x->I, x->f, &p, &c2, &G, &Y, &rm, &phi, &sx);
             double vr4[4] = {x->vr[NI(i, j)], x->vr[NI(i + 1, j)], x->vr[NI(i, j + 1)], x->vr[NI(i + 1, j + 1)]};
             double vz4[4] = {x->vz[NI(i, j)], x->vz[NI(i + 1, j)], x->vz[NI(i, j + 1)], x->vz[NI(i + 1, j + 1)]};
             kin_t k;
-            kinematics(&x->g, i, vr4, vz4, &k);
+            col_t cg = col_at(x, i);
+            kinematics(&cg, x->dzr[j], vr4, vz4, &k);
             /* compression felt by the material (void closes first) */
             double Jn = 1.0 + x->dt * k.D;
             double Dm = Jn < 1.0 ? (1.0 - material_ratio(Jn, phi, sx)) * (1.0 / x->dt) : 0.0;
@@ -759,7 +873,7 @@ static void phase_cell_stress(orc_ctx *x)
 static void phase_node_force(orc_ctx *x)
 {
     int NR = x->NR, NZ = x->NZ;
-    double dt = x->dt, hdz = 0.5 * x->g.dz;
+    double dt = x->dt;
 #pragma omp parallel for schedule(static)
     for (int j = 0; j <= NZ; j++) {
         for (int i = 0; i <= NR; i++) {
@@ -776,22 +890,24 @@ static void phase_node_force(orc_ctx *x)
                 srz[q] = x->sgrz[c];
                 rh[q] = x->rho[c];
             }
-            double rN = (double)i * x->g.dr;
-            double rE = ((double)i + 0.5) * x->g.dr;
-            double rW = ((double)i - 0.5) * x->g.dr;
-            double aE = i < NR ? 0.5 * (rE * rE - rN * rN) : 0.0;
-            double aW = i > 0 ? 0.5 * (rN * rN - rW * rW) : 0.0;
+            /* dual cell: from the west cell's centre rW to the east cell's
+             * centre rE, half the row above (hN) and half the row below (hS) */
+            double rN = x->rn[i];
+            double rE = i < NR ? x->rcn[i] : 0.0;
+            double rW = i > 0 ? x->rcn[i - 1] : 0.0;
+            double aE = i < NR ? x->awc[i] : 0.0;
+            double aW = i > 0 ? x->aec[i - 1] : 0.0;
+            double hN = j < NZ ? 0.5 * x->dzr[j] : 0.0;
+            double hS = j > 0 ? 0.5 * x->dzr[j - 1] : 0.0;
             /* r-direction (radial faces + hoop) and z-direction (axial faces) parts */
-            double Frr = hdz * ((rE * (srr[0] - stt[0]) + rN * stt[0]) + (rE * (srr[2] - stt[2]) + rN * stt[2]))
-                       - hdz * ((rW * (srr[1] - stt[1]) + rN * stt[1]) + (rW * (srr[3] - stt[3]) + rN * stt[3]));
+            double Frr = (hN * (rE * (srr[0] - stt[0]) + rN * stt[0]) + hS * (rE * (srr[2] - stt[2]) + rN * stt[2]))
+                       - (hN * (rW * (srr[1] - stt[1]) + rN * stt[1]) + hS * (rW * (srr[3] - stt[3]) + rN * stt[3]));
             double Frz = (aW * srz[1] + aE * srz[0]) - (aW * srz[3] + aE * srz[2]);
-            double Fzr = hdz * (rE * (srz[0] + srz[2]) - rW * (srz[1] + srz[3]));
+            double Fzr = rE * (hN * srz[0] + hS * srz[2]) - rW * (hN * srz[1] + hS * srz[3]);
             double Fzz = (aW * szz[1] + aE * szz[0]) - (aW * szz[3] + aE * szz[2]);
             double Fr = Frr + Frz, Fz = Fzr + Fzz;
-            double VcE = aE * hdz, VcW = aW * hdz;
-            double macc = VcE * (rh[0] + rh[2]) + VcW * (rh[1] + rh[3]);
-            double nzh = (double)((j < NZ) + (j > 0));
-            double Vd = (VcE + VcW) * nzh;
+            double macc = (aE * hN * rh[0] + aW * hN * rh[1]) + (aE * hS * rh[2] + aW * hS * rh[3]);
+            double Vd = (aE + aW) * (hN + hS);
             double mt = dmax(macc, M_ACC_EPS * x->rho_ref * Vd);
             int n = NI(i, j);
             double db = x->dnz[j], drr = x->dnr[i];
@@ -831,7 +947,8 @@ static void phase_cell_lagrange(orc_ctx *x)
             double vr4[4] = {x->vLr[NI(i, j)], x->vLr[NI(i + 1, j)], x->vLr[NI(i, j + 1)], x->vLr[NI(i + 1, j + 1)]};
             double vz4[4] = {x->vLz[NI(i, j)], x->vLz[NI(i + 1, j)], x->vLz[NI(i, j + 1)], x->vLz[NI(i + 1, j + 1)]};
             kin_t k;
-            kinematics(&x->g, i, vr4, vz4, &k);
+            col_t cg = col_at(x, i);
+            kinematics(&cg, x->dzr[j], vr4, vz4, &k);
             double s[3] = {x->srr[c], x->szz[c], x->srz[c]};
             if (x->any_strength) {
                 double rt[5] = {k.err, k.ezz, k.ett, k.erz, k.om};
@@ -861,11 +978,10 @@ static void phase_cell_lagrange(orc_ctx *x)
                 double dvr = x->vLr[nd[q]] - x->vr[nd[q]], dvz = x->vLz[nd[q]] - x->vz[nd[q]];
                 kd[q] = 0.5 * (dvr * dvr + dvz * dvz);
             }
-            double rN0 = (double)i * x->g.dr, rC = ((double)i + 0.5) * x->g.dr, rN1 = (double)(i + 1) * x->g.dr;
-            double V = vol_c(x, i), hdz = 0.5 * x->g.dz;
+            double V = vol_c(x, i, j), hdz = 0.5 * x->dzr[j];
             double iV = 1.0 / V;
-            double wW = (0.5 * (rC * rC - rN0 * rN0) * hdz) * iV;
-            double wE = (0.5 * (rN1 * rN1 - rC * rC) * hdz) * iV;
+            double wW = (cg.aw * hdz) * iV;
+            double wE = (cg.ae * hdz) * iV;
             double hL = wW * (kd[0] + kd[2]) + wE * (kd[1] + kd[3]);
             x->IL[c] = ((x->I[c] + Wdt / rden) + hL) - dt * (psi2 / rt_);
             for (int m = 0; m < x->nmat; m++) x->fL[m][c] = x->f[m][c] * (Jm / J);
@@ -912,16 +1028,13 @@ static void phase_faces(orc_ctx *x)
     for (int j = 0; j < NZ; j++) {
         for (int i = 0; i <= NR; i++) {
             double u = 0.5 * (x->vLr[NI(i, j)] + x->vLr[NI(i, j + 1)]);
-            x->dVr[RF(i, j)] = dt * (area_r(x, i) * u);
+            x->dVr[RF(i, j)] = dt * (area_r(x, i, j) * u);
         }
     }
 #pragma omp parallel for schedule(static)
     for (int j = 0; j <= NZ; j++) {
         for (int i = 0; i < NR; i++) {
-            double rw = (double)i * x->g.dr, rc = ((double)i + 0.5) * x->g.dr;
-            double re = (double)(i + 1) * x->g.dr;
-            double aw = 0.5 * (rc * rc - rw * rw), ae = 0.5 * (re * re - rc * rc);
-            x->dVz[AF(i, j)] = dt * (aw * x->vLz[NI(i, j)] + ae * x->vLz[NI(i + 1, j)]);
+            x->dVz[AF(i, j)] = dt * (x->awc[i] * x->vLz[NI(i, j)] + x->aec[i] * x->vLz[NI(i + 1, j)]);
         }
     }
 #pragma omp parallel for schedule(static)
@@ -930,7 +1043,7 @@ static void phase_faces(orc_ctx *x)
             int c = CI(i, j);
             double O = ((dmax(-x->dVr[RF(i, j)], 0.0) + dmax(x->dVr[RF(i + 1, j)], 0.0))
                         + dmax(-x->dVz[AF(i, j)], 0.0)) + dmax(x->dVz[AF(i, j + 1)], 0.0);
-            double VL = vol_c(x, i) * x->J[c];
+            double VL = vol_c(x, i, j) * x->J[c];
             x->outv[c] = O;
             x->lam[c] = O > VL ? dmax(VL, 0.0) / O : 1.0;
         }
@@ -978,7 +1091,7 @@ static void phase_cell_remap(orc_ctx *x)
     for (int j = 0; j < NZ; j++) {
         for (int i = 0; i < NR; i++) {
             int c = CI(i, j);
-            double V = vol_c(x, i);
+            double V = vol_c(x, i, j);
             /* faces W, E, S, N: flux (positive along +r / +z), donor cell, inflow flag */
             double F[4] = {x->Fr[RF(i, j)], x->Fr[RF(i + 1, j)], x->Fz[AF(i, j)], x->Fz[AF(i, j + 1)]};
             double dV[4] = {x->dVr[RF(i, j)], x->dVr[RF(i + 1, j)], x->dVz[AF(i, j)], x->dVz[AF(i, j + 1)]};
@@ -1083,7 +1196,7 @@ static double Fz_at(const orc_ctx *x, int i, int j)
 static void phase_node_remap(orc_ctx *x)
 {
     int NR = x->NR, NZ = x->NZ;
-    double dt = x->dt, hdz = 0.5 * x->g.dz;
+    double dt = x->dt;
 #pragma omp parallel for schedule(static)
     for (int j = 0; j <= NZ; j++) {
         for (int i = 0; i <= NR; i++) {
@@ -1093,7 +1206,7 @@ static void phase_node_remap(orc_ctx *x)
             int qi[4] = {i - 1, i, i - 1, i}, qj[4] = {j - 1, j - 1, j, j};
             for (int q = 0; q < 4; q++) {
                 if (qi[q] < 0 || qi[q] >= NR || qj[q] < 0 || qj[q] >= NZ) continue;
-                M[q] = x->rho[CI(qi[q], qj[q])] * vol_c(x, qi[q]);
+                M[q] = x->rho[CI(qi[q], qj[q])] * vol_c(x, qi[q], qj[q]);
             }
             double mL = 0.25 * ((M[0] + M[1]) + (M[2] + M[3]));
             /* dual faces W, E, S, N */
@@ -1126,13 +1239,11 @@ static void phase_node_remap(orc_ctx *x)
                     upz[q] = vLz;
                 }
             }
-            double rN = (double)i * x->g.dr;
-            double rE = ((double)i + 0.5) * x->g.dr;
-            double rW = ((double)i - 0.5) * x->g.dr;
-            double aE = i < NR ? 0.5 * (rE * rE - rN * rN) : 0.0;
-            double aW = i > 0 ? 0.5 * (rN * rN - rW * rW) : 0.0;
-            double nzh = (double)((j < NZ) + (j > 0));
-            double Vd = (aE * hdz + aW * hdz) * nzh;
+            double aE = i < NR ? x->awc[i] : 0.0;
+            double aW = i > 0 ? x->aec[i - 1] : 0.0;
+            double hN = j < NZ ? 0.5 * x->dzr[j] : 0.0;
+            double hS = j > 0 ? 0.5 * x->dzr[j - 1] : 0.0;
+            double Vd = (aE + aW) * (hN + hS);
             double den = dmax(dmax(m1, min_), M_REMAP_FLOOR * x->rho_ref * Vd);
             double iden = 1.0 / den;
             double v1r = vLr + nr * iden;
@@ -1152,7 +1263,7 @@ static void phase_node_remap(orc_ctx *x)
             double Mn = 0.0;
             for (int q = 0; q < 4; q++) {
                 if (qi[q] < 0 || qi[q] >= NR || qj[q] < 0 || qj[q] >= NZ) continue;
-                Mn += x->rho_n[CI(qi[q], qj[q])] * vol_c(x, qi[q]);
+                Mn += x->rho_n[CI(qi[q], qj[q])] * vol_c(x, qi[q], qj[q]);
             }
             x->heat[n] = Mn > M_REMAP_FLOOR * x->rho_ref * Vd ? dmax(dKE, 0.0) / Mn : 0.0;
             double db = x->dnz[j], drr = x->dnr[i];
@@ -1343,7 +1454,7 @@ int orc_diag(orc_ctx *x, double *out)
     for (int j = 0; j < NZ; j++)
         for (int i = 0; i < NR; i++) {
             int c = CI(i, j);
-            double M = x->rho[c] * vol_c(x, i);
+            double M = x->rho[c] * vol_c(x, i, j);
             kadd(&mass, M);
             kadd(&ie, M * x->I[c]);
             kadd(&mp, x->msink[c]);
@@ -1355,7 +1466,7 @@ int orc_diag(orc_ctx *x, double *out)
             double Mq[4] = {0, 0, 0, 0};
             for (int q = 0; q < 4; q++) {
                 if (qi[q] < 0 || qi[q] >= NR || qj[q] < 0 || qj[q] >= NZ) continue;
-                Mq[q] = x->rho[CI(qi[q], qj[q])] * vol_c(x, qi[q]);
+                Mq[q] = x->rho[CI(qi[q], qj[q])] * vol_c(x, qi[q], qj[q]);
             }
             M = 0.25 * ((Mq[0] + Mq[1]) + (Mq[2] + Mq[3]));
             int n = NI(i, j);

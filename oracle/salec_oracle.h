@@ -47,6 +47,9 @@ typedef struct {
     double dt_max, dt_floor;
     double t_stop;      /* >0: clip the step so that t never passes t_stop  */
     double q_lin, q_quad; /* artificial viscosity coefficients C1, C2       */
+    /* stretched grid (Table 2's extension zones): per-column widths (NR
+     * values) and per-row heights (NZ values), or NULL for uniform dr / dz */
+    const double *dr_col, *dz_row;
 } orc_grid;
 
 typedef struct {
@@ -114,8 +117,10 @@ double orc_softening(const orc_mat *m, double e);
 void orc_stress_update(double G, double Y, double dt, const double *rates, double *s);
 /* strain rates of cell (i, j) from its four node velocities
  * vr[4], vz[4] ordered SW, SE, NW, NE -> out = (e_rr, e_zz, e_tt, e_rz, omega, D) */
-void orc_cell_kinematics(const orc_grid *g, int32_t i, const double *vr,
+void orc_cell_kinematics(const orc_grid *g, int32_t i, int32_t j, const double *vr,
                          const double *vz, double *out);
+/* geometry tables: r_node[NR+1], r_cell[NR], z_node[NZ+1], z_cell[NZ] */
+int orc_get_geometry(orc_ctx *x, double *r_node, double *r_cell, double *z_node, double *z_cell);
 
 #ifdef __cplusplus
 }

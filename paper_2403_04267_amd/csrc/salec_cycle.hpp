@@ -42,6 +42,13 @@ struct Regions {
   static constexpr int ZW = TW + 2, ZH = TH + 3, NZF = ZW * ZH;  // axial faces, origin (i0-1, j0-1)
 };
 
+// LDS copy of a stretched tile's geometry: six column fields over columns
+// [i0-3, i0+TW+5), then the row heights over rows [j0-3, j0+TH+5)
+template <int TW, int TH>
+struct GeoLds {
+  static constexpr int GC = TW + 8, GR = TH + 8, N = 6 * GC + GR;
+};
+
 template <int TW, int TH, class T>
 struct Smem {
   using R = Regions<TW, TH>;
@@ -57,14 +64,14 @@ __device__ __forceinline__ bool in_cells(const Geo& g, int i, int j) {
 }
 
 // Courant candidate of one cell of a new state, and its EoS (cached for the
-// next cycle). u4 is the largest corner speed.
+// next cycle). u4 is the largest corner speed, L = min(dr, dz) of the cell.
 template <class T>
-__device__ __forceinline__ double cell_dt(const Geo& g, const Mix<T>& mx, T u4) {
+__device__ __forceinline__ double cell_dt(const Geo& g, const Mix<T>& mx, T u4, double L) {
   using N = Num<T>;
   T cl2 = mx.c2 + N::div(T(4.0 / 3.0) * mx.G, tmax(mx.rmat, GeoT<T>::rho_ref(g) * T(kRhoDenFloor)));
   T cl = N::sqr(cl2);
   T wgt = tmin(tmax(N::div(mx.phi - T(kWLo), T(kWHi - kWLo)), T(0)), T(1));
-  if (wgt > T(0)) return g.cfl * dmin(g.dr, g.dz) / (((double)cl + (double)u4) * (double)wgt);
+  if (wgt > T(0)) return g.cfl * L / (((double)cl + (double)u4) * (double)wgt);
   return __builtin_huge_val();
 }
 
@@ -102,9 +109,10 @@ __device__ __forceinline__ void reg_put(T (&a)[N], int u, T v) {
   for (int q = 0; q < N; q++) a[q] = (u == q) ? v : a[q];
 }
 
-template <int TW, int TH, int NT, int WPE, class T>
+template <int TW, int TH, int NT, int WPE, class T, bool GEO>
 __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_rho, double* s_bigd, T* s_vL,
-                                           double* s_Fr, double* s_Fz, double* s_rho1, double* s_min) {
+                                           double* s_Fr, double* s_Fz, double* s_rho1, double* s_min,
+                                           double* s_geo) {
   using R = Regions<TW, TH>;
   using N = Num<T>;
   using GT = GeoT<T>;
@@ -130,9 +138,37 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   const T* Ss2 = (const T*)S.s[2];
   const double dt = sc->dt;
   const T dtT = (T)dt;
-  const T dr = GT::dr(g), dz = GT::dz(g);
-  const T hdz = T(0.5) * dz;
-  const double hdzd = 0.5 * g.dz;
+  // Grid geometry: the uniform-grid kernel evaluates it from i and j; the
+  // table kernel (GEO, launched when any instance is stretched) reads each
+  // tile's columns and rows from the instance's table, staged in LDS first.
+  using GL = GeoLds<TW, TH>;
+  constexpr bool st = GEO;
+  if constexpr (st) {
+    const int gs = g.NR + 1;
+    const double* grow = in.geo + 6 * gs;
+    for (int k = tid; k < GL::N; k += NT) {
+      double v = 0.0;
+      if (k < 6 * GL::GC) {
+        int f = k / GL::GC, i = i0 - 3 + (k - f * GL::GC);
+        if (i >= 0 && i <= g.NR) v = in.geo[f * gs + i];
+      } else {
+        int j = j0 - 3 + (k - 6 * GL::GC);
+        if (j >= 0 && j < g.NZ) v = grow[j];
+      }
+      s_geo[k] = v;
+    }
+    __syncthreads();
+  }
+  auto colT = [&](int i) -> Col<T> {
+    return st ? col_fields<T>(s_geo, GL::GC, i - (i0 - 3)) : col_uniform<T>(g, i);
+  };
+  auto colD = [&](int i) -> Col<double> {
+    return st ? col_fields<double>(s_geo, GL::GC, i - (i0 - 3)) : col_uniform<double>(g, i);
+  };
+  auto dzD = [&](int j) -> double { return st ? s_geo[6 * GL::GC + (j - (j0 - 3))] : g.dz; };
+  auto dzT = [&](int j) -> T { return st ? (T)s_geo[6 * GL::GC + (j - (j0 - 3))] : GT::dz(g); };
+  auto volD = [&](int i, int j) { return colD(i).az * dzD(j); };
+  auto volT = [&](int i, int j) { return colT(i).az * dzT(j); };
   auto owns_cell = [&](int i, int j) { return i >= i0 && i < i1 && j >= j0 && j < j1; };
   auto owns_node = [&](int i, int j) {
     bool oi = (i >= i0 && i < i1) || (i == g.NR && i1 == g.NR);
@@ -216,8 +252,10 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       T p = ((const T*)S.eos[0])[c], c2 = ((const T*)S.eos[1])[c], sx = ((const T*)S.eos[4])[c];
       T vr4[4] = {v0r, Sv0[nidx(g, i + 1, j)], Sv0[nidx(g, i, j + 1)], Sv0[nidx(g, i + 1, j + 1)]};
       T vz4[4] = {v0z, Sv1[nidx(g, i + 1, j)], Sv1[nidx(g, i, j + 1)], Sv1[nidx(g, i + 1, j + 1)]};
-      Kin<T> kn = kinematics(g, i, vr4, vz4);
-      T L = tmin(dr, dz);
+      const Col<T> cg = colT(i);
+      const T dzj = dzT(j);
+      Kin<T> kn = kinematics(cg, dzj, vr4, vz4);
+      T L = tmin(cg.dr, dzj);
       T dDn = dtT * kn.D;
       T Jn = T(1) + dDn;
       T Dm = Jn < T(1) ? Vol<T>::closing(Jn, dDn, phi, sx) * N::div(T(1), dtT) : T(0);
@@ -271,21 +309,24 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         srz[q] = sig[3 * R::NA + qa[q]];
         rh[q] = (T)s_rho[qa[q]];
       }
-      T rN = (T)i * dr;
-      T rE = ((T)i + T(0.5)) * dr;
-      T rW = ((T)i - T(0.5)) * dr;
-      T aE = i < g.NR ? Ring<T>::w(g, i) : T(0);
-      T aW = i > 0 ? Ring<T>::e(g, i - 1) : T(0);
-      T Frr = hdz * ((rE * (srr[0] - stt[0]) + rN * stt[0]) + (rE * (srr[2] - stt[2]) + rN * stt[2])) -
-              hdz * ((rW * (srr[1] - stt[1]) + rN * stt[1]) + (rW * (srr[3] - stt[3]) + rN * stt[3]));
+      // dual cell: from the west cell's centre rW to the east cell's centre
+      // rE, half the row above (hN) and half the row below (hS)
+      const Col<T> ce = colT(i), cw = colT(i - 1);
+      T rN = ce.rw;
+      T rE = i < g.NR ? ce.rc : T(0);
+      T rW = i > 0 ? cw.rc : T(0);
+      T aE = i < g.NR ? ce.aw : T(0);
+      T aW = i > 0 ? cw.ae : T(0);
+      T hN = j < g.NZ ? T(0.5) * dzT(j) : T(0);
+      T hS = j > 0 ? T(0.5) * dzT(j - 1) : T(0);
+      T Frr = (hN * (rE * (srr[0] - stt[0]) + rN * stt[0]) + hS * (rE * (srr[2] - stt[2]) + rN * stt[2])) -
+              (hN * (rW * (srr[1] - stt[1]) + rN * stt[1]) + hS * (rW * (srr[3] - stt[3]) + rN * stt[3]));
       T Frz = (aW * srz[1] + aE * srz[0]) - (aW * srz[3] + aE * srz[2]);
-      T Fzr = hdz * (rE * (srz[0] + srz[2]) - rW * (srz[1] + srz[3]));
+      T Fzr = rE * (hN * srz[0] + hS * srz[2]) - rW * (hN * srz[1] + hS * srz[3]);
       T Fzz = (aW * szz[1] + aE * szz[0]) - (aW * szz[3] + aE * szz[2]);
       T Fr = Frr + Frz, Fz = Fzr + Fzz;
-      T VcE = aE * hdz, VcW = aW * hdz;
-      T macc = VcE * (rh[0] + rh[2]) + VcW * (rh[1] + rh[3]);
-      T nzh = (T)((j < g.NZ) + (j > 0));
-      T Vd = (VcE + VcW) * nzh;
+      T macc = (aE * hN * rh[0] + aW * hN * rh[1]) + (aE * hS * rh[2] + aW * hS * rh[3]);
+      T Vd = (aE + aW) * (hN + hS);
       T mt = tmax(macc, T(kMAccEps) * GT::rho_ref(g) * Vd);
       T psr = T(0), psz = T(0);
       double db = 0.0, drr = 0.0;
@@ -334,13 +375,11 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   // column i with dual-area node weights)
   auto dv_r = [&](int i, int j) {
     T u = T(0.5) * (s_vL[kB(i, j)] + s_vL[kB(i, j + 1)]);
-    return dtT * ((((T)i * dr) * dz) * u);
+    return dtT * ((colT(i).rw * dzT(j)) * u);
   };
   auto dv_z = [&](int i, int j) {
-    T rw = (T)i * dr, rc = ((T)i + T(0.5)) * dr;
-    T re = (T)(i + 1) * dr;
-    T aw = Ring<T>::w(g, i), ae = Ring<T>::e(g, i);
-    return dtT * (aw * s_vL[R::NB + kB(i, j)] + ae * s_vL[R::NB + kB(i + 1, j)]);
+    const Col<T> c = colT(i);
+    return dtT * (c.aw * s_vL[R::NB + kB(i, j)] + c.ae * s_vL[R::NB + kB(i + 1, j)]);
   };
 
   // ------------------------------------------------------------------ C
@@ -365,7 +404,9 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         vr4[q] = s_vL[nb[q]];
         vz4[q] = s_vL[R::NB + nb[q]];
       }
-      Kin<T> kn = kinematics(g, i, vr4, vz4);
+      const Col<T> cg = colT(i);
+      const T dzj = dzT(j);
+      Kin<T> kn = kinematics(cg, dzj, vr4, vz4);
       T s0rr = T(0), s0zz = T(0), s0rz = T(0);
       if (kKeepA) {
         s0rr = reg_get(rS0, u);
@@ -414,11 +455,11 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       T kd[4];
 #pragma unroll
       for (int q = 0; q < 4; q++) kd[q] = s_kd[nb[q]];
-      T rN0 = (T)i * dr, rC = ((T)i + T(0.5)) * dr, rN1 = (T)(i + 1) * dr;
-      T V = cell_volume<T>(g, i);
+      T V = cg.az * dzj;
       T iV = N::div(T(1), V);
-      T wW = (Ring<T>::w(g, i) * hdz) * iV;
-      T wE = (Ring<T>::e(g, i) * hdz) * iV;
+      T hdz = T(0.5) * dzj;
+      T wW = (cg.aw * hdz) * iV;
+      T wE = (cg.ae * hdz) * iV;
       T hL = wW * (kd[0] + kd[2]) + wE * (kd[1] + kd[3]);
       double psi2 = 0.0, db = 0.0, drr = 0.0;
       long long kb = -1, kr = -1;
@@ -477,7 +518,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     T J = ct[0 * R::NC + kc];
     T dW = dv_r(i, j), dE = dv_r(i + 1, j), dS = dv_z(i, j), dN = dv_z(i, j + 1);
     T O = ((tmax(-dW, T(0)) + tmax(dE, T(0))) + tmax(-dS, T(0))) + tmax(dN, T(0));
-    T VL = cell_volume<T>(g, i) * J;
+    T VL = volT(i, j) * J;
     ct[0 * R::NC + kc] = O > VL ? N::div(tmax(VL, T(0)), O) : T(1);
   }
   __syncthreads();
@@ -526,7 +567,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     double rho1 = 0.0;
     if (in_cells(g, i, j)) {
       bool own = owns_cell(i, j);
-      double V = cell_volume<double>(g, i);
+      double V = volD(i, j);
       T dV[4] = {dv_r(i, j), dv_r(i + 1, j), dv_z(i, j), dv_z(i, j + 1)};
       double F[4] = {s_Fr[kR(i, j)], s_Fr[kR(i + 1, j)], s_Fz[kZ(i, j)], s_Fz[kZ(i, j + 1)]};
       const int dk[4] = {kC(i - 1, j), kC(i + 1, j), kC(i, j - 1), kC(i, j + 1)};
@@ -648,7 +689,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
 #pragma unroll
     for (int q = 0; q < 4; q++) {
       qok[q] = in_cells(g, qi[q], qj[q]);
-      if (qok[q]) M[q] = s_rho[kA(qi[q], qj[q])] * cell_volume<double>(g, qi[q]);
+      if (qok[q]) M[q] = s_rho[kA(qi[q], qj[q])] * volD(qi[q], qj[q]);
     }
     double mL = 0.25 * ((M[0] + M[1]) + (M[2] + M[3]));
     double FD[4];
@@ -684,13 +725,11 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         upz[q] = vLz;
       }
     }
-    double rN = (double)i * g.dr;
-    double rE = ((double)i + 0.5) * g.dr;
-    double rW = ((double)i - 0.5) * g.dr;
-    double aE = i < g.NR ? 0.5 * (rE * rE - rN * rN) : 0.0;
-    double aW = i > 0 ? 0.5 * (rN * rN - rW * rW) : 0.0;
-    double nzh = (double)((j < g.NZ) + (j > 0));
-    double Vd = (aE * hdzd + aW * hdzd) * nzh;
+    double aE = i < g.NR ? colD(i).aw : 0.0;
+    double aW = i > 0 ? colD(i - 1).ae : 0.0;
+    double hN = j < g.NZ ? 0.5 * dzD(j) : 0.0;
+    double hS = j > 0 ? 0.5 * dzD(j - 1) : 0.0;
+    double Vd = (aE + aW) * (hN + hS);
     double den = dmax(dmax(m1, min_), kMRemapFloor * g.rho_ref * Vd);
     double iden = 1.0 / den;
     double v1r = (double)vLr + nr * iden;
@@ -706,7 +745,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     double Mn = 0.0;
 #pragma unroll
     for (int q = 0; q < 4; q++)
-      if (qok[q]) Mn += s_rho1[kE(qi[q], qj[q])] * cell_volume<double>(g, qi[q]);
+      if (qok[q]) Mn += s_rho1[kE(qi[q], qj[q])] * volD(qi[q], qj[q]);
     double h = Mn > kMRemapFloor * g.rho_ref * Vd ? dmax(dKE, 0.0) / Mn : 0.0;
     bool own = owns_node(i, j);
     if (g.pml_on) {
@@ -779,14 +818,14 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     double f[kMaxMat] = {kCarry ? eF0[u] : D.f[0][c], kCarry ? eF1[u] : (g.nmat > 1 ? D.f[1][c] : 0.0)};
     Mix<T> mx = mixture<T>(g, kCarry ? eRho[u] : D.rho[c], I1, f);
     store_eos(D, c, mx);
-    cand = dmin(cand, cell_dt(g, mx, u4));
+    cand = dmin(cand, cell_dt(g, mx, u4, dmin(colD(i).dr, dzD(j))));
   }
   if (flags) atomicOr(&sc->flags, flags);
   double m = block_min<NT>(cand, s_min);
   if (tid == 0) in.dtpart[tile] = m;
 }
 
-template <int TW, int TH, int NT, int WPE, class T>
+template <int TW, int TH, int NT, int WPE, class T, bool GEO>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_cycle(const Inst* __restrict__ insts, const TileRef* __restrict__ sched,
                                               int nsched) {
   using R = Regions<TW, TH>;
@@ -797,6 +836,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   __shared__ double s_F[R::NRF + R::NZF];  // B..C: node KE defect; E1..F: face mass fluxes
   __shared__ double s_rho1[R::NE];    // rho^{n+1} over E (0 outside the grid)
   __shared__ double s_min[NT / 64];
+  __shared__ double s_geo[GEO ? GeoLds<TW, TH>::N : 1];  // a stretched tile's geometry
   // Descriptors and schedule are read-only for the whole launch: reading them
   // through the constant address space lets the compiler keep or re-issue
   // those scalar loads freely across the workgroup barriers below.
@@ -808,7 +848,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     const TileRef tr{csched[e].inst, csched[e].tile};
     if (tr.inst < 0) continue;
     const Inst* in = (const Inst*)(cinst + tr.inst);
-    tile_cycle<TW, TH, NT, WPE, T>(*in, tr.tile, s_rho, s_bigd, s_vL, s_F, s_F + R::NRF, s_rho1, s_min);
+    tile_cycle<TW, TH, NT, WPE, T, GEO>(*in, tr.tile, s_rho, s_bigd, s_vL, s_F, s_F + R::NRF, s_rho1, s_min, s_geo);
     __syncthreads();  // LDS is reused by the next entry
   }
 }
@@ -835,7 +875,7 @@ __global__ void k_prime(Inst in) {
       T a = ((const T*)S.v[0])[nd[q]], b = ((const T*)S.v[1])[nd[q]];
       u4 = tmax(u4, Num<T>::sqr(a * a + b * b));
     }
-    cand = cell_dt(g, mx, u4);
+    cand = cell_dt(g, mx, u4, dmin(col_of<double>(g, in.geo, i).dr, dz_of(g, in.geo, j)));
   }
   for (int off = 32; off > 0; off >>= 1) cand = dmin(cand, __shfl_down(cand, off, 64));
   __shared__ double part[4];
@@ -850,22 +890,38 @@ __global__ void k_prime(Inst in) {
 // Instantiates the cycle kernel of every tile shape and the priming kernel
 // for one bulk type (one translation unit per type keeps builds parallel).
 #define SALEC_CYCLE_TABLE(T, suffix)                                                         \
-  CycleFn cycle_kernel_##suffix(int v) {                                                       \
-    switch (v) {                                                                               \
-      case 0: return k_cycle<64, 14, 768, 3, T>;                                             \
-      case 1: return k_cycle<40, 16, 512, 4, T>;                                             \
-      case 2: return k_cycle<32, 20, 512, 4, T>;                                             \
-      case 3: return k_cycle<64, 15, 768, 3, T>;                                             \
-      case 4: return k_cycle<64, 16, 768, 3, T>;                                             \
-      case 5: return k_cycle<48, 20, 768, 3, T>;                                             \
-      case 6: return k_cycle<40, 24, 768, 3, T>;                                             \
-      case 7: return k_cycle<28, 18, 512, 4, T>;                                             \
-      case 8: return k_cycle<64, 16, 1024, 4, T>;                                            \
-      case 9: return k_cycle<32, 32, 1024, 4, T>;                                            \
-      case 10: return k_cycle<20, 13, 256, 3, T>;                                            \
-      default: return nullptr;                                                                 \
-    }                                                                                          \
-  }                                                                                            \
+  CycleFn cycle_kernel_##suffix(int v) {                                                     \
+    switch (v) {                                                                             \
+      case 0: return k_cycle<64, 14, 768, 3, T, false>;                                      \
+      case 1: return k_cycle<40, 16, 512, 4, T, false>;                                      \
+      case 2: return k_cycle<32, 20, 512, 4, T, false>;                                      \
+      case 3: return k_cycle<64, 15, 768, 3, T, false>;                                      \
+      case 4: return k_cycle<64, 16, 768, 3, T, false>;                                      \
+      case 5: return k_cycle<48, 20, 768, 3, T, false>;                                      \
+      case 6: return k_cycle<40, 24, 768, 3, T, false>;                                      \
+      case 7: return k_cycle<28, 18, 512, 4, T, false>;                                      \
+      case 8: return k_cycle<64, 16, 1024, 4, T, false>;                                     \
+      case 9: return k_cycle<32, 32, 1024, 4, T, false>;                                     \
+      case 10: return k_cycle<20, 13, 256, 3, T, false>;                                     \
+      default: return nullptr;                                                               \
+    }                                                                                        \
+  }                                                                                          \
+  CycleFn cycle_kernel_geo_##suffix(int v) {                                                 \
+    switch (v) {                                                                             \
+      case 0: return k_cycle<64, 14, 768, 3, T, true>;                                       \
+      case 1: return k_cycle<40, 16, 512, 4, T, true>;                                       \
+      case 2: return k_cycle<32, 20, 512, 4, T, true>;                                       \
+      case 3: return k_cycle<64, 15, 768, 3, T, true>;                                       \
+      case 4: return k_cycle<64, 16, 768, 3, T, true>;                                       \
+      case 5: return k_cycle<48, 20, 768, 3, T, true>;                                       \
+      case 6: return k_cycle<40, 24, 768, 3, T, true>;                                       \
+      case 7: return k_cycle<28, 18, 512, 4, T, true>;                                       \
+      case 8: return k_cycle<64, 16, 1024, 4, T, true>;                                      \
+      case 9: return k_cycle<32, 32, 1024, 4, T, true>;                                      \
+      case 10: return k_cycle<20, 13, 256, 3, T, true>;                                      \
+      default: return nullptr;                                                               \
+    }                                                                                        \
+  }                                                                                          \
   hipError_t launch_prime_##suffix(const Inst& in, hipStream_t st) {                           \
     long long nc = (long long)in.g.NR * in.g.NZ;                                               \
     hipLaunchKernelGGL(k_prime<T>, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, in); \

@@ -49,7 +49,8 @@ struct Geo {
   int any_strength, pml_on;
   int same_mat;        // all materials share every constant: evaluate the laws once
   int prec;            // 0: FP64 throughout; 1: FP32 bulk with FP64 energy, mass and volume sums
-  int has_p0, pad_i;   // nonzero initial (lithostatic) pressure profile
+  int has_p0;          // nonzero initial (lithostatic) pressure profile
+  int stretched;       // per-column widths / per-row heights from the geometry table
   double dr, dz, cfl, dt_grow, dt_max, dt_floor, t_stop, q_lin, q_quad;
   double rho_ref;
   float drf, dzf, q_linf, q_quadf, rho_reff, pad_f;
@@ -121,6 +122,11 @@ struct Inst {
   double* dtpart;         // per-tile Courant minima
   double *mout, *eout;    // per-column outflow budgets (mass, internal energy)
   const double* p0;       // initial pressure per cell row (read when g.has_p0)
+  // geometry table of a stretched grid (read when g.stretched): six column
+  // fields of NR + 1 entries (node radius, centre radius, width, west / east
+  // half areas, area per unit height), then the row heights and the node
+  // heights (NZ + 1 entries each)
+  const double* geo;
   int tiles_r, tiles_z;   // tile grid of this instance
   int ntiles, pad;
 };
@@ -419,31 +425,72 @@ template <> struct Vol<float> {
   }
 };
 
-// r-weighted areas of the west and east halves of cell column i,
-// 0.5 (r_{i+1/2}^2 - r_i^2) and 0.5 (r_{i+1}^2 - r_{i+1/2}^2) (per radian,
-// per unit height). FP64 evaluates them as written; FP32 uses the exact
-// factored forms dr^2 (2i + 1/2) / 4 and dr^2 (2i + 3/2) / 4, since the
-// difference of squares cancels at large radius. The west and east halves
-// of node i are ring_w(i) and ring_e(i - 1).
-template <class T> struct Ring;
-template <> struct Ring<double> {
-  static __device__ __forceinline__ double w(const Geo& g, int i) {
-    double rw = (double)i * g.dr, rc = ((double)i + 0.5) * g.dr;
-    return 0.5 * (rc * rc - rw * rw);
-  }
-  static __device__ __forceinline__ double e(const Geo& g, int i) {
-    double rc = ((double)i + 0.5) * g.dr, re = (double)(i + 1) * g.dr;
-    return 0.5 * (re * re - rc * rc);
-  }
+// Geometry of one cell column (per radian): node radii rw, re, centre radius
+// rc, width dr, the r-weighted areas of its west and east halves
+// aw = 0.5 (rc^2 - rw^2), ae = 0.5 (re^2 - rc^2), and its area per unit
+// height az = rc dr. The west and east halves of node i are aw(i) and
+// ae(i - 1).
+template <class T>
+struct Col {
+  T rw, re, rc, dr, aw, ae, az;
 };
-template <> struct Ring<float> {
-  static __device__ __forceinline__ float w(const Geo& g, int i) {
-    return (0.25f * g.drf * g.drf) * (2.0f * (float)i + 0.5f);
-  }
-  static __device__ __forceinline__ float e(const Geo& g, int i) {
-    return (0.25f * g.drf * g.drf) * (2.0f * (float)i + 1.5f);
-  }
-};
+
+// Column i of a uniform grid. FP64 evaluates the half areas as written; FP32
+// uses the exact factored forms dr^2 (2i + 1/2) / 4 and dr^2 (2i + 3/2) / 4,
+// since the difference of squares cancels at large radius.
+template <class T> __device__ Col<T> col_uniform(const Geo& g, int i);
+template <>
+__device__ __forceinline__ Col<double> col_uniform<double>(const Geo& g, int i) {
+  Col<double> c;
+  c.rw = (double)i * g.dr;
+  c.re = (double)(i + 1) * g.dr;
+  c.rc = ((double)i + 0.5) * g.dr;
+  c.dr = g.dr;
+  c.aw = 0.5 * (c.rc * c.rc - c.rw * c.rw);
+  c.ae = 0.5 * (c.re * c.re - c.rc * c.rc);
+  c.az = c.rc * g.dr;
+  return c;
+}
+template <>
+__device__ __forceinline__ Col<float> col_uniform<float>(const Geo& g, int i) {
+  Col<float> c;
+  c.rw = (float)i * g.drf;
+  c.re = (float)(i + 1) * g.drf;
+  c.rc = ((float)i + 0.5f) * g.drf;
+  c.dr = g.drf;
+  c.aw = (0.25f * g.drf * g.drf) * (2.0f * (float)i + 0.5f);
+  c.ae = (0.25f * g.drf * g.drf) * (2.0f * (float)i + 1.5f);
+  c.az = c.rc * g.drf;
+  return c;
+}
+
+// Column i from six FP64 fields with the given stride (0 <= i <= NR; at
+// i = NR only the node radius is meaningful).
+template <class T>
+__device__ __forceinline__ Col<T> col_fields(const double* t, int stride, int i) {
+  Col<T> c;
+  c.rw = (T)t[i];
+  c.re = (T)t[i + 1];
+  c.rc = (T)t[stride + i];
+  c.dr = (T)t[2 * stride + i];
+  c.aw = (T)t[3 * stride + i];
+  c.ae = (T)t[4 * stride + i];
+  c.az = (T)t[5 * stride + i];
+  return c;
+}
+
+// Column geometry, row height and node height of an instance, from its
+// table when the grid is stretched (kernels outside the cycle kernel).
+template <class T>
+__device__ __forceinline__ Col<T> col_of(const Geo& g, const double* geo, int i) {
+  return g.stretched ? col_fields<T>(geo, g.NR + 1, i) : col_uniform<T>(g, i);
+}
+__device__ __forceinline__ double dz_of(const Geo& g, const double* geo, int j) {
+  return g.stretched ? geo[6 * (g.NR + 1) + j] : g.dz;
+}
+__device__ __forceinline__ double zn_of(const Geo& g, const double* geo, int j) {
+  return g.stretched ? geo[6 * (g.NR + 1) + (g.NZ + 1) + j] : (double)j * g.dz;
+}
 
 // ------------------------------------------------------------------ kinematics
 template <class T>
@@ -451,25 +498,23 @@ struct Kin {
   T D, Dr, Dz, err, ezz, ett, erz, om, dvr_dz, dvz_dr;
 };
 
-// Face-mean velocities and rates of cell column i from the corner velocities
-// (SW, SE, NW, NE). Axial faces weight their nodes by the r-weighted areas of
-// the node dual cells, so the node force is the exact volume gradient.
+// Face-mean velocities and rates of a cell of column c and height dz from
+// the corner velocities (SW, SE, NW, NE). Axial faces weight their nodes by
+// the r-weighted areas of the node dual cells, so the node force is the exact
+// volume gradient.
 template <class T>
-__device__ inline Kin<T> kinematics(const Geo& g, int i, const T vr[4], const T vz[4]) {
+__device__ inline Kin<T> kinematics(const Col<T>& c, T dz, const T vr[4], const T vz[4]) {
   using N = Num<T>;
   Kin<T> k;
-  const T dr = GeoT<T>::dr(g), dz = GeoT<T>::dz(g);
-  T rw = (T)i * dr, re = (T)(i + 1) * dr;
-  T rc = ((T)i + T(0.5)) * dr;
-  T Arw = rw * dz, Are = re * dz, Az = rc * dr, V = Az * dz;
-  T aw = Ring<T>::w(g, i), ae = Ring<T>::e(g, i);
+  T Arw = c.rw * dz, Are = c.re * dz, V = c.az * dz;
+  T aw = c.aw, ae = c.ae;
   T ur_w = T(0.5) * (vr[0] + vr[2]);
   T ur_e = T(0.5) * (vr[1] + vr[3]);
   T Ur_w = Arw * ur_w;
   T Ur_e = Are * ur_e;
   T Uz_s = aw * vz[0] + ae * vz[1];
   T Uz_n = aw * vz[2] + ae * vz[3];
-  T iV = N::div(T(1), V), irc = N::div(T(1), rc), idr = N::div(T(1), dr);
+  T iV = N::div(T(1), V), irc = N::div(T(1), c.rc), idr = N::div(T(1), c.dr);
   k.Dr = (Ur_e - Ur_w) * iV;
   k.Dz = (Uz_n - Uz_s) * iV;
   k.D = ((Ur_e - Ur_w) + (Uz_n - Uz_s)) * iV;
@@ -481,12 +526,6 @@ __device__ inline Kin<T> kinematics(const Geo& g, int i, const T vr[4], const T 
   k.erz = T(0.5) * (k.dvr_dz + k.dvz_dr);
   k.om = T(0.5) * (k.dvr_dz - k.dvz_dr);
   return k;
-}
-
-template <class T>
-__device__ __forceinline__ T cell_volume(const Geo& g, int i) {
-  const T dr = GeoT<T>::dr(g);
-  return (((T)i + T(0.5)) * dr * dr) * GeoT<T>::dz(g);
 }
 
 }  // namespace salec

@@ -52,29 +52,101 @@ struct Member {
   size_t aux_off = 0, aux_end = 0;  // PML auxiliaries and budgets (cleared at a run start)
   std::vector<double> dcz, dnz, dcr, dnr;
   std::vector<double> p0;  // initial pressure per cell row (host copy)
+  // geometry: node / centre radii, widths, half-column areas, area per unit
+  // height; node / centre heights, row heights
+  std::vector<double> rn, rcn, drc, awc, aec, azc, zn, zcn, dzr;
   salec_scene scene{};
   bool has_scene = false;
 };
 
+// Grid geometry of a member: uniform from dr, dz, or the running sums of a
+// stretched grid's widths and heights with centres halfway.
+void build_geometry(Member& mb, const salec_grid* gr) {
+  const int NR = mb.g.NR, NZ = mb.g.NZ;
+  mb.rn.assign(NR + 1, 0.0);
+  mb.rcn.assign(NR, 0.0);
+  mb.drc.assign(NR, 0.0);
+  mb.awc.assign(NR, 0.0);
+  mb.aec.assign(NR, 0.0);
+  mb.azc.assign(NR, 0.0);
+  mb.zn.assign(NZ + 1, 0.0);
+  mb.zcn.assign(NZ, 0.0);
+  mb.dzr.assign(NZ, 0.0);
+  for (int i = 0; i < NR; i++) {
+    double rw, re, rc, dr;
+    if (gr->dr_col) {
+      dr = gr->dr_col[i];
+      rw = mb.rn[i];
+      re = rw + dr;
+      rc = rw + 0.5 * dr;
+    } else {
+      dr = gr->dr;
+      rw = (double)i * dr;
+      re = (double)(i + 1) * dr;
+      rc = ((double)i + 0.5) * dr;
+    }
+    mb.rn[i] = rw;
+    mb.rn[i + 1] = re;
+    mb.rcn[i] = rc;
+    mb.drc[i] = dr;
+    mb.awc[i] = 0.5 * (rc * rc - rw * rw);
+    mb.aec[i] = 0.5 * (re * re - rc * rc);
+    mb.azc[i] = rc * dr;
+  }
+  for (int j = 0; j < NZ; j++) {
+    if (gr->dz_row) {
+      mb.dzr[j] = gr->dz_row[j];
+      mb.zn[j + 1] = mb.zn[j] + mb.dzr[j];
+      mb.zcn[j] = mb.zn[j] + 0.5 * mb.dzr[j];
+    } else {
+      mb.dzr[j] = gr->dz;
+      mb.zn[j] = (double)j * gr->dz;
+      mb.zn[j + 1] = (double)(j + 1) * gr->dz;
+      mb.zcn[j] = ((double)j + 0.5) * gr->dz;
+    }
+  }
+}
+
+// The device copy of the geometry: six column fields of NR + 1 entries, then
+// the row heights and the node heights (NZ + 1 entries each).
+std::vector<double> geometry_table(const Member& mb) {
+  const int NR = mb.g.NR, NZ = mb.g.NZ, s = NR + 1;
+  std::vector<double> t((size_t)6 * s + 2 * (size_t)(NZ + 1), 0.0);
+  for (int i = 0; i <= NR; i++) t[i] = mb.rn[i];
+  for (int i = 0; i < NR; i++) {
+    t[s + i] = mb.rcn[i];
+    t[2 * s + i] = mb.drc[i];
+    t[3 * s + i] = mb.awc[i];
+    t[4 * s + i] = mb.aec[i];
+    t[5 * s + i] = mb.azc[i];
+  }
+  for (int j = 0; j < NZ; j++) t[6 * s + j] = mb.dzr[j];
+  for (int j = 0; j <= NZ; j++) t[6 * s + (NZ + 1) + j] = mb.zn[j];
+  return t;
+}
+
 // Lithostatic target column (Sec. 3: the initial pressure p0 with
 // -grad p0 + rho g = 0), rows below surface_j: cell-centre pressures from
-// p = 0 at the surface by the trapezoid rule (top row g dz rho / 2, then
-// g dz (rho_j + rho_{j+1}) / 2 per row), each row's density the cold (E = 0)
+// p = 0 at the surface over the piecewise-constant density (top row
+// g rho dz / 2, then g (rho_{j+1} dz_{j+1} / 2 + rho_j dz_j / 2) per row),
+// each row's density the cold (E = 0)
 // compressed Tillotson state of its pressure, mu = 2p / (A + sqrt(A^2 + 4Bp)),
 // iterated with the pressure to a fixed point (at most 50 passes). p0 is then
 // the cold pressure A mu + B mu^2 of the final density, evaluated as the
 // cycle kernel evaluates the equation of state at E = 0, so that a target at
 // rest is in exact discrete equilibrium (p - p0 = 0 in every cell).
-void lithostatic_column(const Geo& g, int surface_j, int layer_j, double grav, std::vector<double>& rho_row,
+void lithostatic_column(const Member& mb, int surface_j, int layer_j, double grav, std::vector<double>& rho_row,
                         std::vector<double>& p0) {
-  const double hg = 0.5 * grav * g.dz;
+  const Geo& g = mb.g;
   for (int j = surface_j - 1; j >= 0; j--) {
     const MatC& m = g.m[g.nmat > 1 && j < layer_j ? 1 : 0];
     const bool top = j == surface_j - 1;
-    const double p_up = top ? 0.0 : p0[j + 1], r_up = top ? 0.0 : rho_row[j + 1];
+    const double p_up = top ? 0.0 : p0[j + 1];
+    const double w_up = top ? 0.0 : grav * (0.5 * mb.dzr[j + 1]) * rho_row[j + 1];
+    const double hj = grav * (0.5 * mb.dzr[j]);
     double r = m.rho0;
     for (int it = 0; it < 50; it++) {
-      double p = p_up + hg * (r_up + r);
+      double p = p_up + (w_up + hj * r);
       double mu = 2.0 * p / (m.A + std::sqrt(m.A * m.A + 4.0 * m.B * p));
       double rn = m.rho0 * (1.0 + mu);
       if (rn == r) break;
@@ -159,6 +231,7 @@ void carve_constants(Member& mb, Carver& cv) {
   }
   mb.d.dtpart = cv.d((size_t)most);
   mb.d.p0 = cv.d((size_t)g.NZ);
+  mb.d.geo = cv.d((size_t)6 * (g.NR + 1) + 2 * (size_t)(g.NZ + 1));
 }
 
 // Entries of the largest schedule over all tile shapes.
@@ -286,6 +359,7 @@ Geo make_geo(const salec_grid* gr, const salec_material* mats, const salec_pml* 
     if (mats[m].strength) g.any_strength = 1;
     if (mats[m].rho0 > g.rho_ref) g.rho_ref = mats[m].rho0;
   }
+  g.stretched = (gr->dr_col || gr->dz_row) ? 1 : 0;
   g.drf = (float)g.dr;
   g.dzf = (float)g.dz;
   g.q_linf = (float)g.q_lin;
@@ -313,15 +387,16 @@ void pml_profiles(Member& mb, const salec_material* mats, const salec_pml* pml) 
     double G0 = m0.strength ? 3.0 * m0.A * (1.0 - 2.0 * m0.poisson) / (2.0 * (1.0 + m0.poisson)) : 0.0;
     c = std::sqrt((m0.A + (4.0 / 3.0) * G0) / m0.rho0);
   }
+  // y from the inner face of each layer, at cell centres and at nodes
   if (g.pml_b > 0) {
-    double delta = g.pml_b * g.dz;
-    for (int j = 0; j < g.pml_b; j++) mb.dcz[j] = pml_d(c, delta, ((double)(g.pml_b - j) - 0.5) * g.dz, pml->R);
-    for (int j = 0; j < g.pml_b; j++) mb.dnz[j] = pml_d(c, delta, (double)(g.pml_b - j) * g.dz, pml->R);
+    double zf = mb.zn[g.pml_b], delta = zf - mb.zn[0];
+    for (int j = 0; j < g.pml_b; j++) mb.dcz[j] = pml_d(c, delta, zf - mb.zcn[j], pml->R);
+    for (int j = 0; j < g.pml_b; j++) mb.dnz[j] = pml_d(c, delta, zf - mb.zn[j], pml->R);
   }
   if (g.pml_r > 0) {
-    double delta = g.pml_r * g.dr;
-    for (int i = g.n_r; i < g.NR; i++) mb.dcr[i] = pml_d(c, delta, ((double)(i - g.n_r) + 0.5) * g.dr, pml->R);
-    for (int i = g.n_r + 1; i <= g.NR; i++) mb.dnr[i] = pml_d(c, delta, (double)(i - g.n_r) * g.dr, pml->R);
+    double rf = mb.rn[g.n_r], delta = mb.rn[g.NR] - rf;
+    for (int i = g.n_r; i < g.NR; i++) mb.dcr[i] = pml_d(c, delta, mb.rcn[i] - rf, pml->R);
+    for (int i = g.n_r + 1; i <= g.NR; i++) mb.dnr[i] = pml_d(c, delta, mb.rn[i] - rf, pml->R);
   }
 }
 
@@ -338,7 +413,15 @@ int check_members(const salec_instance* inst, int32_t n, std::vector<Member>& ms
     if (I.has_scene && (sc.subsample < 1 || !(sc.radius >= 0) || !(sc.gravity >= 0) || sc.surface_j < 0 ||
                         sc.surface_j > I.grid.n_z + I.grid.pml_b || sc.layer_j < 0 || sc.layer_j > sc.surface_j))
       return why = "instance " + std::to_string(k) + ": scene parameters", SALEC_E_INVALID;
+    const int NR = I.grid.n_r + I.grid.pml_r, NZ = I.grid.n_z + I.grid.pml_b;
+    for (int i = 0; I.grid.dr_col && i < NR; i++)
+      if (!(I.grid.dr_col[i] > 0) || !std::isfinite(I.grid.dr_col[i]))
+        return why = "instance " + std::to_string(k) + ": column widths", SALEC_E_INVALID;
+    for (int j = 0; I.grid.dz_row && j < NZ; j++)
+      if (!(I.grid.dz_row[j] > 0) || !std::isfinite(I.grid.dz_row[j]))
+        return why = "instance " + std::to_string(k) + ": row heights", SALEC_E_INVALID;
     ms[k].g = make_geo(&I.grid, I.mats, &I.pml);
+    build_geometry(ms[k], &I.grid);
     ms[k].d.g = ms[k].g;
     ms[k].has_scene = I.has_scene != 0;
     ms[k].scene = I.scene;
@@ -352,6 +435,7 @@ struct salec_ctx {
   std::vector<Member> ms;
   Layout L;
   int prec = 0;
+  bool geo = false;  // some member is stretched: the cycle kernel reads geometry tables
   void* buf = nullptr;
   hipStream_t st = nullptr;
   bool own_stream = false;
@@ -429,7 +513,7 @@ int capture(salec_ctx* x, int ncyc, hipGraphExec_t* out) {
   HIPCHK(x, hipStreamBeginCapture(x->st, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
   for (int k = 0; k < ncyc && le == hipSuccess; k++) {
-    le = launch_cycle(x->variant, x->prec, x->L.d_inst, x->L.d_sched, x->nsched, grid, x->st);
+    le = launch_cycle(x->variant, x->prec, x->geo, x->L.d_inst, x->L.d_sched, x->nsched, grid, x->st);
     if (le == hipSuccess) le = launch_finalize(x->L.d_inst, (int)x->ms.size(), x->st);
   }
   hipError_t e = hipStreamEndCapture(x->st, &gr);
@@ -507,6 +591,8 @@ int init_common(salec_ctx* x, void* dev_buf, size_t dev_bytes, void* stream) {
   }
   x->buf = dev_buf;
   x->prec = x->ms[0].g.prec;
+  for (const Member& mb : x->ms)
+    if (mb.g.stretched) x->geo = true;
   carve_all(x->ms, dev_buf, x->L);
   if (stream) {
     x->st = (hipStream_t)stream;
@@ -524,11 +610,13 @@ int init_common(salec_ctx* x, void* dev_buf, size_t dev_bytes, void* stream) {
     HIPCHK(x, hipMemcpyAsync((void*)mb.d.pm.dnz, mb.dnz.data(), mb.dnz.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
     HIPCHK(x, hipMemcpyAsync((void*)mb.d.pm.dcr, mb.dcr.data(), mb.dcr.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
     HIPCHK(x, hipMemcpyAsync((void*)mb.d.pm.dnr, mb.dnr.data(), mb.dnr.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
+    const std::vector<double> geo = geometry_table(mb);
+    HIPCHK(x, hipMemcpyAsync((void*)mb.d.geo, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
     mb.p0.assign((size_t)mb.g.NZ, 0.0);
     std::vector<double> rho_row;
     if (mb.has_scene && mb.scene.gravity > 0) {
       rho_row.assign((size_t)mb.g.NZ, 0.0);
-      lithostatic_column(mb.g, mb.scene.surface_j, mb.scene.layer_j, mb.scene.gravity, rho_row, mb.p0);
+      lithostatic_column(mb, mb.scene.surface_j, mb.scene.layer_j, mb.scene.gravity, rho_row, mb.p0);
     }
     HIPCHK(x, hipMemcpyAsync((void*)mb.d.p0, mb.p0.data(), mb.p0.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
     mb.g.has_p0 = 0;
@@ -537,7 +625,7 @@ int init_common(salec_ctx* x, void* dev_buf, size_t dev_bytes, void* stream) {
     mb.d.g = mb.g;
     if (mb.has_scene) {
       const salec_scene& sc = mb.scene;
-      double zc = (double)sc.surface_j * mb.g.dz + sc.radius;
+      double zc = mb.zn[sc.surface_j] + sc.radius;
       // per-row densities of a lithostatic target go after the projectile fractions
       double* rr = nullptr;
       if (!rho_row.empty()) {
@@ -555,7 +643,7 @@ int init_common(salec_ctx* x, void* dev_buf, size_t dev_bytes, void* stream) {
   const int v0 = default_variant(x->prec);
   int rc = use_schedule(x, v0, 0);
   if (rc) return rc;
-  const int g0 = resident_groups(v0, x->prec);
+  const int g0 = resident_groups(v0, x->prec, x->geo);
   if (g0 > 0 && g0 < x->nsched && (rc = use_schedule(x, v0, g0))) return rc;
   x->ready = true;
   return SALEC_OK;
@@ -690,7 +778,7 @@ int salec_time_kernels(salec_ctx* x, int32_t n, double* cycle_ms, double* finali
   const int grid = x->grid > 0 ? std::min(x->grid, x->nsched) : x->nsched;
   hipError_t e = rc ? hipErrorOutOfMemory : hipEventRecord(ev[0], x->st);
   for (int c = 0; c < n && e == hipSuccess; c++) {
-    e = launch_cycle(x->variant, x->prec, x->L.d_inst, x->L.d_sched, x->nsched, grid, x->st);
+    e = launch_cycle(x->variant, x->prec, x->geo, x->L.d_inst, x->L.d_sched, x->nsched, grid, x->st);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * c + 1], x->st);
     if (e == hipSuccess) e = launch_finalize(x->L.d_inst, (int)x->ms.size(), x->st);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * c + 2], x->st);
@@ -933,7 +1021,7 @@ int salec_tune(salec_ctx* x, int32_t cycles, salec_schedule* out) {
   for (int v = 0; v < n_variants(); v++) {
     // one workgroup per tile, and as many workgroups as fit at once walking
     // the tiles (when that is fewer than the tiles)
-    int grids[2] = {0, resident_groups(v, x->prec)};
+    int grids[2] = {0, resident_groups(v, x->prec, x->geo)};
     for (int gi = 0; gi < 2; gi++) {
       if (gi == 1 && (grids[1] <= 0 || grids[1] >= x->nsched)) continue;
       int rc = use_schedule(x, v, grids[gi]);

@@ -19,12 +19,15 @@ void variant_shape(int v, int* tw, int* th, int* nt);
 int default_variant(int prec);
 CycleFn cycle_kernel_f64(int v);
 CycleFn cycle_kernel_f32(int v);
-hipError_t launch_cycle(int v, int prec, const Inst* insts, const TileRef* sched, int nsched, int grid,
+// the same shapes reading the geometry from the instances' tables (stretched grids)
+CycleFn cycle_kernel_geo_f64(int v);
+CycleFn cycle_kernel_geo_f32(int v);
+hipError_t launch_cycle(int v, int prec, bool geo, const Inst* insts, const TileRef* sched, int nsched, int grid,
                         hipStream_t st);
 // end of a cycle: per-instance Courant minimum, clock, errors
 hipError_t launch_finalize(const Inst* insts, int n_inst, hipStream_t st);
 // workgroups of shape v that fit on the device at once (0 if unknown)
-int resident_groups(int v, int prec);
+int resident_groups(int v, int prec, bool geo);
 
 // EoS cache and Courant candidates of the current state (start of a run)
 hipError_t launch_prime_f64(const Inst& in, hipStream_t st);

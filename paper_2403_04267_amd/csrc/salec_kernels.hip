@@ -43,10 +43,12 @@ __global__ void k_scene_cells(Inst in, int surface_j, int layer_j, int S, double
   if (!cell_of(g, i, j)) return;
   long long c = cidx(g, i, j);
   double num = 0.0, den = 0.0;
+  const Col<double> cg = col_of<double>(g, in.geo, i);
+  const double zj = zn_of(g, in.geo, j), dzj = dz_of(g, in.geo, j);
   for (int l = 0; l < S; l++) {
-    double zl = ((double)j + ((double)l + 0.5) / (double)S) * g.dz;
+    double zl = zj + (((double)l + 0.5) / (double)S) * dzj;
     for (int k = 0; k < S; k++) {
-      double rk = ((double)i + ((double)k + 0.5) / (double)S) * g.dr;
+      double rk = cg.rw + (((double)k + 0.5) / (double)S) * cg.dr;
       double dzl = zl - zc;
       if (rk * rk + dzl * dzl <= R * R) num += rk;
       den += rk;
@@ -84,7 +86,7 @@ __global__ void k_scene_nodes(Inst in, const double* fproj, double v_imp) {
   for (int q = 0; q < 4; q++) {
     if (qi[q] < 0 || qi[q] >= g.NR || qj[q] < 0 || qj[q] >= g.NZ) continue;
     long long c = cidx(g, qi[q], qj[q]);
-    double V = cell_volume<double>(g, qi[q]);
+    double V = col_of<double>(g, in.geo, qi[q]).az * dz_of(g, in.geo, qj[q]);
     Mt += S0.rho[c] * V;
     Mp += fproj[c] * g.m[mp].rho0 * V;
   }
@@ -189,7 +191,7 @@ __global__ void k_diag_partial(Inst in, long long n_pml, double* red) {
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < ncell; t += stride) {
     int j = (int)(t / g.NR), i = (int)(t - (long long)j * g.NR);
     long long c = cidx(g, i, j);
-    double M = S.rho[c] * cell_volume<double>(g, i);
+    double M = S.rho[c] * (col_of<double>(g, in.geo, i).az * dz_of(g, in.geo, j));
     ks_add(acc[0], M);
     ks_add(acc[1], M * S.I[c]);
   }
@@ -199,7 +201,7 @@ __global__ void k_diag_partial(Inst in, long long n_pml, double* red) {
     const int qi[4] = {i - 1, i, i - 1, i}, qj[4] = {j - 1, j - 1, j, j};
     for (int q = 0; q < 4; q++) {
       if (qi[q] < 0 || qi[q] >= g.NR || qj[q] < 0 || qj[q] >= g.NZ) continue;
-      Mq[q] = S.rho[cidx(g, qi[q], qj[q])] * cell_volume<double>(g, qi[q]);
+      Mq[q] = S.rho[cidx(g, qi[q], qj[q])] * (col_of<double>(g, in.geo, qi[q]).az * dz_of(g, in.geo, qj[q]));
     }
     double M = 0.25 * ((Mq[0] + Mq[1]) + (Mq[2] + Mq[3]));
     long long n = nidx(g, i, j);

@@ -16,7 +16,7 @@ from __future__ import annotations
 import dataclasses
 import math
 from dataclasses import dataclass, field
-from typing import List, Optional
+from typing import List, Optional, Sequence
 
 import numpy as np
 
@@ -60,6 +60,10 @@ class Grid:
     t_stop: float = 0.0
     q_lin: float = 0.25
     q_quad: float = 1.0
+    # stretched grid: per-column widths (NR values) and per-row heights (NZ
+    # values) in metres, or None for the uniform dr / dz
+    dr_col: Optional[Sequence[float]] = None
+    dz_row: Optional[Sequence[float]] = None
 
     @property
     def NR(self) -> int:
@@ -180,6 +184,54 @@ def layered_impact(n: int, pml: int, radius_cells: int, v_imp: float, crust_cell
                layer_j=max(sj - crust_cells, 0))
     return Problem(grid=g, mats=[basalt(strength=strength), mantle_like(strength=strength)], pml=Pml(),
                    scene=sc, cycles=cycles, precision=precision, name=name)
+
+
+def stretched_widths(n_fine: int, n_ext: int, n_pml: int, d: float, factor: float = 1.05,
+                     d_max: Optional[float] = None) -> List[float]:
+    """Cell widths along one axis, outward (Table 2's zones): n_fine cells of
+    d, n_ext extension cells each `factor` times the previous one (capped at
+    d_max), then n_pml layer cells of the last width."""
+    w = [float(d)] * n_fine
+    cur = float(d)
+    for _ in range(n_ext):
+        cur = cur * factor
+        if d_max is not None:
+            cur = min(cur, float(d_max))
+        w.append(cur)
+    w += [w[-1] if w else float(d)] * n_pml
+    return w
+
+
+def paper_layout(n_x: int = 462, n_y: int = 462, ext=(0, 20, 20, 20), pml=(30, 30), d: float = 400.0,
+                 factor: float = 1.05, d_max: float = 1061.0, nmat: int = 2) -> Grid:
+    """The grid of Table 2: an n_x x n_y zone of d-metre cells, extension
+    zones (left, right, top, bottom) whose spacing grows by `factor` per cell
+    up to d_max, and PML layers (right, bottom) at the last spacing. The
+    axis is the left side, so there is no left extension. Defaults: the
+    paper's SALEc-2D+PML column, 512 x 532 cells."""
+    n_l, n_r, n_t, n_b = ext
+    p_r, p_b = pml
+    if n_l:
+        raise ValueError("the symmetry axis is the left side: no left extension")
+    cols = stretched_widths(n_x, n_r, p_r, d, factor, d_max)
+    below = stretched_widths(0, n_b, p_b, d, factor, d_max)[::-1]  # PML rows at the bottom
+    above = stretched_widths(0, n_t, 0, d, factor, d_max)
+    rows = below + [float(d)] * n_y + above
+    return Grid(n_r=n_x + n_r, n_z=n_b + n_y + n_t, pml_r=p_r, pml_b=p_b, nmat=nmat, dr=d, dz=d,
+                dr_col=cols, dz_row=rows)
+
+
+def stretched_impact(n: int, ext: int, pml: int, radius_cells: int, v_imp: float, strength: bool = True,
+                     nmat: int = 2, d: float = 400.0, precision: str = "fp64", name: str = "") -> Problem:
+    """The impact scene on a Table 2-style grid: an n x n zone of d-metre
+    cells with `ext` extension cells right, above and below (growth 1.05 per
+    cell, capped at 1061 m) and `pml` layer cells right and below; the target
+    surface and the projectile sit in the fine zone."""
+    g = paper_layout(n, n, (0, ext, ext, ext), (pml, pml), d=d, nmat=nmat)
+    sj = g.pml_b + ext + surface_row(n, 0, radius_cells)
+    sc = Scene(surface_j=sj, radius=radius_cells * d, v_imp=v_imp)
+    mat = basalt(strength=strength)
+    return Problem(grid=g, mats=[mat] * nmat, pml=Pml(), scene=sc, precision=precision, name=name)
 
 
 def config_small() -> Problem:

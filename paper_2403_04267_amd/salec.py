@@ -27,7 +27,8 @@ class Grid(C.Structure):
                 ("nmat", C.c_int32), ("top_closed", C.c_int32), ("precision", C.c_int32),
                 ("reserved", C.c_int32)] + \
                [(n, C.c_double) for n in ("dr", "dz", "cfl", "dt_grow", "dt_max", "dt_floor", "t_stop",
-                                          "q_lin", "q_quad")]
+                                          "q_lin", "q_quad")] + \
+               [("dr_col", C.POINTER(C.c_double)), ("dz_row", C.POINTER(C.c_double))]
 
 
 class Material(C.Structure):
@@ -129,10 +130,16 @@ def header_functions() -> list:
     return sorted(set(re.findall(r"\b(salec_[a-z_0-9]+)\s*\(", txt)))
 
 
-def _grid(g, precision) -> Grid:
+def _grid(g, precision, keep: list) -> Grid:
+    """The C grid description; a stretched grid's width / height arrays go
+    into `keep`, which the caller holds until the library has read them."""
+    drc = None if g.dr_col is None else np.ascontiguousarray(g.dr_col, dtype=np.float64)
+    dzr = None if g.dz_row is None else np.ascontiguousarray(g.dz_row, dtype=np.float64)
+    keep.extend([drc, dzr])
     return Grid(g.n_r, g.n_z, g.pml_r, g.pml_b, g.nmat, g.top_closed,
                 SALEC_MIXED if precision == "mixed" else SALEC_FP64, 0,
-                g.dr, g.dz, g.cfl, g.dt_grow, g.dt_max, g.dt_floor, g.t_stop, g.q_lin, g.q_quad)
+                g.dr, g.dz, g.cfl, g.dt_grow, g.dt_max, g.dt_floor, g.t_stop, g.q_lin, g.q_quad,
+                _ptr(drc), _ptr(dzr))
 
 
 def _mat(m) -> Material:
@@ -147,10 +154,10 @@ def _mats(problem):
     return arr
 
 
-def _instance(problem) -> Instance:
+def _instance(problem, keep: list) -> Instance:
     g = problem.grid
     inst = Instance()
-    inst.grid = _grid(g, problem.precision)
+    inst.grid = _grid(g, problem.precision, keep)
     for k, m in enumerate(problem.mats[:g.nmat]):
         inst.mats[k] = _mat(m)
     p = problem.pml
@@ -166,7 +173,8 @@ def plan_bytes(problems) -> int:
     """Device bytes for one problem or a list of problems (an ensemble)."""
     lib = load()
     probs = problems if isinstance(problems, (list, tuple)) else [problems]
-    arr = (Instance * len(probs))(*[_instance(pb) for pb in probs])
+    keep = []
+    arr = (Instance * len(probs))(*[_instance(pb, keep) for pb in probs])
     return lib.salec_plan_batch(arr, len(probs))
 
 
@@ -204,7 +212,8 @@ class Salec:
         self.NR, self.NZ, self.nmat = self.dims[0]
         self.NC, self.NN = self.NR * self.NZ, (self.NR + 1) * (self.NZ + 1)
         self.device = torch.device(device)
-        arr = (Instance * len(self.problems))(*[_instance(pb) for pb in self.problems])
+        keep = []
+        arr = (Instance * len(self.problems))(*[_instance(pb, keep) for pb in self.problems])
         nbytes = lib.salec_plan_batch(arr, len(self.problems))
         if nbytes == 0:
             raise ValueError("salec_plan_batch rejected the problem description")

@@ -1,0 +1,93 @@
+"""GPU parity on stretched grids (Table 2's extension zones), through the
+C ABI: the cycle kernel's table path (each tile's column and row geometry
+staged in LDS) against the FP64 oracle bit for bit, the table path with equal
+widths against the uniform path bit for bit, ensembles mixing uniform and
+stretched members, and the mixed-precision bar.
+"""
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle
+from paper_2403_04267_amd import inputs
+
+from .crater import conserved_errors
+from .test_gpu_parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+def ctx(problems):
+    from paper_2403_04267_amd.salec import Salec
+    return Salec(problems)
+
+
+class Member:
+    def __init__(self, c, k):
+        self.c, self.k = c, k
+
+    def fields(self):
+        return self.c.fields(k=self.k)
+
+    def pml_aux(self):
+        return self.c.pml_aux(k=self.k)
+
+    def diag(self):
+        return self.c.diag(k=self.k)
+
+
+def test_stretched_impact_fp64_bitwise():
+    pb = inputs.stretched_impact(60, 10, 12, 6, 15e3, name="stretched")
+    g, o = ctx(pb), Oracle(pb)
+    done = 0
+    for n in (1, 60, 200):
+        g.step(n - done)
+        o.step(n - done)
+        done = n
+        compare(g, o, f"stretched cycle {n}", tol=0.0)
+
+
+def test_every_tile_shape_on_a_stretched_grid():
+    from paper_2403_04267_amd.salec import num_variants
+    pb = inputs.stretched_impact(41, 7, 9, 5, 12e3, name="shapes")
+    o = Oracle(pb)
+    o.step(40)
+    for v in range(num_variants()):
+        c = ctx(pb)
+        c.set_schedule(v, 0)
+        c.step(40)
+        compare(c, o, f"stretched variant {v}", tol=0.0)
+
+
+def test_equal_widths_match_the_uniform_kernel_bitwise():
+    pb = inputs.impact(50, 10, 5, 12e3, nmat=2, strength=True, cycles=0, dx=4.0)
+    gr = pb.grid
+    st = pb.replace(grid=inputs.Grid(**{**gr.__dict__, "dr_col": [4.0] * gr.NR, "dz_row": [4.0] * gr.NZ}))
+    a, b = ctx(pb), ctx(st)
+    a.step(120)
+    b.step(120)
+    Fa, Fb = a.fields(), b.fields()
+    for k in Fa:
+        assert np.array_equal(Fa[k], Fb[k]), k
+
+
+def test_ensemble_of_uniform_and_stretched_members():
+    members = [inputs.stretched_impact(40, 8, 8, 4, 11e3, name="s1"),
+               inputs.impact(36, 8, 4, 9e3, nmat=2, strength=True, cycles=0, name="u1"),
+               inputs.stretched_impact(30, 6, 10, 3, 16e3, name="s2")]
+    c = ctx(members)
+    oracles = [Oracle(pb) for pb in members]
+    c.step(80)
+    for k, o in enumerate(oracles):
+        o.step(80)
+        compare(Member(c, k), o, f"member {k}", tol=0.0)
+
+
+def test_stretched_impact_mixed_against_oracle():
+    pb = inputs.stretched_impact(60, 10, 12, 6, 15e3, name="stretched")
+    g, o = ctx(pb.replace(precision="mixed")), Oracle(pb)
+    g.step(100)
+    o.step(100)
+    e = conserved_errors(g.fields(), o.fields(), pb.grid)
+    print("[stretched mixed cycle 100] " + " ".join(f"{k} {v:.2e}" for k, v in e.items()), flush=True)
+    bad = {k: v for k, v in e.items() if not v <= 1e-4}
+    assert not bad, bad
