@@ -19,10 +19,12 @@ Also measured (the "extensions" object; skipped with --headline-only):
   batched_mixed  1024 seeded uneven impacts (sides 200-1200), mixed
   layered_fp64   the 1050^2 workload as a two-layer target under gravity
                  (400 m cells, lithostatic initial pressure), plain FP64
+  paper_layout_fp64  the impact on Table 2's stretched 512 x 532 grid (two
+                 layers, gravity), plain FP64
   pml_payoff     the same small impact with a PML, with plain walls and on a
                  10x larger domain, each to the same time (interior error,
                  reflected energy, crater geometry, device time)
-Each of the first five is init + tune + warm-up, then a short timed run.
+Each but the last is init + tune + warm-up, then a short timed run.
 
 Prints one JSON line. `roofline` is the cycle kernel's algorithmic HBM
 bytes per launch (state read and written once, PML auxiliaries) over the
@@ -280,6 +282,8 @@ def main():
         ext["layered_fp64"] = extension("layered 1050^2 fp64",
                                         inputs.layered_impact(1000, 50, 50, 15e3, 70, name="layered"), 500, 20,
                                         args.tune, value)
+        ext["paper_layout_fp64"] = extension("Table 2 grid 512x532 fp64", inputs.config_paper(), 300, 20,
+                                             args.tune, value)
         ext["pml_payoff"] = pml_payoff()
         out["extensions"] = ext
     if not args.no_cpu:

@@ -234,6 +234,20 @@ def stretched_impact(n: int, ext: int, pml: int, radius_cells: int, v_imp: float
     return Problem(grid=g, mats=[mat] * nmat, pml=Pml(), scene=sc, precision=precision, name=name)
 
 
+def config_paper(precision: str = "fp64") -> Problem:
+    """Sec. 4's verification setting on Table 2's grid, with this build's two
+    materials: 512 x 532 cells (462 x 462 of 400 m, extension zones right, top
+    and bottom growing 1.05 per cell to 1061 m, 30-cell PML right and below),
+    a mantle-rock sphere of 7.2 km radius (18 cells) at 12 km/s onto a 33 km
+    basalt crust over mantle rock, lithostatic under 9.81 m/s^2."""
+    g = paper_layout()
+    R = 18
+    sj = g.pml_b + 20 + surface_row(462, 0, R)
+    sc = Scene(surface_j=sj, radius=R * 400.0, v_imp=12e3, gravity=9.81, layer_j=sj - 82)
+    return Problem(grid=g, mats=[basalt(strength=True), mantle_like(strength=True)], pml=Pml(), scene=sc,
+                   precision=precision, name="paper-layout")
+
+
 def config_small() -> Problem:
     """100x100 cells + 20-cell PML, one material, hydrodynamic, R = 10 cells,
     10 km/s, 500 cycles, plain FP64."""

@@ -91,3 +91,16 @@ def test_stretched_impact_mixed_against_oracle():
     print("[stretched mixed cycle 100] " + " ".join(f"{k} {v:.2e}" for k, v in e.items()), flush=True)
     bad = {k: v for k, v in e.items() if not v <= 1e-4}
     assert not bad, bad
+
+
+def test_table2_layout_with_layers_and_gravity_bitwise():
+    """Sec. 4's setting on the 512 x 532 grid of Table 2 (two layers, gravity)."""
+    pb = inputs.config_paper()
+    g, o = ctx(pb), Oracle(pb)
+    assert np.array_equal(g.p0(), o.p0())
+    done = 0
+    for n in (1, 25):
+        g.step(n - done)
+        o.step(n - done)
+        done = n
+        compare(g, o, f"Table 2 grid cycle {n}", tol=0.0)
