@@ -81,3 +81,47 @@ def test_binding_refuses_to_run_without_a_device():
         pytest.skip("a device is visible")
     with pytest.raises(RuntimeError):
         salec.Salec(inputs.config_small())
+
+
+@pytest.mark.parametrize("change", [
+    {"gravity": -9.81}, {"layer_j": -1}, {"radius": -1.0}, {"subsample": 0},
+])
+def test_plan_rejects_invalid_scenes(change):
+    pb = inputs.layered_impact(40, 8, 4, 1e4, 6)
+    for k, v in change.items():
+        setattr(pb.scene, k, v)
+    assert salec.plan_bytes(pb) == 0
+
+
+def test_plan_rejects_a_layer_above_the_surface():
+    pb = inputs.layered_impact(40, 8, 4, 1e4, 6)
+    pb.scene.layer_j = pb.scene.surface_j + 1
+    assert salec.plan_bytes(pb) == 0
+
+
+def test_plan_accepts_a_target_without_projectile():
+    pb = inputs.layered_impact(40, 8, 4, 0.0, 6)
+    pb.scene.radius = 0.0
+    assert salec.plan_bytes(pb) > 0
+
+
+@pytest.mark.parametrize("bad", [0.0, -4.0, float("nan"), float("inf")])
+def test_plan_rejects_invalid_stretched_widths(bad):
+    pb = inputs.stretched_impact(30, 6, 6, 3, 1e4, d=4.0)
+    cols = list(pb.grid.dr_col)
+    cols[5] = bad
+    pb.grid.dr_col = cols
+    assert salec.plan_bytes(pb) == 0
+    pb = inputs.stretched_impact(30, 6, 6, 3, 1e4, d=4.0)
+    rows = list(pb.grid.dz_row)
+    rows[-1] = bad
+    pb.grid.dz_row = rows
+    assert salec.plan_bytes(pb) == 0
+
+
+def test_stretched_plan_matches_uniform_plan_size():
+    """The geometry table is always carved, so stretching costs no space."""
+    pb = inputs.stretched_impact(30, 6, 6, 3, 1e4, d=4.0)
+    g = pb.grid
+    uni = pb.replace(grid=inputs.Grid(**{**g.__dict__, "dr_col": None, "dz_row": None}))
+    assert salec.plan_bytes(pb) == salec.plan_bytes(uni) > 0
