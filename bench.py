@@ -24,6 +24,8 @@ Also measured (the "extensions" object; skipped with --headline-only):
   pml_payoff     the same small impact with a PML, with plain walls and on a
                  10x larger domain, each to the same time (interior error,
                  reflected energy, crater geometry, device time)
+  pml_payoff_table2  the same comparison on Table 2's grid with two layers and
+                 gravity, to 30 s, against ~200 km longer extension zones
 Each but the last is init + tune + warm-up, then a short timed run.
 
 Prints one JSON line. `roofline` is the cycle kernel's algorithmic HBM
@@ -197,6 +199,19 @@ def pml_payoff():
     return r
 
 
+def pml_payoff_table2():
+    """The PML comparison in the paper's setting: Table 2's grid (two layers,
+    gravity) with its PML, with plain walls, and with extension zones ~200 km
+    longer, each to 30 s (the shock has turned at the bottom boundary)."""
+    from paper_2403_04267_amd.pml_study import PaperSetup, paper_run
+    t0 = time.perf_counter()
+    r = paper_run(PaperSetup(t_end=30.0))
+    r["wall_s"] = time.perf_counter() - t0
+    print(f"[bench] pml payoff (Table 2): pml {r['pml']['err_vs_ref']}, bare {r['bare']['err_vs_ref']}",
+          file=sys.stderr, flush=True)
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -285,6 +300,7 @@ def main():
         ext["paper_layout_fp64"] = extension("Table 2 grid 512x532 fp64", inputs.config_paper(), 300, 20,
                                              args.tune, value)
         ext["pml_payoff"] = pml_payoff()
+        ext["pml_payoff_table2"] = pml_payoff_table2()
         out["extensions"] = ext
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pb)

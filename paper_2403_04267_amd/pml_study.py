@@ -16,6 +16,7 @@ and device time.
 """
 from __future__ import annotations
 
+import dataclasses
 import math
 from dataclasses import dataclass
 
@@ -143,6 +144,92 @@ def run(s: Setup = Setup(), device: str = "cuda:0", chunk: int = 200, max_cycles
         }
     res["setup"] = {"n": s.n, "p": s.p, "radius": s.radius, "v_imp": s.v_imp, "t_end": s.t_end,
                     "big": s.big, "strength": s.strength, "precision": s.precision}
+    return res
+
+
+# --------------------------------------------------------------------------
+# the same comparison in the paper's own setting (Sec. 4, Table 2)
+# --------------------------------------------------------------------------
+@dataclass
+class PaperSetup:
+    t_end: float = 30.0     # s (the paper's second panel: the shock has reached the bottom and turned)
+    ext_ref: int = 200      # extension cells right and below in the reference run
+    precision: str = "fp64"
+
+
+def paper_problems(s: PaperSetup):
+    """Table 2's grid with its 30-cell PML, the same grid with plain walls, and
+    a reference whose right and bottom extension zones run ext_ref cells
+    (about 200 km further: nothing returns into the window before ~90 s).
+    The window is the fine zone with its first 20 extension cells right, above
+    and below, which all three grids share cell for cell."""
+    base = inputs.config_paper(s.precision)
+    base.grid.t_stop = s.t_end
+    bare = base.replace(pml=inputs.Pml(enabled=0))
+    gref = inputs.paper_layout(462, 462, (0, s.ext_ref, 20, s.ext_ref), (0, 0))
+    gref.t_stop = s.t_end
+    sj = s.ext_ref + (base.scene.surface_j - base.grid.pml_b - 20)
+    sc = dataclasses.replace(base.scene, surface_j=sj, layer_j=sj - (base.scene.surface_j - base.scene.layer_j))
+    ref = base.replace(grid=gref, scene=sc, pml=inputs.Pml(enabled=0))
+    rows = {"pml": base.grid.pml_b, "bare": base.grid.pml_b, "ref": s.ext_ref - 20}
+    return {"pml": base, "bare": bare, "ref": ref}, rows, 482, 502
+
+
+def _geometry(g):
+    rn = np.concatenate([[0.0], np.cumsum(g.dr_col)])
+    dz = np.asarray(g.dz_row, dtype=np.float64)
+    Vc = 0.5 * (rn[1:] ** 2 - rn[:-1] ** 2)[None, :] * dz[:, None]
+    return Vc
+
+
+def paper_run(s: PaperSetup = PaperSetup(), device: str = "cuda:0", chunk: int = 500,
+              max_cycles: int = 100000) -> dict:
+    """Runs the three problems to s.t_end and compares the target part of the
+    window (below the original surface; the ejecta above it are chaotic in
+    every run): energy of the difference field against the reference
+    (kinetic with the reference's node masses, acoustic (p - p_ref)^2 / (2 A)
+    with the crust's bulk modulus A) per unit impact kinetic energy, and the
+    relative L2 of p - p0 (the quantity the paper plots), next to cells and
+    device time."""
+    from .salec import Salec
+    probs, rows, wc, wr = paper_problems(s)
+    res, win = {}, {}
+    ke0 = 0.0
+    for key, pb in probs.items():
+        ctx = Salec(pb, device)
+        if key == "ref":
+            ke0 = ctx.diag()["ke"]
+        ms, cycles = 0.0, 0
+        while ctx.diag()["t"] < s.t_end * (1.0 - 1e-12) and cycles < max_cycles:
+            ctx.step(chunk)
+            ms += ctx.last_step_ms()
+            cycles += chunk
+        d = ctx.diag()
+        F = ctx.fields()
+        p0 = ctx.p0()
+        r0 = rows[key]
+        sl = slice(r0, r0 + wr)
+        win[key] = {"rho": F["rho"][sl, :wc], "p": F["p"][sl, :wc], "c2": F["c2"][sl, :wc],
+                    "dp": F["p"][sl, :wc] - p0[sl, None], "f": F["f"][:, sl, :wc],
+                    "v": F["v"][:, r0:r0 + wr + 1, :wc + 1]}
+        res[key] = {"cells": pb.grid.ncells, "cycles": int(d["cycle"]), "t": d["t"], "device_ms": ms}
+        del ctx
+    g = probs["pml"].grid
+    ns = probs["pml"].scene.surface_j - rows["pml"]  # target rows of the window
+    Vc = _geometry(g)[rows["pml"]:rows["pml"] + ns, :wc]
+    A = probs["pml"].mats[0].A
+    ref = win["ref"]
+    mref = 0.25 * np.pad(ref["rho"][:ns] * Vc, 1)
+    mref = (mref[:-1, :-1] + mref[:-1, 1:]) + (mref[1:, :-1] + mref[1:, 1:])
+    for key in ("pml", "bare"):
+        w = win[key]
+        dv2 = np.sum((w["v"][:, :ns + 1] - ref["v"][:, :ns + 1]) ** 2, axis=0)
+        e_k = 0.5 * np.sum(mref * dv2)
+        e_p = np.sum(Vc * (w["p"][:ns] - ref["p"][:ns]) ** 2) / (2.0 * A)
+        res[key]["err_vs_ref"] = {"reflected_energy": float((e_k + e_p) / ke0),
+                                  "dp": _rel_l2(w["dp"][:ns], ref["dp"][:ns])}
+    res["setup"] = {"t_end": s.t_end, "ext_ref": s.ext_ref, "precision": s.precision,
+                    "window_cells": [wr, wc]}
     return res
 
 

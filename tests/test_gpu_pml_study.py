@@ -24,3 +24,20 @@ def test_pml_brings_the_interior_close_to_the_large_domain():
         assert e_pml[q] < 0.5 * e_bare[q], (q, e_pml, e_bare)
     assert abs(r["pml"]["crater_depth"] - r["big"]["crater_depth"]) <= 1.0
     assert r["pml"]["cells"] < 0.1 * r["big"]["cells"]
+
+
+def test_pml_in_the_paper_setting():
+    """Sec. 4's setting on Table 2's grid (two layers, gravity) at 20 s, when
+    the shock has reached the bottom boundary: against a reference whose
+    extension zones reach ~200 km further, the PML run's target is within a
+    fraction of a percent while plain walls send back measurable energy."""
+    from paper_2403_04267_amd.pml_study import PaperSetup, paper_run
+    r = paper_run(PaperSetup(t_end=20.0))
+    for k in ("pml", "bare", "ref"):
+        print(k, r[k], flush=True)
+        assert r[k]["t"] == pytest.approx(20.0, rel=1e-9)
+    e_pml, e_bare = r["pml"]["err_vs_ref"], r["bare"]["err_vs_ref"]
+    assert e_bare["reflected_energy"] > 1e-3
+    assert e_pml["reflected_energy"] < 1e-2 * e_bare["reflected_energy"], (e_pml, e_bare)
+    assert e_pml["dp"] < 0.2 * e_bare["dp"], (e_pml, e_bare)
+    assert r["pml"]["cells"] < 0.65 * r["ref"]["cells"]
