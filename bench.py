@@ -232,7 +232,7 @@ def main():
                          "profiling it gives the HBM counter scale factors")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
     if args.copy_calibrate:

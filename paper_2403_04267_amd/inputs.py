@@ -235,7 +235,7 @@ def stretched_impact(n: int, ext: int, pml: int, radius_cells: int, v_imp: float
 
 
 def config_paper(precision: str = "fp64") -> Problem:
-    """Sec. 4's verification setting on Table 2's grid, with this build's two
+    """Sec. 4's verification setting on Table 2's grid, with two
     materials: 512 x 532 cells (462 x 462 of 400 m, extension zones right, top
     and bottom growing 1.05 per cell to 1061 m, 30-cell PML right and below),
     a mantle-rock sphere of 7.2 km radius (18 cells) at 12 km/s onto a 33 km
