@@ -202,3 +202,22 @@ def test_extension_zone_keeps_the_crater():
     ra, rb = crater_radius(fa, ga, sa), crater_radius(fb, ga, sa)
     assert da > 2 * 4.0 and abs(da - db) <= 4.0, (da, db)
     assert abs(ra - rb) <= 4.0, (ra, rb)
+
+
+def test_paper_study_window_is_shared_cell_for_cell():
+    """The Table 2 PML comparison relies on the window (fine zone plus its
+    first 20 extension cells) being the same cells in all three grids, with
+    the same scene and lithostatic column relative to it."""
+    from paper_2403_04267_amd.pml_study import PaperSetup, paper_problems
+    probs, rows, wc, wr = paper_problems(PaperSetup())
+    a, r = probs["pml"], probs["ref"]
+    assert np.array_equal(np.array(a.grid.dr_col[:wc]), np.array(r.grid.dr_col[:wc]))
+    ra, rr = rows["pml"], rows["ref"]
+    assert np.array_equal(np.array(a.grid.dz_row[ra:ra + wr]), np.array(r.grid.dz_row[rr:rr + wr]))
+    assert a.scene.surface_j - ra == r.scene.surface_j - rr
+    assert a.scene.layer_j - ra == r.scene.layer_j - rr
+    assert probs["bare"].grid == a.grid and not probs["bare"].pml.enabled and a.pml.enabled
+    # a wave at 6.5 km/s needs over 50 s to cross the reference's extra zone
+    # below the window and come back (the comparisons stop at 40 s)
+    depth = sum(r.grid.dz_row[:rr])
+    assert 2 * depth / 6.5e3 > 50.0
