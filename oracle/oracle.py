@@ -40,7 +40,8 @@ class _Pml(C.Structure):
 
 class _Scene(C.Structure):
     _fields_ = [("surface_j", C.c_int32), ("subsample", C.c_int32), ("radius", C.c_double),
-                ("v_imp", C.c_double), ("gravity", C.c_double), ("layer_j", C.c_int32)]
+                ("v_imp", C.c_double), ("gravity", C.c_double), ("layer_j", C.c_int32),
+                ("layer2_j", C.c_int32)]
 
 
 def _load():
@@ -126,7 +127,7 @@ class Oracle:
         self.NR, self.NZ = g.n_r + g.pml_r, g.n_z + g.pml_b
         self.NC, self.NN = self.NR * self.NZ, (self.NR + 1) * (self.NZ + 1)
         self.nmat = g.nmat
-        mats = (_Mat * 2)(*[_mat(m) for m in problem.mats[:g.nmat]])
+        mats = (_Mat * 3)(*[_mat(m) for m in problem.mats[:g.nmat]])
         pml = problem.pml
         self._h = lib.orc_create(C.byref(_grid(g)), mats, C.byref(_Pml(int(pml.enabled), pml.R, pml.c_ref)))
         if not self._h:
@@ -135,7 +136,7 @@ class Oracle:
         if problem.scene is not None:
             sc = problem.scene
             rc = lib.orc_init_scene(self._h, C.byref(_Scene(sc.surface_j, sc.subsample, sc.radius, sc.v_imp,
-                                                            sc.gravity, sc.layer_j)))
+                                                            sc.gravity, sc.layer_j, sc.layer2_j)))
             if rc:
                 raise ValueError(f"orc_init_scene failed: {rc}")
 

@@ -696,16 +696,18 @@ static void lithostatic(orc_ctx *x, int surface_j, const int *mat_row, double g,
 }
 
 /* scene: target half-space below surface_j (material 0; with two materials
- * and layer_j > 0 the rows below layer_j are material 1, the projectile's),
- * with an optional lithostatic column (gravity > 0), and a spherical
- * projectile (material 1, or 0 when nmat = 1) resting on the surface at the
+ * the rows below layer_j are material 1, with three the rows below layer2_j
+ * material 2 and those from layer2_j to layer_j material 1), with an
+ * optional lithostatic column (gravity > 0), and a spherical projectile of
+ * the last material (that of the deepest layer) resting on the surface at the
  * axis and moving downward (radius 0: none); momentum-exact nodal velocities */
 int orc_init_scene(orc_ctx *x, const orc_scene *s)
 {
     if (!x || !s || s->subsample < 1 || !(s->radius >= 0) || !(s->gravity >= 0)) return ORC_E_INVALID;
     if (s->surface_j < 0 || s->surface_j > x->NZ || s->layer_j < 0 || s->layer_j > s->surface_j) return ORC_E_INVALID;
+    if (s->layer2_j < 0 || s->layer2_j > s->layer_j || (x->nmat < 3 && s->layer2_j != 0)) return ORC_E_INVALID;
     int NR = x->NR, NZ = x->NZ, S = s->subsample;
-    int mp = x->nmat > 1 ? 1 : 0;
+    int mp = x->nmat - 1;
     double R = s->radius, zc = x->zn[s->surface_j] + R;
     double *fp = zalloc(x->NC);
     for (int j = 0; j < NZ && R > 0; j++) {
@@ -727,7 +729,7 @@ int orc_init_scene(orc_ctx *x, const orc_scene *s)
     int *mat_row = (int *)calloc((size_t)NZ + 1, sizeof(int));
     double *rho_row = zalloc((size_t)NZ + 1);
     for (int j = 0; j < s->surface_j; j++) {
-        mat_row[j] = x->nmat > 1 && j < s->layer_j ? 1 : 0;
+        mat_row[j] = x->nmat == 3 && j < s->layer2_j ? 2 : (x->nmat > 1 && j < s->layer_j ? 1 : 0);
         rho_row[j] = x->m[mat_row[j]].rho0;
     }
     memset(x->p0, 0, sizeof(double) * (size_t)NZ);

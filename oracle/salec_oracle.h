@@ -26,7 +26,7 @@
 extern "C" {
 #endif
 
-#define ORC_MAX_MAT 2
+#define ORC_MAX_MAT 3
 
 /* error codes (negative), shared meaning with the product library */
 #define ORC_OK 0
@@ -39,7 +39,7 @@ typedef struct {
     int32_t n_r, n_z;   /* physical cells in r and z                        */
     int32_t pml_r;      /* PML cells to the right of the physical region    */
     int32_t pml_b;      /* PML cells below the physical region              */
-    int32_t nmat;       /* 1 or 2 materials                                 */
+    int32_t nmat;       /* 1 to 3 materials                                 */
     int32_t top_closed; /* 0: open (outflow) top, 1: rigid top wall         */
     double dr, dz;      /* cell size, m                                     */
     double cfl;         /* Courant constant C0                               */
@@ -72,8 +72,10 @@ typedef struct {
     double radius;      /* projectile radius, m (0: no projectile)          */
     double v_imp;       /* impact speed, m/s (downwards)                    */
     double gravity;     /* g, m/s^2 (0: no lithostatic pressure)            */
-    int32_t layer_j;    /* rows below it are material 1 (nmat = 2), the     */
+    int32_t layer_j;    /* rows below it are material 1 (nmat >= 2), the    */
                         /* rows from it up to the surface material 0        */
+    int32_t layer2_j;   /* nmat = 3: rows below it are material 2           */
+                        /* (<= layer_j); the projectile is material nmat-1  */
 } orc_scene;
 
 typedef struct orc_ctx orc_ctx;

@@ -96,7 +96,8 @@ class Scene:
     v_imp: float
     subsample: int = 8
     gravity: float = 0.0     # m/s^2; > 0: lithostatic target (initial pressure p0)
-    layer_j: int = 0         # two materials: rows below it are material 1
+    layer_j: int = 0         # two or three materials: rows below it are material 1
+    layer2_j: int = 0        # three materials: rows below it are material 2 (<= layer_j)
 
 
 @dataclass
@@ -144,6 +145,41 @@ def mantle_like(strength: bool = False, Y0: float = 10e6, mu_f: float = 0.8,
     return m
 
 
+def _with_strength(m: Material, Y0: float, mu_f: float, Ylim: float) -> Material:
+    m.strength = 1
+    m.Y0, m.mu_f, m.Ylim = Y0, mu_f, Ylim
+    m.p_min = -Y0 / mu_f
+    return m
+
+
+def granite(strength: bool = True) -> Material:
+    """Granite crust: the published Tillotson granite constants (rho0 = 2680
+    kg/m^3, A = B = 18 GPa, E0 = 16 MJ/kg, a = 0.5, b = 1.3, alpha = beta = 5,
+    Eiv = 3.5 MJ/kg, Ecv = 18 MJ/kg); with strength, Table 1's intact
+    cohesion 10 MPa, friction 2.0 and limit 2.5 GPa."""
+    m = Material(rho0=2680.0, A=18e9, B=18e9, E0=16e6, a=0.5, b=1.3, alpha=5.0,
+                 beta=5.0, Eiv=3.5e6, Ecv=18e6, p_min=0.0, c_floor_frac=0.25)
+    return _with_strength(m, 10e6, 2.0, 2.5e9) if strength else m
+
+
+def dunite(strength: bool = True) -> Material:
+    """Dunite mantle and projectile: the mantle-rock stand-in's Tillotson
+    constants with Table 1's intact cohesion 10 MPa, friction 1.2 and limit
+    3.5 GPa."""
+    m = mantle_like(strength=False)
+    return _with_strength(m, 10e6, 1.2, 3.5e9) if strength else m
+
+
+def calcite(strength: bool = True) -> Material:
+    """Calcite sediment stand-in (the paper gives strength parameters only):
+    calcite's density 2710 kg/m^3 and A = B = 70 GPa (about calcite's bulk
+    modulus), the other Tillotson constants as basalt; with strength, Table
+    1's intact cohesion 5 MPa, friction 1.0 and limit 0.5 GPa."""
+    m = Material(rho0=2710.0, A=70e9, B=70e9, E0=487e6, a=0.5, b=1.5, alpha=5.0,
+                 beta=5.0, Eiv=4.72e6, Ecv=18.2e6, p_min=0.0, c_floor_frac=0.25)
+    return _with_strength(m, 5e6, 1.0, 0.5e9) if strength else m
+
+
 def ideal_gas(gamma: float = 1.4) -> Material:
     """Tillotson with a = gamma - 1 and b = A = B = 0 is exactly an ideal gas."""
     return Material(rho0=1.0, A=0.0, B=0.0, E0=1.0, a=gamma - 1.0, b=0.0, alpha=5.0,
@@ -183,6 +219,23 @@ def layered_impact(n: int, pml: int, radius_cells: int, v_imp: float, crust_cell
     sc = Scene(surface_j=sj, radius=radius_cells * dx, v_imp=v_imp, gravity=gravity,
                layer_j=max(sj - crust_cells, 0))
     return Problem(grid=g, mats=[basalt(strength=strength), mantle_like(strength=strength)], pml=Pml(),
+                   scene=sc, cycles=cycles, precision=precision, name=name)
+
+
+def three_layer_impact(n: int, pml: int, radius_cells: int, v_imp: float, sed_cells: int, crust_cells: int,
+                       dx: float = 400.0, gravity: float = 9.81, strength: bool = True, cycles: int = 0,
+                       precision: str = "fp64", name: str = "") -> Problem:
+    """The three-layer target of Sec. 4 on an n x n uniform grid: sed_cells
+    rows of calcite (material 0) over crust_cells rows of granite (material
+    1) over a dunite half-space (material 2, also the projectile's),
+    lithostatic under `gravity`, PML right and below. With dx = 400 m the
+    paper's layers are 7 and 75 rows (2.8 km and 30 km)."""
+    g = Grid(n_r=n, n_z=n, pml_r=pml, pml_b=pml, nmat=3, dr=dx, dz=dx)
+    sj = surface_row(n, pml, radius_cells)
+    lj = max(sj - sed_cells, 0)
+    sc = Scene(surface_j=sj, radius=radius_cells * dx, v_imp=v_imp, gravity=gravity,
+               layer_j=lj, layer2_j=max(lj - crust_cells, 0))
+    return Problem(grid=g, mats=[calcite(strength), granite(strength), dunite(strength)], pml=Pml(),
                    scene=sc, cycles=cycles, precision=precision, name=name)
 
 
@@ -246,6 +299,21 @@ def config_paper(precision: str = "fp64") -> Problem:
     sc = Scene(surface_j=sj, radius=R * 400.0, v_imp=12e3, gravity=9.81, layer_j=sj - 82)
     return Problem(grid=g, mats=[basalt(strength=True), mantle_like(strength=True)], pml=Pml(), scene=sc,
                    precision=precision, name="paper-layout")
+
+
+def config_paper_layers(precision: str = "fp64") -> Problem:
+    """Sec. 4's verification setting on Table 2's grid with its three layers:
+    512 x 532 cells as in the two-material setting, a dunite sphere of 7.2 km
+    radius (18 cells) at 12 km/s onto 2.8 km of calcite (7 rows) over 30 km of
+    granite (75 rows) over dunite, with Table 1's intact strength,
+    lithostatic under 9.81 m/s^2."""
+    g = paper_layout(nmat=3)
+    R = 18
+    sj = g.pml_b + 20 + surface_row(462, 0, R)
+    sc = Scene(surface_j=sj, radius=R * 400.0, v_imp=12e3, gravity=9.81, layer_j=sj - 7,
+               layer2_j=sj - 82)
+    return Problem(grid=g, mats=[calcite(), granite(), dunite()], pml=Pml(), scene=sc,
+                   precision=precision, name="paper-layers")
 
 
 def config_small() -> Problem:
