@@ -21,6 +21,9 @@ Also measured (the "extensions" object; skipped with --headline-only):
                  (400 m cells, lithostatic initial pressure), plain FP64
   paper_layout_fp64  the impact on Table 2's stretched 512 x 532 grid (two
                  layers, gravity), plain FP64
+  three_layer_fp64   the 1050^2 workload as Sec. 4's three-layer target
+                 (calcite, granite, dunite; 400 m cells, gravity), plain FP64
+  paper_layers_fp64  Sec. 4's three-layer setting on Table 2's grid, FP64
   pml_payoff     the same small impact with a PML, with plain walls and on a
                  10x larger domain, each to the same time (interior error,
                  reflected energy, crater geometry, device time)
@@ -299,6 +302,11 @@ def main():
                                         args.tune, value)
         ext["paper_layout_fp64"] = extension("Table 2 grid 512x532 fp64", inputs.config_paper(), 300, 20,
                                              args.tune, value)
+        ext["three_layer_fp64"] = extension("three-layer 1050^2 fp64",
+                                            inputs.three_layer_impact(1000, 50, 50, 15e3, 7, 75, name="three"),
+                                            500, 20, args.tune, value)
+        ext["paper_layers_fp64"] = extension("Table 2 grid 512x532 three layers fp64",
+                                             inputs.config_paper_layers(), 300, 20, args.tune, value)
         ext["pml_payoff"] = pml_payoff()
         ext["pml_payoff_table2"] = pml_payoff_table2()
         out["extensions"] = ext

@@ -60,13 +60,13 @@ extern "C" {
                          energy, every mass / volume / energy flux and its sums,
                          and the Courant reduction                               */
 
-#define SALEC_MAX_MAT 2
+#define SALEC_MAX_MAT 3
 
 typedef struct salec_grid {
     int32_t n_r, n_z;    /* physical cells in r and z (>= 1)                      */
     int32_t pml_r;       /* PML cells right of the physical region (>= 0)        */
     int32_t pml_b;       /* PML cells below the physical region (>= 0)           */
-    int32_t nmat;        /* 1 or 2 materials                                     */
+    int32_t nmat;        /* 1 to 3 materials                                     */
     int32_t top_closed;  /* 0: open top (void ghost), 1: rigid top wall          */
     int32_t precision;   /* SALEC_FP64 or SALEC_MIXED                            */
     int32_t reserved;    /* must be 0                                            */
@@ -106,8 +106,11 @@ typedef struct salec_scene {
     double radius;       /* projectile radius, m (0: no projectile)              */
     double v_imp;        /* vertical impact speed, m/s (downwards)               */
     double gravity;      /* g, m/s^2; > 0: lithostatic target (see below)        */
-    int32_t layer_j;     /* two materials: target rows below it are material 1   */
-                         /* (the projectile's), rows from it up material 0       */
+    int32_t layer_j;     /* two or three materials: target rows below it are     */
+                         /* material 1, rows from it up to the surface material 0 */
+    int32_t layer2_j;    /* three materials: rows below it are material 2        */
+                         /* (<= layer_j; 0 otherwise). The projectile is the last */
+                         /* material, that of the deepest layer.                  */
 } salec_scene;
 
 /* Host FP64 arrays; any pointer may be NULL to skip that field.

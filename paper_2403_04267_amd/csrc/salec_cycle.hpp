@@ -49,11 +49,11 @@ struct GeoLds {
   static constexpr int GC = TW + 8, GR = TH + 8, N = 6 * GC + GR;
 };
 
-template <int TW, int TH, class T>
+template <int TW, int TH, class T, int NM>
 struct Smem {
   using R = Regions<TW, TH>;
-  static constexpr int kBigA = 4 * R::NA * (int)sizeof(T);          // sigma[4][NA]
-  static constexpr int kBigC = R::NC * (4 * 8 + 4 * (int)sizeof(T));  // rhoL, IL, f0, f1 | lambda, sL x3
+  static constexpr int kBigA = 4 * R::NA * (int)sizeof(T);                 // sigma[4][NA]
+  static constexpr int kBigC = R::NC * ((2 + NM) * 8 + 4 * (int)sizeof(T));  // rhoL, IL, f[NM] | lambda, sL x3
   static constexpr int kBigF = R::NF * (8 + (int)sizeof(T));          // heat | speed
   static constexpr int kBig = kBigA > kBigC ? (kBigA > kBigF ? kBigA : kBigF) : (kBigC > kBigF ? kBigC : kBigF);
   static constexpr int kBigD = (kBig + 7) / 8;
@@ -109,7 +109,7 @@ __device__ __forceinline__ void reg_put(T (&a)[N], int u, T v) {
   for (int q = 0; q < N; q++) a[q] = (u == q) ? v : a[q];
 }
 
-template <int TW, int TH, int NT, int WPE, class T, bool GEO>
+template <int TW, int TH, int NT, int WPE, class T, bool GEO, int NM>
 __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_rho, double* s_bigd, T* s_vL,
                                            double* s_Fr, double* s_Fz, double* s_rho1, double* s_min,
                                            double* s_geo) {
@@ -199,8 +199,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     j = q < TH ? j0 + q : (q == TH ? j0 - 1 : j0 + TH);
   };
   T* sig = (T*)s_bigd;                // [4][NA] during A..B
-  double* cd = s_bigd;                // [4][NC] rhoL, IL, f0, f1 during C..E2
-  T* ct = (T*)(s_bigd + 4 * R::NC);   // [4][NC] lambda, sL x3 during C..E2
+  double* cd = s_bigd;                     // [2 + NM][NC] rhoL, IL, f[NM] during C..E2
+  T* ct = (T*)(s_bigd + (2 + NM) * R::NC);  // [4][NC] lambda, sL x3 during C..E2
   double* heat = s_bigd;              // [NF] during F..G
   T* speed = (T*)(s_bigd + R::NF);    // [NF] during F..G
   T* s_kd = (T*)s_Fr;                 // [NB] during B..C: 1/2 |v^L - v^n|^2 per node
@@ -214,12 +214,13 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   // level-n values A loads that C needs again, kept in registers for C
   // (FP64 tiles capped at 128 registers reload them instead)
   constexpr bool kKeepA = !(WPE >= 4 && sizeof(T) == 8);
-  double rF0[UA], rF1[UA];
+  double rF[NM][UA];
   T rS0[UA], rS1[UA], rS2[UA], rSx[UA];
 #pragma unroll
   for (int u = 0; u < UA; u++) {
     rP[u] = rS0[u] = rS1[u] = rS2[u] = rSx[u] = T(0);
-    rF0[u] = rF1[u] = 0.0;
+#pragma unroll
+    for (int m = 0; m < NM; m++) rF[m][u] = 0.0;
   }
 #pragma unroll kUnroll
   for (int u = 0; u < UA; u++) {
@@ -244,8 +245,13 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     }
     if (in_cells(g, i, j)) {
       long long c = cidx(g, i, j);
-      const double f0d = S.f[0][c], f1d = g.nmat > 1 ? S.f[1][c] : 0.0;
-      T f[kMaxMat] = {(T)f0d, (T)f1d};
+      double fd[NM];
+      T f[kMaxMat];
+#pragma unroll
+      for (int m = 0; m < kMaxMat; m++) {
+        if (m < NM) fd[m] = m < g.nmat ? S.f[m][c] : 0.0;
+        f[m] = m < NM ? (T)fd[m] : T(0);
+      }
       rh = S.rho[c];
       T phi, iden, rm;
       matter(g, (T)rh, f, phi, iden, rm);
@@ -276,8 +282,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       s2 = phi * (stt - Pf);
       s3 = phi * srz;
       reg_put(rP, u, P);
-      reg_put(rF0, u, f0d);
-      reg_put(rF1, u, f1d);
+#pragma unroll
+      for (int m = 0; m < NM; m++) reg_put(rF[m], u, fd[m]);
       reg_put(rS0, u, srr);
       reg_put(rS1, u, szz);
       reg_put(rS2, u, srz);
@@ -393,7 +399,9 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     a_cell(k, i, j);
     if (i < i0 - 2 || i >= i0 + TW + 2) continue;
     // outside the grid: a void donor (rho^L = 0, lambda = 1, zero state)
-    double oRhoL = 0.0, oIL = 0.0, of0 = 0.0, of1 = 0.0;
+    double oRhoL = 0.0, oIL = 0.0, of[NM];
+#pragma unroll
+    for (int m = 0; m < NM; m++) of[m] = 0.0;
     T oLam = T(1), os0 = T(0), os1 = T(0), os2 = T(0);
     if (in_cells(g, i, j)) {
       long long c = cidx(g, i, j);
@@ -443,9 +451,13 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       T dD = dtT * kn.D;
       T J = T(1) + dD;
       double rho = s_rho[kA(i, j)];
-      double f0n = kKeepA ? reg_get(rF0, u) : S.f[0][c];
-      double f1n = kKeepA ? reg_get(rF1, u) : (g.nmat > 1 ? S.f[1][c] : 0.0);
-      T fq[kMaxMat] = {(T)f0n, (T)f1n};
+      double fn[NM];
+      T fq[kMaxMat];
+#pragma unroll
+      for (int m = 0; m < kMaxMat; m++) {
+        if (m < NM) fn[m] = kKeepA ? reg_get(rF[m], u) : (m < g.nmat ? S.f[m][c] : 0.0);
+        fq[m] = m < NM ? (T)fn[m] : T(0);
+      }
       T phi, iden, rm;
       matter(g, (T)rho, fq, phi, iden, rm);
       T Jm = Vol<T>::ratio(J, dD, phi, kKeepA ? reg_get(rSx, u) : ((const T*)S.eos[4])[c]);
@@ -473,8 +485,9 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       }
       double IL = ((S.I[c] + (double)N::div(Wdt, rden)) + (double)hL) - dt * (psi2 / rt);
       double fr = (double)N::div(Jm, J);
-      double f0 = f0n * fr;
-      double f1 = g.nmat > 1 ? f1n * fr : 0.0;
+      double fLv[NM];
+#pragma unroll
+      for (int m = 0; m < NM; m++) fLv[m] = (m == 0 || m < g.nmat) ? fn[m] * fr : 0.0;
       if (owns_cell(i, j)) {
         if (db > 0.0) {
           T Wr = ((s0rr * kn.err + stt * kn.ett) + s0rz * kn.dvz_dr) - P * kn.Dr;
@@ -490,15 +503,15 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       os0 = srr;
       os1 = szz;
       os2 = srz;
-      of0 = f0;
-      of1 = f1;
+#pragma unroll
+      for (int m = 0; m < NM; m++) of[m] = fLv[m];
       oLam = J;  // the limiter pass below turns J into lambda
     }
     int kc = kC(i, j);
     cd[0 * R::NC + kc] = oRhoL;
     cd[1 * R::NC + kc] = oIL;
-    cd[2 * R::NC + kc] = of0;
-    cd[3 * R::NC + kc] = of1;
+#pragma unroll
+    for (int m = 0; m < NM; m++) cd[(2 + m) * R::NC + kc] = of[m];
     ct[0 * R::NC + kc] = oLam;
     ct[1 * R::NC + kc] = os0;
     ct[2 * R::NC + kc] = os1;
@@ -555,9 +568,13 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   unsigned flags = 0;
   constexpr int UE = (R::NE + NT - 1) / NT;
   constexpr bool kCarry = WPE < 4;
-  double eRho[UE], eI[UE], eF0[UE], eF1[UE];
+  double eRho[UE], eI[UE], eF[NM][UE];
 #pragma unroll
-  for (int u = 0; u < UE; u++) eRho[u] = eI[u] = eF0[u] = eF1[u] = 0.0;
+  for (int u = 0; u < UE; u++) {
+    eRho[u] = eI[u] = 0.0;
+#pragma unroll
+    for (int m = 0; m < NM; m++) eF[m][u] = 0.0;
+  }
 #pragma unroll 1
   for (int u = 0; u < UE; u++) {
     int k = tid + u * NT;
@@ -578,10 +595,14 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       rho1 = s_rho[kA(i, j)] + netin * iV;
       double M1 = rho1 * V;
       double min_ = 0.0, nI = 0.0, nsrr = 0.0, nszz = 0.0, nsrz = 0.0, vcut = 0.0;
-      double nf0 = 0.0, nf1 = 0.0;
+      double nf[NM], fL[NM];
+#pragma unroll
+      for (int m = 0; m < NM; m++) {
+        nf[m] = 0.0;
+        fL[m] = cd[(2 + m) * R::NC + kc];
+      }
       double IL = cd[1 * R::NC + kc];
       double sL0 = (double)ct[1 * R::NC + kc], sL1 = (double)ct[2 * R::NC + kc], sL2 = (double)ct[3 * R::NC + kc];
-      double fL0 = cd[2 * R::NC + kc], fL1 = cd[3 * R::NC + kc];
       double ed[4];
 #pragma unroll
       for (int q = 0; q < 4; q++) {
@@ -597,8 +618,9 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
           nsrr += aF * ((double)ct[1 * R::NC + d] - sL0);
           nszz += aF * ((double)ct[2 * R::NC + d] - sL1);
           nsrz += aF * ((double)ct[3 * R::NC + d] - sL2);
-          nf0 += adV * (cd[2 * R::NC + d] - fL0);
-          if (g.nmat > 1) nf1 += adV * (cd[3 * R::NC + d] - fL1);
+#pragma unroll
+          for (int m = 0; m < NM; m++)
+            if (m == 0 || m < g.nmat) nf[m] += adV * (cd[(2 + m) * R::NC + d] - fL[m]);
           ed[q] = F[q] * Id;
         } else {
           ed[q] = F[q] * IL;
@@ -610,9 +632,13 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       double iden = 1.0 / den;
       double I1 = IL + nI * iden;
       double ex = (1.0 - lam) * O - vcut;
-      double f1a = dmax(fL0 + (nf0 + fL0 * ex) * iV, 0.0);
-      double f1b = g.nmat > 1 ? dmax(fL1 + (nf1 + fL1 * ex) * iV, 0.0) : 0.0;
-      double fs = g.nmat > 1 ? f1a + f1b : f1a;
+      double f1v[NM];
+#pragma unroll
+      for (int m = 0; m < NM; m++) f1v[m] = (m == 0 || m < g.nmat) ? dmax(fL[m] + (nf[m] + fL[m] * ex) * iV, 0.0) : 0.0;
+      double fs = f1v[0];
+#pragma unroll
+      for (int m = 1; m < NM; m++)
+        if (m < g.nmat) fs = fs + f1v[m];
       if (g.pml_on) {
         double db = pm.dcz[j], drr = pm.dcr[i];
         if (db > 0.0 || drr > 0.0) {
@@ -644,10 +670,12 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         long long c = cidx(g, i, j);
         D.rho[c] = rho1;
         double ifs = 1.0 / dmax(fs, 1.0);
-        double fa = f1a * ifs;
-        double fb = f1b * ifs;
-        D.f[0][c] = fa;
-        if (g.nmat > 1) D.f[1][c] = fb;
+        double fv[NM];
+#pragma unroll
+        for (int m = 0; m < NM; m++) {
+          fv[m] = f1v[m] * ifs;
+          if (m == 0 || m < g.nmat) D.f[m][c] = fv[m];
+        }
         T s0n = (T)(sL0 + nsrr * iden), s1n = (T)(sL1 + nszz * iden), s2n = (T)(sL2 + nsrz * iden);
         if (g.any_strength) {
           ((T*)D.s[0])[c] = s0n;
@@ -661,15 +689,16 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         if constexpr (kCarry) {
           reg_put(eRho, u, rho1);
           reg_put(eI, u, I1);  // before the remap heat, which G adds
-          reg_put(eF0, u, fa);
-          reg_put(eF1, u, fb);
+#pragma unroll
+          for (int m = 0; m < NM; m++) reg_put(eF[m], u, fv[m]);
         } else {
           D.I[c] = I1;  // before the remap heat, which G adds
         }
         double chk = rho1 + I1;
         if (g.any_strength) chk += (double)s0n + (double)s1n + (double)s2n;
-        chk += fa;
-        if (g.nmat > 1) chk += fb;
+#pragma unroll
+        for (int m = 0; m < NM; m++)
+          if (m == 0 || m < g.nmat) chk += fv[m];
         if (!((chk - chk) == 0.0)) flags |= kFlagNonFinite;
         if (rho1 < -kNegMassTol * g.rho_ref) flags |= kFlagNegMass;
       }
@@ -815,7 +844,10 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       if (!((sp - sp) == T(0))) flags |= kFlagNonFinite;
       u4 = tmax(u4, sp);
     }
-    double f[kMaxMat] = {kCarry ? eF0[u] : D.f[0][c], kCarry ? eF1[u] : (g.nmat > 1 ? D.f[1][c] : 0.0)};
+    double f[kMaxMat];
+#pragma unroll
+    for (int m = 0; m < kMaxMat; m++)
+      f[m] = m >= NM ? 0.0 : (kCarry ? reg_get(eF[m], u) : (m < g.nmat ? D.f[m][c] : 0.0));
     Mix<T> mx = mixture<T>(g, kCarry ? eRho[u] : D.rho[c], I1, f);
     store_eos(D, c, mx);
     cand = dmin(cand, cell_dt(g, mx, u4, dmin(colD(i).dr, dzD(j))));
@@ -825,11 +857,11 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   if (tid == 0) in.dtpart[tile] = m;
 }
 
-template <int TW, int TH, int NT, int WPE, class T, bool GEO>
+template <int TW, int TH, int NT, int WPE, class T, bool GEO, int NM>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_cycle(const Inst* __restrict__ insts, const TileRef* __restrict__ sched,
                                               int nsched) {
   using R = Regions<TW, TH>;
-  using SM = Smem<TW, TH, T>;
+  using SM = Smem<TW, TH, T, NM>;
   __shared__ double s_rho[R::NA];     // rho^n over A (0 outside the grid)
   __shared__ double s_bigd[SM::kBigD];  // A..B stress; C..E2 Lagrangian state; F..G heat, speed
   __shared__ T s_vL[2 * R::NB];       // v^L over B
@@ -848,7 +880,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     const TileRef tr{csched[e].inst, csched[e].tile};
     if (tr.inst < 0) continue;
     const Inst* in = (const Inst*)(cinst + tr.inst);
-    tile_cycle<TW, TH, NT, WPE, T, GEO>(*in, tr.tile, s_rho, s_bigd, s_vL, s_F, s_F + R::NRF, s_rho1, s_min, s_geo);
+    tile_cycle<TW, TH, NT, WPE, T, GEO, NM>(*in, tr.tile, s_rho, s_bigd, s_vL, s_F, s_F + R::NRF, s_rho1, s_min,
+                                            s_geo);
     __syncthreads();  // LDS is reused by the next entry
   }
 }
@@ -866,7 +899,8 @@ __global__ void k_prime(Inst in) {
   if (t < (long long)g.NR * g.NZ) {
     int j = (int)(t / g.NR), i = (int)(t - (long long)j * g.NR);
     long long c = cidx(g, i, j);
-    double f[kMaxMat] = {S.f[0][c], g.nmat > 1 ? S.f[1][c] : 0.0};
+    double f[kMaxMat];
+    for (int m = 0; m < kMaxMat; m++) f[m] = m < g.nmat ? S.f[m][c] : 0.0;
     Mix<T> mx = mixture<T>(g, S.rho[c], S.I[c], f);
     store_eos(S, c, mx);
     const long long nd[4] = {nidx(g, i, j), nidx(g, i + 1, j), nidx(g, i, j + 1), nidx(g, i + 1, j + 1)};
@@ -890,37 +924,69 @@ __global__ void k_prime(Inst in) {
 // Instantiates the cycle kernel of every tile shape and the priming kernel
 // for one bulk type (one translation unit per type keeps builds parallel).
 #define SALEC_CYCLE_TABLE(T, suffix)                                                         \
-  CycleFn cycle_kernel_##suffix(int v) {                                                     \
+  static CycleFn cycle_uni2_##suffix(int v) {                                                \
     switch (v) {                                                                             \
-      case 0: return k_cycle<64, 14, 768, 3, T, false>;                                      \
-      case 1: return k_cycle<40, 16, 512, 4, T, false>;                                      \
-      case 2: return k_cycle<32, 20, 512, 4, T, false>;                                      \
-      case 3: return k_cycle<64, 15, 768, 3, T, false>;                                      \
-      case 4: return k_cycle<64, 16, 768, 3, T, false>;                                      \
-      case 5: return k_cycle<48, 20, 768, 3, T, false>;                                      \
-      case 6: return k_cycle<40, 24, 768, 3, T, false>;                                      \
-      case 7: return k_cycle<28, 18, 512, 4, T, false>;                                      \
-      case 8: return k_cycle<64, 16, 1024, 4, T, false>;                                     \
-      case 9: return k_cycle<32, 32, 1024, 4, T, false>;                                     \
-      case 10: return k_cycle<20, 13, 256, 3, T, false>;                                     \
+      case 0: return k_cycle<64, 14, 768, 3, T, false, 2>;                                   \
+      case 1: return k_cycle<40, 16, 512, 4, T, false, 2>;                                   \
+      case 2: return k_cycle<32, 20, 512, 4, T, false, 2>;                                   \
+      case 3: return k_cycle<64, 15, 768, 3, T, false, 2>;                                   \
+      case 4: return k_cycle<64, 16, 768, 3, T, false, 2>;                                   \
+      case 5: return k_cycle<48, 20, 768, 3, T, false, 2>;                                   \
+      case 6: return k_cycle<40, 24, 768, 3, T, false, 2>;                                   \
+      case 7: return k_cycle<28, 18, 512, 4, T, false, 2>;                                   \
+      case 8: return k_cycle<64, 16, 1024, 4, T, false, 2>;                                  \
+      case 9: return k_cycle<32, 32, 1024, 4, T, false, 2>;                                  \
+      case 10: return k_cycle<20, 13, 256, 3, T, false, 2>;                                  \
       default: return nullptr;                                                               \
     }                                                                                        \
   }                                                                                          \
-  CycleFn cycle_kernel_geo_##suffix(int v) {                                                 \
+  static CycleFn cycle_uni3_##suffix(int v) {                                                \
     switch (v) {                                                                             \
-      case 0: return k_cycle<64, 14, 768, 3, T, true>;                                       \
-      case 1: return k_cycle<40, 16, 512, 4, T, true>;                                       \
-      case 2: return k_cycle<32, 20, 512, 4, T, true>;                                       \
-      case 3: return k_cycle<64, 15, 768, 3, T, true>;                                       \
-      case 4: return k_cycle<64, 16, 768, 3, T, true>;                                       \
-      case 5: return k_cycle<48, 20, 768, 3, T, true>;                                       \
-      case 6: return k_cycle<40, 24, 768, 3, T, true>;                                       \
-      case 7: return k_cycle<28, 18, 512, 4, T, true>;                                       \
-      case 8: return k_cycle<64, 16, 1024, 4, T, true>;                                      \
-      case 9: return k_cycle<32, 32, 1024, 4, T, true>;                                      \
-      case 10: return k_cycle<20, 13, 256, 3, T, true>;                                      \
+      case 0: return k_cycle<64, 14, 768, 3, T, false, 3>;                                   \
+      case 1: return k_cycle<40, 16, 512, 4, T, false, 3>;                                   \
+      case 2: return k_cycle<32, 20, 512, 4, T, false, 3>;                                   \
+      case 3: return k_cycle<64, 15, 768, 3, T, false, 3>;                                   \
+      case 5: return k_cycle<48, 20, 768, 3, T, false, 3>;                                   \
+      case 6: return k_cycle<40, 24, 768, 3, T, false, 3>;                                   \
+      case 7: return k_cycle<28, 18, 512, 4, T, false, 3>;                                   \
+      case 9: return k_cycle<32, 32, 1024, 4, T, false, 3>;                                  \
+      case 10: return k_cycle<20, 13, 256, 3, T, false, 3>;                                  \
       default: return nullptr;                                                               \
     }                                                                                        \
+  }                                                                                          \
+  static CycleFn cycle_geo2_##suffix(int v) {                                                \
+    switch (v) {                                                                             \
+      case 0: return k_cycle<64, 14, 768, 3, T, true, 2>;                                    \
+      case 1: return k_cycle<40, 16, 512, 4, T, true, 2>;                                    \
+      case 2: return k_cycle<32, 20, 512, 4, T, true, 2>;                                    \
+      case 3: return k_cycle<64, 15, 768, 3, T, true, 2>;                                    \
+      case 4: return k_cycle<64, 16, 768, 3, T, true, 2>;                                    \
+      case 5: return k_cycle<48, 20, 768, 3, T, true, 2>;                                    \
+      case 6: return k_cycle<40, 24, 768, 3, T, true, 2>;                                    \
+      case 7: return k_cycle<28, 18, 512, 4, T, true, 2>;                                    \
+      case 8: return k_cycle<64, 16, 1024, 4, T, true, 2>;                                   \
+      case 9: return k_cycle<32, 32, 1024, 4, T, true, 2>;                                   \
+      case 10: return k_cycle<20, 13, 256, 3, T, true, 2>;                                   \
+      default: return nullptr;                                                               \
+    }                                                                                        \
+  }                                                                                          \
+  static CycleFn cycle_geo3_##suffix(int v) {                                                \
+    switch (v) {                                                                             \
+      case 0: return k_cycle<64, 14, 768, 3, T, true, 3>;                                    \
+      case 1: return k_cycle<40, 16, 512, 4, T, true, 3>;                                    \
+      case 2: return k_cycle<32, 20, 512, 4, T, true, 3>;                                    \
+      case 3: return k_cycle<64, 15, 768, 3, T, true, 3>;                                    \
+      case 5: return k_cycle<48, 20, 768, 3, T, true, 3>;                                    \
+      case 6: return k_cycle<40, 24, 768, 3, T, true, 3>;                                    \
+      case 7: return k_cycle<28, 18, 512, 4, T, true, 3>;                                    \
+      case 9: return k_cycle<32, 32, 1024, 4, T, true, 3>;                                   \
+      case 10: return k_cycle<20, 13, 256, 3, T, true, 3>;                                   \
+      default: return nullptr;                                                               \
+    }                                                                                        \
+  }                                                                                          \
+  CycleFn cycle_kernel_##suffix(int v, bool geo, int nm) {                                   \
+    if (nm <= 2) return geo ? cycle_geo2_##suffix(v) : cycle_uni2_##suffix(v);               \
+    return geo ? cycle_geo3_##suffix(v) : cycle_uni3_##suffix(v);                            \
   }                                                                                          \
   hipError_t launch_prime_##suffix(const Inst& in, hipStream_t st) {                           \
     long long nc = (long long)in.g.NR * in.g.NZ;                                               \

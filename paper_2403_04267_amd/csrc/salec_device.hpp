@@ -14,7 +14,7 @@
 
 namespace salec {
 
-constexpr int kMaxMat = 2;
+constexpr int kMaxMat = 3;
 constexpr double kPhiEps = 1e-12;       // volume fraction treated as void
 constexpr double kRhoEosFloor = 1e-6;   // EoS density floor (x rho0)
 constexpr double kRhoDenFloor = 1e-6;   // energy-update density floor (x rho_ref)

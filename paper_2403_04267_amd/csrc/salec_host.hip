@@ -135,11 +135,11 @@ std::vector<double> geometry_table(const Member& mb) {
 // the cold pressure A mu + B mu^2 of the final density, evaluated as the
 // cycle kernel evaluates the equation of state at E = 0, so that a target at
 // rest is in exact discrete equilibrium (p - p0 = 0 in every cell).
-void lithostatic_column(const Member& mb, int surface_j, int layer_j, double grav, std::vector<double>& rho_row,
-                        std::vector<double>& p0) {
+void lithostatic_column(const Member& mb, int surface_j, int layer_j, int layer2_j, double grav,
+                        std::vector<double>& rho_row, std::vector<double>& p0) {
   const Geo& g = mb.g;
   for (int j = surface_j - 1; j >= 0; j--) {
-    const MatC& m = g.m[g.nmat > 1 && j < layer_j ? 1 : 0];
+    const MatC& m = g.m[g.nmat == 3 && j < layer2_j ? 2 : (g.nmat > 1 && j < layer_j ? 1 : 0)];
     const bool top = j == surface_j - 1;
     const double p_up = top ? 0.0 : p0[j + 1];
     const double w_up = top ? 0.0 : grav * (0.5 * mb.dzr[j + 1]) * rho_row[j + 1];
@@ -282,7 +282,7 @@ int validate(const salec_grid* g, const salec_material* mats, const salec_pml* p
   if (g->n_r < 1 || g->n_z < 1 || g->pml_r < 0 || g->pml_b < 0) return why = "grid sizes", SALEC_E_INVALID;
   if ((long long)(g->n_r + g->pml_r + 1) * (g->n_z + g->pml_b + 1) > (1ll << 31))
     return why = "grid too large for one instance", SALEC_E_INVALID;
-  if (g->nmat < 1 || g->nmat > SALEC_MAX_MAT) return why = "nmat must be 1 or 2", SALEC_E_INVALID;
+  if (g->nmat < 1 || g->nmat > SALEC_MAX_MAT) return why = "nmat must be 1, 2 or 3", SALEC_E_INVALID;
   if (g->precision != SALEC_FP64 && g->precision != SALEC_MIXED) return why = "precision", SALEC_E_INVALID;
   if (!(g->dr > 0) || !(g->dz > 0)) return why = "cell size must be > 0", SALEC_E_INVALID;
   if (!(g->cfl > 0) || g->cfl > 1.0) return why = "cfl must be in (0, 1]", SALEC_E_INVALID;
@@ -411,7 +411,8 @@ int check_members(const salec_instance* inst, int32_t n, std::vector<Member>& ms
       return why = "every instance of a context must use the same precision", SALEC_E_INVALID;
     const salec_scene& sc = I.scene;
     if (I.has_scene && (sc.subsample < 1 || !(sc.radius >= 0) || !(sc.gravity >= 0) || sc.surface_j < 0 ||
-                        sc.surface_j > I.grid.n_z + I.grid.pml_b || sc.layer_j < 0 || sc.layer_j > sc.surface_j))
+                        sc.surface_j > I.grid.n_z + I.grid.pml_b || sc.layer_j < 0 || sc.layer_j > sc.surface_j ||
+                        sc.layer2_j < 0 || sc.layer2_j > sc.layer_j || (I.grid.nmat < 3 && sc.layer2_j != 0)))
       return why = "instance " + std::to_string(k) + ": scene parameters", SALEC_E_INVALID;
     const int NR = I.grid.n_r + I.grid.pml_r, NZ = I.grid.n_z + I.grid.pml_b;
     for (int i = 0; I.grid.dr_col && i < NR; i++)
@@ -436,6 +437,7 @@ struct salec_ctx {
   Layout L;
   int prec = 0;
   bool geo = false;  // some member is stretched: the cycle kernel reads geometry tables
+  int nm = 2;        // material slots of the cycle kernel: 3 when some member has three materials
   void* buf = nullptr;
   hipStream_t st = nullptr;
   bool own_stream = false;
@@ -513,7 +515,7 @@ int capture(salec_ctx* x, int ncyc, hipGraphExec_t* out) {
   HIPCHK(x, hipStreamBeginCapture(x->st, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
   for (int k = 0; k < ncyc && le == hipSuccess; k++) {
-    le = launch_cycle(x->variant, x->prec, x->geo, x->L.d_inst, x->L.d_sched, x->nsched, grid, x->st);
+    le = launch_cycle(x->variant, x->prec, x->geo, x->nm, x->L.d_inst, x->L.d_sched, x->nsched, grid, x->st);
     if (le == hipSuccess) le = launch_finalize(x->L.d_inst, (int)x->ms.size(), x->st);
   }
   hipError_t e = hipStreamEndCapture(x->st, &gr);
@@ -532,6 +534,10 @@ int capture(salec_ctx* x, int ncyc, hipGraphExec_t* out) {
 int use_schedule(salec_ctx* x, int v, int grid) {
   if (v < 0 || v >= n_variants() || grid < 0) {
     x->err = "schedule out of range";
+    return SALEC_E_INVALID;
+  }
+  if (!variant_available(v, x->prec, x->geo, x->nm)) {
+    x->err = "tile shape not available for three materials (its tile does not fit the LDS)";
     return SALEC_E_INVALID;
   }
   HIPCHK(x, hipStreamSynchronize(x->st));
@@ -591,8 +597,10 @@ int init_common(salec_ctx* x, void* dev_buf, size_t dev_bytes, void* stream) {
   }
   x->buf = dev_buf;
   x->prec = x->ms[0].g.prec;
-  for (const Member& mb : x->ms)
+  for (const Member& mb : x->ms) {
     if (mb.g.stretched) x->geo = true;
+    if (mb.g.nmat > 2) x->nm = 3;
+  }
   carve_all(x->ms, dev_buf, x->L);
   if (stream) {
     x->st = (hipStream_t)stream;
@@ -616,7 +624,8 @@ int init_common(salec_ctx* x, void* dev_buf, size_t dev_bytes, void* stream) {
     std::vector<double> rho_row;
     if (mb.has_scene && mb.scene.gravity > 0) {
       rho_row.assign((size_t)mb.g.NZ, 0.0);
-      lithostatic_column(mb, mb.scene.surface_j, mb.scene.layer_j, mb.scene.gravity, rho_row, mb.p0);
+      lithostatic_column(mb, mb.scene.surface_j, mb.scene.layer_j, mb.scene.layer2_j, mb.scene.gravity, rho_row,
+                         mb.p0);
     }
     HIPCHK(x, hipMemcpyAsync((void*)mb.d.p0, mb.p0.data(), mb.p0.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
     mb.g.has_p0 = 0;
@@ -632,8 +641,8 @@ int init_common(salec_ctx* x, void* dev_buf, size_t dev_bytes, void* stream) {
         rr = x->L.scratch + (size_t)mb.g.NZ * mb.g.pc;
         HIPCHK(x, hipMemcpyAsync(rr, rho_row.data(), rho_row.size() * sizeof(double), hipMemcpyHostToDevice, x->st));
       }
-      HIPCHK(x, launch_scene(mb.d, sc.surface_j, sc.layer_j, sc.subsample, sc.radius, zc, sc.v_imp, rr,
-                             x->L.scratch, x->st));
+      HIPCHK(x, launch_scene(mb.d, sc.surface_j, sc.layer_j, sc.layer2_j, sc.subsample, sc.radius, zc, sc.v_imp,
+                             rr, x->L.scratch, x->st));
     }
     HIPCHK(x, hipStreamSynchronize(x->st));  // the profile vectors are reused below
     int rc = start_run(x, (int)k);
@@ -643,7 +652,7 @@ int init_common(salec_ctx* x, void* dev_buf, size_t dev_bytes, void* stream) {
   const int v0 = default_variant(x->prec);
   int rc = use_schedule(x, v0, 0);
   if (rc) return rc;
-  const int g0 = resident_groups(v0, x->prec, x->geo);
+  const int g0 = resident_groups(v0, x->prec, x->geo, x->nm);
   if (g0 > 0 && g0 < x->nsched && (rc = use_schedule(x, v0, g0))) return rc;
   x->ready = true;
   return SALEC_OK;
@@ -778,7 +787,7 @@ int salec_time_kernels(salec_ctx* x, int32_t n, double* cycle_ms, double* finali
   const int grid = x->grid > 0 ? std::min(x->grid, x->nsched) : x->nsched;
   hipError_t e = rc ? hipErrorOutOfMemory : hipEventRecord(ev[0], x->st);
   for (int c = 0; c < n && e == hipSuccess; c++) {
-    e = launch_cycle(x->variant, x->prec, x->geo, x->L.d_inst, x->L.d_sched, x->nsched, grid, x->st);
+    e = launch_cycle(x->variant, x->prec, x->geo, x->nm, x->L.d_inst, x->L.d_sched, x->nsched, grid, x->st);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * c + 1], x->st);
     if (e == hipSuccess) e = launch_finalize(x->L.d_inst, (int)x->ms.size(), x->st);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * c + 2], x->st);
@@ -1019,9 +1028,10 @@ int salec_tune(salec_ctx* x, int32_t cycles, salec_schedule* out) {
   int best_v = x->variant, best_g = x->grid;
   double best = 1e300;
   for (int v = 0; v < n_variants(); v++) {
+    if (!variant_available(v, x->prec, x->geo, x->nm)) continue;
     // one workgroup per tile, and as many workgroups as fit at once walking
     // the tiles (when that is fewer than the tiles)
-    int grids[2] = {0, resident_groups(v, x->prec, x->geo)};
+    int grids[2] = {0, resident_groups(v, x->prec, x->geo, x->nm)};
     for (int gi = 0; gi < 2; gi++) {
       if (gi == 1 && (grids[1] <= 0 || grids[1] >= x->nsched)) continue;
       int rc = use_schedule(x, v, grids[gi]);

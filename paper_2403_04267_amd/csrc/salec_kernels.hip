@@ -35,7 +35,7 @@ inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs)
 // node velocities (state level 0)
 // ======================================================================
 template <class T>
-__global__ void k_scene_cells(Inst in, int surface_j, int layer_j, int S, double R, double zc,
+__global__ void k_scene_cells(Inst in, int surface_j, int layer_j, int layer2_j, int S, double R, double zc,
                               const double* rho_row, double* fproj) {
   const Geo& g = in.g;
   const State& S0 = in.S[0];
@@ -55,11 +55,11 @@ __global__ void k_scene_cells(Inst in, int surface_j, int layer_j, int S, double
     }
   }
   double fp = R > 0.0 ? num / den : 0.0;
-  int mp = g.nmat > 1 ? 1 : 0;
-  double f[kMaxMat] = {0.0, 0.0};
+  int mp = g.nmat - 1;  // the projectile: the last material
+  double f[kMaxMat] = {0.0, 0.0, 0.0};
   double rho;
-  if (j < surface_j) {  // target row: material 1 below layer_j (two materials), else 0
-    const int mt = g.nmat > 1 && j < layer_j ? 1 : 0;
+  if (j < surface_j) {  // target row: the layer's material (the last one is the deepest)
+    const int mt = g.nmat == 3 && j < layer2_j ? 2 : (g.nmat > 1 && j < layer_j ? 1 : 0);
     f[mt] = 1.0;
     rho = rho_row ? rho_row[j] : g.m[mt].rho0;
   } else {
@@ -80,7 +80,7 @@ __global__ void k_scene_nodes(Inst in, const double* fproj, double v_imp) {
   const State& S0 = in.S[0];
   int i, j;
   if (!node_of(g, i, j)) return;
-  int mp = g.nmat > 1 ? 1 : 0;
+  int mp = g.nmat - 1;  // the projectile: the last material
   double Mt = 0.0, Mp = 0.0;
   const int qi[4] = {i - 1, i, i - 1, i}, qj[4] = {j - 1, j - 1, j, j};
   for (int q = 0; q < 4; q++) {
@@ -153,7 +153,8 @@ __global__ void k_eos_out(Inst in, double* p, double* c2) {
   if (!cell_of(g, i, j)) return;
   const State& S = in.S[in.sc->cycle & 1];
   long long c = cidx(g, i, j);
-  double f[kMaxMat] = {S.f[0][c], g.nmat > 1 ? S.f[1][c] : 0.0};
+  double f[kMaxMat];
+  for (int m = 0; m < kMaxMat; m++) f[m] = m < g.nmat ? S.f[m][c] : 0.0;
   Mix<T> mx = mixture<T>(g, S.rho[c], S.I[c], f);
   p[c] = (double)mx.p;
   c2[c] = (double)mx.c2;
@@ -249,16 +250,16 @@ __global__ void k_diag_final(const double* red, int nblocks, double* out) {
 // ======================================================================
 // launchers
 // ======================================================================
-hipError_t launch_scene(const Inst& in, int surface_j, int layer_j, int S, double R, double zc, double v_imp,
-                        const double* rho_row, double* scratch, hipStream_t st) {
+hipError_t launch_scene(const Inst& in, int surface_j, int layer_j, int layer2_j, int S, double R, double zc,
+                        double v_imp, const double* rho_row, double* scratch, hipStream_t st) {
   const int bs = 256;
   long long nc = (long long)in.g.NR * in.g.NZ, nn = (long long)(in.g.NR + 1) * (in.g.NZ + 1);
   if (in.g.prec == 0) {
-    hipLaunchKernelGGL(k_scene_cells<double>, dim3(nblk(nc, bs)), dim3(bs), 0, st, in, surface_j, layer_j, S, R, zc,
+    hipLaunchKernelGGL(k_scene_cells<double>, dim3(nblk(nc, bs)), dim3(bs), 0, st, in, surface_j, layer_j, layer2_j, S, R, zc,
                        rho_row, scratch);
     hipLaunchKernelGGL(k_scene_nodes<double>, dim3(nblk(nn, bs)), dim3(bs), 0, st, in, scratch, v_imp);
   } else {
-    hipLaunchKernelGGL(k_scene_cells<float>, dim3(nblk(nc, bs)), dim3(bs), 0, st, in, surface_j, layer_j, S, R, zc,
+    hipLaunchKernelGGL(k_scene_cells<float>, dim3(nblk(nc, bs)), dim3(bs), 0, st, in, surface_j, layer_j, layer2_j, S, R, zc,
                        rho_row, scratch);
     hipLaunchKernelGGL(k_scene_nodes<float>, dim3(nblk(nn, bs)), dim3(bs), 0, st, in, scratch, v_imp);
   }

@@ -44,7 +44,8 @@ class PmlC(C.Structure):
 
 class SceneC(C.Structure):
     _fields_ = [("surface_j", C.c_int32), ("subsample", C.c_int32), ("radius", C.c_double),
-                ("v_imp", C.c_double), ("gravity", C.c_double), ("layer_j", C.c_int32)]
+                ("v_imp", C.c_double), ("gravity", C.c_double), ("layer_j", C.c_int32),
+                ("layer2_j", C.c_int32)]
 
 
 _DP = C.POINTER(C.c_double)
@@ -62,7 +63,7 @@ class Diag(C.Structure):
 
 
 class Instance(C.Structure):
-    _fields_ = [("grid", Grid), ("mats", Material * 2), ("pml", PmlC), ("scene", SceneC),
+    _fields_ = [("grid", Grid), ("mats", Material * 3), ("pml", PmlC), ("scene", SceneC),
                 ("has_scene", C.c_int32), ("reserved", C.c_int32)]
 
 
@@ -148,7 +149,7 @@ def _mat(m) -> Material:
 
 
 def _mats(problem):
-    arr = (Material * 2)()
+    arr = (Material * 3)()
     for k, m in enumerate(problem.mats[:problem.grid.nmat]):
         arr[k] = _mat(m)
     return arr
@@ -164,7 +165,8 @@ def _instance(problem, keep: list) -> Instance:
     inst.pml = PmlC(int(p.enabled), 0, p.R, p.c_ref)
     if problem.scene is not None:
         sc = problem.scene
-        inst.scene = SceneC(sc.surface_j, sc.subsample, sc.radius, sc.v_imp, sc.gravity, sc.layer_j)
+        inst.scene = SceneC(sc.surface_j, sc.subsample, sc.radius, sc.v_imp, sc.gravity, sc.layer_j,
+                             sc.layer2_j)
         inst.has_scene = 1
     return inst
 

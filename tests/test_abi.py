@@ -26,7 +26,7 @@ def test_plan_accepts_workloads_and_scales():
 
 
 @pytest.mark.parametrize("field,value", [
-    ("n_r", 0), ("pml_b", -1), ("nmat", 3), ("dr", 0.0), ("cfl", 1.5), ("cfl", 0.0),
+    ("n_r", 0), ("pml_b", -1), ("nmat", 4), ("dr", 0.0), ("cfl", 1.5), ("cfl", 0.0),
     ("dt_grow", 0.5), ("q_lin", -1.0),
 ])
 def test_plan_rejects_invalid_grids(field, value):
