@@ -21,7 +21,7 @@ _lib = None
 class _Grid(C.Structure):
     _fields_ = [("n_r", C.c_int32), ("n_z", C.c_int32), ("pml_r", C.c_int32),
                 ("pml_b", C.c_int32), ("nmat", C.c_int32), ("top_closed", C.c_int32),
-                ("dr", C.c_double), ("dz", C.c_double), ("cfl", C.c_double),
+                ("closure", C.c_int32), ("dr", C.c_double), ("dz", C.c_double), ("cfl", C.c_double),
                 ("dt_grow", C.c_double), ("dt_max", C.c_double), ("dt_floor", C.c_double),
                 ("t_stop", C.c_double), ("q_lin", C.c_double), ("q_quad", C.c_double),
                 ("dr_col", C.POINTER(C.c_double)), ("dz_row", C.POINTER(C.c_double))]
@@ -62,6 +62,8 @@ def _load():
     lib.orc_init_scene.argtypes = [P, C.POINTER(_Scene)]
     lib.orc_set_fields.argtypes = [P, D, D, D, D, D]
     lib.orc_set_p0.argtypes = [P, D]
+    lib.orc_set_materials.argtypes = [P, D, D]
+    lib.orc_get_materials.argtypes = [P, D, D]
     lib.orc_get_p0.argtypes = [P, D]
     lib.orc_step.argtypes = [P, C.c_int32]
     lib.orc_get_fields.argtypes = [P, D, D, D, D, D, D, D]
@@ -93,7 +95,7 @@ def _grid(g) -> _Grid:
     kept alive on the returned structure for as long as it is used."""
     drc = None if g.dr_col is None else np.ascontiguousarray(g.dr_col, dtype=np.float64)
     dzr = None if g.dz_row is None else np.ascontiguousarray(g.dz_row, dtype=np.float64)
-    out = _Grid(g.n_r, g.n_z, g.pml_r, g.pml_b, g.nmat, g.top_closed, g.dr, g.dz, g.cfl,
+    out = _Grid(g.n_r, g.n_z, g.pml_r, g.pml_b, g.nmat, g.top_closed, g.closure, g.dr, g.dz, g.cfl,
                 g.dt_grow, g.dt_max, g.dt_floor, g.t_stop, g.q_lin, g.q_quad, _ptr(drc), _ptr(dzr))
     out._keep = (drc, dzr)
     return out
@@ -167,6 +169,23 @@ class Oracle:
         out = np.empty(self.NZ)
         self._lib.orc_get_p0(self._h, _ptr(out))
         return out
+
+    def set_materials(self, mu, Im):
+        """Per-material state (closure 1): partial densities and specific
+        energies, each (nmat, NZ, NR)."""
+        n = self.nmat * self.NC
+        mu = np.ascontiguousarray(mu, dtype=np.float64).reshape(n)
+        Im = np.ascontiguousarray(Im, dtype=np.float64).reshape(n)
+        if self._lib.orc_set_materials(self._h, _ptr(mu), _ptr(Im)):
+            raise ValueError("orc_set_materials failed")
+
+    def materials(self) -> dict:
+        """{"mu": partial densities, "Im": specific energies}, (nmat, NZ, NR)."""
+        mu, Im = np.empty(self.nmat * self.NC), np.empty(self.nmat * self.NC)
+        if self._lib.orc_get_materials(self._h, _ptr(mu), _ptr(Im)):
+            raise ValueError("orc_get_materials failed (closure 0)")
+        shp = (self.nmat, self.NZ, self.NR)
+        return {"mu": mu.reshape(shp), "Im": Im.reshape(shp)}
 
     def step(self, n: int, check: bool = True) -> int:
         rc = self._lib.orc_step(self._h, int(n))

@@ -51,12 +51,15 @@
 #define W_HI 1e-2           /* volume fraction where the CFL weight is 1     */
 #define NEG_MASS_TOL 1e-9   /* density below -tol*rho_ref is an error        */
 #define PCAV_FRAC 1e-4      /* pressure ramp of the cavitation rule, fraction of A */
+#define F_PM_EPS 1e-6       /* closure 1: a material below this volume fraction
+                               takes the cell's matter density in its EoS  */
 
 struct orc_ctx {
     orc_grid g;
     orc_mat m[ORC_MAX_MAT];
     orc_pml pml;
     int NR, NZ, NC, NN, nmat, any_strength;
+    int pm; /* closure 1: per-material density and specific energy */
     double rho_ref, Gm[ORC_MAX_MAT]; /* shear / bulk modulus ratio per material */
 
     /* state at the start of the cycle */
@@ -86,6 +89,14 @@ struct orc_ctx {
     double *J, *IL, *sLrr, *sLzz, *sLrz, *fL[ORC_MAX_MAT];
     double *dVr, *Fr, *dVz, *Fz, *dVre, *dVze, *lam, *outv;
     double *rho_n, *I_n, *f_n[ORC_MAX_MAT], *srr_n, *szz_n, *srz_n, *vr_n, *vz_n;
+
+    /* closure 1: partial densities mu_m (mass of material m per cell volume)
+     * and specific energies I_m (state), the material pressures and densities
+     * the cycle's EoS used, Lagrangian energies, per-material face mass fluxes;
+     * rho and I then hold sum(mu_m) and the mass-weighted energy */
+    double *mu[ORC_MAX_MAT], *Im[ORC_MAX_MAT], *mu_n[ORC_MAX_MAT], *Im_n[ORC_MAX_MAT];
+    double *pmm[ORC_MAX_MAT], *rhm[ORC_MAX_MAT], *ILm[ORC_MAX_MAT];
+    double *Fmr[ORC_MAX_MAT], *Fmz[ORC_MAX_MAT];
 };
 
 #define CI(i, j) ((j) * NR + (i))
@@ -262,6 +273,73 @@ static void mixture(const orc_ctx *x, int c, const double *rho, const double *I,
     *phi_o = phi;
 }
 
+/* Closure 1: the same volume-fraction average, each material at its own
+ * density rho_m = mu_m / f_m and its own specific energy I_m (materials below
+ * F_PM_EPS, or without mass, at the cell's matter density). Also returns the
+ * material pressures (after the floor) and densities the energy update uses. */
+static void mixture_pm(const orc_ctx *x, int c, const double *rho, double *const *f, double *const *mu,
+                       double *const *Im, double *p_o, double *c2_o, double *G_o, double *Y_o,
+                       double *rmat_o, double *phi_o, double *sx_o, double *pm_o, double *rhm_o)
+{
+    double phi = 0.0;
+    for (int m = 0; m < x->nmat; m++) phi += f[m][c];
+    double den = phi > PHI_EPS ? phi : PHI_EPS;
+    double iden = 1.0 / den;
+    double rm = rho[c] * iden;
+    double p = 0.0, c2 = 0.0, G = 0.0;
+    double wm[ORC_MAX_MAT], sf[ORC_MAX_MAT];
+    for (int m = 0; m < x->nmat; m++) {
+        double fm = f[m][c], mm = mu[m][c];
+        double rmm = fm > F_PM_EPS && mm > 0.0 ? mm / fm : rm;
+        double pm, c2m;
+        wm[m] = fm * iden;
+        orc_tillotson(&x->m[m], rmm, Im[m][c], &pm, &c2m);
+        pm = dmax(pm, x->m[m].p_min);
+        c2m = dmax(c2m, x->m[m].c_floor_frac * x->m[m].A / x->m[m].rho0);
+        p += wm[m] * pm;
+        c2 += wm[m] * c2m;
+        sf[m] = orc_softening(&x->m[m], Im[m][c]);
+        G += wm[m] * (sf[m] * (x->Gm[m] * (rmm * c2m)));
+        if (pm_o) pm_o[m] = pm;
+        if (rhm_o) rhm_o[m] = rmm;
+    }
+    double Y = 0.0, pmin = 0.0, ps = 0.0;
+    for (int m = 0; m < x->nmat; m++) {
+        Y += wm[m] * (sf[m] * orc_yield(&x->m[m], p));
+        pmin += wm[m] * x->m[m].p_min;
+        ps += wm[m] * (PCAV_FRAC * x->m[m].A);
+    }
+    double d = p - pmin;
+    *sx_o = d >= ps ? 1.0 : (ps > 0.0 ? dmax(d, 0.0) / ps : 0.0);
+    *p_o = p;
+    *c2_o = c2;
+    *G_o = G;
+    *Y_o = Y;
+    *rmat_o = rm;
+    *phi_o = phi;
+}
+
+/* the cell's mixture under the context's closure (state at the cycle start) */
+static void cell_mixture(const orc_ctx *x, int c, double *p_o, double *c2_o, double *G_o, double *Y_o,
+                         double *rmat_o, double *phi_o, double *sx_o, double *pm_o, double *rhm_o)
+{
+    if (x->pm)
+        mixture_pm(x, c, x->rho, x->f, x->mu, x->Im, p_o, c2_o, G_o, Y_o, rmat_o, phi_o, sx_o, pm_o, rhm_o);
+    else
+        mixture(x, c, x->rho, x->I, x->f, p_o, c2_o, G_o, Y_o, rmat_o, phi_o, sx_o);
+}
+
+/* closure 1: rho = sum of the partial densities, I = their mass-weighted
+ * specific energy (0 where there is no mass) */
+static void derive_cell(const orc_ctx *x, double *const *mu, double *const *Im, double *rho, double *I, int c)
+{
+    double r = 0.0, e = 0.0;
+    for (int m = 0; m < x->nmat; m++) r += mu[m][c];
+    for (int m = 0; m < x->nmat; m++) e += mu[m][c] * Im[m][c];
+    rho[c] = r;
+    I[c] = r > 0.0 ? e / r : 0.0;
+}
+
 /* ========================================================================
  * Cell kinematics: face-mean velocities, flux-form divergence and the
  * strain-rate / spin components of cell (i, j) in r-z.
@@ -431,6 +509,7 @@ orc_ctx *orc_create(const orc_grid *g, const orc_mat *mats, const orc_pml *pml)
     if (!g || !mats || !pml) return NULL;
     if (g->n_r < 1 || g->n_z < 1 || g->pml_r < 0 || g->pml_b < 0) return NULL;
     if (g->nmat < 1 || g->nmat > ORC_MAX_MAT) return NULL;
+    if (g->closure != 0 && g->closure != 1) return NULL;
     if (!(g->dr > 0) || !(g->dz > 0) || !(g->cfl > 0) || g->cfl > 1.0) return NULL;
     for (int i = 0; g->dr_col && i < g->n_r + g->pml_r; i++)
         if (!(g->dr_col[i] > 0) || !isfinite(g->dr_col[i])) return NULL;
@@ -440,6 +519,7 @@ orc_ctx *orc_create(const orc_grid *g, const orc_mat *mats, const orc_pml *pml)
     x->g = *g;
     x->pml = *pml;
     x->nmat = g->nmat;
+    x->pm = g->closure == 1;
     for (int m = 0; m < g->nmat; m++) {
         x->m[m] = mats[m];
         x->Gm[m] = mats[m].strength ? 3.0 * (1.0 - 2.0 * mats[m].poisson) / (2.0 * (1.0 + mats[m].poisson)) : 0.0;
@@ -517,6 +597,15 @@ orc_ctx *orc_create(const orc_grid *g, const orc_mat *mats, const orc_pml *pml)
         x->f[m] = zalloc(NC);
         x->f_n[m] = zalloc(NC);
         x->fL[m] = zalloc(NC);
+        x->mu[m] = zalloc(NC);
+        x->Im[m] = zalloc(NC);
+        x->mu_n[m] = zalloc(NC);
+        x->Im_n[m] = zalloc(NC);
+        x->pmm[m] = zalloc(NC);
+        x->rhm[m] = zalloc(NC);
+        x->ILm[m] = zalloc(NC);
+        x->Fmr[m] = zalloc(NRF);
+        x->Fmz[m] = zalloc(NAF);
     }
     x->p0 = zalloc(NZ);
     x->dcz = zalloc(NZ);
@@ -585,6 +674,9 @@ void orc_destroy(orc_ctx *x)
         free(x->f[m]);
         free(x->f_n[m]);
         free(x->fL[m]);
+        double *pa[] = {x->mu[m], x->Im[m], x->mu_n[m], x->Im_n[m], x->pmm[m], x->rhm[m], x->ILm[m],
+                        x->Fmr[m], x->Fmz[m]};
+        for (size_t k = 0; k < sizeof(pa) / sizeof(pa[0]); k++) free(pa[k]);
     }
     free(x);
 }
@@ -603,7 +695,7 @@ static double dt_candidate_min(orc_ctx *x)
         for (int i = 0; i < NR; i++) {
             int c = CI(i, j);
             double p, c2, G, Y, rm, phi, sx;
-            mixture(x, c, x->rho, x->I, x->f, &p, &c2, &G, &Y, &rm, &phi, &sx);
+            cell_mixture(x, c, &p, &c2, &G, &Y, &rm, &phi, &sx, NULL, NULL);
             double cl2 = c2 + (4.0 / 3.0) * G / dmax(rm, x->rho_ref * RHO_DEN_FLOOR);
             double cl = sqrt(cl2);
             int nd[4] = {NI(i, j), NI(i + 1, j), NI(i, j + 1), NI(i + 1, j + 1)};
@@ -748,6 +840,12 @@ int orc_init_scene(orc_ctx *x, const orc_scene *s)
             }
             x->rho[c] = rho;
             x->I[c] = 0.0;
+            /* closure 1: each cell holds one material's mass */
+            for (int m = 0; m < x->nmat; m++) {
+                int own = j < s->surface_j ? m == mat_row[j] : m == mp;
+                x->mu[m][c] = own ? rho : 0.0;
+                x->Im[m][c] = 0.0;
+            }
             x->srr[c] = x->szz[c] = x->srz[c] = 0.0;
         }
     }
@@ -819,7 +917,42 @@ int orc_set_fields(orc_ctx *x, const double *rho, const double *I, const double 
     }
     memcpy(x->vr, v, sizeof(double) * NN);
     memcpy(x->vz, v + NN, sizeof(double) * NN);
+    /* closure 1: every material of a cell at the cell's matter density and
+     * specific energy */
+    for (size_t c = 0; c < NC; c++) {
+        double phi = 0.0;
+        for (int m = 0; m < x->nmat; m++) phi += x->f[m][c];
+        double iden = 1.0 / (phi > PHI_EPS ? phi : PHI_EPS);
+        for (int m = 0; m < x->nmat; m++) {
+            x->mu[m][c] = x->rho[c] * (x->f[m][c] * iden);
+            x->Im[m][c] = x->I[c];
+        }
+    }
     start_run(x);
+    return ORC_OK;
+}
+
+int orc_set_materials(orc_ctx *x, const double *mu, const double *Im)
+{
+    if (!x || !mu || !Im || !x->pm) return ORC_E_INVALID;
+    size_t NC = x->NC;
+    for (int m = 0; m < x->nmat; m++) {
+        memcpy(x->mu[m], mu + m * NC, sizeof(double) * NC);
+        memcpy(x->Im[m], Im + m * NC, sizeof(double) * NC);
+    }
+    for (size_t c = 0; c < NC; c++) derive_cell(x, x->mu, x->Im, x->rho, x->I, (int)c);
+    start_run(x);
+    return ORC_OK;
+}
+
+int orc_get_materials(orc_ctx *x, double *mu, double *Im)
+{
+    if (!x || !x->pm) return ORC_E_INVALID;
+    size_t NC = x->NC;
+    for (int m = 0; m < x->nmat; m++) {
+        if (mu) memcpy(mu + m * NC, x->mu[m], sizeof(double) * NC);
+        if (Im) memcpy(Im + m * NC, x->Im[m], sizeof(double) * NC);
+    }
     return ORC_OK;
 }
 
@@ -839,8 +972,12 @@ static void phase_cell_stress(orc_ctx *x)
         for (int i = 0; i < NR; i++) {
             int c = CI(i, j);
             double L = dmin(x->drc[i], x->dzr[j]);
-            double p, c2, G, Y, rm, phi, sx;
-            mixture(x, c, x->rho, x->I, x->f, &p, &c2, &G, &Y, &rm, &phi, &sx);
+            double p, c2, G, Y, rm, phi, sx, pmv[ORC_MAX_MAT], rhv[ORC_MAX_MAT];
+            cell_mixture(x, c, &p, &c2, &G, &Y, &rm, &phi, &sx, pmv, rhv);
+            for (int m = 0; x->pm && m < x->nmat; m++) {
+                x->pmm[m][c] = pmv[m];
+                x->rhm[m][c] = rhv[m];
+            }
             double vr4[4] = {x->vr[NI(i, j)], x->vr[NI(i + 1, j)], x->vr[NI(i, j + 1)], x->vr[NI(i + 1, j + 1)]};
             double vz4[4] = {x->vz[NI(i, j)], x->vz[NI(i + 1, j)], x->vz[NI(i, j + 1)], x->vz[NI(i + 1, j + 1)]};
             kin_t k;
@@ -986,6 +1123,15 @@ static void phase_cell_lagrange(orc_ctx *x)
             double wE = (cg.ae * hdz) * iV;
             double hL = wW * (kd[0] + kd[2]) + wE * (kd[1] + kd[3]);
             x->IL[c] = ((x->I[c] + Wdt / rden) + hL) - dt * (psi2 / rt_);
+            /* closure 1: each material does the deviatoric work and its own
+             * p dV work on the cell's volume change (the sum over materials of
+             * mu_m times the specific work is the cell's work above) */
+            for (int m = 0; x->pm && m < x->nmat; m++) {
+                double Pm = x->pmm[m][c] + x->Q[c];
+                double Wm = dt * sde - Pm * (J - 1.0);
+                double rdm = dmax(x->rhm[m][c], x->rho_ref * RHO_DEN_FLOOR);
+                x->ILm[m][c] = ((x->Im[m][c] + Wm / rdm) + hL) - dt * (psi2 / rt_);
+            }
             for (int m = 0; m < x->nmat; m++) x->fL[m][c] = x->f[m][c] * (Jm / J);
             double db = x->dcz[j], drr = x->dcr[i];
             if (db > 0.0) {
@@ -1010,6 +1156,13 @@ static double rhoL(const orc_ctx *x, int i, int j)
     int NR = x->NR;
     if (i < 0 || i >= NR || j < 0 || j >= x->NZ) return 0.0;
     return x->rho[CI(i, j)] / x->J[CI(i, j)];
+}
+/* closure 1: Lagrangian partial density of material m (mass per Lagrangian volume) */
+static double muL(const orc_ctx *x, int m, int i, int j)
+{
+    int NR = x->NR;
+    if (i < 0 || i >= NR || j < 0 || j >= x->NZ) return 0.0;
+    return x->mu[m][CI(i, j)] / x->J[CI(i, j)];
 }
 static double lam_at(const orc_ctx *x, int i, int j)
 {
@@ -1054,12 +1207,24 @@ static void phase_faces(orc_ctx *x)
     for (int j = 0; j < NZ; j++) {
         for (int i = 0; i <= NR; i++) {
             double dV = x->dVr[RF(i, j)], e = 0.0, F = 0.0;
+            int di = i;
             if (dV > 0.0) {
+                di = i - 1;
                 e = dV * lam_at(x, i - 1, j);
                 F = e * rhoL(x, i - 1, j);
             } else if (dV < 0.0) {
                 e = dV * lam_at(x, i, j);
                 F = e * rhoL(x, i, j);
+            }
+            if (x->pm) {
+                /* closure 1: each material carries its own donor mass; the
+                 * face's mass flux is their sum */
+                F = 0.0;
+                for (int m = 0; m < x->nmat; m++) {
+                    double Fm = dV != 0.0 ? e * muL(x, m, di, j) : 0.0;
+                    x->Fmr[m][RF(i, j)] = Fm;
+                    F += Fm;
+                }
             }
             x->dVre[RF(i, j)] = e;
             x->Fr[RF(i, j)] = F;
@@ -1069,12 +1234,22 @@ static void phase_faces(orc_ctx *x)
     for (int j = 0; j <= NZ; j++) {
         for (int i = 0; i < NR; i++) {
             double dV = x->dVz[AF(i, j)], e = 0.0, F = 0.0;
+            int dj = j;
             if (dV > 0.0) {
+                dj = j - 1;
                 e = dV * lam_at(x, i, j - 1);
                 F = e * rhoL(x, i, j - 1);
             } else if (dV < 0.0) {
                 e = dV * lam_at(x, i, j);
                 F = e * rhoL(x, i, j);
+            }
+            if (x->pm) {
+                F = 0.0;
+                for (int m = 0; m < x->nmat; m++) {
+                    double Fm = dV != 0.0 ? e * muL(x, m, i, dj) : 0.0;
+                    x->Fmz[m][AF(i, j)] = Fm;
+                    F += Fm;
+                }
             }
             x->dVze[AF(i, j)] = e;
             x->Fz[AF(i, j)] = F;
@@ -1103,6 +1278,21 @@ static void phase_cell_remap(orc_ctx *x)
             double iV = 1.0 / V;
             double netin = ((F[0] - F[1]) + F[2]) - F[3];
             double rho1 = x->rho[c] + netin * iV;
+            /* closure 1: each partial density takes its own net inflow; rho is
+             * their sum */
+            double mu1[ORC_MAX_MAT], I1m[ORC_MAX_MAT], Fm[ORC_MAX_MAT][4];
+            if (x->pm) {
+                rho1 = 0.0;
+                for (int m = 0; m < nm; m++) {
+                    Fm[m][0] = x->Fmr[m][RF(i, j)];
+                    Fm[m][1] = x->Fmr[m][RF(i + 1, j)];
+                    Fm[m][2] = x->Fmz[m][AF(i, j)];
+                    Fm[m][3] = x->Fmz[m][AF(i, j + 1)];
+                    double nin = ((Fm[m][0] - Fm[m][1]) + Fm[m][2]) - Fm[m][3];
+                    mu1[m] = x->mu[m][c] + nin * iV;
+                    rho1 += mu1[m];
+                }
+            }
             double M1 = rho1 * V;
             double min_ = 0.0, nI = 0.0, nsrr = 0.0, nszz = 0.0, nsrz = 0.0, vcut = 0.0;
             double nf[ORC_MAX_MAT] = {0.0, 0.0};
@@ -1145,6 +1335,30 @@ static void phase_cell_remap(orc_ctx *x)
             double ifs = 1.0 / dmax(fs, 1.0);
             for (int m = 0; m < nm; m++) x->f_n[m][c] = f1[m] * ifs;
 
+            /* closure 1: each material's specific energy is remapped with its
+             * own mass fluxes (donor values, as I above); the energy fluxes
+             * are the sums over materials */
+            if (x->pm) {
+                for (int q = 0; q < 4; q++) ed[q] = 0.0;
+                for (int m = 0; m < nm; m++) {
+                    double ILc = x->ILm[m][c], minm = 0.0, nIm = 0.0;
+                    for (int q = 0; q < 4; q++) {
+                        int dc_ok = di[q] >= 0 && di[q] < NR && dj[q] >= 0 && dj[q] < NZ;
+                        if (in[q]) {
+                            double Id = dc_ok ? x->ILm[m][CI(di[q], dj[q])] : 0.0;
+                            double aF = fabs(Fm[m][q]);
+                            minm += aF;
+                            nIm += aF * (Id - ILc);
+                            ed[q] += Fm[m][q] * Id;
+                        } else {
+                            ed[q] += Fm[m][q] * ILc;
+                        }
+                    }
+                    double denm = dmax(dmax(mu1[m] * V, minm), M_REMAP_FLOOR * x->rho_ref * V);
+                    I1m[m] = ILc + nIm * (1.0 / denm);
+                }
+            }
+
             /* PML: damping of the fluctuation about the initial state plus the
              * unstretched-direction auxiliary terms; r-faces feed the bottom
              * layer's phi, z-faces feed the right layer's phi */
@@ -1157,6 +1371,18 @@ static void phase_cell_remap(orc_ctx *x)
                 double rho2 = dmax(rho1 - dt * (dsum * (rho1 - x->rref[c]) + (x->phi1b[c] + x->phi1r[c])), 0.0);
                 double rt_ = dmax(rho1, x->rho_ref * PML_RHO_FLOOR);
                 double I2 = I1 - dt * (dsum * I1 + (x->phi3b[c] + x->phi3r[c]) / rt_);
+                if (x->pm) {
+                    /* every material loses the same fraction of its mass and
+                     * the same specific energy */
+                    double kap = rho1 > 0.0 ? rho2 / rho1 : 0.0;
+                    double r2 = 0.0;
+                    for (int m = 0; m < nm; m++) {
+                        mu1[m] = mu1[m] * kap;
+                        r2 += mu1[m];
+                        I1m[m] = I1m[m] - dt * (dsum * I1m[m] + (x->phi3b[c] + x->phi3r[c]) / rt_);
+                    }
+                    rho2 = r2;
+                }
                 x->msink[c] = x->msink[c] + V * (rho1 - rho2);
                 if (db > 0.0) {
                     x->phi1b[c] = x->phi1b[c] + db * ((F[1] - F[0]) * iV);
@@ -1171,6 +1397,10 @@ static void phase_cell_remap(orc_ctx *x)
             }
             x->rho_n[c] = rho1;
             x->I_n[c] = I1;
+            for (int m = 0; x->pm && m < nm; m++) {
+                x->mu_n[m][c] = mu1[m];
+                x->Im_n[m][c] = I1m[m];
+            }
             if (j == NZ - 1) {
                 x->mout_col[i] += F[3];
                 x->eout_col[i] += ed[3];
@@ -1306,6 +1536,10 @@ static void phase_cell_heat(orc_ctx *x)
             int c = CI(i, j);
             double h = (x->heat[NI(i, j)] + x->heat[NI(i + 1, j)]) + (x->heat[NI(i, j + 1)] + x->heat[NI(i + 1, j + 1)]);
             x->I_n[c] = x->I_n[c] + h;
+            if (x->pm) {
+                for (int m = 0; m < x->nmat; m++) x->Im_n[m][c] = x->Im_n[m][c] + h;
+                derive_cell(x, x->mu_n, x->Im_n, x->rho_n, x->I_n, c);
+            }
         }
     }
 }
@@ -1325,6 +1559,7 @@ static int check_state(orc_ctx *x)
     for (size_t c = 0; c < NC; c++) {
         double s = x->rho[c] + x->I[c] + x->srr[c] + x->szz[c] + x->srz[c];
         for (int m = 0; m < x->nmat; m++) s += x->f[m][c];
+        for (int m = 0; x->pm && m < x->nmat; m++) s += x->mu[m][c] + x->Im[m][c];
         if (!isfinite(s)) bad = 1;
         if (x->rho[c] < tol) neg = 1;
     }
@@ -1347,6 +1582,10 @@ static int one_cycle(orc_ctx *x)
     swap(&x->rho, &x->rho_n);
     swap(&x->I, &x->I_n);
     for (int m = 0; m < x->nmat; m++) swap(&x->f[m], &x->f_n[m]);
+    for (int m = 0; x->pm && m < x->nmat; m++) {
+        swap(&x->mu[m], &x->mu_n[m]);
+        swap(&x->Im[m], &x->Im_n[m]);
+    }
     swap(&x->srr, &x->srr_n);
     swap(&x->szz, &x->szz_n);
     swap(&x->srz, &x->srz_n);
@@ -1401,7 +1640,7 @@ int orc_get_fields(orc_ctx *x, double *rho, double *I, double *f, double *s, dou
     if (p || c2) {
         for (size_t c = 0; c < NC; c++) {
             double pp, cc, G, Y, rm, phi, sx;
-            mixture(x, (int)c, x->rho, x->I, x->f, &pp, &cc, &G, &Y, &rm, &phi, &sx);
+            cell_mixture(x, (int)c, &pp, &cc, &G, &Y, &rm, &phi, &sx, NULL, NULL);
             if (p) p[c] = pp;
             if (c2) c2[c] = cc;
         }

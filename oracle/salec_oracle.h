@@ -41,6 +41,9 @@ typedef struct {
     int32_t pml_b;      /* PML cells below the physical region              */
     int32_t nmat;       /* 1 to 3 materials                                 */
     int32_t top_closed; /* 0: open (outflow) top, 1: rigid top wall         */
+    int32_t closure;    /* mixed cells: 0 shared material density and      */
+                        /* specific energy, 1 per-material density and      */
+                        /* specific energy (partial densities advected)     */
     double dr, dz;      /* cell size, m                                     */
     double cfl;         /* Courant constant C0                               */
     double dt_grow;     /* max growth factor of dt per cycle                */
@@ -94,6 +97,13 @@ int orc_set_fields(orc_ctx *x, const double *rho, const double *I,
  * rho g = 0). Zero unless a scene with gravity or this call sets it; kept
  * across orc_set_fields. */
 int orc_set_p0(orc_ctx *x, const double *p0);
+/* per-material state (closure 1): mu = partial densities (mass of material m
+ * per cell volume, nmat*NC, material-major), Im = specific internal energies
+ * (nmat*NC). Setting them also sets rho = sum of mu and I = the mass-weighted
+ * energy; orc_set_fields in this mode gives every material of a cell the
+ * cell's matter density and its specific energy. */
+int orc_set_materials(orc_ctx *x, const double *mu, const double *Im);
+int orc_get_materials(orc_ctx *x, double *mu, double *Im);
 int orc_get_p0(orc_ctx *x, double *p0);
 int orc_step(orc_ctx *x, int32_t n);
 /* any pointer may be NULL; p and c2 are evaluated from the current state */

@@ -51,6 +51,9 @@ class Grid:
     pml_b: int = 0
     nmat: int = 1
     top_closed: int = 0
+    # mixed cells: 0 = one material density and specific energy shared by the
+    # materials of a cell, 1 = per-material densities and specific energies
+    closure: int = 0
     dr: float = 1.0
     dz: float = 1.0
     cfl: float = 0.5
