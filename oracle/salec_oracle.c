@@ -293,6 +293,11 @@ static void mixture_pm(const orc_ctx *x, int c, const double *rho, double *const
         double rmm = fm > F_PM_EPS && mm > 0.0 ? mm / fm : rm;
         double pm, c2m;
         wm[m] = fm * iden;
+        sf[m] = 0.0;
+        if (pm_o) pm_o[m] = 0.0;
+        if (rhm_o) rhm_o[m] = rmm;
+        /* a material absent from the cell has no pressure and adds nothing */
+        if (fm == 0.0) continue;
         orc_tillotson(&x->m[m], rmm, Im[m][c], &pm, &c2m);
         pm = dmax(pm, x->m[m].p_min);
         c2m = dmax(c2m, x->m[m].c_floor_frac * x->m[m].A / x->m[m].rho0);
@@ -301,10 +306,10 @@ static void mixture_pm(const orc_ctx *x, int c, const double *rho, double *const
         sf[m] = orc_softening(&x->m[m], Im[m][c]);
         G += wm[m] * (sf[m] * (x->Gm[m] * (rmm * c2m)));
         if (pm_o) pm_o[m] = pm;
-        if (rhm_o) rhm_o[m] = rmm;
     }
     double Y = 0.0, pmin = 0.0, ps = 0.0;
     for (int m = 0; m < x->nmat; m++) {
+        if (f[m][c] == 0.0) continue;
         Y += wm[m] * (sf[m] * orc_yield(&x->m[m], p));
         pmin += wm[m] * x->m[m].p_min;
         ps += wm[m] * (PCAV_FRAC * x->m[m].A);
