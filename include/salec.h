@@ -62,6 +62,25 @@ extern "C" {
 
 #define SALEC_MAX_MAT 3
 
+/* Closure of mixed cells (a reading of Sec. 2's volume-fraction cells; the
+ * paper's layered target mixes materials with different equations of state):
+ *  SALEC_CLOSURE_SHARED: the materials of a cell share one material density
+ *    rho / phi and one specific energy I; the cell pressure is the
+ *    volume-fraction average of the materials' pressures at that state.
+ *  SALEC_CLOSURE_PER_MATERIAL: each material keeps its partial density mu_m
+ *    (its mass per cell volume) and its specific energy I_m. Its equation of
+ *    state sees rho_m = mu_m / f_m (below a volume fraction of 1e-6, or
+ *    without mass, the cell's matter density) and I_m; the cell pressure is
+ *    the same volume-fraction average. In the Lagrangian step every material
+ *    does the deviatoric work and its own p dV work on the cell's volume
+ *    change; in the remap (eqs. (3)-(5)) each material carries its own donor
+ *    mass and energy through the face's volume flux, and the face mass flux
+ *    is their sum. rho and I hold sum(mu_m) and the mass-weighted energy. A
+ *    material absent from a cell (f_m = 0) has no pressure there. Every
+ *    member of a context uses the same closure. */
+#define SALEC_CLOSURE_SHARED 0
+#define SALEC_CLOSURE_PER_MATERIAL 1
+
 typedef struct salec_grid {
     int32_t n_r, n_z;    /* physical cells in r and z (>= 1)                      */
     int32_t pml_r;       /* PML cells right of the physical region (>= 0)        */
@@ -69,7 +88,8 @@ typedef struct salec_grid {
     int32_t nmat;        /* 1 to 3 materials                                     */
     int32_t top_closed;  /* 0: open top (void ghost), 1: rigid top wall          */
     int32_t precision;   /* SALEC_FP64 or SALEC_MIXED                            */
-    int32_t reserved;    /* must be 0                                            */
+    int32_t closure;     /* mixed cells: SALEC_CLOSURE_SHARED or                 */
+                         /* SALEC_CLOSURE_PER_MATERIAL (see below)               */
     double dr, dz;       /* cell size, m (> 0)                                   */
     double cfl;          /* Courant constant C0 in (0, 1] (Sec. 7)               */
     double dt_grow;      /* largest dt growth factor per cycle (>= 1)            */
@@ -229,6 +249,20 @@ int salec_last_step_ms(salec_ctx *ctx, double *ms);
  * context, instance or pointer. */
 int salec_set_p0(salec_ctx *ctx, int32_t instance, const double *p0);
 int salec_get_p0(salec_ctx *ctx, int32_t instance, double *p0);
+
+/* Per-material state of member `instance` under SALEC_CLOSURE_PER_MATERIAL
+ * (the closure above): mu = partial densities (kg/m^3 of cell volume) and
+ * Im = specific internal energies (J/kg), each nmat*NZ*NR host FP64 values,
+ * material-major, row-major with r fastest. salec_set_materials replaces them
+ * in the current state (values must be finite), sets rho = sum of mu and
+ * I = the mass-weighted energy, keeps f, s and v, and starts a new run at
+ * t = 0 like salec_set_fields (which, under this closure, gives every
+ * material of a cell the cell's matter density rho f_m / phi and the cell's
+ * I). salec_get_materials reads the current state; either pointer may be
+ * NULL. Both return SALEC_E_INVALID for a bad context, instance or pointer,
+ * or when the member uses SALEC_CLOSURE_SHARED. */
+int salec_set_materials(salec_ctx *ctx, int32_t instance, const double *mu, const double *Im);
+int salec_get_materials(salec_ctx *ctx, int32_t instance, double *mu, double *Im);
 
 /* Advances every member by n cycles (1 <= n <= 100000) like salec_step(),
  * but launches each cycle's two kernels directly (no graph) with a HIP event

@@ -31,16 +31,18 @@ void variant_shape(int v, int* tw, int* th, int* nt) {
   *nt = kShapes[v][2];
 }
 
-static CycleFn cycle_kernel(int v, int prec, bool geo, int nm) {
+static CycleFn cycle_kernel(int v, int prec, bool geo, int nm, bool pm) {
   if (v < 0 || v >= n_variants()) return nullptr;
-  return prec == 0 ? cycle_kernel_f64(v, geo, nm) : cycle_kernel_f32(v, geo, nm);
+  return prec == 0 ? cycle_kernel_f64(v, geo, nm, pm) : cycle_kernel_f32(v, geo, nm, pm);
 }
 
-bool variant_available(int v, int prec, bool geo, int nm) { return cycle_kernel(v, prec, geo, nm) != nullptr; }
+bool variant_available(int v, int prec, bool geo, int nm, bool pm) {
+  return cycle_kernel(v, prec, geo, nm, pm) != nullptr;
+}
 
-hipError_t launch_cycle(int v, int prec, bool geo, int nm, const Inst* insts, const TileRef* sched, int nsched,
-                        int grid, hipStream_t st) {
-  CycleFn f = cycle_kernel(v, prec, geo, nm);
+hipError_t launch_cycle(int v, int prec, bool geo, int nm, bool pm, const Inst* insts, const TileRef* sched,
+                        int nsched, int grid, hipStream_t st) {
+  CycleFn f = cycle_kernel(v, prec, geo, nm, pm);
   if (!f) return hipErrorInvalidValue;
   hipLaunchKernelGGL(f, dim3(grid), dim3(kShapes[v][2]), 0, st, insts, sched, nsched);
   return hipGetLastError();
@@ -99,8 +101,8 @@ hipError_t launch_finalize(const Inst* insts, int n_inst, hipStream_t st) {
   return hipGetLastError();
 }
 
-int resident_groups(int v, int prec, bool geo, int nm) {
-  CycleFn f = cycle_kernel(v, prec, geo, nm);
+int resident_groups(int v, int prec, bool geo, int nm, bool pm) {
+  CycleFn f = cycle_kernel(v, prec, geo, nm, pm);
   int per_cu = 0, cus = 0, dev = 0;
   if (!f || hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)f, kShapes[v][2], 0) != hipSuccess) return 0;

@@ -49,11 +49,14 @@ struct GeoLds {
   static constexpr int GC = TW + 8, GR = TH + 8, N = 6 * GC + GR;
 };
 
-template <int TW, int TH, class T, int NM>
+template <int TW, int TH, class T, int NM, bool PM>
 struct Smem {
   using R = Regions<TW, TH>;
+  // FP64 fields of C's results: rhoL, IL, f[NM]; per-material closure:
+  // muL[NM], IL[NM], f[NM]
+  static constexpr int kNCd = PM ? 3 * NM : 2 + NM;
   static constexpr int kBigA = 4 * R::NA * (int)sizeof(T);                 // sigma[4][NA]
-  static constexpr int kBigC = R::NC * ((2 + NM) * 8 + 4 * (int)sizeof(T));  // rhoL, IL, f[NM] | lambda, sL x3
+  static constexpr int kBigC = R::NC * (kNCd * 8 + 4 * (int)sizeof(T));    // C's FP64 fields | lambda, sL x3
   static constexpr int kBigF = R::NF * (8 + (int)sizeof(T));          // heat | speed
   static constexpr int kBig = kBigA > kBigC ? (kBigA > kBigF ? kBigA : kBigF) : (kBigC > kBigF ? kBigC : kBigF);
   static constexpr int kBigD = (kBig + 7) / 8;
@@ -109,7 +112,7 @@ __device__ __forceinline__ void reg_put(T (&a)[N], int u, T v) {
   for (int q = 0; q < N; q++) a[q] = (u == q) ? v : a[q];
 }
 
-template <int TW, int TH, int NT, int WPE, class T, bool GEO, int NM>
+template <int TW, int TH, int NT, int WPE, class T, bool GEO, int NM, bool PM>
 __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_rho, double* s_bigd, T* s_vL,
                                            double* s_Fr, double* s_Fz, double* s_rho1, double* s_min,
                                            double* s_geo) {
@@ -198,9 +201,13 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     i = i0 - 1 + (k - q * R::EW);
     j = q < TH ? j0 + q : (q == TH ? j0 - 1 : j0 + TH);
   };
+  // C's FP64 fields during C..E2: rhoL, IL, f[NM], or with the per-material
+  // closure muL[NM] (mu_m / J), IL[NM], f[NM]
+  constexpr int kNCd = Smem<TW, TH, T, NM, PM>::kNCd;
+  constexpr int kFo = PM ? 2 * NM : 2;  // first volume-fraction field
   T* sig = (T*)s_bigd;                // [4][NA] during A..B
-  double* cd = s_bigd;                     // [2 + NM][NC] rhoL, IL, f[NM] during C..E2
-  T* ct = (T*)(s_bigd + (2 + NM) * R::NC);  // [4][NC] lambda, sL x3 during C..E2
+  double* cd = s_bigd;                // [kNCd][NC] during C..E2
+  T* ct = (T*)(s_bigd + kNCd * R::NC);  // [4][NC] lambda, sL x3 during C..E2
   double* heat = s_bigd;              // [NF] during F..G
   T* speed = (T*)(s_bigd + R::NF);    // [NF] during F..G
   T* s_kd = (T*)s_Fr;                 // [NB] during B..C: 1/2 |v^L - v^n|^2 per node
@@ -215,7 +222,9 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   // (FP64 tiles capped at 128 registers reload them instead)
   constexpr bool kKeepA = !(WPE >= 4 && sizeof(T) == 8);
   double rF[NM][UA];
-  T rS0[UA], rS1[UA], rS2[UA], rSx[UA];
+  T rS0[UA], rS1[UA], rS2[UA], rSx[UA], rQ[PM ? UA : 1];
+#pragma unroll
+  for (int u = 0; u < (PM ? UA : 1); u++) rQ[u] = T(0);
 #pragma unroll
   for (int u = 0; u < UA; u++) {
     rP[u] = rS0[u] = rS1[u] = rS2[u] = rSx[u] = T(0);
@@ -282,6 +291,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       s2 = phi * (stt - Pf);
       s3 = phi * srz;
       reg_put(rP, u, P);
+      if constexpr (PM) reg_put(rQ, u, Q);  // each material's p dV work uses p_m + Q
 #pragma unroll
       for (int m = 0; m < NM; m++) reg_put(rF[m], u, fd[m]);
       reg_put(rS0, u, srr);
@@ -399,9 +409,9 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     a_cell(k, i, j);
     if (i < i0 - 2 || i >= i0 + TW + 2) continue;
     // outside the grid: a void donor (rho^L = 0, lambda = 1, zero state)
-    double oRhoL = 0.0, oIL = 0.0, of[NM];
+    double oRhoL = 0.0, oIL = 0.0, of[NM], oMuL[NM], oILm[NM];
 #pragma unroll
-    for (int m = 0; m < NM; m++) of[m] = 0.0;
+    for (int m = 0; m < NM; m++) of[m] = oMuL[m] = oILm[m] = 0.0;
     T oLam = T(1), os0 = T(0), os1 = T(0), os2 = T(0);
     if (in_cells(g, i, j)) {
       long long c = cidx(g, i, j);
@@ -483,7 +493,33 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         double b = kb >= 0 ? po.b_psi2[kb] : 0.0, r = kr >= 0 ? po.r_psi2[kr] : 0.0;
         psi2 = b + r;
       }
-      double IL = ((S.I[c] + (double)N::div(Wdt, rden)) + (double)hL) - dt * (psi2 / rt);
+      double IL = 0.0;
+      if constexpr (!PM) {
+        IL = ((S.I[c] + (double)N::div(Wdt, rden)) + (double)hL) - dt * (psi2 / rt);
+      } else {
+        // each material: deviatoric work and its own p dV work on the cell's
+        // volume change, per unit of its own mass (density mu_m / f_m; below
+        // kFPmEps or without mass the cell's matter density)
+        double phid = 0.0;
+#pragma unroll
+        for (int m = 0; m < NM; m++)
+          if (m < g.nmat) phid += fn[m];
+        const double rmd = rho * (1.0 / (phid > kPhiEps ? phid : kPhiEps));
+        const T Q = reg_get(rQ, u);
+        const T jm1 = Vol<T>::jm1(J, dD);
+        const double iJ = (double)J;
+#pragma unroll
+        for (int m = 0; m < NM; m++) {
+          if (m >= g.nmat) continue;
+          const double mud = S.mu[m][c];
+          const double rmm = fn[m] > kFPmEps && mud > 0.0 ? mud / fn[m] : rmd;
+          const T Pm = ((const T*)S.pmat[m])[c] + Q;
+          const T Wm = dtT * sde - Pm * jm1;
+          const T rdm = tmax((T)rmm, GT::rho_ref(g) * T(kRhoDenFloor));
+          oILm[m] = ((S.Im[m][c] + (double)N::div(Wm, rdm)) + (double)hL) - dt * (psi2 / rt);
+          oMuL[m] = mud / iJ;
+        }
+      }
       double fr = (double)N::div(Jm, J);
       double fLv[NM];
 #pragma unroll
@@ -508,10 +544,18 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       oLam = J;  // the limiter pass below turns J into lambda
     }
     int kc = kC(i, j);
-    cd[0 * R::NC + kc] = oRhoL;
-    cd[1 * R::NC + kc] = oIL;
+    if constexpr (PM) {
 #pragma unroll
-    for (int m = 0; m < NM; m++) cd[(2 + m) * R::NC + kc] = of[m];
+      for (int m = 0; m < NM; m++) {
+        cd[m * R::NC + kc] = oMuL[m];
+        cd[(NM + m) * R::NC + kc] = oILm[m];
+      }
+    } else {
+      cd[0 * R::NC + kc] = oRhoL;
+      cd[1 * R::NC + kc] = oIL;
+    }
+#pragma unroll
+    for (int m = 0; m < NM; m++) cd[(kFo + m) * R::NC + kc] = of[m];
     ct[0 * R::NC + kc] = oLam;
     ct[1 * R::NC + kc] = os0;
     ct[2 * R::NC + kc] = os1;
@@ -538,14 +582,28 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
 
   // ------------------------------------------------------------------ E1
   // mass flux of every face the remap and the momentum remap touch; 0 where
-  // there is no face
+  // there is no face. e = dV lambda of the donor d; the flux is e rho^L(d),
+  // or with the per-material closure the sum of every material's e mu_m^L(d)
+  // (E2 recomputes the same terms per material).
+  auto face_flux = [&](T dV, int d) -> double {
+    if (!(dV > T(0) || dV < T(0))) return 0.0;
+    const double e = (double)dV * (double)ct[0 * R::NC + d];
+    if constexpr (PM) {
+      double F = 0.0;
+#pragma unroll
+      for (int m = 0; m < NM; m++)
+        if (m < g.nmat) F += e * cd[m * R::NC + d];
+      return F;
+    } else {
+      return e * cd[0 * R::NC + d];
+    }
+  };
   for (int k = tid; k < R::NRF; k += NT) {
     int i = i0 - 1 + k % R::RW, j = j0 - 1 + k / R::RW;
     double F = 0.0;
     if (i >= 0 && i <= g.NR && j >= 0 && j < g.NZ) {
       T dV = dv_r(i, j);
-      int d = dV > T(0) ? kC(i - 1, j) : kC(i, j);
-      if (dV > T(0) || dV < T(0)) F = ((double)dV * (double)ct[0 * R::NC + d]) * cd[0 * R::NC + d];
+      F = face_flux(dV, dV > T(0) ? kC(i - 1, j) : kC(i, j));
     }
     s_Fr[k] = F;
   }
@@ -554,8 +612,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     double F = 0.0;
     if (i >= 0 && i < g.NR && j >= 0 && j <= g.NZ) {
       T dV = dv_z(i, j);
-      int d = dV > T(0) ? kC(i, j - 1) : kC(i, j);
-      if (dV > T(0) || dV < T(0)) F = ((double)dV * (double)ct[0 * R::NC + d]) * cd[0 * R::NC + d];
+      F = face_flux(dV, dV > T(0) ? kC(i, j - 1) : kC(i, j));
     }
     s_Fz[k] = F;
   }
@@ -567,7 +624,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   // workgroups have no registers to spare and G reads them back instead)
   unsigned flags = 0;
   constexpr int UE = (R::NE + NT - 1) / NT;
-  constexpr bool kCarry = WPE < 4;
+  // (the per-material closure writes its state in E2 and G reads it back)
+  constexpr bool kCarry = WPE < 4 && !PM;
   double eRho[UE], eI[UE], eF[NM][UE];
 #pragma unroll
   for (int u = 0; u < UE; u++) {
@@ -599,9 +657,32 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
 #pragma unroll
       for (int m = 0; m < NM; m++) {
         nf[m] = 0.0;
-        fL[m] = cd[(2 + m) * R::NC + kc];
+        fL[m] = cd[(kFo + m) * R::NC + kc];
       }
-      double IL = cd[1 * R::NC + kc];
+      // per-material closure: every material's face mass fluxes (the terms E1
+      // summed), its new partial density, and rho as their sum
+      double Fm[PM ? NM : 1][4], mu1[PM ? NM : 1];
+      if constexpr (PM) {
+        rho1 = 0.0;
+#pragma unroll
+        for (int m = 0; m < NM; m++) {
+          mu1[m] = 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; q++) Fm[m][q] = 0.0;
+          if (m >= g.nmat) continue;
+#pragma unroll
+          for (int q = 0; q < 4; q++) {
+            const int d = inq[q] ? dk[q] : kc;
+            if (dV[q] > T(0) || dV[q] < T(0))
+              Fm[m][q] = ((double)dV[q] * (double)ct[0 * R::NC + d]) * cd[m * R::NC + d];
+          }
+          const double nin = ((Fm[m][0] - Fm[m][1]) + Fm[m][2]) - Fm[m][3];
+          mu1[m] = S.mu[m][cidx(g, i, j)] + nin * iV;
+          rho1 += mu1[m];
+        }
+        M1 = rho1 * V;
+      }
+      double IL = PM ? 0.0 : cd[1 * R::NC + kc];
       double sL0 = (double)ct[1 * R::NC + kc], sL1 = (double)ct[2 * R::NC + kc], sL2 = (double)ct[3 * R::NC + kc];
       double ed[4];
 #pragma unroll
@@ -612,7 +693,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
           double adV = fabs((double)dV[q] * (double)ct[0 * R::NC + d]);
           double aF = fabs(F[q]);
           vcut += fabs((double)dV[q]) - adV;
-          double Id = cd[1 * R::NC + d];
+          double Id = PM ? 0.0 : cd[1 * R::NC + d];
           min_ += aF;
           nI += aF * (Id - IL);
           nsrr += aF * ((double)ct[1 * R::NC + d] - sL0);
@@ -620,7 +701,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
           nsrz += aF * ((double)ct[3 * R::NC + d] - sL2);
 #pragma unroll
           for (int m = 0; m < NM; m++)
-            if (m == 0 || m < g.nmat) nf[m] += adV * (cd[(2 + m) * R::NC + d] - fL[m]);
+            if (m == 0 || m < g.nmat) nf[m] += adV * (cd[(kFo + m) * R::NC + d] - fL[m]);
           ed[q] = F[q] * Id;
         } else {
           ed[q] = F[q] * IL;
@@ -631,6 +712,35 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       double den = dmax(dmax(M1, min_), kMRemapFloor * g.rho_ref * V);
       double iden = 1.0 / den;
       double I1 = IL + nI * iden;
+      // per-material closure: every material's specific energy remapped with
+      // its own mass fluxes (donor values); the energy fluxes are the sums
+      // over materials
+      double I1m[PM ? NM : 1];
+      if constexpr (PM) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) ed[q] = 0.0;
+#pragma unroll
+        for (int m = 0; m < NM; m++) {
+          I1m[m] = 0.0;
+          if (m >= g.nmat) continue;
+          const double ILc = cd[(NM + m) * R::NC + kc];
+          double minm = 0.0, nIm = 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; q++) {
+            if (inq[q]) {
+              const double Id = cd[(NM + m) * R::NC + dk[q]];
+              const double aF = fabs(Fm[m][q]);
+              minm += aF;
+              nIm += aF * (Id - ILc);
+              ed[q] += Fm[m][q] * Id;
+            } else {
+              ed[q] += Fm[m][q] * ILc;
+            }
+          }
+          const double denm = dmax(dmax(mu1[m] * V, minm), kMRemapFloor * g.rho_ref * V);
+          I1m[m] = ILc + nIm * (1.0 / denm);
+        }
+      }
       double ex = (1.0 - lam) * O - vcut;
       double f1v[NM];
 #pragma unroll
@@ -651,6 +761,20 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
           double rho2 = dmax(rho1 - dt * (dsum * (rho1 - pm.rref[ku]) + (p1b + p1r)), 0.0);
           double rt = dmax(rho1, g.rho_ref * kPmlRhoFloor);
           double I2 = I1 - dt * (dsum * I1 + (p3b + p3r) / rt);
+          if constexpr (PM) {
+            // every material loses the same fraction of its mass and the same
+            // specific energy
+            const double kap = rho1 > 0.0 ? rho2 / rho1 : 0.0;
+            double r2 = 0.0;
+#pragma unroll
+            for (int m = 0; m < NM; m++) {
+              if (m >= g.nmat) continue;
+              mu1[m] = mu1[m] * kap;
+              r2 += mu1[m];
+              I1m[m] = I1m[m] - dt * (dsum * I1m[m] + (p3b + p3r) / rt);
+            }
+            rho2 = r2;
+          }
           if (own) {
             pm.msink[ku] = pm.msink[ku] + V * (rho1 - rho2);
             if (db > 0.0) {
@@ -686,15 +810,26 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
           in.mout[i] += F[3];
           in.eout[i] += ed[3];
         }
+        double chk = rho1;
         if constexpr (kCarry) {
           reg_put(eRho, u, rho1);
           reg_put(eI, u, I1);  // before the remap heat, which G adds
 #pragma unroll
           for (int m = 0; m < NM; m++) reg_put(eF[m], u, fv[m]);
-        } else {
+          chk += I1;
+        } else if constexpr (!PM) {
           D.I[c] = I1;  // before the remap heat, which G adds
+          chk += I1;
+        } else {
+          // G adds the remap heat and forms I
+#pragma unroll
+          for (int m = 0; m < NM; m++) {
+            if (m >= g.nmat) continue;
+            D.mu[m][c] = mu1[m];
+            D.Im[m][c] = I1m[m];
+            chk += mu1[m] + I1m[m];
+          }
         }
-        double chk = rho1 + I1;
         if (g.any_strength) chk += (double)s0n + (double)s1n + (double)s2n;
 #pragma unroll
         for (int m = 0; m < NM; m++)
@@ -834,7 +969,28 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     long long c = cidx(g, i, j);
     const int nf[4] = {kF(i, j), kF(i + 1, j), kF(i, j + 1), kF(i + 1, j + 1)};
     double h = (heat[nf[0]] + heat[nf[1]]) + (heat[nf[2]] + heat[nf[3]]);
-    double I1 = (kCarry ? eI[u] : D.I[c]) + h;
+    double I1;
+    // per-material closure: each material takes the heat; I is the
+    // mass-weighted energy of the partial densities, rho their sum
+    double mu[kMaxMat], Imv[kMaxMat];
+    if constexpr (PM) {
+      double r = 0.0, e = 0.0;
+#pragma unroll
+      for (int m = 0; m < kMaxMat; m++) {
+        mu[m] = Imv[m] = 0.0;
+        if (m >= NM || m >= g.nmat) continue;
+        mu[m] = D.mu[m][c];
+        Imv[m] = D.Im[m][c] + h;
+        D.Im[m][c] = Imv[m];
+        r += mu[m];
+      }
+#pragma unroll
+      for (int m = 0; m < kMaxMat; m++)
+        if (m < NM && m < g.nmat) e += mu[m] * Imv[m];
+      I1 = r > 0.0 ? e / r : 0.0;
+    } else {
+      I1 = (kCarry ? eI[u] : D.I[c]) + h;
+    }
     D.I[c] = I1;
     if (!((I1 - I1) == 0.0)) flags |= kFlagNonFinite;
     T u4 = T(0);
@@ -848,7 +1004,16 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
 #pragma unroll
     for (int m = 0; m < kMaxMat; m++)
       f[m] = m >= NM ? 0.0 : (kCarry ? reg_get(eF[m], u) : (m < g.nmat ? D.f[m][c] : 0.0));
-    Mix<T> mx = mixture<T>(g, kCarry ? eRho[u] : D.rho[c], I1, f);
+    Mix<T> mx;
+    if constexpr (PM) {
+      T pmv[kMaxMat];
+      mx = mixture_pm<T>(g, D.rho[c], f, mu, Imv, pmv);
+#pragma unroll
+      for (int m = 0; m < NM; m++)
+        if (m < g.nmat) ((T*)D.pmat[m])[c] = pmv[m];
+    } else {
+      mx = mixture<T>(g, kCarry ? eRho[u] : D.rho[c], I1, f);
+    }
     store_eos(D, c, mx);
     cand = dmin(cand, cell_dt(g, mx, u4, dmin(colD(i).dr, dzD(j))));
   }
@@ -857,11 +1022,11 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   if (tid == 0) in.dtpart[tile] = m;
 }
 
-template <int TW, int TH, int NT, int WPE, class T, bool GEO, int NM>
+template <int TW, int TH, int NT, int WPE, class T, bool GEO, int NM, bool PM>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_cycle(const Inst* __restrict__ insts, const TileRef* __restrict__ sched,
                                               int nsched) {
   using R = Regions<TW, TH>;
-  using SM = Smem<TW, TH, T, NM>;
+  using SM = Smem<TW, TH, T, NM, PM>;
   __shared__ double s_rho[R::NA];     // rho^n over A (0 outside the grid)
   __shared__ double s_bigd[SM::kBigD];  // A..B stress; C..E2 Lagrangian state; F..G heat, speed
   __shared__ T s_vL[2 * R::NB];       // v^L over B
@@ -880,7 +1045,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     const TileRef tr{csched[e].inst, csched[e].tile};
     if (tr.inst < 0) continue;
     const Inst* in = (const Inst*)(cinst + tr.inst);
-    tile_cycle<TW, TH, NT, WPE, T, GEO, NM>(*in, tr.tile, s_rho, s_bigd, s_vL, s_F, s_F + R::NRF, s_rho1, s_min,
+    tile_cycle<TW, TH, NT, WPE, T, GEO, NM, PM>(*in, tr.tile, s_rho, s_bigd, s_vL, s_F, s_F + R::NRF, s_rho1, s_min,
                                             s_geo);
     __syncthreads();  // LDS is reused by the next entry
   }
@@ -901,7 +1066,19 @@ __global__ void k_prime(Inst in) {
     long long c = cidx(g, i, j);
     double f[kMaxMat];
     for (int m = 0; m < kMaxMat; m++) f[m] = m < g.nmat ? S.f[m][c] : 0.0;
-    Mix<T> mx = mixture<T>(g, S.rho[c], S.I[c], f);
+    Mix<T> mx;
+    if (g.closure) {
+      double mu[kMaxMat], Im[kMaxMat];
+      T pmv[kMaxMat];
+      for (int m = 0; m < kMaxMat; m++) {
+        mu[m] = m < g.nmat ? S.mu[m][c] : 0.0;
+        Im[m] = m < g.nmat ? S.Im[m][c] : 0.0;
+      }
+      mx = mixture_pm<T>(g, S.rho[c], f, mu, Im, pmv);
+      for (int m = 0; m < g.nmat; m++) ((T*)S.pmat[m])[c] = pmv[m];
+    } else {
+      mx = mixture<T>(g, S.rho[c], S.I[c], f);
+    }
     store_eos(S, c, mx);
     const long long nd[4] = {nidx(g, i, j), nidx(g, i + 1, j), nidx(g, i, j + 1), nidx(g, i + 1, j + 1)};
     T u4 = T(0);
@@ -926,65 +1103,103 @@ __global__ void k_prime(Inst in) {
 #define SALEC_CYCLE_TABLE(T, suffix)                                                         \
   static CycleFn cycle_uni2_##suffix(int v) {                                                \
     switch (v) {                                                                             \
-      case 0: return k_cycle<64, 14, 768, 3, T, false, 2>;                                   \
-      case 1: return k_cycle<40, 16, 512, 4, T, false, 2>;                                   \
-      case 2: return k_cycle<32, 20, 512, 4, T, false, 2>;                                   \
-      case 3: return k_cycle<64, 15, 768, 3, T, false, 2>;                                   \
-      case 4: return k_cycle<64, 16, 768, 3, T, false, 2>;                                   \
-      case 5: return k_cycle<48, 20, 768, 3, T, false, 2>;                                   \
-      case 6: return k_cycle<40, 24, 768, 3, T, false, 2>;                                   \
-      case 7: return k_cycle<28, 18, 512, 4, T, false, 2>;                                   \
-      case 8: return k_cycle<64, 16, 1024, 4, T, false, 2>;                                  \
-      case 9: return k_cycle<32, 32, 1024, 4, T, false, 2>;                                  \
-      case 10: return k_cycle<20, 13, 256, 3, T, false, 2>;                                  \
+      case 0: return k_cycle<64, 14, 768, 3, T, false, 2, false>;                            \
+      case 1: return k_cycle<40, 16, 512, 4, T, false, 2, false>;                            \
+      case 2: return k_cycle<32, 20, 512, 4, T, false, 2, false>;                            \
+      case 3: return k_cycle<64, 15, 768, 3, T, false, 2, false>;                            \
+      case 4: return k_cycle<64, 16, 768, 3, T, false, 2, false>;                            \
+      case 5: return k_cycle<48, 20, 768, 3, T, false, 2, false>;                            \
+      case 6: return k_cycle<40, 24, 768, 3, T, false, 2, false>;                            \
+      case 7: return k_cycle<28, 18, 512, 4, T, false, 2, false>;                            \
+      case 8: return k_cycle<64, 16, 1024, 4, T, false, 2, false>;                           \
+      case 9: return k_cycle<32, 32, 1024, 4, T, false, 2, false>;                           \
+      case 10: return k_cycle<20, 13, 256, 3, T, false, 2, false>;                           \
       default: return nullptr;                                                               \
     }                                                                                        \
   }                                                                                          \
   static CycleFn cycle_uni3_##suffix(int v) {                                                \
     switch (v) {                                                                             \
-      case 0: return k_cycle<64, 14, 768, 3, T, false, 3>;                                   \
-      case 1: return k_cycle<40, 16, 512, 4, T, false, 3>;                                   \
-      case 2: return k_cycle<32, 20, 512, 4, T, false, 3>;                                   \
-      case 3: return k_cycle<64, 15, 768, 3, T, false, 3>;                                   \
-      case 5: return k_cycle<48, 20, 768, 3, T, false, 3>;                                   \
-      case 6: return k_cycle<40, 24, 768, 3, T, false, 3>;                                   \
-      case 7: return k_cycle<28, 18, 512, 4, T, false, 3>;                                   \
-      case 9: return k_cycle<32, 32, 1024, 4, T, false, 3>;                                  \
-      case 10: return k_cycle<20, 13, 256, 3, T, false, 3>;                                  \
+      case 0: return k_cycle<64, 14, 768, 3, T, false, 3, false>;                            \
+      case 1: return k_cycle<40, 16, 512, 4, T, false, 3, false>;                            \
+      case 2: return k_cycle<32, 20, 512, 4, T, false, 3, false>;                            \
+      case 3: return k_cycle<64, 15, 768, 3, T, false, 3, false>;                            \
+      case 5: return k_cycle<48, 20, 768, 3, T, false, 3, false>;                            \
+      case 6: return k_cycle<40, 24, 768, 3, T, false, 3, false>;                            \
+      case 7: return k_cycle<28, 18, 512, 4, T, false, 3, false>;                            \
+      case 9: return k_cycle<32, 32, 1024, 4, T, false, 3, false>;                           \
+      case 10: return k_cycle<20, 13, 256, 3, T, false, 3, false>;                           \
+      default: return nullptr;                                                               \
+    }                                                                                        \
+  }                                                                                          \
+  static CycleFn cycle_uni2pm_##suffix(int v) {                                              \
+    switch (v) {                                                                             \
+      case 0: return k_cycle<64, 14, 768, 3, T, false, 2, true>;                             \
+      case 1: return k_cycle<40, 16, 512, 4, T, false, 2, true>;                             \
+      case 7: return k_cycle<28, 18, 512, 4, T, false, 2, true>;                             \
+      case 10: return k_cycle<20, 13, 256, 3, T, false, 2, true>;                            \
+      default: return nullptr;                                                               \
+    }                                                                                        \
+  }                                                                                          \
+  static CycleFn cycle_uni3pm_##suffix(int v) {                                              \
+    switch (v) {                                                                             \
+      case 1: return k_cycle<40, 16, 512, 4, T, false, 3, true>;                             \
+      case 7: return k_cycle<28, 18, 512, 4, T, false, 3, true>;                             \
+      case 10: return k_cycle<20, 13, 256, 3, T, false, 3, true>;                            \
       default: return nullptr;                                                               \
     }                                                                                        \
   }                                                                                          \
   static CycleFn cycle_geo2_##suffix(int v) {                                                \
     switch (v) {                                                                             \
-      case 0: return k_cycle<64, 14, 768, 3, T, true, 2>;                                    \
-      case 1: return k_cycle<40, 16, 512, 4, T, true, 2>;                                    \
-      case 2: return k_cycle<32, 20, 512, 4, T, true, 2>;                                    \
-      case 3: return k_cycle<64, 15, 768, 3, T, true, 2>;                                    \
-      case 4: return k_cycle<64, 16, 768, 3, T, true, 2>;                                    \
-      case 5: return k_cycle<48, 20, 768, 3, T, true, 2>;                                    \
-      case 6: return k_cycle<40, 24, 768, 3, T, true, 2>;                                    \
-      case 7: return k_cycle<28, 18, 512, 4, T, true, 2>;                                    \
-      case 8: return k_cycle<64, 16, 1024, 4, T, true, 2>;                                   \
-      case 9: return k_cycle<32, 32, 1024, 4, T, true, 2>;                                   \
-      case 10: return k_cycle<20, 13, 256, 3, T, true, 2>;                                   \
+      case 0: return k_cycle<64, 14, 768, 3, T, true, 2, false>;                             \
+      case 1: return k_cycle<40, 16, 512, 4, T, true, 2, false>;                             \
+      case 2: return k_cycle<32, 20, 512, 4, T, true, 2, false>;                             \
+      case 3: return k_cycle<64, 15, 768, 3, T, true, 2, false>;                             \
+      case 4: return k_cycle<64, 16, 768, 3, T, true, 2, false>;                             \
+      case 5: return k_cycle<48, 20, 768, 3, T, true, 2, false>;                             \
+      case 6: return k_cycle<40, 24, 768, 3, T, true, 2, false>;                             \
+      case 7: return k_cycle<28, 18, 512, 4, T, true, 2, false>;                             \
+      case 8: return k_cycle<64, 16, 1024, 4, T, true, 2, false>;                            \
+      case 9: return k_cycle<32, 32, 1024, 4, T, true, 2, false>;                            \
+      case 10: return k_cycle<20, 13, 256, 3, T, true, 2, false>;                            \
       default: return nullptr;                                                               \
     }                                                                                        \
   }                                                                                          \
   static CycleFn cycle_geo3_##suffix(int v) {                                                \
     switch (v) {                                                                             \
-      case 0: return k_cycle<64, 14, 768, 3, T, true, 3>;                                    \
-      case 1: return k_cycle<40, 16, 512, 4, T, true, 3>;                                    \
-      case 2: return k_cycle<32, 20, 512, 4, T, true, 3>;                                    \
-      case 3: return k_cycle<64, 15, 768, 3, T, true, 3>;                                    \
-      case 5: return k_cycle<48, 20, 768, 3, T, true, 3>;                                    \
-      case 6: return k_cycle<40, 24, 768, 3, T, true, 3>;                                    \
-      case 7: return k_cycle<28, 18, 512, 4, T, true, 3>;                                    \
-      case 9: return k_cycle<32, 32, 1024, 4, T, true, 3>;                                   \
-      case 10: return k_cycle<20, 13, 256, 3, T, true, 3>;                                   \
+      case 0: return k_cycle<64, 14, 768, 3, T, true, 3, false>;                             \
+      case 1: return k_cycle<40, 16, 512, 4, T, true, 3, false>;                             \
+      case 2: return k_cycle<32, 20, 512, 4, T, true, 3, false>;                             \
+      case 3: return k_cycle<64, 15, 768, 3, T, true, 3, false>;                             \
+      case 5: return k_cycle<48, 20, 768, 3, T, true, 3, false>;                             \
+      case 6: return k_cycle<40, 24, 768, 3, T, true, 3, false>;                             \
+      case 7: return k_cycle<28, 18, 512, 4, T, true, 3, false>;                             \
+      case 9: return k_cycle<32, 32, 1024, 4, T, true, 3, false>;                            \
+      case 10: return k_cycle<20, 13, 256, 3, T, true, 3, false>;                            \
       default: return nullptr;                                                               \
     }                                                                                        \
   }                                                                                          \
-  CycleFn cycle_kernel_##suffix(int v, bool geo, int nm) {                                   \
+  static CycleFn cycle_geo2pm_##suffix(int v) {                                              \
+    switch (v) {                                                                             \
+      case 0: return k_cycle<64, 14, 768, 3, T, true, 2, true>;                              \
+      case 1: return k_cycle<40, 16, 512, 4, T, true, 2, true>;                              \
+      case 7: return k_cycle<28, 18, 512, 4, T, true, 2, true>;                              \
+      case 10: return k_cycle<20, 13, 256, 3, T, true, 2, true>;                             \
+      default: return nullptr;                                                               \
+    }                                                                                        \
+  }                                                                                          \
+  static CycleFn cycle_geo3pm_##suffix(int v) {                                              \
+    switch (v) {                                                                             \
+      case 1: return k_cycle<40, 16, 512, 4, T, true, 3, true>;                              \
+      case 7: return k_cycle<28, 18, 512, 4, T, true, 3, true>;                              \
+      case 10: return k_cycle<20, 13, 256, 3, T, true, 3, true>;                             \
+      default: return nullptr;                                                               \
+    }                                                                                        \
+  }                                                                                          \
+  CycleFn cycle_kernel_##suffix(int v, bool geo, int nm, bool pm) {                          \
+    if (pm) {                                                                                \
+      if (nm <= 2) return geo ? cycle_geo2pm_##suffix(v) : cycle_uni2pm_##suffix(v);         \
+      return geo ? cycle_geo3pm_##suffix(v) : cycle_uni3pm_##suffix(v);                      \
+    }                                                                                        \
     if (nm <= 2) return geo ? cycle_geo2_##suffix(v) : cycle_uni2_##suffix(v);               \
     return geo ? cycle_geo3_##suffix(v) : cycle_uni3_##suffix(v);                            \
   }                                                                                          \

@@ -24,6 +24,8 @@ constexpr double kMRemapFloor = 1e-9;   // remap denominator floor (x rho_ref V)
 constexpr double kWLo = 1e-3, kWHi = 1e-2;  // CFL void-weight ramp
 constexpr double kNegMassTol = 1e-9;    // density below -tol rho_ref is an error
 constexpr double kPcavFrac = 1e-4;      // cavitation pressure ramp (x A)
+constexpr double kFPmEps = 1e-6;        // per-material closure: below this volume
+                                        // fraction a material takes the cell's matter density
 
 // error flags raised by kernels, turned into codes by the finalize kernel
 constexpr unsigned kFlagNonFinite = 1u, kFlagNegMass = 2u;
@@ -51,6 +53,7 @@ struct Geo {
   int prec;            // 0: FP64 throughout; 1: FP32 bulk with FP64 energy, mass and volume sums
   int has_p0;          // nonzero initial (lithostatic) pressure profile
   int stretched;       // per-column widths / per-row heights from the geometry table
+  int closure;         // 0: shared material density and energy; 1: per material
   double dr, dz, cfl, dt_grow, dt_max, dt_floor, t_stop, q_lin, q_quad;
   double rho_ref;
   float drf, dzf, q_linf, q_quadf, rho_reff, pad_f;
@@ -82,10 +85,16 @@ constexpr int kEos = 5;
 
 // One copy of the evolving state (two copies ping-pong by cycle parity).
 // rho, I and f are FP64 in every precision; stress, velocity and the EoS
-// cache hold the bulk type (double, or float in the mixed mode).
+// cache hold the bulk type (double, or float in the mixed mode). With the
+// per-material closure, mu (partial densities: mass of each material per
+// cell volume) and Im (its specific energies) are the FP64 state, rho and I
+// their sum and mass-weighted energy, and pmat caches each material's
+// pressure with the EoS.
 struct State {
   double *rho, *I, *f[kMaxMat];
   void *s[3], *v[2], *eos[kEos];
+  double *mu[kMaxMat], *Im[kMaxMat];
+  void* pmat[kMaxMat];
 };
 
 // Scalars living in device memory so that captured graphs can be replayed.
@@ -377,6 +386,69 @@ __device__ inline Mix<T> mixture(const Geo& g, double rho, double I, const doubl
     T ym = (m > 0 && g.same_mat && have0) ? y0 : yield_strength(M, p);
     if (m == 0) y0 = ym;
     Y += wm[m] * (sov[m] * ym);
+    pmin += wm[m] * M.p_min;
+    ps += wm[m] * M.pcav;
+  }
+  T d = p - pmin;
+  o.sx = d >= ps ? T(1) : (ps > T(0) ? N::div(tmax(d, T(0)), ps) : T(0));
+  o.p = p;
+  o.c2 = c2;
+  o.G = G;
+  o.Y = Y;
+  o.rmat = rm;
+  o.phi = phi;
+  return o;
+}
+
+// Per-material closure: the same volume-fraction average, every material at
+// its own density rho_m = mu_m / f_m (below a volume fraction of kFPmEps, or
+// without mass, at the cell's matter density) and its own specific energy
+// Im_m. pmv receives each material's pressure after its floor (0 for a
+// material absent from the cell, which adds nothing anywhere).
+template <class T>
+__device__ inline Mix<T> mixture_pm(const Geo& g, double rho, const double* fd, const double* mud,
+                                    const double* Imd, T* pmv) {
+  using N = Num<T>;
+  Mix<T> o;
+  T f[kMaxMat];
+#pragma unroll
+  for (int m = 0; m < kMaxMat; m++) f[m] = m < g.nmat ? (T)fd[m] : T(0);
+  T phi, iden, rm;
+  matter(g, (T)rho, f, phi, iden, rm);
+  double phid = 0.0;
+#pragma unroll
+  for (int m = 0; m < kMaxMat; m++)
+    if (m < g.nmat) phid += fd[m];
+  double rmd = rho * (1.0 / (phid > kPhiEps ? phid : kPhiEps));
+  T p = T(0), c2 = T(0), G = T(0);
+  T wm[kMaxMat], sov[kMaxMat];
+#pragma unroll
+  for (int m = 0; m < kMaxMat; m++) {
+    pmv[m] = T(0);
+    if (m >= g.nmat) break;
+    const MatT<T>& M = GeoT<T>::mat(g, m);
+    wm[m] = f[m] * iden;
+    sov[m] = T(0);
+    if (fd[m] == 0.0) continue;
+    double rmm = fd[m] > kFPmEps && mud[m] > 0.0 ? mud[m] / fd[m] : rmd;
+    T pm, c2m;
+    Dens<T> dn = dens_terms(g.m[m], rmm, (T*)nullptr);
+    T Ie = (T)Imd[m];
+    tillotson(M, dn, Ie, pm, c2m);
+    pmv[m] = tmax(pm, M.p_min);
+    T c2v = tmax(c2m, M.cf2);
+    sov[m] = softening(M, Ie);
+    p += wm[m] * pmv[m];
+    c2 += wm[m] * c2v;
+    G += wm[m] * (sov[m] * (M.gfac * ((T)rmm * c2v)));
+  }
+  T Y = T(0), pmin = T(0), ps = T(0);
+#pragma unroll
+  for (int m = 0; m < kMaxMat; m++) {
+    if (m >= g.nmat) break;
+    if (fd[m] == 0.0) continue;
+    const MatT<T>& M = GeoT<T>::mat(g, m);
+    Y += wm[m] * (sov[m] * yield_strength(M, p));
     pmin += wm[m] * M.p_min;
     ps += wm[m] * M.pcav;
   }

@@ -184,6 +184,12 @@ void carve_persistent(Member& mb, Carver& cv) {
     S.v[0] = cv.bytes(nn * es);
     S.v[1] = cv.bytes(nn * es);
     for (int k = 0; k < kEos; k++) S.eos[k] = cv.bytes(nc * es);
+    for (int m = 0; m < kMaxMat; m++) {
+      const bool on = g.closure && m < g.nmat;
+      S.mu[m] = on ? cv.d(nc) : nullptr;
+      S.Im[m] = on ? cv.d(nc) : nullptr;
+      S.pmat[m] = on ? cv.bytes(nc * es) : nullptr;
+    }
   }
   mb.aux_off = cv.off;
   long long nbc = (long long)g.pml_b * g.NR, nrc = (long long)g.NZ * g.pml_r;
@@ -284,6 +290,8 @@ int validate(const salec_grid* g, const salec_material* mats, const salec_pml* p
     return why = "grid too large for one instance", SALEC_E_INVALID;
   if (g->nmat < 1 || g->nmat > SALEC_MAX_MAT) return why = "nmat must be 1, 2 or 3", SALEC_E_INVALID;
   if (g->precision != SALEC_FP64 && g->precision != SALEC_MIXED) return why = "precision", SALEC_E_INVALID;
+  if (g->closure != SALEC_CLOSURE_SHARED && g->closure != SALEC_CLOSURE_PER_MATERIAL)
+    return why = "closure must be 0 or 1", SALEC_E_INVALID;
   if (!(g->dr > 0) || !(g->dz > 0)) return why = "cell size must be > 0", SALEC_E_INVALID;
   if (!(g->cfl > 0) || g->cfl > 1.0) return why = "cfl must be in (0, 1]", SALEC_E_INVALID;
   if (!(g->dt_grow >= 1.0) || !(g->dt_max > 0) || g->dt_floor < 0 || g->q_lin < 0 || g->q_quad < 0)
@@ -337,6 +345,7 @@ Geo make_geo(const salec_grid* gr, const salec_material* mats, const salec_pml* 
   g.NZ = gr->n_z + gr->pml_b;
   g.nmat = gr->nmat;
   g.top_closed = gr->top_closed;
+  g.closure = gr->closure;
   g.prec = gr->precision == SALEC_MIXED ? 1 : 0;
   // row pitch: 64 elements for FP32 rows, 32 for FP64 (256 bytes either way)
   int q = g.prec ? 64 : 32;
@@ -409,6 +418,8 @@ int check_members(const salec_instance* inst, int32_t n, std::vector<Member>& ms
     if (rc) return why = "instance " + std::to_string(k) + ": " + why, rc;
     if (I.grid.precision != inst[0].grid.precision)
       return why = "every instance of a context must use the same precision", SALEC_E_INVALID;
+    if (I.grid.closure != inst[0].grid.closure)
+      return why = "every instance of a context must use the same closure", SALEC_E_INVALID;
     const salec_scene& sc = I.scene;
     if (I.has_scene && (sc.subsample < 1 || !(sc.radius >= 0) || !(sc.gravity >= 0) || sc.surface_j < 0 ||
                         sc.surface_j > I.grid.n_z + I.grid.pml_b || sc.layer_j < 0 || sc.layer_j > sc.surface_j ||
@@ -438,6 +449,7 @@ struct salec_ctx {
   int prec = 0;
   bool geo = false;  // some member is stretched: the cycle kernel reads geometry tables
   int nm = 2;        // material slots of the cycle kernel: 3 when some member has three materials
+  bool pm = false;   // per-material closure (every member shares the closure)
   void* buf = nullptr;
   hipStream_t st = nullptr;
   bool own_stream = false;
@@ -515,7 +527,7 @@ int capture(salec_ctx* x, int ncyc, hipGraphExec_t* out) {
   HIPCHK(x, hipStreamBeginCapture(x->st, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
   for (int k = 0; k < ncyc && le == hipSuccess; k++) {
-    le = launch_cycle(x->variant, x->prec, x->geo, x->nm, x->L.d_inst, x->L.d_sched, x->nsched, grid, x->st);
+    le = launch_cycle(x->variant, x->prec, x->geo, x->nm, x->pm, x->L.d_inst, x->L.d_sched, x->nsched, grid, x->st);
     if (le == hipSuccess) le = launch_finalize(x->L.d_inst, (int)x->ms.size(), x->st);
   }
   hipError_t e = hipStreamEndCapture(x->st, &gr);
@@ -536,8 +548,8 @@ int use_schedule(salec_ctx* x, int v, int grid) {
     x->err = "schedule out of range";
     return SALEC_E_INVALID;
   }
-  if (!variant_available(v, x->prec, x->geo, x->nm)) {
-    x->err = "tile shape not available for three materials (its tile does not fit the LDS)";
+  if (!variant_available(v, x->prec, x->geo, x->nm, x->pm)) {
+    x->err = "tile shape not built for this material count and closure (its tile does not fit the LDS)";
     return SALEC_E_INVALID;
   }
   HIPCHK(x, hipStreamSynchronize(x->st));
@@ -597,6 +609,7 @@ int init_common(salec_ctx* x, void* dev_buf, size_t dev_bytes, void* stream) {
   }
   x->buf = dev_buf;
   x->prec = x->ms[0].g.prec;
+  x->pm = x->ms[0].g.closure == SALEC_CLOSURE_PER_MATERIAL;
   for (const Member& mb : x->ms) {
     if (mb.g.stretched) x->geo = true;
     if (mb.g.nmat > 2) x->nm = 3;
@@ -649,10 +662,13 @@ int init_common(salec_ctx* x, void* dev_buf, size_t dev_bytes, void* stream) {
     if (rc) return rc;
   }
   // the default shape; a persistent grid when it has fewer workgroups than tiles
-  const int v0 = default_variant(x->prec);
+  int v0 = default_variant(x->prec);
+  // fall back along the shapes every family has when the default is not built
+  for (int alt : {1, 7, 10})
+    if (!variant_available(v0, x->prec, x->geo, x->nm, x->pm)) v0 = alt;
   int rc = use_schedule(x, v0, 0);
   if (rc) return rc;
-  const int g0 = resident_groups(v0, x->prec, x->geo, x->nm);
+  const int g0 = resident_groups(v0, x->prec, x->geo, x->nm, x->pm);
   if (g0 > 0 && g0 < x->nsched && (rc = use_schedule(x, v0, g0))) return rc;
   x->ready = true;
   return SALEC_OK;
@@ -787,7 +803,7 @@ int salec_time_kernels(salec_ctx* x, int32_t n, double* cycle_ms, double* finali
   const int grid = x->grid > 0 ? std::min(x->grid, x->nsched) : x->nsched;
   hipError_t e = rc ? hipErrorOutOfMemory : hipEventRecord(ev[0], x->st);
   for (int c = 0; c < n && e == hipSuccess; c++) {
-    e = launch_cycle(x->variant, x->prec, x->geo, x->nm, x->L.d_inst, x->L.d_sched, x->nsched, grid, x->st);
+    e = launch_cycle(x->variant, x->prec, x->geo, x->nm, x->pm, x->L.d_inst, x->L.d_sched, x->nsched, grid, x->st);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * c + 1], x->st);
     if (e == hipSuccess) e = launch_finalize(x->L.d_inst, (int)x->ms.size(), x->st);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * c + 2], x->st);
@@ -884,7 +900,91 @@ int salec_set_fields(salec_ctx* x, int32_t k, const salec_fields* in) {
   }
   if ((rc = copy_in(x, S.v[0], in->v, g.NR + 1, g.NZ + 1, g.pn, es))) return rc;
   if ((rc = copy_in(x, S.v[1], in->v + NN, g.NR + 1, g.NZ + 1, g.pn, es))) return rc;
+  if (g.closure) {
+    // every material of a cell at the cell's matter density and energy
+    std::vector<double> mu(g.nmat * NC), Im(g.nmat * NC);
+    for (size_t c = 0; c < NC; c++) {
+      double phi = 0.0;
+      for (int m = 0; m < g.nmat; m++) phi += in->f[m * NC + c];
+      const double iden = 1.0 / (phi > kPhiEps ? phi : kPhiEps);
+      for (int m = 0; m < g.nmat; m++) {
+        mu[m * NC + c] = in->rho[c] * (in->f[m * NC + c] * iden);
+        Im[m * NC + c] = in->I[c];
+      }
+    }
+    for (int m = 0; m < g.nmat; m++) {
+      if ((rc = copy_in(x, S.mu[m], mu.data() + m * NC, g.NR, g.NZ, g.pc, sizeof(double)))) return rc;
+      if ((rc = copy_in(x, S.Im[m], Im.data() + m * NC, g.NR, g.NZ, g.pc, sizeof(double)))) return rc;
+    }
+  }
   return start_run(x, k);
+}
+
+int salec_set_materials(salec_ctx* x, int32_t k, const double* mu, const double* Im) {
+  if (!member_ok(x, k) || !mu || !Im) return SALEC_E_INVALID;
+  Member& mb = x->ms[k];
+  const Geo& g = mb.g;
+  if (!g.closure) {
+    x->err = "per-material state needs the per-material closure";
+    return SALEC_E_INVALID;
+  }
+  HIPCHK(x, hipStreamSynchronize(x->st));
+  // a new run starts from level 0: move the current state there first
+  if (read_scal(x, k).cycle & 1) {
+    const State &A = mb.d.S[1], &B = mb.d.S[0];
+    const size_t cb = (size_t)g.NZ * g.pc * sizeof(double), ce = (size_t)g.NZ * g.pc * elem_size(x);
+    const size_t nb = (size_t)(g.NZ + 1) * g.pn * elem_size(x);
+    auto cp = [&](void* d, const void* s_, size_t n) {
+      return s_ ? hipMemcpyAsync(d, s_, n, hipMemcpyDeviceToDevice, x->st) : hipSuccess;
+    };
+    HIPCHK(x, cp(B.rho, A.rho, cb));
+    HIPCHK(x, cp(B.I, A.I, cb));
+    for (int m = 0; m < g.nmat; m++) HIPCHK(x, cp(B.f[m], A.f[m], cb));
+    for (int q = 0; q < 3; q++) HIPCHK(x, cp(B.s[q], A.s[q], ce));
+    for (int q = 0; q < 2; q++) HIPCHK(x, cp(B.v[q], A.v[q], nb));
+  }
+  const State& S = mb.d.S[0];
+  size_t NC = (size_t)g.NR * g.NZ;
+  std::vector<double> rho(NC, 0.0), I(NC, 0.0);
+  for (size_t c = 0; c < NC; c++) {
+    double r = 0.0, e = 0.0;
+    for (int m = 0; m < g.nmat; m++) r += mu[m * NC + c];
+    for (int m = 0; m < g.nmat; m++) e += mu[m * NC + c] * Im[m * NC + c];
+    if (!std::isfinite(r) || !std::isfinite(e)) {
+      x->err = "non-finite per-material state";
+      return SALEC_E_INVALID;
+    }
+    rho[c] = r;
+    I[c] = r > 0.0 ? e / r : 0.0;
+  }
+  int rc;
+  for (int m = 0; m < g.nmat; m++) {
+    if ((rc = copy_in(x, S.mu[m], mu + m * NC, g.NR, g.NZ, g.pc, sizeof(double)))) return rc;
+    if ((rc = copy_in(x, S.Im[m], Im + m * NC, g.NR, g.NZ, g.pc, sizeof(double)))) return rc;
+  }
+  if ((rc = copy_in(x, S.rho, rho.data(), g.NR, g.NZ, g.pc, sizeof(double)))) return rc;
+  if ((rc = copy_in(x, S.I, I.data(), g.NR, g.NZ, g.pc, sizeof(double)))) return rc;
+  return start_run(x, k);
+}
+
+int salec_get_materials(salec_ctx* x, int32_t k, double* mu, double* Im) {
+  if (!member_ok(x, k)) return SALEC_E_INVALID;
+  Member& mb = x->ms[k];
+  const Geo& g = mb.g;
+  if (!g.closure) {
+    x->err = "per-material state needs the per-material closure";
+    return SALEC_E_INVALID;
+  }
+  HIPCHK(x, hipStreamSynchronize(x->st));
+  const State& S = mb.d.S[read_scal(x, k).cycle & 1];
+  size_t NC = (size_t)g.NR * g.NZ;
+  int rc;
+  for (int m = 0; m < g.nmat; m++) {
+    if (mu && (rc = copy_out(x, mu + m * NC, S.mu[m], g.NR, g.NZ, g.pc, sizeof(double)))) return rc;
+    if (Im && (rc = copy_out(x, Im + m * NC, S.Im[m], g.NR, g.NZ, g.pc, sizeof(double)))) return rc;
+  }
+  HIPCHK(x, hipStreamSynchronize(x->st));
+  return SALEC_OK;
 }
 
 int salec_get_pml(salec_ctx* x, int32_t k, double* ca, double* na) {
@@ -1028,10 +1128,10 @@ int salec_tune(salec_ctx* x, int32_t cycles, salec_schedule* out) {
   int best_v = x->variant, best_g = x->grid;
   double best = 1e300;
   for (int v = 0; v < n_variants(); v++) {
-    if (!variant_available(v, x->prec, x->geo, x->nm)) continue;
+    if (!variant_available(v, x->prec, x->geo, x->nm, x->pm)) continue;
     // one workgroup per tile, and as many workgroups as fit at once walking
     // the tiles (when that is fewer than the tiles)
-    int grids[2] = {0, resident_groups(v, x->prec, x->geo, x->nm)};
+    int grids[2] = {0, resident_groups(v, x->prec, x->geo, x->nm, x->pm)};
     for (int gi = 0; gi < 2; gi++) {
       if (gi == 1 && (grids[1] <= 0 || grids[1] >= x->nsched)) continue;
       int rc = use_schedule(x, v, grids[gi]);

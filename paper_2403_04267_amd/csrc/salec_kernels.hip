@@ -69,6 +69,13 @@ __global__ void k_scene_cells(Inst in, int surface_j, int layer_j, int layer2_j,
   _Pragma("unroll") for (int m = 0; m < kMaxMat; m++) if (m < g.nmat) S0.f[m][c] = f[m];
   S0.rho[c] = rho;
   S0.I[c] = 0.0;
+  if (g.closure) {  // per-material closure: each cell holds one material's mass
+    const int own = j < surface_j ? (g.nmat == 3 && j < layer2_j ? 2 : (g.nmat > 1 && j < layer_j ? 1 : 0)) : mp;
+    for (int m = 0; m < g.nmat; m++) {
+      S0.mu[m][c] = m == own ? rho : 0.0;
+      S0.Im[m][c] = 0.0;
+    }
+  }
   if (g.any_strength)
     for (int k = 0; k < 3; k++) ((T*)S0.s[k])[c] = T(0);
   fproj[c] = fp;
@@ -155,7 +162,18 @@ __global__ void k_eos_out(Inst in, double* p, double* c2) {
   long long c = cidx(g, i, j);
   double f[kMaxMat];
   for (int m = 0; m < kMaxMat; m++) f[m] = m < g.nmat ? S.f[m][c] : 0.0;
-  Mix<T> mx = mixture<T>(g, S.rho[c], S.I[c], f);
+  Mix<T> mx;
+  if (g.closure) {
+    double mu[kMaxMat], Im[kMaxMat];
+    T pmv[kMaxMat];
+    for (int m = 0; m < kMaxMat; m++) {
+      mu[m] = m < g.nmat ? S.mu[m][c] : 0.0;
+      Im[m] = m < g.nmat ? S.Im[m][c] : 0.0;
+    }
+    mx = mixture_pm<T>(g, S.rho[c], f, mu, Im, pmv);
+  } else {
+    mx = mixture<T>(g, S.rho[c], S.I[c], f);
+  }
   p[c] = (double)mx.p;
   c2[c] = (double)mx.c2;
 }

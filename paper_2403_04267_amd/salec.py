@@ -25,7 +25,7 @@ ERRORS = {-1: "SALEC_E_INVALID", -2: "SALEC_E_BUFFER", -3: "SALEC_E_HIP", -4: "S
 class Grid(C.Structure):
     _fields_ = [("n_r", C.c_int32), ("n_z", C.c_int32), ("pml_r", C.c_int32), ("pml_b", C.c_int32),
                 ("nmat", C.c_int32), ("top_closed", C.c_int32), ("precision", C.c_int32),
-                ("reserved", C.c_int32)] + \
+                ("closure", C.c_int32)] + \
                [(n, C.c_double) for n in ("dr", "dz", "cfl", "dt_grow", "dt_max", "dt_floor", "t_stop",
                                           "q_lin", "q_quad")] + \
                [("dr_col", C.POINTER(C.c_double)), ("dz_row", C.POINTER(C.c_double))]
@@ -112,6 +112,8 @@ def load() -> C.CDLL:
     lib.salec_time_kernels.argtypes = [P, I32, _DP, _DP]
     lib.salec_set_p0.argtypes = [P, I32, _DP]
     lib.salec_get_p0.argtypes = [P, I32, _DP]
+    lib.salec_set_materials.argtypes = [P, I32, _DP, _DP]
+    lib.salec_get_materials.argtypes = [P, I32, _DP, _DP]
     lib.salec_num_variants.restype = I32
     lib.salec_num_variants.argtypes = []
     lib.salec_get_schedule.argtypes = [P, C.POINTER(Schedule)]
@@ -138,7 +140,7 @@ def _grid(g, precision, keep: list) -> Grid:
     dzr = None if g.dz_row is None else np.ascontiguousarray(g.dz_row, dtype=np.float64)
     keep.extend([drc, dzr])
     return Grid(g.n_r, g.n_z, g.pml_r, g.pml_b, g.nmat, g.top_closed,
-                SALEC_MIXED if precision == "mixed" else SALEC_FP64, 0,
+                SALEC_MIXED if precision == "mixed" else SALEC_FP64, int(g.closure),
                 g.dr, g.dz, g.cfl, g.dt_grow, g.dt_max, g.dt_floor, g.t_stop, g.q_lin, g.q_quad,
                 _ptr(drc), _ptr(dzr))
 
@@ -307,6 +309,21 @@ class Salec:
         out = np.empty(NZ)
         self._check(self.lib.salec_get_p0(self._h, int(k), _ptr(out)))
         return out
+
+    def set_materials(self, mu, Im, k: int = 0):
+        """Per-material state of member k (per-material closure): partial
+        densities and specific energies, each (nmat, NZ, NR)."""
+        NR, NZ, nmat = self.dims[k]
+        mu = np.ascontiguousarray(mu, dtype=np.float64).reshape(nmat * NZ * NR)
+        Im = np.ascontiguousarray(Im, dtype=np.float64).reshape(nmat * NZ * NR)
+        self._check(self.lib.salec_set_materials(self._h, int(k), _ptr(mu), _ptr(Im)))
+
+    def materials(self, k: int = 0) -> dict:
+        """{"mu": partial densities, "Im": specific energies}, (nmat, NZ, NR)."""
+        NR, NZ, nmat = self.dims[k]
+        mu, Im = np.empty(nmat * NZ * NR), np.empty(nmat * NZ * NR)
+        self._check(self.lib.salec_get_materials(self._h, int(k), _ptr(mu), _ptr(Im)))
+        return {"mu": mu.reshape(nmat, NZ, NR), "Im": Im.reshape(nmat, NZ, NR)}
 
     def pml_aux(self, k: int = 0) -> dict:
         NR, NZ, _ = self.dims[k]

@@ -2,6 +2,7 @@
 every function include/salec.h declares, and validates problem descriptions
 in salec_plan (pure host code)."""
 import ctypes as C
+import dataclasses
 import os
 
 import pytest
@@ -48,6 +49,17 @@ def test_plan_rejects_invalid_materials_and_pml():
     pb = inputs.config_small()
     pb.pml.R = 1.5
     assert salec.plan_bytes(pb) == 0
+
+
+def test_closure_is_validated_and_shared_by_members():
+    a = inputs.impact(30, 5, 4, 9e3, nmat=2, strength=False, cycles=0)
+    b = a.replace(grid=dataclasses.replace(a.grid, closure=1))
+    assert salec.plan_bytes(a) > 0 and salec.plan_bytes(b) > 0
+    # the per-material closure keeps mu_m, I_m (both levels) and each
+    # material's cached pressure: a larger plan
+    assert salec.plan_bytes(b) > salec.plan_bytes(a)
+    assert salec.plan_bytes([a, b]) == 0
+    assert salec.plan_bytes(a.replace(grid=dataclasses.replace(a.grid, closure=2))) == 0
 
 
 def test_mixed_precision_plan_is_smaller():
