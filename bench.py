@@ -24,6 +24,8 @@ Also measured (the "extensions" object; skipped with --headline-only):
   three_layer_fp64   the 1050^2 workload as Sec. 4's three-layer target
                  (calcite, granite, dunite; 400 m cells, gravity), plain FP64
   paper_layers_fp64  Sec. 4's three-layer setting on Table 2's grid, FP64
+  three_layer_pm_fp64  the three-layer 1050^2 target with the per-material
+                 closure (each material's own density and energy), FP64
   pml_payoff     the same small impact with a PML, with plain walls and on a
                  10x larger domain, each to the same time (interior error,
                  reflected energy, crater geometry, device time)
@@ -40,6 +42,7 @@ same time, in GB/s, or null when the kernel sources or the schedule differ
 from those the counters were taken with.
 """
 import argparse
+import dataclasses
 import glob
 import hashlib
 import json
@@ -70,11 +73,12 @@ def algorithmic_bytes_per_cell(pb) -> float:
     cell; plus the PML auxiliaries (3 cell + 4 node values per damped
     direction, read + written; corner cells count twice; the reference
     density read and the sink read + written) averaged over all cells.
-    Mixed precision: stress and velocity are 4-byte values."""
+    Mixed precision: stress and velocity are 4-byte values. The per-material
+    closure adds each material's partial density and specific energy."""
     g = pb.grid
     nmat = g.nmat
     strength = any(m.strength for m in pb.mats[:nmat])
-    wide = 8 * (2 + nmat)
+    wide = 8 * (2 + nmat + (2 * nmat if g.closure else 0))
     narrow = (8 if pb.precision == "fp64" else 4) * ((3 if strength else 0) + 2)
     state = 2 * (wide + narrow)
     NR, NZ = g.NR, g.NZ
@@ -307,6 +311,10 @@ def main():
                                             500, 20, args.tune, value)
         ext["paper_layers_fp64"] = extension("Table 2 grid 512x532 three layers fp64",
                                              inputs.config_paper_layers(), 300, 20, args.tune, value)
+        three = inputs.three_layer_impact(1000, 50, 50, 15e3, 7, 75, name="three-pm")
+        ext["three_layer_pm_fp64"] = extension("three-layer 1050^2 per-material fp64",
+                                               three.replace(grid=dataclasses.replace(three.grid, closure=1)),
+                                               500, 20, args.tune, value)
         ext["pml_payoff"] = pml_payoff()
         ext["pml_payoff_table2"] = pml_payoff_table2()
         out["extensions"] = ext
