@@ -7,7 +7,9 @@ namespace salec {
 // 768-thread tiles run one workgroup per CU at three waves per SIMD (LDS
 // holds one tile); 512-thread tiles are capped at 128 registers so that two
 // workgroups (four waves per SIMD) share a CU where two tiles fit the LDS
-// (the FP32 instantiation); 256-thread tiles run three to a CU.
+// (the FP32 instantiation); 256-thread tiles run three to a CU. The last
+// shape is built only for the per-material closure and three material slots,
+// whose wider LDS records leave no 768-thread tile of the other sizes room.
 static const int kShapes[][3] = {
     {64, 14, 768},
     {40, 16, 512},
@@ -19,7 +21,8 @@ static const int kShapes[][3] = {
     {28, 18, 512},
     {64, 16, 1024},
     {32, 32, 1024},
-    {20, 13, 256}};
+    {20, 13, 256},
+    {48, 14, 768}};
 
 int default_variant(int prec) { return prec == 0 ? 0 : 1; }
 

@@ -1128,6 +1128,7 @@ __global__ void k_prime(Inst in) {
       case 7: return k_cycle<28, 18, 512, 4, T, false, 3, false>;                            \
       case 9: return k_cycle<32, 32, 1024, 4, T, false, 3, false>;                           \
       case 10: return k_cycle<20, 13, 256, 3, T, false, 3, false>;                           \
+      case 11: return k_cycle<48, 14, 768, 3, T, false, 3, false>;                           \
       default: return nullptr;                                                               \
     }                                                                                        \
   }                                                                                          \
@@ -1137,6 +1138,7 @@ __global__ void k_prime(Inst in) {
       case 1: return k_cycle<40, 16, 512, 4, T, false, 2, true>;                             \
       case 7: return k_cycle<28, 18, 512, 4, T, false, 2, true>;                             \
       case 10: return k_cycle<20, 13, 256, 3, T, false, 2, true>;                            \
+      case 11: return k_cycle<48, 14, 768, 3, T, false, 2, true>;                            \
       default: return nullptr;                                                               \
     }                                                                                        \
   }                                                                                          \
@@ -1145,6 +1147,7 @@ __global__ void k_prime(Inst in) {
       case 1: return k_cycle<40, 16, 512, 4, T, false, 3, true>;                             \
       case 7: return k_cycle<28, 18, 512, 4, T, false, 3, true>;                             \
       case 10: return k_cycle<20, 13, 256, 3, T, false, 3, true>;                            \
+      case 11: return k_cycle<48, 14, 768, 3, T, false, 3, true>;                            \
       default: return nullptr;                                                               \
     }                                                                                        \
   }                                                                                          \
@@ -1175,6 +1178,7 @@ __global__ void k_prime(Inst in) {
       case 7: return k_cycle<28, 18, 512, 4, T, true, 3, false>;                             \
       case 9: return k_cycle<32, 32, 1024, 4, T, true, 3, false>;                            \
       case 10: return k_cycle<20, 13, 256, 3, T, true, 3, false>;                            \
+      case 11: return k_cycle<48, 14, 768, 3, T, true, 3, false>;                            \
       default: return nullptr;                                                               \
     }                                                                                        \
   }                                                                                          \
@@ -1184,6 +1188,7 @@ __global__ void k_prime(Inst in) {
       case 1: return k_cycle<40, 16, 512, 4, T, true, 2, true>;                              \
       case 7: return k_cycle<28, 18, 512, 4, T, true, 2, true>;                              \
       case 10: return k_cycle<20, 13, 256, 3, T, true, 2, true>;                             \
+      case 11: return k_cycle<48, 14, 768, 3, T, true, 2, true>;                             \
       default: return nullptr;                                                               \
     }                                                                                        \
   }                                                                                          \
@@ -1192,6 +1197,7 @@ __global__ void k_prime(Inst in) {
       case 1: return k_cycle<40, 16, 512, 4, T, true, 3, true>;                              \
       case 7: return k_cycle<28, 18, 512, 4, T, true, 3, true>;                              \
       case 10: return k_cycle<20, 13, 256, 3, T, true, 3, true>;                             \
+      case 11: return k_cycle<48, 14, 768, 3, T, true, 3, true>;                             \
       default: return nullptr;                                                               \
     }                                                                                        \
   }                                                                                          \

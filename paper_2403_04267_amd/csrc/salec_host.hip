@@ -543,7 +543,8 @@ int capture(salec_ctx* x, int ncyc, hipGraphExec_t* out) {
 }
 
 // Selects a schedule: uploads descriptors and tile list, recaptures graphs.
-int use_schedule(salec_ctx* x, int v, int grid) {
+// whether (v, grid) names a schedule this context can run; nothing changes
+int check_schedule(salec_ctx* x, int v, int grid) {
   if (v < 0 || v >= n_variants() || grid < 0) {
     x->err = "schedule out of range";
     return SALEC_E_INVALID;
@@ -552,6 +553,12 @@ int use_schedule(salec_ctx* x, int v, int grid) {
     x->err = "tile shape not built for this material count and closure (its tile does not fit the LDS)";
     return SALEC_E_INVALID;
   }
+  return SALEC_OK;
+}
+
+int use_schedule(salec_ctx* x, int v, int grid) {
+  int rc0 = check_schedule(x, v, grid);
+  if (rc0) return rc0;
   HIPCHK(x, hipStreamSynchronize(x->st));
   if (x->gx1) (void)hipGraphExecDestroy(x->gx1);
   if (x->gxN) (void)hipGraphExecDestroy(x->gxN);
@@ -1117,8 +1124,11 @@ int salec_get_schedule(const salec_ctx* x, salec_schedule* out) {
 
 int salec_set_schedule(salec_ctx* x, int32_t variant, int32_t grid) {
   if (!x || !x->ready) return SALEC_E_INVALID;
+  // a schedule the context cannot run is refused without touching it
+  int rc = check_schedule(x, variant, grid);
+  if (rc) return rc;
   x->tuned_ms = 0.0;
-  int rc = use_schedule(x, variant, grid);
+  rc = use_schedule(x, variant, grid);
   if (rc) x->ready = false;
   return rc;
 }

@@ -191,3 +191,16 @@ def test_three_layer_per_material_mixed_against_oracle():
     print("[three-layer pm mixed cycle 100] " + " ".join(f"{k} {v:.2e}" for k, v in e.items()), flush=True)
     bad = {k: v for k, v in e.items() if not v <= 1e-4}
     assert not bad, bad
+
+
+def test_a_refused_shape_leaves_the_context_usable():
+    from paper_2403_04267_amd.salec import SalecError
+    pb = pm(impact3())
+    c = ctx(pb)
+    before = c.schedule()
+    with pytest.raises(SalecError):
+        c.set_schedule(0, 0)  # 64 x 14 does not fit the LDS with three per-material slots
+    assert c.schedule() == before
+    o = Oracle(pb)
+    step_both(c, o, 30)
+    compare(c, o, "after a refused shape", tol=0.0)

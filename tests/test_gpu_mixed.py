@@ -97,12 +97,16 @@ def test_mixed_rest_state_is_bitwise_unchanged():
 
 
 def test_mixed_tile_shapes_agree_bitwise():
-    from paper_2403_04267_amd.salec import num_variants
+    from paper_2403_04267_amd.salec import SalecError, num_variants
     pb = inputs.impact(61, 13, 6, 15e3, nmat=2, strength=True, cycles=0, precision="mixed")
     ref = None
     for v in range(num_variants()):
         c = ctx(pb)
-        c.set_schedule(v, 0)
+        try:
+            c.set_schedule(v, 0)
+        except SalecError:
+            assert v == 11  # built for three slots and the per-material closure only
+            continue
         c.step(80)
         F = c.fields()
         if ref is None:

@@ -47,14 +47,18 @@ def small_members():
 
 
 def test_every_tile_shape_matches_the_oracle():
-    from paper_2403_04267_amd.salec import num_variants
+    from paper_2403_04267_amd.salec import SalecError, num_variants
     pb = inputs.impact(61, 13, 6, 15e3, nmat=2, strength=True, cycles=0, name="shapes")
     o = Oracle(pb)
     o.step(60)
     for v in range(num_variants()):
         for grid in (0, 24):
             c = ctx(pb)
-            c.set_schedule(v, grid)
+            try:
+                c.set_schedule(v, grid)
+            except SalecError:
+                assert v == 11  # built for three slots and the per-material closure only
+                continue
             sch = c.schedule()
             assert sch["variant"] == v
             c.step(60)
@@ -111,7 +115,8 @@ def test_tuner_picks_a_schedule_without_changing_results():
     assert 0 <= sch["variant"] < num_variants() and sch["ms_per_cycle"] > 0
     # (cycles + 1) per candidate: every shape, some also with a persistent grid
     advanced = int(a.diag(k=0)["cycle"])
-    assert advanced % 3 == 0 and 3 * num_variants() <= advanced <= 6 * num_variants()
+    # (the last shape is not built for two-material shared-closure contexts)
+    assert advanced % 3 == 0 and 3 * (num_variants() - 1) <= advanced <= 6 * num_variants()
     b.step(advanced)
     a.step(20)
     b.step(20)

@@ -47,13 +47,17 @@ def test_stretched_impact_fp64_bitwise():
 
 
 def test_every_tile_shape_on_a_stretched_grid():
-    from paper_2403_04267_amd.salec import num_variants
+    from paper_2403_04267_amd.salec import SalecError, num_variants
     pb = inputs.stretched_impact(41, 7, 9, 5, 12e3, name="shapes")
     o = Oracle(pb)
     o.step(40)
     for v in range(num_variants()):
         c = ctx(pb)
-        c.set_schedule(v, 0)
+        try:
+            c.set_schedule(v, 0)
+        except SalecError:
+            assert v == 11  # built for three slots and the per-material closure only
+            continue
         c.step(40)
         compare(c, o, f"stretched variant {v}", tol=0.0)
 
