@@ -639,10 +639,16 @@ orc_ctx *orc_create(const orc_grid *g, const orc_mat *mats, const orc_pml *pml)
     /* damping profiles; y is measured from the inner face of each layer,
      * at cell centres for cell quantities and at nodes for node quantities */
     if (pml->enabled) {
+        /* Sec. 3: c is the largest acoustic speed; by default the largest
+         * longitudinal speed at rest over the materials */
         double c = pml->c_ref;
         if (!(c > 0)) {
-            const orc_mat *m0 = &mats[0];
-            c = sqrt((m0->A + (4.0 / 3.0) * orc_shear_modulus(m0)) / m0->rho0);
+            c = 0.0;
+            for (int m = 0; m < g->nmat; m++) {
+                const orc_mat *mm = &mats[m];
+                double cm = sqrt((mm->A + (4.0 / 3.0) * orc_shear_modulus(mm)) / mm->rho0);
+                if (cm > c) c = cm;
+            }
         }
         if (g->pml_b > 0) {
             double zf = x->zn[g->pml_b], delta = zf - x->zn[0];

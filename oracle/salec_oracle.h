@@ -66,7 +66,8 @@ typedef struct {
 typedef struct {
     int32_t enabled;
     double R;     /* theoretical reflection coefficient                    */
-    double c_ref; /* <=0: longitudinal speed of material 0 at rest         */
+    double c_ref; /* <=0: the largest longitudinal speed at rest over the  */
+                  /* materials                                             */
 } orc_pml;
 
 typedef struct {

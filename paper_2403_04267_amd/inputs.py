@@ -89,7 +89,7 @@ class Grid:
 class Pml:
     enabled: int = 1
     R: float = 0.01
-    c_ref: float = 0.0  # <= 0: longitudinal speed of material 0 at rest
+    c_ref: float = 0.0  # <= 0: the largest longitudinal speed at rest over the materials
 
 
 @dataclass
