@@ -35,7 +35,7 @@ class _Mat(C.Structure):
 
 
 class _Pml(C.Structure):
-    _fields_ = [("enabled", C.c_int32), ("R", C.c_double), ("c_ref", C.c_double)]
+    _fields_ = [("enabled", C.c_int32), ("damp_stress", C.c_int32), ("R", C.c_double), ("c_ref", C.c_double)]
 
 
 class _Scene(C.Structure):
@@ -131,7 +131,8 @@ class Oracle:
         self.nmat = g.nmat
         mats = (_Mat * 3)(*[_mat(m) for m in problem.mats[:g.nmat]])
         pml = problem.pml
-        self._h = lib.orc_create(C.byref(_grid(g)), mats, C.byref(_Pml(int(pml.enabled), pml.R, pml.c_ref)))
+        self._h = lib.orc_create(C.byref(_grid(g)), mats, C.byref(_Pml(int(pml.enabled), int(pml.damp_stress), pml.R,
+                                                                          pml.c_ref)))
         if not self._h:
             raise ValueError("oracle rejected the problem description")
         self._lib = lib

@@ -515,6 +515,7 @@ orc_ctx *orc_create(const orc_grid *g, const orc_mat *mats, const orc_pml *pml)
     if (g->n_r < 1 || g->n_z < 1 || g->pml_r < 0 || g->pml_b < 0) return NULL;
     if (g->nmat < 1 || g->nmat > ORC_MAX_MAT) return NULL;
     if (g->closure != 0 && g->closure != 1) return NULL;
+    if (pml->damp_stress != 0 && pml->damp_stress != 1) return NULL;
     if (!(g->dr > 0) || !(g->dz > 0) || !(g->cfl > 0) || g->cfl > 1.0) return NULL;
     for (int i = 0; g->dr_col && i < g->n_r + g->pml_r; i++)
         if (!(g->dr_col[i] > 0) || !isfinite(g->dr_col[i])) return NULL;
@@ -1395,6 +1396,13 @@ static void phase_cell_remap(orc_ctx *x)
                     rho2 = r2;
                 }
                 x->msink[c] = x->msink[c] + V * (rho1 - rho2);
+                /* extension: the deviatoric stress relaxes toward its initial
+                 * value (zero) at the layer's rate, like the velocity */
+                if (x->pml.damp_stress) {
+                    x->srr_n[c] = x->srr_n[c] - dt * (dsum * x->srr_n[c]);
+                    x->szz_n[c] = x->szz_n[c] - dt * (dsum * x->szz_n[c]);
+                    x->srz_n[c] = x->srz_n[c] - dt * (dsum * x->srz_n[c]);
+                }
                 if (db > 0.0) {
                     x->phi1b[c] = x->phi1b[c] + db * ((F[1] - F[0]) * iV);
                     x->phi3b[c] = x->phi3b[c] + db * ((ed[1] - ed[0]) * iV);

@@ -65,6 +65,9 @@ typedef struct {
 
 typedef struct {
     int32_t enabled;
+    int32_t damp_stress; /* 1: the layers also relax the deviatoric stress */
+                         /* toward zero at the rate d (an extension: Sec. 3 */
+                         /* damps mass, momentum and energy only)           */
     double R;     /* theoretical reflection coefficient                    */
     double c_ref; /* <=0: the largest longitudinal speed at rest over the  */
                   /* materials                                             */

@@ -90,6 +90,9 @@ class Pml:
     enabled: int = 1
     R: float = 0.01
     c_ref: float = 0.0  # <= 0: the largest longitudinal speed at rest over the materials
+    # 1: the layers also relax the deviatoric stress toward zero at the rate d
+    # (an extension; Sec. 3 damps mass, momentum and energy only)
+    damp_stress: int = 0
 
 
 @dataclass

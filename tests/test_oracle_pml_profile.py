@@ -40,3 +40,46 @@ def test_profile_uses_the_largest_acoustic_speed(make):
     # an explicit speed overrides the default
     o2 = Oracle(pb.replace(pml=inputs.Pml(c_ref=1000.0)))
     assert o2.profiles()[0][0] == pytest.approx(dcz[0] * 1000.0 / c, rel=1e-12)
+
+
+def _random_problem(damp, strength=True):
+    # dt_max well below the Courant limit (~1.5e-3 s): both runs take the same
+    # steps, so only the damping can make them differ
+    g = inputs.Grid(n_r=40, n_z=40, pml_r=10, pml_b=10, nmat=1, dr=10.0, dz=10.0, dt_max=2e-4)
+    pb = inputs.Problem(grid=g, mats=[inputs.basalt(strength=strength)], pml=inputs.Pml(damp_stress=damp))
+    o = Oracle(pb)
+    rho, I, v = inputs.random_state(g, 11)
+    o.set_fields(rho, I, np.ones((1, g.NZ, g.NR)), v)
+    return o
+
+
+def test_stress_damping_acts_only_in_the_layers():
+    """The extension that also relaxes the deviatoric stress in the layers
+    (not in Sec. 3): outside the layers' numerical domain of dependence the
+    state is bit for bit that of Sec. 3's layers; inside them the stress is
+    smaller; with no stress at all it changes nothing."""
+    n = 6
+    a, b = _random_problem(0), _random_problem(1)
+    a.step(n)
+    b.step(n)
+    A, B = a.fields(eos=False), b.fields(eos=False)
+    g = a.problem.grid
+    reach = 5 * n + 2  # cells per cycle of the cycle's stencil, generously
+    j0, i1 = g.pml_b + reach, g.n_r - reach
+    assert j0 < g.NZ and i1 > 0
+    for k in ("rho", "I", "s"):
+        x, y = A[k][..., j0:, :i1], B[k][..., j0:, :i1]
+        assert np.array_equal(x, y), k
+    assert np.array_equal(A["v"][:, j0 + 1:, :i1], B["v"][:, j0 + 1:, :i1])
+    lay = np.zeros((g.NZ, g.NR), dtype=bool)
+    lay[:g.pml_b, :] = True
+    lay[:, g.n_r:] = True
+    sa, sb = np.abs(A["s"][:, lay]).sum(), np.abs(B["s"][:, lay]).sum()
+    assert 0.0 < sb < sa, (sa, sb)
+    # hydrodynamic material: no stress, nothing to relax
+    c, d = _random_problem(0, strength=False), _random_problem(1, strength=False)
+    c.step(n)
+    d.step(n)
+    C_, D_ = c.fields(eos=False), d.fields(eos=False)
+    for k in C_:
+        assert np.array_equal(C_[k], D_[k]), k
