@@ -115,9 +115,15 @@ typedef struct salec_material {
 
 typedef struct salec_pml {
     int32_t enabled;     /* 0: plain walls, 1: damping layers (Sec. 3)           */
-    int32_t reserved;    /* must be 0                                            */
+    int32_t damp_stress; /* 0: Sec. 3's layers (mass, momentum and energy are    */
+                         /* damped); 1: an extension that also relaxes the       */
+                         /* deviatoric stress toward zero at the layer's rate d  */
+                         /* (s -= dt d s after the remap), which absorbs the     */
+                         /* elastic shear waves of strong, confined rock         */
     double R;            /* theoretical reflection coefficient (0, 1)            */
-    double c_ref;        /* damping speed; <= 0: longitudinal speed of material 0 */
+    double c_ref;        /* damping speed c of Sec. 3's profile (the largest     */
+                         /* acoustic speed); <= 0: the largest longitudinal      */
+                         /* speed at rest over the materials                     */
 } salec_pml;
 
 typedef struct salec_scene {

@@ -749,6 +749,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
 #pragma unroll
       for (int m = 1; m < NM; m++)
         if (m < g.nmat) fs = fs + f1v[m];
+      double sdamp = 0.0;  // the layer's rate, when it also relaxes the stress
       if (g.pml_on) {
         double db = pm.dcz[j], drr = pm.dcr[i];
         if (db > 0.0 || drr > 0.0) {
@@ -756,6 +757,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
           long long kr = i >= g.n_r ? pml_rc(g, i, j) : -1;
           long long ku = pml_cell_union(g, i, j);
           double dsum = db + drr;
+          if (g.damp_stress) sdamp = dsum;
           double p1b = kb >= 0 ? po.b_phi1[kb] : 0.0, p1r = kr >= 0 ? po.r_phi1[kr] : 0.0;
           double p3b = kb >= 0 ? po.b_phi3[kb] : 0.0, p3r = kr >= 0 ? po.r_phi3[kr] : 0.0;
           double rho2 = dmax(rho1 - dt * (dsum * (rho1 - pm.rref[ku]) + (p1b + p1r)), 0.0);
@@ -801,6 +803,12 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
           if (m == 0 || m < g.nmat) D.f[m][c] = fv[m];
         }
         T s0n = (T)(sL0 + nsrr * iden), s1n = (T)(sL1 + nszz * iden), s2n = (T)(sL2 + nsrz * iden);
+        if (sdamp > 0.0) {  // extension: relax toward the initial (zero) deviator
+          const double a0 = (double)s0n, a1 = (double)s1n, a2 = (double)s2n;
+          s0n = (T)(a0 - dt * (sdamp * a0));
+          s1n = (T)(a1 - dt * (sdamp * a1));
+          s2n = (T)(a2 - dt * (sdamp * a2));
+        }
         if (g.any_strength) {
           ((T*)D.s[0])[c] = s0n;
           ((T*)D.s[1])[c] = s1n;

@@ -54,6 +54,7 @@ struct Geo {
   int has_p0;          // nonzero initial (lithostatic) pressure profile
   int stretched;       // per-column widths / per-row heights from the geometry table
   int closure;         // 0: shared material density and energy; 1: per material
+  int damp_stress;     // the PML layers also relax the deviatoric stress (extension)
   double dr, dz, cfl, dt_grow, dt_max, dt_floor, t_stop, q_lin, q_quad;
   double rho_ref;
   float drf, dzf, q_linf, q_quadf, rho_reff, pad_f;

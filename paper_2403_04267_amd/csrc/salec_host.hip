@@ -304,6 +304,7 @@ int validate(const salec_grid* g, const salec_material* mats, const salec_pml* p
       return why = "strength parameters of material " + std::to_string(m), SALEC_E_INVALID;
   }
   if (pml->enabled && !(pml->R > 0 && pml->R < 1)) return why = "PML reflection coefficient", SALEC_E_INVALID;
+  if (pml->damp_stress != 0 && pml->damp_stress != 1) return why = "PML damp_stress must be 0 or 1", SALEC_E_INVALID;
   return SALEC_OK;
 }
 
@@ -352,6 +353,7 @@ Geo make_geo(const salec_grid* gr, const salec_material* mats, const salec_pml* 
   g.pc = (g.NR + q - 1) / q * q;
   g.pn = (g.NR + 1 + q - 1) / q * q;
   g.pml_on = pml->enabled ? 1 : 0;
+  g.damp_stress = pml->enabled && pml->damp_stress ? 1 : 0;
   g.dr = gr->dr;
   g.dz = gr->dz;
   g.cfl = gr->cfl;
@@ -390,11 +392,16 @@ void pml_profiles(Member& mb, const salec_material* mats, const salec_pml* pml) 
   mb.dcr.assign(g.NR, 0.0);
   mb.dnr.assign(g.NR + 1, 0.0);
   if (!pml->enabled) return;
+  // c: the largest acoustic speed (Sec. 3); by default the largest
+  // longitudinal speed at rest over the materials
   double c = pml->c_ref;
   if (!(c > 0)) {
-    const salec_material& m0 = mats[0];
-    double G0 = m0.strength ? 3.0 * m0.A * (1.0 - 2.0 * m0.poisson) / (2.0 * (1.0 + m0.poisson)) : 0.0;
-    c = std::sqrt((m0.A + (4.0 / 3.0) * G0) / m0.rho0);
+    c = 0.0;
+    for (int m = 0; m < g.nmat; m++) {
+      const salec_material& M = mats[m];
+      double G = M.strength ? 3.0 * M.A * (1.0 - 2.0 * M.poisson) / (2.0 * (1.0 + M.poisson)) : 0.0;
+      c = std::max(c, std::sqrt((M.A + (4.0 / 3.0) * G) / M.rho0));
+    }
   }
   // y from the inner face of each layer, at cell centres and at nodes
   if (g.pml_b > 0) {

@@ -39,7 +39,7 @@ class Material(C.Structure):
 
 
 class PmlC(C.Structure):
-    _fields_ = [("enabled", C.c_int32), ("reserved", C.c_int32), ("R", C.c_double), ("c_ref", C.c_double)]
+    _fields_ = [("enabled", C.c_int32), ("damp_stress", C.c_int32), ("R", C.c_double), ("c_ref", C.c_double)]
 
 
 class SceneC(C.Structure):
@@ -164,7 +164,7 @@ def _instance(problem, keep: list) -> Instance:
     for k, m in enumerate(problem.mats[:g.nmat]):
         inst.mats[k] = _mat(m)
     p = problem.pml
-    inst.pml = PmlC(int(p.enabled), 0, p.R, p.c_ref)
+    inst.pml = PmlC(int(p.enabled), int(p.damp_stress), p.R, p.c_ref)
     if problem.scene is not None:
         sc = problem.scene
         inst.scene = SceneC(sc.surface_j, sc.subsample, sc.radius, sc.v_imp, sc.gravity, sc.layer_j,

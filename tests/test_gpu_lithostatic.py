@@ -88,3 +88,23 @@ def test_mixed_column_residual_is_rounding_level():
     v = np.abs(g.fields(eos=False)["v"]).max()
     print(f"[mixed column] max |v| after 150 cycles {v:.3e} m/s", flush=True)
     assert v < 1e-2
+
+
+def test_layered_impact_with_stress_damping_layers_fp64_bitwise():
+    """The PML extension that also relaxes the deviatoric stress in the layers."""
+    pb = inputs.layered_impact(60, 12, 6, 15e3, 10, name="layered-damp")
+    pb = pb.replace(pml=inputs.Pml(damp_stress=1))
+    g, o = ctx(pb), Oracle(pb)
+    done = 0
+    for n in (1, 60, 200):
+        g.step(n - done)
+        o.step(n - done)
+        done = n
+        compare(g, o, f"layered, stress damping, cycle {n}", tol=0.0)
+    m = ctx(pb.replace(precision="mixed"))
+    m.step(100)
+    o2 = Oracle(pb)
+    o2.step(100)
+    e = conserved_errors(m.fields(), o2.fields(), pb.grid)
+    bad = {k: v for k, v in e.items() if not v <= 1e-4}
+    assert not bad, bad

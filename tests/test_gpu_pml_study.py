@@ -27,17 +27,36 @@ def test_pml_brings_the_interior_close_to_the_large_domain():
 
 
 def test_pml_in_the_paper_setting():
-    """Sec. 4's setting on Table 2's grid (two layers, gravity) at 20 s, when
-    the shock has reached the bottom boundary: against a reference whose
-    extension zones reach ~200 km further, the PML run's target is within a
-    fraction of a percent while plain walls send back measurable energy."""
+    """Sec. 4's setting on Table 2's grid (calcite, granite, dunite, gravity)
+    at 30 s, when the shock has passed the bottom boundary, against a
+    reference whose extension zones reach ~200 km further; compared away from
+    the crater (further than 60 km from the impact point), where what the
+    boundaries send back shows.
+
+    Sec. 3's layers damp mass, momentum and energy. Without strength they
+    send back next to nothing; with Table 1's strength under a lithostatic
+    column the deep rock stays elastic and its shear stress, which the layers
+    leave undamped, returns part of the energy. The extension that also
+    relaxes the deviatoric stress in the layers absorbs it."""
     from paper_2403_04267_amd.pml_study import PaperSetup, paper_run
-    r = paper_run(PaperSetup(t_end=20.0))
-    for k in ("pml", "bare", "ref"):
-        print(k, r[k], flush=True)
-        assert r[k]["t"] == pytest.approx(20.0, rel=1e-9)
-    e_pml, e_bare = r["pml"]["err_vs_ref"], r["bare"]["err_vs_ref"]
-    assert e_bare["reflected_energy"] > 1e-3
-    assert e_pml["reflected_energy"] < 1e-2 * e_bare["reflected_energy"], (e_pml, e_bare)
-    assert e_pml["dp"] < 0.2 * e_bare["dp"], (e_pml, e_bare)
-    assert r["pml"]["cells"] < 0.65 * r["ref"]["cells"]
+    res = {}
+    for name, kw in (("paper", {}), ("damp_stress", {"damp_stress": 1}), ("hydro", {"strength": False})):
+        r = paper_run(PaperSetup(t_end=30.0, **kw))
+        for k in ("pml", "bare", "ref"):
+            print(name, k, {q: r[k][q] for q in ("cells", "cycles", "t", "device_ms")},
+                  r[k].get("err_vs_ref_far"), flush=True)
+            assert r[k]["t"] == pytest.approx(30.0, rel=1e-9)
+        res[name] = (r["pml"]["err_vs_ref_far"], r["bare"]["err_vs_ref_far"])
+        assert r["pml"]["cells"] < 0.65 * r["ref"]["cells"]
+    e_pml, e_bare = res["paper"]
+    assert e_bare["reflected_energy"] > 1e-3  # the walls' reflections are in the target
+    assert e_pml["reflected_energy"] < 0.3 * e_bare["reflected_energy"], (e_pml, e_bare)
+    assert e_pml["dp"] < 0.6 * e_bare["dp"], (e_pml, e_bare)
+    d_pml, d_bare = res["damp_stress"]
+    assert d_bare == e_bare  # plain walls do not depend on the layers' form
+    assert d_pml["reflected_energy"] < 0.02 * d_bare["reflected_energy"], (d_pml, d_bare)
+    assert d_pml["reflected_energy"] < 0.1 * e_pml["reflected_energy"], (d_pml, e_pml)
+    assert d_pml["dp"] < 0.2 * d_bare["dp"], (d_pml, d_bare)
+    h_pml, h_bare = res["hydro"]
+    assert h_bare["reflected_energy"] > 1e-4
+    assert h_pml["reflected_energy"] < 1e-4 * h_bare["reflected_energy"], (h_pml, h_bare)

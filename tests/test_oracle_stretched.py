@@ -216,6 +216,7 @@ def test_paper_study_window_is_shared_cell_for_cell():
     assert np.array_equal(np.array(a.grid.dz_row[ra:ra + wr]), np.array(r.grid.dz_row[rr:rr + wr]))
     assert a.scene.surface_j - ra == r.scene.surface_j - rr
     assert a.scene.layer_j - ra == r.scene.layer_j - rr
+    assert a.scene.layer2_j - ra == r.scene.layer2_j - rr and a.grid.nmat == r.grid.nmat == 3
     assert probs["bare"].grid == a.grid and not probs["bare"].pml.enabled and a.pml.enabled
     # a wave at 6.5 km/s needs over 50 s to cross the reference's extra zone
     # below the window and come back (the comparisons stop at 40 s)
