@@ -109,6 +109,28 @@ def traffic_per_launch(schedule):
     return None
 
 
+# VALU issue peak of the chip: 256 CUs x 4 SIMDs, one wave64 FP64/FP32 VALU
+# instruction per SIMD every 4 cycles at 2.4 GHz, 64 lanes each (the FMA of
+# the published 78.6 TFLOP/s FP64 vector peak counts as 2 of its flops).
+VALU_LANE_OPS_PEAK = 256 * 4 * 2.4e9 / 4 * 64
+
+
+def valu_per_launch(schedule):
+    """VALU instructions per cycle-kernel launch (SQ_INSTS_VALU, wave64
+    instructions, recorded with the traffic records), if taken from the
+    current kernel sources and the schedule being timed."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh).get("valu")
+    except (OSError, ValueError, AttributeError):
+        return None
+    if not rec or rec.get("kernel_sources_sha256") != kernel_sources_sha():
+        return None
+    if not all(schedule.get(k) == v for k, v in rec.get("schedule", {}).items()):
+        return None
+    return rec.get("sq_insts_valu_per_dispatch")
+
+
 def cpu_baseline(pb, budget_s=12.0):
     from oracle import oracle as O
     from oracle.oracle import Oracle
@@ -272,6 +294,7 @@ def main():
     achieved = bpc * pb.grid.ncells / (k_ms / 1e3) / 1e9
     traffic_b = traffic_per_launch(sch)
     traffic = traffic_b / (k_ms / 1e3) / 1e9 if traffic_b else None
+    valu = valu_per_launch(sch)
     d = ctx.diag()
     del ctx
     torch.cuda.empty_cache()
@@ -290,7 +313,14 @@ def main():
                      "traffic_frac_of_copy": traffic / copy_gbs if traffic else None,
                      "kernel": "k_cycle (one launch = one cycle of the whole grid)",
                      "kernel_ms": k_ms, "kernel_timing_cycles": args.kernel_cycles,
-                     "finalize_ms": f_ms, "bytes_per_cell_update": bpc},
+                     "finalize_ms": f_ms, "bytes_per_cell_update": bpc,
+                     # what bounds this kernel in practice: VALU issue (counted
+                     # instructions, halo recomputation included) and latency
+                     "valu_issue": None if not valu else {
+                         "lane_ops_per_cell_update": valu * 64 / pb.grid.ncells,
+                         "achieved_lane_ops_per_s": valu * 64 / (k_ms / 1e3),
+                         "peak_lane_ops_per_s": VALU_LANE_OPS_PEAK,
+                         "frac": valu * 64 / (k_ms / 1e3) / VALU_LANE_OPS_PEAK}},
         "schedule": sch,
         "median_of_5": {"value": rates[2], "min": rates[0], "max": rates[4],
                         "note": "the timed cycles as 5 consecutive calls; value is over all of them"},
