@@ -280,3 +280,111 @@ def paper_run(s: PaperSetup = PaperSetup(), device: str = "cuda:0", chunk: int =
 if __name__ == "__main__":
     import json
     print(json.dumps(run(), indent=1))
+
+
+# --------------------------------------------------------------------------
+# crater profiles in the paper's setting (Sec. 4 compares them over time)
+# --------------------------------------------------------------------------
+def _level_from_top(x, zc, level=0.5):
+    """Per column: the height where x first reaches `level` scanning down
+    from the top (linear between cell centres zc); NaN where it never does."""
+    nz, nr = x.shape
+    out = np.full(nr, np.nan)
+    for i in range(nr):
+        col = x[:, i]
+        hit = np.nonzero(col >= level)[0]
+        if hit.size == 0:
+            continue
+        j = hit[-1]
+        if j == nz - 1:
+            out[i] = zc[j]
+            continue
+        a, b = col[j], col[j + 1]
+        out[i] = zc[j] + (a - level) / (a - b) * (zc[j + 1] - zc[j])
+    return out
+
+
+def _level_from_bottom(x, zc, level=0.5):
+    """Per column: the height where x first reaches `level` scanning up from
+    the bottom; NaN where it never does."""
+    nz, nr = x.shape
+    out = np.full(nr, np.nan)
+    for i in range(nr):
+        col = x[:, i]
+        hit = np.nonzero(col >= level)[0]
+        if hit.size == 0:
+            continue
+        j = hit[0]
+        if j == 0:
+            out[i] = zc[0]
+            continue
+        a, b = col[j - 1], col[j]
+        out[i] = zc[j - 1] + (level - a) / (b - a) * (zc[j] - zc[j - 1])
+    return out
+
+
+def paper_profiles(times=(10.0, 30.0, 60.0), r_crater_km: float = 60.0, r_inner_km: float = 35.0,
+                   r_moho_km: float = 100.0,
+                   device: str = "cuda:0", bare_until: float = 30.0, chunk: int = 500,
+                   max_cycles: int = 200000, **setup) -> dict:
+    """The crater surface (matter fraction 0.5 from below) and the base of
+    the granite crust (granite fraction 0.5 from below: the crust-mantle
+    boundary, unaffected by the dunite projectile in the crater floor) of the
+    PML run and of the reference with ~200 km longer extension zones, at each
+    time, within r_crater_km (and inside the rim, r_inner_km) and r_moho_km of
+    the axis; largest, mean and median absolute differences in metres (the
+    largest sit at the rim, where an overturned flap makes any level reading
+    fragile). Plain walls too up to bare_until (later
+    their trapped reflections collapse the time step)."""
+    from .salec import Salec
+    out = {}
+    for t in times:
+        s = PaperSetup(t_end=float(t), **setup)
+        probs, rows, wc, wr = paper_problems(s)
+        keys = ("pml", "ref", "bare") if t <= bare_until else ("pml", "ref")
+        prof = {}
+        for key in keys:
+            pb = probs[key]
+            ctx = Salec(pb, device)
+            cycles = 0
+            while ctx.diag()["t"] < s.t_end * (1.0 - 1e-12) and cycles < max_cycles:
+                ctx.step(chunk)
+                cycles += chunk
+            F = ctx.fields(eos=False)
+            del ctx
+            g = pb.grid
+            r0 = rows[key]
+            zn = np.concatenate([[0.0], np.cumsum(g.dz_row)])
+            zs = zn[pb.scene.surface_j]
+            zc = 0.5 * (zn[1:] + zn[:-1])[r0:r0 + wr] - zs  # heights relative to the original surface
+            f = F["f"][:, r0:r0 + wr, :wc]
+            # the target's surface: matter fraction 0.5 scanning up from the
+            # bottom, so that ejecta in flight over the cavity do not count
+            prof[key] = {"crater": _level_from_bottom(1.0 - f.sum(axis=0), zc),
+                         "moho": _level_from_bottom(f[1], zc) if pb.grid.nmat == 3 else None}
+        g = probs["pml"].grid
+        rn = np.concatenate([[0.0], np.cumsum(g.dr_col)])[:wc + 1]
+        rc = 0.5 * (rn[1:] + rn[:-1])
+        res = {}
+        for key in keys:
+            if key == "ref":
+                continue
+            d = {}
+            for name, src, rmax in (("crater", "crater", r_crater_km), ("crater_inner", "crater", r_inner_km),
+                                    ("moho", "moho", r_moho_km)):
+                a, b = prof[key][src], prof["ref"][src]
+                if a is None:
+                    continue
+                sel = (rc <= rmax * 1e3) & np.isfinite(a) & np.isfinite(b)
+                diff = np.abs(a[sel] - b[sel])
+                d[name] = {"max_m": float(diff.max()), "mean_m": float(diff.mean()),
+                           "median_m": float(np.median(diff)), "r_at_max_km": float(rc[sel][np.argmax(diff)] / 1e3)}
+            res[key] = d
+        ref = prof["ref"]
+        sel = rc <= r_crater_km * 1e3
+        res["ref_crater_depth_m"] = float(-np.nanmin(ref["crater"][sel]))
+        if ref["moho"] is not None:
+            m = ref["moho"][rc <= r_moho_km * 1e3]
+            res["ref_moho_uplift_m"] = float(np.nanmax(m) - np.nanmedian(m[-20:]))
+        out[f"{t:g}s"] = res
+    return out

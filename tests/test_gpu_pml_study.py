@@ -60,3 +60,26 @@ def test_pml_in_the_paper_setting():
     h_pml, h_bare = res["hydro"]
     assert h_bare["reflected_energy"] > 1e-4
     assert h_pml["reflected_energy"] < 1e-4 * h_bare["reflected_energy"], (h_pml, h_bare)
+
+
+def test_crater_and_crust_base_profiles_in_the_paper_setting():
+    """Sec. 4 compares crater profiles over time (within 1400 m, 3.5 cells).
+    Against the reference with ~200 km longer extension zones, the PML run's
+    crater surface (matter fraction 0.5 from below) and crust base (granite
+    fraction 0.5 from below) are the reference's exactly at 30 s, before the
+    layers return anything, while plain walls have already moved the crater
+    floor; at 60 s they stay within the paper's 1400 m, closer with the
+    stress-damping extension."""
+    from paper_2403_04267_amd.pml_study import paper_profiles
+    a = paper_profiles(times=(30.0, 60.0))
+    b = paper_profiles(times=(60.0,), damp_stress=1)
+    print("Sec. 3 layers", a, flush=True)
+    print("stress damping", b, flush=True)
+    p30 = a["30s"]
+    assert p30["pml"]["crater"]["max_m"] < 1.0 and p30["pml"]["moho"]["max_m"] < 1.0
+    assert p30["bare"]["crater_inner"]["max_m"] > 100.0
+    p60, d60 = a["60s"]["pml"], b["60s"]["pml"]
+    assert p60["crater_inner"]["median_m"] < 400.0 and p60["crater_inner"]["mean_m"] < 1400.0
+    assert p60["moho"]["max_m"] < 400.0
+    assert d60["crater"]["max_m"] < 1400.0 and d60["moho"]["max_m"] < 100.0
+    assert d60["crater_inner"]["mean_m"] < p60["crater_inner"]["mean_m"]
