@@ -13,7 +13,11 @@ kernel's own mean duration is measured over further cycles launched between
 HIP events; the roofline uses it.
 
 Also measured (the "extensions" object; skipped with --headline-only):
-  mixed_scale    the same workload in the mixed-precision mode
+  mixed_scale    the same workload in the mixed-precision mode (with its error
+                 against a plain-FP64 GPU run: conserved densities at cycle 200,
+                 crater level at cycle 2000; likewise for mixed_large, and the
+                 per-member crater level of 64 sampled members for
+                 batched_mixed)
   mixed_large    4000 x 4000 + 100 PML (4100^2 cells), mixed precision
   batched_fp64   256 seeded uneven impacts (sides 200-800), plain FP64
   batched_mixed  1024 seeded uneven impacts (sides 200-1200), mixed
@@ -215,6 +219,56 @@ def extension(name, problems, steps, warmup, tune, fp64_rate=None):
     return out
 
 
+def mixed_accuracy(pb64, early=200, late=2000):
+    """The mixed mode against plain FP64 on the GPU, same problem from the same
+    start: relative L2 errors of the conserved densities at cycle `early`
+    (rho, rho I, phi p, f, phi s, node momentum) and the crater level on the
+    axis at cycle `late`, in cells."""
+    import torch
+    from paper_2403_04267_amd.salec import Salec
+    from tests.crater import conserved_errors, crater_depth
+    a, b = Salec(pb64), Salec(pb64.replace(precision="mixed"))
+    a.step(early)
+    b.step(early)
+    e = conserved_errors(b.fields(), a.fields(), pb64.grid)
+    a.step(late - early)
+    b.step(late - early)
+    sj = pb64.scene.surface_j
+    da = crater_depth(a.fields(eos=False)["f"], pb64.grid, sj)
+    db = crater_depth(b.fields(eos=False)["f"], pb64.grid, sj)
+    del a, b
+    torch.cuda.empty_cache()
+    return {"against": "plain-FP64 GPU run (bit for bit the oracle at every size the oracle runs)",
+            "cycles": early, "rel_l2": e, "rel_l2_max": max(e.values()),
+            "late_cycles": late, "crater_level_diff_cells": abs(da - db) / pb64.grid.dz}
+
+
+def ensemble_accuracy(cycles=1000):
+    """64 members sampled (every 16th) from the 1024-member ensemble, mixed
+    against plain FP64 after `cycles` cycles: per-member difference of the
+    crater level on the axis, in cells."""
+    import numpy as np
+    import torch
+    from paper_2403_04267_amd import inputs
+    from paper_2403_04267_amd.salec import Salec
+    from tests.crater import crater_depth
+    sample = inputs.ensemble(4267, 1024, 200, 1200)[::16]
+    a, b = Salec(sample), Salec([p.replace(precision="mixed") for p in sample])
+    a.step(cycles)
+    b.step(cycles)
+    d = []
+    for k, pb in enumerate(sample):
+        sj = pb.scene.surface_j
+        d.append(abs(crater_depth(a.fields(eos=False, k=k)["f"], pb.grid, sj) -
+                     crater_depth(b.fields(eos=False, k=k)["f"], pb.grid, sj)) / pb.grid.dz)
+    del a, b
+    torch.cuda.empty_cache()
+    d = np.array(d)
+    return {"against": "plain-FP64 GPU batch", "members": len(d), "cycles": cycles,
+            "crater_level_diff_cells": {"max": float(d.max()), "mean": float(d.mean()),
+                                        "median": float(np.median(d)), "within_1": int((d <= 1).sum())}}
+
+
 def pml_payoff():
     """The PML payoff study: the 100x100 hydrodynamic impact (R = 10 cells,
     10 km/s) with a 20-cell PML, with plain walls, and on a 1000x1000 domain,
@@ -332,10 +386,13 @@ def main():
         ext = {}
         ext["mixed_scale"] = extension("mixed 1050^2", pb.replace(precision="mixed"), args.steps,
                                        args.warmup, args.tune, value)
+        ext["mixed_scale"]["accuracy"] = mixed_accuracy(pb.replace(precision="fp64"))
         ext["mixed_large"] = extension("mixed 4100^2", inputs.config_large("mixed"), 200, 10, 1)
+        ext["mixed_large"]["accuracy"] = mixed_accuracy(inputs.config_large("fp64"))
         ext["batched_fp64"] = extension("batched 256 fp64", inputs.ensemble(2403, 256, 200, 800), 40, 2, 1)
         ext["batched_mixed"] = extension("batched 1024 mixed",
                                          inputs.ensemble(4267, 1024, 200, 1200, precision="mixed"), 10, 1, 1)
+        ext["batched_mixed"]["accuracy"] = ensemble_accuracy()
         ext["layered_fp64"] = extension("layered 1050^2 fp64",
                                         inputs.layered_impact(1000, 50, 50, 15e3, 70, name="layered"), 500, 20,
                                         args.tune, value)
