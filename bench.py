@@ -15,9 +15,10 @@ HIP events; the roofline uses it.
 Also measured (the "extensions" object; skipped with --headline-only):
   mixed_scale    the same workload in the mixed-precision mode (with its error
                  against a plain-FP64 GPU run: conserved densities at cycle 200,
-                 crater level at cycle 2000; likewise for mixed_large, and the
-                 per-member crater level of 64 sampled members for
-                 batched_mixed)
+                 crater level at cycle 2000, also for a run started in FP64
+                 and handed to the mixed mode at cycle 40; likewise for
+                 mixed_large, and the per-member crater level of 64 sampled
+                 members for batched_mixed)
   mixed_large    4000 x 4000 + 100 PML (4100^2 cells), mixed precision
   batched_fp64   256 seeded uneven impacts (sides 200-800), plain FP64
   batched_mixed  1024 seeded uneven impacts (sides 200-1200), mixed
@@ -219,28 +220,37 @@ def extension(name, problems, steps, warmup, tune, fp64_rate=None):
     return out
 
 
-def mixed_accuracy(pb64, early=200, late=2000):
+def mixed_accuracy(pb64, early=200, late=2000, hand=40):
     """The mixed mode against plain FP64 on the GPU, same problem from the same
     start: relative L2 errors of the conserved densities at cycle `early`
     (rho, rho I, phi p, f, phi s, node momentum) and the crater level on the
-    axis at cycle `late`, in cells."""
+    axis at cycle `late`, in cells. The same for a run that starts in FP64 and
+    continues in the mixed mode from cycle `hand` (fields, PML auxiliaries and
+    clock handed over between contexts)."""
     import torch
     from paper_2403_04267_amd.salec import Salec
     from tests.crater import conserved_errors, crater_depth
     a, b = Salec(pb64), Salec(pb64.replace(precision="mixed"))
-    a.step(early)
-    b.step(early)
-    e = conserved_errors(b.fields(), a.fields(), pb64.grid)
-    a.step(late - early)
-    b.step(late - early)
+    a.step(hand)
+    b.step(hand)
+    c = Salec(pb64.replace(precision="mixed"))
+    c.continue_from(a)
+    for x in (a, b, c):
+        x.step(early - hand)
+    Fa = a.fields()
+    e, ec = conserved_errors(b.fields(), Fa, pb64.grid), conserved_errors(c.fields(), Fa, pb64.grid)
+    del Fa
+    for x in (a, b, c):
+        x.step(late - early)
     sj = pb64.scene.surface_j
-    da = crater_depth(a.fields(eos=False)["f"], pb64.grid, sj)
-    db = crater_depth(b.fields(eos=False)["f"], pb64.grid, sj)
-    del a, b
+    da, db, dc = (crater_depth(x.fields(eos=False)["f"], pb64.grid, sj) for x in (a, b, c))
+    del a, b, c
     torch.cuda.empty_cache()
     return {"against": "plain-FP64 GPU run (bit for bit the oracle at every size the oracle runs)",
             "cycles": early, "rel_l2": e, "rel_l2_max": max(e.values()),
-            "late_cycles": late, "crater_level_diff_cells": abs(da - db) / pb64.grid.dz}
+            "late_cycles": late, "crater_level_diff_cells": abs(da - db) / pb64.grid.dz,
+            "fp64_start": {"hand_over_cycle": hand, "rel_l2": ec, "rel_l2_max": max(ec.values()),
+                           "crater_level_diff_cells": abs(da - dc) / pb64.grid.dz}}
 
 
 def ensemble_accuracy(cycles=1000):

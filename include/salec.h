@@ -227,6 +227,28 @@ int salec_set_fields(salec_ctx *ctx, int32_t instance, const salec_fields *in);
  *   node_aux 8*(NZ+1)*(NR+1): phi2_b (r, z), psi1_b (r, z), phi2_r (r, z), psi1_r (r, z) */
 int salec_get_pml(salec_ctx *ctx, int32_t instance, double *cell_aux, double *node_aux);
 
+/* Continuing a run in another context (same problem, possibly another
+ * precision), e.g. an FP64 start handed to the mixed mode. The state of the
+ * scheme between cycles (Sec. 2's staggered fields, the auxiliary fields of
+ * Sec. 3's PML and the clock) is: salec_get_fields (eos = NULL), with
+ * salec_get_materials under the per-material closure, salec_get_pml and
+ * salec_diag's t and dt. Restore it in this order: salec_set_fields,
+ * salec_set_materials (per-material closure), salec_set_pml, salec_set_clock.
+ * An FP64 member continued this way repeats the uninterrupted run bit for bit;
+ * the cycle counter and the outflow budgets restart from zero.
+ *
+ * salec_set_pml writes the current level of member `instance`'s PML
+ * auxiliaries, reference density and sink from the layouts salec_get_pml
+ * returns (entries outside the layers are ignored; a NULL array leaves its
+ * group unchanged; nothing happens without a PML). SALEC_E_INVALID if an
+ * entry inside the layers is not finite.
+ *
+ * salec_set_clock sets the member's time t and the step dt of its next cycle
+ * (salec_diag's t and dt). SALEC_E_INVALID unless t >= 0 and 0 < dt <=
+ * dt_max, and, with a stop time, dt <= t_stop - t. */
+int salec_set_pml(salec_ctx *ctx, int32_t instance, const double *cell_aux, const double *node_aux);
+int salec_set_clock(salec_ctx *ctx, int32_t instance, double t, double dt);
+
 /* Checkpoint: the whole device state of every member (fields, EoS cache,
  * PML, budgets, t, dt, cycle, errors). */
 size_t salec_state_bytes(const salec_ctx *ctx);

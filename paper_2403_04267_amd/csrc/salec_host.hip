@@ -1064,6 +1064,104 @@ int salec_get_pml(salec_ctx* x, int32_t k, double* ca, double* na) {
   return SALEC_OK;
 }
 
+int salec_set_pml(salec_ctx* x, int32_t k, const double* ca, const double* na) {
+  if (!member_ok(x, k)) return SALEC_E_INVALID;
+  HIPCHK(x, hipStreamSynchronize(x->st));
+  Member& mb = x->ms[k];
+  const Geo& g = mb.g;
+  if (!g.pml_on) return SALEC_OK;
+  size_t NC = (size_t)g.NR * g.NZ, NN = (size_t)(g.NR + 1) * (g.NZ + 1);
+  const Pml& pm = mb.d.pm;
+  const PmlAux& au = pm.a[read_scal(x, k).cycle & 1];
+  size_t nbc = (size_t)g.pml_b * g.NR, nrc = (size_t)g.NZ * g.pml_r, nu = nbc + (size_t)g.n_z * g.pml_r;
+  size_t nbn = (size_t)g.pml_b * (g.NR + 1), nrn = (size_t)(g.NZ + 1) * g.pml_r;
+  // the layouts of salec_get_pml gathered back into the strips; everything
+  // is checked before anything is written
+  std::vector<double> hc[8], hn[8];
+  if (ca) {
+    for (int q = 0; q < 3; q++) {
+      hc[q].assign(nbc, 0.0);
+      hc[3 + q].assign(nrc, 0.0);
+    }
+    hc[6].assign(nu, 0.0);
+    hc[7].assign(nu, 0.0);
+    for (int j = 0; j < g.NZ; j++)
+      for (int i = 0; i < g.NR; i++) {
+        size_t c = (size_t)j * g.NR + i;
+        if (j < g.pml_b)
+          for (int q = 0; q < 3; q++) hc[q][(size_t)j * g.NR + i] = ca[q * NC + c];
+        if (i >= g.n_r)
+          for (int q = 0; q < 3; q++) hc[3 + q][(size_t)j * g.pml_r + (i - g.n_r)] = ca[(3 + q) * NC + c];
+        long long u = -1;
+        if (j < g.pml_b) u = (long long)j * g.NR + i;
+        else if (i >= g.n_r) u = (long long)nbc + (long long)(j - g.pml_b) * g.pml_r + (i - g.n_r);
+        if (u >= 0) {
+          hc[6][u] = ca[6 * NC + c];
+          hc[7][u] = ca[7 * NC + c];
+        }
+      }
+  }
+  if (na) {
+    for (int q = 0; q < 4; q++) {
+      hn[q].assign(nbn, 0.0);
+      hn[4 + q].assign(nrn, 0.0);
+    }
+    for (int j = 0; j <= g.NZ; j++)
+      for (int i = 0; i <= g.NR; i++) {
+        size_t n = (size_t)j * (g.NR + 1) + i;
+        if (j < g.pml_b)
+          for (int q = 0; q < 4; q++) hn[q][(size_t)j * (g.NR + 1) + i] = na[q * NN + n];
+        if (i > g.n_r)
+          for (int q = 0; q < 4; q++) hn[4 + q][(size_t)j * g.pml_r + (i - g.n_r - 1)] = na[(4 + q) * NN + n];
+      }
+  }
+  for (int t = 0; t < 8; t++)
+    for (const std::vector<double>* h : {&hc[t], &hn[t]})
+      for (double v : *h)
+        if (!std::isfinite(v)) {
+          x->err = "PML auxiliaries not finite";
+          return SALEC_E_INVALID;
+        }
+  auto put = [&](double* dev, const std::vector<double>& h) -> int {
+    if (dev && !h.empty()) HIPCHK(x, hipMemcpy(dev, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+    return SALEC_OK;
+  };
+  if (ca) {
+    double* b[3] = {au.b_phi1, au.b_phi3, au.b_psi2};
+    double* r[3] = {au.r_phi1, au.r_phi3, au.r_psi2};
+    for (int q = 0; q < 3; q++)
+      if (put(b[q], hc[q]) || put(r[q], hc[3 + q])) return SALEC_E_HIP;
+    if (put(pm.rref, hc[6]) || put(pm.msink, hc[7])) return SALEC_E_HIP;
+  }
+  if (na) {
+    double* b[4] = {au.b_phi2r, au.b_phi2z, au.b_psi1r, au.b_psi1z};
+    double* r[4] = {au.r_phi2r, au.r_phi2z, au.r_psi1r, au.r_psi1z};
+    for (int q = 0; q < 4; q++)
+      if (put(b[q], hn[q]) || put(r[q], hn[4 + q])) return SALEC_E_HIP;
+  }
+  return SALEC_OK;
+}
+
+int salec_set_clock(salec_ctx* x, int32_t k, double t, double dt) {
+  if (!member_ok(x, k)) return SALEC_E_INVALID;
+  const Geo& g = x->ms[k].g;
+  if (!std::isfinite(t) || t < 0.0 || !std::isfinite(dt) || !(dt > 0.0) || dt > g.dt_max) {
+    x->err = "clock needs t >= 0 and 0 < dt <= dt_max";
+    return SALEC_E_INVALID;
+  }
+  if (g.t_stop > 0 && dt > g.t_stop - t) {
+    x->err = "time step passes the stop time";
+    return SALEC_E_INVALID;
+  }
+  HIPCHK(x, hipStreamSynchronize(x->st));
+  Scal s = read_scal(x, k);
+  s.t = t;
+  s.dt = dt;
+  HIPCHK(x, hipMemcpyAsync(x->ms[k].d.sc, &s, sizeof(Scal), hipMemcpyHostToDevice, x->st));
+  HIPCHK(x, hipStreamSynchronize(x->st));
+  return SALEC_OK;
+}
+
 size_t salec_state_bytes(const salec_ctx* x) {
   if (!x || !x->ready) return 0;
   return 32 + x->L.persist_bytes;

@@ -103,6 +103,8 @@ def load() -> C.CDLL:
     lib.salec_get_fields.argtypes = [P, I32, C.POINTER(Fields)]
     lib.salec_set_fields.argtypes = [P, I32, C.POINTER(Fields)]
     lib.salec_get_pml.argtypes = [P, I32, _DP, _DP]
+    lib.salec_set_pml.argtypes = [P, I32, _DP, _DP]
+    lib.salec_set_clock.argtypes = [P, I32, C.c_double, C.c_double]
     lib.salec_state_bytes.restype = C.c_size_t
     lib.salec_state_bytes.argtypes = [P]
     lib.salec_get_state.argtypes = [P, P, C.c_size_t]
@@ -337,6 +339,35 @@ class Salec:
         out = {n: ca[i] for i, n in enumerate(names_c)}
         out.update({n: na[i] for i, n in enumerate(names_n)})
         return out
+
+    def set_pml(self, aux: dict, k: int = 0):
+        """Writes member k's PML auxiliaries back in the layout pml_aux returns."""
+        NR, NZ, _ = self.dims[k]
+        names_c = ["phi1_b", "phi3_b", "psi2_b", "phi1_r", "phi3_r", "psi2_r", "rho_ref", "msink"]
+        names_n = ["phi2_b_r", "phi2_b_z", "psi1_b_r", "psi1_b_z", "phi2_r_r", "phi2_r_z", "psi1_r_r",
+                   "psi1_r_z"]
+        ca = np.ascontiguousarray(np.stack([np.asarray(aux[n], dtype=np.float64).reshape(NZ, NR)
+                                            for n in names_c]))
+        na = np.ascontiguousarray(np.stack([np.asarray(aux[n], dtype=np.float64).reshape(NZ + 1, NR + 1)
+                                            for n in names_n]))
+        self._check(self.lib.salec_set_pml(self._h, int(k), _ptr(ca.reshape(-1)), _ptr(na.reshape(-1))))
+
+    def set_clock(self, t: float, dt: float, k: int = 0):
+        """Time of member k and the step of its next cycle."""
+        self._check(self.lib.salec_set_clock(self._h, int(k), float(t), float(dt)))
+
+    def continue_from(self, src: "Salec", k_src: int = 0, k: int = 0):
+        """Member k takes over member k_src of context src between cycles:
+        fields, per-material state, PML auxiliaries and clock, each in this
+        context's precision. The problems must be the same up to precision."""
+        F = src.fields(eos=False, k=k_src)
+        self.set_fields(F["rho"], F["I"], F["f"], F["v"], F["s"], k=k)
+        if self.problems[k].grid.closure:
+            M = src.materials(k=k_src)
+            self.set_materials(M["mu"], M["Im"], k=k)
+        self.set_pml(src.pml_aux(k=k_src), k=k)
+        d = src.diag(k=k_src)
+        self.set_clock(d["t"], d["dt"], k=k)
 
     def diag(self, k: int = 0) -> dict:
         d = Diag()

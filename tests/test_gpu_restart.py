@@ -1,0 +1,210 @@
+"""Continuing a run in another context: fields, per-material state, PML
+auxiliaries and clock (salec_set_pml, salec_set_clock).
+
+An FP64 member taken over after an odd number of cycles (its state in the
+second time level, the new context's in the first) and stepped on must equal
+the oracle's uninterrupted run bit for bit: every field, the PML auxiliaries
+(the layers are active at the hand-over), t, dt and the in-grid budgets.
+Covered: an impact with strength, a layered target under gravity, the same
+with stress damping in the layers, the three-layer target under the
+per-material closure, and a stretched grid. A mixed-mode member continued in
+another mixed context equals the uninterrupted mixed run bit for bit.
+
+On the 1050^2 strength impact the mixed mode's error is seeded during the
+first cycles of the contact: an FP64 start handed to the mixed mode after 40
+cycles keeps every conserved density within 1e-4 of the FP64 run at cycle
+200, where the mixed run from t = 0 is past it in the stress.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle
+from paper_2403_04267_amd import inputs
+
+from .crater import conserved_errors
+from .test_gpu_parity import rel_linf
+
+pytestmark = pytest.mark.gpu
+
+
+def ctx(problems):
+    from paper_2403_04267_amd.salec import Salec
+    return Salec(problems)
+
+
+def _pm(pb):
+    return pb.replace(grid=dataclasses.replace(pb.grid, closure=1))
+
+
+def _damped(pb):
+    return pb.replace(pml=dataclasses.replace(pb.pml, damp_stress=1))
+
+
+CASES = {
+    "impact-strength": lambda: inputs.impact(32, 8, 4, 12e3, 2, True, 0, name="impact"),
+    "layered-gravity": lambda: inputs.layered_impact(32, 8, 4, 14e3, 6, name="layered"),
+    "layered-damped": lambda: _damped(inputs.layered_impact(32, 8, 4, 14e3, 6, name="layered-damped")),
+    "three-layer-pm": lambda: _pm(inputs.three_layer_impact(36, 8, 4, 14e3, 3, 6, name="three-layer-pm")),
+    "stretched": lambda: inputs.stretched_impact(24, 6, 6, 3, 12e3, name="stretched"),
+}
+
+N_HAND, N_MORE = 101, 40
+
+
+def layer_mask(o, shape):
+    """Cells of the layers: the library keeps the reference density only there."""
+    g = o.g
+    lay = np.zeros(shape, dtype=bool)
+    lay[: g.pml_b, :] = True
+    lay[:, g.n_r:] = True
+    return lay
+
+
+def bitwise(g, o, pb, label):
+    Fg, Fo = g.fields(), o.fields()
+    errs = {}
+    for k in ("rho", "I", "p", "c2"):
+        errs[k] = rel_linf(Fg[k], Fo[k])
+    for m in range(Fo["f"].shape[0]):
+        errs[f"f{m}"] = rel_linf(Fg["f"][m], Fo["f"][m])
+    for q in range(3):
+        errs[f"s{q}"] = rel_linf(Fg["s"][q], Fo["s"][q])
+    for q in range(2):
+        errs[f"v{q}"] = rel_linf(Fg["v"][q], Fo["v"][q])
+    if pb.grid.closure:
+        Mg, Mo = g.materials(), o.materials()
+        for m in range(Mo["mu"].shape[0]):
+            errs[f"mu{m}"] = rel_linf(Mg["mu"][m], Mo["mu"][m])
+            errs[f"Im{m}"] = rel_linf(Mg["Im"][m], Mo["Im"][m])
+    Ag, Ao = g.pml_aux(), dict(o.pml_aux())
+    lay = layer_mask(o, Ao["rho_ref"].shape)
+    Ao["rho_ref"] = np.where(lay, Ao["rho_ref"], 0.0)
+    for k in Ao:
+        errs["pml." + k] = rel_linf(Ag[k], Ao[k])
+    dg, do = g.diag(), o.diag()
+    assert dg["err"] == 0 and do["err"] == 0, label
+    for k in ("t", "dt", "mass", "ie", "ke", "mass_pml"):
+        errs["diag." + k] = abs(dg[k] - do[k]) / max(abs(do[k]), 1e-300)
+    worst = max(errs, key=errs.get)
+    print(f"[{label}] worst {worst} = {errs[worst]:.3e}", flush=True)
+    bad = {k: v for k, v in errs.items() if not v == 0.0}
+    assert not bad, f"{label}: {bad}"
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_fp64_continuation_equals_the_uninterrupted_oracle_run(case):
+    pb = CASES[case]()
+    a = ctx(pb)
+    a.step(N_HAND)
+    aux = a.pml_aux()
+    active = max(float(np.abs(aux[k]).max()) for k in ("phi1_b", "psi2_b", "phi2_b_z", "psi1_r_r"))
+    print(f"[{case}] hand-over after {N_HAND} cycles, largest PML auxiliary {active:.3e}", flush=True)
+    assert active > 0.0, "the layers must be active at the hand-over"
+    b = ctx(pb)
+    b.step(7)  # a run of its own, replaced by the hand-over
+    b.continue_from(a)
+    assert b.diag()["t"] == a.diag()["t"] and b.diag()["dt"] == a.diag()["dt"]
+    b.step(N_MORE)
+    o = Oracle(pb)
+    o.step(N_HAND + N_MORE)
+    bitwise(b, o, pb, f"{case} continued")
+    assert int(b.diag()["cycle"]) == N_MORE
+
+
+def test_mixed_continuation_equals_the_uninterrupted_mixed_run():
+    pb = inputs.layered_impact(40, 8, 4, 14e3, 6, precision="mixed", name="layered-mixed")
+    a, b = ctx(pb), ctx(pb)
+    a.step(N_HAND)
+    b.continue_from(a)
+    a.step(N_MORE)
+    b.step(N_MORE)
+    Fa, Fb = a.fields(), b.fields()
+    for k in ("rho", "I", "f", "s", "v", "p", "c2"):
+        assert np.array_equal(Fa[k], Fb[k]), k
+    Aa, Ab = a.pml_aux(), b.pml_aux()
+    for k in Aa:
+        assert np.array_equal(Aa[k], Ab[k]), k
+    assert a.diag()["t"] == b.diag()["t"] and a.diag()["dt"] == b.diag()["dt"]
+
+
+def test_continuation_into_a_batch_member():
+    """Member 1 of a two-member batch takes over a single run's member 0."""
+    pb = inputs.impact(32, 8, 4, 12e3, 2, True, 0, name="impact")
+    other = inputs.impact(28, 6, 3, 9e3, 2, True, 0, name="other")
+    a = ctx(pb)
+    a.step(N_HAND)
+    b = ctx([other, pb])
+    b.step(3)
+    b.continue_from(a, k_src=0, k=1)
+    b.step(N_MORE)
+    o = Oracle(pb)
+    o.step(N_HAND + N_MORE)
+
+    class Member:
+        def __init__(self, c, k):
+            self.c, self.k = c, k
+
+        def fields(self):
+            return self.c.fields(k=self.k)
+
+        def pml_aux(self):
+            return self.c.pml_aux(k=self.k)
+
+        def diag(self):
+            return self.c.diag(k=self.k)
+
+        def materials(self):
+            return self.c.materials(k=self.k)
+
+    bitwise(Member(b, 1), o, pb, "batch member 1 continued")
+    o0 = Oracle(other)
+    o0.step(3 + N_MORE)
+    bitwise(Member(b, 0), o0, other, "batch member 0 untouched")
+
+
+def test_clock_and_pml_arguments_are_checked():
+    from paper_2403_04267_amd.salec import SalecError
+    pb = inputs.impact(32, 8, 4, 12e3, 2, True, 0, name="impact")
+    a = ctx(pb)
+    a.step(20)
+    d = a.diag()
+    for t, dt in ((d["t"], 0.0), (d["t"], -1e-6), (-1.0, d["dt"]), (d["t"], float("nan")),
+                  (d["t"], 2 * pb.grid.dt_max)):
+        with pytest.raises(SalecError):
+            a.set_clock(t, dt)
+    aux = a.pml_aux()
+    bad = dict(aux)
+    bad["psi2_b"] = aux["psi2_b"].copy()
+    bad["psi2_b"][0, 0] = np.nan
+    with pytest.raises(SalecError):
+        a.set_pml(bad)
+    # the refused calls changed nothing
+    o = Oracle(pb)
+    o.step(20)
+    bitwise(a, o, pb, "after refused calls")
+    # NaN outside the layers is ignored
+    outside = dict(aux)
+    outside["phi1_b"] = aux["phi1_b"].copy()
+    outside["phi1_b"][-1, 0] = np.nan
+    a.set_pml(outside)
+    a.step(10)
+    o.step(10)
+    bitwise(a, o, pb, "NaN outside the layers ignored")
+
+
+def test_fp64_start_handed_to_mixed_meets_the_bar_on_the_1050_impact():
+    pb = inputs.config_scale()
+    a = ctx(pb)
+    a.step(40)
+    b = ctx(pb.replace(precision="mixed"))
+    b.continue_from(a)
+    a.step(160)
+    b.step(160)
+    assert b.diag()["t"] == pytest.approx(a.diag()["t"], rel=1e-5)
+    e = conserved_errors(b.fields(), a.fields(), pb.grid)
+    print("[1050^2, FP64 for 40 cycles then mixed, cycle 200] " +
+          " ".join(f"{k} {v:.2e}" for k, v in e.items()), flush=True)
+    bad = {k: v for k, v in e.items() if not v <= 1e-4}
+    assert not bad, bad
