@@ -7,9 +7,15 @@ namespace salec {
 // 768-thread tiles run one workgroup per CU at three waves per SIMD (LDS
 // holds one tile); 512-thread tiles are capped at 128 registers so that two
 // workgroups (four waves per SIMD) share a CU where two tiles fit the LDS
-// (the FP32 instantiation); 256-thread tiles run three to a CU. The last
-// shape is built only for the per-material closure and three material slots,
-// whose wider LDS records leave no 768-thread tile of the other sizes room.
+// (the FP32 instantiation); 256-thread tiles run three to a CU. Shape 11 is
+// built only for the per-material closure and three material slots, whose
+// wider LDS records leave no 768-thread tile of the other sizes room. Shape
+// 12, the near-square 35 x 31 tile, has the smallest halo share of the
+// 768-thread tiles that keep two cells of the widest halo per thread (1.40
+// halo-inclusive cells per owned cell against 1.56 for 64 x 14) and tiles a
+// 1050-cell side in whole columns (1020 tiles, four rounds of one workgroup
+// per CU); its LDS leaves no room for the wider records of three slots or of
+// the per-material closure, so it is built for two slots only.
 static const int kShapes[][3] = {
     {64, 14, 768},
     {40, 16, 512},
@@ -22,9 +28,10 @@ static const int kShapes[][3] = {
     {64, 16, 1024},
     {32, 32, 1024},
     {20, 13, 256},
-    {48, 14, 768}};
+    {48, 14, 768},
+    {35, 31, 768}};
 
-int default_variant(int prec) { return prec == 0 ? 0 : 1; }
+int default_variant(int prec) { return prec == 0 ? 12 : 1; }
 
 int n_variants() { return (int)(sizeof(kShapes) / sizeof(kShapes[0])); }
 

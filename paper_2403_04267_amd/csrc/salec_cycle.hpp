@@ -1122,6 +1122,7 @@ __global__ void k_prime(Inst in) {
       case 8: return k_cycle<64, 16, 1024, 4, T, false, 2, false>;                           \
       case 9: return k_cycle<32, 32, 1024, 4, T, false, 2, false>;                           \
       case 10: return k_cycle<20, 13, 256, 3, T, false, 2, false>;                           \
+      case 12: return k_cycle<35, 31, 768, 3, T, false, 2, false>;                           \
       default: return nullptr;                                                               \
     }                                                                                        \
   }                                                                                          \
@@ -1172,6 +1173,7 @@ __global__ void k_prime(Inst in) {
       case 8: return k_cycle<64, 16, 1024, 4, T, true, 2, false>;                            \
       case 9: return k_cycle<32, 32, 1024, 4, T, true, 2, false>;                            \
       case 10: return k_cycle<20, 13, 256, 3, T, true, 2, false>;                            \
+      case 12: return k_cycle<35, 31, 768, 3, T, true, 2, false>;                            \
       default: return nullptr;                                                               \
     }                                                                                        \
   }                                                                                          \
