@@ -122,18 +122,22 @@ VALU_LANE_OPS_PEAK = 256 * 4 * 2.4e9 / 4 * 64
 
 def valu_per_launch(schedule):
     """VALU instructions per cycle-kernel launch (SQ_INSTS_VALU, wave64
-    instructions, recorded with the traffic records), if taken from the
-    current kernel sources and the schedule being timed."""
+    instructions, recorded with the traffic records, one record or a list),
+    if taken from the current kernel sources and the schedule being timed."""
     try:
         with open(TRAFFIC_FILE) as fh:
-            rec = json.load(fh).get("valu")
+            recs = json.load(fh).get("valu")
     except (OSError, ValueError, AttributeError):
         return None
-    if not rec or rec.get("kernel_sources_sha256") != kernel_sources_sha():
-        return None
-    if not all(schedule.get(k) == v for k, v in rec.get("schedule", {}).items()):
-        return None
-    return rec.get("sq_insts_valu_per_dispatch")
+    if isinstance(recs, dict):
+        recs = [recs]
+    sha = kernel_sources_sha()
+    for rec in recs or []:
+        if rec.get("kernel_sources_sha256") != sha:
+            continue
+        if all(schedule.get(k) == v for k, v in rec.get("schedule", {}).items()):
+            return rec.get("sq_insts_valu_per_dispatch")
+    return None
 
 
 def cpu_baseline(pb, budget_s=12.0):

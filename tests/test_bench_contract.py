@@ -49,6 +49,10 @@ def test_counters_apply_only_to_their_sources_and_schedule(monkeypatch):
     other = dict(sched, grid=sched["grid"] + 8)
     assert bench.traffic_per_launch(other) is None or any(
         r["schedule"] == other for r in rec["records"])
+    valu = rec.get("valu")
+    for v in ([valu] if isinstance(valu, dict) else valu or []):
+        if v["kernel_sources_sha256"] == bench.kernel_sources_sha():
+            assert bench.valu_per_launch(dict(v["schedule"])) == v["sq_insts_valu_per_dispatch"]
     monkeypatch.setattr(bench, "kernel_sources_sha", lambda: "0" * 64)
     assert bench.traffic_per_launch(sched) is None
     assert bench.valu_per_launch(sched) is None
