@@ -312,8 +312,9 @@ int salec_time_kernels(salec_ctx *ctx, int32_t n, double *cycle_ms, double *fina
  * (the members advance by (cycles + 1) cycles per candidate, at most
  * 2 * salec_num_variants() candidates), keeps the fastest and reports it in
  * out (may be NULL). Not every shape is built for every context: three
- * material slots and the per-material closure need more LDS per cell, and
- * the last shape exists only for them. salec_set_schedule() refuses a shape
+ * material slots and the per-material closure need more LDS per cell, so
+ * the larger tiles are not built for them, and shapes 11 and 14 are built
+ * only for them. salec_set_schedule() refuses a shape
  * the context cannot run with SALEC_E_INVALID and leaves the context as it
  * was; salec_tune() skips such shapes. A HIP error while switching leaves
  * the context unusable (SALEC_E_HIP). */

@@ -9,13 +9,14 @@ namespace salec {
 // workgroups (four waves per SIMD) share a CU where two tiles fit the LDS
 // (the FP32 instantiation); 256-thread tiles run three to a CU. Shape 11 is
 // built only for the per-material closure and three material slots, whose
-// wider LDS records leave no 768-thread tile of the other sizes room. Shape
-// 12, the near-square 35 x 31 tile, has the smallest halo share of the
-// 768-thread tiles that keep two cells of the widest halo per thread (1.40
-// halo-inclusive cells per owned cell against 1.56 for 64 x 14) and tiles a
-// 1050-cell side in whole columns (1020 tiles, four rounds of one workgroup
-// per CU); its LDS leaves no room for the wider records of three slots or of
-// the per-material closure, so it is built for two slots only.
+// wider LDS records leave no 768-thread tile of the other sizes room. Shapes
+// 12-14 are near-square 768-thread tiles that keep two cells of the widest
+// halo per thread: less halo recomputed per owned cell (1.40 halo-inclusive
+// cells for 35 x 31 against 1.56 for 64 x 14) and tile counts that fill whole
+// rounds of one workgroup per CU (35 x 31: 1020 tiles on a 1050-cell square;
+// 32 x 34: 256 tiles on the 512 x 532 stretched grid). Each is built where
+// its LDS records fit: 35 x 31 for two slots and for three on uniform grids,
+// 32 x 34 for two slots, 27 x 27 for the per-material closure with three.
 static const int kShapes[][3] = {
     {64, 14, 768},
     {40, 16, 512},
@@ -29,7 +30,9 @@ static const int kShapes[][3] = {
     {32, 32, 1024},
     {20, 13, 256},
     {48, 14, 768},
-    {35, 31, 768}};
+    {35, 31, 768},
+    {32, 34, 768},
+    {27, 27, 768}};
 
 int default_variant(int prec) { return prec == 0 ? 12 : 1; }
 

@@ -1123,6 +1123,7 @@ __global__ void k_prime(Inst in) {
       case 9: return k_cycle<32, 32, 1024, 4, T, false, 2, false>;                           \
       case 10: return k_cycle<20, 13, 256, 3, T, false, 2, false>;                           \
       case 12: return k_cycle<35, 31, 768, 3, T, false, 2, false>;                           \
+      case 13: return k_cycle<32, 34, 768, 3, T, false, 2, false>;                           \
       default: return nullptr;                                                               \
     }                                                                                        \
   }                                                                                          \
@@ -1138,6 +1139,7 @@ __global__ void k_prime(Inst in) {
       case 9: return k_cycle<32, 32, 1024, 4, T, false, 3, false>;                           \
       case 10: return k_cycle<20, 13, 256, 3, T, false, 3, false>;                           \
       case 11: return k_cycle<48, 14, 768, 3, T, false, 3, false>;                           \
+      case 12: return k_cycle<35, 31, 768, 3, T, false, 3, false>;                           \
       default: return nullptr;                                                               \
     }                                                                                        \
   }                                                                                          \
@@ -1157,6 +1159,7 @@ __global__ void k_prime(Inst in) {
       case 7: return k_cycle<28, 18, 512, 4, T, false, 3, true>;                             \
       case 10: return k_cycle<20, 13, 256, 3, T, false, 3, true>;                            \
       case 11: return k_cycle<48, 14, 768, 3, T, false, 3, true>;                            \
+      case 14: return k_cycle<27, 27, 768, 3, T, false, 3, true>;                            \
       default: return nullptr;                                                               \
     }                                                                                        \
   }                                                                                          \
@@ -1174,6 +1177,7 @@ __global__ void k_prime(Inst in) {
       case 9: return k_cycle<32, 32, 1024, 4, T, true, 2, false>;                            \
       case 10: return k_cycle<20, 13, 256, 3, T, true, 2, false>;                            \
       case 12: return k_cycle<35, 31, 768, 3, T, true, 2, false>;                            \
+      case 13: return k_cycle<32, 34, 768, 3, T, true, 2, false>;                            \
       default: return nullptr;                                                               \
     }                                                                                        \
   }                                                                                          \
@@ -1208,6 +1212,7 @@ __global__ void k_prime(Inst in) {
       case 7: return k_cycle<28, 18, 512, 4, T, true, 3, true>;                              \
       case 10: return k_cycle<20, 13, 256, 3, T, true, 3, true>;                             \
       case 11: return k_cycle<48, 14, 768, 3, T, true, 3, true>;                             \
+      case 14: return k_cycle<27, 27, 768, 3, T, true, 3, true>;                             \
       default: return nullptr;                                                               \
     }                                                                                        \
   }                                                                                          \

@@ -678,7 +678,7 @@ int init_common(salec_ctx* x, void* dev_buf, size_t dev_bytes, void* stream) {
   // the default shape; a persistent grid when it has fewer workgroups than tiles
   int v0 = default_variant(x->prec);
   // fall back along the shapes every family has when the default is not built
-  for (int alt : {0, 1, 7, 10})
+  for (int alt : {0, 14, 1, 7, 10})
     if (!variant_available(v0, x->prec, x->geo, x->nm, x->pm)) v0 = alt;
   int rc = use_schedule(x, v0, 0);
   if (rc) return rc;

@@ -105,7 +105,7 @@ def test_mixed_tile_shapes_agree_bitwise():
         try:
             c.set_schedule(v, 0)
         except SalecError:
-            assert v == 11  # built for three slots and the per-material closure only
+            assert v in (11, 14)  # built for three slots and the per-material closure only
             continue
         c.step(80)
         F = c.fields()

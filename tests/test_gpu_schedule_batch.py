@@ -57,7 +57,7 @@ def test_every_tile_shape_matches_the_oracle():
             try:
                 c.set_schedule(v, grid)
             except SalecError:
-                assert v == 11  # built for three slots and the per-material closure only
+                assert v in (11, 14)  # built for three slots and the per-material closure only
                 continue
             sch = c.schedule()
             assert sch["variant"] == v
@@ -115,8 +115,8 @@ def test_tuner_picks_a_schedule_without_changing_results():
     assert 0 <= sch["variant"] < num_variants() and sch["ms_per_cycle"] > 0
     # (cycles + 1) per candidate: every shape, some also with a persistent grid
     advanced = int(a.diag(k=0)["cycle"])
-    # (the last shape is not built for two-material shared-closure contexts)
-    assert advanced % 3 == 0 and 3 * (num_variants() - 1) <= advanced <= 6 * num_variants()
+    # (two shapes are not built for two-material shared-closure contexts)
+    assert advanced % 3 == 0 and 3 * (num_variants() - 2) <= advanced <= 6 * num_variants()
     b.step(advanced)
     a.step(20)
     b.step(20)

@@ -99,7 +99,7 @@ def test_every_three_material_tile_shape_matches_the_oracle():
         c.step(40)
         compare(c, o, f"three-layer shape {v}", tol=0.0)
         ran += 1
-    assert ran >= num_variants() - 3  # all but the three shapes whose LDS is too small for three slots
+    assert ran >= num_variants() - 4  # all but the four shapes not built for three slots
     # the tuner runs real cycles of the run ((cycles + 1) per candidate) and
     # only times shapes that exist for three materials
     c = ctx(pb)
