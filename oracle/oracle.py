@@ -68,6 +68,8 @@ def _load():
     lib.orc_step.argtypes = [P, C.c_int32]
     lib.orc_get_fields.argtypes = [P, D, D, D, D, D, D, D]
     lib.orc_get_pml.argtypes = [P, D, D]
+    lib.orc_set_pml.argtypes = [P, D, D]
+    lib.orc_set_clock.argtypes = [P, C.c_double, C.c_double]
     lib.orc_diag.argtypes = [P, D]
     lib.orc_get_profiles.argtypes = [P, D, D, D, D]
     lib.orc_tillotson.argtypes = [C.POINTER(_Mat), C.c_double, C.c_double, D, D]
@@ -226,6 +228,34 @@ class Oracle:
         out = {k: ca[i] for i, k in enumerate(names_c)}
         out.update({k: na[i] for i, k in enumerate(names_n)})
         return out
+
+    def set_pml(self, aux: dict):
+        """Writes the PML auxiliaries back in the layout pml_aux returns."""
+        names_c = ["phi1_b", "phi3_b", "psi2_b", "phi1_r", "phi3_r", "psi2_r", "rho_ref", "msink"]
+        names_n = ["phi2_b_r", "phi2_b_z", "psi1_b_r", "psi1_b_z", "phi2_r_r", "phi2_r_z",
+                   "psi1_r_r", "psi1_r_z"]
+        ca = np.ascontiguousarray(np.stack([np.asarray(aux[k], dtype=np.float64).reshape(self.NZ, self.NR)
+                                            for k in names_c])).reshape(-1)
+        na = np.ascontiguousarray(np.stack([np.asarray(aux[k], dtype=np.float64).reshape(self.NZ + 1, self.NR + 1)
+                                            for k in names_n])).reshape(-1)
+        if self._lib.orc_set_pml(self._h, _ptr(ca), _ptr(na)):
+            raise ValueError("orc_set_pml failed")
+
+    def set_clock(self, t: float, dt: float):
+        if self._lib.orc_set_clock(self._h, float(t), float(dt)):
+            raise ValueError("orc_set_clock: needs t >= 0 and 0 < dt <= dt_max (and dt <= t_stop - t)")
+
+    def continue_from(self, src: "Oracle"):
+        """Takes over src's state between cycles: fields, per-material state,
+        PML auxiliaries and clock. The problems must be the same."""
+        F = src.fields(eos=False)
+        self.set_fields(F["rho"], F["I"], F["f"], F["v"], F["s"])
+        if self.problem.grid.closure:
+            M = src.materials()
+            self.set_materials(M["mu"], M["Im"])
+        self.set_pml(src.pml_aux())
+        d = src.diag()
+        self.set_clock(d["t"], d["dt"])
 
     def geometry(self):
         """Node and centre radii and heights of the grid."""

@@ -1683,6 +1683,36 @@ int orc_get_pml(orc_ctx *x, double *ca, double *na)
     return ORC_OK;
 }
 
+/* Inverse of orc_get_pml: the PML auxiliary fields, reference density and
+ * sink of the current state, in the same full-grid layouts. */
+int orc_set_pml(orc_ctx *x, const double *ca, const double *na)
+{
+    if (!x) return ORC_E_INVALID;
+    size_t NC = x->NC, NN = x->NN;
+    if (ca) {
+        double *dst[8] = {x->phi1b, x->phi3b, x->psi2b, x->phi1r, x->phi3r, x->psi2r, x->rref, x->msink};
+        for (int k = 0; k < 8; k++) memcpy(dst[k], ca + k * NC, sizeof(double) * NC);
+    }
+    if (na) {
+        double *dst[8] = {x->phi2b_r, x->phi2b_z, x->psi1b_r, x->psi1b_z,
+                          x->phi2r_r, x->phi2r_z, x->psi1r_r, x->psi1r_z};
+        for (int k = 0; k < 8; k++) memcpy(dst[k], na + k * NN, sizeof(double) * NN);
+    }
+    return ORC_OK;
+}
+
+/* Time of the state and the step of the next cycle (Sec. 7's step is chosen
+ * at the end of the cycle before; a continued run takes it over). */
+int orc_set_clock(orc_ctx *x, double t, double dt)
+{
+    if (!x || !isfinite(t) || t < 0.0 || !isfinite(dt) || !(dt > 0.0) || dt > x->g.dt_max)
+        return ORC_E_INVALID;
+    if (x->g.t_stop > 0 && dt > x->g.t_stop - t) return ORC_E_INVALID;
+    x->t = t;
+    x->dt = dt;
+    return ORC_OK;
+}
+
 int orc_get_profiles(orc_ctx *x, double *dcz, double *dnz, double *dcr, double *dnr)
 {
     if (!x) return ORC_E_INVALID;

@@ -116,6 +116,11 @@ int orc_get_fields(orc_ctx *x, double *rho, double *I, double *f, double *s,
 /* cell_aux: 8*NC = phi1_b, phi3_b, psi2_b, phi1_r, phi3_r, psi2_r, rho_ref, msink
  * node_aux: 8*NN = phi2_b(r,z), psi1_b(r,z), phi2_r(r,z), psi1_r(r,z) */
 int orc_get_pml(orc_ctx *x, double *cell_aux, double *node_aux);
+/* Continuing a run: the PML auxiliaries (layouts of orc_get_pml) and the
+ * clock (t, and the dt of the next cycle) of a state set with
+ * orc_set_fields / orc_set_materials, which start a run at t = 0. */
+int orc_set_pml(orc_ctx *x, const double *cell_aux, const double *node_aux);
+int orc_set_clock(orc_ctx *x, double t, double dt);
 /* out[0..11]: t, dt, cycle, mass, internal energy, kinetic energy,
  * mass_out, mass_pml, ie_out, err, err_cycle, dt_prev */
 int orc_diag(orc_ctx *x, double *out);
