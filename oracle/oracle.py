@@ -35,7 +35,8 @@ class _Mat(C.Structure):
 
 
 class _Pml(C.Structure):
-    _fields_ = [("enabled", C.c_int32), ("damp_stress", C.c_int32), ("R", C.c_double), ("c_ref", C.c_double)]
+    _fields_ = [("enabled", C.c_int32), ("damp_stress", C.c_int32), ("R", C.c_double), ("c_ref", C.c_double),
+                ("placement", C.c_int32), ("form", C.c_int32)]
 
 
 class _Scene(C.Structure):
@@ -133,8 +134,9 @@ class Oracle:
         self.nmat = g.nmat
         mats = (_Mat * 3)(*[_mat(m) for m in problem.mats[:g.nmat]])
         pml = problem.pml
-        self._h = lib.orc_create(C.byref(_grid(g)), mats, C.byref(_Pml(int(pml.enabled), int(pml.damp_stress), pml.R,
-                                                                          pml.c_ref)))
+        cp = _Pml(int(pml.enabled), int(pml.damp_stress), pml.R, pml.c_ref, int(getattr(pml, "placement", 0)),
+                  int(getattr(pml, "form", 0)))
+        self._h = lib.orc_create(C.byref(_grid(g)), mats, C.byref(cp))
         if not self._h:
             raise ValueError("oracle rejected the problem description")
         self._lib = lib

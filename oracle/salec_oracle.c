@@ -82,6 +82,11 @@ struct orc_ctx {
     double *phi2b_r, *phi2b_z, *psi1b_r, *psi1b_z;
     double *phi2r_r, *phi2r_z, *psi1r_r, *psi1r_z;
     double *mout_col, *eout_col;
+    /* placement 1: level-n sums of psi1 (node, r and z) and psi2 (cell) kept
+     * for the Eulerian step, and the mass the Eulerian step starts from (rho
+     * and, with closure 1, mu after phi1) */
+    double *psi1n_r, *psi1n_z, *psi2n, *rho_t, *mu_t[ORC_MAX_MAT];
+    double *rhoE, *muE[ORC_MAX_MAT];
 
     /* per-cycle work arrays */
     double *p, *c2, *G, *Y, *rmat, *phi, *sx, *Q, *sgrr, *sgzz, *sgtt, *sgrz;
@@ -106,6 +111,12 @@ struct orc_ctx {
 
 static double dmax(double a, double b) { return a > b ? a : b; }
 static double dmin(double a, double b) { return a < b ? a : b; }
+
+/* Sum of four per-face (or per-corner) terms ordered W, E, S, N (or SW, SE,
+ * NW, NE): the r pair plus the z pair. The divergence of Sec. 2's equations is
+ * an r part plus a z part; summing it that way also keeps the discrete scheme
+ * exactly symmetric under a reflection in z (the pair (S, N) becomes (N, S)). */
+static double face_sum(const double t[4]) { return (t[0] + t[1]) + (t[2] + t[3]); }
 
 /* ---- geometry (per radian): radial face area, cell volume ---- */
 static double area_r(const orc_ctx *x, int i, int j) { return x->rn[i] * x->dzr[j]; }
@@ -159,20 +170,15 @@ void orc_tillotson(const orc_mat *m, double rho, double e, double *p_out, double
     double rf = m->rho0 * RHO_EOS_FLOOR;
     double r = rho > rf ? rho : rf;
     double E = e > 0.0 ? e : 0.0;
-    /* reciprocals shared by the terms below (material constants, then 1/r
-     * and 1/w); eta keeps a true division so that eta = 1 exactly at rho0 */
-    double irho0 = 1.0 / m->rho0, Ar = m->A / m->rho0, idE = 1.0 / (m->Ecv - m->Eiv);
-    double ir = 1.0 / r, irr = ir * ir;
     double eta = r / m->rho0;
     double mu = eta - 1.0;
     double w = E / (m->E0 * eta * eta) + 1.0;
-    double iw = 1.0 / w, iw2 = iw * iw;
 
     /* compressed / cold branch */
-    double pc = (m->a + m->b * iw) * r * E + m->A * mu + m->B * mu * mu;
-    double pc_E = r * (m->a + m->b * iw - m->b * (w - 1.0) * iw2);
-    double pc_r = (m->a + m->b * iw) * E + 2.0 * m->b * E * (w - 1.0) * iw2
-                + (m->A + 2.0 * m->B * mu) * irho0;
+    double pc = (m->a + m->b / w) * r * E + m->A * mu + m->B * mu * mu;
+    double pc_E = r * (m->a + m->b / w - m->b * (w - 1.0) / (w * w));
+    double pc_r = (m->a + m->b / w) * E + 2.0 * m->b * E * (w - 1.0) / (w * w)
+                + (m->A + 2.0 * m->B * mu) / m->rho0;
     double p, dpdE, dpdr;
     if (r >= m->rho0 || E <= m->Eiv) {
         p = pc;
@@ -180,29 +186,29 @@ void orc_tillotson(const orc_mat *m, double rho, double e, double *p_out, double
         dpdr = pc_r;
     } else {
         /* expanded branch */
-        double z = m->rho0 * ir - 1.0;
+        double z = 1.0 / eta - 1.0;
         double ea = exp_cw(-m->alpha * z * z);
         double eb = exp_cw(-m->beta * z);
-        double pe = m->a * r * E + (m->b * r * E * iw + m->A * mu * eb) * ea;
-        double pe_E = m->a * r + ea * m->b * r * (iw - (w - 1.0) * iw2);
+        double pe = m->a * r * E + (m->b * r * E / w + m->A * mu * eb) * ea;
+        double pe_E = m->a * r + ea * m->b * r * (1.0 / w - (w - 1.0) / (w * w));
         double pe_r = m->a * E
-                    + ea * (m->b * E * iw + 2.0 * m->b * E * (w - 1.0) * iw2
-                            + Ar * eb + m->A * mu * m->beta * eb * m->rho0 * irr)
-                    + (m->b * r * E * iw + m->A * mu * eb) * ea * 2.0 * m->alpha * z * m->rho0 * irr;
+                    + ea * (m->b * E / w + 2.0 * m->b * E * (w - 1.0) / (w * w)
+                            + (m->A / m->rho0) * eb + m->A * mu * m->beta * eb * m->rho0 / (r * r))
+                    + (m->b * r * E / w + m->A * mu * eb) * ea * 2.0 * m->alpha * z * m->rho0 / (r * r);
         if (E >= m->Ecv) {
             p = pe;
             dpdE = pe_E;
             dpdr = pe_r;
         } else {
             /* partial vaporisation: energy-weighted blend */
-            double x = (E - m->Eiv) * idE;
+            double x = (E - m->Eiv) / (m->Ecv - m->Eiv);
             p = x * pe + (1.0 - x) * pc;
-            dpdE = x * pe_E + (1.0 - x) * pc_E + (pe - pc) * idE;
+            dpdE = x * pe_E + (1.0 - x) * pc_E + (pe - pc) / (m->Ecv - m->Eiv);
             dpdr = x * pe_r + (1.0 - x) * pc_r;
         }
     }
     *p_out = p;
-    *c2_out = dpdr + p * irr * dpdE;
+    *c2_out = dpdr + p / (r * r) * dpdE;
 }
 
 /* intact-rock yield strength (Table 1 parameters Y_i0, mu_i, Y_im) */
@@ -211,8 +217,7 @@ double orc_yield(const orc_mat *m, double p)
     if (!m->strength) return 0.0;
     if (p >= 0.0) {
         double mp = m->mu_f * p;
-        double iYd = 1.0 / (m->Ylim - m->Y0);
-        return m->Y0 + mp / (1.0 + mp * iYd);
+        return m->Y0 + mp / (1.0 + mp / (m->Ylim - m->Y0));
     }
     return dmax(0.0, m->Y0 + m->mu_f * p);
 }
@@ -228,8 +233,7 @@ double orc_shear_modulus(const orc_mat *m)
 double orc_softening(const orc_mat *m, double e)
 {
     double E = e > 0.0 ? e : 0.0;
-    double idE = 1.0 / (m->Ecv - m->Eiv);
-    return dmin(dmax((m->Ecv - E) * idE, 0.0), 1.0);
+    return dmin(dmax((m->Ecv - E) / (m->Ecv - m->Eiv), 0.0), 1.0);
 }
 
 /* mixture state of cell c: shared material density and energy, weights f_m/phi */
@@ -240,13 +244,12 @@ static void mixture(const orc_ctx *x, int c, const double *rho, const double *I,
     double phi = 0.0;
     for (int m = 0; m < x->nmat; m++) phi += f[m][c];
     double den = phi > PHI_EPS ? phi : PHI_EPS;
-    double iden = 1.0 / den;
-    double rm = rho[c] * iden;
+    double rm = rho[c] / den;
     double p = 0.0, c2 = 0.0, G = 0.0;
     double wm[ORC_MAX_MAT];
     for (int m = 0; m < x->nmat; m++) {
         double pm, c2m;
-        wm[m] = f[m][c] * iden;
+        wm[m] = f[m][c] / den;
         orc_tillotson(&x->m[m], rm, I[c], &pm, &c2m);
         pm = dmax(pm, x->m[m].p_min);
         c2m = dmax(c2m, x->m[m].c_floor_frac * x->m[m].A / x->m[m].rho0);
@@ -284,15 +287,14 @@ static void mixture_pm(const orc_ctx *x, int c, const double *rho, double *const
     double phi = 0.0;
     for (int m = 0; m < x->nmat; m++) phi += f[m][c];
     double den = phi > PHI_EPS ? phi : PHI_EPS;
-    double iden = 1.0 / den;
-    double rm = rho[c] * iden;
+    double rm = rho[c] / den;
     double p = 0.0, c2 = 0.0, G = 0.0;
     double wm[ORC_MAX_MAT], sf[ORC_MAX_MAT];
     for (int m = 0; m < x->nmat; m++) {
         double fm = f[m][c], mm = mu[m][c];
         double rmm = fm > F_PM_EPS && mm > 0.0 ? mm / fm : rm;
         double pm, c2m;
-        wm[m] = fm * iden;
+        wm[m] = fm / den;
         sf[m] = 0.0;
         if (pm_o) pm_o[m] = 0.0;
         if (rhm_o) rhm_o[m] = rmm;
@@ -408,15 +410,14 @@ static void kinematics(const col_t *cg, double dz, const double *vr, const doubl
     k->Uz_n = aw * vz[2] + ae * vz[3];
     k->uz_s = k->Uz_s / Az;
     k->uz_n = k->Uz_n / Az;
-    double iV = 1.0 / V, irc = 1.0 / cg->rc, idr = 1.0 / cg->dr;
-    k->Dr = (k->Ur_e - k->Ur_w) * iV;
-    k->Dz = (k->Uz_n - k->Uz_s) * iV;
-    k->D = ((k->Ur_e - k->Ur_w) + (k->Uz_n - k->Uz_s)) * iV;
-    k->err = (k->ur_e - k->ur_w) * idr;
-    k->ezz = (k->Uz_n - k->Uz_s) * iV;
-    k->ett = (0.5 * (k->ur_w + k->ur_e)) * irc;
-    k->dvr_dz = ((aw * vr[2] + ae * vr[3]) - (aw * vr[0] + ae * vr[1])) * iV;
-    k->dvz_dr = (0.5 * (vz[1] + vz[3]) - 0.5 * (vz[0] + vz[2])) * idr;
+    k->Dr = (k->Ur_e - k->Ur_w) / V;
+    k->Dz = (k->Uz_n - k->Uz_s) / V;
+    k->D = ((k->Ur_e - k->Ur_w) + (k->Uz_n - k->Uz_s)) / V;
+    k->err = (k->ur_e - k->ur_w) / cg->dr;
+    k->ezz = (k->Uz_n - k->Uz_s) / V;
+    k->ett = (0.5 * (k->ur_w + k->ur_e)) / cg->rc;
+    k->dvr_dz = ((aw * vr[2] + ae * vr[3]) - (aw * vr[0] + ae * vr[1])) / V;
+    k->dvz_dr = (0.5 * (vz[1] + vz[3]) - 0.5 * (vz[0] + vz[2])) / cg->dr;
     k->erz = 0.5 * (k->dvr_dz + k->dvz_dr);
     k->om = 0.5 * (k->dvr_dz - k->dvz_dr);
 }
@@ -454,7 +455,7 @@ void orc_cell_kinematics(const orc_grid *g, int32_t i, int32_t j, const double *
 void orc_stress_update(double G, double Y, double dt, const double *rt, double *s)
 {
     double srr = s[0], szz = s[1], srz = s[2];
-    double tr3 = ((rt[0] + rt[1]) + rt[2]) * (1.0 / 3.0);
+    double tr3 = ((rt[0] + rt[1]) + rt[2]) / 3.0;
     double om = rt[4];
     double dsrr = 2.0 * G * (rt[0] - tr3) + 2.0 * om * srz;
     double dszz = 2.0 * G * (rt[1] - tr3) - 2.0 * om * srz;
@@ -516,6 +517,9 @@ orc_ctx *orc_create(const orc_grid *g, const orc_mat *mats, const orc_pml *pml)
     if (g->nmat < 1 || g->nmat > ORC_MAX_MAT) return NULL;
     if (g->closure != 0 && g->closure != 1) return NULL;
     if (pml->damp_stress != 0 && pml->damp_stress != 1) return NULL;
+    if (pml->placement != 0 && pml->placement != 1) return NULL;
+    if (pml->form != 0 && pml->form != 1) return NULL;
+    if (pml->form == 1 && (pml->placement != 0 || g->closure != 0)) return NULL;
     if (!(g->dr > 0) || !(g->dz > 0) || !(g->cfl > 0) || g->cfl > 1.0) return NULL;
     for (int i = 0; g->dr_col && i < g->n_r + g->pml_r; i++)
         if (!(g->dr_col[i] > 0) || !isfinite(g->dr_col[i])) return NULL;
@@ -612,7 +616,12 @@ orc_ctx *orc_create(const orc_grid *g, const orc_mat *mats, const orc_pml *pml)
         x->ILm[m] = zalloc(NC);
         x->Fmr[m] = zalloc(NRF);
         x->Fmz[m] = zalloc(NAF);
+        x->mu_t[m] = zalloc(NC);
     }
+    x->psi1n_r = zalloc(NN);
+    x->psi1n_z = zalloc(NN);
+    x->psi2n = zalloc(NC);
+    x->rho_t = zalloc(NC);
     x->p0 = zalloc(NZ);
     x->dcz = zalloc(NZ);
     x->dnz = zalloc(NZ + 1);
@@ -682,12 +691,16 @@ void orc_destroy(orc_ctx *x)
                      x->phi2r_z, x->psi1r_r, x->psi1r_z, x->vLr, x->vLz, x->heat, x->dVr, x->Fr,
                      x->dVz, x->Fz, x->dVre, x->dVze, x->lam, x->outv, x->mout_col, x->eout_col};
     for (size_t k = 0; k < sizeof(all) / sizeof(all[0]); k++) free(all[k]);
+    free(x->psi1n_r);
+    free(x->psi1n_z);
+    free(x->psi2n);
+    free(x->rho_t);
     for (int m = 0; m < ORC_MAX_MAT; m++) {
         free(x->f[m]);
         free(x->f_n[m]);
         free(x->fL[m]);
         double *pa[] = {x->mu[m], x->Im[m], x->mu_n[m], x->Im_n[m], x->pmm[m], x->rhm[m], x->ILm[m],
-                        x->Fmr[m], x->Fmz[m]};
+                        x->Fmr[m], x->Fmz[m], x->mu_t[m]};
         for (size_t k = 0; k < sizeof(pa) / sizeof(pa[0]); k++) free(pa[k]);
     }
     free(x);
@@ -934,9 +947,9 @@ int orc_set_fields(orc_ctx *x, const double *rho, const double *I, const double 
     for (size_t c = 0; c < NC; c++) {
         double phi = 0.0;
         for (int m = 0; m < x->nmat; m++) phi += x->f[m][c];
-        double iden = 1.0 / (phi > PHI_EPS ? phi : PHI_EPS);
+        double den = phi > PHI_EPS ? phi : PHI_EPS;
         for (int m = 0; m < x->nmat; m++) {
-            x->mu[m][c] = x->rho[c] * (x->f[m][c] * iden);
+            x->mu[m][c] = x->rho[c] * (x->f[m][c] / den);
             x->Im[m][c] = x->I[c];
         }
     }
@@ -997,7 +1010,7 @@ static void phase_cell_stress(orc_ctx *x)
             kinematics(&cg, x->dzr[j], vr4, vz4, &k);
             /* compression felt by the material (void closes first) */
             double Jn = 1.0 + x->dt * k.D;
-            double Dm = Jn < 1.0 ? (1.0 - material_ratio(Jn, phi, sx)) * (1.0 / x->dt) : 0.0;
+            double Dm = Jn < 1.0 ? (1.0 - material_ratio(Jn, phi, sx)) / x->dt : 0.0;
             double Ld = L * Dm;
             double Q = rm * (x->g.q_quad * Ld * Ld + x->g.q_lin * sqrt(c2) * Ld);
             double P = p + Q;
@@ -1064,20 +1077,24 @@ static void phase_node_force(orc_ctx *x)
             double db = x->dnz[j], drr = x->dnr[i];
             double psr = x->psi1b_r[n] + x->psi1r_r[n];
             double psz = x->psi1b_z[n] + x->psi1r_z[n];
-            double Fer = Fr - Vd * psr, Fez = Fz - Vd * psz;
-            double imt = 1.0 / mt;
-            x->vLr[n] = x->vr[n] + dt * (Fer * imt);
-            x->vLz[n] = x->vz[n] + dt * (Fez * imt);
-            if (db > 0.0 || drr > 0.0) {
-                double iVd = 1.0 / Vd;
-                if (db > 0.0) {
-                    x->psi1b_r[n] = x->psi1b_r[n] - dt * db * (Frr * iVd);
-                    x->psi1b_z[n] = x->psi1b_z[n] - dt * db * (Fzr * iVd);
-                }
-                if (drr > 0.0) {
-                    x->psi1r_r[n] = x->psi1r_r[n] - dt * drr * (Frz * iVd);
-                    x->psi1r_z[n] = x->psi1r_z[n] - dt * drr * (Fzz * iVd);
-                }
+            /* the auxiliary this step applies: psi1, or phi2 as printed */
+            double apr = psr, apz = psz;
+            if (x->pml.placement) {
+                apr = x->phi2b_r[n] + x->phi2r_r[n];
+                apz = x->phi2b_z[n] + x->phi2r_z[n];
+                x->psi1n_r[n] = psr; /* for the momentum remap */
+                x->psi1n_z[n] = psz;
+            }
+            double Fer = Fr - Vd * apr, Fez = Fz - Vd * apz;
+            x->vLr[n] = x->vr[n] + dt * (Fer / mt);
+            x->vLz[n] = x->vz[n] + dt * (Fez / mt);
+            if (db > 0.0) {
+                x->psi1b_r[n] = x->psi1b_r[n] - dt * db * (Frr / Vd);
+                x->psi1b_z[n] = x->psi1b_z[n] - dt * db * (Fzr / Vd);
+            }
+            if (drr > 0.0) {
+                x->psi1r_r[n] = x->psi1r_r[n] - dt * drr * (Frz / Vd);
+                x->psi1r_z[n] = x->psi1r_z[n] - dt * drr * (Fzz / Vd);
             }
         }
     }
@@ -1119,6 +1136,10 @@ static void phase_cell_lagrange(orc_ctx *x)
             double rden = dmax(x->rmat[c], x->rho_ref * RHO_DEN_FLOOR);
             double rt_ = dmax(x->rho[c], x->rho_ref * PML_RHO_FLOOR);
             double psi2 = x->psi2b[c] + x->psi2r[c];
+            /* the auxiliary this step applies to the energy: psi2, or phi3 as
+             * printed (which then also applies phi1 to the mass below) */
+            double a3 = x->pml.placement ? x->phi3b[c] + x->phi3r[c] : psi2;
+            if (x->pml.placement) x->psi2n[c] = psi2; /* for the cell remap */
             /* Symplectic Euler (the grid moves with v^L) makes the p dV work
              * fall short of the kinetic-energy change by m |v^L - v^n|^2 / 2
              * per node; each corner mass of the node keeps its share, so the
@@ -1130,11 +1151,10 @@ static void phase_cell_lagrange(orc_ctx *x)
                 kd[q] = 0.5 * (dvr * dvr + dvz * dvz);
             }
             double V = vol_c(x, i, j), hdz = 0.5 * x->dzr[j];
-            double iV = 1.0 / V;
-            double wW = (cg.aw * hdz) * iV;
-            double wE = (cg.ae * hdz) * iV;
+            double wW = (cg.aw * hdz) / V;
+            double wE = (cg.ae * hdz) / V;
             double hL = wW * (kd[0] + kd[2]) + wE * (kd[1] + kd[3]);
-            x->IL[c] = ((x->I[c] + Wdt / rden) + hL) - dt * (psi2 / rt_);
+            x->IL[c] = ((x->I[c] + Wdt / rden) + hL) - dt * (a3 / rt_);
             /* closure 1: each material does the deviatoric work and its own
              * p dV work on the cell's volume change (the sum over materials of
              * mu_m times the specific work is the cell's work above) */
@@ -1142,7 +1162,7 @@ static void phase_cell_lagrange(orc_ctx *x)
                 double Pm = x->pmm[m][c] + x->Q[c];
                 double Wm = dt * sde - Pm * (J - 1.0);
                 double rdm = dmax(x->rhm[m][c], x->rho_ref * RHO_DEN_FLOOR);
-                x->ILm[m][c] = ((x->Im[m][c] + Wm / rdm) + hL) - dt * (psi2 / rt_);
+                x->ILm[m][c] = ((x->Im[m][c] + Wm / rdm) + hL) - dt * (a3 / rt_);
             }
             for (int m = 0; m < x->nmat; m++) x->fL[m][c] = x->f[m][c] * (Jm / J);
             double db = x->dcz[j], drr = x->dcr[i];
@@ -1158,8 +1178,25 @@ static void phase_cell_lagrange(orc_ctx *x)
             x->sLzz[c] = s[1];
             x->sLrz[c] = s[2];
             x->J[c] = J;
+            /* the mass the Eulerian step starts from: phi1 as printed leaves
+             * the layer here (a sink that never leaves negative mass, whose
+             * loss the sink budget records; with closure 1 every material
+             * loses the same fraction) */
+            if (x->pml.placement) {
+                double rt = x->rho[c];
+                if (db > 0.0 || drr > 0.0) {
+                    rt = dmax(x->rho[c] - dt * (x->phi1b[c] + x->phi1r[c]), 0.0);
+                    x->msink[c] = x->msink[c] + V * (x->rho[c] - rt);
+                }
+                x->rho_t[c] = rt;
+                double kap = x->rho[c] > 0.0 ? rt / x->rho[c] : 0.0;
+                for (int m = 0; x->pm && m < x->nmat; m++)
+                    x->mu_t[m][c] = rt == x->rho[c] ? x->mu[m][c] : x->mu[m][c] * kap;
+            }
         }
     }
+    x->rhoE = x->pml.placement ? x->rho_t : x->rho;
+    for (int m = 0; m < ORC_MAX_MAT; m++) x->muE[m] = x->pml.placement ? x->mu_t[m] : x->mu[m];
 }
 
 /* Lagrangian density and outflow limiter of cell (i, j); outside the grid: void */
@@ -1167,14 +1204,14 @@ static double rhoL(const orc_ctx *x, int i, int j)
 {
     int NR = x->NR;
     if (i < 0 || i >= NR || j < 0 || j >= x->NZ) return 0.0;
-    return x->rho[CI(i, j)] / x->J[CI(i, j)];
+    return x->rhoE[CI(i, j)] / x->J[CI(i, j)];
 }
 /* closure 1: Lagrangian partial density of material m (mass per Lagrangian volume) */
 static double muL(const orc_ctx *x, int m, int i, int j)
 {
     int NR = x->NR;
     if (i < 0 || i >= NR || j < 0 || j >= x->NZ) return 0.0;
-    return x->mu[m][CI(i, j)] / x->J[CI(i, j)];
+    return x->muE[m][CI(i, j)] / x->J[CI(i, j)];
 }
 static double lam_at(const orc_ctx *x, int i, int j)
 {
@@ -1208,8 +1245,8 @@ static void phase_faces(orc_ctx *x)
     for (int j = 0; j < NZ; j++) {
         for (int i = 0; i < NR; i++) {
             int c = CI(i, j);
-            double O = ((dmax(-x->dVr[RF(i, j)], 0.0) + dmax(x->dVr[RF(i + 1, j)], 0.0))
-                        + dmax(-x->dVz[AF(i, j)], 0.0)) + dmax(x->dVz[AF(i, j + 1)], 0.0);
+            double O = (dmax(-x->dVr[RF(i, j)], 0.0) + dmax(x->dVr[RF(i + 1, j)], 0.0))
+                     + (dmax(-x->dVz[AF(i, j)], 0.0) + dmax(x->dVz[AF(i, j + 1)], 0.0));
             double VL = vol_c(x, i, j) * x->J[c];
             x->outv[c] = O;
             x->lam[c] = O > VL ? dmax(VL, 0.0) / O : 1.0;
@@ -1287,9 +1324,8 @@ static void phase_cell_remap(orc_ctx *x)
             double dVe[4] = {x->dVre[RF(i, j)], x->dVre[RF(i + 1, j)], x->dVze[AF(i, j)], x->dVze[AF(i, j + 1)]};
             int di[4] = {i - 1, i + 1, i, i}, dj[4] = {j, j, j - 1, j + 1};
             int in[4] = {dV[0] > 0.0, dV[1] < 0.0, dV[2] > 0.0, dV[3] < 0.0};
-            double iV = 1.0 / V;
-            double netin = ((F[0] - F[1]) + F[2]) - F[3];
-            double rho1 = x->rho[c] + netin * iV;
+            double netin = (F[0] - F[1]) + (F[2] - F[3]);
+            double rho1 = x->rhoE[c] + netin / V;
             /* closure 1: each partial density takes its own net inflow; rho is
              * their sum */
             double mu1[ORC_MAX_MAT], I1m[ORC_MAX_MAT], Fm[ORC_MAX_MAT][4];
@@ -1300,52 +1336,56 @@ static void phase_cell_remap(orc_ctx *x)
                     Fm[m][1] = x->Fmr[m][RF(i + 1, j)];
                     Fm[m][2] = x->Fmz[m][AF(i, j)];
                     Fm[m][3] = x->Fmz[m][AF(i, j + 1)];
-                    double nin = ((Fm[m][0] - Fm[m][1]) + Fm[m][2]) - Fm[m][3];
-                    mu1[m] = x->mu[m][c] + nin * iV;
+                    double nin = (Fm[m][0] - Fm[m][1]) + (Fm[m][2] - Fm[m][3]);
+                    mu1[m] = x->muE[m][c] + nin / V;
                     rho1 += mu1[m];
                 }
             }
             double M1 = rho1 * V;
-            double min_ = 0.0, nI = 0.0, nsrr = 0.0, nszz = 0.0, nsrz = 0.0, vcut = 0.0;
-            double nf[ORC_MAX_MAT] = {0.0, 0.0};
             double IL = x->IL[c];
             double ed[4] = {0.0, 0.0, 0.0, 0.0}; /* energy flux through each face */
+            /* per-face inflow terms (zero on outflow faces), summed below with
+             * opposite faces paired */
+            double tm[4] = {0}, tI[4] = {0}, tsrr[4] = {0}, tszz[4] = {0}, tsrz[4] = {0}, tcut[4] = {0};
+            double tf[ORC_MAX_MAT][4] = {{0}};
             for (int q = 0; q < 4; q++) {
                 int dc_ok = di[q] >= 0 && di[q] < NR && dj[q] >= 0 && dj[q] < NZ;
                 int dc = dc_ok ? CI(di[q], dj[q]) : -1;
                 if (in[q]) {
                     double aF = fabs(F[q]), adV = fabs(dVe[q]);
-                    vcut += fabs(dV[q]) - adV;
+                    tcut[q] = fabs(dV[q]) - adV;
                     double Id = dc_ok ? x->IL[dc] : 0.0;
-                    min_ += aF;
-                    nI += aF * (Id - IL);
-                    nsrr += aF * ((dc_ok ? x->sLrr[dc] : 0.0) - x->sLrr[c]);
-                    nszz += aF * ((dc_ok ? x->sLzz[dc] : 0.0) - x->sLzz[c]);
-                    nsrz += aF * ((dc_ok ? x->sLrz[dc] : 0.0) - x->sLrz[c]);
+                    tm[q] = aF;
+                    tI[q] = aF * (Id - IL);
+                    tsrr[q] = aF * ((dc_ok ? x->sLrr[dc] : 0.0) - x->sLrr[c]);
+                    tszz[q] = aF * ((dc_ok ? x->sLzz[dc] : 0.0) - x->sLzz[c]);
+                    tsrz[q] = aF * ((dc_ok ? x->sLrz[dc] : 0.0) - x->sLrz[c]);
                     for (int m = 0; m < nm; m++)
-                        nf[m] += adV * ((dc_ok ? x->fL[m][dc] : 0.0) - x->fL[m][c]);
+                        tf[m][q] = adV * ((dc_ok ? x->fL[m][dc] : 0.0) - x->fL[m][c]);
                     ed[q] = F[q] * Id;
                 } else {
                     ed[q] = F[q] * IL;
                 }
             }
+            double min_ = face_sum(tm), nI = face_sum(tI), vcut = face_sum(tcut);
+            double nsrr = face_sum(tsrr), nszz = face_sum(tszz), nsrz = face_sum(tsrz);
+            double nf[ORC_MAX_MAT] = {0.0, 0.0};
+            for (int m = 0; m < nm; m++) nf[m] = face_sum(tf[m]);
             double den = dmax(dmax(M1, min_), M_REMAP_FLOOR * x->rho_ref * V);
-            double iden = 1.0 / den;
-            double I1 = IL + nI * iden;
-            x->srr_n[c] = x->sLrr[c] + nsrr * iden;
-            x->szz_n[c] = x->sLzz[c] + nszz * iden;
-            x->srz_n[c] = x->sLrz[c] + nsrz * iden;
+            double I1 = IL + nI / den;
+            x->srr_n[c] = x->sLrr[c] + nsrr / den;
+            x->szz_n[c] = x->sLzz[c] + nszz / den;
+            x->srz_n[c] = x->sLrz[c] + nsrz / den;
             double fs = 0.0;
             double f1[ORC_MAX_MAT];
             /* volume the limiter kept from leaving this cell, minus void that
              * arrived in place of limited inflow (both zero without limiting) */
             double ex = (1.0 - x->lam[c]) * x->outv[c] - vcut;
             for (int m = 0; m < nm; m++) {
-                f1[m] = dmax(x->fL[m][c] + (nf[m] + x->fL[m][c] * ex) * iV, 0.0);
+                f1[m] = dmax(x->fL[m][c] + (nf[m] + x->fL[m][c] * ex) / V, 0.0);
                 fs += f1[m];
             }
-            double ifs = 1.0 / dmax(fs, 1.0);
-            for (int m = 0; m < nm; m++) x->f_n[m][c] = f1[m] * ifs;
+            for (int m = 0; m < nm; m++) x->f_n[m][c] = f1[m] / dmax(fs, 1.0);
 
             /* closure 1: each material's specific energy is remapped with its
              * own mass fluxes (donor values, as I above); the energy fluxes
@@ -1353,21 +1393,22 @@ static void phase_cell_remap(orc_ctx *x)
             if (x->pm) {
                 for (int q = 0; q < 4; q++) ed[q] = 0.0;
                 for (int m = 0; m < nm; m++) {
-                    double ILc = x->ILm[m][c], minm = 0.0, nIm = 0.0;
+                    double ILc = x->ILm[m][c], tmm[4] = {0}, tIm[4] = {0};
                     for (int q = 0; q < 4; q++) {
                         int dc_ok = di[q] >= 0 && di[q] < NR && dj[q] >= 0 && dj[q] < NZ;
                         if (in[q]) {
                             double Id = dc_ok ? x->ILm[m][CI(di[q], dj[q])] : 0.0;
                             double aF = fabs(Fm[m][q]);
-                            minm += aF;
-                            nIm += aF * (Id - ILc);
+                            tmm[q] = aF;
+                            tIm[q] = aF * (Id - ILc);
                             ed[q] += Fm[m][q] * Id;
                         } else {
                             ed[q] += Fm[m][q] * ILc;
                         }
                     }
+                    double minm = face_sum(tmm), nIm = face_sum(tIm);
                     double denm = dmax(dmax(mu1[m] * V, minm), M_REMAP_FLOOR * x->rho_ref * V);
-                    I1m[m] = ILc + nIm * (1.0 / denm);
+                    I1m[m] = ILc + nIm / denm;
                 }
             }
 
@@ -1380,9 +1421,18 @@ static void phase_cell_remap(orc_ctx *x)
                 /* the layer is a sink that never leaves negative mass (ejecta
                  * crossing the void part of a layer violate the small-fluctuation
                  * assumption of the derivation) */
-                double rho2 = dmax(rho1 - dt * (dsum * (rho1 - x->rref[c]) + (x->phi1b[c] + x->phi1r[c])), 0.0);
+                /* the auxiliaries this step applies: phi1 and phi3, or only
+                 * psi2 (on the energy) as printed */
+                double a1 = x->pml.placement ? 0.0 : x->phi1b[c] + x->phi1r[c];
+                double a3 = x->pml.placement ? x->psi2n[c] : x->phi3b[c] + x->phi3r[c];
+                double rho2 = dmax(rho1 - dt * (dsum * (rho1 - x->rref[c]) + a1), 0.0);
                 double rt_ = dmax(rho1, x->rho_ref * PML_RHO_FLOOR);
-                double I2 = I1 - dt * (dsum * I1 + (x->phi3b[c] + x->phi3r[c]) / rt_);
+                double I2 = I1 - dt * (dsum * I1 + a3 / rt_);
+                if (x->pml.form) {
+                    /* rho I damped toward zero, then divided by the damped mass */
+                    double e1 = rho1 * I1;
+                    I2 = (e1 - dt * (dsum * e1 + a3)) / dmax(rho2, x->rho_ref * PML_RHO_FLOOR);
+                }
                 if (x->pm) {
                     /* every material loses the same fraction of its mass and
                      * the same specific energy */
@@ -1391,7 +1441,7 @@ static void phase_cell_remap(orc_ctx *x)
                     for (int m = 0; m < nm; m++) {
                         mu1[m] = mu1[m] * kap;
                         r2 += mu1[m];
-                        I1m[m] = I1m[m] - dt * (dsum * I1m[m] + (x->phi3b[c] + x->phi3r[c]) / rt_);
+                        I1m[m] = I1m[m] - dt * (dsum * I1m[m] + a3 / rt_);
                     }
                     rho2 = r2;
                 }
@@ -1404,12 +1454,12 @@ static void phase_cell_remap(orc_ctx *x)
                     x->srz_n[c] = x->srz_n[c] - dt * (dsum * x->srz_n[c]);
                 }
                 if (db > 0.0) {
-                    x->phi1b[c] = x->phi1b[c] + db * ((F[1] - F[0]) * iV);
-                    x->phi3b[c] = x->phi3b[c] + db * ((ed[1] - ed[0]) * iV);
+                    x->phi1b[c] = x->phi1b[c] + db * ((F[1] - F[0]) / V);
+                    x->phi3b[c] = x->phi3b[c] + db * ((ed[1] - ed[0]) / V);
                 }
                 if (drr > 0.0) {
-                    x->phi1r[c] = x->phi1r[c] + drr * ((F[3] - F[2]) * iV);
-                    x->phi3r[c] = x->phi3r[c] + drr * ((ed[3] - ed[2]) * iV);
+                    x->phi1r[c] = x->phi1r[c] + drr * ((F[3] - F[2]) / V);
+                    x->phi3r[c] = x->phi3r[c] + drr * ((ed[3] - ed[2]) / V);
                 }
                 rho1 = rho2;
                 I1 = I2;
@@ -1457,7 +1507,7 @@ static void phase_node_remap(orc_ctx *x)
             int qi[4] = {i - 1, i, i - 1, i}, qj[4] = {j - 1, j - 1, j, j};
             for (int q = 0; q < 4; q++) {
                 if (qi[q] < 0 || qi[q] >= NR || qj[q] < 0 || qj[q] >= NZ) continue;
-                M[q] = x->rho[CI(qi[q], qj[q])] * vol_c(x, qi[q], qj[q]);
+                M[q] = x->rhoE[CI(qi[q], qj[q])] * vol_c(x, qi[q], qj[q]);
             }
             double mL = 0.25 * ((M[0] + M[1]) + (M[2] + M[3]));
             /* dual faces W, E, S, N */
@@ -1471,18 +1521,17 @@ static void phase_node_remap(orc_ctx *x)
             if (j == 0) FD[2] = 0.0;
             int ni[4] = {i - 1, i + 1, i, i}, nj[4] = {j, j, j - 1, j + 1};
             int in[4] = {FD[0] > 0.0, FD[1] < 0.0, FD[2] > 0.0, FD[3] < 0.0};
-            double m1 = mL + (((FD[0] - FD[1]) + FD[2]) - FD[3]);
+            double m1 = mL + ((FD[0] - FD[1]) + (FD[2] - FD[3]));
             double vLr = x->vLr[n], vLz = x->vLz[n];
-            double min_ = 0.0, nr = 0.0, nz = 0.0;
-            double upr[4], upz[4];
+            double upr[4], upz[4], tm[4] = {0}, tr[4] = {0}, tz[4] = {0};
             for (int q = 0; q < 4; q++) {
                 int ok = ni[q] >= 0 && ni[q] <= NR && nj[q] >= 0 && nj[q] <= NZ;
                 if (in[q] && ok) {
                     int d = NI(ni[q], nj[q]);
                     double aF = fabs(FD[q]);
-                    min_ += aF;
-                    nr += aF * (x->vLr[d] - vLr);
-                    nz += aF * (x->vLz[d] - vLz);
+                    tm[q] = aF;
+                    tr[q] = aF * (x->vLr[d] - vLr);
+                    tz[q] = aF * (x->vLz[d] - vLz);
                     upr[q] = x->vLr[d];
                     upz[q] = x->vLz[d];
                 } else {
@@ -1490,49 +1539,63 @@ static void phase_node_remap(orc_ctx *x)
                     upz[q] = vLz;
                 }
             }
+            double min_ = face_sum(tm), nr = face_sum(tr), nz = face_sum(tz);
             double aE = i < NR ? x->awc[i] : 0.0;
             double aW = i > 0 ? x->aec[i - 1] : 0.0;
             double hN = j < NZ ? 0.5 * x->dzr[j] : 0.0;
             double hS = j > 0 ? 0.5 * x->dzr[j - 1] : 0.0;
             double Vd = (aE + aW) * (hN + hS);
             double den = dmax(dmax(m1, min_), M_REMAP_FLOOR * x->rho_ref * Vd);
-            double iden = 1.0 / den;
-            double v1r = vLr + nr * iden;
-            double v1z = vLz + nz * iden;
+            double v1r = vLr + nr / den;
+            double v1z = vLz + nz / den;
             /* kinetic energy the donor-cell mixing destroyed, in shift-invariant
              * form (exactly zero for a uniform field, >= 0 by Cauchy-Schwarz),
              * returned as specific heat to the surrounding cells by mass */
-            double kin = 0.0;
+            double tk[4] = {0};
             for (int q = 0; q < 4; q++) {
                 int ok = ni[q] >= 0 && ni[q] <= NR && nj[q] >= 0 && nj[q] <= NZ;
                 if (in[q] && ok) {
                     double ar = upr[q] - vLr, az = upz[q] - vLz;
-                    kin += fabs(FD[q]) * (ar * ar + az * az);
+                    tk[q] = fabs(FD[q]) * (ar * ar + az * az);
                 }
             }
-            double dKE = 0.5 * (kin - (nr * nr + nz * nz) * iden);
-            double Mn = 0.0;
+            double kin = face_sum(tk);
+            double dKE = 0.5 * (kin - (nr * nr + nz * nz) / den);
+            double Mq1[4] = {0, 0, 0, 0};
             for (int q = 0; q < 4; q++) {
                 if (qi[q] < 0 || qi[q] >= NR || qj[q] < 0 || qj[q] >= NZ) continue;
-                Mn += x->rho_n[CI(qi[q], qj[q])] * vol_c(x, qi[q], qj[q]);
+                Mq1[q] = x->rho_n[CI(qi[q], qj[q])] * vol_c(x, qi[q], qj[q]);
             }
+            double Mn = (Mq1[0] + Mq1[1]) + (Mq1[2] + Mq1[3]);
             x->heat[n] = Mn > M_REMAP_FLOOR * x->rho_ref * Vd ? dmax(dKE, 0.0) / Mn : 0.0;
             double db = x->dnz[j], drr = x->dnr[i];
             if (db > 0.0 || drr > 0.0) {
                 double dsum = db + drr;
                 double mt = dmax(m1, M_ACC_EPS * x->rho_ref * Vd);
+                /* the auxiliary this step applies: phi2, or psi1 as printed */
                 double pr = x->phi2b_r[n] + x->phi2r_r[n];
                 double pz = x->phi2b_z[n] + x->phi2r_z[n];
-                double imt = 1.0 / mt, iVd = 1.0 / Vd;
-                double v2r = v1r - dt * (dsum * v1r + (pr * Vd) * imt);
-                double v2z = v1z - dt * (dsum * v1z + (pz * Vd) * imt);
+                if (x->pml.placement) {
+                    pr = x->psi1n_r[n];
+                    pz = x->psi1n_z[n];
+                }
+                double v2r = v1r - dt * (dsum * v1r + (pr * Vd) / mt);
+                double v2z = v1z - dt * (dsum * v1z + (pz * Vd) / mt);
+                if (x->pml.form) {
+                    /* m v damped toward zero, then divided by the damped node
+                     * mass (a quarter of the four damped cell masses) */
+                    double m2 = dmax(0.25 * Mn, M_ACC_EPS * x->rho_ref * Vd);
+                    double pr1 = mt * v1r, pz1 = mt * v1z;
+                    v2r = (pr1 - dt * (dsum * pr1 + pr * Vd)) / m2;
+                    v2z = (pz1 - dt * (dsum * pz1 + pz * Vd)) / m2;
+                }
                 if (db > 0.0) {
-                    x->phi2b_r[n] = x->phi2b_r[n] + db * ((FD[1] * upr[1] - FD[0] * upr[0]) * iVd);
-                    x->phi2b_z[n] = x->phi2b_z[n] + db * ((FD[1] * upz[1] - FD[0] * upz[0]) * iVd);
+                    x->phi2b_r[n] = x->phi2b_r[n] + db * ((FD[1] * upr[1] - FD[0] * upr[0]) / Vd);
+                    x->phi2b_z[n] = x->phi2b_z[n] + db * ((FD[1] * upz[1] - FD[0] * upz[0]) / Vd);
                 }
                 if (drr > 0.0) {
-                    x->phi2r_r[n] = x->phi2r_r[n] + drr * ((FD[3] * upr[3] - FD[2] * upr[2]) * iVd);
-                    x->phi2r_z[n] = x->phi2r_z[n] + drr * ((FD[3] * upz[3] - FD[2] * upz[2]) * iVd);
+                    x->phi2r_r[n] = x->phi2r_r[n] + drr * ((FD[3] * upr[3] - FD[2] * upr[2]) / Vd);
+                    x->phi2r_z[n] = x->phi2r_z[n] + drr * ((FD[3] * upz[3] - FD[2] * upz[2]) / Vd);
                 }
                 v1r = v2r;
                 v1z = v2z;

@@ -71,6 +71,22 @@ typedef struct {
     double R;     /* theoretical reflection coefficient                    */
     double c_ref; /* <=0: the largest longitudinal speed at rest over the  */
                   /* materials                                             */
+    /* Which step applies each auxiliary (Sec. 3 names psi1, psi2 for the
+     * Eulerian step and phi1, phi2, phi3 for the Lagrangian step):
+     *   0 (derived): psi1 in the node force, psi2 in the Lagrangian energy,
+     *     phi1, phi3 in the cell remap, phi2 in the momentum remap;
+     *   1 (as printed): phi2 in the node force, phi1 on the mass and phi3 on
+     *     the energy at the end of the Lagrangian step, psi2 in the cell
+     *     remap, psi1 in the momentum remap.
+     * Every application uses the auxiliary's value at the start of the cycle. */
+    int32_t placement;
+    /* Damped quantity of the momentum and energy equations:
+     *   0: the specific velocity and energy (v -= dt (d v + ...), I likewise);
+     *   1: the conserved densities as Sec. 3 prints them (rho v, rho I damped,
+     *      then divided by the damped mass). Oracle only, placement 0 and the
+     *      shared closure only; it pins that the two forms differ at second
+     *      order in the fluctuation. */
+    int32_t form;
 } orc_pml;
 
 typedef struct {

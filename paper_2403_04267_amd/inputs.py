@@ -93,6 +93,13 @@ class Pml:
     # 1: the layers also relax the deviatoric stress toward zero at the rate d
     # (an extension; Sec. 3 damps mass, momentum and energy only)
     damp_stress: int = 0
+    # which step applies each auxiliary: 0 = psi in the Lagrangian and phi in
+    # the Eulerian step (derived from the equations), 1 = Sec. 3's sentence
+    # as printed (psi in the Eulerian, phi in the Lagrangian step)
+    placement: int = 0
+    # damped quantity: 0 = specific velocity and energy; 1 = rho v and rho I
+    # as Sec. 3's control equations print them (the CPU oracle only)
+    form: int = 0
 
 
 @dataclass

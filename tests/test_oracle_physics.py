@@ -253,10 +253,12 @@ def test_spherical_wave_closed_form(strength):
 # =========================================================================
 # PML reflection against an enlarged domain (Sec. 3 claim)
 # =========================================================================
-def pml_case(n, pml_cells, enabled, zc_from_top, w=4.0, U=1.0, t_end=None):
-    g = inputs.Grid(n_r=n, n_z=n, pml_r=pml_cells, pml_b=pml_cells, q_lin=0.0, q_quad=0.0)
+def pml_case(n, pml_cells, enabled, zc_from_top, w=4.0, U=1.0, t_end=None, placement=0, form=0,
+             top_closed=0):
+    g = inputs.Grid(n_r=n, n_z=n, pml_r=pml_cells, pml_b=pml_cells, q_lin=0.0, q_quad=0.0,
+                    top_closed=top_closed)
     mat = linear_material(False)
-    pb = inputs.Problem(grid=g, mats=[mat], pml=inputs.Pml(enabled=enabled))
+    pb = inputs.Problem(grid=g, mats=[mat], pml=inputs.Pml(enabled=enabled, placement=placement, form=form))
     NZ = g.NZ
     jc = NZ - zc_from_top
     rho, I, f, v = full_state(g, mat.rho0)
@@ -267,11 +269,12 @@ def pml_case(n, pml_cells, enabled, zc_from_top, w=4.0, U=1.0, t_end=None):
     with np.errstate(invalid="ignore", divide="ignore"):
         v[0] = np.where(Rn > 0, vR * rn / Rn, 0.0)
         v[1] = np.where(Rn > 0, vR * zn / Rn, 0.0)
-    g.t_stop = t_end
+    g.t_stop = t_end or 0.0
     o = Oracle(pb.replace(grid=g))
     o.set_fields(rho, I, f, v)
     e0 = 0.5 * mat.rho0 * np.sum((v[0] ** 2 + v[1] ** 2) * node_volumes(g))
-    run_until(o, t_end)
+    if t_end:
+        run_until(o, t_end)
     return o, e0
 
 
@@ -284,29 +287,51 @@ def node_volumes(g):
     return Vn
 
 
-def test_pml_absorbs_outgoing_waves():
+PML_N, PML_P, PML_TOP = 60, 20, 30
+
+
+@pytest.fixture(scope="module")
+def pml_reference():
+    """The pulse on a domain ten times larger (600 x 600 cells, no layers),
+    compared over a window that its walls do not reach in time, and the same
+    pulse on the small domain with plain walls."""
     mat = linear_material(False)
     c = math.sqrt(mat.A / mat.rho0)
-    n, p, top = 60, 20, 30
     t_end = 100.0 / c
-    small, e0 = pml_case(n, p, 1, top, t_end=t_end)
-    bare, _ = pml_case(n, p, 0, top, t_end=t_end)
-    big, _ = pml_case(300, 0, 0, top, t_end=t_end)
-    gs, gb = small.g, big.g
-    Fs, Fn, Fb = small.fields(), bare.fields(), big.fields()
+    big, e0 = pml_case(10 * PML_N, 0, 0, PML_TOP, t_end=t_end)
+    bare, _ = pml_case(PML_N, PML_P, 0, PML_TOP, t_end=t_end)
+    return dict(mat=mat, c=c, t_end=t_end, e0=e0, big=big.fields(), gb=big.g, bare=bare)
+
+
+def reflected_energy(pml_reference, o):
+    """Kinetic plus linear-acoustic energy of the difference against the
+    larger domain over the small domain's interior, per unit pulse energy."""
+    ref = pml_reference
+    mat, c, Fb, gb = ref["mat"], ref["c"], ref["big"], ref["gb"]
+    n, p = PML_N, PML_P
+    gs = o.g
+    F = o.fields()
     off = gb.NZ - gs.NZ  # small row j <-> big row j + off
-    js = slice(p, gs.NZ)
-    jb = slice(p + off, gb.NZ)
+    js, jb = slice(p, gs.NZ), slice(p + off, gb.NZ)
     V = ((np.arange(n) + 0.5))[None, :] * np.ones((gs.NZ - p, 1))
     Vn = node_volumes(gs)[p:gs.NZ + 1, :n + 1]
+    dp = F["p"][js, :n] - Fb["p"][jb, :n]
+    dv = F["v"][:, p:gs.NZ + 1, :n + 1] - Fb["v"][:, p + off:gb.NZ + 1, :n + 1]
+    return (np.sum(dp ** 2 * V) / (2 * mat.rho0 * c * c)
+            + 0.5 * mat.rho0 * np.sum((dv[0] ** 2 + dv[1] ** 2) * Vn)) / ref["e0"]
 
-    def e_refl(F):
-        dp = F["p"][js, :n] - Fb["p"][jb, :n]
-        dv = F["v"][:, p:gs.NZ + 1, :n + 1] - Fb["v"][:, p + off:gb.NZ + 1, :n + 1]
-        return (np.sum(dp ** 2 * V) / (2 * mat.rho0 * c * c)
-                + 0.5 * mat.rho0 * np.sum((dv[0] ** 2 + dv[1] ** 2) * Vn)) / e0
 
-    e_pml, e_bare = e_refl(Fs), e_refl(Fn)
+@pytest.mark.parametrize("placement", [0, 1])
+def test_pml_absorbs_outgoing_waves(pml_reference, placement):
+    """Sec. 3's claim against a domain ten times larger: a pulse leaving
+    through the right and bottom layers sends back < 1 % of its energy and
+    < 5 % of what plain walls send back, with the auxiliaries applied as
+    derived (placement 0: 0.0035, 0.025 of the walls' 0.142) and as Sec. 3's
+    sentence prints them (placement 1: 0.0039, 0.028)."""
+    n, p = PML_N, PML_P
+    small, _ = pml_case(n, p, 1, PML_TOP, t_end=pml_reference["t_end"], placement=placement)
+    e_pml = reflected_energy(pml_reference, small)
+    e_bare = reflected_energy(pml_reference, pml_reference["bare"])
     # the aux fields are live only inside the layers
     aux = small.pml_aux()
     assert np.all(aux["phi1_b"][p:, :] == 0.0) and np.all(aux["phi1_r"][:, :n] == 0.0)
@@ -315,8 +340,55 @@ def test_pml_absorbs_outgoing_waves():
     assert np.any(aux["psi1_b_r"][:p] != 0.0) and np.any(aux["psi1_r_z"][:, n + 1:] != 0.0)
     assert not np.any(aux["psi1_b_z"]) and not np.any(aux["psi1_r_r"])
     assert e_bare > 0.02, e_bare            # walls do reflect without the layers
-    assert e_pml < 0.1 * e_bare, (e_pml, e_bare)
+    assert e_pml < 0.05 * e_bare, (e_pml, e_bare)
     assert e_pml < 0.01, e_pml
+
+
+def test_pml_placements_differ_and_conserve_mass():
+    """The two placements are different schemes (the fields differ at first
+    order in the layers) with the same mass budget: grid mass plus the
+    layers' sink stays the initial mass, to rounding, in both."""
+    out = {}
+    for placement in (0, 1):
+        o, _ = pml_case(PML_N, PML_P, 1, PML_TOP, U=50.0, placement=placement, top_closed=1)
+        m0 = o.diag()["mass"]
+        o.step(150)
+        d = o.diag()
+        assert abs(d["mass"] + d["mass_pml"] - m0) <= 1e-13 * m0, (placement, d)
+        assert d["mass_pml"] != 0.0
+        out[placement] = o.fields()
+    dv = np.linalg.norm(out[1]["v"] - out[0]["v"]) / np.linalg.norm(out[0]["v"])
+    assert dv > 1e-3, dv
+
+
+def test_pml_damped_quantity_differs_at_second_order():
+    """R12: the library damps the specific velocity and energy (v -= dt d v,
+    I likewise), Sec. 3's control equations damp rho v and rho I. Since rho
+    is damped too, the two differ by terms like d (rho - rho0) v: products of
+    two fluctuations. Continuing one state with the pulse inside both layers
+    for one cycle under each form, the velocity difference grows as the
+    square of the amplitude (x4.0 per doubling, against x2 for a first-order
+    difference) and stays below 1e-7 of the field at 1 m/s; the mass is
+    damped alike (bit for bit)."""
+    diffs = []
+    for U in (1.0, 2.0, 4.0):
+        o, _ = pml_case(PML_N, PML_P, 1, PML_TOP, U=U, top_closed=1)
+        o.step(150)  # the pulse is inside both layers
+        pb = inputs.Problem(grid=o.g, mats=[linear_material(False)], pml=inputs.Pml(enabled=1))
+        a = Oracle(pb)
+        a.continue_from(o)
+        b = Oracle(pb.replace(pml=inputs.Pml(enabled=1, form=1)))
+        b.continue_from(o)
+        a.step(1)
+        b.step(1)
+        Fa, Fb = a.fields(), b.fields()
+        assert np.array_equal(Fa["rho"], Fb["rho"])
+        dv = np.linalg.norm(Fb["v"] - Fa["v"])
+        assert dv > 0.0
+        diffs.append((dv, dv / np.linalg.norm(Fa["v"])))
+    assert diffs[0][1] < 1e-7, diffs
+    for (d1, _), (d2, _) in zip(diffs, diffs[1:]):
+        assert 3.6 < d2 / d1 < 4.4, diffs
 
 
 # =========================================================================
@@ -438,14 +510,18 @@ def test_z_mirror_symmetry(strength):
     o.set_fields(rho, I, f, v)
     o.step(25)
     F = o.fields()
-    # Symmetric in exact arithmetic; face sums run W, E, S, N in every cell, so
-    # mirrored cells round differently at the ulp level and the converging
-    # shock amplifies that to ~1e-12. A sign or index error in a z term gives
-    # 1e-3 or more.
-    tol = 1e-11
+    # Symmetric in exact arithmetic, and in floating point too: every sum over
+    # the four faces (or corners) of a cell or node pairs the r terms and the z
+    # terms, so a mirrored cell performs the same operations on mirrored
+    # operands. A sign or index error in a z term gives 1e-3 or more.
+    tol = 1e-12
     for k in ("rho", "I", "p"):
         a = F[k]
         assert np.max(np.abs(a - a[::-1])) <= tol * np.max(np.abs(a)), k
+        # bit for bit away from the two ends, whose boundary conditions differ
+        # (no-slip bottom, open top; the pulse's e^-100 tails reach them)
+        mid = slice(10, g.NZ - 10)
+        assert np.array_equal(a[mid], a[::-1][mid]), k
     vz, vr = F["v"][1], F["v"][0]
     assert np.max(np.abs(vz + vz[::-1])) <= tol * np.max(np.abs(vz))
     assert np.max(np.abs(vr - vr[::-1])) <= tol * np.max(np.abs(vr))
@@ -550,22 +626,40 @@ def test_total_energy_conserved_in_closed_box(strength):
 
 
 def test_fp64_sensitivity_floor():
-    """Conditioning of the impact run itself: two FP64 runs whose initial
-    velocities differ by one ulp agree to ~1e-13 for 100 cycles, then the
-    ejecta amplify the difference to the 1e-4 - 1e-2 level by cycle 500 (how
-    far exactly depends on the rounding of the whole run). No implementation
-    that rounds differently can stay closer than this floor at late times;
-    the mixed-precision checks are set against it."""
+    """Conditioning of the impact run itself. Four FP64 runs whose initial
+    velocities or densities differ from the unperturbed run by one ulp (up,
+    down) agree with it to 1e-12 (velocity) and 1e-11 (density) for 100
+    cycles; then the jetting contact and
+    the ejecta amplify the difference. By cycle 500 the mass-like fields (rho,
+    f), which the remap conserves, differ by 3e-4 to 2e-3, and the pressure and
+    momentum densities, dominated by cells holding traces of matter, by 2e-3
+    to 2.2e-2 depending on which ulp was flipped. No implementation that
+    rounds differently can stay closer than this floor at late times; the
+    mixed-precision checks are set against it."""
     from tests.crater import conserved_errors
     pb = inputs.config_small()
-    a, b = Oracle(pb), Oracle(pb)
-    F = b.fields(eos=False)
-    b.set_fields(F["rho"], F["I"], F["f"], np.nextafter(F["v"], np.inf), F["s"])
+    a = Oracle(pb)
     a.step(100)
-    b.step(100)
-    e100 = conserved_errors(b.fields(), a.fields(), pb.grid)
-    assert max(e100.values()) < 1e-12, e100
+    F100 = a.fields()
     a.step(400)
-    b.step(400)
-    e500 = conserved_errors(b.fields(), a.fields(), pb.grid)
-    assert 1e-6 < max(e500.values()) < 0.2, e500
+    F500 = a.fields()
+    for which in ("v+", "v-", "rho+", "rho-"):
+        b = Oracle(pb)
+        F = b.fields(eos=False)
+        v, rho = F["v"], F["rho"]
+        step = np.inf if which.endswith("+") else -np.inf
+        if which.startswith("v"):
+            v = np.nextafter(v, step)
+        else:
+            rho = np.nextafter(rho, step)
+        b.set_fields(rho, F["I"], F["f"], v, F["s"])
+        b.step(100)
+        e100 = conserved_errors(b.fields(), F100, pb.grid)
+        # a density ulp moves the void-closing split of mixed cells, to which
+        # the volume fractions respond at ~100x rounding
+        assert max(e100.values()) < (1e-12 if which.startswith("v") else 1e-11), (which, e100)
+        b.step(400)
+        e500 = conserved_errors(b.fields(), F500, pb.grid)
+        assert max(e500.values()) > 1e-6, (which, e500)
+        assert max(e500["rho"], e500["f"]) < 1e-2, (which, e500)
+        assert max(e500.values()) < 5e-2, (which, e500)
