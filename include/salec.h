@@ -124,6 +124,21 @@ typedef struct salec_pml {
     double c_ref;        /* damping speed c of Sec. 3's profile (the largest     */
                          /* acoustic speed); <= 0: the largest longitudinal      */
                          /* speed at rest over the materials                     */
+    int32_t placement;   /* which step applies each auxiliary variable of        */
+                         /* Sec. 3 (every application uses its value at the      */
+                         /* start of the cycle):                                 */
+                         /* 0 (derived from the auxiliaries' definitions): psi1  */
+                         /*   in the node force and psi2 in the internal energy  */
+                         /*   of the Lagrangian step; phi1, phi3 in the cell     */
+                         /*   remap and phi2 in the momentum remap (Eulerian);   */
+                         /* 1 (Sec. 3's sentence as printed: psi1, psi2 in the   */
+                         /*   Eulerian step, phi1, phi2, phi3 in the Lagrangian  */
+                         /*   step): phi2 in the node force; phi1 on the mass    */
+                         /*   and phi3 on the energy at the end of the Lagrangian */
+                         /*   step (the remap starts from that mass; the sink    */
+                         /*   budget records it); psi2 in the cell remap, psi1   */
+                         /*   in the momentum remap                              */
+    int32_t reserved;    /* must be 0                                            */
 } salec_pml;
 
 typedef struct salec_scene {

@@ -62,6 +62,12 @@ struct Smem {
   static constexpr int kBigD = (kBig + 7) / 8;
 };
 
+// Sum of four per-face (or per-corner) terms ordered W, E, S, N (or SW, SE,
+// NW, NE): the r pair plus the z pair, as the divergence of Sec. 2 is an r
+// part plus a z part; a reflection in z then maps every sum onto itself
+// exactly.
+__device__ __forceinline__ double face_sum(const double t[4]) { return (t[0] + t[1]) + (t[2] + t[3]); }
+
 __device__ __forceinline__ bool in_cells(const Geo& g, int i, int j) {
   return i >= 0 && i < g.NR && j >= 0 && j < g.NZ;
 }
@@ -262,8 +268,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         f[m] = m < NM ? (T)fd[m] : T(0);
       }
       rh = S.rho[c];
-      T phi, iden, rm;
-      matter(g, (T)rh, f, phi, iden, rm);
+      T phi, den, rm;
+      matter(g, (T)rh, f, phi, den, rm);
       T p = ((const T*)S.eos[0])[c], c2 = ((const T*)S.eos[1])[c], sx = ((const T*)S.eos[4])[c];
       T vr4[4] = {v0r, Sv0[nidx(g, i + 1, j)], Sv0[nidx(g, i, j + 1)], Sv0[nidx(g, i + 1, j + 1)]};
       T vz4[4] = {v0z, Sv1[nidx(g, i + 1, j)], Sv1[nidx(g, i, j + 1)], Sv1[nidx(g, i + 1, j + 1)]};
@@ -273,7 +279,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       T L = tmin(cg.dr, dzj);
       T dDn = dtT * kn.D;
       T Jn = T(1) + dDn;
-      T Dm = Jn < T(1) ? Vol<T>::closing(Jn, dDn, phi, sx) * N::div(T(1), dtT) : T(0);
+      T Dm = Jn < T(1) ? N::div(Vol<T>::closing(Jn, dDn, phi, sx), dtT) : T(0);
       T Ld = L * Dm;
       T Q = rm * (GT::q_quad(g) * Ld * Ld + GT::q_lin(g) * N::sqr(c2) * Ld);
       T P = p + Q;
@@ -352,24 +358,28 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         drr = pm.dnr[i];
         if (j < g.pml_b) kb = pml_bn(g, i, j);
         if (i > g.n_r) kr = pml_rn(g, i, j);
-        double br = kb >= 0 ? po.b_psi1r[kb] : 0.0, bz = kb >= 0 ? po.b_psi1z[kb] : 0.0;
-        double rr = kr >= 0 ? po.r_psi1r[kr] : 0.0, rz = kr >= 0 ? po.r_psi1z[kr] : 0.0;
+        // the auxiliary this step applies: psi1, or phi2 when the layers
+        // follow Sec. 3's sentence as printed
+        const double* ar_b = g.pml_place ? po.b_phi2r : po.b_psi1r;
+        const double* az_b = g.pml_place ? po.b_phi2z : po.b_psi1z;
+        const double* ar_r = g.pml_place ? po.r_phi2r : po.r_psi1r;
+        const double* az_r = g.pml_place ? po.r_phi2z : po.r_psi1z;
+        double br = kb >= 0 ? ar_b[kb] : 0.0, bz = kb >= 0 ? az_b[kb] : 0.0;
+        double rr = kr >= 0 ? ar_r[kr] : 0.0, rz = kr >= 0 ? az_r[kr] : 0.0;
         psr = (T)(br + rr);
         psz = (T)(bz + rz);
       }
       T Fer = Fr - Vd * psr, Fez = Fz - Vd * psz;
-      T imt = N::div(T(1), mt);
-      vLr = vnr + dtT * (Fer * imt);
-      vLz = vnz + dtT * (Fez * imt);
+      vLr = vnr + dtT * N::div(Fer, mt);
+      vLz = vnz + dtT * N::div(Fez, mt);
       if (owns_node(i, j) && (db > 0.0 || drr > 0.0)) {
-        T iVd = N::div(T(1), Vd);
         if (db > 0.0) {
-          pn.b_psi1r[kb] = po.b_psi1r[kb] - dt * db * (double)(Frr * iVd);
-          pn.b_psi1z[kb] = po.b_psi1z[kb] - dt * db * (double)(Fzr * iVd);
+          pn.b_psi1r[kb] = po.b_psi1r[kb] - dt * db * (double)N::div(Frr, Vd);
+          pn.b_psi1z[kb] = po.b_psi1z[kb] - dt * db * (double)N::div(Fzr, Vd);
         }
         if (drr > 0.0) {
-          pn.r_psi1r[kr] = po.r_psi1r[kr] - dt * drr * (double)(Frz * iVd);
-          pn.r_psi1z[kr] = po.r_psi1z[kr] - dt * drr * (double)(Fzz * iVd);
+          pn.r_psi1r[kr] = po.r_psi1r[kr] - dt * drr * (double)N::div(Frz, Vd);
+          pn.r_psi1z[kr] = po.r_psi1z[kr] - dt * drr * (double)N::div(Fzz, Vd);
         }
       }
       if (i == 0 || i == g.NR) vLr = T(0);
@@ -438,7 +448,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       T srr = s0rr, szz = s0zz, srz = s0rz;
       if (g.any_strength) {
         T G = ((const T*)S.eos[2])[c], Y = ((const T*)S.eos[3])[c];
-        T tr3 = ((kn.err + kn.ezz) + kn.ett) * T(1.0 / 3.0);
+        T tr3 = N::div((kn.err + kn.ezz) + kn.ett, T(3));
         T om = kn.om;
         T dsrr = T(2) * G * (kn.err - tr3) + T(2) * om * srz;
         T dszz = T(2) * G * (kn.ezz - tr3) - T(2) * om * srz;
@@ -468,8 +478,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         if (m < NM) fn[m] = kKeepA ? reg_get(rF[m], u) : (m < g.nmat ? S.f[m][c] : 0.0);
         fq[m] = m < NM ? (T)fn[m] : T(0);
       }
-      T phi, iden, rm;
-      matter(g, (T)rho, fq, phi, iden, rm);
+      T phi, den, rm;
+      matter(g, (T)rho, fq, phi, den, rm);
       T Jm = Vol<T>::ratio(J, dD, phi, kKeepA ? reg_get(rSx, u) : ((const T*)S.eos[4])[c]);
       T Wdt = dtT * sde - P * Vol<T>::jm1(J, dD);
       T rden = tmax(rm, GT::rho_ref(g) * T(kRhoDenFloor));
@@ -478,10 +488,9 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
 #pragma unroll
       for (int q = 0; q < 4; q++) kd[q] = s_kd[nb[q]];
       T V = cg.az * dzj;
-      T iV = N::div(T(1), V);
       T hdz = T(0.5) * dzj;
-      T wW = (cg.aw * hdz) * iV;
-      T wE = (cg.ae * hdz) * iV;
+      T wW = N::div(cg.aw * hdz, V);
+      T wE = N::div(cg.ae * hdz, V);
       T hL = wW * (kd[0] + kd[2]) + wE * (kd[1] + kd[3]);
       double psi2 = 0.0, db = 0.0, drr = 0.0;
       long long kb = -1, kr = -1;
@@ -490,8 +499,19 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         drr = pm.dcr[i];
         if (j < g.pml_b) kb = pml_bc(g, i, j);
         if (i >= g.n_r) kr = pml_rc(g, i, j);
-        double b = kb >= 0 ? po.b_psi2[kb] : 0.0, r = kr >= 0 ? po.r_psi2[kr] : 0.0;
+        // the auxiliary this step applies to the energy: psi2, or phi3 as
+        // printed (which then also applies phi1 to the mass below)
+        const double* a_b = g.pml_place ? po.b_phi3 : po.b_psi2;
+        const double* a_r = g.pml_place ? po.r_phi3 : po.r_psi2;
+        double b = kb >= 0 ? a_b[kb] : 0.0, r = kr >= 0 ? a_r[kr] : 0.0;
         psi2 = b + r;
+      }
+      // the mass the Eulerian step starts from: with the printed placement
+      // phi1 leaves the layer cell here (never below zero mass)
+      double rhoE = rho;
+      if (g.pml_place && (db > 0.0 || drr > 0.0)) {
+        double b = kb >= 0 ? po.b_phi1[kb] : 0.0, r = kr >= 0 ? po.r_phi1[kr] : 0.0;
+        rhoE = dmax(rho - dt * (b + r), 0.0);
       }
       double IL = 0.0;
       if constexpr (!PM) {
@@ -504,7 +524,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
 #pragma unroll
         for (int m = 0; m < NM; m++)
           if (m < g.nmat) phid += fn[m];
-        const double rmd = rho * (1.0 / (phid > kPhiEps ? phid : kPhiEps));
+        const double rmd = rho / (phid > kPhiEps ? phid : kPhiEps);
         const T Q = reg_get(rQ, u);
         const T jm1 = Vol<T>::jm1(J, dD);
         const double iJ = (double)J;
@@ -517,7 +537,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
           const T Wm = dtT * sde - Pm * jm1;
           const T rdm = tmax((T)rmm, GT::rho_ref(g) * T(kRhoDenFloor));
           oILm[m] = ((S.Im[m][c] + (double)N::div(Wm, rdm)) + (double)hL) - dt * (psi2 / rt);
-          oMuL[m] = mud / iJ;
+          const double kap = rho > 0.0 ? rhoE / rho : 0.0;
+          oMuL[m] = (rhoE == rho ? mud : mud * kap) / iJ;
         }
       }
       double fr = (double)N::div(Jm, J);
@@ -534,7 +555,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
           pn.r_psi2[kr] = po.r_psi2[kr] - dt * drr * (double)(phi * Wz);
         }
       }
-      oRhoL = rho / (double)J;
+      oRhoL = rhoE / (double)J;
+      if (rhoE != rho) s_rho[kA(i, j)] = rhoE;  // E2 and F start from it (B is done with rho^n)
       oIL = IL;
       os0 = srr;
       os1 = szz;
@@ -574,7 +596,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     int kc = kC(i, j);
     T J = ct[0 * R::NC + kc];
     T dW = dv_r(i, j), dE = dv_r(i + 1, j), dS = dv_z(i, j), dN = dv_z(i, j + 1);
-    T O = ((tmax(-dW, T(0)) + tmax(dE, T(0))) + tmax(-dS, T(0))) + tmax(dN, T(0));
+    T O = (tmax(-dW, T(0)) + tmax(dE, T(0))) + (tmax(-dS, T(0)) + tmax(dN, T(0)));
     T VL = volT(i, j) * J;
     ct[0 * R::NC + kc] = O > VL ? N::div(tmax(VL, T(0)), O) : T(1);
   }
@@ -648,17 +670,12 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       const int dk[4] = {kC(i - 1, j), kC(i + 1, j), kC(i, j - 1), kC(i, j + 1)};
       const bool inq[4] = {dV[0] > T(0), dV[1] < T(0), dV[2] > T(0), dV[3] < T(0)};
       int kc = kC(i, j);
-      double iV = 1.0 / V;
-      double netin = ((F[0] - F[1]) + F[2]) - F[3];
-      rho1 = s_rho[kA(i, j)] + netin * iV;
+      double netin = (F[0] - F[1]) + (F[2] - F[3]);
+      rho1 = s_rho[kA(i, j)] + netin / V;
       double M1 = rho1 * V;
-      double min_ = 0.0, nI = 0.0, nsrr = 0.0, nszz = 0.0, nsrz = 0.0, vcut = 0.0;
-      double nf[NM], fL[NM];
+      double fL[NM];
 #pragma unroll
-      for (int m = 0; m < NM; m++) {
-        nf[m] = 0.0;
-        fL[m] = cd[(kFo + m) * R::NC + kc];
-      }
+      for (int m = 0; m < NM; m++) fL[m] = cd[(kFo + m) * R::NC + kc];
       // per-material closure: every material's face mass fluxes (the terms E1
       // summed), its new partial density, and rho as their sum
       double Fm[PM ? NM : 1][4], mu1[PM ? NM : 1];
@@ -676,42 +693,56 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
             if (dV[q] > T(0) || dV[q] < T(0))
               Fm[m][q] = ((double)dV[q] * (double)ct[0 * R::NC + d]) * cd[m * R::NC + d];
           }
-          const double nin = ((Fm[m][0] - Fm[m][1]) + Fm[m][2]) - Fm[m][3];
-          mu1[m] = S.mu[m][cidx(g, i, j)] + nin * iV;
+          const double nin = (Fm[m][0] - Fm[m][1]) + (Fm[m][2] - Fm[m][3]);
+          double mu0 = S.mu[m][cidx(g, i, j)];
+          if (g.pml_place) {  // the printed placement's phi1 in the Lagrangian step
+            const double rn = S.rho[cidx(g, i, j)], rE = s_rho[kA(i, j)];
+            if (rE != rn) mu0 = mu0 * (rn > 0.0 ? rE / rn : 0.0);
+          }
+          mu1[m] = mu0 + nin / V;
           rho1 += mu1[m];
         }
         M1 = rho1 * V;
       }
       double IL = PM ? 0.0 : cd[1 * R::NC + kc];
       double sL0 = (double)ct[1 * R::NC + kc], sL1 = (double)ct[2 * R::NC + kc], sL2 = (double)ct[3 * R::NC + kc];
-      double ed[4];
+      // per-face inflow terms (zero on outflow faces), each sum pairing the
+      // r faces and the z faces
+      double ed[4], tm[4], tI[4], ts0[4], ts1[4], ts2[4], tcut[4], tf[NM][4];
 #pragma unroll
       for (int q = 0; q < 4; q++) {
         // e = dV * lambda of the donor (the own cell on outflow faces)
         int d = inq[q] ? dk[q] : kc;
+        tm[q] = tI[q] = ts0[q] = ts1[q] = ts2[q] = tcut[q] = 0.0;
+#pragma unroll
+        for (int m = 0; m < NM; m++) tf[m][q] = 0.0;
         if (inq[q]) {
           double adV = fabs((double)dV[q] * (double)ct[0 * R::NC + d]);
           double aF = fabs(F[q]);
-          vcut += fabs((double)dV[q]) - adV;
+          tcut[q] = fabs((double)dV[q]) - adV;
           double Id = PM ? 0.0 : cd[1 * R::NC + d];
-          min_ += aF;
-          nI += aF * (Id - IL);
-          nsrr += aF * ((double)ct[1 * R::NC + d] - sL0);
-          nszz += aF * ((double)ct[2 * R::NC + d] - sL1);
-          nsrz += aF * ((double)ct[3 * R::NC + d] - sL2);
+          tm[q] = aF;
+          tI[q] = aF * (Id - IL);
+          ts0[q] = aF * ((double)ct[1 * R::NC + d] - sL0);
+          ts1[q] = aF * ((double)ct[2 * R::NC + d] - sL1);
+          ts2[q] = aF * ((double)ct[3 * R::NC + d] - sL2);
 #pragma unroll
           for (int m = 0; m < NM; m++)
-            if (m == 0 || m < g.nmat) nf[m] += adV * (cd[(kFo + m) * R::NC + d] - fL[m]);
+            if (m == 0 || m < g.nmat) tf[m][q] = adV * (cd[(kFo + m) * R::NC + d] - fL[m]);
           ed[q] = F[q] * Id;
         } else {
           ed[q] = F[q] * IL;
         }
       }
+      const double min_ = face_sum(tm), nI = face_sum(tI), vcut = face_sum(tcut);
+      const double nsrr = face_sum(ts0), nszz = face_sum(ts1), nsrz = face_sum(ts2);
+      double nf[NM];
+#pragma unroll
+      for (int m = 0; m < NM; m++) nf[m] = face_sum(tf[m]);
       double lam = (double)ct[0 * R::NC + kc];
-      double O = (double)(((tmax(-dV[0], T(0)) + tmax(dV[1], T(0))) + tmax(-dV[2], T(0))) + tmax(dV[3], T(0)));
+      double O = (double)((tmax(-dV[0], T(0)) + tmax(dV[1], T(0))) + (tmax(-dV[2], T(0)) + tmax(dV[3], T(0))));
       double den = dmax(dmax(M1, min_), kMRemapFloor * g.rho_ref * V);
-      double iden = 1.0 / den;
-      double I1 = IL + nI * iden;
+      double I1 = IL + nI / den;
       // per-material closure: every material's specific energy remapped with
       // its own mass fluxes (donor values); the energy fluxes are the sums
       // over materials
@@ -724,27 +755,29 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
           I1m[m] = 0.0;
           if (m >= g.nmat) continue;
           const double ILc = cd[(NM + m) * R::NC + kc];
-          double minm = 0.0, nIm = 0.0;
+          double tmm[4], tIm[4];
 #pragma unroll
           for (int q = 0; q < 4; q++) {
+            tmm[q] = tIm[q] = 0.0;
             if (inq[q]) {
               const double Id = cd[(NM + m) * R::NC + dk[q]];
               const double aF = fabs(Fm[m][q]);
-              minm += aF;
-              nIm += aF * (Id - ILc);
+              tmm[q] = aF;
+              tIm[q] = aF * (Id - ILc);
               ed[q] += Fm[m][q] * Id;
             } else {
               ed[q] += Fm[m][q] * ILc;
             }
           }
+          const double minm = face_sum(tmm), nIm = face_sum(tIm);
           const double denm = dmax(dmax(mu1[m] * V, minm), kMRemapFloor * g.rho_ref * V);
-          I1m[m] = ILc + nIm * (1.0 / denm);
+          I1m[m] = ILc + nIm / denm;
         }
       }
       double ex = (1.0 - lam) * O - vcut;
       double f1v[NM];
 #pragma unroll
-      for (int m = 0; m < NM; m++) f1v[m] = (m == 0 || m < g.nmat) ? dmax(fL[m] + (nf[m] + fL[m] * ex) * iV, 0.0) : 0.0;
+      for (int m = 0; m < NM; m++) f1v[m] = (m == 0 || m < g.nmat) ? dmax(fL[m] + (nf[m] + fL[m] * ex) / V, 0.0) : 0.0;
       double fs = f1v[0];
 #pragma unroll
       for (int m = 1; m < NM; m++)
@@ -760,9 +793,16 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
           if (g.damp_stress) sdamp = dsum;
           double p1b = kb >= 0 ? po.b_phi1[kb] : 0.0, p1r = kr >= 0 ? po.r_phi1[kr] : 0.0;
           double p3b = kb >= 0 ? po.b_phi3[kb] : 0.0, p3r = kr >= 0 ? po.r_phi3[kr] : 0.0;
-          double rho2 = dmax(rho1 - dt * (dsum * (rho1 - pm.rref[ku]) + (p1b + p1r)), 0.0);
+          // the auxiliaries this step applies: phi1 and phi3, or only psi2
+          // (on the energy) as printed
+          double a1 = p1b + p1r, a3 = p3b + p3r;
+          if (g.pml_place) {
+            a1 = 0.0;
+            a3 = (kb >= 0 ? po.b_psi2[kb] : 0.0) + (kr >= 0 ? po.r_psi2[kr] : 0.0);
+          }
+          double rho2 = dmax(rho1 - dt * (dsum * (rho1 - pm.rref[ku]) + a1), 0.0);
           double rt = dmax(rho1, g.rho_ref * kPmlRhoFloor);
-          double I2 = I1 - dt * (dsum * I1 + (p3b + p3r) / rt);
+          double I2 = I1 - dt * (dsum * I1 + a3 / rt);
           if constexpr (PM) {
             // every material loses the same fraction of its mass and the same
             // specific energy
@@ -773,19 +813,22 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
               if (m >= g.nmat) continue;
               mu1[m] = mu1[m] * kap;
               r2 += mu1[m];
-              I1m[m] = I1m[m] - dt * (dsum * I1m[m] + (p3b + p3r) / rt);
+              I1m[m] = I1m[m] - dt * (dsum * I1m[m] + a3 / rt);
             }
             rho2 = r2;
           }
           if (own) {
-            pm.msink[ku] = pm.msink[ku] + V * (rho1 - rho2);
+            double sink = pm.msink[ku];
+            // the printed placement's phi1 left the cell in the Lagrangian step
+            if (g.pml_place) sink = sink + V * (S.rho[cidx(g, i, j)] - s_rho[kA(i, j)]);
+            pm.msink[ku] = sink + V * (rho1 - rho2);
             if (db > 0.0) {
-              pn.b_phi1[kb] = p1b + db * ((F[1] - F[0]) * iV);
-              pn.b_phi3[kb] = p3b + db * ((ed[1] - ed[0]) * iV);
+              pn.b_phi1[kb] = p1b + db * ((F[1] - F[0]) / V);
+              pn.b_phi3[kb] = p3b + db * ((ed[1] - ed[0]) / V);
             }
             if (drr > 0.0) {
-              pn.r_phi1[kr] = p1r + drr * ((F[3] - F[2]) * iV);
-              pn.r_phi3[kr] = p3r + drr * ((ed[3] - ed[2]) * iV);
+              pn.r_phi1[kr] = p1r + drr * ((F[3] - F[2]) / V);
+              pn.r_phi3[kr] = p3r + drr * ((ed[3] - ed[2]) / V);
             }
           }
           rho1 = rho2;
@@ -795,14 +838,13 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       if (own) {
         long long c = cidx(g, i, j);
         D.rho[c] = rho1;
-        double ifs = 1.0 / dmax(fs, 1.0);
         double fv[NM];
 #pragma unroll
         for (int m = 0; m < NM; m++) {
-          fv[m] = f1v[m] * ifs;
+          fv[m] = f1v[m] / dmax(fs, 1.0);
           if (m == 0 || m < g.nmat) D.f[m][c] = fv[m];
         }
-        T s0n = (T)(sL0 + nsrr * iden), s1n = (T)(sL1 + nszz * iden), s2n = (T)(sL2 + nsrz * iden);
+        T s0n = (T)(sL0 + nsrr / den), s1n = (T)(sL1 + nszz / den), s2n = (T)(sL2 + nsrz / den);
         if (sdamp > 0.0) {  // extension: relax toward the initial (zero) deviator
           const double a0 = (double)s0n, a1 = (double)s1n, a2 = (double)s2n;
           s0n = (T)(a0 - dt * (sdamp * a0));
@@ -874,22 +916,23 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     if (j == 0) FD[2] = 0.0;
     const int ni[4] = {i - 1, i + 1, i, i}, nj[4] = {j, j, j - 1, j + 1};
     const bool inq[4] = {FD[0] > 0.0, FD[1] < 0.0, FD[2] > 0.0, FD[3] < 0.0};
-    double m1 = mL + (((FD[0] - FD[1]) + FD[2]) - FD[3]);
+    double m1 = mL + ((FD[0] - FD[1]) + (FD[2] - FD[3]));
     int kb0 = kB(i, j);
     T vLr = s_vL[kb0], vLz = s_vL[R::NB + kb0];
-    double min_ = 0.0, nr = 0.0, nz = 0.0, kin = 0.0;
     T upr[4], upz[4];
     bool ok[4];
+    double tm[4], tr[4], tz[4], tk[4];
 #pragma unroll
     for (int q = 0; q < 4; q++) {
       ok[q] = ni[q] >= 0 && ni[q] <= g.NR && nj[q] >= 0 && nj[q] <= g.NZ;
+      tm[q] = tr[q] = tz[q] = tk[q] = 0.0;
       if (inq[q] && ok[q]) {
         int d = kB(ni[q], nj[q]);
         double aF = fabs(FD[q]);
         T ur = s_vL[d], uz = s_vL[R::NB + d];
-        min_ += aF;
-        nr += aF * (double)(ur - vLr);
-        nz += aF * (double)(uz - vLz);
+        tm[q] = aF;
+        tr[q] = aF * (double)(ur - vLr);
+        tz[q] = aF * (double)(uz - vLz);
         upr[q] = ur;
         upz[q] = uz;
       } else {
@@ -897,27 +940,28 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         upz[q] = vLz;
       }
     }
+    const double min_ = face_sum(tm), nr = face_sum(tr), nz = face_sum(tz);
     double aE = i < g.NR ? colD(i).aw : 0.0;
     double aW = i > 0 ? colD(i - 1).ae : 0.0;
     double hN = j < g.NZ ? 0.5 * dzD(j) : 0.0;
     double hS = j > 0 ? 0.5 * dzD(j - 1) : 0.0;
     double Vd = (aE + aW) * (hN + hS);
     double den = dmax(dmax(m1, min_), kMRemapFloor * g.rho_ref * Vd);
-    double iden = 1.0 / den;
-    double v1r = (double)vLr + nr * iden;
-    double v1z = (double)vLz + nz * iden;
+    double v1r = (double)vLr + nr / den;
+    double v1z = (double)vLz + nz / den;
 #pragma unroll
     for (int q = 0; q < 4; q++) {
       if (inq[q] && ok[q]) {
         T ar = upr[q] - vLr, az = upz[q] - vLz;
-        kin += fabs(FD[q]) * (double)(ar * ar + az * az);
+        tk[q] = fabs(FD[q]) * (double)(ar * ar + az * az);
       }
     }
-    double dKE = 0.5 * (kin - (nr * nr + nz * nz) * iden);
-    double Mn = 0.0;
+    const double kin = face_sum(tk);
+    double dKE = 0.5 * (kin - (nr * nr + nz * nz) / den);
+    double Mq1[4];
 #pragma unroll
-    for (int q = 0; q < 4; q++)
-      if (qok[q]) Mn += s_rho1[kE(qi[q], qj[q])] * volD(qi[q], qj[q]);
+    for (int q = 0; q < 4; q++) Mq1[q] = qok[q] ? s_rho1[kE(qi[q], qj[q])] * volD(qi[q], qj[q]) : 0.0;
+    const double Mn = face_sum(Mq1);
     double h = Mn > kMRemapFloor * g.rho_ref * Vd ? dmax(dKE, 0.0) / Mn : 0.0;
     bool own = owns_node(i, j);
     if (g.pml_on) {
@@ -929,18 +973,22 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         double mt = dmax(m1, kMAccEps * g.rho_ref * Vd);
         double bpr = kb >= 0 ? po.b_phi2r[kb] : 0.0, bpz = kb >= 0 ? po.b_phi2z[kb] : 0.0;
         double rpr = kr >= 0 ? po.r_phi2r[kr] : 0.0, rpz = kr >= 0 ? po.r_phi2z[kr] : 0.0;
+        // the auxiliary this step applies: phi2, or psi1 as printed
         double pr = bpr + rpr, pz = bpz + rpz;
-        double imt = 1.0 / mt, iVd = 1.0 / Vd;
-        double v2r = v1r - dt * (dsum * v1r + (pr * Vd) * imt);
-        double v2z = v1z - dt * (dsum * v1z + (pz * Vd) * imt);
+        if (g.pml_place) {
+          pr = (kb >= 0 ? po.b_psi1r[kb] : 0.0) + (kr >= 0 ? po.r_psi1r[kr] : 0.0);
+          pz = (kb >= 0 ? po.b_psi1z[kb] : 0.0) + (kr >= 0 ? po.r_psi1z[kr] : 0.0);
+        }
+        double v2r = v1r - dt * (dsum * v1r + (pr * Vd) / mt);
+        double v2z = v1z - dt * (dsum * v1z + (pz * Vd) / mt);
         if (own) {
           if (db > 0.0) {
-            pn.b_phi2r[kb] = bpr + db * ((FD[1] * (double)upr[1] - FD[0] * (double)upr[0]) * iVd);
-            pn.b_phi2z[kb] = bpz + db * ((FD[1] * (double)upz[1] - FD[0] * (double)upz[0]) * iVd);
+            pn.b_phi2r[kb] = bpr + db * ((FD[1] * (double)upr[1] - FD[0] * (double)upr[0]) / Vd);
+            pn.b_phi2z[kb] = bpz + db * ((FD[1] * (double)upz[1] - FD[0] * (double)upz[0]) / Vd);
           }
           if (drr > 0.0) {
-            pn.r_phi2r[kr] = rpr + drr * ((FD[3] * (double)upr[3] - FD[2] * (double)upr[2]) * iVd);
-            pn.r_phi2z[kr] = rpz + drr * ((FD[3] * (double)upz[3] - FD[2] * (double)upz[2]) * iVd);
+            pn.r_phi2r[kr] = rpr + drr * ((FD[3] * (double)upr[3] - FD[2] * (double)upr[2]) / Vd);
+            pn.r_phi2z[kr] = rpz + drr * ((FD[3] * (double)upz[3] - FD[2] * (double)upz[2]) / Vd);
           }
         }
         v1r = v2r;

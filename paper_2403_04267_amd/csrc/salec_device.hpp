@@ -39,7 +39,9 @@ struct MatT {
   T gfac;         // shear / bulk modulus ratio (0: no strength)
   T Y0, mu_f, Ylim;
   T pcav;         // cavitation pressure ramp
-  T irho0, Ar, idE, iYd;  // 1/rho0, A/rho0, 1/(Ecv - Eiv), 1/(Ylim - Y0)
+  // 1/rho0, A/rho0, 1/(Ecv - Eiv), 1/(Ylim - Y0), formed once on the host in
+  // FP64; only the FP32 arithmetic uses them (FP64 divides as the method does)
+  T irho0, Ar, idE, iYd;
   int strength, pad;
 };
 using MatC = MatT<double>;
@@ -55,6 +57,8 @@ struct Geo {
   int stretched;       // per-column widths / per-row heights from the geometry table
   int closure;         // 0: shared material density and energy; 1: per material
   int damp_stress;     // the PML layers also relax the deviatoric stress (extension)
+  int pml_place;       // 1: phi in the Lagrangian and psi in the Eulerian step
+  int pad_i;
   double dr, dz, cfl, dt_grow, dt_max, dt_floor, t_stop, q_lin, q_quad;
   double rho_ref;
   float drf, dzf, q_linf, q_quadf, rho_reff, pad_f;
@@ -201,15 +205,22 @@ __device__ inline double exp_cw(double x) {
 // Elementary operations of the bulk type. FP64 keeps IEEE division, square
 // root and the fixed exponential above (reproducible to the bit); the mixed
 // mode's FP32 uses the hardware reciprocal, square root and exponential.
+// divk(a, b, ib) and qk(a, b, q) divide by a material constant b: FP64 forms
+// the quotient a / b, FP32 multiplies by the reciprocal ib (or takes the
+// quotient q) the host formed once.
 template <class T> struct Num;
 template <> struct Num<double> {
   static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+  static __device__ __forceinline__ double divk(double a, double b, double) { return a / b; }
+  static __device__ __forceinline__ double qk(double a, double b, double) { return a / b; }
   static __device__ __forceinline__ double sqr(double a) { return sqrt(a); }
   static __device__ __forceinline__ double ex(double a) { return exp_cw(a); }
   static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
 };
 template <> struct Num<float> {
   static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+  static __device__ __forceinline__ float divk(float a, float, float ib) { return a * ib; }
+  static __device__ __forceinline__ float qk(float, float, float q) { return q; }
   static __device__ __forceinline__ float sqr(float a) { return __builtin_sqrtf(a); }
   static __device__ __forceinline__ float ex(float a) { return __expf(a); }
   static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
@@ -224,16 +235,15 @@ template <class T> __device__ __forceinline__ T tmin(T a, T b) { return a < b ? 
 // most of their digits in weak waves.
 template <class T>
 struct Dens {
-  T r, ir, eta, mu, z;
+  T r, eta, mu, z;
 };
 __device__ __forceinline__ Dens<double> dens_terms(const MatC& m, double rho, double*) {
   Dens<double> d;
   double rf = m.rho0 * kRhoEosFloor;
   d.r = rho > rf ? rho : rf;
-  d.ir = 1.0 / d.r;
-  d.eta = d.r / m.rho0;  // a true division: eta = 1 exactly at rho0
+  d.eta = d.r / m.rho0;
   d.mu = d.eta - 1.0;
-  d.z = m.rho0 * d.ir - 1.0;
+  d.z = 1.0 / d.eta - 1.0;
   return d;
 }
 __device__ __forceinline__ Dens<float> dens_terms(const MatC& m, double rho, float*) {
@@ -243,7 +253,6 @@ __device__ __forceinline__ Dens<float> dens_terms(const MatC& m, double rho, flo
   double rf = m.rho0 * kRhoEosFloor;
   double r = rho > rf ? rho : rf;
   d.r = (float)r;
-  d.ir = Num<float>::div(1.0f, d.r);
   d.mu = (float)((r - m.rho0) * m.irho0);
   d.eta = 1.0f + d.mu;
   d.z = -Num<float>::div(d.mu, d.eta);
@@ -255,14 +264,14 @@ __device__ __forceinline__ Dens<float> dens_terms(const MatC& m, double rho, flo
 template <class T>
 __device__ inline void tillotson(const MatT<T>& m, const Dens<T>& d, T e, T& p_out, T& c2_out) {
   using N = Num<T>;
-  const T r = d.r, eta = d.eta, mu = d.mu, ir = d.ir;
-  const T irr = ir * ir;
+  const T r = d.r, eta = d.eta, mu = d.mu;
   T E = e > T(0) ? e : T(0);
   T w = N::div(E, m.E0 * eta * eta) + T(1);
-  T iw = N::div(T(1), w), iw2 = iw * iw;
-  T pc = (m.a + m.b * iw) * r * E + m.A * mu + m.B * mu * mu;
-  T pc_E = r * (m.a + m.b * iw - m.b * (w - T(1)) * iw2);
-  T pc_r = (m.a + m.b * iw) * E + T(2) * m.b * E * (w - T(1)) * iw2 + (m.A + T(2) * m.B * mu) * m.irho0;
+  T bw = N::div(m.b, w);
+  T pc = (m.a + bw) * r * E + m.A * mu + m.B * mu * mu;
+  T pc_E = r * (m.a + bw - N::div(m.b * (w - T(1)), w * w));
+  T pc_r = (m.a + bw) * E + N::div(T(2) * m.b * E * (w - T(1)), w * w) +
+           N::divk(m.A + T(2) * m.B * mu, m.rho0, m.irho0);
   T p, dpdE, dpdr;
   if (r >= m.rho0 || E <= m.Eiv) {
     p = pc;
@@ -272,24 +281,27 @@ __device__ inline void tillotson(const MatT<T>& m, const Dens<T>& d, T e, T& p_o
     T z = d.z;
     T ea = N::ex(-m.alpha * z * z);
     T eb = N::ex(-m.beta * z);
-    T pe = m.a * r * E + (m.b * r * E * iw + m.A * mu * eb) * ea;
-    T pe_E = m.a * r + ea * m.b * r * (iw - (w - T(1)) * iw2);
+    T rr = r * r;
+    T brw = N::div(m.b * r * E, w);
+    T pe = m.a * r * E + (brw + m.A * mu * eb) * ea;
+    T pe_E = m.a * r + ea * m.b * r * (N::div(T(1), w) - N::div(w - T(1), w * w));
     T pe_r = m.a * E +
-             ea * (m.b * E * iw + T(2) * m.b * E * (w - T(1)) * iw2 + m.Ar * eb + m.A * mu * m.beta * eb * m.rho0 * irr) +
-             (m.b * r * E * iw + m.A * mu * eb) * ea * T(2) * m.alpha * z * m.rho0 * irr;
+             ea * (N::div(m.b * E, w) + N::div(T(2) * m.b * E * (w - T(1)), w * w) + N::qk(m.A, m.rho0, m.Ar) * eb +
+                   N::div(m.A * mu * m.beta * eb * m.rho0, rr)) +
+             N::div((brw + m.A * mu * eb) * ea * T(2) * m.alpha * z * m.rho0, rr);
     if (E >= m.Ecv) {
       p = pe;
       dpdE = pe_E;
       dpdr = pe_r;
     } else {
-      T x = (E - m.Eiv) * m.idE;
+      T x = N::divk(E - m.Eiv, m.Ecv - m.Eiv, m.idE);
       p = x * pe + (T(1) - x) * pc;
-      dpdE = x * pe_E + (T(1) - x) * pc_E + (pe - pc) * m.idE;
+      dpdE = x * pe_E + (T(1) - x) * pc_E + N::divk(pe - pc, m.Ecv - m.Eiv, m.idE);
       dpdr = x * pe_r + (T(1) - x) * pc_r;
     }
   }
   p_out = p;
-  c2_out = dpdr + p * irr * dpdE;
+  c2_out = dpdr + N::div(p, r * r) * dpdE;
 }
 
 // intact-rock yield curve (Table 1 parameters)
@@ -298,7 +310,7 @@ __device__ inline T yield_strength(const MatT<T>& m, T p) {
   if (!m.strength) return T(0);
   if (p >= T(0)) {
     T mp = m.mu_f * p;
-    return m.Y0 + Num<T>::div(mp, T(1) + mp * m.iYd);
+    return m.Y0 + Num<T>::div(mp, T(1) + Num<T>::divk(mp, m.Ylim - m.Y0, m.iYd));
   }
   return tmax(T(0), m.Y0 + m.mu_f * p);
 }
@@ -307,7 +319,7 @@ __device__ inline T yield_strength(const MatT<T>& m, T p) {
 template <class T>
 __device__ inline T softening(const MatT<T>& m, T e) {
   T E = e > T(0) ? e : T(0);
-  return tmin(tmax((m.Ecv - E) * m.idE, T(0)), T(1));
+  return tmin(tmax(Num<T>::divk(m.Ecv - E, m.Ecv - m.Eiv, m.idE), T(0)), T(1));
 }
 
 template <class T>
@@ -315,16 +327,16 @@ struct Mix {
   T p, c2, G, Y, rmat, phi, sx;
 };
 
-// volume fraction of matter and the shared material density of a mixed cell
+// volume fraction of matter, its floored value den (the weights of the
+// materials are f_m / den) and the shared material density of a mixed cell
 template <class T>
-__device__ __forceinline__ void matter(const Geo& g, T rho, const T* f, T& phi, T& iden, T& rm) {
+__device__ __forceinline__ void matter(const Geo& g, T rho, const T* f, T& phi, T& den, T& rm) {
   phi = T(0);
 #pragma unroll
   for (int m = 0; m < kMaxMat; m++)
     if (m < g.nmat) phi += f[m];
-  T den = phi > T(kPhiEps) ? phi : T(kPhiEps);
-  iden = Num<T>::div(T(1), den);
-  rm = rho * iden;
+  den = phi > T(kPhiEps) ? phi : T(kPhiEps);
+  rm = Num<T>::div(rho, den);
 }
 
 // Mixed-cell state from the FP64 cell state (rho, I, f): all materials
@@ -338,14 +350,14 @@ __device__ inline Mix<T> mixture(const Geo& g, double rho, double I, const doubl
   T f[kMaxMat];
 #pragma unroll
   for (int m = 0; m < kMaxMat; m++) f[m] = m < g.nmat ? (T)fd[m] : T(0);
-  T phi, iden, rm;
-  matter(g, (T)rho, f, phi, iden, rm);
+  T phi, den, rm;
+  matter(g, (T)rho, f, phi, den, rm);
   // material density for the density terms, in FP64
   double phid = 0.0;
 #pragma unroll
   for (int m = 0; m < kMaxMat; m++)
     if (m < g.nmat) phid += fd[m];
-  double rmd = rho * (1.0 / (phid > kPhiEps ? phid : kPhiEps));
+  double rmd = rho / (phid > kPhiEps ? phid : kPhiEps);
   T Ie = (T)I;
   T p = T(0), c2 = T(0), G = T(0);
   T wm[kMaxMat], pmv[kMaxMat], c2v[kMaxMat], sov[kMaxMat];
@@ -357,7 +369,7 @@ __device__ inline Mix<T> mixture(const Geo& g, double rho, double I, const doubl
   for (int m = 0; m < kMaxMat; m++) {
     if (m >= g.nmat) break;
     const MatT<T>& M = GeoT<T>::mat(g, m);
-    wm[m] = f[m] * iden;
+    wm[m] = N::div(f[m], den);
     pmv[m] = c2v[m] = sov[m] = T(0);
     if (fd[m] == 0.0) continue;
     if (m > 0 && g.same_mat && have0) {
@@ -414,13 +426,13 @@ __device__ inline Mix<T> mixture_pm(const Geo& g, double rho, const double* fd, 
   T f[kMaxMat];
 #pragma unroll
   for (int m = 0; m < kMaxMat; m++) f[m] = m < g.nmat ? (T)fd[m] : T(0);
-  T phi, iden, rm;
-  matter(g, (T)rho, f, phi, iden, rm);
+  T phi, den, rm;
+  matter(g, (T)rho, f, phi, den, rm);
   double phid = 0.0;
 #pragma unroll
   for (int m = 0; m < kMaxMat; m++)
     if (m < g.nmat) phid += fd[m];
-  double rmd = rho * (1.0 / (phid > kPhiEps ? phid : kPhiEps));
+  double rmd = rho / (phid > kPhiEps ? phid : kPhiEps);
   T p = T(0), c2 = T(0), G = T(0);
   T wm[kMaxMat], sov[kMaxMat];
 #pragma unroll
@@ -428,7 +440,7 @@ __device__ inline Mix<T> mixture_pm(const Geo& g, double rho, const double* fd, 
     pmv[m] = T(0);
     if (m >= g.nmat) break;
     const MatT<T>& M = GeoT<T>::mat(g, m);
-    wm[m] = f[m] * iden;
+    wm[m] = N::div(f[m], den);
     sov[m] = T(0);
     if (fd[m] == 0.0) continue;
     double rmm = fd[m] > kFPmEps && mud[m] > 0.0 ? mud[m] / fd[m] : rmd;
@@ -587,15 +599,14 @@ __device__ inline Kin<T> kinematics(const Col<T>& c, T dz, const T vr[4], const 
   T Ur_e = Are * ur_e;
   T Uz_s = aw * vz[0] + ae * vz[1];
   T Uz_n = aw * vz[2] + ae * vz[3];
-  T iV = N::div(T(1), V), irc = N::div(T(1), c.rc), idr = N::div(T(1), c.dr);
-  k.Dr = (Ur_e - Ur_w) * iV;
-  k.Dz = (Uz_n - Uz_s) * iV;
-  k.D = ((Ur_e - Ur_w) + (Uz_n - Uz_s)) * iV;
-  k.err = (ur_e - ur_w) * idr;
+  k.Dr = N::div(Ur_e - Ur_w, V);
+  k.Dz = N::div(Uz_n - Uz_s, V);
+  k.D = N::div((Ur_e - Ur_w) + (Uz_n - Uz_s), V);
+  k.err = N::div(ur_e - ur_w, c.dr);
   k.ezz = k.Dz;
-  k.ett = (T(0.5) * (ur_w + ur_e)) * irc;
-  k.dvr_dz = ((aw * vr[2] + ae * vr[3]) - (aw * vr[0] + ae * vr[1])) * iV;
-  k.dvz_dr = (T(0.5) * (vz[1] + vz[3]) - T(0.5) * (vz[0] + vz[2])) * idr;
+  k.ett = N::div(T(0.5) * (ur_w + ur_e), c.rc);
+  k.dvr_dz = N::div((aw * vr[2] + ae * vr[3]) - (aw * vr[0] + ae * vr[1]), V);
+  k.dvz_dr = N::div(T(0.5) * (vz[1] + vz[3]) - T(0.5) * (vz[0] + vz[2]), c.dr);
   k.erz = T(0.5) * (k.dvr_dz + k.dvz_dr);
   k.om = T(0.5) * (k.dvr_dz - k.dvz_dr);
   return k;

@@ -305,6 +305,8 @@ int validate(const salec_grid* g, const salec_material* mats, const salec_pml* p
   }
   if (pml->enabled && !(pml->R > 0 && pml->R < 1)) return why = "PML reflection coefficient", SALEC_E_INVALID;
   if (pml->damp_stress != 0 && pml->damp_stress != 1) return why = "PML damp_stress must be 0 or 1", SALEC_E_INVALID;
+  if (pml->placement != 0 && pml->placement != 1) return why = "PML placement must be 0 or 1", SALEC_E_INVALID;
+  if (pml->reserved != 0) return why = "PML reserved field must be 0", SALEC_E_INVALID;
   return SALEC_OK;
 }
 
@@ -328,7 +330,7 @@ void fill_mat(MatT<T>& c, const salec_material& M) {
   c.mu_f = (T)M.mu_f;
   c.Ylim = (T)M.Ylim;
   c.pcav = (T)(kPcavFrac * M.A);
-  // reciprocals, formed in FP64 exactly as the reference algorithm forms them
+  // reciprocals for the FP32 arithmetic (the FP64 arithmetic divides)
   c.irho0 = (T)(1.0 / M.rho0);
   c.Ar = (T)(M.A / M.rho0);
   c.idE = (T)(1.0 / (M.Ecv - M.Eiv));
@@ -354,6 +356,7 @@ Geo make_geo(const salec_grid* gr, const salec_material* mats, const salec_pml* 
   g.pn = (g.NR + 1 + q - 1) / q * q;
   g.pml_on = pml->enabled ? 1 : 0;
   g.damp_stress = pml->enabled && pml->damp_stress ? 1 : 0;
+  g.pml_place = pml->enabled && pml->placement ? 1 : 0;
   g.dr = gr->dr;
   g.dz = gr->dz;
   g.cfl = gr->cfl;
@@ -920,9 +923,9 @@ int salec_set_fields(salec_ctx* x, int32_t k, const salec_fields* in) {
     for (size_t c = 0; c < NC; c++) {
       double phi = 0.0;
       for (int m = 0; m < g.nmat; m++) phi += in->f[m * NC + c];
-      const double iden = 1.0 / (phi > kPhiEps ? phi : kPhiEps);
+      const double den = phi > kPhiEps ? phi : kPhiEps;
       for (int m = 0; m < g.nmat; m++) {
-        mu[m * NC + c] = in->rho[c] * (in->f[m * NC + c] * iden);
+        mu[m * NC + c] = in->rho[c] * (in->f[m * NC + c] / den);
         Im[m * NC + c] = in->I[c];
       }
     }

@@ -39,7 +39,8 @@ class Material(C.Structure):
 
 
 class PmlC(C.Structure):
-    _fields_ = [("enabled", C.c_int32), ("damp_stress", C.c_int32), ("R", C.c_double), ("c_ref", C.c_double)]
+    _fields_ = [("enabled", C.c_int32), ("damp_stress", C.c_int32), ("R", C.c_double), ("c_ref", C.c_double),
+                ("placement", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SceneC(C.Structure):
@@ -166,7 +167,9 @@ def _instance(problem, keep: list) -> Instance:
     for k, m in enumerate(problem.mats[:g.nmat]):
         inst.mats[k] = _mat(m)
     p = problem.pml
-    inst.pml = PmlC(int(p.enabled), int(p.damp_stress), p.R, p.c_ref)
+    if int(getattr(p, "form", 0)) != 0:
+        raise ValueError("the library damps the specific velocity and energy (pml.form = 0)")
+    inst.pml = PmlC(int(p.enabled), int(p.damp_stress), p.R, p.c_ref, int(getattr(p, "placement", 0)), 0)
     if problem.scene is not None:
         sc = problem.scene
         inst.scene = SceneC(sc.surface_j, sc.subsample, sc.radius, sc.v_imp, sc.gravity, sc.layer_j,
