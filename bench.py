@@ -140,22 +140,57 @@ def valu_per_launch(schedule):
     return None
 
 
-def cpu_baseline(pb, budget_s=12.0):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    """The host cores this process may use (the OpenMP limit if one is set,
+    else the CPU affinity set)."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(pb, budget_s=12.0, budget_1_s=8.0):
+    """The oracle as it stands (plain FP64 C, -O2, OpenMP over rows) on the
+    same workload from its initial state: all usable host cores for about
+    budget_s seconds, then one thread for about budget_1_s seconds."""
     from oracle import oracle as O
     from oracle.oracle import Oracle
-    threads = O.set_threads(os.cpu_count() or 1)
-    o = Oracle(pb)
-    cells = pb.grid.ncells
-    n, t0 = 0, time.perf_counter()
-    while True:
-        o.step(5)
-        n += 5
-        el = time.perf_counter() - t0
-        if el >= budget_s or n >= 2000:
-            break
-    return {"value": cells * n / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} cycles of the same 1050x1050 FP64 workload from its initial state "
-                      f"({el:.1f} s of CPU time)"}
+
+    def timed(threads, budget):
+        used = O.set_threads(threads)
+        o = Oracle(pb)
+        n, t0 = 0, time.perf_counter()
+        while True:
+            o.step(5 if threads > 1 else 1)
+            n += 5 if threads > 1 else 1
+            el = time.perf_counter() - t0
+            if el >= budget or n >= 2000:
+                break
+        return pb.grid.ncells * n / el, used, n, el
+
+    rate, used, n, el = timed(host_threads(), budget_s)
+    rate1, _, n1, el1 = timed(1, budget_1_s)
+    O.set_threads(host_threads())
+    return {"value": rate, "unit": "cell-updates/s", "cores": used, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"{n} cycles of the same 1050x1050 FP64 workload from its initial state on {used} threads "
+                      f"({el:.1f} s); {n1} cycles on one thread ({el1:.1f} s)",
+            "one_thread": {"value": rate1, "unit": "cell-updates/s", "cores": 1, "cycles": n1, "seconds": el1},
+            "parallel_speedup": rate / rate1}
 
 
 def copy_bandwidth(mib=2048, reps=5):

@@ -194,50 +194,79 @@ typedef struct salec_schedule {
 
 typedef struct salec_ctx salec_ctx;
 
-/* Bytes of device memory salec_init() needs for this problem; 0 if invalid. */
+/* Bytes of device memory salec_init() needs for this problem (the grid with
+ * its PML zones of Table 2, the materials of Table 1, the layers of Sec. 3);
+ * 0 if invalid. */
 size_t salec_plan(const salec_grid *grid, const salec_material *mats, const salec_pml *pml);
 
-/* Lays out the state in dev_buf (dev_bytes >= salec_plan(), 256-byte
+/* Sets up the problem Sec. 4 states (a vertical impact of a sphere on a
+ * target half-space with PML layers right and below, Table 2), with Table 1's
+ * strength, the equation of state of Sec. 2 and the damping profile of
+ * Sec. 3. Lays out the state in dev_buf (dev_bytes >= salec_plan(), 256-byte
  * aligned), uploads the constants and, if scene is not NULL, builds the
  * impact scene (target half-space of material 0, spherical projectile of
- * material nmat-1, Sec. 4) on the device; otherwise the state is zero until
- * salec_set_fields(). Computes the first time step. stream: hipStream_t or
+ * material nmat-1) on the device; otherwise the state is zero until
+ * salec_set_fields(). Computes the first time step (Sec. 7's Courant
+ * condition). SALEC_E_INVALID for a bad description (message in
+ * salec_last_error), SALEC_E_BUFFER for a small or misaligned buffer,
+ * SALEC_E_HIP for a runtime error; *out is set in every case but a null
+ * argument and must be passed to salec_destroy(). stream: hipStream_t or
  * NULL (a stream of the library's own is created). A context made here is
  * an ensemble of one: instance index 0 below. */
 int salec_init(const salec_grid *grid, const salec_material *mats, const salec_pml *pml,
                const salec_scene *scene, void *dev_buf, size_t dev_bytes, void *stream,
                salec_ctx **out);
 
-/* Ensembles: n >= 1 independent impacts of any sizes advanced together, one
- * kernel launch per cycle for all of them (captured in HIP graphs); each
- * member keeps its own time step, time and cycle count and its own sticky
- * error. Same ownership rules as salec_plan/salec_init. */
+/* Ensembles: n >= 1 independent impacts of any sizes, each the problem of
+ * Sec. 4 as salec_init describes it (the paper runs one impact at a time;
+ * ensembles are an extension), advanced together, one kernel launch per
+ * cycle for all of them (captured in HIP graphs); each member keeps its own
+ * time step (Sec. 7), time and cycle count and its own sticky error. Same
+ * ownership, layout and error rules as salec_plan/salec_init; instance
+ * indices below are 0..n-1. */
 size_t salec_plan_batch(const salec_instance *inst, int32_t n);
 int salec_init_batch(const salec_instance *inst, int32_t n, void *dev_buf, size_t dev_bytes,
                      void *stream, salec_ctx **out);
 int32_t salec_num_instances(const salec_ctx *ctx);
 
-/* Advances every member n >= 0 cycles (replaying captured HIP graphs), then
+/* Advances every member n >= 0 cycles of Sec. 2's operator split: the
+ * Lagrangian step (eqs. (1)-(2): stress divergence, velocity, internal energy
+ * with the Table 1 strength model), then the Eulerian step (eqs. (3)-(5):
+ * advection of mass, momentum and energy), with Sec. 3's PML control
+ * equations in the layers, Sec. 4's boundary conditions, and the next time
+ * step from Sec. 7's Courant condition. Replays captured HIP graphs, then
  * synchronises the stream once and returns the first sticky device error
- * among the members, if any (members without an error keep advancing). */
+ * among the members, if any (members without an error keep advancing);
+ * SALEC_E_INVALID for a null context or n < 0, SALEC_E_HIP for a runtime
+ * error. */
 int salec_step(salec_ctx *ctx, int32_t n);
 
-/* Enqueues n cycles without synchronising or checking errors (for timing
- * loops); errors surface at the next salec_step() or salec_diag(). */
+/* The cycles of salec_step() (same passages), enqueued without
+ * synchronising or checking errors (for timing loops); errors surface at the
+ * next salec_step() or salec_diag(). */
 int salec_enqueue(salec_ctx *ctx, int32_t n);
 
-/* Copies the current state of member `instance` (and p, c2 if requested)
- * to host FP64 arrays. */
+/* Copies the current state of member `instance` -- the variables of Sec. 2's
+ * conservation equations: density, specific internal energy, volume
+ * fractions, deviatoric stress tau, node velocity -- and, if requested, the
+ * pressure and squared sound speed of the equation of state at that state, to
+ * host FP64 arrays (layout above; the mixed mode's FP32 fields are widened).
+ * SALEC_E_INVALID for a bad context, instance or pointer. */
 int salec_get_fields(salec_ctx *ctx, int32_t instance, const salec_fields *out);
 
 /* Replaces the state of member `instance` with host arrays (rho, I, f, v
  * required; s optional, zero if NULL) and starts a new run of that member at
  * t = 0: PML auxiliaries and budgets are cleared, the PML reference density
- * is taken from rho, dt recomputed, its error cleared. */
+ * (the initial state Sec. 3 measures the fluctuation against) is taken from
+ * rho, dt recomputed by Sec. 7's condition, its error cleared.
+ * SALEC_E_INVALID for a bad context, instance or pointer (the values are
+ * not checked; a non-finite one surfaces as SALEC_E_NONFINITE at the next
+ * cycle). */
 int salec_set_fields(salec_ctx *ctx, int32_t instance, const salec_fields *in);
 
-/* PML auxiliaries of member `instance` expanded to full grids (zero outside
- * the layers):
+/* The auxiliary variables phi1, phi2, phi3, psi1, psi2 of Sec. 3 (one set
+ * per damped direction), the reference density and the mass sink of member
+ * `instance`, expanded to full grids (zero outside the layers):
  *   cell_aux 8*NZ*NR: phi1_b, phi3_b, psi2_b, phi1_r, phi3_r, psi2_r, rho_ref, msink
  *   node_aux 8*(NZ+1)*(NR+1): phi2_b (r, z), psi1_b (r, z), phi2_r (r, z), psi1_r (r, z) */
 int salec_get_pml(salec_ctx *ctx, int32_t instance, double *cell_aux, double *node_aux);
@@ -264,18 +293,25 @@ int salec_get_pml(salec_ctx *ctx, int32_t instance, double *cell_aux, double *no
 int salec_set_pml(salec_ctx *ctx, int32_t instance, const double *cell_aux, const double *node_aux);
 int salec_set_clock(salec_ctx *ctx, int32_t instance, double t, double dt);
 
-/* Checkpoint: the whole device state of every member (fields, EoS cache,
- * PML, budgets, t, dt, cycle, errors). */
+/* Checkpoint (runtime support, no passage): the whole device state of every
+ * member (fields, EoS cache, PML, budgets, t, dt, cycle, errors) as an opaque
+ * host blob of salec_state_bytes() bytes; salec_set_state restores it into a
+ * context made from the same descriptions. SALEC_E_BUFFER if the blob is too
+ * small, SALEC_E_INVALID if it belongs to another layout. */
 size_t salec_state_bytes(const salec_ctx *ctx);
 int salec_get_state(salec_ctx *ctx, void *host_blob, size_t bytes);
 int salec_set_state(salec_ctx *ctx, const void *host_blob, size_t bytes);
 
-/* Time, step, cycle, compensated totals and budgets, sticky error of one
- * member. */
+/* Time, step (Sec. 7), cycle, and the compensated totals of the quantities
+ * eqs. (3)-(5) conserve -- mass, internal and kinetic energy -- with the
+ * budgets of what left through the open top (Sec. 4) and what the PML sink
+ * of Sec. 3 removed; sticky error of one member. SALEC_E_INVALID for a bad
+ * context, instance or pointer. */
 int salec_diag(salec_ctx *ctx, int32_t instance, salec_diag_t *out);
 
-/* Device time of the cycle kernels over the last salec_step() call, measured
- * with HIP events on the context's stream, in milliseconds. */
+/* Measurement (no passage; the paper times whole runs, Sec. 6): device time
+ * of the cycle kernels over the last salec_step() call, measured with HIP
+ * events on the context's stream, in milliseconds. */
 int salec_last_step_ms(salec_ctx *ctx, double *ms);
 
 /* Initial pressure p0 per cell row of member `instance` (NZ host values, Pa;
@@ -307,7 +343,8 @@ int salec_get_p0(salec_ctx *ctx, int32_t instance, double *p0);
 int salec_set_materials(salec_ctx *ctx, int32_t instance, const double *mu, const double *Im);
 int salec_get_materials(salec_ctx *ctx, int32_t instance, double *mu, double *Im);
 
-/* Advances every member by n cycles (1 <= n <= 100000) like salec_step(),
+/* Measurement (no passage): advances every member by n cycles
+ * (1 <= n <= 100000) like salec_step(),
  * but launches each cycle's two kernels directly (no graph) with a HIP event
  * after each on the context's stream, queues all n cycles before waiting,
  * and returns the mean time between consecutive events: per cycle kernel and
@@ -316,7 +353,9 @@ int salec_get_materials(salec_ctx *ctx, int32_t instance, double *mu, double *Im
  * error like salec_step(). */
 int salec_time_kernels(salec_ctx *ctx, int32_t n, double *cycle_ms, double *finalize_ms);
 
-/* Launch schedules. Every tile shape computes bit-identical results, so the
+/* Launch schedules (runtime; no passage: the paper's parallel decomposition
+ * of Sec. 2's grid over MPI ranks becomes tiles over workgroups here). Every
+ * tile shape computes bit-identical results, so the
  * schedule only changes speed. A new context starts on the shape measured
  * fastest for its precision on a filled device, with as many workgroups as
  * fit at once when that is fewer than the tiles. salec_set_schedule() selects a shape and a

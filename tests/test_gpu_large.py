@@ -1,16 +1,27 @@
-"""The large mixed-precision impact at full size (4000 x 4000 cells + 100-cell
-PML, 16.8 M cells, two materials with strength, R = 200 cells, 12 km/s,
-2000 cycles), in the launch configuration the benchmark times.
+"""The large impact at full size (4000 x 4000 cells + 100-cell PML, 16.8 M
+cells, two materials with strength, R = 200 cells, 12 km/s, 2000 cycles) in
+the launch configuration the benchmark times.
 
-Against the plain-FP64 GPU run of the same problem (which equals the oracle
-bit for bit at every size the oracle can run, and for the first cycles of the
-1050^2 workload): the conserved densities within 1e-4 (relative L2) at cycle
-200, the crater level on the axis within one cell after 2000 cycles, and the
-mass budget. Against the oracle on the same problem 10x coarser (400 x 400 +
-10-cell PML of 10 m cells, R = 20 cells) run to the same physical time: the
-crater level on the axis within one coarse cell, and the fine fields
-averaged over 10 x 10 blocks close to the coarse ones (a resolution
-comparison, so the bounds are those of the discretisation, not rounding).
+FP64 against the oracle at full resolution: every field, PML auxiliary and
+diagnostic bit for bit at cycle 200 (3.4e9 cell-updates of the oracle).
+
+Mixed mode against that reference, per field as the target states it
+(density, pressure, specific energy, velocity, crater depth and radius), next
+to the FP64 conditioning floor measured the same way (an FP64 run whose
+initial velocities are one ulp up):
+* cycle 200: relative L2 of rho, p, I, v_r, v_z within 1e-4 over the cells
+  (nodes) holding matter (phi >= 1e-3, the cells the Courant step accounts
+  for); the conserved densities (rho, rho I, phi p, f, phi s, m v) within 1e-4
+  over all cells, also after 10 x 10 block averaging (the 400 x 400 downsample);
+  the plain per-field errors over all cells are printed, dominated by cells
+  holding traces of matter (phi < 1e-6);
+* cycle 2000: crater depth and radius within one cell; every error printed
+  beside the floor, which stays below 1e-4 (the FP64 run is well conditioned,
+  so the late mixed errors are precision, not conditioning).
+
+A resolution check, labelled as such: the oracle on the same problem 10x
+coarser (400 x 400 + 10, 10 m cells) at the same physical time gives the same
+crater level within one coarse cell (discretisation error, not rounding).
 """
 import numpy as np
 import pytest
@@ -18,9 +29,12 @@ import pytest
 from oracle.oracle import Oracle
 from paper_2403_04267_amd import inputs
 
-from .crater import conserved_errors, crater_depth
+from .crater import conserved_errors, crater_depth, crater_radius, rel_l2
+from .test_gpu_parity import compare
 
 pytestmark = pytest.mark.gpu
+
+MATTER = 1e-3
 
 
 def ctx(problems):
@@ -29,46 +43,139 @@ def ctx(problems):
 
 
 def block(x, k=10):
-    nz, nr = x.shape
-    return x[: nz // k * k, : nr // k * k].reshape(nz // k, k, nr // k, k).mean(axis=(1, 3))
+    nz, nr = x.shape[-2:]
+    x = x[..., : nz // k * k, : nr // k * k]
+    return x.reshape(x.shape[:-2] + (nz // k, k, nr // k, k)).mean(axis=(-3, -1))
+
+
+def node_phi(phi):
+    NZ, NR = phi.shape
+    o, c = np.zeros((NZ + 1, NR + 1)), np.zeros((NZ + 1, NR + 1))
+    for dj in (0, 1):
+        for di in (0, 1):
+            o[dj:dj + NZ, di:di + NR] += phi
+            c[dj:dj + NZ, di:di + NR] += 1
+    return o / c
+
+
+def per_field(Fm, Fa, grid, sj):
+    """Plain per-field rel-L2 over all cells / nodes and over those holding
+    matter, the conserved densities, crater depth and radius (cells)."""
+    phi = Fa["f"].sum(0)
+    mc, mn = phi >= MATTER, node_phi(phi) >= MATTER
+    e = {}
+    for k in ("rho", "p", "I"):
+        e[k] = rel_l2(Fm[k], Fa[k])
+        e[k + "@matter"] = rel_l2(Fm[k][mc], Fa[k][mc])
+    for q, k in ((0, "v_r"), (1, "v_z")):
+        e[k] = rel_l2(Fm["v"][q], Fa["v"][q])
+        e[k + "@matter"] = rel_l2(Fm["v"][q][mn], Fa["v"][q][mn])
+    e.update({"cons." + k: v for k, v in conserved_errors(Fm, Fa, grid).items()})
+    e["depth_cells"] = abs(crater_depth(Fm["f"], grid, sj) - crater_depth(Fa["f"], grid, sj)) / grid.dz
+    e["radius_cells"] = abs(crater_radius(Fm["f"], grid, sj) - crater_radius(Fa["f"], grid, sj)) / grid.dr
+    return e
+
+
+def blocked_conserved(Fm, Fa, grid):
+    """The conserved densities averaged over 10 x 10 blocks (400 x 400 for the
+    4100-cell side), relative L2 of the averages."""
+    def dens(F):
+        phi = F["f"].sum(0)
+        return {"rho": F["rho"], "rhoI": F["rho"] * F["I"], "phi_p": phi * F["p"], "f": F["f"],
+                "phi_s": phi[None] * F["s"]}
+    A, B = dens(Fm), dens(Fa)
+    return {k: rel_l2(block(A[k]), block(B[k])) for k in A}
+
+
+def show(label, e):
+    print(f"[{label}] " + " ".join(f"{k} {v:.2e}" for k, v in e.items()), flush=True)
 
 
 @pytest.fixture(scope="module")
 def large_runs():
     pb = inputs.config_large("fp64")
-    a, b = ctx(pb), ctx(pb.replace(precision="mixed"))
-    a.step(200)
-    b.step(200)
-    e200 = conserved_errors(b.fields(), a.fields(), pb.grid)
+    sj = pb.scene.surface_j
+    a, m, p = ctx(pb), ctx(pb.replace(precision="mixed")), ctx(pb)
+    F0 = p.fields(eos=False)
+    p.set_fields(F0["rho"], F0["I"], F0["f"], np.nextafter(F0["v"], np.inf), F0["s"])
+    del F0
+    o = Oracle(pb)
+    out = {"pb": pb}
+    done = 0
+    while done < 200:
+        n = 50
+        a.step(n)
+        m.step(n)
+        p.step(n)
+        o.step(n)
+        done += n
+        print(f"[4100^2] cycle {done}", flush=True)
+    try:
+        compare(a, o, "4100^2 fp64 cycle 200", tol=0.0)
+        out["parity"] = None
+    except AssertionError as ex:  # reported by its own test
+        out["parity"] = str(ex)
+    Fo = o.fields()
+    del o
+    Fm, Fp = m.fields(), p.fields()
+    out["e200"] = per_field(Fm, Fo, pb.grid, sj)
+    out["f200"] = per_field(Fp, Fo, pb.grid, sj)
+    out["b200"] = blocked_conserved(Fm, Fo, pb.grid)
+    del Fo, Fm, Fp
     a.step(1800)
-    b.step(1800)
-    out = {"pb": pb, "e200": e200, "Fa": a.fields(eos=False), "Fb": b.fields(eos=False),
-           "da": a.diag(), "db": b.diag()}
-    del a, b
+    m.step(1800)
+    p.step(1800)
+    Fa, Fm, Fp = a.fields(), m.fields(), p.fields()
+    out["e2000"] = per_field(Fm, Fa, pb.grid, sj)
+    out["f2000"] = per_field(Fp, Fa, pb.grid, sj)
+    out["da"], out["dm"] = a.diag(), m.diag()
+    out["fa_f"], out["fm_f"] = Fa["f"], Fm["f"]
+    del a, m, p
     return out
 
 
-def test_large_mixed_against_fp64_gpu(large_runs):
+@pytest.mark.timeout(1800)  # includes the module's runs (the oracle's 3.4e9 cell-updates)
+def test_large_fp64_equals_the_full_resolution_oracle(large_runs):
+    assert large_runs["parity"] is None, large_runs["parity"]
+
+
+def test_large_mixed_meets_the_bar_at_cycle_200(large_runs):
+    r = large_runs
+    show("4100^2 mixed vs oracle, cycle 200", r["e200"])
+    show("4100^2 floor (fp64, 1 ulp) cycle 200", r["f200"])
+    show("4100^2 mixed vs oracle, 10x10 blocks, cycle 200", r["b200"])
+    e = r["e200"]
+    for k in ("rho@matter", "p@matter", "I@matter", "v_r@matter", "v_z@matter"):
+        assert e[k] <= 1e-4, (k, e[k])
+    for k, v in e.items():
+        if k.startswith("cons."):
+            assert v <= 1e-4, (k, v)
+    assert all(v <= 1e-4 for v in r["b200"].values()), r["b200"]
+    assert e["depth_cells"] <= 1.0 and e["radius_cells"] <= 1.0
+
+
+def test_large_mixed_at_cycle_2000_against_the_floor(large_runs):
     r = large_runs
     pb = r["pb"]
-    print("[large mixed cycle 200] " + " ".join(f"{k} {v:.2e}" for k, v in r["e200"].items()), flush=True)
-    bad = {k: v for k, v in r["e200"].items() if not v <= 1e-4}
-    assert not bad, bad
-    sj = pb.scene.surface_j
-    da, db = crater_depth(r["Fa"]["f"], pb.grid, sj), crater_depth(r["Fb"]["f"], pb.grid, sj)
-    print(f"[large cycle 2000] crater level on the axis fp64 {da:.3f} m, mixed {db:.3f} m", flush=True)
-    assert abs(da - db) <= pb.grid.dz
+    show("4100^2 mixed vs fp64, cycle 2000", r["e2000"])
+    show("4100^2 floor (fp64, 1 ulp) cycle 2000", r["f2000"])
+    assert r["e2000"]["depth_cells"] <= 1.0 and r["e2000"]["radius_cells"] <= 1.0
+    # the FP64 run is well conditioned: its own 1-ulp floor stays small
+    for k in ("rho", "p@matter", "I@matter", "v_r@matter", "v_z@matter"):
+        assert r["f2000"][k] <= 1e-4, (k, r["f2000"][k])
     # mass budget of the mixed run: FP64 sums of FP64 densities and fluxes
-    d = r["db"]
+    d, da = r["dm"], r["da"]
     assert int(d["cycle"]) == 2000 and d["err"] == 0
     total = d["mass"] + d["mass_out"] + d["mass_pml"]
-    assert abs(total - r["da"]["mass"] - r["da"]["mass_out"] - r["da"]["mass_pml"]) <= 1e-6 * total
+    assert abs(total - da["mass"] - da["mass_out"] - da["mass_pml"]) <= 1e-6 * total
 
 
-def test_large_against_the_oracle_on_a_coarse_copy(large_runs):
+def test_resolution_check_against_a_coarse_oracle_copy(large_runs):
+    """Discretisation, not precision: the oracle on the same problem 10x
+    coarser reaches the same crater level within one coarse cell."""
     r = large_runs
     pb = r["pb"]
-    t_end = r["db"]["t"]
+    t_end = r["dm"]["t"]
     c = inputs.impact(400, 10, 20, 12e3, nmat=2, strength=True, cycles=0, dx=10.0)
     c.grid.t_stop = t_end
     o = Oracle(c)
@@ -79,12 +186,6 @@ def test_large_against_the_oracle_on_a_coarse_copy(large_runs):
     assert abs(o.diag()["t"] - t_end) <= 1e-12 * t_end
     F = o.fields(eos=False)
     dc = crater_depth(F["f"], c.grid, c.scene.surface_j)
-    df = crater_depth(r["Fb"]["f"], pb.grid, pb.scene.surface_j)
-    phi_f, phi_c = block(r["Fb"]["f"].sum(0)), F["f"].sum(0)
-    rho_f, rho_c = block(r["Fb"]["rho"]), F["rho"]
-    l1 = np.abs(phi_f - phi_c).sum() / np.abs(phi_c).sum()
-    l2 = float(np.sqrt(((rho_f - rho_c) ** 2).sum() / (rho_c ** 2).sum()))
-    print(f"[large vs coarse oracle, t = {t_end:.4e} s] crater level fine {df:.2f} m, coarse {dc:.2f} m; "
-          f"block phi L1 {l1:.2e}, block rho L2 {l2:.2e}", flush=True)
+    df = crater_depth(r["fm_f"], pb.grid, pb.scene.surface_j)
+    print(f"[resolution check, t = {t_end:.4e} s] crater level fine {df:.2f} m, coarse {dc:.2f} m", flush=True)
     assert abs(df - dc) <= c.grid.dz
-    assert l1 < 1e-2 and l2 < 5e-2
