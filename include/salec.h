@@ -309,6 +309,22 @@ int salec_set_state(salec_ctx *ctx, const void *host_blob, size_t bytes);
  * context, instance or pointer. */
 int salec_diag(salec_ctx *ctx, int32_t instance, salec_diag_t *out);
 
+/* For callers that cannot allocate or synchronise (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * compensated totals of salec_diag (mass, ie, ke, mass_out, mass_pml, ie_out,
+ * in this order) of member `instance`, written to dev_totals, 6 FP64 values in
+ * device memory owned by the caller. Only enqueues the reduction on the
+ * context's stream: no allocation of any kind, no memset, no host
+ * synchronisation; the values are ready when the stream reaches that point,
+ * and equal salec_diag's bit for bit. Its partial sums live in one scratch
+ * array per GPU that the library holds for the life of the process (the
+ * 240 x 6 compensated partials of the fixed reduction tree, 23 KB; every
+ * instance size reduces into them, so no size is refused). Every call on one
+ * GPU shares that array, so calls that overlap on one GPU (other streams,
+ * other contexts, other host threads) race; successive calls on one stream do
+ * not. SALEC_E_INVALID for a bad context, instance or pointer. */
+int salec_diag_totals(salec_ctx *ctx, int32_t instance, double *dev_totals);
+
 /* Measurement (no passage; the paper times whole runs, Sec. 6): device time
  * of the cycle kernels over the last salec_step() call, measured with HIP
  * events on the context's stream, in milliseconds. */

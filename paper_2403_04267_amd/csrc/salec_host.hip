@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -469,8 +470,42 @@ struct salec_ctx {
   int variant = 0, grid = 0, nsched = 0;
   double tuned_ms = 0.0;
   bool ready = false;
+  double* diag_scratch = nullptr;  // this device's copy of `scratch` (salec_diag_totals)
   std::string err;
 };
+
+// Scratch of salec_diag_totals: the compensated partial sums (sum and
+// compensation) of the kDiagQ totals of every block of the fixed reduction
+// tree. Its size does not depend on the instance: every grid reduces into
+// these kDiagBlocks blocks. Each GPU the library runs on holds its own copy
+// until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device (kept per device below).
+constexpr size_t kDiagScratch = (size_t)kDiagBlocks * kDiagQ * 2;
+static __device__ __align__(256) double scratch[kDiagScratch];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per
+// device, with that device current).
+hipError_t scratch_address(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
 
 namespace {
 
@@ -640,6 +675,7 @@ int init_common(salec_ctx* x, void* dev_buf, size_t dev_bytes, void* stream) {
   }
   HIPCHK(x, hipEventCreate(&x->ev0));
   HIPCHK(x, hipEventCreate(&x->ev1));
+  HIPCHK(x, scratch_address(&x->diag_scratch));
   HIPCHK(x, hipMemsetAsync(dev_buf, 0, x->L.total, x->st));
   for (size_t k = 0; k < x->ms.size(); k++) {
     Member& mb = x->ms[k];
@@ -1215,6 +1251,18 @@ int salec_diag(salec_ctx* x, int32_t k, salec_diag_t* out) {
   out->ie_out = q[5];
   out->err = s.err;
   out->err_cycle = s.err_cycle;
+  return SALEC_OK;
+}
+
+int salec_diag_totals(salec_ctx* x, int32_t k, double* dev_totals) {
+  if (!member_ok(x, k) || !dev_totals) return SALEC_E_INVALID;
+  if (!x->diag_scratch) {
+    x->err = "salec_diag_totals: no device scratch for this context";
+    return SALEC_E_HIP;
+  }
+  // every block overwrites all its partials, so nothing needs clearing
+  Member& mb = x->ms[k];
+  HIPCHK(x, launch_diag(mb.d, mb.n_pml, x->diag_scratch, dev_totals, x->st));
   return SALEC_OK;
 }
 

@@ -111,6 +111,7 @@ def load() -> C.CDLL:
     lib.salec_get_state.argtypes = [P, P, C.c_size_t]
     lib.salec_set_state.argtypes = [P, P, C.c_size_t]
     lib.salec_diag.argtypes = [P, I32, C.POINTER(Diag)]
+    lib.salec_diag_totals.argtypes = [P, I32, P]
     lib.salec_last_step_ms.argtypes = [P, _DP]
     lib.salec_time_kernels.argtypes = [P, I32, _DP, _DP]
     lib.salec_set_p0.argtypes = [P, I32, _DP]
@@ -376,6 +377,16 @@ class Salec:
         d = Diag()
         self._check(self.lib.salec_diag(self._h, int(k), C.byref(d)))
         return {n: getattr(d, n) for n, _ in Diag._fields_}
+
+    def diag_totals(self, out, k: int = 0):
+        """Enqueues member k's compensated totals (mass, ie, ke, mass_out,
+        mass_pml, ie_out) into `out`, a float64 tensor of >= 6 values on the
+        context's device, on the context's stream (no allocation, no
+        synchronisation: wait on self.stream before reading)."""
+        if not out.dtype.is_floating_point or out.element_size() != 8 or out.numel() < 6 or not out.is_cuda \
+                or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 device tensor of at least 6 values")
+        self._check(self.lib.salec_diag_totals(self._h, int(k), C.c_void_p(out.data_ptr())))
 
     def get_state(self) -> bytes:
         n = self.lib.salec_state_bytes(self._h)
