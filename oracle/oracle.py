@@ -31,7 +31,10 @@ class _Mat(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("rho0", "A", "B", "E0", "a", "b", "alpha", "beta",
                                           "Eiv", "Ecv", "p_min", "c_floor_frac")] + \
                [("strength", C.c_int32)] + \
-               [(n, C.c_double) for n in ("Y0", "mu_f", "Ylim", "poisson")]
+               [(n, C.c_double) for n in ("Y0", "mu_f", "Ylim", "poisson")] + \
+               [("damage", C.c_int32)] + \
+               [(n, C.c_double) for n in ("Yd0", "mu_d", "Ydm", "eps_fb", "B_dmg", "p_bd",
+                                          "gamma_eta", "gamma_T", "c_vib", "af_h")]
 
 
 class _Pml(C.Structure):
@@ -66,6 +69,12 @@ def _load():
     lib.orc_set_materials.argtypes = [P, D, D]
     lib.orc_get_materials.argtypes = [P, D, D]
     lib.orc_get_p0.argtypes = [P, D]
+    lib.orc_set_damage.argtypes = [P, D, D]
+    lib.orc_get_damage.argtypes = [P, D, D]
+    lib.orc_yield_damaged.argtypes = [C.POINTER(_Mat), C.c_double, C.c_double, C.c_double]
+    lib.orc_yield_damaged.restype = C.c_double
+    lib.orc_failure_strain.argtypes = [C.POINTER(_Mat), C.c_double]
+    lib.orc_failure_strain.restype = C.c_double
     lib.orc_step.argtypes = [P, C.c_int32]
     lib.orc_get_fields.argtypes = [P, D, D, D, D, D, D, D]
     lib.orc_get_pml.argtypes = [P, D, D]
@@ -106,7 +115,10 @@ def _grid(g) -> _Grid:
 
 def _mat(m) -> _Mat:
     return _Mat(m.rho0, m.A, m.B, m.E0, m.a, m.b, m.alpha, m.beta, m.Eiv, m.Ecv, m.p_min,
-                m.c_floor_frac, int(m.strength), m.Y0, m.mu_f, m.Ylim, m.poisson)
+                m.c_floor_frac, int(m.strength), m.Y0, m.mu_f, m.Ylim, m.poisson,
+                int(getattr(m, "damage", 0)), *[float(getattr(m, n, d)) for n, d in (
+                    ("Yd0", 0.0), ("mu_d", 0.0), ("Ydm", 0.0), ("eps_fb", 1e-4), ("B_dmg", 1e-11),
+                    ("p_bd", 3e8), ("gamma_eta", 0.0), ("gamma_T", 0.0), ("c_vib", 0.0), ("af_h", 0.0))])
 
 
 def set_threads(n: int) -> int:
@@ -191,6 +203,22 @@ class Oracle:
             raise ValueError("orc_get_materials failed (closure 0)")
         shp = (self.nmat, self.NZ, self.NR)
         return {"mu": mu.reshape(shp), "Im": Im.reshape(shp)}
+
+    def set_damage(self, D=None, vib=None):
+        """Damage and block-model vibration speed per cell (NZ x NR each)."""
+        a = None if D is None else np.ascontiguousarray(D, dtype=np.float64).reshape(-1)
+        b = None if vib is None else np.ascontiguousarray(vib, dtype=np.float64).reshape(-1)
+        for x in (a, b):
+            if x is not None and x.size != self.NC:
+                raise ValueError("damage arrays must have NZ x NR values")
+        rc = self._lib.orc_set_damage(self._h, _ptr(a), _ptr(b))
+        if rc:
+            raise ValueError(rc)
+
+    def damage(self) -> dict:
+        D, vib = np.empty(self.NC), np.empty(self.NC)
+        self._lib.orc_get_damage(self._h, _ptr(D), _ptr(vib))
+        return {"D": D.reshape(self.NZ, self.NR), "vib": vib.reshape(self.NZ, self.NR)}
 
     def step(self, n: int, check: bool = True) -> int:
         rc = self._lib.orc_step(self._h, int(n))
@@ -293,6 +321,14 @@ def tillotson(mat, rho: float, e: float):
 
 def yield_strength(mat, p: float) -> float:
     return _load().orc_yield(C.byref(_mat(mat)), float(p))
+
+
+def yield_damaged(mat, p: float, D: float, p_vib: float) -> float:
+    return _load().orc_yield_damaged(C.byref(_mat(mat)), float(p), float(D), float(p_vib))
+
+
+def failure_strain(mat, p: float) -> float:
+    return _load().orc_failure_strain(C.byref(_mat(mat)), float(p))
 
 
 def shear_modulus(mat) -> float:

@@ -53,6 +53,8 @@
 #define PCAV_FRAC 1e-4      /* pressure ramp of the cavitation rule, fraction of A */
 #define F_PM_EPS 1e-6       /* closure 1: a material below this volume fraction
                                takes the cell's matter density in its EoS  */
+#define VIB_ON 1e-3         /* block model: vibration speed (m/s) above which its
+                               viscosity acts fully (linear ramp below)     */
 
 struct orc_ctx {
     orc_grid g;
@@ -61,6 +63,12 @@ struct orc_ctx {
     int NR, NZ, NC, NN, nmat, any_strength;
     int pm; /* closure 1: per-material density and specific energy */
     double rho_ref, Gm[ORC_MAX_MAT]; /* shear / bulk modulus ratio per material */
+    /* damage and acoustic fluidization: some material accumulates damage; per
+     * material the longitudinal speed at rest, the block model's kinematic
+     * viscosity gamma_eta c h and vibration decay time gamma_T h / c */
+    int dmg;
+    double cL0[ORC_MAX_MAT], nub[ORC_MAX_MAT], Tvib[ORC_MAX_MAT];
+    double *D, *vib, *D_n, *vib_n, *DL, *vibL, *etab;
 
     /* state at the start of the cycle */
     double *rho, *I, *f[ORC_MAX_MAT], *srr, *szz, *srz, *vr, *vz;
@@ -236,9 +244,33 @@ double orc_softening(const orc_mat *m, double e)
     return dmin(dmax((m->Ecv - E) / (m->Ecv - m->Eiv), 0.0), 1.0);
 }
 
+/* Damaged strength (Table 1's Y_d0, mu_d, Y_dm): Y_d = min(Y_d0 + mu_d q, Y_dm)
+ * at the effective pressure q = max(p - p_vib, 0) of the block model for
+ * p >= 0, max(0, Y_d0 + mu_d p) in tension, never above the intact curve;
+ * the cell's strength blends the two by its damage D. */
+double orc_yield_damaged(const orc_mat *m, double p, double D, double p_vib)
+{
+    double Yi = orc_yield(m, p);
+    if (!m->strength || !m->damage) return Yi;
+    double Yd;
+    if (p >= 0.0)
+        Yd = dmin(m->Yd0 + m->mu_d * dmax(p - p_vib, 0.0), m->Ydm);
+    else
+        Yd = dmax(0.0, m->Yd0 + m->mu_d * p);
+    Yd = dmin(Yd, Yi);
+    return (1.0 - D) * Yi + D * Yd;
+}
+
+/* plastic strain at failure of the damage law, eps_f = max(eps_fb, B (p - p_bd))
+ * (brittle below the transition pressure p_bd, increasingly ductile above) */
+double orc_failure_strain(const orc_mat *m, double p)
+{
+    return dmax(m->eps_fb, m->B_dmg * (p - m->p_bd));
+}
+
 /* mixture state of cell c: shared material density and energy, weights f_m/phi */
 static void mixture(const orc_ctx *x, int c, const double *rho, const double *I,
-                    double *const *f, double *p_o, double *c2_o, double *G_o,
+                    double *const *f, double Dc, double vibc, double *p_o, double *c2_o, double *G_o,
                     double *Y_o, double *rmat_o, double *phi_o, double *sx_o)
 {
     double phi = 0.0;
@@ -261,7 +293,9 @@ static void mixture(const orc_ctx *x, int c, const double *rho, const double *I,
     }
     double Y = 0.0, pmin = 0.0, ps = 0.0;
     for (int m = 0; m < x->nmat; m++) {
-        Y += wm[m] * (orc_softening(&x->m[m], I[c]) * orc_yield(&x->m[m], p));
+        /* the block model's vibration pressure rho c v_vib */
+        double Ym = x->dmg ? orc_yield_damaged(&x->m[m], p, Dc, rm * x->cL0[m] * vibc) : orc_yield(&x->m[m], p);
+        Y += wm[m] * (orc_softening(&x->m[m], I[c]) * Ym);
         pmin += wm[m] * x->m[m].p_min;
         ps += wm[m] * (PCAV_FRAC * x->m[m].A);
     }
@@ -281,18 +315,19 @@ static void mixture(const orc_ctx *x, int c, const double *rho, const double *I,
  * F_PM_EPS, or without mass, at the cell's matter density). Also returns the
  * material pressures (after the floor) and densities the energy update uses. */
 static void mixture_pm(const orc_ctx *x, int c, const double *rho, double *const *f, double *const *mu,
-                       double *const *Im, double *p_o, double *c2_o, double *G_o, double *Y_o,
-                       double *rmat_o, double *phi_o, double *sx_o, double *pm_o, double *rhm_o)
+                       double *const *Im, double Dc, double vibc, double *p_o, double *c2_o, double *G_o,
+                       double *Y_o, double *rmat_o, double *phi_o, double *sx_o, double *pm_o, double *rhm_o)
 {
     double phi = 0.0;
     for (int m = 0; m < x->nmat; m++) phi += f[m][c];
     double den = phi > PHI_EPS ? phi : PHI_EPS;
     double rm = rho[c] / den;
     double p = 0.0, c2 = 0.0, G = 0.0;
-    double wm[ORC_MAX_MAT], sf[ORC_MAX_MAT];
+    double wm[ORC_MAX_MAT], sf[ORC_MAX_MAT], rmv[ORC_MAX_MAT];
     for (int m = 0; m < x->nmat; m++) {
         double fm = f[m][c], mm = mu[m][c];
         double rmm = fm > F_PM_EPS && mm > 0.0 ? mm / fm : rm;
+        rmv[m] = rmm;
         double pm, c2m;
         wm[m] = fm / den;
         sf[m] = 0.0;
@@ -312,7 +347,8 @@ static void mixture_pm(const orc_ctx *x, int c, const double *rho, double *const
     double Y = 0.0, pmin = 0.0, ps = 0.0;
     for (int m = 0; m < x->nmat; m++) {
         if (f[m][c] == 0.0) continue;
-        Y += wm[m] * (sf[m] * orc_yield(&x->m[m], p));
+        double Ym = x->dmg ? orc_yield_damaged(&x->m[m], p, Dc, rmv[m] * x->cL0[m] * vibc) : orc_yield(&x->m[m], p);
+        Y += wm[m] * (sf[m] * Ym);
         pmin += wm[m] * x->m[m].p_min;
         ps += wm[m] * (PCAV_FRAC * x->m[m].A);
     }
@@ -330,10 +366,11 @@ static void mixture_pm(const orc_ctx *x, int c, const double *rho, double *const
 static void cell_mixture(const orc_ctx *x, int c, double *p_o, double *c2_o, double *G_o, double *Y_o,
                          double *rmat_o, double *phi_o, double *sx_o, double *pm_o, double *rhm_o)
 {
+    double Dc = x->dmg ? x->D[c] : 0.0, vc = x->dmg ? x->vib[c] : 0.0;
     if (x->pm)
-        mixture_pm(x, c, x->rho, x->f, x->mu, x->Im, p_o, c2_o, G_o, Y_o, rmat_o, phi_o, sx_o, pm_o, rhm_o);
+        mixture_pm(x, c, x->rho, x->f, x->mu, x->Im, Dc, vc, p_o, c2_o, G_o, Y_o, rmat_o, phi_o, sx_o, pm_o, rhm_o);
     else
-        mixture(x, c, x->rho, x->I, x->f, p_o, c2_o, G_o, Y_o, rmat_o, phi_o, sx_o);
+        mixture(x, c, x->rho, x->I, x->f, Dc, vc, p_o, c2_o, G_o, Y_o, rmat_o, phi_o, sx_o);
 }
 
 /* closure 1: rho = sum of the partial densities, I = their mass-weighted
@@ -452,7 +489,15 @@ void orc_cell_kinematics(const orc_grid *g, int32_t i, int32_t j, const double *
 
 /* Jaumann-rate elastic trial stress and radial return onto Y (strength model,
  * Table 1). rates = (e_rr, e_zz, e_tt, e_rz, omega); s = (s_rr, s_zz, s_rz). */
+static double stress_update(double G, double Y, double dt, const double *rt, double *s);
+
 void orc_stress_update(double G, double Y, double dt, const double *rt, double *s)
+{
+    (void)stress_update(G, Y, dt, rt, s);
+}
+
+/* the same, returning the equivalent stress of the elastic trial state */
+static double stress_update(double G, double Y, double dt, const double *rt, double *s)
 {
     double srr = s[0], szz = s[1], srz = s[2];
     double tr3 = ((rt[0] + rt[1]) + rt[2]) / 3.0;
@@ -474,6 +519,7 @@ void orc_stress_update(double G, double Y, double dt, const double *rt, double *
     s[0] = srr;
     s[1] = szz;
     s[2] = srz;
+    return seq;
 }
 
 /* Material volume ratio over a Lagrangian step whose cell volume ratio is J,
@@ -525,16 +571,31 @@ orc_ctx *orc_create(const orc_grid *g, const orc_mat *mats, const orc_pml *pml)
         if (!(g->dr_col[i] > 0) || !isfinite(g->dr_col[i])) return NULL;
     for (int j = 0; g->dz_row && j < g->n_z + g->pml_b; j++)
         if (!(g->dz_row[j] > 0) || !isfinite(g->dz_row[j])) return NULL;
+    for (int m = 0; m < g->nmat; m++) {
+        const orc_mat *M = &mats[m];
+        if (M->damage != 0 && M->damage != 1) return NULL;
+        if (M->damage && (!M->strength || !(M->Yd0 >= 0) || !(M->Ydm >= M->Yd0) || !(M->mu_d >= 0) ||
+                          !(M->eps_fb > 0) || !(M->B_dmg >= 0) || !(M->gamma_eta >= 0) || !(M->gamma_T >= 0) ||
+                          !(M->c_vib >= 0) || ((M->gamma_eta > 0 || M->gamma_T > 0) && !(M->af_h > 0))))
+            return NULL;
+    }
     orc_ctx *x = (orc_ctx *)calloc(1, sizeof(orc_ctx));
     x->g = *g;
     x->pml = *pml;
     x->nmat = g->nmat;
     x->pm = g->closure == 1;
     for (int m = 0; m < g->nmat; m++) {
+        const orc_mat *M = &mats[m];
         x->m[m] = mats[m];
         x->Gm[m] = mats[m].strength ? 3.0 * (1.0 - 2.0 * mats[m].poisson) / (2.0 * (1.0 + mats[m].poisson)) : 0.0;
         if (mats[m].strength) x->any_strength = 1;
         if (mats[m].rho0 > x->rho_ref) x->rho_ref = mats[m].rho0;
+        if (M->damage) {
+            x->dmg = 1;
+            x->cL0[m] = sqrt((M->A + (4.0 / 3.0) * orc_shear_modulus(M)) / M->rho0);
+            x->nub[m] = M->gamma_eta * x->cL0[m] * M->af_h;
+            x->Tvib[m] = M->gamma_T * M->af_h / x->cL0[m];
+        }
     }
     int NR = g->n_r + g->pml_r, NZ = g->n_z + g->pml_b;
     x->NR = NR;
@@ -622,6 +683,8 @@ orc_ctx *orc_create(const orc_grid *g, const orc_mat *mats, const orc_pml *pml)
     x->psi1n_z = zalloc(NN);
     x->psi2n = zalloc(NC);
     x->rho_t = zalloc(NC);
+    double **dmga[] = {&x->D, &x->vib, &x->D_n, &x->vib_n, &x->DL, &x->vibL, &x->etab};
+    for (size_t k = 0; k < sizeof(dmga) / sizeof(dmga[0]); k++) *dmga[k] = zalloc(NC);
     x->p0 = zalloc(NZ);
     x->dcz = zalloc(NZ);
     x->dnz = zalloc(NZ + 1);
@@ -695,6 +758,8 @@ void orc_destroy(orc_ctx *x)
     free(x->psi1n_z);
     free(x->psi2n);
     free(x->rho_t);
+    double *dmga[] = {x->D, x->vib, x->D_n, x->vib_n, x->DL, x->vibL, x->etab};
+    for (size_t k = 0; k < sizeof(dmga) / sizeof(dmga[0]); k++) free(dmga[k]);
     for (int m = 0; m < ORC_MAX_MAT; m++) {
         free(x->f[m]);
         free(x->f_n[m]);
@@ -872,6 +937,7 @@ int orc_init_scene(orc_ctx *x, const orc_scene *s)
                 x->Im[m][c] = 0.0;
             }
             x->srr[c] = x->szz[c] = x->srz[c] = 0.0;
+            x->D[c] = x->vib[c] = 0.0;
         }
     }
     /* node velocity = -v_imp * (projectile mass) / (total mass) over the four
@@ -942,6 +1008,8 @@ int orc_set_fields(orc_ctx *x, const double *rho, const double *I, const double 
     }
     memcpy(x->vr, v, sizeof(double) * NN);
     memcpy(x->vz, v + NN, sizeof(double) * NN);
+    memset(x->D, 0, sizeof(double) * NC);
+    memset(x->vib, 0, sizeof(double) * NC);
     /* closure 1: every material of a cell at the cell's matter density and
      * specific energy */
     for (size_t c = 0; c < NC; c++) {
@@ -954,6 +1022,22 @@ int orc_set_fields(orc_ctx *x, const double *rho, const double *I, const double 
         }
     }
     start_run(x);
+    return ORC_OK;
+}
+
+int orc_set_damage(orc_ctx *x, const double *D, const double *vib)
+{
+    if (!x) return ORC_E_INVALID;
+    if (D) memcpy(x->D, D, sizeof(double) * (size_t)x->NC);
+    if (vib) memcpy(x->vib, vib, sizeof(double) * (size_t)x->NC);
+    return ORC_OK;
+}
+
+int orc_get_damage(orc_ctx *x, double *D, double *vib)
+{
+    if (!x) return ORC_E_INVALID;
+    if (D) memcpy(D, x->D, sizeof(double) * (size_t)x->NC);
+    if (vib) memcpy(vib, x->vib, sizeof(double) * (size_t)x->NC);
     return ORC_OK;
 }
 
@@ -1028,6 +1112,14 @@ static void phase_cell_stress(orc_ctx *x)
             x->sgzz[c] = phi * (x->szz[c] - Pf);
             x->sgtt[c] = phi * (stt - Pf);
             x->sgrz[c] = phi * x->srz[c];
+            if (x->dmg) {
+                /* block model: dynamic viscosity rho gamma_eta c h of the damaged
+                 * rock (weight D) while it vibrates (ramp to full at VIB_ON) */
+                double nu = 0.0;
+                for (int m = 0; m < x->nmat; m++)
+                    if (x->m[m].damage) nu += (x->f[m][c] / dmax(phi, PHI_EPS)) * x->nub[m];
+                x->etab[c] = (x->D[c] * dmin(x->vib[c] / VIB_ON, 1.0)) * (rm * nu);
+            }
         }
     }
 }
@@ -1118,10 +1210,35 @@ static void phase_cell_lagrange(orc_ctx *x)
             col_t cg = col_at(x, i);
             kinematics(&cg, x->dzr[j], vr4, vz4, &k);
             double s[3] = {x->srr[c], x->szz[c], x->srz[c]};
+            double DLc = x->dmg ? x->D[c] : 0.0;
             if (x->any_strength) {
                 double rt[5] = {k.err, k.ezz, k.ett, k.erz, k.om};
-                orc_stress_update(x->G[c], x->Y[c], dt, rt, s);
+                double Yr = x->Y[c];
+                if (x->dmg) {
+                    /* the block model's viscous resistance (Bingham): the flow
+                     * stress exceeds Y by 3 eta times the equivalent strain rate
+                     * sqrt(2/3 e':e') of this step */
+                    double tr3 = ((k.err + k.ezz) + k.ett) / 3.0;
+                    double dr_ = k.err - tr3, dz_ = k.ezz - tr3, dt_ = k.ett - tr3;
+                    double e2 = ((dr_ * dr_ + dz_ * dz_) + dt_ * dt_) + 2.0 * (k.erz * k.erz);
+                    Yr = Yr + 3.0 * x->etab[c] * sqrt((2.0 / 3.0) * e2);
+                }
+                double seq = stress_update(x->G[c], Yr, dt, rt, s);
+                if (x->dmg) {
+                    /* damage grows by the equivalent plastic strain of the
+                     * return, (trial - yield) / 3G, over the failure strain at
+                     * the cell's pressure (volume-fraction weighted rate) */
+                    double G = x->G[c];
+                    double dep = G > 0.0 ? dmax(seq - Yr, 0.0) / (3.0 * G) : 0.0;
+                    double rate = 0.0;
+                    for (int m = 0; m < x->nmat; m++)
+                        if (x->m[m].damage)
+                            rate += (x->f[m][c] / dmax(x->phi[c], PHI_EPS)) / orc_failure_strain(&x->m[m], x->p[c]);
+                    DLc = dmin(x->D[c] + dep * rate, 1.0);
+                }
             }
+            x->DL[c] = DLc;
+            x->vibL[c] = x->dmg ? x->vib[c] : 0.0;
             /* the deviatoric power uses s^n, the stress that produced the node
              * forces, so the step's work equals the forces' work exactly */
             double s0rr = x->srr[c], s0zz = x->szz[c], s0rz = x->srz[c];
@@ -1348,11 +1465,17 @@ static void phase_cell_remap(orc_ctx *x)
              * opposite faces paired */
             double tm[4] = {0}, tI[4] = {0}, tsrr[4] = {0}, tszz[4] = {0}, tsrz[4] = {0}, tcut[4] = {0};
             double tf[ORC_MAX_MAT][4] = {{0}};
+            double tD[4] = {0}, tV[4] = {0};
             for (int q = 0; q < 4; q++) {
                 int dc_ok = di[q] >= 0 && di[q] < NR && dj[q] >= 0 && dj[q] < NZ;
                 int dc = dc_ok ? CI(di[q], dj[q]) : -1;
                 if (in[q]) {
                     double aF = fabs(F[q]), adV = fabs(dVe[q]);
+                    if (x->dmg) {
+                        /* damage and vibration speed travel with the mass */
+                        tD[q] = aF * ((dc_ok ? x->DL[dc] : 0.0) - x->DL[c]);
+                        tV[q] = aF * ((dc_ok ? x->vibL[dc] : 0.0) - x->vibL[c]);
+                    }
                     tcut[q] = fabs(dV[q]) - adV;
                     double Id = dc_ok ? x->IL[dc] : 0.0;
                     tm[q] = aF;
@@ -1373,6 +1496,10 @@ static void phase_cell_remap(orc_ctx *x)
             for (int m = 0; m < nm; m++) nf[m] = face_sum(tf[m]);
             double den = dmax(dmax(M1, min_), M_REMAP_FLOOR * x->rho_ref * V);
             double I1 = IL + nI / den;
+            if (x->dmg) {
+                x->D_n[c] = x->DL[c] + face_sum(tD) / den;
+                x->vib_n[c] = x->vibL[c] + face_sum(tV) / den;
+            }
             x->srr_n[c] = x->sLrr[c] + nsrr / den;
             x->szz_n[c] = x->sLzz[c] + nszz / den;
             x->srz_n[c] = x->sLrz[c] + nsrz / den;
@@ -1618,6 +1745,26 @@ static void phase_cell_heat(orc_ctx *x)
             int c = CI(i, j);
             double h = (x->heat[NI(i, j)] + x->heat[NI(i + 1, j)]) + (x->heat[NI(i, j + 1)] + x->heat[NI(i + 1, j + 1)]);
             x->I_n[c] = x->I_n[c] + h;
+            if (x->dmg) {
+                /* block model: the vibration decays as exp(-dt / T) over the
+                 * step and is excited to c_vib times the largest corner speed
+                 * of the new velocities (volume-fraction weighted constants) */
+                double phin = 0.0;
+                for (int m = 0; m < x->nmat; m++) phin += x->f_n[m][c];
+                double den = phin > PHI_EPS ? phin : PHI_EPS;
+                double kdec = 0.0, cv = 0.0;
+                for (int m = 0; m < x->nmat; m++) {
+                    if (!x->m[m].damage) continue;
+                    double w = x->f_n[m][c] / den;
+                    kdec += w * (x->Tvib[m] > 0.0 ? exp_cw(-x->dt / x->Tvib[m]) : 0.0);
+                    cv += w * x->m[m].c_vib;
+                }
+                int nd[4] = {NI(i, j), NI(i + 1, j), NI(i, j + 1), NI(i + 1, j + 1)};
+                double u = 0.0;
+                for (int q = 0; q < 4; q++)
+                    u = dmax(u, sqrt(x->vr_n[nd[q]] * x->vr_n[nd[q]] + x->vz_n[nd[q]] * x->vz_n[nd[q]]));
+                x->vib_n[c] = dmax(x->vib_n[c] * kdec, cv * u);
+            }
             if (x->pm) {
                 for (int m = 0; m < x->nmat; m++) x->Im_n[m][c] = x->Im_n[m][c] + h;
                 derive_cell(x, x->mu_n, x->Im_n, x->rho_n, x->I_n, c);
@@ -1642,6 +1789,7 @@ static int check_state(orc_ctx *x)
         double s = x->rho[c] + x->I[c] + x->srr[c] + x->szz[c] + x->srz[c];
         for (int m = 0; m < x->nmat; m++) s += x->f[m][c];
         for (int m = 0; x->pm && m < x->nmat; m++) s += x->mu[m][c] + x->Im[m][c];
+        if (x->dmg) s += x->D[c] + x->vib[c];
         if (!isfinite(s)) bad = 1;
         if (x->rho[c] < tol) neg = 1;
     }
@@ -1671,6 +1819,10 @@ static int one_cycle(orc_ctx *x)
     swap(&x->srr, &x->srr_n);
     swap(&x->szz, &x->szz_n);
     swap(&x->srz, &x->srz_n);
+    if (x->dmg) {
+        swap(&x->D, &x->D_n);
+        swap(&x->vib, &x->vib_n);
+    }
     swap(&x->vr, &x->vr_n);
     swap(&x->vz, &x->vz_n);
     x->t = x->t + x->dt;

@@ -61,6 +61,21 @@ typedef struct {
     double c_floor_frac; /* c^2 floor = c_floor_frac * A / rho0             */
     int32_t strength;    /* 0: hydrodynamic, 1: elasto-plastic              */
     double Y0, mu_f, Ylim, poisson;
+    /* Damage and acoustic fluidization (Table 1's damaged-material and
+     * block-model constants; the equations are readings, see the source):
+     * with damage = 1 the yield strength blends from the intact curve to the
+     * damaged one, Y_d = min(Yd0 + mu_d p, Ydm) (never above the intact), by
+     * the cell's damage D, which grows by the plastic strain of the radial
+     * return over the failure strain max(eps_fb, B_dmg (p - p_bd)); the
+     * damaged friction sees the pressure less the vibration pressure
+     * rho c v_vib of the block model, whose vibration speed decays with time
+     * constant gamma_T h / c and is excited to c_vib times the local flow
+     * speed, and whose viscosity gamma_eta rho c h resists the flow of
+     * damaged, vibrating rock (c: longitudinal speed at rest, h: block size) */
+    int32_t damage;
+    double Yd0, mu_d, Ydm;
+    double eps_fb, B_dmg, p_bd;
+    double gamma_eta, gamma_T, c_vib, af_h;
 } orc_mat;
 
 typedef struct {
@@ -125,6 +140,10 @@ int orc_set_p0(orc_ctx *x, const double *p0);
 int orc_set_materials(orc_ctx *x, const double *mu, const double *Im);
 int orc_get_materials(orc_ctx *x, double *mu, double *Im);
 int orc_get_p0(orc_ctx *x, double *p0);
+/* damage D and block-model vibration speed v_vib per cell (NC values each;
+ * zero after orc_set_fields and orc_init_scene); either pointer may be NULL */
+int orc_set_damage(orc_ctx *x, const double *D, const double *vib);
+int orc_get_damage(orc_ctx *x, double *D, double *vib);
 int orc_step(orc_ctx *x, int32_t n);
 /* any pointer may be NULL; p and c2 are evaluated from the current state */
 int orc_get_fields(orc_ctx *x, double *rho, double *I, double *f, double *s,
@@ -150,6 +169,11 @@ double orc_yield(const orc_mat *m, double p);
 double orc_shear_modulus(const orc_mat *m);
 /* strength factor in [0, 1] from the specific internal energy */
 double orc_softening(const orc_mat *m, double e);
+/* yield strength of damage D at pressure p and vibration pressure p_vib
+ * (before softening; the intact curve when damage is off) */
+double orc_yield_damaged(const orc_mat *m, double p, double D, double p_vib);
+/* failure strain max(eps_fb, B_dmg (p - p_bd)) of the damage law */
+double orc_failure_strain(const orc_mat *m, double p);
 /* one constitutive update: s[3] in/out, rates = (e_rr, e_zz, e_tt, e_rz, omega) */
 void orc_stress_update(double G, double Y, double dt, const double *rates, double *s);
 /* strain rates of cell (i, j) from its four node velocities

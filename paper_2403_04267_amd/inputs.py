@@ -41,6 +41,21 @@ class Material:
     mu_f: float = 0.0
     Ylim: float = 0.0
     poisson: float = 0.25
+    # damage and acoustic fluidization (Table 1's damaged cohesion, friction
+    # and limit, and the block model's gamma_eta, gamma_T, c_vib); the damage
+    # law's failure strain max(eps_fb, B_dmg (p - p_bd)) and the block size
+    # af_h (m) are not in the paper
+    damage: int = 0
+    Yd0: float = 0.0
+    mu_d: float = 0.0
+    Ydm: float = 0.0
+    eps_fb: float = 1e-4
+    B_dmg: float = 1e-11
+    p_bd: float = 3e8
+    gamma_eta: float = 0.0
+    gamma_T: float = 0.0
+    c_vib: float = 0.0
+    af_h: float = 0.0
 
 
 @dataclass
@@ -191,6 +206,25 @@ def calcite(strength: bool = True) -> Material:
     m = Material(rho0=2710.0, A=70e9, B=70e9, E0=487e6, a=0.5, b=1.5, alpha=5.0,
                  beta=5.0, Eiv=4.72e6, Ecv=18.2e6, p_min=0.0, c_floor_frac=0.25)
     return _with_strength(m, 5e6, 1.0, 0.5e9) if strength else m
+
+
+def with_damage(m: Material, Yd0: float, mu_d: float, Ydm: float, gamma_eta: float = 0.0,
+                gamma_T: float = 0.0, c_vib: float = 0.0, af_h: float = 0.0) -> Material:
+    """The same material with damage and, where gamma_eta, gamma_T or c_vib
+    are nonzero, the block model of acoustic fluidization (block size af_h)."""
+    m = dataclasses.replace(m)
+    m.damage = 1
+    m.Yd0, m.mu_d, m.Ydm = Yd0, mu_d, Ydm
+    m.gamma_eta, m.gamma_T, m.c_vib, m.af_h = gamma_eta, gamma_T, c_vib, af_h
+    return m
+
+
+# Table 1's damaged-material and block-model constants per rock
+TABLE1_DAMAGE = {
+    "granite": dict(Yd0=0.01e6, mu_d=0.6, Ydm=2.5e9, gamma_eta=0.008, gamma_T=115.0, c_vib=0.1),
+    "dunite": dict(Yd0=0.01e6, mu_d=0.6, Ydm=3.5e9, gamma_eta=0.08, gamma_T=50.0, c_vib=0.1),
+    "calcite": dict(Yd0=0.01e6, mu_d=0.4, Ydm=0.5e9, gamma_eta=0.0, gamma_T=0.0, c_vib=0.0),
+}
 
 
 def ideal_gas(gamma: float = 1.4) -> Material:
