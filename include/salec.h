@@ -109,8 +109,28 @@ typedef struct salec_material {
     double p_min;        /* pressure floor, Pa                                   */
     double c_floor_frac; /* c^2 >= c_floor_frac * A / rho0                       */
     int32_t strength;    /* 0: hydrodynamic, 1: elasto-plastic (Table 1 form)     */
-    int32_t reserved;    /* must be 0                                            */
+    int32_t damage;      /* 0: intact strength only; 1: damage and the block     */
+                         /* model of acoustic fluidization (needs strength;      */
+                         /* the fields below; Table 1 lists their parameters     */
+                         /* and the paper gives no equations, so the laws are    */
+                         /* the library's documented readings)                   */
     double Y0, mu_f, Ylim, poisson; /* cohesion, friction, limit strength, nu   */
+    /* damage = 1 only: the yield blends (1 - D) Y_intact(p) + D Y_damaged,     */
+    /* Y_damaged = min(Yd0 + mu_d max(p - p_vib, 0), Ydm) for p >= 0 (never     */
+    /* above the intact curve), and D (per cell, in [0, 1], advected with the   */
+    /* mass) grows by the radial return's plastic strain (trial - Y) / 3G over  */
+    /* the failure strain max(eps_fb, B_dmg (p - p_bd))                         */
+    double Yd0, mu_d, Ydm;  /* damaged cohesion (Pa), friction, limit (Pa)      */
+    double eps_fb;       /* failure strain of brittle rock (> 0)                 */
+    double B_dmg;        /* its growth with pressure, 1/Pa (>= 0)                */
+    double p_bd;         /* brittle-ductile transition pressure, Pa              */
+    /* block model: a vibration speed v_vib per cell decays as exp(-dt / T),   */
+    /* T = gamma_T h / c, is excited to c_vib times the largest corner speed,   */
+    /* relieves the damaged friction by p_vib = rho c v_vib, and the viscosity  */
+    /* rho gamma_eta c h raises the flow stress of damaged, vibrating rock by   */
+    /* 3 eta times its equivalent strain rate (c: longitudinal speed at rest)   */
+    double gamma_eta, gamma_T, c_vib; /* >= 0 each (zeros: no fluidization)     */
+    double af_h;         /* block size h, m (> 0 when gamma_eta or gamma_T > 0)  */
 } salec_material;
 
 typedef struct salec_pml {
@@ -358,6 +378,20 @@ int salec_get_p0(salec_ctx *ctx, int32_t instance, double *p0);
  * or when the member uses SALEC_CLOSURE_SHARED. */
 int salec_set_materials(salec_ctx *ctx, int32_t instance, const double *mu, const double *Im);
 int salec_get_materials(salec_ctx *ctx, int32_t instance, double *mu, double *Im);
+
+/* Damage D and block-model vibration speed v_vib (m/s) of member `instance`
+ * (Table 1's damaged-material and acoustic-fluidization rows), NZ*NR host
+ * FP64 values each, row-major with r fastest. They exist when some material
+ * of the context has damage = 1 (then every member carries them); the scene
+ * set-up and salec_set_fields leave intact, quiet rock (0, 0). salec_set_damage
+ * replaces either (a NULL pointer keeps it; D in [0, 1], v_vib finite and
+ * >= 0), keeps the rest of the current state and starts a new run at t = 0
+ * like salec_set_fields. salec_get_damage reads the current state; either
+ * pointer may be NULL. Checkpoints include both. Both return
+ * SALEC_E_INVALID for a bad context, instance or value, or when no material
+ * has damage. */
+int salec_set_damage(salec_ctx *ctx, int32_t instance, const double *D, const double *vib);
+int salec_get_damage(salec_ctx *ctx, int32_t instance, double *D, double *vib);
 
 /* Measurement (no passage): advances every member by n cycles
  * (1 <= n <= 100000) like salec_step(),

@@ -14,8 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsalec.so")
-SOURCES = ["salec_cycle_f64.hip", "salec_cycle_f32.hip", "salec_cycle.hip", "salec_kernels.hip",
-           "salec_host.hip"]
+SOURCES = ["salec_cycle_f64.hip", "salec_cycle_f32.hip", "salec_cycle_dm_f64.hip", "salec_cycle_dm_f32.hip",
+           "salec_cycle.hip", "salec_kernels.hip", "salec_host.hip"]
 HEADERS = ["salec_device.hpp", "salec_internal.hpp", "salec_cycle.hpp"]
 ARCH = os.environ.get("SALEC_ARCH", "gfx950")
 

@@ -44,18 +44,19 @@ void variant_shape(int v, int* tw, int* th, int* nt) {
   *nt = kShapes[v][2];
 }
 
-static CycleFn cycle_kernel(int v, int prec, bool geo, int nm, bool pm) {
+static CycleFn cycle_kernel(int v, int prec, bool geo, int nm, bool pm, bool dm) {
   if (v < 0 || v >= n_variants()) return nullptr;
+  if (dm) return prec == 0 ? cycle_kernel_dm_f64(v, geo, nm, pm) : cycle_kernel_dm_f32(v, geo, nm, pm);
   return prec == 0 ? cycle_kernel_f64(v, geo, nm, pm) : cycle_kernel_f32(v, geo, nm, pm);
 }
 
-bool variant_available(int v, int prec, bool geo, int nm, bool pm) {
-  return cycle_kernel(v, prec, geo, nm, pm) != nullptr;
+bool variant_available(int v, int prec, bool geo, int nm, bool pm, bool dm) {
+  return cycle_kernel(v, prec, geo, nm, pm, dm) != nullptr;
 }
 
-hipError_t launch_cycle(int v, int prec, bool geo, int nm, bool pm, const Inst* insts, const TileRef* sched,
-                        int nsched, int grid, hipStream_t st) {
-  CycleFn f = cycle_kernel(v, prec, geo, nm, pm);
+hipError_t launch_cycle(int v, int prec, bool geo, int nm, bool pm, bool dm, const Inst* insts,
+                        const TileRef* sched, int nsched, int grid, hipStream_t st) {
+  CycleFn f = cycle_kernel(v, prec, geo, nm, pm, dm);
   if (!f) return hipErrorInvalidValue;
   hipLaunchKernelGGL(f, dim3(grid), dim3(kShapes[v][2]), 0, st, insts, sched, nsched);
   return hipGetLastError();
@@ -114,8 +115,8 @@ hipError_t launch_finalize(const Inst* insts, int n_inst, hipStream_t st) {
   return hipGetLastError();
 }
 
-int resident_groups(int v, int prec, bool geo, int nm, bool pm) {
-  CycleFn f = cycle_kernel(v, prec, geo, nm, pm);
+int resident_groups(int v, int prec, bool geo, int nm, bool pm, bool dm) {
+  CycleFn f = cycle_kernel(v, prec, geo, nm, pm, dm);
   int per_cu = 0, cus = 0, dev = 0;
   if (!f || hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)f, kShapes[v][2], 0) != hipSuccess) return 0;

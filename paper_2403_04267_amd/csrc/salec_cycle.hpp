@@ -49,12 +49,12 @@ struct GeoLds {
   static constexpr int GC = TW + 8, GR = TH + 8, N = 6 * GC + GR;
 };
 
-template <int TW, int TH, class T, int NM, bool PM>
+template <int TW, int TH, class T, int NM, bool PM, bool DM = false>
 struct Smem {
   using R = Regions<TW, TH>;
   // FP64 fields of C's results: rhoL, IL, f[NM]; per-material closure:
-  // muL[NM], IL[NM], f[NM]
-  static constexpr int kNCd = PM ? 3 * NM : 2 + NM;
+  // muL[NM], IL[NM], f[NM]; with damage also D^L and v_vib
+  static constexpr int kNCd = (PM ? 3 * NM : 2 + NM) + (DM ? 2 : 0);
   static constexpr int kBigA = 4 * R::NA * (int)sizeof(T);                 // sigma[4][NA]
   static constexpr int kBigC = R::NC * (kNCd * 8 + 4 * (int)sizeof(T));    // C's FP64 fields | lambda, sL x3
   static constexpr int kBigF = R::NF * (8 + (int)sizeof(T));          // heat | speed
@@ -118,7 +118,7 @@ __device__ __forceinline__ void reg_put(T (&a)[N], int u, T v) {
   for (int q = 0; q < N; q++) a[q] = (u == q) ? v : a[q];
 }
 
-template <int TW, int TH, int NT, int WPE, class T, bool GEO, int NM, bool PM>
+template <int TW, int TH, int NT, int WPE, class T, bool GEO, int NM, bool PM, bool DM>
 __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_rho, double* s_bigd, T* s_vL,
                                            double* s_Fr, double* s_Fz, double* s_rho1, double* s_min,
                                            double* s_geo) {
@@ -208,9 +208,10 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     j = q < TH ? j0 + q : (q == TH ? j0 - 1 : j0 + TH);
   };
   // C's FP64 fields during C..E2: rhoL, IL, f[NM], or with the per-material
-  // closure muL[NM] (mu_m / J), IL[NM], f[NM]
-  constexpr int kNCd = Smem<TW, TH, T, NM, PM>::kNCd;
+  // closure muL[NM] (mu_m / J), IL[NM], f[NM]; then, with damage, D^L, v_vib
+  constexpr int kNCd = Smem<TW, TH, T, NM, PM, DM>::kNCd;
   constexpr int kFo = PM ? 2 * NM : 2;  // first volume-fraction field
+  constexpr int kDo = kFo + NM;         // damage field (then the vibration speed)
   T* sig = (T*)s_bigd;                // [4][NA] during A..B
   double* cd = s_bigd;                // [kNCd][NC] during C..E2
   T* ct = (T*)(s_bigd + kNCd * R::NC);  // [4][NC] lambda, sL x3 during C..E2
@@ -423,6 +424,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
 #pragma unroll
     for (int m = 0; m < NM; m++) of[m] = oMuL[m] = oILm[m] = 0.0;
     T oLam = T(1), os0 = T(0), os1 = T(0), os2 = T(0);
+    double oDL = 0.0, oVib = 0.0;  // damage and vibration speed (void donor: 0)
     if (in_cells(g, i, j)) {
       long long c = cidx(g, i, j);
       const int nb[4] = {kB(i, j), kB(i + 1, j), kB(i, j + 1), kB(i + 1, j + 1)};
@@ -449,6 +451,32 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       if (g.any_strength) {
         T G = ((const T*)S.eos[2])[c], Y = ((const T*)S.eos[3])[c];
         T tr3 = N::div((kn.err + kn.ezz) + kn.ett, T(3));
+        // damage: the volume-fraction weights of the level-n cell
+        T dw[kMaxMat];
+        if constexpr (DM) {
+          oDL = S.dmg[c];
+          oVib = S.vib[c];
+          T fw[kMaxMat];
+#pragma unroll
+          for (int m = 0; m < kMaxMat; m++)
+            fw[m] = m < NM && m < g.nmat ? (T)(kKeepA ? reg_get(rF[m], u) : S.f[m][c]) : T(0);
+          T phw, dnw, rmw;
+          matter(g, (T)s_rho[kA(i, j)], fw, phw, dnw, rmw);
+          // block model: dynamic viscosity rho gamma_eta c h of the damaged
+          // rock (weight D) while it vibrates (full above kVibOn); the flow
+          // stress exceeds Y by 3 eta times the equivalent strain rate
+          // sqrt(2/3 e':e') of the step (a Bingham material)
+          T nu = T(0);
+#pragma unroll
+          for (int m = 0; m < kMaxMat; m++) {
+            dw[m] = N::div(fw[m], dnw);
+            if (m < NM && m < g.nmat && GT::mat(g, m).damage) nu += dw[m] * GT::mat(g, m).nub;
+          }
+          T eta = ((T)oDL * tmin(N::div((T)oVib, T(kVibOn)), T(1))) * (rmw * nu);
+          T er = kn.err - tr3, ez = kn.ezz - tr3, et = kn.ett - tr3;
+          T e2 = ((er * er + ez * ez) + et * et) + T(2) * (kn.erz * kn.erz);
+          Y = Y + T(3) * eta * N::sqr(T(2.0 / 3.0) * e2);
+        }
         T om = kn.om;
         T dsrr = T(2) * G * (kn.err - tr3) + T(2) * om * srz;
         T dszz = T(2) * G * (kn.ezz - tr3) - T(2) * om * srz;
@@ -463,6 +491,22 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
           srr = srr * fac;
           szz = szz * fac;
           srz = srz * fac;
+        }
+        if constexpr (DM) {
+          // damage grows by the equivalent plastic strain of the return,
+          // (trial - yield) / 3G, over each damaging material's failure
+          // strain max(eps_fb, B (p - p_bd)) at the cell's pressure
+          // (volume-fraction weighted rate), capped at 1
+          T dep = G > T(0) ? N::div(tmax(seq - Y, T(0)), T(3) * G) : T(0);
+          T pc = ((const T*)S.eos[0])[c];
+          T rate = T(0);
+#pragma unroll
+          for (int m = 0; m < kMaxMat; m++) {
+            if (!(m < NM && m < g.nmat)) continue;
+            const MatT<T>& M = GT::mat(g, m);
+            if (M.damage) rate += N::div(dw[m], tmax(M.eps_fb, M.B_dmg * (pc - M.p_bd)));
+          }
+          oDL = dmin(oDL + (double)(dep * rate), 1.0);
         }
       }
       T stt = -(s0rr + s0zz);
@@ -566,6 +610,10 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       oLam = J;  // the limiter pass below turns J into lambda
     }
     int kc = kC(i, j);
+    if constexpr (DM) {
+      cd[kDo * R::NC + kc] = oDL;
+      cd[(kDo + 1) * R::NC + kc] = oVib;
+    }
     if constexpr (PM) {
 #pragma unroll
       for (int m = 0; m < NM; m++) {
@@ -743,6 +791,24 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       double O = (double)((tmax(-dV[0], T(0)) + tmax(dV[1], T(0))) + (tmax(-dV[2], T(0)) + tmax(dV[3], T(0))));
       double den = dmax(dmax(M1, min_), kMRemapFloor * g.rho_ref * V);
       double I1 = IL + nI / den;
+      // damage and vibration speed travel with the mass (donor values, the
+      // faces paired as above)
+      double Dn = 0.0, Vn = 0.0;
+      if constexpr (DM) {
+        const double DLc = cd[kDo * R::NC + kc], VLc = cd[(kDo + 1) * R::NC + kc];
+        double tD[4], tV[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          tD[q] = tV[q] = 0.0;
+          if (inq[q]) {
+            const double aF = fabs(F[q]);
+            tD[q] = aF * (cd[kDo * R::NC + dk[q]] - DLc);
+            tV[q] = aF * (cd[(kDo + 1) * R::NC + dk[q]] - VLc);
+          }
+        }
+        Dn = DLc + face_sum(tD) / den;
+        Vn = VLc + face_sum(tV) / den;
+      }
       // per-material closure: every material's specific energy remapped with
       // its own mass fluxes (donor values); the energy fluxes are the sums
       // over materials
@@ -884,6 +950,12 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
 #pragma unroll
         for (int m = 0; m < NM; m++)
           if (m == 0 || m < g.nmat) chk += fv[m];
+        if constexpr (DM) {
+          // G excites the vibration speed and reads both back
+          D.dmg[c] = Dn;
+          D.vib[c] = Vn;
+          chk += Dn + Vn;
+        }
         if (!((chk - chk) == 0.0)) flags |= kFlagNonFinite;
         if (rho1 < -kNegMassTol * g.rho_ref) flags |= kFlagNegMass;
       }
@@ -1060,15 +1132,39 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
 #pragma unroll
     for (int m = 0; m < kMaxMat; m++)
       f[m] = m >= NM ? 0.0 : (kCarry ? reg_get(eF[m], u) : (m < g.nmat ? D.f[m][c] : 0.0));
+    // block model: the vibration speed decays as exp(-dt / T_vib) over the
+    // step and is excited to c_vib times the largest corner speed of the new
+    // velocities (volume-fraction weighted constants of the damaging
+    // materials); the new state's yield sees it and the new damage
+    double Dg = 0.0, Vg = 0.0;
+    if constexpr (DM) {
+      Dg = D.dmg[c];
+      double phin = 0.0;
+#pragma unroll
+      for (int m = 0; m < kMaxMat; m++)
+        if (m < NM && m < g.nmat) phin += f[m];
+      const double dn = phin > kPhiEps ? phin : kPhiEps;
+      double kdec = 0.0, cv = 0.0;
+#pragma unroll
+      for (int m = 0; m < kMaxMat; m++) {
+        if (!(m < NM && m < g.nmat) || !g.m[m].damage) continue;
+        const double w = f[m] / dn;
+        kdec += w * (g.m[m].Tvib > 0.0 ? exp_cw(-dt / g.m[m].Tvib) : 0.0);
+        cv += w * g.m[m].c_vib;
+      }
+      Vg = dmax(D.vib[c] * kdec, cv * (double)u4);
+      D.vib[c] = Vg;
+      if (!((Vg - Vg) == 0.0)) flags |= kFlagNonFinite;
+    }
     Mix<T> mx;
     if constexpr (PM) {
       T pmv[kMaxMat];
-      mx = mixture_pm<T>(g, D.rho[c], f, mu, Imv, pmv);
+      mx = mixture_pm<T, DM>(g, D.rho[c], f, mu, Imv, pmv, Dg, Vg);
 #pragma unroll
       for (int m = 0; m < NM; m++)
         if (m < g.nmat) ((T*)D.pmat[m])[c] = pmv[m];
     } else {
-      mx = mixture<T>(g, kCarry ? eRho[u] : D.rho[c], I1, f);
+      mx = mixture<T, DM>(g, kCarry ? eRho[u] : D.rho[c], I1, f, Dg, Vg);
     }
     store_eos(D, c, mx);
     cand = dmin(cand, cell_dt(g, mx, u4, dmin(colD(i).dr, dzD(j))));
@@ -1078,11 +1174,11 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   if (tid == 0) in.dtpart[tile] = m;
 }
 
-template <int TW, int TH, int NT, int WPE, class T, bool GEO, int NM, bool PM>
+template <int TW, int TH, int NT, int WPE, class T, bool GEO, int NM, bool PM, bool DM = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_cycle(const Inst* __restrict__ insts, const TileRef* __restrict__ sched,
                                               int nsched) {
   using R = Regions<TW, TH>;
-  using SM = Smem<TW, TH, T, NM, PM>;
+  using SM = Smem<TW, TH, T, NM, PM, DM>;
   __shared__ double s_rho[R::NA];     // rho^n over A (0 outside the grid)
   __shared__ double s_bigd[SM::kBigD];  // A..B stress; C..E2 Lagrangian state; F..G heat, speed
   __shared__ T s_vL[2 * R::NB];       // v^L over B
@@ -1101,7 +1197,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     const TileRef tr{csched[e].inst, csched[e].tile};
     if (tr.inst < 0) continue;
     const Inst* in = (const Inst*)(cinst + tr.inst);
-    tile_cycle<TW, TH, NT, WPE, T, GEO, NM, PM>(*in, tr.tile, s_rho, s_bigd, s_vL, s_F, s_F + R::NRF, s_rho1, s_min,
+    tile_cycle<TW, TH, NT, WPE, T, GEO, NM, PM, DM>(*in, tr.tile, s_rho, s_bigd, s_vL, s_F, s_F + R::NRF, s_rho1, s_min,
                                             s_geo);
     __syncthreads();  // LDS is reused by the next entry
   }
@@ -1130,10 +1226,11 @@ __global__ void k_prime(Inst in) {
         mu[m] = m < g.nmat ? S.mu[m][c] : 0.0;
         Im[m] = m < g.nmat ? S.Im[m][c] : 0.0;
       }
-      mx = mixture_pm<T>(g, S.rho[c], f, mu, Im, pmv);
+      mx = g.dmg ? mixture_pm<T, true>(g, S.rho[c], f, mu, Im, pmv, S.dmg[c], S.vib[c])
+                 : mixture_pm<T>(g, S.rho[c], f, mu, Im, pmv);
       for (int m = 0; m < g.nmat; m++) ((T*)S.pmat[m])[c] = pmv[m];
     } else {
-      mx = mixture<T>(g, S.rho[c], S.I[c], f);
+      mx = g.dmg ? mixture<T, true>(g, S.rho[c], S.I[c], f, S.dmg[c], S.vib[c]) : mixture<T>(g, S.rho[c], S.I[c], f);
     }
     store_eos(S, c, mx);
     const long long nd[4] = {nidx(g, i, j), nidx(g, i + 1, j), nidx(g, i, j + 1), nidx(g, i + 1, j + 1)};
@@ -1276,6 +1373,36 @@ __global__ void k_prime(Inst in) {
     long long nc = (long long)in.g.NR * in.g.NZ;                                               \
     hipLaunchKernelGGL(k_prime<T>, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, in); \
     return hipGetLastError();                                                                  \
+  }
+
+// The damage family (damage and the block model of acoustic fluidization):
+// the same cycle with two more FP64 records per cell in LDS, so only the
+// shapes whose tiles still fit beside them (40 x 16 and 28 x 18 at 512
+// threads, 20 x 13 at 256, 48 x 14 at 768) are built.
+#define SALEC_CYCLE_DM_SHAPES(T, GEO, NM, PM)                 \
+  switch (v) {                                                \
+    case 1: return k_cycle<40, 16, 512, 4, T, GEO, NM, PM, true>;  \
+    case 7: return k_cycle<28, 18, 512, 4, T, GEO, NM, PM, true>;  \
+    case 10: return k_cycle<20, 13, 256, 3, T, GEO, NM, PM, true>; \
+    case 11: return k_cycle<48, 14, 768, 3, T, GEO, NM, PM, true>; \
+    default: return nullptr;                                  \
+  }
+#define SALEC_CYCLE_DM_TABLE(T, suffix)                                           \
+  CycleFn cycle_kernel_dm_##suffix(int v, bool geo, int nm, bool pm) {            \
+    if (geo) {                                                                    \
+      if (pm) {                                                                   \
+        if (nm <= 2) SALEC_CYCLE_DM_SHAPES(T, true, 2, true)                      \
+        SALEC_CYCLE_DM_SHAPES(T, true, 3, true)                                   \
+      }                                                                           \
+      if (nm <= 2) SALEC_CYCLE_DM_SHAPES(T, true, 2, false)                       \
+      SALEC_CYCLE_DM_SHAPES(T, true, 3, false)                                    \
+    }                                                                             \
+    if (pm) {                                                                     \
+      if (nm <= 2) SALEC_CYCLE_DM_SHAPES(T, false, 2, true)                       \
+      SALEC_CYCLE_DM_SHAPES(T, false, 3, true)                                    \
+    }                                                                             \
+    if (nm <= 2) SALEC_CYCLE_DM_SHAPES(T, false, 2, false)                        \
+    SALEC_CYCLE_DM_SHAPES(T, false, 3, false)                                     \
   }
 
 }  // namespace salec

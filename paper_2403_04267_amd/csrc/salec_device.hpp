@@ -26,6 +26,8 @@ constexpr double kNegMassTol = 1e-9;    // density below -tol rho_ref is an erro
 constexpr double kPcavFrac = 1e-4;      // cavitation pressure ramp (x A)
 constexpr double kFPmEps = 1e-6;        // per-material closure: below this volume
                                         // fraction a material takes the cell's matter density
+constexpr double kVibOn = 1e-3;         // block model: vibration speed (m/s) above which
+                                        // its viscosity acts fully (linear ramp below)
 
 // error flags raised by kernels, turned into codes by the finalize kernel
 constexpr unsigned kFlagNonFinite = 1u, kFlagNegMass = 2u;
@@ -42,7 +44,13 @@ struct MatT {
   // 1/rho0, A/rho0, 1/(Ecv - Eiv), 1/(Ylim - Y0), formed once on the host in
   // FP64; only the FP32 arithmetic uses them (FP64 divides as the method does)
   T irho0, Ar, idE, iYd;
-  int strength, pad;
+  // damage and the block model of acoustic fluidization (Table 1's damaged
+  // cohesion, friction and limit; gamma_eta, gamma_T, c_vib): the damaged
+  // curve, the failure strain max(eps_fb, B_dmg (p - p_bd)), the
+  // longitudinal speed at rest cL0, the kinematic viscosity gamma_eta cL0 h
+  // and the vibration decay time gamma_T h / cL0 (h: block size)
+  T Yd0, mu_d, Ydm, eps_fb, B_dmg, p_bd, cL0, nub, Tvib, c_vib;
+  int strength, damage;
 };
 using MatC = MatT<double>;
 using MatF = MatT<float>;
@@ -58,7 +66,7 @@ struct Geo {
   int closure;         // 0: shared material density and energy; 1: per material
   int damp_stress;     // the PML layers also relax the deviatoric stress (extension)
   int pml_place;       // 1: phi in the Lagrangian and psi in the Eulerian step
-  int pad_i;
+  int dmg;             // some material accumulates damage (state D, v_vib)
   double dr, dz, cfl, dt_grow, dt_max, dt_floor, t_stop, q_lin, q_quad;
   double rho_ref;
   float drf, dzf, q_linf, q_quadf, rho_reff, pad_f;
@@ -100,6 +108,9 @@ struct State {
   void *s[3], *v[2], *eos[kEos];
   double *mu[kMaxMat], *Im[kMaxMat];
   void* pmat[kMaxMat];
+  // damage and block-model vibration speed (FP64 in every precision;
+  // allocated when some material accumulates damage)
+  double *dmg, *vib;
 };
 
 // Scalars living in device memory so that captured graphs can be replayed.
@@ -315,6 +326,24 @@ __device__ inline T yield_strength(const MatT<T>& m, T p) {
   return tmax(T(0), m.Y0 + m.mu_f * p);
 }
 
+// Strength of a material with damage D (Table 1's damaged cohesion Y_d0,
+// friction mu_d and limit Y_dm): the damaged curve min(Y_d0 + mu_d q, Y_dm)
+// at the effective pressure q = max(p - pv, 0), pv the block model's
+// vibration pressure, for p >= 0, max(0, Y_d0 + mu_d p) in tension, never
+// above the intact curve; the two blend linearly in D.
+template <class T>
+__device__ inline T yield_damaged(const MatT<T>& m, T p, T D, T pv) {
+  T Yi = yield_strength(m, p);
+  if (!m.strength || !m.damage) return Yi;
+  T Yd;
+  if (p >= T(0))
+    Yd = tmin(m.Yd0 + m.mu_d * tmax(p - pv, T(0)), m.Ydm);
+  else
+    Yd = tmax(T(0), m.Yd0 + m.mu_d * p);
+  Yd = tmin(Yd, Yi);
+  return (T(1) - D) * Yi + D * Yd;
+}
+
 // strength fades linearly between incipient and complete vaporisation
 template <class T>
 __device__ inline T softening(const MatT<T>& m, T e) {
@@ -343,8 +372,11 @@ __device__ __forceinline__ void matter(const Geo& g, T rho, const T* f, T& phi, 
 // share rho_mat = rho / phi and I; p, c^2, G, Y are volume-fraction
 // weighted; sx is the expansion weight of the cavitation rule (1 above the
 // tension floor + ramp). Arithmetic in T (the density terms as above).
-template <class T>
-__device__ inline Mix<T> mixture(const Geo& g, double rho, double I, const double* fd) {
+// DM: the yield is the damaged strength at the cell's damage Dc and the
+// vibration pressure rho_mat cL0 vibc of each material.
+template <class T, bool DM = false>
+__device__ inline Mix<T> mixture(const Geo& g, double rho, double I, const double* fd, double Dc = 0.0,
+                                 double vibc = 0.0) {
   using N = Num<T>;
   Mix<T> o;
   T f[kMaxMat];
@@ -396,7 +428,13 @@ __device__ inline Mix<T> mixture(const Geo& g, double rho, double I, const doubl
     if (m >= g.nmat) break;
     if (fd[m] == 0.0) continue;
     const MatT<T>& M = GeoT<T>::mat(g, m);
-    T ym = (m > 0 && g.same_mat && have0) ? y0 : yield_strength(M, p);
+    T ym;
+    if (m > 0 && g.same_mat && have0)
+      ym = y0;
+    else if constexpr (DM)
+      ym = yield_damaged(M, p, (T)Dc, rm * M.cL0 * (T)vibc);
+    else
+      ym = yield_strength(M, p);
     if (m == 0) y0 = ym;
     Y += wm[m] * (sov[m] * ym);
     pmin += wm[m] * M.p_min;
@@ -418,9 +456,9 @@ __device__ inline Mix<T> mixture(const Geo& g, double rho, double I, const doubl
 // without mass, at the cell's matter density) and its own specific energy
 // Im_m. pmv receives each material's pressure after its floor (0 for a
 // material absent from the cell, which adds nothing anywhere).
-template <class T>
+template <class T, bool DM = false>
 __device__ inline Mix<T> mixture_pm(const Geo& g, double rho, const double* fd, const double* mud,
-                                    const double* Imd, T* pmv) {
+                                    const double* Imd, T* pmv, double Dc = 0.0, double vibc = 0.0) {
   using N = Num<T>;
   Mix<T> o;
   T f[kMaxMat];
@@ -434,16 +472,18 @@ __device__ inline Mix<T> mixture_pm(const Geo& g, double rho, const double* fd, 
     if (m < g.nmat) phid += fd[m];
   double rmd = rho / (phid > kPhiEps ? phid : kPhiEps);
   T p = T(0), c2 = T(0), G = T(0);
-  T wm[kMaxMat], sov[kMaxMat];
+  T wm[kMaxMat], sov[kMaxMat], rmv[kMaxMat];
 #pragma unroll
   for (int m = 0; m < kMaxMat; m++) {
     pmv[m] = T(0);
+    rmv[m] = T(0);
     if (m >= g.nmat) break;
     const MatT<T>& M = GeoT<T>::mat(g, m);
     wm[m] = N::div(f[m], den);
     sov[m] = T(0);
     if (fd[m] == 0.0) continue;
     double rmm = fd[m] > kFPmEps && mud[m] > 0.0 ? mud[m] / fd[m] : rmd;
+    rmv[m] = (T)rmm;
     T pm, c2m;
     Dens<T> dn = dens_terms(g.m[m], rmm, (T*)nullptr);
     T Ie = (T)Imd[m];
@@ -461,7 +501,12 @@ __device__ inline Mix<T> mixture_pm(const Geo& g, double rho, const double* fd, 
     if (m >= g.nmat) break;
     if (fd[m] == 0.0) continue;
     const MatT<T>& M = GeoT<T>::mat(g, m);
-    Y += wm[m] * (sov[m] * yield_strength(M, p));
+    T ym;
+    if constexpr (DM)
+      ym = yield_damaged(M, p, (T)Dc, rmv[m] * M.cL0 * (T)vibc);
+    else
+      ym = yield_strength(M, p);
+    Y += wm[m] * (sov[m] * ym);
     pmin += wm[m] * M.p_min;
     ps += wm[m] * M.pcav;
   }

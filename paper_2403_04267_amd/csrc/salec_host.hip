@@ -191,6 +191,8 @@ void carve_persistent(Member& mb, Carver& cv) {
       S.Im[m] = on ? cv.d(nc) : nullptr;
       S.pmat[m] = on ? cv.bytes(nc * es) : nullptr;
     }
+    S.dmg = g.dmg ? cv.d(nc) : nullptr;
+    S.vib = g.dmg ? cv.d(nc) : nullptr;
   }
   mb.aux_off = cv.off;
   long long nbc = (long long)g.pml_b * g.NR, nrc = (long long)g.NZ * g.pml_r;
@@ -303,6 +305,13 @@ int validate(const salec_grid* g, const salec_material* mats, const salec_pml* p
       return why = "Tillotson parameters of material " + std::to_string(m), SALEC_E_INVALID;
     if (M.strength && (!(M.Ylim > M.Y0) || M.Y0 < 0 || M.mu_f < 0 || !(M.poisson > -1.0 && M.poisson < 0.5)))
       return why = "strength parameters of material " + std::to_string(m), SALEC_E_INVALID;
+    if (M.damage != 0 && M.damage != 1) return why = "damage must be 0 or 1", SALEC_E_INVALID;
+    if (M.damage && (!M.strength || !(M.Yd0 >= 0) || !(M.Ydm >= M.Yd0) || !(M.mu_d >= 0) || !(M.eps_fb > 0) ||
+                     !(M.B_dmg >= 0) || !std::isfinite(M.p_bd) || !(M.gamma_eta >= 0) || !(M.gamma_T >= 0) ||
+                     !(M.c_vib >= 0) || ((M.gamma_eta > 0 || M.gamma_T > 0) && !(M.af_h > 0))))
+      return why = "damage parameters of material " + std::to_string(m) +
+                   " (damage needs strength; block size > 0 with gamma_eta or gamma_T)",
+             SALEC_E_INVALID;
   }
   if (pml->enabled && !(pml->R > 0 && pml->R < 1)) return why = "PML reflection coefficient", SALEC_E_INVALID;
   if (pml->damp_stress != 0 && pml->damp_stress != 1) return why = "PML damp_stress must be 0 or 1", SALEC_E_INVALID;
@@ -336,6 +345,27 @@ void fill_mat(MatT<T>& c, const salec_material& M) {
   c.Ar = (T)(M.A / M.rho0);
   c.idE = (T)(1.0 / (M.Ecv - M.Eiv));
   c.iYd = (T)(M.strength && M.Ylim != M.Y0 ? 1.0 / (M.Ylim - M.Y0) : 0.0);
+  // damage and the block model: the longitudinal speed at rest
+  // sqrt((A + 4G/3) / rho0), the kinematic viscosity gamma_eta cL0 h and the
+  // decay time gamma_T h / cL0 (formed in FP64)
+  c.damage = M.damage ? 1 : 0;
+  double cL0 = 0.0, nub = 0.0, Tvib = 0.0;
+  if (M.damage) {
+    double G = 3.0 * M.A * (1.0 - 2.0 * M.poisson) / (2.0 * (1.0 + M.poisson));
+    cL0 = std::sqrt((M.A + (4.0 / 3.0) * G) / M.rho0);
+    nub = M.gamma_eta * cL0 * M.af_h;
+    Tvib = M.gamma_T * M.af_h / cL0;
+  }
+  c.Yd0 = (T)(M.damage ? M.Yd0 : 0.0);
+  c.mu_d = (T)(M.damage ? M.mu_d : 0.0);
+  c.Ydm = (T)(M.damage ? M.Ydm : 0.0);
+  c.eps_fb = (T)(M.damage ? M.eps_fb : 0.0);
+  c.B_dmg = (T)(M.damage ? M.B_dmg : 0.0);
+  c.p_bd = (T)(M.damage ? M.p_bd : 0.0);
+  c.c_vib = (T)(M.damage ? M.c_vib : 0.0);
+  c.cL0 = (T)cL0;
+  c.nub = (T)nub;
+  c.Tvib = (T)Tvib;
 }
 
 Geo make_geo(const salec_grid* gr, const salec_material* mats, const salec_pml* pml) {
@@ -372,6 +402,7 @@ Geo make_geo(const salec_grid* gr, const salec_material* mats, const salec_pml* 
     fill_mat(g.m[m], mats[m]);
     fill_mat(g.mf[m], mats[m]);
     if (mats[m].strength) g.any_strength = 1;
+    if (mats[m].damage) g.dmg = 1;
     if (mats[m].rho0 > g.rho_ref) g.rho_ref = mats[m].rho0;
   }
   g.stretched = (gr->dr_col || gr->dz_row) ? 1 : 0;
@@ -449,6 +480,15 @@ int check_members(const salec_instance* inst, int32_t n, std::vector<Member>& ms
     ms[k].has_scene = I.has_scene != 0;
     ms[k].scene = I.scene;
   }
+  // one cycle-kernel family per context: when some member accumulates
+  // damage, every member carries the damage state (zero where no material
+  // of that member is damaging, which the damage arithmetic leaves at zero)
+  int any_dmg = 0;
+  for (const Member& mb : ms) any_dmg |= mb.g.dmg;
+  for (Member& mb : ms) {
+    mb.g.dmg = any_dmg;
+    mb.d.g = mb.g;
+  }
   return SALEC_OK;
 }
 
@@ -461,6 +501,7 @@ struct salec_ctx {
   bool geo = false;  // some member is stretched: the cycle kernel reads geometry tables
   int nm = 2;        // material slots of the cycle kernel: 3 when some member has three materials
   bool pm = false;   // per-material closure (every member shares the closure)
+  bool dm = false;   // damage and acoustic fluidization (some member's material)
   void* buf = nullptr;
   hipStream_t st = nullptr;
   bool own_stream = false;
@@ -572,7 +613,7 @@ int capture(salec_ctx* x, int ncyc, hipGraphExec_t* out) {
   HIPCHK(x, hipStreamBeginCapture(x->st, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
   for (int k = 0; k < ncyc && le == hipSuccess; k++) {
-    le = launch_cycle(x->variant, x->prec, x->geo, x->nm, x->pm, x->L.d_inst, x->L.d_sched, x->nsched, grid, x->st);
+    le = launch_cycle(x->variant, x->prec, x->geo, x->nm, x->pm, x->dm, x->L.d_inst, x->L.d_sched, x->nsched, grid, x->st);
     if (le == hipSuccess) le = launch_finalize(x->L.d_inst, (int)x->ms.size(), x->st);
   }
   hipError_t e = hipStreamEndCapture(x->st, &gr);
@@ -594,8 +635,8 @@ int check_schedule(salec_ctx* x, int v, int grid) {
     x->err = "schedule out of range";
     return SALEC_E_INVALID;
   }
-  if (!variant_available(v, x->prec, x->geo, x->nm, x->pm)) {
-    x->err = "tile shape not built for this material count and closure (its tile does not fit the LDS)";
+  if (!variant_available(v, x->prec, x->geo, x->nm, x->pm, x->dm)) {
+    x->err = "tile shape not built for this material count, closure and damage (its tile does not fit the LDS)";
     return SALEC_E_INVALID;
   }
   return SALEC_OK;
@@ -662,6 +703,7 @@ int init_common(salec_ctx* x, void* dev_buf, size_t dev_bytes, void* stream) {
   x->buf = dev_buf;
   x->prec = x->ms[0].g.prec;
   x->pm = x->ms[0].g.closure == SALEC_CLOSURE_PER_MATERIAL;
+  x->dm = x->ms[0].g.dmg != 0;
   for (const Member& mb : x->ms) {
     if (mb.g.stretched) x->geo = true;
     if (mb.g.nmat > 2) x->nm = 3;
@@ -718,10 +760,10 @@ int init_common(salec_ctx* x, void* dev_buf, size_t dev_bytes, void* stream) {
   int v0 = default_variant(x->prec);
   // fall back along the shapes every family has when the default is not built
   for (int alt : {0, 14, 1, 7, 10})
-    if (!variant_available(v0, x->prec, x->geo, x->nm, x->pm)) v0 = alt;
+    if (!variant_available(v0, x->prec, x->geo, x->nm, x->pm, x->dm)) v0 = alt;
   int rc = use_schedule(x, v0, 0);
   if (rc) return rc;
-  const int g0 = resident_groups(v0, x->prec, x->geo, x->nm, x->pm);
+  const int g0 = resident_groups(v0, x->prec, x->geo, x->nm, x->pm, x->dm);
   if (g0 > 0 && g0 < x->nsched && (rc = use_schedule(x, v0, g0))) return rc;
   x->ready = true;
   return SALEC_OK;
@@ -856,7 +898,7 @@ int salec_time_kernels(salec_ctx* x, int32_t n, double* cycle_ms, double* finali
   const int grid = x->grid > 0 ? std::min(x->grid, x->nsched) : x->nsched;
   hipError_t e = rc ? hipErrorOutOfMemory : hipEventRecord(ev[0], x->st);
   for (int c = 0; c < n && e == hipSuccess; c++) {
-    e = launch_cycle(x->variant, x->prec, x->geo, x->nm, x->pm, x->L.d_inst, x->L.d_sched, x->nsched, grid, x->st);
+    e = launch_cycle(x->variant, x->prec, x->geo, x->nm, x->pm, x->dm, x->L.d_inst, x->L.d_sched, x->nsched, grid, x->st);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * c + 1], x->st);
     if (e == hipSuccess) e = launch_finalize(x->L.d_inst, (int)x->ms.size(), x->st);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * c + 2], x->st);
@@ -953,6 +995,11 @@ int salec_set_fields(salec_ctx* x, int32_t k, const salec_fields* in) {
   }
   if ((rc = copy_in(x, S.v[0], in->v, g.NR + 1, g.NZ + 1, g.pn, es))) return rc;
   if ((rc = copy_in(x, S.v[1], in->v + NN, g.NR + 1, g.NZ + 1, g.pn, es))) return rc;
+  // intact, quiet rock (salec_set_damage sets other damage)
+  if (g.dmg) {
+    HIPCHK(x, hipMemsetAsync(S.dmg, 0, (size_t)g.NZ * g.pc * sizeof(double), x->st));
+    HIPCHK(x, hipMemsetAsync(S.vib, 0, (size_t)g.NZ * g.pc * sizeof(double), x->st));
+  }
   if (g.closure) {
     // every material of a cell at the cell's matter density and energy
     std::vector<double> mu(g.nmat * NC), Im(g.nmat * NC);
@@ -973,6 +1020,80 @@ int salec_set_fields(salec_ctx* x, int32_t k, const salec_fields* in) {
   return start_run(x, k);
 }
 
+}  // extern "C"
+
+namespace {
+// A new run starts from level 0: copies member k's state there when the
+// current cycle left it in level 1 (the EoS cache is recomputed by the run
+// start).
+int state_to_level0(salec_ctx* x, int k) {
+  if (!(read_scal(x, k).cycle & 1)) return SALEC_OK;
+  const Member& mb = x->ms[k];
+  const Geo& g = mb.g;
+  const State &A = mb.d.S[1], &B = mb.d.S[0];
+  const size_t cb = (size_t)g.NZ * g.pc * sizeof(double), ce = (size_t)g.NZ * g.pc * elem_size(x);
+  const size_t nb = (size_t)(g.NZ + 1) * g.pn * elem_size(x);
+  auto cp = [&](void* d, const void* s_, size_t n) {
+    return s_ ? hipMemcpyAsync(d, s_, n, hipMemcpyDeviceToDevice, x->st) : hipSuccess;
+  };
+  HIPCHK(x, cp(B.rho, A.rho, cb));
+  HIPCHK(x, cp(B.I, A.I, cb));
+  for (int m = 0; m < g.nmat; m++) HIPCHK(x, cp(B.f[m], A.f[m], cb));
+  for (int q = 0; q < 3; q++) HIPCHK(x, cp(B.s[q], A.s[q], ce));
+  for (int q = 0; q < 2; q++) HIPCHK(x, cp(B.v[q], A.v[q], nb));
+  for (int m = 0; m < g.nmat; m++) {
+    HIPCHK(x, cp(B.mu[m], A.mu[m], cb));
+    HIPCHK(x, cp(B.Im[m], A.Im[m], cb));
+  }
+  HIPCHK(x, cp(B.dmg, A.dmg, cb));
+  HIPCHK(x, cp(B.vib, A.vib, cb));
+  HIPCHK(x, hipStreamSynchronize(x->st));
+  return SALEC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int salec_set_damage(salec_ctx* x, int32_t k, const double* D, const double* vib) {
+  if (!member_ok(x, k)) return SALEC_E_INVALID;
+  Member& mb = x->ms[k];
+  const Geo& g = mb.g;
+  if (!g.dmg) {
+    x->err = "damage state needs a material with damage";
+    return SALEC_E_INVALID;
+  }
+  const size_t NC = (size_t)g.NR * g.NZ;
+  for (size_t c = 0; c < NC; c++)
+    if ((D && !(D[c] >= 0.0 && D[c] <= 1.0)) || (vib && !(vib[c] >= 0.0 && std::isfinite(vib[c])))) {
+      x->err = "damage must lie in [0, 1] and the vibration speed be finite and >= 0";
+      return SALEC_E_INVALID;
+    }
+  HIPCHK(x, hipStreamSynchronize(x->st));
+  int rc = state_to_level0(x, k);
+  if (rc) return rc;
+  const State& S = mb.d.S[0];
+  if (D && (rc = copy_in(x, S.dmg, D, g.NR, g.NZ, g.pc, sizeof(double)))) return rc;
+  if (vib && (rc = copy_in(x, S.vib, vib, g.NR, g.NZ, g.pc, sizeof(double)))) return rc;
+  return start_run(x, k);
+}
+
+int salec_get_damage(salec_ctx* x, int32_t k, double* D, double* vib) {
+  if (!member_ok(x, k)) return SALEC_E_INVALID;
+  Member& mb = x->ms[k];
+  const Geo& g = mb.g;
+  if (!g.dmg) {
+    x->err = "damage state needs a material with damage";
+    return SALEC_E_INVALID;
+  }
+  HIPCHK(x, hipStreamSynchronize(x->st));
+  const State& S = mb.d.S[read_scal(x, k).cycle & 1];
+  int rc;
+  if (D && (rc = copy_out(x, D, S.dmg, g.NR, g.NZ, g.pc, sizeof(double)))) return rc;
+  if (vib && (rc = copy_out(x, vib, S.vib, g.NR, g.NZ, g.pc, sizeof(double)))) return rc;
+  HIPCHK(x, hipStreamSynchronize(x->st));
+  return SALEC_OK;
+}
+
 int salec_set_materials(salec_ctx* x, int32_t k, const double* mu, const double* Im) {
   if (!member_ok(x, k) || !mu || !Im) return SALEC_E_INVALID;
   Member& mb = x->ms[k];
@@ -982,20 +1103,8 @@ int salec_set_materials(salec_ctx* x, int32_t k, const double* mu, const double*
     return SALEC_E_INVALID;
   }
   HIPCHK(x, hipStreamSynchronize(x->st));
-  // a new run starts from level 0: move the current state there first
-  if (read_scal(x, k).cycle & 1) {
-    const State &A = mb.d.S[1], &B = mb.d.S[0];
-    const size_t cb = (size_t)g.NZ * g.pc * sizeof(double), ce = (size_t)g.NZ * g.pc * elem_size(x);
-    const size_t nb = (size_t)(g.NZ + 1) * g.pn * elem_size(x);
-    auto cp = [&](void* d, const void* s_, size_t n) {
-      return s_ ? hipMemcpyAsync(d, s_, n, hipMemcpyDeviceToDevice, x->st) : hipSuccess;
-    };
-    HIPCHK(x, cp(B.rho, A.rho, cb));
-    HIPCHK(x, cp(B.I, A.I, cb));
-    for (int m = 0; m < g.nmat; m++) HIPCHK(x, cp(B.f[m], A.f[m], cb));
-    for (int q = 0; q < 3; q++) HIPCHK(x, cp(B.s[q], A.s[q], ce));
-    for (int q = 0; q < 2; q++) HIPCHK(x, cp(B.v[q], A.v[q], nb));
-  }
+  int rc0 = state_to_level0(x, k);
+  if (rc0) return rc0;
   const State& S = mb.d.S[0];
   size_t NC = (size_t)g.NR * g.NZ;
   std::vector<double> rho(NC, 0.0), I(NC, 0.0);
@@ -1294,10 +1403,10 @@ int salec_tune(salec_ctx* x, int32_t cycles, salec_schedule* out) {
   int best_v = x->variant, best_g = x->grid;
   double best = 1e300;
   for (int v = 0; v < n_variants(); v++) {
-    if (!variant_available(v, x->prec, x->geo, x->nm, x->pm)) continue;
+    if (!variant_available(v, x->prec, x->geo, x->nm, x->pm, x->dm)) continue;
     // one workgroup per tile, and as many workgroups as fit at once walking
     // the tiles (when that is fewer than the tiles)
-    int grids[2] = {0, resident_groups(v, x->prec, x->geo, x->nm, x->pm)};
+    int grids[2] = {0, resident_groups(v, x->prec, x->geo, x->nm, x->pm, x->dm)};
     for (int gi = 0; gi < 2; gi++) {
       if (gi == 1 && (grids[1] <= 0 || grids[1] >= x->nsched)) continue;
       int rc = use_schedule(x, v, grids[gi]);

@@ -19,17 +19,21 @@ void variant_shape(int v, int* tw, int* th, int* nt);
 int default_variant(int prec);
 // (geo: the family that reads the geometry from the instances' tables, for
 // stretched grids; nm: material slots, 2 or 3; pm: per-material closure;
-// null where the shape is not built for that family)
+// dm: damage and acoustic fluidization; null where the shape is not built
+// for that family)
 CycleFn cycle_kernel_f64(int v, bool geo, int nm, bool pm);
 CycleFn cycle_kernel_f32(int v, bool geo, int nm, bool pm);
-hipError_t launch_cycle(int v, int prec, bool geo, int nm, bool pm, const Inst* insts, const TileRef* sched,
-                        int nsched, int grid, hipStream_t st);
+CycleFn cycle_kernel_dm_f64(int v, bool geo, int nm, bool pm);
+CycleFn cycle_kernel_dm_f32(int v, bool geo, int nm, bool pm);
+hipError_t launch_cycle(int v, int prec, bool geo, int nm, bool pm, bool dm, const Inst* insts,
+                        const TileRef* sched, int nsched, int grid, hipStream_t st);
 // end of a cycle: per-instance Courant minimum, clock, errors
 hipError_t launch_finalize(const Inst* insts, int n_inst, hipStream_t st);
 // workgroups of shape v that fit on the device at once (0 if unknown)
-int resident_groups(int v, int prec, bool geo, int nm, bool pm);
-// whether shape v exists for this precision, family, material count and closure
-bool variant_available(int v, int prec, bool geo, int nm, bool pm);
+int resident_groups(int v, int prec, bool geo, int nm, bool pm, bool dm);
+// whether shape v exists for this precision, family, material count, closure
+// and damage
+bool variant_available(int v, int prec, bool geo, int nm, bool pm, bool dm);
 
 // EoS cache and Courant candidates of the current state (start of a run)
 hipError_t launch_prime_f64(const Inst& in, hipStream_t st);

@@ -34,8 +34,9 @@ class Grid(C.Structure):
 class Material(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("rho0", "A", "B", "E0", "a", "b", "alpha", "beta", "Eiv", "Ecv",
                                           "p_min", "c_floor_frac")] + \
-               [("strength", C.c_int32), ("reserved", C.c_int32)] + \
-               [(n, C.c_double) for n in ("Y0", "mu_f", "Ylim", "poisson")]
+               [("strength", C.c_int32), ("damage", C.c_int32)] + \
+               [(n, C.c_double) for n in ("Y0", "mu_f", "Ylim", "poisson", "Yd0", "mu_d", "Ydm", "eps_fb",
+                                          "B_dmg", "p_bd", "gamma_eta", "gamma_T", "c_vib", "af_h")]
 
 
 class PmlC(C.Structure):
@@ -118,6 +119,8 @@ def load() -> C.CDLL:
     lib.salec_get_p0.argtypes = [P, I32, _DP]
     lib.salec_set_materials.argtypes = [P, I32, _DP, _DP]
     lib.salec_get_materials.argtypes = [P, I32, _DP, _DP]
+    lib.salec_set_damage.argtypes = [P, I32, _DP, _DP]
+    lib.salec_get_damage.argtypes = [P, I32, _DP, _DP]
     lib.salec_num_variants.restype = I32
     lib.salec_num_variants.argtypes = []
     lib.salec_get_schedule.argtypes = [P, C.POINTER(Schedule)]
@@ -151,7 +154,8 @@ def _grid(g, precision, keep: list) -> Grid:
 
 def _mat(m) -> Material:
     return Material(m.rho0, m.A, m.B, m.E0, m.a, m.b, m.alpha, m.beta, m.Eiv, m.Ecv, m.p_min,
-                    m.c_floor_frac, int(m.strength), 0, m.Y0, m.mu_f, m.Ylim, m.poisson)
+                    m.c_floor_frac, int(m.strength), int(m.damage), m.Y0, m.mu_f, m.Ylim, m.poisson,
+                    m.Yd0, m.mu_d, m.Ydm, m.eps_fb, m.B_dmg, m.p_bd, m.gamma_eta, m.gamma_T, m.c_vib, m.af_h)
 
 
 def _mats(problem):
@@ -331,6 +335,25 @@ class Salec:
         self._check(self.lib.salec_get_materials(self._h, int(k), _ptr(mu), _ptr(Im)))
         return {"mu": mu.reshape(nmat, NZ, NR), "Im": Im.reshape(nmat, NZ, NR)}
 
+    def set_damage(self, D=None, vib=None, k: int = 0):
+        """Damage and block-model vibration speed of member k, each (NZ, NR);
+        None keeps that field. Starts a new run from the current state."""
+        NR, NZ, _ = self.dims[k]
+        Dp = None if D is None else np.ascontiguousarray(D, dtype=np.float64).reshape(NZ * NR)
+        Vp = None if vib is None else np.ascontiguousarray(vib, dtype=np.float64).reshape(NZ * NR)
+        self._check(self.lib.salec_set_damage(self._h, int(k), _ptr(Dp), _ptr(Vp)))
+
+    def damage(self, k: int = 0) -> dict:
+        """{"D": damage, "vib": vibration speed}, (NZ, NR) each."""
+        NR, NZ, _ = self.dims[k]
+        D, V = np.empty(NZ * NR), np.empty(NZ * NR)
+        self._check(self.lib.salec_get_damage(self._h, int(k), _ptr(D), _ptr(V)))
+        return {"D": D.reshape(NZ, NR), "vib": V.reshape(NZ, NR)}
+
+    @property
+    def has_damage(self) -> bool:
+        return any(int(m.damage) for pb in self.problems for m in pb.mats[:pb.grid.nmat])
+
     def pml_aux(self, k: int = 0) -> dict:
         NR, NZ, _ = self.dims[k]
         NC, NN = NR * NZ, (NR + 1) * (NZ + 1)
@@ -369,6 +392,9 @@ class Salec:
         if self.problems[k].grid.closure:
             M = src.materials(k=k_src)
             self.set_materials(M["mu"], M["Im"], k=k)
+        if self.has_damage:
+            Dm = src.damage(k=k_src)
+            self.set_damage(Dm["D"], Dm["vib"], k=k)
         self.set_pml(src.pml_aux(k=k_src), k=k)
         d = src.diag(k=k_src)
         self.set_clock(d["t"], d["dt"], k=k)

@@ -137,3 +137,34 @@ def test_stretched_plan_matches_uniform_plan_size():
     g = pb.grid
     uni = pb.replace(grid=inputs.Grid(**{**g.__dict__, "dr_col": None, "dz_row": None}))
     assert salec.plan_bytes(pb) == salec.plan_bytes(uni) > 0
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """sizeof and every field offset of the ABI structs, as a C compiler lays
+    them out from include/salec.h, equal the Python binding's ctypes
+    structures (a mismatch would pass garbage silently)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"salec_grid": salec.Grid, "salec_material": salec.Material, "salec_pml": salec.PmlC,
+               "salec_scene": salec.SceneC, "salec_fields": salec.Fields, "salec_diag_t": salec.Diag,
+               "salec_instance": salec.Instance, "salec_schedule": salec.Schedule}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "salec.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    inc = os.path.join(os.path.dirname(salec.HEADER))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(ln.split()[:2]): int(ln.split()[2]) for ln in out if ln.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

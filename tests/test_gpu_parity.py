@@ -54,6 +54,10 @@ def compare(gpu, orc, label, tol=TOL, pml=True):
         Ao["rho_ref"] = np.where(lay, Ao["rho_ref"], 0.0)
         for k in Ao:
             errs["pml." + k] = rel_linf(Ag[k], Ao[k])
+    if getattr(gpu, "has_damage", False):
+        Dg, Do = gpu.damage(), orc.damage()
+        errs["D"] = rel_linf(Dg["D"], Do["D"])
+        errs["vib"] = rel_linf(Dg["vib"], Do["vib"])
     dg, do = gpu.diag(), orc.diag()
     assert int(dg["cycle"]) == int(do["cycle"]), label
     assert dg["err"] == do["err"], label
