@@ -37,7 +37,11 @@ Also measured (the "extensions" object; skipped with --headline-only):
   pml_payoff_table2  the same comparison on Table 2's grid with Sec. 4's three
                  layers and gravity, to 30 s, against ~200 km longer extension
                  zones; Sec. 3's layers and the stress-damping extension
-Each but the last is init + tune + warm-up, then a short timed run.
+  paper_layers_damage_fp64  paper_layers_fp64 with Table 1's damage and
+                 block-model constants (the damage kernels), FP64
+  damage_table2  the PML run of that setting against the reference to 60 s:
+                 crater and crust-base profile differences, crust-base uplift
+Each but the last three is init + tune + warm-up, then a short timed run.
 
 Prints one JSON line. `roofline` is the cycle kernel's algorithmic HBM
 bytes per launch (state read and written once, PML auxiliaries) over the
@@ -80,11 +84,13 @@ def algorithmic_bytes_per_cell(pb) -> float:
     direction, read + written; corner cells count twice; the reference
     density read and the sink read + written) averaged over all cells.
     Mixed precision: stress and velocity are 4-byte values. The per-material
-    closure adds each material's partial density and specific energy."""
+    closure adds each material's partial density and specific energy; damage
+    adds D and the vibration speed (FP64)."""
     g = pb.grid
     nmat = g.nmat
     strength = any(m.strength for m in pb.mats[:nmat])
-    wide = 8 * (2 + nmat + (2 * nmat if g.closure else 0))
+    damage = any(int(getattr(m, "damage", 0)) for m in pb.mats[:nmat])
+    wide = 8 * (2 + nmat + (2 * nmat if g.closure else 0) + (2 if damage else 0))
     narrow = (8 if pb.precision == "fp64" else 4) * ((3 if strength else 0) + 2)
     state = 2 * (wide + narrow)
     NR, NZ = g.NR, g.NZ
@@ -349,6 +355,32 @@ def pml_payoff_table2():
     return r
 
 
+def paper_layers_damage():
+    """Sec. 4's three-layer setting on Table 2's grid with Table 1's damage
+    and block-model constants on every layer (block size the projectile
+    radius)."""
+    pb = inputs.config_paper_layers()
+    h = pb.scene.radius
+    keys = ("calcite", "granite", "dunite")
+    return pb.replace(mats=[inputs.with_damage(m, **inputs.TABLE1_DAMAGE[k], af_h=h) for m, k in zip(pb.mats, keys)],
+                      name="paper-layers-damage")
+
+
+def damage_table2():
+    """The PML run of Sec. 4's three-layer setting with damage and the block
+    model against the reference with ~200 km longer extension zones, at 60 s:
+    crater surface and crust base profile differences, crust-base uplift and
+    crater depth of both, the time and cycles each run reached."""
+    from paper_2403_04267_amd.pml_study import paper_profiles
+    t0 = time.perf_counter()
+    r = paper_profiles(times=(60.0,), damage=1)
+    r["wall_s"] = time.perf_counter() - t0
+    p = r["60s"]["pml"]
+    print(f"[bench] damage, Table 2, 60 s: crater median {p['crater']['median_m']:.0f} m, crust base max "
+          f"{p['moho']['max_m']:.0f} m", file=sys.stderr, flush=True)
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -456,8 +488,11 @@ def main():
         ext["three_layer_pm_fp64"] = extension("three-layer 1050^2 per-material fp64",
                                                three.replace(grid=dataclasses.replace(three.grid, closure=1)),
                                                500, 20, args.tune, value)
+        ext["paper_layers_damage_fp64"] = extension("Table 2 grid three layers, damage fp64",
+                                                    paper_layers_damage(), 300, 20, args.tune, value)
         ext["pml_payoff"] = pml_payoff()
         ext["pml_payoff_table2"] = pml_payoff_table2()
+        ext["damage_table2"] = damage_table2()
         out["extensions"] = ext
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pb)

@@ -339,8 +339,10 @@ def config_paper(precision: str = "fp64") -> Problem:
     materials: 512 x 532 cells (462 x 462 of 400 m, extension zones right, top
     and bottom growing 1.05 per cell to 1061 m, 30-cell PML right and below),
     a mantle-rock sphere of 7.2 km radius (18 cells) at 12 km/s onto a 33 km
-    basalt crust over mantle rock, lithostatic under 9.81 m/s^2."""
+    basalt crust over mantle rock, lithostatic under 9.81 m/s^2; Courant
+    factor 0.2, the value Sec. 7 gives for this example."""
     g = paper_layout()
+    g.cfl = 0.2
     R = 18
     sj = g.pml_b + 20 + surface_row(462, 0, R)
     sc = Scene(surface_j=sj, radius=R * 400.0, v_imp=12e3, gravity=9.81, layer_j=sj - 82)
@@ -353,8 +355,9 @@ def config_paper_layers(precision: str = "fp64") -> Problem:
     512 x 532 cells as in the two-material setting, a dunite sphere of 7.2 km
     radius (18 cells) at 12 km/s onto 2.8 km of calcite (7 rows) over 30 km of
     granite (75 rows) over dunite, with Table 1's intact strength,
-    lithostatic under 9.81 m/s^2."""
+    lithostatic under 9.81 m/s^2; Courant factor 0.2 as Sec. 7 gives."""
     g = paper_layout(nmat=3)
+    g.cfl = 0.2
     R = 18
     sj = g.pml_b + 20 + surface_row(462, 0, R)
     sc = Scene(surface_j=sj, radius=R * 400.0, v_imp=12e3, gravity=9.81, layer_j=sj - 7,

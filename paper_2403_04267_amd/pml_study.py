@@ -168,6 +168,8 @@ class PaperSetup:
     far_km: float = 60.0    # the far field: target cells further than this from the impact point
     strength: bool = True   # Table 1's strength (False: hydrodynamic layers)
     damp_stress: int = 0    # 1: the layers also relax the deviatoric stress (an extension)
+    damage: int = 0         # 1: Table 1's damage and block-model constants on every layer
+    af_h: float = 0.0       # block size of the block model, m (0: the projectile radius)
 
 
 def paper_problems(s: PaperSetup):
@@ -183,9 +185,17 @@ def paper_problems(s: PaperSetup):
         mats = ([inputs.calcite(False), inputs.granite(False), inputs.dunite(False)] if s.layers == 3
                 else [inputs.basalt(False), inputs.mantle_like(False)])
         base = base.replace(mats=mats)
+    if s.damage:
+        if not s.strength:
+            raise ValueError("damage needs Table 1's strength")
+        h = s.af_h if s.af_h > 0 else base.scene.radius
+        keys = ("calcite", "granite", "dunite") if s.layers == 3 else ("granite", "dunite")
+        base = base.replace(mats=[inputs.with_damage(m, **inputs.TABLE1_DAMAGE[k], af_h=h)
+                                  for m, k in zip(base.mats, keys)])
     base = base.replace(pml=inputs.Pml(damp_stress=s.damp_stress))
     bare = base.replace(pml=inputs.Pml(enabled=0))
     gref = inputs.paper_layout(462, 462, (0, s.ext_ref, 20, s.ext_ref), (0, 0), nmat=base.grid.nmat)
+    gref.cfl = base.grid.cfl
     gref.t_stop = s.t_end
     gref.closure = s.closure
     sj = s.ext_ref + (base.scene.surface_j - base.grid.pml_b - 20)
@@ -205,7 +215,7 @@ def _geometry(g):
 
 
 def paper_run(s: PaperSetup = PaperSetup(), device: str = "cuda:0", chunk: int = 500,
-              max_cycles: int = 100000) -> dict:
+              max_cycles: int = 1000000) -> dict:
     """Runs the three problems to s.t_end and compares the target part of the
     window (below the original surface; the ejecta above it are chaotic in
     every run): energy of the difference field against the reference
@@ -273,7 +283,8 @@ def paper_run(s: PaperSetup = PaperSetup(), device: str = "cuda:0", chunk: int =
                                                     np.where(far, pr * ref["dp"][:ns], 0.0))}
     res["setup"] = {"t_end": s.t_end, "ext_ref": s.ext_ref, "precision": s.precision, "layers": s.layers,
                     "closure": s.closure, "window_cells": [wr, wc], "far_km": s.far_km,
-                    "strength": s.strength, "damp_stress": s.damp_stress}
+                    "strength": s.strength, "damp_stress": s.damp_stress, "damage": s.damage,
+                    "af_h": s.af_h}
     return res
 
 
@@ -326,7 +337,7 @@ def _level_from_bottom(x, zc, level=0.5):
 def paper_profiles(times=(10.0, 30.0, 60.0), r_crater_km: float = 60.0, r_inner_km: float = 35.0,
                    r_moho_km: float = 100.0,
                    device: str = "cuda:0", bare_until: float = 30.0, chunk: int = 500,
-                   max_cycles: int = 200000, **setup) -> dict:
+                   max_cycles: int = 1000000, **setup) -> dict:
     """The crater surface (matter fraction 0.5 from below) and the base of
     the granite crust (granite fraction 0.5 from below: the crust-mantle
     boundary, unaffected by the dunite projectile in the crater floor) of the
@@ -342,7 +353,7 @@ def paper_profiles(times=(10.0, 30.0, 60.0), r_crater_km: float = 60.0, r_inner_
         s = PaperSetup(t_end=float(t), **setup)
         probs, rows, wc, wr = paper_problems(s)
         keys = ("pml", "ref", "bare") if t <= bare_until else ("pml", "ref")
-        prof = {}
+        prof, reached = {}, {}
         for key in keys:
             pb = probs[key]
             ctx = Salec(pb, device)
@@ -350,6 +361,8 @@ def paper_profiles(times=(10.0, 30.0, 60.0), r_crater_km: float = 60.0, r_inner_
             while ctx.diag()["t"] < s.t_end * (1.0 - 1e-12) and cycles < max_cycles:
                 ctx.step(chunk)
                 cycles += chunk
+            d = ctx.diag()
+            reached[key] = {"t": d["t"], "cycles": int(d["cycle"])}
             F = ctx.fields(eos=False)
             del ctx
             g = pb.grid
@@ -376,9 +389,13 @@ def paper_profiles(times=(10.0, 30.0, 60.0), r_crater_km: float = 60.0, r_inner_
                 if a is None:
                     continue
                 sel = (rc <= rmax * 1e3) & np.isfinite(a) & np.isfinite(b)
+                if not sel.any():  # no column where both runs have the level
+                    d[name] = None
+                    continue
                 diff = np.abs(a[sel] - b[sel])
                 d[name] = {"max_m": float(diff.max()), "mean_m": float(diff.mean()),
-                           "median_m": float(np.median(diff)), "r_at_max_km": float(rc[sel][np.argmax(diff)] / 1e3)}
+                           "median_m": float(np.median(diff)), "r_at_max_km": float(rc[sel][np.argmax(diff)] / 1e3),
+                           "columns": int(sel.sum())}
             res[key] = d
         ref = prof["ref"]
         sel = rc <= r_crater_km * 1e3
@@ -386,5 +403,11 @@ def paper_profiles(times=(10.0, 30.0, 60.0), r_crater_km: float = 60.0, r_inner_
         if ref["moho"] is not None:
             m = ref["moho"][rc <= r_moho_km * 1e3]
             res["ref_moho_uplift_m"] = float(np.nanmax(m) - np.nanmedian(m[-20:]))
+        pm = prof["pml"]
+        res["pml_crater_depth_m"] = float(-np.nanmin(pm["crater"][sel]))
+        if pm["moho"] is not None:
+            m = pm["moho"][rc <= r_moho_km * 1e3]
+            res["pml_moho_uplift_m"] = float(np.nanmax(m) - np.nanmedian(m[-20:]))
+        res["reached"] = reached
         out[f"{t:g}s"] = res
     return out
