@@ -102,11 +102,11 @@ def algorithmic_bytes_per_cell(pb) -> float:
     return state + aux / ncell if pb.pml.enabled else state
 
 
-def traffic_per_launch(schedule):
+def traffic_per_launch(schedule, workload="scale"):
     """Measured HBM bytes per cycle-kernel launch (FETCH_SIZE + WRITE_SIZE,
     each scaled by the reading for a plain copy of known size), if the
-    recorded counters were taken from the current kernel sources and the
-    schedule being timed."""
+    recorded counters were taken from the current kernel sources, the
+    workload and the schedule being timed."""
     try:
         with open(TRAFFIC_FILE) as fh:
             recs = json.load(fh).get("records", [])
@@ -115,6 +115,8 @@ def traffic_per_launch(schedule):
     sha = kernel_sources_sha()
     for rec in recs:
         want = rec.get("schedule", {})
+        if rec.get("workload", "scale") != workload:
+            continue
         if rec.get("kernel_sources_sha256") == sha and all(schedule.get(k) == v for k, v in want.items()):
             return rec.get("hbm_bytes_per_launch")
     return None
@@ -126,7 +128,7 @@ def traffic_per_launch(schedule):
 VALU_LANE_OPS_PEAK = 256 * 4 * 2.4e9 / 4 * 64
 
 
-def valu_per_launch(schedule):
+def valu_per_launch(schedule, workload="scale"):
     """VALU instructions per cycle-kernel launch (SQ_INSTS_VALU, wave64
     instructions, recorded with the traffic records, one record or a list),
     if taken from the current kernel sources and the schedule being timed."""
@@ -139,7 +141,7 @@ def valu_per_launch(schedule):
         recs = [recs]
     sha = kernel_sources_sha()
     for rec in recs or []:
-        if rec.get("kernel_sources_sha256") != sha:
+        if rec.get("kernel_sources_sha256") != sha or rec.get("workload", "scale") != workload:
             continue
         if all(schedule.get(k) == v for k, v in rec.get("schedule", {}).items()):
             return rec.get("sq_insts_valu_per_dispatch")
@@ -359,6 +361,7 @@ def paper_layers_damage():
     """Sec. 4's three-layer setting on Table 2's grid with Table 1's damage
     and block-model constants on every layer (block size the projectile
     radius)."""
+    from paper_2403_04267_amd import inputs
     pb = inputs.config_paper_layers()
     h = pb.scene.radius
     keys = ("calcite", "granite", "dunite")
@@ -381,6 +384,27 @@ def damage_table2():
     return r
 
 
+WORKLOADS = ("scale", "large", "ens256", "ens1024", "paper_layers_damage", "three_layer", "three_layer_pm")
+
+
+def workload(name):
+    """The headline workload (scale) or one of the workloads the extensions
+    time, by name (for profiling runs)."""
+    from paper_2403_04267_amd import inputs
+    return {"scale": inputs.config_scale, "large": lambda: inputs.config_large("mixed"),
+            "ens256": lambda: inputs.ensemble(2403, 256, 200, 800),
+            "ens1024": lambda: inputs.ensemble(4267, 1024, 200, 1200, precision="mixed"),
+            "paper_layers_damage": paper_layers_damage,
+            "three_layer": lambda: inputs.three_layer_impact(1000, 50, 50, 15e3, 7, 75, name="three"),
+            "three_layer_pm": lambda: three_layer_pm(inputs)}[name]()
+
+
+def three_layer_pm(inputs):
+    """The three-layer 1050^2 target under the per-material closure."""
+    three = inputs.three_layer_impact(1000, 50, 50, 15e3, 7, 75, name="three-pm")
+    return three.replace(grid=dataclasses.replace(three.grid, closure=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -396,10 +420,14 @@ def main():
     ap.add_argument("--grid", type=int, default=0, help="workgroups per launch with --variant (0: one per tile)")
     ap.add_argument("--kernel-cycles", type=int, default=200,
                     help="cycles after the timed ones over which the cycle kernel's own duration is measured")
+    ap.add_argument("--workload", default="scale", choices=sorted(WORKLOADS),
+                    help="profiling only: time another workload in place of the headline's")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes (3 launches) and exit; "
                          "profiling it gives the HBM counter scale factors")
     args = ap.parse_args()
+    if args.workload != "scale":  # a profiling run: the workload alone
+        args.headline_only, args.no_cpu = True, True
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -415,9 +443,12 @@ def main():
         return
     from paper_2403_04267_amd import inputs
 
-    pb = inputs.config_scale()
+    pb = workload(args.workload)
     if args.mixed:
-        pb = pb.replace(precision="mixed")
+        pb = [p.replace(precision="mixed") for p in pb] if isinstance(pb, list) else pb.replace(precision="mixed")
+    probs = pb if isinstance(pb, list) else [pb]
+    ncells = sum(p.grid.ncells for p in probs)
+    precision = probs[0].precision
     t_wall = time.perf_counter()
     value, ms_cycle, sch, ctx, rates = run(pb, args.steps, args.warmup, args.tune, args.variant, args.grid, parts=5)
     wall = time.perf_counter() - t_wall
@@ -425,11 +456,11 @@ def main():
     # the cycle kernel's own mean duration, right after the timed cycles, same
     # context and schedule (launched between HIP events instead of in graphs)
     k_ms, f_ms = ctx.time_kernels(args.kernel_cycles)
-    bpc = algorithmic_bytes_per_cell(pb)
-    achieved = bpc * pb.grid.ncells / (k_ms / 1e3) / 1e9
-    traffic_b = traffic_per_launch(sch)
+    bpc = sum(algorithmic_bytes_per_cell(p) * p.grid.ncells for p in probs) / ncells
+    achieved = bpc * ncells / (k_ms / 1e3) / 1e9
+    traffic_b = traffic_per_launch(sch, args.workload)
     traffic = traffic_b / (k_ms / 1e3) / 1e9 if traffic_b else None
-    valu = valu_per_launch(sch)
+    valu = valu_per_launch(sch, args.workload)
     d = ctx.diag()
     del ctx
     torch.cuda.empty_cache()
@@ -438,9 +469,10 @@ def main():
         "metric": "cell-updates/s", "value": value, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_cycle,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64" if args.mixed else "f64", "data": "synthetic",
-        "config": {"workload": f"impact-1050x1050-2mat-strength-pml50-{pb.precision}", "cells": pb.grid.ncells,
-                   "cycles": args.steps, "precision": pb.precision},
+        "dtype": "f32+f64" if precision == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": (f"impact-1050x1050-2mat-strength-pml50-{precision}" if args.workload == "scale"
+                                else f"{args.workload}-{precision} (profiling run, not the headline)"),
+                   "cells": ncells, "instances": len(probs), "cycles": args.steps, "precision": precision},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_bytes_per_launch": traffic_b,
@@ -452,7 +484,7 @@ def main():
                      # what bounds this kernel in practice: VALU issue (counted
                      # instructions, halo recomputation included) and latency
                      "valu_issue": None if not valu else {
-                         "lane_ops_per_cell_update": valu * 64 / pb.grid.ncells,
+                         "lane_ops_per_cell_update": valu * 64 / ncells,
                          "achieved_lane_ops_per_s": valu * 64 / (k_ms / 1e3),
                          "peak_lane_ops_per_s": VALU_LANE_OPS_PEAK,
                          "frac": valu * 64 / (k_ms / 1e3) / VALU_LANE_OPS_PEAK}},
@@ -484,9 +516,7 @@ def main():
                                             500, 20, args.tune, value)
         ext["paper_layers_fp64"] = extension("Table 2 grid 512x532 three layers fp64",
                                              inputs.config_paper_layers(), 300, 20, args.tune, value)
-        three = inputs.three_layer_impact(1000, 50, 50, 15e3, 7, 75, name="three-pm")
-        ext["three_layer_pm_fp64"] = extension("three-layer 1050^2 per-material fp64",
-                                               three.replace(grid=dataclasses.replace(three.grid, closure=1)),
+        ext["three_layer_pm_fp64"] = extension("three-layer 1050^2 per-material fp64", three_layer_pm(inputs),
                                                500, 20, args.tune, value)
         ext["paper_layers_damage_fp64"] = extension("Table 2 grid three layers, damage fp64",
                                                     paper_layers_damage(), 300, 20, args.tune, value)
@@ -495,7 +525,7 @@ def main():
         ext["damage_table2"] = damage_table2()
         out["extensions"] = ext
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(pb)
+        out["cpu_baseline"] = cpu_baseline(probs[0])
     print(json.dumps(out), flush=True)
 
 

@@ -34,7 +34,7 @@ static const int kShapes[][3] = {
     {32, 34, 768},
     {27, 27, 768}};
 
-int default_variant(int prec) { return prec == 0 ? 12 : 1; }
+int default_variant(int) { return 12; }
 
 int n_variants() { return (int)(sizeof(kShapes) / sizeof(kShapes[0])); }
 

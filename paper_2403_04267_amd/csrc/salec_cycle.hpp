@@ -68,6 +68,38 @@ struct Smem {
 // exactly.
 __device__ __forceinline__ double face_sum(const double t[4]) { return (t[0] + t[1]) + (t[2] + t[3]); }
 
+// The same sum fed one term at a time in the order W, E, S, N (q = 0..3, a
+// compile-time index in unrolled loops), so that only the pending pair is
+// live: (t0 + t1) + (t2 + t3) bit for bit.
+struct FaceAcc {
+  double h = 0.0, r = 0.0;
+  __device__ __forceinline__ void put(int q, double t) {
+    if (q == 0 || q == 2)
+      h = t;
+    else if (q == 1)
+      r = h + t;
+    else
+      h = h + t;
+  }
+  __device__ __forceinline__ double sum() const { return r + h; }
+};
+
+// Quotients of the FP64 sums by one shared denominator b. The FP64 kernel
+// forms each quotient a / b as the discrete algorithm does; the mixed kernel,
+// whose results are not meant to repeat the FP64 algorithm bit for bit,
+// multiplies by the reciprocal formed once.
+template <class T> struct Over;
+template <> struct Over<double> {
+  double b;
+  __device__ __forceinline__ explicit Over(double b_) : b(b_) {}
+  __device__ __forceinline__ double operator()(double a) const { return a / b; }
+};
+template <> struct Over<float> {
+  double r;
+  __device__ __forceinline__ explicit Over(double b_) : r(1.0 / b_) {}
+  __device__ __forceinline__ double operator()(double a) const { return a * r; }
+};
+
 __device__ __forceinline__ bool in_cells(const Geo& g, int i, int j) {
   return i >= 0 && i < g.NR && j >= 0 && j < g.NZ;
 }
@@ -559,7 +591,9 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       }
       double IL = 0.0;
       if constexpr (!PM) {
-        IL = ((S.I[c] + (double)N::div(Wdt, rden)) + (double)hL) - dt * (psi2 / rt);
+        IL = (S.I[c] + (double)N::div(Wdt, rden)) + (double)hL;
+        // outside the strips psi2 is +0 and so is its term: x - (+0) = x
+        if (kb >= 0 || kr >= 0) IL = IL - dt * (psi2 / rt);
       } else {
         // each material: deviatoric work and its own p dV work on the cell's
         // volume change, per unit of its own mass (density mu_m / f_m; below
@@ -580,12 +614,14 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
           const T Pm = ((const T*)S.pmat[m])[c] + Q;
           const T Wm = dtT * sde - Pm * jm1;
           const T rdm = tmax((T)rmm, GT::rho_ref(g) * T(kRhoDenFloor));
-          oILm[m] = ((S.Im[m][c] + (double)N::div(Wm, rdm)) + (double)hL) - dt * (psi2 / rt);
+          oILm[m] = (S.Im[m][c] + (double)N::div(Wm, rdm)) + (double)hL;
+          if (kb >= 0 || kr >= 0) oILm[m] = oILm[m] - dt * (psi2 / rt);
           const double kap = rho > 0.0 ? rhoE / rho : 0.0;
           oMuL[m] = (rhoE == rho ? mud : mud * kap) / iJ;
         }
       }
-      double fr = (double)N::div(Jm, J);
+      // Jm / J, which is exactly 1 where the material follows the cell (Jm = J)
+      double fr = (Jm == J && J > T(0)) ? 1.0 : (double)N::div(Jm, J);
       double fLv[NM];
 #pragma unroll
       for (int m = 0; m < NM; m++) fLv[m] = (m == 0 || m < g.nmat) ? fn[m] * fr : 0.0;
@@ -690,19 +726,10 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
 
   // ------------------------------------------------------------------ E2
   // (the new density, energy and volume fractions of owned cells reach G,
-  // which uses the same cell-to-thread map, in registers; 1024-thread
-  // workgroups have no registers to spare and G reads them back instead)
+  // which uses the same cell-to-thread map, through memory: this workgroup
+  // wrote them, and holding them in registers across F costs spills)
   unsigned flags = 0;
   constexpr int UE = (R::NE + NT - 1) / NT;
-  // (the per-material closure writes its state in E2 and G reads it back)
-  constexpr bool kCarry = WPE < 4 && !PM;
-  double eRho[UE], eI[UE], eF[NM][UE];
-#pragma unroll
-  for (int u = 0; u < UE; u++) {
-    eRho[u] = eI[u] = 0.0;
-#pragma unroll
-    for (int m = 0; m < NM; m++) eF[m][u] = 0.0;
-  }
 #pragma unroll 1
   for (int u = 0; u < UE; u++) {
     int k = tid + u * NT;
@@ -719,7 +746,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       const bool inq[4] = {dV[0] > T(0), dV[1] < T(0), dV[2] > T(0), dV[3] < T(0)};
       int kc = kC(i, j);
       double netin = (F[0] - F[1]) + (F[2] - F[3]);
-      rho1 = s_rho[kA(i, j)] + netin / V;
+      const Over<T> byV(V);
+      rho1 = s_rho[kA(i, j)] + byV(netin);
       double M1 = rho1 * V;
       double fL[NM];
 #pragma unroll
@@ -747,7 +775,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
             const double rn = S.rho[cidx(g, i, j)], rE = s_rho[kA(i, j)];
             if (rE != rn) mu0 = mu0 * (rn > 0.0 ? rE / rn : 0.0);
           }
-          mu1[m] = mu0 + nin / V;
+          mu1[m] = mu0 + byV(nin);
           rho1 += mu1[m];
         }
         M1 = rho1 * V;
@@ -756,58 +784,70 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       double sL0 = (double)ct[1 * R::NC + kc], sL1 = (double)ct[2 * R::NC + kc], sL2 = (double)ct[3 * R::NC + kc];
       // per-face inflow terms (zero on outflow faces), each sum pairing the
       // r faces and the z faces
-      double ed[4], tm[4], tI[4], ts0[4], ts1[4], ts2[4], tcut[4], tf[NM][4];
+      double ed[4];
+      FaceAcc am, aI, as0, as1, as2, acut, af[NM];
 #pragma unroll
       for (int q = 0; q < 4; q++) {
         // e = dV * lambda of the donor (the own cell on outflow faces)
         int d = inq[q] ? dk[q] : kc;
-        tm[q] = tI[q] = ts0[q] = ts1[q] = ts2[q] = tcut[q] = 0.0;
+        double tm = 0.0, tI = 0.0, ts0 = 0.0, ts1 = 0.0, ts2 = 0.0, tcut = 0.0, tf[NM];
 #pragma unroll
-        for (int m = 0; m < NM; m++) tf[m][q] = 0.0;
+        for (int m = 0; m < NM; m++) tf[m] = 0.0;
         if (inq[q]) {
           double adV = fabs((double)dV[q] * (double)ct[0 * R::NC + d]);
           double aF = fabs(F[q]);
-          tcut[q] = fabs((double)dV[q]) - adV;
+          tcut = fabs((double)dV[q]) - adV;
           double Id = PM ? 0.0 : cd[1 * R::NC + d];
-          tm[q] = aF;
-          tI[q] = aF * (Id - IL);
-          ts0[q] = aF * ((double)ct[1 * R::NC + d] - sL0);
-          ts1[q] = aF * ((double)ct[2 * R::NC + d] - sL1);
-          ts2[q] = aF * ((double)ct[3 * R::NC + d] - sL2);
+          tm = aF;
+          tI = aF * (Id - IL);
+          ts0 = aF * ((double)ct[1 * R::NC + d] - sL0);
+          ts1 = aF * ((double)ct[2 * R::NC + d] - sL1);
+          ts2 = aF * ((double)ct[3 * R::NC + d] - sL2);
 #pragma unroll
           for (int m = 0; m < NM; m++)
-            if (m == 0 || m < g.nmat) tf[m][q] = adV * (cd[(kFo + m) * R::NC + d] - fL[m]);
+            if (m == 0 || m < g.nmat) tf[m] = adV * (cd[(kFo + m) * R::NC + d] - fL[m]);
           ed[q] = F[q] * Id;
         } else {
           ed[q] = F[q] * IL;
         }
+        am.put(q, tm);
+        aI.put(q, tI);
+        as0.put(q, ts0);
+        as1.put(q, ts1);
+        as2.put(q, ts2);
+        acut.put(q, tcut);
+#pragma unroll
+        for (int m = 0; m < NM; m++) af[m].put(q, tf[m]);
       }
-      const double min_ = face_sum(tm), nI = face_sum(tI), vcut = face_sum(tcut);
-      const double nsrr = face_sum(ts0), nszz = face_sum(ts1), nsrz = face_sum(ts2);
+      const double min_ = am.sum(), nI = aI.sum(), vcut = acut.sum();
+      const double nsrr = as0.sum(), nszz = as1.sum(), nsrz = as2.sum();
       double nf[NM];
 #pragma unroll
-      for (int m = 0; m < NM; m++) nf[m] = face_sum(tf[m]);
+      for (int m = 0; m < NM; m++) nf[m] = af[m].sum();
       double lam = (double)ct[0 * R::NC + kc];
       double O = (double)((tmax(-dV[0], T(0)) + tmax(dV[1], T(0))) + (tmax(-dV[2], T(0)) + tmax(dV[3], T(0))));
       double den = dmax(dmax(M1, min_), kMRemapFloor * g.rho_ref * V);
-      double I1 = IL + nI / den;
+      const Over<T> byDen(den);
+      double I1 = IL + byDen(nI);
       // damage and vibration speed travel with the mass (donor values, the
       // faces paired as above)
       double Dn = 0.0, Vn = 0.0;
       if constexpr (DM) {
         const double DLc = cd[kDo * R::NC + kc], VLc = cd[(kDo + 1) * R::NC + kc];
-        double tD[4], tV[4];
+        FaceAcc aD, aV;
 #pragma unroll
         for (int q = 0; q < 4; q++) {
-          tD[q] = tV[q] = 0.0;
+          double tD = 0.0, tV = 0.0;
           if (inq[q]) {
             const double aF = fabs(F[q]);
-            tD[q] = aF * (cd[kDo * R::NC + dk[q]] - DLc);
-            tV[q] = aF * (cd[(kDo + 1) * R::NC + dk[q]] - VLc);
+            tD = aF * (cd[kDo * R::NC + dk[q]] - DLc);
+            tV = aF * (cd[(kDo + 1) * R::NC + dk[q]] - VLc);
           }
+          aD.put(q, tD);
+          aV.put(q, tV);
         }
-        Dn = DLc + face_sum(tD) / den;
-        Vn = VLc + face_sum(tV) / den;
+        Dn = DLc + byDen(aD.sum());
+        Vn = VLc + byDen(aV.sum());
       }
       // per-material closure: every material's specific energy remapped with
       // its own mass fluxes (donor values); the energy fluxes are the sums
@@ -821,21 +861,23 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
           I1m[m] = 0.0;
           if (m >= g.nmat) continue;
           const double ILc = cd[(NM + m) * R::NC + kc];
-          double tmm[4], tIm[4];
+          FaceAcc amm, aIm;
 #pragma unroll
           for (int q = 0; q < 4; q++) {
-            tmm[q] = tIm[q] = 0.0;
+            double tmm = 0.0, tIm = 0.0;
             if (inq[q]) {
               const double Id = cd[(NM + m) * R::NC + dk[q]];
               const double aF = fabs(Fm[m][q]);
-              tmm[q] = aF;
-              tIm[q] = aF * (Id - ILc);
+              tmm = aF;
+              tIm = aF * (Id - ILc);
               ed[q] += Fm[m][q] * Id;
             } else {
               ed[q] += Fm[m][q] * ILc;
             }
+            amm.put(q, tmm);
+            aIm.put(q, tIm);
           }
-          const double minm = face_sum(tmm), nIm = face_sum(tIm);
+          const double minm = amm.sum(), nIm = aIm.sum();
           const double denm = dmax(dmax(mu1[m] * V, minm), kMRemapFloor * g.rho_ref * V);
           I1m[m] = ILc + nIm / denm;
         }
@@ -843,7 +885,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       double ex = (1.0 - lam) * O - vcut;
       double f1v[NM];
 #pragma unroll
-      for (int m = 0; m < NM; m++) f1v[m] = (m == 0 || m < g.nmat) ? dmax(fL[m] + (nf[m] + fL[m] * ex) / V, 0.0) : 0.0;
+      for (int m = 0; m < NM; m++) f1v[m] = (m == 0 || m < g.nmat) ? dmax(fL[m] + byV(nf[m] + fL[m] * ex), 0.0) : 0.0;
       double fs = f1v[0];
 #pragma unroll
       for (int m = 1; m < NM; m++)
@@ -905,12 +947,14 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         long long c = cidx(g, i, j);
         D.rho[c] = rho1;
         double fv[NM];
+        // fractions summing above 1 are scaled back (x / 1 = x below that)
+        const Over<T> byFs(dmax(fs, 1.0));
 #pragma unroll
         for (int m = 0; m < NM; m++) {
-          fv[m] = f1v[m] / dmax(fs, 1.0);
+          fv[m] = fs > 1.0 ? byFs(f1v[m]) : f1v[m];
           if (m == 0 || m < g.nmat) D.f[m][c] = fv[m];
         }
-        T s0n = (T)(sL0 + nsrr / den), s1n = (T)(sL1 + nszz / den), s2n = (T)(sL2 + nsrz / den);
+        T s0n = (T)(sL0 + byDen(nsrr)), s1n = (T)(sL1 + byDen(nszz)), s2n = (T)(sL2 + byDen(nsrz));
         if (sdamp > 0.0) {  // extension: relax toward the initial (zero) deviator
           const double a0 = (double)s0n, a1 = (double)s1n, a2 = (double)s2n;
           s0n = (T)(a0 - dt * (sdamp * a0));
@@ -927,13 +971,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
           in.eout[i] += ed[3];
         }
         double chk = rho1;
-        if constexpr (kCarry) {
-          reg_put(eRho, u, rho1);
-          reg_put(eI, u, I1);  // before the remap heat, which G adds
-#pragma unroll
-          for (int m = 0; m < NM; m++) reg_put(eF[m], u, fv[m]);
-          chk += I1;
-        } else if constexpr (!PM) {
+        if constexpr (!PM) {
           D.I[c] = I1;  // before the remap heat, which G adds
           chk += I1;
         } else {
@@ -992,44 +1030,44 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     int kb0 = kB(i, j);
     T vLr = s_vL[kb0], vLz = s_vL[R::NB + kb0];
     T upr[4], upz[4];
-    bool ok[4];
-    double tm[4], tr[4], tz[4], tk[4];
+    FaceAcc am, ar_, az_, ak;
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-      ok[q] = ni[q] >= 0 && ni[q] <= g.NR && nj[q] >= 0 && nj[q] <= g.NZ;
-      tm[q] = tr[q] = tz[q] = tk[q] = 0.0;
-      if (inq[q] && ok[q]) {
+      const bool ok = ni[q] >= 0 && ni[q] <= g.NR && nj[q] >= 0 && nj[q] <= g.NZ;
+      double tm = 0.0, tr = 0.0, tz = 0.0, tk = 0.0;
+      if (inq[q] && ok) {
         int d = kB(ni[q], nj[q]);
         double aF = fabs(FD[q]);
         T ur = s_vL[d], uz = s_vL[R::NB + d];
-        tm[q] = aF;
-        tr[q] = aF * (double)(ur - vLr);
-        tz[q] = aF * (double)(uz - vLz);
+        tm = aF;
+        tr = aF * (double)(ur - vLr);
+        tz = aF * (double)(uz - vLz);
+        // the kinetic energy the donor flux carries in, relative to v^L
+        T dr_ = ur - vLr, dz_ = uz - vLz;
+        tk = aF * (double)(dr_ * dr_ + dz_ * dz_);
         upr[q] = ur;
         upz[q] = uz;
       } else {
         upr[q] = vLr;
         upz[q] = vLz;
       }
+      am.put(q, tm);
+      ar_.put(q, tr);
+      az_.put(q, tz);
+      ak.put(q, tk);
     }
-    const double min_ = face_sum(tm), nr = face_sum(tr), nz = face_sum(tz);
+    const double min_ = am.sum(), nr = ar_.sum(), nz = az_.sum();
     double aE = i < g.NR ? colD(i).aw : 0.0;
     double aW = i > 0 ? colD(i - 1).ae : 0.0;
     double hN = j < g.NZ ? 0.5 * dzD(j) : 0.0;
     double hS = j > 0 ? 0.5 * dzD(j - 1) : 0.0;
     double Vd = (aE + aW) * (hN + hS);
     double den = dmax(dmax(m1, min_), kMRemapFloor * g.rho_ref * Vd);
-    double v1r = (double)vLr + nr / den;
-    double v1z = (double)vLz + nz / den;
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-      if (inq[q] && ok[q]) {
-        T ar = upr[q] - vLr, az = upz[q] - vLz;
-        tk[q] = fabs(FD[q]) * (double)(ar * ar + az * az);
-      }
-    }
-    const double kin = face_sum(tk);
-    double dKE = 0.5 * (kin - (nr * nr + nz * nz) / den);
+    const Over<T> byDen(den);
+    double v1r = (double)vLr + byDen(nr);
+    double v1z = (double)vLz + byDen(nz);
+    const double kin = ak.sum();
+    double dKE = 0.5 * (kin - byDen(nr * nr + nz * nz));
     double Mq1[4];
 #pragma unroll
     for (int q = 0; q < 4; q++) Mq1[q] = qok[q] ? s_rho1[kE(qi[q], qj[q])] * volD(qi[q], qj[q]) : 0.0;
@@ -1117,7 +1155,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         if (m < NM && m < g.nmat) e += mu[m] * Imv[m];
       I1 = r > 0.0 ? e / r : 0.0;
     } else {
-      I1 = (kCarry ? eI[u] : D.I[c]) + h;
+      I1 = D.I[c] + h;
     }
     D.I[c] = I1;
     if (!((I1 - I1) == 0.0)) flags |= kFlagNonFinite;
@@ -1131,7 +1169,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     double f[kMaxMat];
 #pragma unroll
     for (int m = 0; m < kMaxMat; m++)
-      f[m] = m >= NM ? 0.0 : (kCarry ? reg_get(eF[m], u) : (m < g.nmat ? D.f[m][c] : 0.0));
+      f[m] = m >= NM ? 0.0 : (m < g.nmat ? D.f[m][c] : 0.0);
     // block model: the vibration speed decays as exp(-dt / T_vib) over the
     // step and is excited to c_vib times the largest corner speed of the new
     // velocities (volume-fraction weighted constants of the damaging
@@ -1164,7 +1202,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       for (int m = 0; m < NM; m++)
         if (m < g.nmat) ((T*)D.pmat[m])[c] = pmv[m];
     } else {
-      mx = mixture<T, DM>(g, kCarry ? eRho[u] : D.rho[c], I1, f, Dg, Vg);
+      mx = mixture<T, DM>(g, D.rho[c], I1, f, Dg, Vg);
     }
     store_eos(D, c, mx);
     cand = dmin(cand, cell_dt(g, mx, u4, dmin(colD(i).dr, dzD(j))));
