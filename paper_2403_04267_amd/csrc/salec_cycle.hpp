@@ -616,8 +616,11 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
           const T rdm = tmax((T)rmm, GT::rho_ref(g) * T(kRhoDenFloor));
           oILm[m] = (S.Im[m][c] + (double)N::div(Wm, rdm)) + (double)hL;
           if (kb >= 0 || kr >= 0) oILm[m] = oILm[m] - dt * (psi2 / rt);
-          const double kap = rho > 0.0 ? rhoE / rho : 0.0;
-          oMuL[m] = (rhoE == rho ? mud : mud * kap) / iJ;
+          // the printed placement's phi1 removes the same fraction of every
+          // material's mass (the quotient only where it acted)
+          double muE = mud;
+          if (rhoE != rho) muE = mud * (rho > 0.0 ? rhoE / rho : 0.0);
+          oMuL[m] = muE / iJ;
         }
       }
       // Jm / J, which is exactly 1 where the material follows the cell (Jm = J)

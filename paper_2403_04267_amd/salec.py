@@ -298,6 +298,14 @@ class Salec:
             out["c2"] = c2.reshape(NZ, NR)
         return out
 
+    def fractions(self, k: int = 0):
+        """Volume fractions of member k only, (nmat, NZ, NR)."""
+        NR, NZ, nmat = self.dims[k]
+        f = np.empty(nmat * NR * NZ)
+        fl = Fields(None, None, _ptr(f), None, None, None, None)
+        self._check(self.lib.salec_get_fields(self._h, int(k), C.byref(fl)))
+        return f.reshape(nmat, NZ, NR)
+
     def set_fields(self, rho, I, f, v, s=None, k: int = 0):
         NR, NZ, nmat = self.dims[k]
         NC, NN = NR * NZ, (NR + 1) * (NZ + 1)

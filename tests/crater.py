@@ -76,3 +76,38 @@ def conserved_errors(Fa, Fb, grid):
     e["mv_r"] = rel_l2(ma * Fa["v"][0], mb * Fb["v"][0])
     e["mv_z"] = rel_l2(ma * Fa["v"][1], mb * Fb["v"][1])
     return e
+
+
+MATTER = 1e-3  # cells (nodes) holding matter: the ones the Courant step accounts for
+
+
+def node_phi(phi):
+    """Matter fraction at the nodes: the mean over the (up to four) cells
+    around each node."""
+    NZ, NR = phi.shape
+    o, c = np.zeros((NZ + 1, NR + 1)), np.zeros((NZ + 1, NR + 1))
+    for dj in (0, 1):
+        for di in (0, 1):
+            o[dj:dj + NZ, di:di + NR] += phi
+            c[dj:dj + NZ, di:di + NR] += 1
+    return o / c
+
+
+def per_field(Fm, Fa, grid, sj):
+    """Run m against reference run a: plain per-field relative L2 of rho, p,
+    I, v_r, v_z over all cells (nodes) and over those holding matter, the
+    conserved densities, and the crater depth and radius difference in
+    cells."""
+    phi = Fa["f"].sum(0)
+    mc, mn = phi >= MATTER, node_phi(phi) >= MATTER
+    e = {}
+    for k in ("rho", "p", "I"):
+        e[k] = rel_l2(Fm[k], Fa[k])
+        e[k + "@matter"] = rel_l2(Fm[k][mc], Fa[k][mc])
+    for q, k in ((0, "v_r"), (1, "v_z")):
+        e[k] = rel_l2(Fm["v"][q], Fa["v"][q])
+        e[k + "@matter"] = rel_l2(Fm["v"][q][mn], Fa["v"][q][mn])
+    e.update({"cons." + k: v for k, v in conserved_errors(Fm, Fa, grid).items()})
+    e["depth_cells"] = abs(crater_depth(Fm["f"], grid, sj) - crater_depth(Fa["f"], grid, sj)) / grid.dz
+    e["radius_cells"] = abs(crater_radius(Fm["f"], grid, sj) - crater_radius(Fa["f"], grid, sj)) / grid.dr
+    return e

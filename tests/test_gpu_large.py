@@ -29,12 +29,10 @@ import pytest
 from oracle.oracle import Oracle
 from paper_2403_04267_amd import inputs
 
-from .crater import conserved_errors, crater_depth, crater_radius, rel_l2
+from .crater import crater_depth, per_field, rel_l2
 from .test_gpu_parity import compare
 
 pytestmark = pytest.mark.gpu
-
-MATTER = 1e-3
 
 
 def ctx(problems):
@@ -46,34 +44,6 @@ def block(x, k=10):
     nz, nr = x.shape[-2:]
     x = x[..., : nz // k * k, : nr // k * k]
     return x.reshape(x.shape[:-2] + (nz // k, k, nr // k, k)).mean(axis=(-3, -1))
-
-
-def node_phi(phi):
-    NZ, NR = phi.shape
-    o, c = np.zeros((NZ + 1, NR + 1)), np.zeros((NZ + 1, NR + 1))
-    for dj in (0, 1):
-        for di in (0, 1):
-            o[dj:dj + NZ, di:di + NR] += phi
-            c[dj:dj + NZ, di:di + NR] += 1
-    return o / c
-
-
-def per_field(Fm, Fa, grid, sj):
-    """Plain per-field rel-L2 over all cells / nodes and over those holding
-    matter, the conserved densities, crater depth and radius (cells)."""
-    phi = Fa["f"].sum(0)
-    mc, mn = phi >= MATTER, node_phi(phi) >= MATTER
-    e = {}
-    for k in ("rho", "p", "I"):
-        e[k] = rel_l2(Fm[k], Fa[k])
-        e[k + "@matter"] = rel_l2(Fm[k][mc], Fa[k][mc])
-    for q, k in ((0, "v_r"), (1, "v_z")):
-        e[k] = rel_l2(Fm["v"][q], Fa["v"][q])
-        e[k + "@matter"] = rel_l2(Fm["v"][q][mn], Fa["v"][q][mn])
-    e.update({"cons." + k: v for k, v in conserved_errors(Fm, Fa, grid).items()})
-    e["depth_cells"] = abs(crater_depth(Fm["f"], grid, sj) - crater_depth(Fa["f"], grid, sj)) / grid.dz
-    e["radius_cells"] = abs(crater_radius(Fm["f"], grid, sj) - crater_radius(Fa["f"], grid, sj)) / grid.dr
-    return e
 
 
 def blocked_conserved(Fm, Fa, grid):
