@@ -51,6 +51,20 @@ def test_table2_layout():
     assert np.all(rows[:30] == 1061.0) and np.all(rows[50:512] == 400.0)
 
 
+def test_table2_vertical_extent_reading():
+    """Table 2 prints y in [-181, 48.6] km (229.6 km) beside extension counts
+    (0, 20, 20, 20) and a 30-row PML below. With the top zone of 20 rows the
+    counts give 244.4 km; without it, 230.5 km (the radial extent, printed
+    231 km, is 230.5 km too). Only the layout without the top zone fits the
+    printed range; the default keeps the printed counts."""
+    with_top = inputs.paper_layout()
+    no_top = inputs.paper_layout(ext=(0, 20, 0, 20))
+    assert sum(with_top.dz_row) / 1e3 == pytest.approx(244.4, abs=0.05)
+    assert sum(no_top.dz_row) / 1e3 == pytest.approx(181.0 + 48.6, abs=1.0)
+    assert abs(sum(with_top.dz_row) / 1e3 - 229.6) > 14.0
+    assert sum(no_top.dr_col) == sum(with_top.dr_col)
+
+
 def test_geometry_tables():
     g = small_grid()
     o = Oracle(inputs.Problem(grid=g, mats=[inputs.basalt()], pml=inputs.Pml(enabled=0)))
