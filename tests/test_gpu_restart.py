@@ -7,7 +7,8 @@ the oracle's uninterrupted run bit for bit: every field, the PML auxiliaries
 (the layers are active at the hand-over), t, dt and the in-grid budgets.
 Covered: an impact with strength, with and without the PML, a layered target
 under gravity, the same with stress damping in the layers, the three-layer
-target under the per-material closure, and a stretched grid. A mixed-mode member continued in
+target under the per-material closure, a stretched grid, and an impact with damage and the block
+model (damage and vibration speed handed over too). A mixed-mode member continued in
 another mixed context equals the uninterrupted mixed run bit for bit.
 
 On the 1050^2 strength impact the mixed mode's error is seeded during the
@@ -46,6 +47,11 @@ def _damped(pb):
     return pb.replace(pml=dataclasses.replace(pb.pml, damp_stress=1))
 
 
+def _damage(pb):
+    keys = ("granite", "dunite")
+    return pb.replace(mats=[inputs.with_damage(m, **inputs.TABLE1_DAMAGE[k], af_h=2.0) for m, k in zip(pb.mats, keys)])
+
+
 CASES = {
     "impact-strength": lambda: inputs.impact(32, 8, 4, 12e3, 2, True, 0, name="impact"),
     "layered-gravity": lambda: inputs.layered_impact(32, 8, 4, 14e3, 6, name="layered"),
@@ -53,6 +59,7 @@ CASES = {
     "three-layer-pm": lambda: _pm(inputs.three_layer_impact(36, 8, 4, 14e3, 3, 6, name="three-layer-pm")),
     "stretched": lambda: inputs.stretched_impact(24, 6, 6, 3, 12e3, name="stretched"),
     "no-pml": lambda: _no_pml(inputs.impact(32, 8, 4, 12e3, 2, True, 0, name="no-pml")),
+    "damage": lambda: _damage(inputs.impact(32, 8, 4, 12e3, 2, True, 0, name="damage")),
 }
 
 N_HAND, N_MORE = 101, 40
@@ -84,6 +91,10 @@ def bitwise(g, o, pb, label):
         for m in range(Mo["mu"].shape[0]):
             errs[f"mu{m}"] = rel_linf(Mg["mu"][m], Mo["mu"][m])
             errs[f"Im{m}"] = rel_linf(Mg["Im"][m], Mo["Im"][m])
+    if any(int(m.damage) for m in pb.mats[:pb.grid.nmat]):
+        Dg, Do = g.damage(), o.damage()
+        errs["D"] = rel_linf(Dg["D"], Do["D"])
+        errs["vib"] = rel_linf(Dg["vib"], Do["vib"])
     Ag, Ao = g.pml_aux(), dict(o.pml_aux())
     lay = layer_mask(o, Ao["rho_ref"].shape)
     Ao["rho_ref"] = np.where(lay, Ao["rho_ref"], 0.0)
