@@ -6,10 +6,16 @@ Bars. Errors are relative L2 norms of the conserved volume densities (see
 tests/crater.py: rho, rho I, phi p, f, phi s, node momentum). While the runs
 are still deterministic in the ejecta (first 100 cycles) every one is
 <= 1e-4. Later the method's own amplification of rounding in the ejecta
-takes over (two FP64 runs that differ by one ulp in the initial velocities
-drift apart to 1e-4 - 1e-3 by cycle 500, see test_fp64_sensitivity_floor in
-tests/test_oracle_physics.py), so at the end of the runs the check is the
-crater depth and radius within one cell, and the mass budget.
+takes over: two FP64 runs that differ by one ulp in the initial velocities
+drift apart to 1e-4 - 1e-2 by cycle 500 (test_fp64_sensitivity_floor in
+tests/test_oracle_physics.py). The floor is measured on each problem with
+the oracle (initial velocities one ulp up) and printed, per field over the
+cells holding matter, beside the mixed run's. In the hydrodynamic impact the
+floor is of the mixed error's size, and each conserved density is held to
+max(1e-4, 10 x floor). The strength impact is not chaotic (floor 2e-7 at
+cycle 300) while the mixed run's density is 2.7e-3 off: that is single
+precision's own loss, so there the bar is the measured one, density and
+fractions within 1e-2. Both hold crater depth and radius to one cell.
 """
 import numpy as np
 import pytest
@@ -17,7 +23,7 @@ import pytest
 from oracle.oracle import Oracle
 from paper_2403_04267_amd import inputs
 
-from .crater import conserved_errors, crater_depth, crater_radius, rel_l2
+from .crater import conserved_errors, crater_depth, crater_radius, per_field, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -29,27 +35,38 @@ def ctx(problems):
     return Salec(problems)
 
 
-def check_pair(pb, early, late, label):
+def check_pair(pb, early, late, label, floor_bar):
     pm = pb.replace(precision="mixed")
-    g, o = ctx(pm), Oracle(pb)
+    g, o, p = ctx(pm), Oracle(pb), Oracle(pb)
+    F0 = p.fields(eos=False)
+    p.set_fields(F0["rho"], F0["I"], F0["f"], np.nextafter(F0["v"], np.inf), F0["s"])
     g.step(early)
     o.step(early)
+    p.step(early)
     e = conserved_errors(g.fields(), o.fields(), pb.grid)
     print(f"[{label} cycle {early}] " + " ".join(f"{k} {v:.2e}" for k, v in e.items()), flush=True)
     bad = {k: v for k, v in e.items() if not v <= TOL}
     assert not bad, bad
     g.step(late - early)
     o.step(late - early)
-    Fg, Fo = g.fields(), o.fields()
+    p.step(late - early)
+    Fg, Fo, Fp = g.fields(), o.fields(), p.fields()
     e = conserved_errors(Fg, Fo, pb.grid)
     sj = pb.scene.surface_j
+    eg, ep = per_field(Fg, Fo, pb.grid, sj), per_field(Fp, Fo, pb.grid, sj)
+    for name, x in (("mixed", eg), ("FP64 floor", ep)):
+        print(f"[{label} cycle {late}, {name}] " + " ".join(f"{k} {v:.2e}" for k, v in x.items()), flush=True)
+    if floor_bar:
+        for k, v in e.items():
+            assert v <= max(TOL, 10.0 * ep["cons." + k]), (k, v, ep["cons." + k])
+    else:
+        assert e["rho"] < 1e-2 and e["f"] < 1e-2
     dg, do = crater_depth(Fg["f"], pb.grid, sj), crater_depth(Fo["f"], pb.grid, sj)
     rg, ro = crater_radius(Fg["f"], pb.grid, sj), crater_radius(Fo["f"], pb.grid, sj)
     print(f"[{label} cycle {late}] " + " ".join(f"{k} {v:.2e}" for k, v in e.items()) +
           f" depth {dg:.3f}/{do:.3f} radius {rg:.3f}/{ro:.3f}", flush=True)
     assert abs(dg - do) <= pb.grid.dz
     assert abs(rg - ro) <= pb.grid.dr
-    assert e["rho"] < 1e-2 and e["f"] < 1e-2
     dgd, dod = g.diag(), o.diag()
     assert dgd["cycle"] == dod["cycle"] == late
     # dt follows the fastest ejecta, where the runs differ most
@@ -59,12 +76,12 @@ def check_pair(pb, early, late, label):
 
 def test_mixed_small_impact_against_oracle():
     """100x100 + 20 PML hydrodynamic impact, 500 cycles."""
-    check_pair(inputs.config_small(), 100, 500, "small")
+    check_pair(inputs.config_small(), 100, 500, "small", floor_bar=True)
 
 
 def test_mixed_strength_two_materials_against_oracle():
     pb = inputs.impact(61, 13, 6, 15e3, nmat=2, strength=True, cycles=300, name="strength-61")
-    check_pair(pb, 100, 300, "strength-61")
+    check_pair(pb, 100, 300, "strength-61", floor_bar=False)
 
 
 def test_mixed_mass_budget_is_exact_to_fp64_sums():
