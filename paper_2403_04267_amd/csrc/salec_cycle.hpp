@@ -287,19 +287,26 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       v0r = Sv0[n];
       v0z = Sv1[n];
     }
-    if (node_ok && i >= i0 - 2 && j >= j0 - 2) {
-      s_vL[kB(i, j)] = v0r;
-      s_vL[R::NB + kB(i, j)] = v0z;
-    }
     if (in_cells(g, i, j)) {
       long long c = cidx(g, i, j);
+      // every load of the cell first, with no branch among them (arrays a
+      // material or the strength model lacks are replaced by one that exists,
+      // read and unused), so that they are in flight together
       double fd[NM];
       T f[kMaxMat];
 #pragma unroll
       for (int m = 0; m < kMaxMat; m++) {
-        if (m < NM) fd[m] = m < g.nmat ? S.f[m][c] : 0.0;
+        if (m < NM) {
+          const double x = S.f[m < g.nmat ? m : 0][c];
+          fd[m] = m < g.nmat ? x : 0.0;
+        }
         f[m] = m < NM ? (T)fd[m] : T(0);
       }
+      const T* St0 = g.any_strength ? Ss0 : (const T*)S.eos[0];
+      const T* St1 = g.any_strength ? Ss1 : (const T*)S.eos[0];
+      const T* St2 = g.any_strength ? Ss2 : (const T*)S.eos[0];
+      const T l0 = St0[c], l1 = St1[c], l2 = St2[c];
+      const T p0j = (T)(g.has_p0 ? in.p0 : S.rho)[j];
       rh = S.rho[c];
       T phi, den, rm;
       matter(g, (T)rh, f, phi, den, rm);
@@ -317,13 +324,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       T Q = rm * (GT::q_quad(g) * Ld * Ld + GT::q_lin(g) * N::sqr(c2) * Ld);
       T P = p + Q;
       // the momentum balance (and so psi1) sees p - p0; C's energy terms keep P
-      const T Pf = g.has_p0 ? P - (T)in.p0[j] : P;
-      T srr = T(0), szz = T(0), srz = T(0);
-      if (g.any_strength) {
-        srr = Ss0[c];
-        szz = Ss1[c];
-        srz = Ss2[c];
-      }
+      const T Pf = g.has_p0 ? P - p0j : P;
+      const T srr = g.any_strength ? l0 : T(0), szz = g.any_strength ? l1 : T(0), srz = g.any_strength ? l2 : T(0);
       T stt = -(srr + szz);
       s0 = phi * (srr - Pf);
       s1 = phi * (szz - Pf);
@@ -337,6 +339,10 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       reg_put(rS1, u, szz);
       reg_put(rS2, u, srz);
       reg_put(rSx, u, sx);
+    }
+    if (node_ok && i >= i0 - 2 && j >= j0 - 2) {
+      s_vL[kB(i, j)] = v0r;
+      s_vL[R::NB + kB(i, j)] = v0z;
     }
     const int ka = kA(i, j);
     sig[0 * R::NA + ka] = s0;
@@ -459,6 +465,11 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     double oDL = 0.0, oVib = 0.0;  // damage and vibration speed (void donor: 0)
     if (in_cells(g, i, j)) {
       long long c = cidx(g, i, j);
+      // the cell's loads first, with no branch among them (as in A)
+      const T Gl = ((const T*)S.eos[2])[c], Yl = ((const T*)S.eos[3])[c];
+      double Il = 0.0;
+      if constexpr (!PM) Il = S.I[c];
+      const double dbl = (g.pml_on ? pm.dcz : S.rho)[j], drl = (g.pml_on ? pm.dcr : S.rho)[i];
       const int nb[4] = {kB(i, j), kB(i + 1, j), kB(i, j + 1), kB(i + 1, j + 1)};
       T vr4[4], vz4[4];
 #pragma unroll
@@ -481,7 +492,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       }
       T srr = s0rr, szz = s0zz, srz = s0rz;
       if (g.any_strength) {
-        T G = ((const T*)S.eos[2])[c], Y = ((const T*)S.eos[3])[c];
+        T G = Gl, Y = Yl;
         T tr3 = N::div((kn.err + kn.ezz) + kn.ett, T(3));
         // damage: the volume-fraction weights of the level-n cell
         T dw[kMaxMat];
@@ -571,8 +582,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       double psi2 = 0.0, db = 0.0, drr = 0.0;
       long long kb = -1, kr = -1;
       if (g.pml_on) {
-        db = pm.dcz[j];
-        drr = pm.dcr[i];
+        db = dbl;
+        drr = drl;
         if (j < g.pml_b) kb = pml_bc(g, i, j);
         if (i >= g.n_r) kr = pml_rc(g, i, j);
         // the auxiliary this step applies to the energy: psi2, or phi3 as
@@ -591,7 +602,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       }
       double IL = 0.0;
       if constexpr (!PM) {
-        IL = (S.I[c] + (double)N::div(Wdt, rden)) + (double)hL;
+        IL = (Il + (double)N::div(Wdt, rden)) + (double)hL;
         // outside the strips psi2 is +0 and so is its term: x - (+0) = x
         if (kb >= 0 || kr >= 0) IL = IL - dt * (psi2 / rt);
       } else {
@@ -741,6 +752,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     e_cell(k, i, j);
     double rho1 = 0.0;
     if (in_cells(g, i, j)) {
+      // the damping profiles first: their latency hides behind the flux sums
+      const double dbl = (g.pml_on ? pm.dcz : S.rho)[j], drl = (g.pml_on ? pm.dcr : S.rho)[i];
       bool own = owns_cell(i, j);
       double V = volD(i, j);
       T dV[4] = {dv_r(i, j), dv_r(i + 1, j), dv_z(i, j), dv_z(i, j + 1)};
@@ -895,7 +908,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         if (m < g.nmat) fs = fs + f1v[m];
       double sdamp = 0.0;  // the layer's rate, when it also relaxes the stress
       if (g.pml_on) {
-        double db = pm.dcz[j], drr = pm.dcr[i];
+        double db = dbl, drr = drl;
         if (db > 0.0 || drr > 0.0) {
           long long kb = j < g.pml_b ? pml_bc(g, i, j) : -1;
           long long kr = i >= g.n_r ? pml_rc(g, i, j) : -1;
@@ -1009,6 +1022,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   for (int k = tid; k < R::NF; k += NT) {
     int i = i0 + k % R::FW, j = j0 + k / R::FW;
     if (i > g.NR || j > g.NZ) continue;
+    // the damping profiles first: their latency hides behind the flux sums
+    const double dbl = (g.pml_on ? pm.dnz : S.rho)[j], drl = (g.pml_on ? pm.dnr : S.rho)[i];
     // node mass: a quarter of the four cell masses (SW, SE, NW, NE)
     const int qi[4] = {i - 1, i, i - 1, i}, qj[4] = {j - 1, j - 1, j, j};
     double M[4] = {0, 0, 0, 0};
@@ -1078,7 +1093,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     double h = Mn > kMRemapFloor * g.rho_ref * Vd ? dmax(dKE, 0.0) / Mn : 0.0;
     bool own = owns_node(i, j);
     if (g.pml_on) {
-      double db = pm.dnz[j], drr = pm.dnr[i];
+      double db = dbl, drr = drl;
       if (db > 0.0 || drr > 0.0) {
         long long kb = j < g.pml_b ? pml_bn(g, i, j) : -1;
         long long kr = i > g.n_r ? pml_rn(g, i, j) : -1;
@@ -1136,6 +1151,21 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     e_cell(k, i, j);
     if (!owns_cell(i, j)) continue;
     long long c = cidx(g, i, j);
+    // the cell's loads first, ahead of its stores (which the compiler may not
+    // move them past) and with no branch among them (as in A)
+    double f[kMaxMat];
+#pragma unroll
+    for (int m = 0; m < kMaxMat; m++) {
+      if (m < NM) {
+        const double x = D.f[m < g.nmat ? m : 0][c];
+        f[m] = m < g.nmat ? x : 0.0;
+      } else {
+        f[m] = 0.0;
+      }
+    }
+    const double rhoG = D.rho[c];
+    double Ig = 0.0;
+    if constexpr (!PM) Ig = D.I[c];
     const int nf[4] = {kF(i, j), kF(i + 1, j), kF(i, j + 1), kF(i + 1, j + 1)};
     double h = (heat[nf[0]] + heat[nf[1]]) + (heat[nf[2]] + heat[nf[3]]);
     double I1;
@@ -1158,7 +1188,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
         if (m < NM && m < g.nmat) e += mu[m] * Imv[m];
       I1 = r > 0.0 ? e / r : 0.0;
     } else {
-      I1 = D.I[c] + h;
+      I1 = Ig + h;
     }
     D.I[c] = I1;
     if (!((I1 - I1) == 0.0)) flags |= kFlagNonFinite;
@@ -1169,10 +1199,6 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       if (!((sp - sp) == T(0))) flags |= kFlagNonFinite;
       u4 = tmax(u4, sp);
     }
-    double f[kMaxMat];
-#pragma unroll
-    for (int m = 0; m < kMaxMat; m++)
-      f[m] = m >= NM ? 0.0 : (m < g.nmat ? D.f[m][c] : 0.0);
     // block model: the vibration speed decays as exp(-dt / T_vib) over the
     // step and is excited to c_vib times the largest corner speed of the new
     // velocities (volume-fraction weighted constants of the damaging
@@ -1200,12 +1226,12 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     Mix<T> mx;
     if constexpr (PM) {
       T pmv[kMaxMat];
-      mx = mixture_pm<T, DM>(g, D.rho[c], f, mu, Imv, pmv, Dg, Vg);
+      mx = mixture_pm<T, DM>(g, rhoG, f, mu, Imv, pmv, Dg, Vg);
 #pragma unroll
       for (int m = 0; m < NM; m++)
         if (m < g.nmat) ((T*)D.pmat[m])[c] = pmv[m];
     } else {
-      mx = mixture<T, DM>(g, D.rho[c], I1, f, Dg, Vg);
+      mx = mixture<T, DM>(g, rhoG, I1, f, Dg, Vg);
     }
     store_eos(D, c, mx);
     cand = dmin(cand, cell_dt(g, mx, u4, dmin(colD(i).dr, dzD(j))));
