@@ -701,10 +701,12 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   __syncthreads();
 
   // ------------------------------------------------------------------ E1
-  // mass flux of every face the remap and the momentum remap touch; 0 where
-  // there is no face. e = dV lambda of the donor d; the flux is e rho^L(d),
-  // or with the per-material closure the sum of every material's e mu_m^L(d)
-  // (E2 recomputes the same terms per material).
+  // mass flux of a face (0 where there is no face): e = dV lambda of the
+  // donor d; the flux is e rho^L(d), or with the per-material closure the
+  // sum of every material's e mu_m^L(d) (E2 recomputes the same terms per
+  // material). Each E2 position forms the fluxes of its four faces and leaves
+  // those F needs in LDS: its west and south faces, the east faces of the
+  // last column and the north faces of the last row.
   auto face_flux = [&](T dV, int d) -> double {
     if (!(dV > T(0) || dV < T(0))) return 0.0;
     const double e = (double)dV * (double)ct[0 * R::NC + d];
@@ -718,25 +720,6 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       return e * cd[0 * R::NC + d];
     }
   };
-  for (int k = tid; k < R::NRF; k += NT) {
-    int i = i0 - 1 + k % R::RW, j = j0 - 1 + k / R::RW;
-    double F = 0.0;
-    if (i >= 0 && i <= g.NR && j >= 0 && j < g.NZ) {
-      T dV = dv_r(i, j);
-      F = face_flux(dV, dV > T(0) ? kC(i - 1, j) : kC(i, j));
-    }
-    s_Fr[k] = F;
-  }
-  for (int k = tid; k < R::NZF; k += NT) {
-    int i = i0 - 1 + k % R::ZW, j = j0 - 1 + k / R::ZW;
-    double F = 0.0;
-    if (i >= 0 && i < g.NR && j >= 0 && j <= g.NZ) {
-      T dV = dv_z(i, j);
-      F = face_flux(dV, dV > T(0) ? kC(i, j - 1) : kC(i, j));
-    }
-    s_Fz[k] = F;
-  }
-  __syncthreads();
 
   // ------------------------------------------------------------------ E2
   // (the new density, energy and volume fractions of owned cells reach G,
@@ -751,16 +734,24 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     int i, j;
     e_cell(k, i, j);
     double rho1 = 0.0;
+    const T dV[4] = {dv_r(i, j), dv_r(i + 1, j), dv_z(i, j), dv_z(i, j + 1)};
+    const int dk[4] = {kC(i - 1, j), kC(i + 1, j), kC(i, j - 1), kC(i, j + 1)};
+    const bool inq[4] = {dV[0] > T(0), dV[1] < T(0), dV[2] > T(0), dV[3] < T(0)};
+    const int kc = kC(i, j);
+    const bool face[4] = {i >= 0 && i <= g.NR && j >= 0 && j < g.NZ, i + 1 >= 0 && i + 1 <= g.NR && j >= 0 && j < g.NZ,
+                          i >= 0 && i < g.NR && j >= 0 && j <= g.NZ, i >= 0 && i < g.NR && j + 1 >= 0 && j + 1 <= g.NZ};
+    double F[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) F[q] = face[q] ? face_flux(dV[q], inq[q] ? dk[q] : kc) : 0.0;
+    s_Fr[kR(i, j)] = F[0];
+    s_Fz[kZ(i, j)] = F[2];
+    if (i == i0 + TW) s_Fr[kR(i + 1, j)] = F[1];
+    if (j == j0 + TH) s_Fz[kZ(i, j + 1)] = F[3];
     if (in_cells(g, i, j)) {
       // the damping profiles first: their latency hides behind the flux sums
       const double dbl = (g.pml_on ? pm.dcz : S.rho)[j], drl = (g.pml_on ? pm.dcr : S.rho)[i];
       bool own = owns_cell(i, j);
       double V = volD(i, j);
-      T dV[4] = {dv_r(i, j), dv_r(i + 1, j), dv_z(i, j), dv_z(i, j + 1)};
-      double F[4] = {s_Fr[kR(i, j)], s_Fr[kR(i + 1, j)], s_Fz[kZ(i, j)], s_Fz[kZ(i, j + 1)]};
-      const int dk[4] = {kC(i - 1, j), kC(i + 1, j), kC(i, j - 1), kC(i, j + 1)};
-      const bool inq[4] = {dV[0] > T(0), dV[1] < T(0), dV[2] > T(0), dV[3] < T(0)};
-      int kc = kC(i, j);
       double netin = (F[0] - F[1]) + (F[2] - F[3]);
       const Over<T> byV(V);
       rho1 = s_rho[kA(i, j)] + byV(netin);
