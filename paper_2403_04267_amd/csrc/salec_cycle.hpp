@@ -161,12 +161,20 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
 
   const Geo& g = in.g;
   Scal* sc = in.sc;
-  if (sc->err) return;
+  // the instance's clock: written only by the finalize kernel between
+  // launches, so read through the constant address space (scalar loads, one
+  // batch) rather than as vector loads behind the error test
+  using CScal = const __attribute__((address_space(4))) Scal;
+  const CScal* csc = (const CScal*)sc;
+  const int err = csc->err;
+  const long long cyc = csc->cycle;
+  const double dt = csc->dt;
+  if (err) return;
   const int tid = threadIdx.x;
   const int ti = tile % in.tiles_r, tj = tile / in.tiles_r;
   const int i0 = ti * TW, j0 = tj * TH;
   const int i1 = min(i0 + TW, g.NR), j1 = min(j0 + TH, g.NZ);  // owned cells [i0, i1) x [j0, j1)
-  const int par = (int)(sc->cycle & 1);
+  const int par = (int)(cyc & 1);
   const State& S = in.S[par];
   const State& D = in.S[par ^ 1];
   const Pml& pm = in.pm;
@@ -177,7 +185,6 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   const T* Ss0 = (const T*)S.s[0];
   const T* Ss1 = (const T*)S.s[1];
   const T* Ss2 = (const T*)S.s[2];
-  const double dt = sc->dt;
   const T dtT = (T)dt;
   // Grid geometry: the uniform-grid kernel evaluates it from i and j; the
   // table kernel (GEO, launched when any instance is stretched) reads each
@@ -280,13 +287,10 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     double rh = 0.0;
     // v^n of the node at the cell's lower-left corner; B's nodes are these
     // corners of A's cells from (i0-2, j0-2) on, so A hands them to B in LDS
+    // (read from a clamped node, and used only where the node exists)
     const bool node_ok = i >= 0 && i <= g.NR && j >= 0 && j <= g.NZ;
-    T v0r = T(0), v0z = T(0);
-    if (node_ok) {
-      const long long n = nidx(g, i, j);
-      v0r = Sv0[n];
-      v0z = Sv1[n];
-    }
+    const long long n0 = nidx(g, min(max(i, 0), g.NR), min(max(j, 0), g.NZ));
+    const T v0r = Sv0[n0], v0z = Sv1[n0];
     if (in_cells(g, i, j)) {
       long long c = cidx(g, i, j);
       // every load of the cell first, with no branch among them (arrays a
@@ -358,6 +362,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     int i = i0 - 2 + k % R::BW, j = j0 - 2 + k / R::BW;
     T vLr = T(0), vLz = T(0), kdn = T(0);
     if (i >= 0 && i <= g.NR && j >= 0 && j <= g.NZ) {
+      // the damping profiles first: their latency hides behind the forces
+      const double dbl = (g.pml_on ? pm.dnz : S.rho)[j], drl = (g.pml_on ? pm.dnr : S.rho)[i];
       const T vnr = s_vL[k], vnz = s_vL[R::NB + k];  // v^n, from A
       // quadrants NE = (i, j), NW = (i-1, j), SE = (i, j-1), SW = (i-1, j-1)
       const int qa[4] = {kA(i, j), kA(i - 1, j), kA(i, j - 1), kA(i - 1, j - 1)};
@@ -393,8 +399,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       double db = 0.0, drr = 0.0;
       long long kb = -1, kr = -1;
       if (g.pml_on) {
-        db = pm.dnz[j];
-        drr = pm.dnr[i];
+        db = dbl;
+        drr = drl;
         if (j < g.pml_b) kb = pml_bn(g, i, j);
         if (i > g.n_r) kr = pml_rn(g, i, j);
         // the auxiliary this step applies: psi1, or phi2 when the layers
@@ -657,7 +663,13 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       os2 = srz;
 #pragma unroll
       for (int m = 0; m < NM; m++) of[m] = fLv[m];
-      oLam = J;  // the limiter pass below turns J into lambda
+      // donor outflow limiter: volume leaving through the four faces vs V^L = V J
+      {
+        T dW = dv_r(i, j), dE = dv_r(i + 1, j), dS = dv_z(i, j), dN = dv_z(i, j + 1);
+        T O = (tmax(-dW, T(0)) + tmax(dE, T(0))) + (tmax(-dS, T(0)) + tmax(dN, T(0)));
+        T VL = volT(i, j) * J;
+        oLam = O > VL ? N::div(tmax(VL, T(0)), O) : T(1);
+      }
     }
     int kc = kC(i, j);
     if constexpr (DM) {
@@ -680,23 +692,6 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     ct[1 * R::NC + kc] = os0;
     ct[2 * R::NC + kc] = os1;
     ct[3 * R::NC + kc] = os2;
-  }
-  // donor outflow limiter (same cells and threads as C, in a pass of its own
-  // to keep C's register peak down): volume leaving through the four faces
-  // vs V^L = V J
-#pragma unroll kUnroll
-  for (int u = 0; u < UA; u++) {
-    int k = tid + u * NT;
-    if (k >= (R::AH - 2) * R::AW) continue;
-    int i, j;
-    a_cell(k, i, j);
-    if (i < i0 - 2 || i >= i0 + TW + 2 || !in_cells(g, i, j)) continue;
-    int kc = kC(i, j);
-    T J = ct[0 * R::NC + kc];
-    T dW = dv_r(i, j), dE = dv_r(i + 1, j), dS = dv_z(i, j), dN = dv_z(i, j + 1);
-    T O = (tmax(-dW, T(0)) + tmax(dE, T(0))) + (tmax(-dS, T(0)) + tmax(dN, T(0)));
-    T VL = volT(i, j) * J;
-    ct[0 * R::NC + kc] = O > VL ? N::div(tmax(VL, T(0)), O) : T(1);
   }
   __syncthreads();
 
