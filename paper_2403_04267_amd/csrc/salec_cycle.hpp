@@ -60,6 +60,11 @@ struct Smem {
   static constexpr int kBigF = R::NF * (8 + (int)sizeof(T));          // heat | speed
   static constexpr int kBig = kBigA > kBigC ? (kBigA > kBigF ? kBigA : kBigF) : (kBigC > kBigF ? kBigC : kBigF);
   static constexpr int kBigD = (kBig + 7) / 8;
+  // the damping profiles are staged in LDS where the workgroup's LDS still
+  // fits with them (else the phases read them from memory); kRest: every
+  // other LDS array of the cycle kernel but s_min and s_geo
+  static constexpr int kDamp = R::CW + R::CH + R::BW + R::BH;
+  static constexpr int kRest = 8 * (R::NA + kBigD + R::NRF + R::NZF + R::NE) + 2 * R::NB * (int)sizeof(T);
 };
 
 // Sum of four per-face (or per-corner) terms ordered W, E, S, N (or SW, SE,
@@ -150,10 +155,10 @@ __device__ __forceinline__ void reg_put(T (&a)[N], int u, T v) {
   for (int q = 0; q < N; q++) a[q] = (u == q) ? v : a[q];
 }
 
-template <int TW, int TH, int NT, int WPE, class T, bool GEO, int NM, bool PM, bool DM>
+template <int TW, int TH, int NT, int WPE, class T, bool GEO, int NM, bool PM, bool DM, bool DL>
 __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_rho, double* s_bigd, T* s_vL,
                                            double* s_Fr, double* s_Fz, double* s_rho1, double* s_min,
-                                           double* s_geo) {
+                                           double* s_geo, double* s_damp) {
   using R = Regions<TW, TH>;
   using N = Num<T>;
   using GT = GeoT<T>;
@@ -259,6 +264,34 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   T* s_kd = (T*)s_Fr;                 // [NB] during B..C: 1/2 |v^L - v^n|^2 per node
   static_assert(R::NB * (int)sizeof(T) <= (R::NRF + R::NZF) * 8, "node buffer must fit in the flux buffers");
 
+  // The damping profiles of the tile's cell columns and rows (C's region)
+  // and node columns and rows (B's region), staged in LDS during A for B, C,
+  // E2 and F: the loads join A's batch (from a clamped index, or the density
+  // array's first entry when there are no layers), the stores follow A's loop.
+  constexpr int kDamp = R::CW + R::CH + R::BW + R::BH;
+  double* s_dcr = s_damp;
+  double* s_dcz = s_dcr + R::CW;
+  double* s_dnr = s_dcz + R::CH;
+  double* s_dnz = s_dnr + R::BW;
+  bool damp_ok;
+  double damp_v;
+  {
+    const int k = tid < kDamp ? tid : 0;
+    const double* a;
+    int idx, lim;
+    if (k < R::CW) {
+      a = pm.dcr, idx = i0 - 2 + k, lim = g.NR;
+    } else if (k < R::CW + R::CH) {
+      a = pm.dcz, idx = j0 - 2 + (k - R::CW), lim = g.NZ;
+    } else if (k < R::CW + R::CH + R::BW) {
+      a = pm.dnr, idx = i0 - 2 + (k - R::CW - R::CH), lim = g.NR + 1;
+    } else {
+      a = pm.dnz, idx = j0 - 2 + (k - R::CW - R::CH - R::BW), lim = g.NZ + 1;
+    }
+    damp_ok = g.pml_on && tid < kDamp && idx >= 0 && idx < lim;
+    damp_v = (g.pml_on ? a : S.rho)[g.pml_on ? min(max(idx, 0), lim - 1) : 0];
+  }
+
   // ------------------------------------------------------------------ A
   // 1024-thread workgroups keep the per-cell loops of A and C rolled: four
   // waves per SIMD leave no registers for two cells in flight at once
@@ -355,6 +388,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     sig[3 * R::NA + ka] = s3;
     s_rho[ka] = rh;
   }
+  if (DL && tid < kDamp) s_damp[tid] = damp_ok ? damp_v : 0.0;
   __syncthreads();
 
   // ------------------------------------------------------------------ B
@@ -363,7 +397,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     T vLr = T(0), vLz = T(0), kdn = T(0);
     if (i >= 0 && i <= g.NR && j >= 0 && j <= g.NZ) {
       // the damping profiles first: their latency hides behind the forces
-      const double dbl = (g.pml_on ? pm.dnz : S.rho)[j], drl = (g.pml_on ? pm.dnr : S.rho)[i];
+      const double dbl = DL ? s_dnz[j - (j0 - 2)] : (g.pml_on ? pm.dnz : S.rho)[j];
+      const double drl = DL ? s_dnr[i - (i0 - 2)] : (g.pml_on ? pm.dnr : S.rho)[i];
       const T vnr = s_vL[k], vnz = s_vL[R::NB + k];  // v^n, from A
       // quadrants NE = (i, j), NW = (i-1, j), SE = (i, j-1), SW = (i-1, j-1)
       const int qa[4] = {kA(i, j), kA(i - 1, j), kA(i, j - 1), kA(i - 1, j - 1)};
@@ -475,7 +510,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       const T Gl = ((const T*)S.eos[2])[c], Yl = ((const T*)S.eos[3])[c];
       double Il = 0.0;
       if constexpr (!PM) Il = S.I[c];
-      const double dbl = (g.pml_on ? pm.dcz : S.rho)[j], drl = (g.pml_on ? pm.dcr : S.rho)[i];
+      const double dbl = DL ? s_dcz[j - (j0 - 2)] : (g.pml_on ? pm.dcz : S.rho)[j];
+      const double drl = DL ? s_dcr[i - (i0 - 2)] : (g.pml_on ? pm.dcr : S.rho)[i];
       const int nb[4] = {kB(i, j), kB(i + 1, j), kB(i, j + 1), kB(i + 1, j + 1)};
       T vr4[4], vz4[4];
 #pragma unroll
@@ -744,7 +780,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     if (j == j0 + TH) s_Fz[kZ(i, j + 1)] = F[3];
     if (in_cells(g, i, j)) {
       // the damping profiles first: their latency hides behind the flux sums
-      const double dbl = (g.pml_on ? pm.dcz : S.rho)[j], drl = (g.pml_on ? pm.dcr : S.rho)[i];
+      const double dbl = DL ? s_dcz[j - (j0 - 2)] : (g.pml_on ? pm.dcz : S.rho)[j];
+      const double drl = DL ? s_dcr[i - (i0 - 2)] : (g.pml_on ? pm.dcr : S.rho)[i];
       bool own = owns_cell(i, j);
       double V = volD(i, j);
       double netin = (F[0] - F[1]) + (F[2] - F[3]);
@@ -1009,7 +1046,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     int i = i0 + k % R::FW, j = j0 + k / R::FW;
     if (i > g.NR || j > g.NZ) continue;
     // the damping profiles first: their latency hides behind the flux sums
-    const double dbl = (g.pml_on ? pm.dnz : S.rho)[j], drl = (g.pml_on ? pm.dnr : S.rho)[i];
+    const double dbl = DL ? s_dnz[j - (j0 - 2)] : (g.pml_on ? pm.dnz : S.rho)[j];
+    const double drl = DL ? s_dnr[i - (i0 - 2)] : (g.pml_on ? pm.dnr : S.rho)[i];
     // node mass: a quarter of the four cell masses (SW, SE, NW, NE)
     const int qi[4] = {i - 1, i, i - 1, i}, qj[4] = {j - 1, j - 1, j, j};
     double M[4] = {0, 0, 0, 0};
@@ -1239,6 +1277,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   __shared__ double s_rho1[R::NE];    // rho^{n+1} over E (0 outside the grid)
   __shared__ double s_min[NT / 64];
   __shared__ double s_geo[GEO ? GeoLds<TW, TH>::N : 1];  // a stretched tile's geometry
+  // the tile's damping profiles (where they fit)
+  constexpr bool kDampLds = SM::kRest + 8 * (NT / 64 + (GEO ? GeoLds<TW, TH>::N : 1) + SM::kDamp) <= 163840 - 64;
+  __shared__ double s_damp[kDampLds ? SM::kDamp : 1];
   // Descriptors and schedule are read-only for the whole launch: reading them
   // through the constant address space lets the compiler keep or re-issue
   // those scalar loads freely across the workgroup barriers below.
@@ -1250,8 +1291,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     const TileRef tr{csched[e].inst, csched[e].tile};
     if (tr.inst < 0) continue;
     const Inst* in = (const Inst*)(cinst + tr.inst);
-    tile_cycle<TW, TH, NT, WPE, T, GEO, NM, PM, DM>(*in, tr.tile, s_rho, s_bigd, s_vL, s_F, s_F + R::NRF, s_rho1, s_min,
-                                            s_geo);
+    tile_cycle<TW, TH, NT, WPE, T, GEO, NM, PM, DM, kDampLds>(*in, tr.tile, s_rho, s_bigd, s_vL, s_F, s_F + R::NRF, s_rho1, s_min,
+                                            s_geo, s_damp);
     __syncthreads();  // LDS is reused by the next entry
   }
 }
