@@ -9,8 +9,8 @@
 //   A  cells [i0-3, i0+TW+3)  viscosity, phi-scaled stress less p0 (EoS from cache) -> LDS
 //   B  nodes [i0-2, i0+TW+2]  control-volume force, PML psi1 -> v^L         -> LDS
 //   C  cells [i0-2, i0+TW+1]  Lagrangian update, PML psi2, limiter           -> LDS
-//   E1 faces of the cells below: volume and donor mass fluxes                -> LDS
-//   E2 cells [i0-1, i0+TW]    donor-cell remap, PML phi1/phi3                -> LDS
+//   E2 cells [i0-1, i0+TW]    face volume and donor mass fluxes, donor-cell
+//                             remap, PML phi1/phi3                           -> LDS
 //   F  nodes [i0, i0+TW]      momentum remap, KE-loss heat, PML phi2         -> LDS
 //   G  cells of the tile      heat, checks, EoS of the new state (cached), dt
 // (the same ranges in z). Halo values are recomputed with bit-identical
@@ -731,7 +731,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   }
   __syncthreads();
 
-  // ------------------------------------------------------------------ E1
+  // ------------------------------------------------------- face mass fluxes
   // mass flux of a face (0 where there is no face): e = dV lambda of the
   // donor d; the flux is e rho^L(d), or with the per-material closure the
   // sum of every material's e mu_m^L(d) (E2 recomputes the same terms per
@@ -791,7 +791,7 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       double fL[NM];
 #pragma unroll
       for (int m = 0; m < NM; m++) fL[m] = cd[(kFo + m) * R::NC + kc];
-      // per-material closure: every material's face mass fluxes (the terms E1
+      // per-material closure: every material's face mass fluxes (the terms face_flux
       // summed), its new partial density, and rho as their sum
       double Fm[PM ? NM : 1][4], mu1[PM ? NM : 1];
       if constexpr (PM) {
@@ -1273,7 +1273,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   __shared__ double s_rho[R::NA];     // rho^n over A (0 outside the grid)
   __shared__ double s_bigd[SM::kBigD];  // A..B stress; C..E2 Lagrangian state; F..G heat, speed
   __shared__ T s_vL[2 * R::NB];       // v^L over B
-  __shared__ double s_F[R::NRF + R::NZF];  // B..C: node KE defect; E1..F: face mass fluxes
+  __shared__ double s_F[R::NRF + R::NZF];  // B..C: node KE defect; E2..F: face mass fluxes
   __shared__ double s_rho1[R::NE];    // rho^{n+1} over E (0 outside the grid)
   __shared__ double s_min[NT / 64];
   __shared__ double s_geo[GEO ? GeoLds<TW, TH>::N : 1];  // a stretched tile's geometry
