@@ -396,9 +396,10 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     int i = i0 - 2 + k % R::BW, j = j0 - 2 + k / R::BW;
     T vLr = T(0), vLz = T(0), kdn = T(0);
     if (i >= 0 && i <= g.NR && j >= 0 && j <= g.NZ) {
-      // the damping profiles first: their latency hides behind the forces
-      const double dbl = DL ? s_dnz[j - (j0 - 2)] : (g.pml_on ? pm.dnz : S.rho)[j];
-      const double drl = DL ? s_dnr[i - (i0 - 2)] : (g.pml_on ? pm.dnr : S.rho)[i];
+      // the node's damping rates (staged in LDS by A where they fit; else
+      // read here, ahead of the forces, from an array that always exists)
+      const double dbl = DL ? s_dnz[j - (j0 - 2)] : (g.pml_on ? pm.dnz : S.rho)[g.pml_on ? j : 0];
+      const double drl = DL ? s_dnr[i - (i0 - 2)] : (g.pml_on ? pm.dnr : S.rho)[g.pml_on ? i : 0];
       const T vnr = s_vL[k], vnz = s_vL[R::NB + k];  // v^n, from A
       // quadrants NE = (i, j), NW = (i-1, j), SE = (i, j-1), SW = (i-1, j-1)
       const int qa[4] = {kA(i, j), kA(i - 1, j), kA(i, j - 1), kA(i - 1, j - 1)};
@@ -510,8 +511,8 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
       const T Gl = ((const T*)S.eos[2])[c], Yl = ((const T*)S.eos[3])[c];
       double Il = 0.0;
       if constexpr (!PM) Il = S.I[c];
-      const double dbl = DL ? s_dcz[j - (j0 - 2)] : (g.pml_on ? pm.dcz : S.rho)[j];
-      const double drl = DL ? s_dcr[i - (i0 - 2)] : (g.pml_on ? pm.dcr : S.rho)[i];
+      const double dbl = DL ? s_dcz[j - (j0 - 2)] : (g.pml_on ? pm.dcz : S.rho)[g.pml_on ? j : 0];
+      const double drl = DL ? s_dcr[i - (i0 - 2)] : (g.pml_on ? pm.dcr : S.rho)[g.pml_on ? i : 0];
       const int nb[4] = {kB(i, j), kB(i + 1, j), kB(i, j + 1), kB(i + 1, j + 1)};
       T vr4[4], vz4[4];
 #pragma unroll
@@ -779,9 +780,9 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
     if (i == i0 + TW) s_Fr[kR(i + 1, j)] = F[1];
     if (j == j0 + TH) s_Fz[kZ(i, j + 1)] = F[3];
     if (in_cells(g, i, j)) {
-      // the damping profiles first: their latency hides behind the flux sums
-      const double dbl = DL ? s_dcz[j - (j0 - 2)] : (g.pml_on ? pm.dcz : S.rho)[j];
-      const double drl = DL ? s_dcr[i - (i0 - 2)] : (g.pml_on ? pm.dcr : S.rho)[i];
+      // the cell's damping rates (LDS, or memory ahead of the flux sums)
+      const double dbl = DL ? s_dcz[j - (j0 - 2)] : (g.pml_on ? pm.dcz : S.rho)[g.pml_on ? j : 0];
+      const double drl = DL ? s_dcr[i - (i0 - 2)] : (g.pml_on ? pm.dcr : S.rho)[g.pml_on ? i : 0];
       bool own = owns_cell(i, j);
       double V = volD(i, j);
       double netin = (F[0] - F[1]) + (F[2] - F[3]);
@@ -1045,9 +1046,9 @@ __device__ __forceinline__ void tile_cycle(const Inst& in, int tile, double* s_r
   for (int k = tid; k < R::NF; k += NT) {
     int i = i0 + k % R::FW, j = j0 + k / R::FW;
     if (i > g.NR || j > g.NZ) continue;
-    // the damping profiles first: their latency hides behind the flux sums
-    const double dbl = DL ? s_dnz[j - (j0 - 2)] : (g.pml_on ? pm.dnz : S.rho)[j];
-    const double drl = DL ? s_dnr[i - (i0 - 2)] : (g.pml_on ? pm.dnr : S.rho)[i];
+    // the node's damping rates (LDS, or memory ahead of the flux sums)
+    const double dbl = DL ? s_dnz[j - (j0 - 2)] : (g.pml_on ? pm.dnz : S.rho)[g.pml_on ? j : 0];
+    const double drl = DL ? s_dnr[i - (i0 - 2)] : (g.pml_on ? pm.dnr : S.rho)[g.pml_on ? i : 0];
     // node mass: a quarter of the four cell masses (SW, SE, NW, NE)
     const int qi[4] = {i - 1, i, i - 1, i}, qj[4] = {j - 1, j - 1, j, j};
     double M[4] = {0, 0, 0, 0};
