@@ -575,10 +575,19 @@ int start_run(salec_ctx* x, int k) {
 }
 
 // Tile list of every member for tile shape v, grouped into kXcds contiguous
-// chunks: entry e goes to chunk e % kXcds, so the workgroups one L2 domain
-// runs work on neighbouring tiles.
+// chunks: entry e is position e / kXcds of chunk e % kXcds, so the
+// workgroups one L2 domain runs work on neighbouring tiles. Tiles that reach
+// into a PML strip cost about a fifth more than the others (the layers'
+// auxiliaries); a workgroup drawing several of them would finish last, so
+// they are spread where each workgroup takes only a few tiles: first evenly
+// over the chunks (a strip tile of a chunk holding too many changes places
+// with another chunk's plain tile), then to the first positions of each
+// chunk, which the grid-stride order hands to different workgroups.
 int build_schedule(salec_ctx* x, int v) {
   std::vector<TileRef> list;
+  std::vector<char> strip;
+  int tw, th, nthr;
+  variant_shape(v, &tw, &th, &nthr);
   for (size_t k = 0; k < x->ms.size(); k++) {
     Member& mb = x->ms[k];
     int tr, tz;
@@ -586,13 +595,42 @@ int build_schedule(salec_ctx* x, int v) {
     mb.d.tiles_r = tr;
     mb.d.tiles_z = tz;
     mb.d.ntiles = nt;
-    for (int t = 0; t < nt; t++) list.push_back(TileRef{(int)k, t});
+    for (int t = 0; t < nt; t++) {
+      const int i1 = std::min((t % tr + 1) * tw, mb.g.NR), j0 = (t / tr) * th;
+      list.push_back(TileRef{(int)k, t});
+      strip.push_back(mb.g.pml_on && (i1 > mb.g.n_r || j0 < mb.g.pml_b));
+    }
   }
   size_t T = list.size(), per = (T + kXcds - 1) / kXcds;
+  std::vector<std::vector<size_t>> chunk(kXcds);
+  for (size_t i = 0; i < T; i++) chunk[i / per].push_back(i);
+  // only where each workgroup takes a few tiles (with many, the mix averages out)
+  if (x->grid > 0 && T <= 16 * (size_t)x->grid) {
+    std::vector<size_t> n(kXcds, 0), ps(kXcds), pp(kXcds);
+    size_t total = 0;
+    for (int c = 0; c < kXcds; c++) {
+      for (size_t i : chunk[c]) n[c] += strip[i];
+      total += n[c];
+      ps[c] = pp[c] = chunk[c].size();  // scan positions for strip / plain tiles, from the end
+    }
+    const size_t want = (total + kXcds - 1) / kXcds;
+    for (int a = 0; a < kXcds; a++)
+      for (int b = 0; b < kXcds && n[a] > want; b++)
+        while (n[a] > want && n[b] < want) {
+          while (ps[a] > 0 && !strip[chunk[a][ps[a] - 1]]) ps[a]--;
+          while (pp[b] > 0 && strip[chunk[b][pp[b] - 1]]) pp[b]--;
+          if (ps[a] == 0 || pp[b] == 0) break;
+          std::swap(chunk[a][ps[a] - 1], chunk[b][pp[b] - 1]);
+          n[a]--, n[b]++;
+        }
+    for (int c = 0; c < kXcds; c++)
+      std::stable_partition(chunk[c].begin(), chunk[c].end(), [&](size_t i) { return strip[i] != 0; });
+  }
   std::vector<TileRef> sched(per * kXcds);
   for (size_t e = 0; e < sched.size(); e++) {
-    size_t idx = (e % kXcds) * per + e / kXcds;
-    sched[e] = idx < T ? list[idx] : TileRef{-1, 0};
+    const std::vector<size_t>& ch = chunk[e % kXcds];
+    size_t q = e / kXcds;
+    sched[e] = q < ch.size() ? list[ch[q]] : TileRef{-1, 0};
   }
   if (sched.size() > x->L.sched_cap) {
     x->err = "schedule larger than its reserved space";
