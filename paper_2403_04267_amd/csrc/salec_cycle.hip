@@ -65,7 +65,8 @@ hipError_t launch_cycle(int v, int prec, bool geo, int nm, bool pm, bool dm, con
 // End of a cycle, one workgroup per instance: the Courant minimum over the
 // instance's tiles, then time, cycle count, next step (growth cap, maximum,
 // stop time) and sticky errors (Sec. 7). The clock is read while the tile
-// minima load, so the kernel costs about two memory round trips.
+// minima load (eight per thread in flight at a time), so the kernel costs
+// about two memory round trips.
 constexpr int kFinalizeThreads = 256;
 
 __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(const Inst* __restrict__ insts) {
@@ -82,8 +83,17 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(const Inst* __res
     fl = sc->flags;
     err = sc->err;
   }
+  // the tile minima in batches of eight loads in flight (from a clamped
+  // index; the minimum takes them in the order of a plain strided loop)
   double m = __builtin_huge_val();
-  for (int q = tid; q < in.ntiles; q += kFinalizeThreads) m = dmin(m, in.dtpart[q]);
+  for (int q0 = tid; q0 < in.ntiles; q0 += 8 * kFinalizeThreads) {
+    double v[8];
+#pragma unroll
+    for (int r = 0; r < 8; r++) v[r] = in.dtpart[min(q0 + r * kFinalizeThreads, in.ntiles - 1)];
+#pragma unroll
+    for (int r = 0; r < 8; r++)
+      if (q0 + r * kFinalizeThreads < in.ntiles) m = dmin(m, v[r]);
+  }
   for (int off = 32; off > 0; off >>= 1) m = dmin(m, __shfl_down(m, off, 64));
   __shared__ double part[kFinalizeThreads / 64];
   if ((tid & 63) == 0) part[tid >> 6] = m;
